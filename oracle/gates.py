@@ -1,0 +1,197 @@
+"""Gates on a fixed-(N_alpha, N_beta) state matrix Gamma (dim_a x dim_b), complex128.
+
+Every gate here is the plain definition written out; no Givens sweeps, no
+merging, no fusion.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import strings as st
+
+
+# ---------------------------------------------------------------------------
+# Orbital rotation (Sec. 2.3 and Table 1)
+# ---------------------------------------------------------------------------
+
+def compound_matrix(U: np.ndarray, n: int, chunk: int = 256) -> np.ndarray:
+    """C_n(U)[J, I] = det U[J, I] over n-subsets J (rows) and I (columns), ascending addresses.
+
+    From the defining relation of an orbital rotation, script-U a^dag_p
+    script-U^dag = sum_q U_qp a^dag_q (Sec. 2.3): applying it to
+    cre(I)|vac> = a^dag_{i_n}...a^dag_{i_1}|vac> and collecting the ordered
+    products gives sum_J det(U[J, I]) |J>, i.e. column I of C_n(U).
+    C_0(U) = [[1]].
+    """
+    norb = U.shape[0]
+    occ = st.occupied_lists(norb, n)
+    d = len(occ)
+    if n == 0:
+        return np.ones((1, 1), dtype=np.complex128)
+    out = np.empty((d, d), dtype=np.complex128)
+    for j0 in range(0, d, chunk):
+        rows = occ[j0:j0 + chunk]                       # (c, n)
+        # minors[a, b] = U[rows[a]][:, occ[b]]  -> shape (c, d, n, n)
+        sub = U[rows[:, None, :, None], occ[None, :, None, :]]
+        out[j0:j0 + chunk] = np.linalg.det(sub)
+    return out
+
+
+def apply_orbital_rotation(vec: np.ndarray, U_a: np.ndarray, norb: int, nelec,
+                           U_b: np.ndarray | None = None) -> np.ndarray:
+    """script-U(U) = exp(sum_pq log(U)_pq a^dag_p a_q) on both spins (Sec. 2.3, 3.2.3).
+
+    Gamma' = C_{n_a}(U_a) Gamma C_{n_b}(U_b)^T (transpose, not dagger: the beta
+    index is the column index).  U_b = None means the same U for both spins.
+    """
+    na, nb = nelec
+    if U_b is None:
+        U_b = U_a
+    Ca = compound_matrix(np.asarray(U_a, dtype=np.complex128), na)
+    Cb = Ca if (U_b is U_a and na == nb) else compound_matrix(np.asarray(U_b, dtype=np.complex128), nb)
+    return Ca @ vec @ Cb.T
+
+
+# ---------------------------------------------------------------------------
+# Number-operator-sum evolution (Sec. 3.2.1)
+# ---------------------------------------------------------------------------
+
+def apply_num_op_sum_evolution(vec: np.ndarray, lam_a: np.ndarray, time: float, norb: int,
+                               nelec, lam_b: np.ndarray | None = None) -> np.ndarray:
+    """gamma' = exp(-i t (sum_{p in I_a} lam_a[p] + sum_{p in I_b} lam_b[p])) gamma."""
+    na, nb = nelec
+    if lam_b is None:
+        lam_b = lam_a
+    xa = st.occupations(norb, na)
+    xb = st.occupations(norb, nb)
+    ang = (xa @ np.asarray(lam_a, float))[:, None] + (xb @ np.asarray(lam_b, float))[None, :]
+    return np.exp(-1j * time * ang) * vec
+
+
+# ---------------------------------------------------------------------------
+# Diagonal Coulomb evolution (Sec. 3.2.2)
+# ---------------------------------------------------------------------------
+
+def diag_coulomb_angle(norb: int, nelec, J_aa: np.ndarray, J_ab: np.ndarray | None = None,
+                       J_bb: np.ndarray | None = None) -> np.ndarray:
+    """sum over the multiset S of (p, q) pairs of J^{sigma tau}_pq, per configuration.
+
+    S holds (p in I_a, q in I_a), (p in I_a, q in I_b), (p in I_b, q in I_a),
+    (p in I_b, q in I_b), diagonal p = q included.  The (b, a) block uses
+    J^{ba} = (J^{ab})^T.  A single matrix fills all blocks.
+    Returns a (dim_a, dim_b) array of sum_{(p,q) in S} J_pq.
+    """
+    na, nb = nelec
+    if J_ab is None:
+        J_ab = J_aa
+    if J_bb is None:
+        J_bb = J_aa
+    xa = st.occupations(norb, na)
+    xb = st.occupations(norb, nb)
+    aa = np.einsum("ip,pq,iq->i", xa, J_aa, xa)
+    bb = np.einsum("ip,pq,iq->i", xb, J_bb, xb)
+    ab = xa @ J_ab @ xb.T          # p in I_a, q in I_b
+    ba = (xb @ J_ab.T @ xa.T).T    # p in I_b, q in I_a with J^{ba} = (J^{ab})^T
+    return aa[:, None] + bb[None, :] + ab + ba
+
+
+def apply_diag_coulomb_evolution(vec: np.ndarray, J: np.ndarray, time: float, norb: int, nelec,
+                                 J_ab: np.ndarray | None = None,
+                                 J_bb: np.ndarray | None = None) -> np.ndarray:
+    """gamma' = exp(-(1/2) i t sum_{(p,q) in S} J_pq) gamma (Sec. 3.2.2).
+
+    With only J given, J^{aa} = J^{ab} = J^{bb} = J.
+    """
+    ang = diag_coulomb_angle(norb, nelec, J, J_ab, J_bb)
+    return np.exp(-0.5j * time * ang) * vec
+
+
+# ---------------------------------------------------------------------------
+# Givens pair action (Sec. 3.2.3)
+# ---------------------------------------------------------------------------
+
+def apply_givens(vec: np.ndarray, c: float, s: complex, p: int, q: int, norb: int, nelec,
+                 spin: int) -> np.ndarray:
+    """The Givens rotation [[c, s], [-s*, c]] on orbitals (p, q) of one spin.
+
+    For each configuration I with p in I, q not in I and I' = I^{p->q}:
+      gamma'(I) = c gamma(I) + eps s gamma(I'),  gamma'(I') = -eps s* gamma(I) + c gamma(I'),
+    where eps = (-1)^(number of occupied orbitals strictly between p and q).
+    The paper's formula omits eps; it is exact as printed for adjacent orbitals
+    (eps = 1), which is the only case the rotation networks use.
+    """
+    n = nelec[spin]
+    s_list = st.strings(norb, n)
+    amap = st.address_map(norb, n)
+    out = vec.copy()
+    for i, m in enumerate(s_list):
+        m = int(m)
+        if (m >> p) & 1 and not (m >> q) & 1:
+            m2 = (m & ~(1 << p)) | (1 << q)
+            j = amap[m2]
+            eps = st.excitation_sign(m, q, p)
+            if spin == 0:
+                x, y = vec[i, :], vec[j, :]
+                out[i, :] = c * x + eps * s * y
+                out[j, :] = -eps * np.conj(s) * x + c * y
+            else:
+                x, y = vec[:, i], vec[:, j]
+                out[:, i] = c * x + eps * s * y
+                out[:, j] = -eps * np.conj(s) * x + c * y
+    return out
+
+
+# ---------------------------------------------------------------------------
+# One-body excitation operators E^sigma_pq = a^dag_{p sigma} a_{q sigma}
+# ---------------------------------------------------------------------------
+
+def excitation_matrix(norb: int, n: int, p: int, q: int) -> sp.csr_matrix:
+    """Sparse dim x dim matrix of a^dag_p a_q on n-electron strings of one spin."""
+    s_list = st.strings(norb, n)
+    amap = st.address_map(norb, n)
+    rows, cols, vals = [], [], []
+    for i, m in enumerate(s_list):
+        m = int(m)
+        if not (m >> q) & 1:
+            continue
+        if p != q and (m >> p) & 1:
+            continue
+        m2 = (m & ~(1 << q)) | (1 << p)
+        rows.append(amap[m2])
+        cols.append(i)
+        vals.append(float(st.excitation_sign(m, p, q)) if p != q else 1.0)
+    d = len(s_list)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(d, d), dtype=np.complex128)
+
+
+def one_body_matrix(M: np.ndarray, norb: int, n: int) -> sp.csr_matrix:
+    """sum_pq M_pq a^dag_p a_q restricted to n-electron strings of one spin."""
+    d = st.dim(norb, n)
+    out = sp.csr_matrix((d, d), dtype=np.complex128)
+    for p in range(norb):
+        for q in range(norb):
+            if M[p, q] != 0:
+                out = out + M[p, q] * excitation_matrix(norb, n, p, q)
+    return out
+
+
+def apply_one_body(vec: np.ndarray, M: np.ndarray, norb: int, nelec) -> np.ndarray:
+    """(sum_pq M_pq sum_sigma a^dag_{p sigma} a_{q sigma}) applied to Gamma."""
+    na, nb = nelec
+    Aa = one_body_matrix(M, norb, na)
+    Ab = one_body_matrix(M, norb, nb)
+    return Aa @ vec + (Ab @ vec.T).T
+
+
+def transition_one_body(lam: np.ndarray, vec: np.ndarray, norb: int, nelec) -> np.ndarray:
+    """T_pq = <lam| sum_sigma a^dag_{p sigma} a_{q sigma} |vec>, summed over both spins."""
+    na, nb = nelec
+    T = np.zeros((norb, norb), dtype=np.complex128)
+    lc = lam.conj()
+    for p in range(norb):
+        for q in range(norb):
+            Ea = excitation_matrix(norb, na, p, q)
+            Eb = excitation_matrix(norb, nb, p, q)
+            T[p, q] = np.sum(lc * (Ea @ vec)) + np.sum(lc * (Eb @ vec.T).T)
+    return T

@@ -1,0 +1,166 @@
+/*
+ * ffx.h - C ABI of libffx: evolution of a fermionic state vector at fixed
+ * particle number and S_z on AMD MI355X (gfx950).
+ *
+ * The state of a sector (N_alpha, N_beta) with N spatial orbitals is the
+ * dim_a x dim_b complex matrix Gamma[i_a][i_b] = gamma(I_alpha, I_beta)
+ * (paper Sec. 3.1), dim_sigma = C(N, N_sigma), stored alpha-major
+ * (element (i_a, i_b) at offset i_a * dim_b + i_b) as interleaved
+ * (re, im) pairs: complex128 (FFX_C128) or complex64 (FFX_C64).
+ * Configurations of one spin are N-bit masks (bit p set <=> orbital p
+ * occupied, Sec. 2.2); address = rank in ascending integer order, so the
+ * Hartree-Fock configuration {0..n-1} has address 0.
+ *
+ * Conventions shared by every call:
+ *   - Return value: FFX_OK (0) or a negative error code.  No call aborts the
+ *     process.  ffx_last_error() returns a thread-local message for the most
+ *     recent failure on the calling thread.
+ *   - Device pointers (vec, workspace) are caller-owned device memory on the
+ *     plan's device.  Small matrices and vectors are caller-owned HOST arrays
+ *     of double, read during the call only: real matrices row-major
+ *     norb x norb; complex matrices row-major with interleaved (re, im).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  apply_* calls
+ *     only enqueue work and return; energy / gradient calls synchronize the
+ *     stream before returning host results.  A plan must not be used from two
+ *     streams or two threads at the same time.
+ *   - Orbital rotations, diagonal Coulomb and number-operator gates are applied
+ *     IN PLACE to vec.
+ */
+#ifndef FFX_H
+#define FFX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FFX_OK = 0,
+  FFX_EINVAL = -1,       /* bad norb / nelec / pointer / dtype / size / parameter */
+  FFX_ENOTUNITARY = -2,  /* ||U^dag U - I||_max > 1e-10 */
+  FFX_ENOMEM = -3,       /* device or pinned host allocation failed */
+  FFX_EDEVICE = -4,      /* a HIP runtime call failed */
+  FFX_EUNSUPPORTED = -5  /* valid request this build does not implement */
+};
+
+typedef enum { FFX_C128 = 0, FFX_C64 = 1 } ffx_dtype;
+
+typedef struct ffx_plan_s* ffx_plan;
+
+/* Message for the last failure on this thread ("" if none). */
+const char* ffx_last_error(void);
+
+/* C(norb, n): the number of configurations of one spin (Sec. 2.5).
+   Returns -1 for norb outside [1, 32] or n outside [0, norb]. */
+int64_t ffx_dim(int norb, int n);
+
+/* Host-only: the dim configurations of n electrons in norb orbitals as bit
+   masks in address order (Sec. 2.2, 3.1).  out_masks holds ffx_dim(norb, n)
+   entries.  Needs no GPU. */
+int ffx_strings(int norb, int n, uint64_t* out_masks);
+
+/* Host-only: decomposition of a norb x norb unitary U into adjacent Givens
+   rotations and a final phase layer (Sec. 3.2.3):
+     U = diag(exp(i phase)) G_K ... G_1,  K = norb (norb - 1) / 2,
+   where G_k acts on orbitals (p_k, p_k + 1) as the 2x2 block
+   [[c_k, s_k], [-conj(s_k), c_k]] (c_k real).  G_1 is applied to the state
+   first.  Outputs: p (K ints), c (K doubles), s (K complex, interleaved),
+   phase (norb doubles).  Returns FFX_ENOTUNITARY for a non-unitary U.  Needs
+   no GPU. */
+int ffx_givens_decomposition(int norb, const double* U, int* p, double* c, double* s,
+                             double* phase);
+
+/* A plan owns the device string tables, window tables and a small parameter
+   upload ring for one (norb, n_alpha, n_beta, dtype, device).
+   1 <= norb <= 32; the state must fit in device memory. */
+int ffx_plan_create(ffx_plan* out, int norb, int n_alpha, int n_beta, ffx_dtype dtype,
+                    int device);
+int ffx_plan_destroy(ffx_plan plan);
+/* dim_a, dim_b and the state size in bytes. */
+int ffx_plan_info(ffx_plan plan, int64_t* dim_a, int64_t* dim_b, int64_t* state_bytes);
+/* Copy of the device string table of one spin (0 = alpha, 1 = beta) to host,
+   dim entries; bit-exact with ffx_strings. */
+int ffx_plan_strings(ffx_plan plan, int spin, uint64_t* out_masks);
+
+/* Orbital rotation script-U(U) = exp(sum_pq log(U)_pq a^dag_p a_q), per spin
+   (Table 1, Sec. 2.3, 3.2.3).  U_a, U_b: complex norb x norb unitaries;
+   U_b = NULL means U_b = U_a.  Implemented as Givens sweeps over
+   configuration pairs, several rotations per pass over HBM. */
+int ffx_apply_orbital_rotation(ffx_plan plan, void* vec, const double* U_a, const double* U_b,
+                               void* stream);
+
+/* Number-operator-sum evolution exp(-i t sum_{p,sigma} lam^sigma_p n_{p sigma})
+   (Table 1, Sec. 3.2.1).  lam_a, lam_b: norb real; lam_b = NULL means lam_a. */
+int ffx_apply_num_op_sum_evolution(ffx_plan plan, void* vec, const double* lam_a,
+                                   const double* lam_b, double time, void* stream);
+
+/* Diagonal Coulomb evolution
+   exp(-(1/2) i t sum_{pq, sigma tau} J^{sigma tau}_pq n_{p sigma} n_{q tau})
+   (Table 1, Sec. 3.2.2).  J_aa, J_ab, J_bb: real symmetric norb x norb;
+   J^{ba} = (J^{ab})^T; J_ab or J_bb = NULL means J_aa. */
+int ffx_apply_diag_coulomb_evolution(ffx_plan plan, void* vec, const double* J_aa,
+                                     const double* J_ab, const double* J_bb, double time,
+                                     void* stream);
+
+/* Double-factorized Hamiltonian (Eq. double-factorized-hamiltonian):
+   H = sum h_pq a^dag_{p s} a_{q s} + 1/2 sum_t sum J^(t)_pq n^(t)_{p s} n^(t)_{q t'}.
+   h: real symmetric norb^2; J: n_terms * norb^2 real symmetric;
+   U: n_terms * norb^2 complex unitaries (interleaved). */
+typedef struct {
+  int norb;
+  int n_terms;
+  const double* h;
+  const double* J;
+  const double* U;
+} ffx_df_ham;
+
+/* Trotter-Suzuki evolution exp(-i H T) ~ S_order(T / n_steps)^n_steps with
+   T = dt * n_steps (Sec. 4.5.3).  order 0: S_0 (one-body term first, then the
+   two-body terms in array order); order 1: the symmetric S_1; order k >= 2:
+   Suzuki's recursion.  Adjacent orbital rotations are merged through
+   script-U(U) script-U(V) = script-U(UV) (Sec. 2.3). */
+int ffx_apply_df_trotter_step(ffx_plan plan, void* vec, const ffx_df_ham* ham, double dt,
+                              int n_steps, int order, void* stream);
+
+/* LUCJ ansatz (Sec. 4.3): vec is OVERWRITTEN with
+   prod_{k = n_reps..1} [script-U(U_k) D_k script-U(U_k)^dag] |HF>.
+   Per repetition the flat real parameter block is
+   [Re A (norb^2), Im A (norb^2), j_same (norb - 1), j_opp (norb)],
+   U_k = expm(A - A^dag) for both spins, D_k = diagonal Coulomb evolution at
+   t = 1 with J^{aa} = J^{bb} holding j_same[p] at (p, p+1) and (p+1, p),
+   J^{ab} = diag(j_opp).  n_params = n_reps (2 norb^2 + 2 norb - 1). */
+typedef struct {
+  int norb;
+  int n_reps;
+  const double* params;
+} ffx_lucj;
+
+int ffx_lucj_n_params(int norb, int n_reps);
+int ffx_apply_lucj(ffx_plan plan, void* vec, const ffx_lucj* op, void* stream);
+
+/* Workspace size in bytes for ffx_df_energy / ffx_lucj_energy_grad. */
+int64_t ffx_workspace_bytes(ffx_plan plan, int what /* 0 = energy, 1 = gradient */);
+
+/* Energy <psi|H|psi> of vec for the DF Hamiltonian (Sec. 4.2), evaluated as
+   sum_t sum_I w_t(I) |(script-U(U_t)^dag psi)(I)|^2 with the one-body term in
+   the eigenbasis of h; FP64 accumulation in a fixed order, so repeated calls
+   give identical results.  workspace: device buffer of
+   ffx_workspace_bytes(plan, 0) bytes.  Synchronizes the stream. */
+int ffx_df_energy(ffx_plan plan, const void* vec, const ffx_df_ham* ham, double* energy,
+                  void* workspace, void* stream);
+
+/* LUCJ energy E(theta) = <psi(theta)|H|psi(theta)> and its gradient
+   dE/dtheta (n_params doubles) by the adjoint method: the costate
+   lambda = H psi is pulled back through the gates while psi is uncomputed,
+   so no intermediate state is stored.  workspace: ffx_workspace_bytes(plan, 1)
+   bytes.  psi_out (device, may be NULL) receives psi(theta).  Synchronizes. */
+int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ham,
+                         double* energy, double* grad, void* psi_out, void* workspace,
+                         void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFX_H */

@@ -1,0 +1,111 @@
+// Launchers for the HIP kernels of libffx (kernels.hip).  All launches are
+// asynchronous on the given stream; every pointer is device memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ffx {
+namespace dev {
+
+// One Givens rotation as read by the kernels: local orbital p (relative to the
+// window start), cosine c and complex sine (sr, si).
+struct RotDev {
+  int p;
+  int pad;
+  double c, sr, si;
+};
+
+// Window class table on the device (see WindowTable in host.h).
+struct WinDev {
+  const int* tab;
+  const int* chunk_m;
+  const int* chunk_off;
+  const int* cls;
+  int n_chunks;
+  int n_cls;
+  int a, w;
+};
+
+// Diagonal function f(I_a, I_b) = A[i_a] + B[i_b] + sum_{p in I_a} V[p * dim_b + i_b].
+struct DiagDev {
+  const double* A;
+  const double* B;
+  const double* V;  // may be null (no cross term)
+};
+
+// Parameters for building DiagDev tables from occupation vectors:
+//   A[i] = lin_a . x + 1/2 x^T Q_a x,  B[i] = lin_b . x + 1/2 x^T Q_b x,
+//   V[p][i_b] = (C x_b)[p].  Any matrix pointer may be null (= zero).
+struct DiagSpecDev {
+  const double* lin_a;
+  const double* lin_b;
+  const double* Qa;
+  const double* Qb;
+  const double* C;
+};
+
+// Largest window width with a kernel instantiation (register budget: about
+// twice C(W, W/2) complex amplitudes per lane).
+inline int max_window(bool c64) { return c64 ? 7 : 6; }
+
+// c128 = complex double state, c64 = complex float state.
+void win_pass(bool c64, bool real, int spin, void* vec, int64_t dim_a, int64_t dim_b,
+              const WinDev& wt, const RotDev* rots, int nrot, const void* phase,
+              hipStream_t stream);
+
+// phase[i] = exp(i sum_{p in I_i} delta[p]) in the state's precision.
+void string_phase(bool c64, const uint32_t* masks, int64_t n, const double* delta, int norb,
+                  void* phase, hipStream_t stream);
+
+void diag_tables(const uint32_t* masks_a, int64_t dim_a, const uint32_t* masks_b, int64_t dim_b,
+                 int norb, const DiagSpecDev& spec, double* A, double* B, double* V,
+                 hipStream_t stream);
+
+// vec *= exp(i * scale * f)
+void diag_phase(bool c64, void* vec, int64_t dim_a, int64_t dim_b, const uint32_t* masks_a,
+                int norb, const DiagDev& f, double scale, hipStream_t stream);
+// vec *= f
+void diag_scale(bool c64, void* vec, int64_t dim_a, int64_t dim_b, const uint32_t* masks_a,
+                int norb, const DiagDev& f, hipStream_t stream);
+// partials[blk] = sum f |vec|^2 over a block of the state; returns number of partials
+int diag_expect(bool c64, const void* vec, int64_t dim_a, int64_t dim_b, const uint32_t* masks_a,
+                int norb, const DiagDev& f, double* partials, hipStream_t stream);
+int diag_expect_partials(int64_t dim_a, int64_t dim_b);
+// out[0] = sum of partials[0..n) in a fixed order
+void sum_partials(const double* partials, int n, double* out, hipStream_t stream);
+// complex inner product <x|y> in FP64: partials of size 2 * nblocks, out[0..2) = (re, im)
+int inner_partials(int64_t n);
+void inner(bool c64, const void* x, const void* y, int64_t n, double* partials, double* out,
+           hipStream_t stream);
+
+// y += x
+void axpy(bool c64, const void* x, void* y, int64_t n, hipStream_t stream);
+// vec[i_a, i_b] = a[i_a] * b[i_b] (a, b complex double)
+void outer(bool c64, const double* a, const double* b, void* vec, int64_t dim_a, int64_t dim_b,
+           hipStream_t stream);
+// dst = src^T (rows x cols -> cols x rows)
+void transpose(bool c64, const void* src, void* dst, int64_t rows, int64_t cols,
+               hipStream_t stream);
+
+// Transition one-body matrix of the row spin: for every row string I and every
+// (p, q) with q in I and (p not in I or p == q), J = I - q + p:
+//   part[(p * norb + q) * rows + i] = sign * sum_col conj(lam[J, col]) psi[I, col]
+// (zero where (p, q) is not an excitation of I).  Then T[p][q] = sum_i part.
+void rdm_rows(bool c64, const void* lam, const void* psi, int64_t rows, int64_t cols,
+              const uint32_t* masks_rows, int norb, double* part, hipStream_t stream);
+void rdm_reduce(const double* part, int64_t rows, int norb, double* T, hipStream_t stream);
+
+// Diagonal-gate gradient reductions (see api): for each row i_a and
+//   z = Im(conj(lam) psi), g_0 = 1, g_{1+p} = x_b[p], g_{1+N+p} = x_b[p] x_b[p+1]:
+//   rowout[i_a * 2N + k] = sum_{i_b} z * g_k(I_b)
+void diag_grad_rows(bool c64, const void* lam, const void* psi, int64_t dim_a, int64_t dim_b,
+                    const uint32_t* masks_b, int norb, double* rowout, hipStream_t stream);
+// out[p]      (p < N-1) = 2 sum_{i_a} (x_a[p] x_a[p+1] rowout[i_a][0] + rowout[i_a][1+N+p])
+// out[N-1+p]  (p < N)   = 2 sum_{i_a} x_a[p] rowout[i_a][1+p]
+void diag_grad_combine(const double* rowout, int64_t dim_a, const uint32_t* masks_a, int norb,
+                       double* out, hipStream_t stream);
+
+}  // namespace dev
+}  // namespace ffx

@@ -1,0 +1,306 @@
+// Host-side building blocks of libffx (see host.h).
+#include "host.h"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <unordered_map>
+
+#include "ffx.h"
+
+namespace ffx {
+
+int64_t binom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  int64_t r = 1;
+  for (int i = 0; i < k; ++i) r = r * (n - i) / (i + 1);
+  return r;
+}
+
+std::vector<uint64_t> make_strings(int norb, int n) {
+  std::vector<uint64_t> out;
+  out.reserve((size_t)binom(norb, n));
+  if (n == 0) {
+    out.push_back(0);
+    return out;
+  }
+  uint64_t x = (n == 64) ? ~0ull : ((1ull << n) - 1);
+  const uint64_t limit = 1ull << norb;
+  while (x < limit) {
+    out.push_back(x);
+    // Gosper's hack: next larger integer with the same popcount
+    uint64_t u = x & (~x + 1);
+    uint64_t v = x + u;
+    if (v == 0) break;
+    x = v + (((v ^ x) / u) >> 2);
+  }
+  return out;
+}
+
+double unitarity_defect(int norb, const cd* U) {
+  double worst = 0;
+  for (int i = 0; i < norb; ++i)
+    for (int j = 0; j < norb; ++j) {
+      cd acc = 0;
+      for (int k = 0; k < norb; ++k) acc += std::conj(U[k * norb + i]) * U[k * norb + j];
+      worst = std::max(worst, std::abs(acc - (i == j ? 1.0 : 0.0)));
+    }
+  return worst;
+}
+
+// Column elimination by right multiplication: for rows i = N-1 .. 1, zero
+// V[i][j] for j = 0 .. i-1 with a rotation R of columns (j, j+1).  Then
+// U R_1 ... R_K = D, i.e. U = D R_K^dag ... R_1^dag, and the state sees
+// G_k = R_k^dag in the recorded order.
+Decomposition givens_decompose(int norb, const cd* U) {
+  if (unitarity_defect(norb, U) > 1e-10) throw Error(FFX_ENOTUNITARY, "orbital rotation is not unitary");
+  std::vector<cd> V(U, U + norb * norb);
+  Decomposition d;
+  bool real = true;
+  for (int k = 0; k < norb * norb; ++k)
+    if (U[k].imag() != 0.0) real = false;
+  for (int i = norb - 1; i >= 1; --i) {
+    for (int j = 0; j < i; ++j) {
+      cd a = V[i * norb + j], b = V[i * norb + j + 1];
+      double aa = std::abs(a), ab = std::abs(b);
+      double r = std::hypot(aa, ab);
+      double c;
+      cd s;
+      if (r == 0.0) {
+        c = 1.0;
+        s = 0.0;
+      } else if (ab == 0.0) {
+        c = 0.0;
+        s = 1.0;
+      } else {
+        c = ab / r;
+        s = std::conj(a) * (b / ab) / r;
+      }
+      // V <- V R on columns (j, j+1), R = [[c, s], [-conj(s), c]]
+      for (int row = 0; row < norb; ++row) {
+        cd x = V[row * norb + j], y = V[row * norb + j + 1];
+        V[row * norb + j] = c * x - std::conj(s) * y;
+        V[row * norb + j + 1] = s * x + c * y;
+      }
+      V[i * norb + j] = 0.0;
+      d.rots.push_back(Givens{j, c, -s});
+    }
+  }
+  d.phase.resize(norb);
+  for (int p = 0; p < norb; ++p) d.phase[p] = std::arg(V[p * norb + p]);
+  if (real) {
+    for (auto& g : d.rots) g.s = cd(g.s.real(), 0.0);
+    for (int p = 0; p < norb; ++p) d.phase[p] = (V[p * norb + p].real() < 0) ? M_PI : 0.0;
+  }
+  d.real = real;
+  return d;
+}
+
+std::vector<Pass> schedule_windows(const std::vector<Givens>& rots, int norb, int w) {
+  const int n = (int)rots.size();
+  std::vector<std::vector<int>> deps(n);
+  std::vector<int> last(norb, -1);
+  for (int i = 0; i < n; ++i) {
+    int p = rots[i].p;
+    for (int q : {p, p + 1})
+      if (last[q] >= 0) deps[i].push_back(last[q]);
+    last[p] = last[p + 1] = i;
+  }
+  std::vector<char> done(n, 0);
+  int remaining = n;
+  std::vector<Pass> out;
+  while (remaining > 0) {
+    int best_a = -1;
+    std::vector<char> best;
+    int best_count = -1;
+    for (int a = 0; a + w <= norb; ++a) {
+      std::vector<char> taken(n, 0);
+      int count = 0;
+      // one ordered scan suffices: dependencies point backwards
+      for (int i = 0; i < n; ++i) {
+        if (done[i]) continue;
+        int p = rots[i].p;
+        if (p < a || p + 1 >= a + w) continue;
+        bool ok = true;
+        for (int dd : deps[i])
+          if (!done[dd] && !taken[dd]) {
+            ok = false;
+            break;
+          }
+        if (ok) {
+          taken[i] = 1;
+          ++count;
+        }
+      }
+      if (count > best_count) {
+        best_count = count;
+        best_a = a;
+        best = taken;
+      }
+    }
+    Pass ps;
+    ps.a = best_a;
+    for (int i = 0; i < n; ++i)
+      if (best[i]) {
+        ps.idx.push_back(i);
+        done[i] = 1;
+      }
+    remaining -= best_count;
+    out.push_back(std::move(ps));
+  }
+  return out;
+}
+
+WindowTable build_window_table(const std::vector<uint64_t>& strs, int norb, int n, int a, int w) {
+  (void)norb;
+  (void)n;
+  WindowTable t;
+  t.a = a;
+  t.w = w;
+  const uint64_t wmask = ((1ull << w) - 1) << a;
+  // in-window pattern -> rank among patterns with the same popcount
+  std::vector<int> prank(1 << w, -1);
+  {
+    std::vector<int> cnt(w + 1, 0);
+    for (int x = 0; x < (1 << w); ++x) prank[x] = cnt[__builtin_popcount(x)]++;
+  }
+  // class key (outside bits) -> member addresses
+  std::map<std::pair<int, uint64_t>, std::vector<int>> classes;  // (m, key) -> members
+  for (size_t i = 0; i < strs.size(); ++i) {
+    uint64_t s = strs[i];
+    int pat = (int)((s & wmask) >> a);
+    int m = __builtin_popcount(pat);
+    auto& v = classes[{m, s & ~wmask}];
+    if (v.empty()) v.assign((size_t)binom(w, m), -1);
+    v[prank[pat]] = (int)i;
+  }
+  int cur_m = -1, lane = 64;
+  for (auto& kv : classes) {
+    int m = kv.first.first;
+    const int C = (int)binom(w, m);
+    if (m != cur_m || lane == 64) {
+      cur_m = m;
+      lane = 0;
+      t.chunk_m.push_back(m);
+      t.chunk_off.push_back((int)t.tab.size());
+      t.chunk_n.push_back(0);
+      t.tab.resize(t.tab.size() + (size_t)C * 64, -1);
+    }
+    const int ch = (int)t.chunk_m.size() - 1;
+    for (int k = 0; k < C; ++k) t.tab[t.chunk_off[ch] + k * 64 + lane] = kv.second[k];
+    t.cls.push_back((ch << 6) | lane);
+    t.chunk_n[ch] = lane + 1;
+    ++lane;
+  }
+  return t;
+}
+
+std::vector<cd> matmul(int n, const std::vector<cd>& A, const std::vector<cd>& B) {
+  std::vector<cd> C((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      cd a = A[i * n + k];
+      for (int j = 0; j < n; ++j) C[i * n + j] += a * B[k * n + j];
+    }
+  return C;
+}
+
+std::vector<cd> dagger(int n, const std::vector<cd>& A) {
+  std::vector<cd> B((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) B[j * n + i] = std::conj(A[i * n + j]);
+  return B;
+}
+
+void eigh(int n, const std::vector<cd>& Ain, std::vector<double>& w, std::vector<cd>& W) {
+  std::vector<cd> A = Ain;
+  W.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) W[i * n + i] = 1.0;
+  double norm = 0;
+  for (auto& x : A) norm += std::norm(x);
+  norm = std::sqrt(norm);
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += std::norm(A[p * n + q]);
+    if (std::sqrt(off) <= 1e-17 * std::max(norm, 1e-300)) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        cd apq = A[p * n + q];
+        double r = std::abs(apq);
+        if (r == 0.0) continue;
+        cd ph = apq / r;  // e^{i phi}
+        double app = A[p * n + p].real(), aqq = A[q * n + q].real();
+        double tau = (aqq - app) / (2 * r);
+        double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1 + tau * tau));
+        double c = 1 / std::sqrt(1 + t * t), s = t * c;
+        // J = P R with P = diag(1, conj(ph)) on (p, q), R = [[c, s], [-s, c]]
+        // columns: J[:, p] = (c, -s conj(ph)), J[:, q] = (s, c conj(ph)) in rows (p, q)
+        cd jpp = c, jqp = -s * std::conj(ph), jpq = s, jqq = c * std::conj(ph);
+        // A <- A J (columns)
+        for (int k = 0; k < n; ++k) {
+          cd x = A[k * n + p], y = A[k * n + q];
+          A[k * n + p] = x * jpp + y * jqp;
+          A[k * n + q] = x * jpq + y * jqq;
+        }
+        // A <- J^dag A (rows)
+        for (int k = 0; k < n; ++k) {
+          cd x = A[p * n + k], y = A[q * n + k];
+          A[p * n + k] = std::conj(jpp) * x + std::conj(jqp) * y;
+          A[q * n + k] = std::conj(jpq) * x + std::conj(jqq) * y;
+        }
+        A[p * n + q] = A[q * n + p] = 0.0;
+        for (int k = 0; k < n; ++k) {
+          cd x = W[k * n + p], y = W[k * n + q];
+          W[k * n + p] = x * jpp + y * jqp;
+          W[k * n + q] = x * jpq + y * jqq;
+        }
+      }
+  }
+  w.resize(n);
+  for (int i = 0; i < n; ++i) w[i] = A[i * n + i].real();
+}
+
+std::vector<cd> expm_antihermitian(int n, const std::vector<cd>& K) {
+  // H = i K is Hermitian; K = -i H = W diag(-i w) W^dag
+  std::vector<cd> H((size_t)n * n);
+  for (int i = 0; i < n * n; ++i) H[i] = cd(0, 1) * K[i];
+  std::vector<double> w;
+  std::vector<cd> W;
+  eigh(n, H, w, W);
+  std::vector<cd> E((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      cd acc = 0;
+      for (int k = 0; k < n; ++k) acc += W[i * n + k] * std::exp(cd(0, -w[k])) * std::conj(W[j * n + k]);
+      E[i * n + j] = acc;
+    }
+  return E;
+}
+
+std::vector<cd> slater_column_minors(int norb, int n, const std::vector<cd>& U,
+                                     const std::vector<uint64_t>& strs) {
+  // level m: D_m(S) = det U[S, 0:m] over m-subsets S, expanded along column m-1
+  std::unordered_map<uint64_t, cd> prev, cur;
+  prev[0] = 1.0;
+  for (int m = 1; m <= n; ++m) {
+    cur.clear();
+    for (uint64_t S : make_strings(norb, m)) {
+      cd acc = 0;
+      int i = 0;
+      for (int r = 0; r < norb; ++r) {
+        if (!((S >> r) & 1)) continue;
+        double sign = ((i + m - 1) & 1) ? -1.0 : 1.0;
+        acc += sign * U[r * norb + (m - 1)] * prev[S & ~(1ull << r)];
+        ++i;
+      }
+      cur[S] = acc;
+    }
+    prev.swap(cur);
+  }
+  std::vector<cd> out(strs.size());
+  for (size_t i = 0; i < strs.size(); ++i) out[i] = prev[strs[i]];
+  return out;
+}
+
+}  // namespace ffx

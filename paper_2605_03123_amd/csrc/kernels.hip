@@ -1,0 +1,884 @@
+// HIP kernels of libffx for gfx950 (CDNA4, 64-wide wavefronts).
+//
+// The state is the dim_a x dim_b matrix Gamma (alpha-major) of interleaved
+// complex numbers (re, im): complex128 or complex64.
+//
+// Givens sweeps (Sec. 3.2.3).  A window pass applies a list of adjacent Givens
+// rotations whose orbitals all lie in one window [a, a+W) of one spin.  Such
+// rotations only mix configurations that agree outside the window, so each
+// class of those configurations (C(W, m) members, m = electrons in the window)
+// is loaded once into registers, every rotation of the pass is applied in
+// registers, and the class is stored once: one HBM round trip for the whole
+// list.  The member pairs touched by a rotation on (p, p+1) are compile-time
+// constants for given (W, m, p), so the register arrays are indexed
+// statically.
+//   alpha pass: a block owns one alpha class and 256 consecutive columns;
+//               lanes run along the contiguous beta index (coalesced).
+//   beta pass:  a wave owns 64 beta classes of one row that share m; lanes of
+//               classes with consecutive low patterns touch consecutive columns.
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "device.h"
+
+namespace ffx {
+namespace dev {
+
+// Complex amplitudes as plain aligned structs (HIP's union-based vector types
+// keep register arrays of them from being promoted out of scratch memory).
+struct alignas(16) zc128 {
+  double x, y;
+};
+struct alignas(8) zc64 {
+  float x, y;
+};
+template <class R>
+struct V2T;
+template <>
+struct V2T<double> {
+  using type = zc128;
+};
+template <>
+struct V2T<float> {
+  using type = zc64;
+};
+
+constexpr int cbinom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  long long r = 1;
+  for (int i = 0; i < k; ++i) r = r * (n - i) / (i + 1);
+  return (int)r;
+}
+
+struct BinomTab {
+  int v[33][33];
+  constexpr BinomTab() : v{} {
+    for (int n = 0; n <= 32; ++n)
+      for (int k = 0; k <= 32; ++k) v[n][k] = cbinom(n, k);
+  }
+};
+__constant__ const BinomTab kBinom = BinomTab();
+
+// address of a configuration: sum_k C(i_k, k) over its set bits i_1 < i_2 < ...
+__device__ __forceinline__ int colex_rank(uint32_t m) {
+  int r = 0, k = 1;
+  while (m) {
+    int i = __builtin_ctz(m);
+    r += kBinom.v[i][k++];
+    m &= m - 1;
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// compile-time pattern and pair tables
+// ---------------------------------------------------------------------------
+template <int W, int M>
+struct Pat {
+  static constexpr int C = cbinom(W, M);
+  int mask[C > 0 ? C : 1];
+  constexpr Pat() : mask{} {
+    int k = 0;
+    for (int x = 0; x < (1 << W); ++x) {
+      int pc = 0;
+      for (int b = 0; b < W; ++b) pc += (x >> b) & 1;
+      if (pc == M) mask[k++] = x;
+    }
+  }
+  constexpr int index(int x) const {
+    for (int k = 0; k < C; ++k)
+      if (mask[k] == x) return k;
+    return -1;
+  }
+};
+
+template <int W, int M, int P>
+struct Pairs {
+  static constexpr int NP = cbinom(W - 2, M - 1);
+  int a[NP > 0 ? NP : 1];
+  int b[NP > 0 ? NP : 1];
+  constexpr Pairs() : a{}, b{} {
+    Pat<W, M> pt{};
+    int n = 0;
+    for (int k = 0; k < Pat<W, M>::C; ++k) {
+      int x = pt.mask[k];
+      if (((x >> P) & 1) && !((x >> (P + 1)) & 1)) {
+        a[n] = k;
+        b[n] = pt.index(x ^ (3 << P));
+        ++n;
+      }
+    }
+  }
+};
+
+template <class V, class R>
+__device__ __forceinline__ V cmul(V a, V b) {
+  V r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+
+// x' = c x + s y, y' = -conj(s) x + c y on one member pair (A, B)
+template <int A, int B, bool REAL, class R>
+__device__ __forceinline__ void rot_pair(typename V2T<R>::type* v, R c, R sr, R si) {
+  using V = typename V2T<R>::type;
+  V x = v[A], y = v[B];
+  V nx, ny;
+  if constexpr (REAL) {
+    nx.x = c * x.x + sr * y.x;
+    nx.y = c * x.y + sr * y.y;
+    ny.x = c * y.x - sr * x.x;
+    ny.y = c * y.y - sr * x.y;
+  } else {
+    nx.x = c * x.x + sr * y.x - si * y.y;
+    nx.y = c * x.y + sr * y.y + si * y.x;
+    ny.x = c * y.x - sr * x.x - si * x.y;
+    ny.y = c * y.y - sr * x.y + si * x.x;
+  }
+  v[A] = nx;
+  v[B] = ny;
+}
+
+// every member pair of rotation P, expanded at compile time so that the
+// register array is only ever indexed by constants
+template <int W, int M, int P, bool REAL, class R, int... I>
+__device__ __forceinline__ void rot_pairs(typename V2T<R>::type* v, R c, R sr, R si,
+                                          std::integer_sequence<int, I...>) {
+  constexpr Pairs<W, M, P> pr{};
+  (rot_pair<pr.a[I], pr.b[I], REAL, R>(v, c, sr, si), ...);
+}
+
+template <int W, int M, int P, bool REAL, class R>
+__device__ __forceinline__ void rot_one(typename V2T<R>::type* v, R c, R sr, R si) {
+  rot_pairs<W, M, P, REAL, R>(v, c, sr, si, std::make_integer_sequence<int, Pairs<W, M, P>::NP>{});
+}
+
+template <int W, int M, bool REAL, class R, int P = 0>
+__device__ __forceinline__ void rot_dispatch(int p, typename V2T<R>::type* v, R c, R sr, R si) {
+  if constexpr (P < W - 1) {
+    if (p == P)
+      rot_one<W, M, P, REAL, R>(v, c, sr, si);
+    else
+      rot_dispatch<W, M, REAL, R, P + 1>(p, v, c, sr, si);
+  }
+}
+
+template <int W, int M, bool REAL, class R>
+__device__ __forceinline__ void apply_rots(typename V2T<R>::type* v, const RotDev* __restrict__ rots,
+                                           int nrot) {
+  for (int r = 0; r < nrot; ++r) {
+    const RotDev rd = rots[r];
+    rot_dispatch<W, M, REAL, R>(rd.p, v, (R)rd.c, (R)rd.sr, (R)rd.si);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// window passes
+// ---------------------------------------------------------------------------
+// Row bases are wave-uniform (scalar registers) and the lane part is one
+// 32-bit byte offset shared by every member, so each access is a scalar-base +
+// vector-offset load with no per-member 64-bit address registers.
+template <class V>
+__device__ __forceinline__ const V& at_off(const V* base, uint32_t off) {
+  return *(const V*)((const char*)base + off);
+}
+template <class V>
+__device__ __forceinline__ V& at_off(V* base, uint32_t off) {
+  return *(V*)((char*)base + off);
+}
+template <class V, class R, int... K>
+__device__ __forceinline__ void load_alpha(V* v, const V* __restrict__ vec, int64_t dim_b, const int* __restrict__ t,
+                                           uint32_t off, std::integer_sequence<int, K...>) {
+  ((v[K] = at_off(vec + (int64_t)t[K * 64] * dim_b, off)), ...);
+}
+template <class V, class R, int... K>
+__device__ __forceinline__ void store_alpha(const V* v, V* __restrict__ vec, int64_t dim_b, const int* t,
+                                            uint32_t off, const V* __restrict__ phase,
+                                            std::integer_sequence<int, K...>) {
+  if (phase)
+    ((at_off(vec + (int64_t)t[K * 64] * dim_b, off) = cmul<V, R>(v[K], phase[t[K * 64]])), ...);
+  else
+    ((at_off(vec + (int64_t)t[K * 64] * dim_b, off) = v[K]), ...);
+}
+template <class V, class R, int... K>
+__device__ __forceinline__ void load_beta(V* v, const V* __restrict__ rowp, const int* __restrict__ t,
+                                          std::integer_sequence<int, K...>) {
+  ((v[K] = rowp[t[K * 64]]), ...);
+}
+// The member columns are re-read from the (cache-resident) table at store time
+// instead of being kept live across the rotations: at W = 8 they would cost 70
+// extra registers per lane.
+template <class V, class R, int... K>
+__device__ __forceinline__ void store_beta(const V* v, V* __restrict__ rowp, const int* t,
+                                           const V* __restrict__ phase, std::integer_sequence<int, K...>) {
+  const volatile int* tv = t;
+  if (phase)
+    ((rowp[tv[K * 64]] = cmul<V, R>(v[K], phase[tv[K * 64]])), ...);
+  else
+    ((rowp[tv[K * 64]] = v[K]), ...);
+}
+
+template <int W, int M, bool REAL, class R>
+__device__ __forceinline__ void alpha_body(typename V2T<R>::type* __restrict__ vec, int64_t dim_b,
+                                           const int* __restrict__ t, uint32_t col,
+                                           const RotDev* __restrict__ rots, int nrot,
+                                           const typename V2T<R>::type* __restrict__ phase) {
+  using V = typename V2T<R>::type;
+  constexpr int C = cbinom(W, M);
+  V v[C];
+  const uint32_t off = col * (uint32_t)sizeof(V);
+  load_alpha<V, R>(v, vec, dim_b, t, off, std::make_integer_sequence<int, C>{});
+  apply_rots<W, M, REAL, R>(v, rots, nrot);
+  store_alpha<V, R>(v, vec, dim_b, t, off, phase, std::make_integer_sequence<int, C>{});
+}
+
+template <int W, int M, bool REAL, class R>
+__device__ __forceinline__ void beta_body(typename V2T<R>::type* __restrict__ rowp,
+                                          const int* __restrict__ t, const RotDev* __restrict__ rots,
+                                          int nrot, const typename V2T<R>::type* __restrict__ phase) {
+  using V = typename V2T<R>::type;
+  constexpr int C = cbinom(W, M);
+  V v[C];
+  load_beta<V, R>(v, rowp, t, std::make_integer_sequence<int, C>{});
+  apply_rots<W, M, REAL, R>(v, rots, nrot);
+  store_beta<V, R>(v, rowp, t, phase, std::make_integer_sequence<int, C>{});
+}
+
+template <int W, bool REAL, class R, int M = 0>
+__device__ __forceinline__ void alpha_m(int m, typename V2T<R>::type* vec, int64_t dim_b, const int* t,
+                                        uint32_t col, const RotDev* rots, int nrot,
+                                        const typename V2T<R>::type* phase) {
+  if constexpr (M <= W) {
+    if (m == M)
+      alpha_body<W, M, REAL, R>(vec, dim_b, t, col, rots, nrot, phase);
+    else
+      alpha_m<W, REAL, R, M + 1>(m, vec, dim_b, t, col, rots, nrot, phase);
+  }
+}
+
+template <int W, bool REAL, class R, int M = 0>
+__device__ __forceinline__ void beta_m(int m, typename V2T<R>::type* rowp, const int* t,
+                                       const RotDev* rots, int nrot,
+                                       const typename V2T<R>::type* phase) {
+  if constexpr (M <= W) {
+    if (m == M)
+      beta_body<W, M, REAL, R>(rowp, t, rots, nrot, phase);
+    else
+      beta_m<W, REAL, R, M + 1>(m, rowp, t, rots, nrot, phase);
+  }
+}
+
+template <int W, bool REAL, class R>
+__global__ __launch_bounds__(256) void k_win_alpha(typename V2T<R>::type* __restrict__ vec,
+                                                   int64_t dim_b, WinDev wt,
+                                                   const RotDev* __restrict__ rots, int nrot,
+                                                   const typename V2T<R>::type* __restrict__ phase) {
+  const int cl = wt.cls[blockIdx.x];
+  const int ch = cl >> 6, lane = cl & 63;
+  const uint32_t col = blockIdx.y * 256 + threadIdx.x;
+  if ((int64_t)col >= dim_b) return;
+  const int m = wt.chunk_m[ch];
+  // classes with an empty or full window only need touching for a phase
+  if (!phase && (m == 0 || m == W)) return;
+  const int* t = wt.tab + wt.chunk_off[ch] + lane;
+  alpha_m<W, REAL, R>(m, vec, dim_b, t, col, rots, nrot, phase);
+}
+
+template <int W, bool REAL, class R>
+__global__ __launch_bounds__(256) void k_win_beta(typename V2T<R>::type* __restrict__ vec,
+                                                  int64_t dim_a, int64_t dim_b, WinDev wt,
+                                                  const RotDev* __restrict__ rots, int nrot,
+                                                  const typename V2T<R>::type* __restrict__ phase) {
+  const int ch = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (row >= dim_a) return;
+  const int m = wt.chunk_m[ch];
+  if (!phase && (m == 0 || m == W)) return;
+  const int* t = wt.tab + wt.chunk_off[ch] + lane;
+  if (t[0] < 0) return;
+  beta_m<W, REAL, R>(m, vec + row * dim_b, t, rots, nrot, phase);
+}
+
+template <int W, bool REAL, class R>
+static void launch_win(int spin, void* vec, int64_t dim_a, int64_t dim_b, const WinDev& wt,
+                       const RotDev* rots, int nrot, const void* phase, hipStream_t s) {
+  using V = typename V2T<R>::type;
+  if (spin == 0) {
+    if (wt.n_cls == 0) return;
+    dim3 grid(wt.n_cls, (unsigned)((dim_b + 255) / 256));
+    hipLaunchKernelGGL((k_win_alpha<W, REAL, R>), grid, dim3(256), 0, s, (V*)vec, dim_b, wt, rots,
+                       nrot, (const V*)phase);
+  } else {
+    if (wt.n_chunks == 0) return;
+    dim3 grid(wt.n_chunks, (unsigned)((dim_a + 3) / 4));
+    hipLaunchKernelGGL((k_win_beta<W, REAL, R>), grid, dim3(256), 0, s, (V*)vec, dim_a, dim_b, wt,
+                       rots, nrot, (const V*)phase);
+  }
+}
+
+template <bool REAL, class R>
+static void launch_win_w(int spin, void* vec, int64_t dim_a, int64_t dim_b, const WinDev& wt,
+                         const RotDev* rots, int nrot, const void* phase, hipStream_t s) {
+  switch (wt.w) {
+    case 1: launch_win<1, REAL, R>(spin, vec, dim_a, dim_b, wt, rots, nrot, phase, s); break;
+    case 2: launch_win<2, REAL, R>(spin, vec, dim_a, dim_b, wt, rots, nrot, phase, s); break;
+    case 3: launch_win<3, REAL, R>(spin, vec, dim_a, dim_b, wt, rots, nrot, phase, s); break;
+    case 4: launch_win<4, REAL, R>(spin, vec, dim_a, dim_b, wt, rots, nrot, phase, s); break;
+    case 5: launch_win<5, REAL, R>(spin, vec, dim_a, dim_b, wt, rots, nrot, phase, s); break;
+    case 6: launch_win<6, REAL, R>(spin, vec, dim_a, dim_b, wt, rots, nrot, phase, s); break;
+    case 7:
+      if constexpr (sizeof(R) == 4) launch_win<7, REAL, R>(spin, vec, dim_a, dim_b, wt, rots, nrot, phase, s);
+      break;
+    default: break;
+  }
+}
+
+void win_pass(bool c64, bool real, int spin, void* vec, int64_t dim_a, int64_t dim_b,
+              const WinDev& wt, const RotDev* rots, int nrot, const void* phase,
+              hipStream_t stream) {
+  if (c64) {
+    if (real)
+      launch_win_w<true, float>(spin, vec, dim_a, dim_b, wt, rots, nrot, phase, stream);
+    else
+      launch_win_w<false, float>(spin, vec, dim_a, dim_b, wt, rots, nrot, phase, stream);
+  } else {
+    if (real)
+      launch_win_w<true, double>(spin, vec, dim_a, dim_b, wt, rots, nrot, phase, stream);
+    else
+      launch_win_w<false, double>(spin, vec, dim_a, dim_b, wt, rots, nrot, phase, stream);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-string tables
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ typename V2T<R>::type phase_factor(double ang);
+template <>
+__device__ __forceinline__ zc128 phase_factor<double>(double ang) {
+  double s, c;
+  sincos(ang, &s, &c);
+  return zc128{c, s};
+}
+template <>
+__device__ __forceinline__ zc64 phase_factor<float>(double ang) {
+  // the angle stays FP64; reduce to [-pi, pi] before the FP32 sincos
+  const double twopi = 6.283185307179586476925286766559;
+  double r = ang - twopi * rint(ang / twopi);
+  float s, c;
+  sincosf((float)r, &s, &c);
+  return zc64{c, s};
+}
+
+template <class R>
+__global__ void k_string_phase(const uint32_t* __restrict__ masks, int64_t n,
+                               const double* __restrict__ delta, int norb,
+                               typename V2T<R>::type* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t m = masks[i];
+  double ang = 0;
+  while (m) {
+    int p = __builtin_ctz(m);
+    ang += delta[p];
+    m &= m - 1;
+  }
+  out[i] = phase_factor<R>(ang);
+}
+
+void string_phase(bool c64, const uint32_t* masks, int64_t n, const double* delta, int norb,
+                  void* phase, hipStream_t s) {
+  dim3 grid((unsigned)((n + 255) / 256));
+  if (c64)
+    hipLaunchKernelGGL(k_string_phase<float>, grid, dim3(256), 0, s, masks, n, delta, norb, (zc64*)phase);
+  else
+    hipLaunchKernelGGL(k_string_phase<double>, grid, dim3(256), 0, s, masks, n, delta, norb, (zc128*)phase);
+}
+
+__global__ void k_diag_tables(const uint32_t* __restrict__ ma, int64_t da, const uint32_t* __restrict__ mb,
+                              int64_t db, int norb, DiagSpecDev sp, double* __restrict__ A,
+                              double* __restrict__ B, double* __restrict__ V) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < da && A) {
+    uint32_t m = ma[i];
+    double acc = 0;
+    for (int p = 0; p < norb; ++p) {
+      if (!((m >> p) & 1)) continue;
+      if (sp.lin_a) acc += sp.lin_a[p];
+      if (sp.Qa)
+        for (int q = 0; q < norb; ++q)
+          if ((m >> q) & 1) acc += 0.5 * sp.Qa[p * norb + q];
+    }
+    A[i] = acc;
+  }
+  if (i < db) {
+    uint32_t m = mb[i];
+    if (B) {
+      double acc = 0;
+      for (int p = 0; p < norb; ++p) {
+        if (!((m >> p) & 1)) continue;
+        if (sp.lin_b) acc += sp.lin_b[p];
+        if (sp.Qb)
+          for (int q = 0; q < norb; ++q)
+            if ((m >> q) & 1) acc += 0.5 * sp.Qb[p * norb + q];
+      }
+      B[i] = acc;
+    }
+    if (V && sp.C) {
+      for (int p = 0; p < norb; ++p) {
+        double acc = 0;
+        for (int q = 0; q < norb; ++q)
+          if ((m >> q) & 1) acc += sp.C[p * norb + q];
+        V[(int64_t)p * db + i] = acc;
+      }
+    }
+  }
+}
+
+void diag_tables(const uint32_t* masks_a, int64_t dim_a, const uint32_t* masks_b, int64_t dim_b,
+                 int norb, const DiagSpecDev& spec, double* A, double* B, double* V,
+                 hipStream_t s) {
+  int64_t n = dim_a > dim_b ? dim_a : dim_b;
+  hipLaunchKernelGGL(k_diag_tables, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, masks_a, dim_a,
+                     masks_b, dim_b, norb, spec, A, B, V);
+}
+
+// ---------------------------------------------------------------------------
+// diagonal operations: thread <-> column, block <-> (256 columns, ROWS rows)
+// ---------------------------------------------------------------------------
+constexpr int DIAG_ROWS = 16;
+
+template <int NM>
+struct DiagCol {
+  double vb[NM];
+  double B;
+  __device__ __forceinline__ void load(const DiagDev& f, int64_t dim_b, int64_t col, int norb) {
+    B = f.B ? f.B[col] : 0.0;
+#pragma unroll
+    for (int p = 0; p < NM; ++p) vb[p] = (f.V && p < norb) ? f.V[(int64_t)p * dim_b + col] : 0.0;
+  }
+  __device__ __forceinline__ double eval(const DiagDev& f, int64_t row, uint32_t ma) const {
+    double v = B + (f.A ? f.A[row] : 0.0);
+    if (f.V) {
+#pragma unroll
+      for (int p = 0; p < NM; ++p)
+        if ((ma >> p) & 1) v += vb[p];
+    }
+    return v;
+  }
+};
+
+// mode 0: vec *= exp(i scale f); mode 1: vec *= f
+template <int NM, int MODE, class R>
+__global__ __launch_bounds__(256) void k_diag_apply(typename V2T<R>::type* __restrict__ vec, int64_t dim_a,
+                                                    int64_t dim_b, const uint32_t* __restrict__ masks_a,
+                                                    int norb, DiagDev f, double scale) {
+  using V = typename V2T<R>::type;
+  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (col >= dim_b) return;
+  DiagCol<NM> dc;
+  dc.load(f, dim_b, col, norb);
+  const int64_t r0 = (int64_t)blockIdx.y * DIAG_ROWS;
+  const int64_t r1 = r0 + DIAG_ROWS < dim_a ? r0 + DIAG_ROWS : dim_a;
+  for (int64_t row = r0; row < r1; ++row) {
+    double v = dc.eval(f, row, masks_a[row]);
+    V x = vec[row * dim_b + col];
+    if constexpr (MODE == 0) {
+      x = cmul<V, R>(x, phase_factor<R>(scale * v));
+    } else {
+      x.x *= (R)v;
+      x.y *= (R)v;
+    }
+    vec[row * dim_b + col] = x;
+  }
+}
+
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+  __syncthreads();
+  return r;
+}
+
+template <int NM, class R>
+__global__ __launch_bounds__(256) void k_diag_expect(const typename V2T<R>::type* __restrict__ vec,
+                                                     int64_t dim_a, int64_t dim_b,
+                                                     const uint32_t* __restrict__ masks_a, int norb,
+                                                     DiagDev f, double* __restrict__ partials) {
+  using V = typename V2T<R>::type;
+  __shared__ double sh[4];
+  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double acc = 0;
+  if (col < dim_b) {
+    DiagCol<NM> dc;
+    dc.load(f, dim_b, col, norb);
+    const int64_t r0 = (int64_t)blockIdx.y * DIAG_ROWS;
+    const int64_t r1 = r0 + DIAG_ROWS < dim_a ? r0 + DIAG_ROWS : dim_a;
+    for (int64_t row = r0; row < r1; ++row) {
+      double v = dc.eval(f, row, masks_a[row]);
+      V x = vec[row * dim_b + col];
+      acc += v * ((double)x.x * (double)x.x + (double)x.y * (double)x.y);
+    }
+  }
+  double t = block_sum256(acc, sh);
+  if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
+}
+
+static dim3 diag_grid(int64_t dim_a, int64_t dim_b) {
+  return dim3((unsigned)((dim_b + 255) / 256), (unsigned)((dim_a + DIAG_ROWS - 1) / DIAG_ROWS));
+}
+
+int diag_expect_partials(int64_t dim_a, int64_t dim_b) {
+  dim3 g = diag_grid(dim_a, dim_b);
+  return (int)(g.x * g.y);
+}
+
+template <int MODE, class R>
+static void diag_apply_r(void* vec, int64_t da, int64_t db, const uint32_t* ma, int norb,
+                         const DiagDev& f, double scale, hipStream_t s) {
+  using V = typename V2T<R>::type;
+  dim3 g = diag_grid(da, db);
+  if (norb <= 16)
+    hipLaunchKernelGGL((k_diag_apply<16, MODE, R>), g, dim3(256), 0, s, (V*)vec, da, db, ma, norb, f, scale);
+  else
+    hipLaunchKernelGGL((k_diag_apply<32, MODE, R>), g, dim3(256), 0, s, (V*)vec, da, db, ma, norb, f, scale);
+}
+
+void diag_phase(bool c64, void* vec, int64_t da, int64_t db, const uint32_t* ma, int norb,
+                const DiagDev& f, double scale, hipStream_t s) {
+  if (c64)
+    diag_apply_r<0, float>(vec, da, db, ma, norb, f, scale, s);
+  else
+    diag_apply_r<0, double>(vec, da, db, ma, norb, f, scale, s);
+}
+
+void diag_scale(bool c64, void* vec, int64_t da, int64_t db, const uint32_t* ma, int norb,
+                const DiagDev& f, hipStream_t s) {
+  if (c64)
+    diag_apply_r<1, float>(vec, da, db, ma, norb, f, 0.0, s);
+  else
+    diag_apply_r<1, double>(vec, da, db, ma, norb, f, 0.0, s);
+}
+
+template <class R>
+static int diag_expect_r(const void* vec, int64_t da, int64_t db, const uint32_t* ma, int norb,
+                         const DiagDev& f, double* partials, hipStream_t s) {
+  using V = typename V2T<R>::type;
+  dim3 g = diag_grid(da, db);
+  if (norb <= 16)
+    hipLaunchKernelGGL((k_diag_expect<16, R>), g, dim3(256), 0, s, (const V*)vec, da, db, ma, norb, f, partials);
+  else
+    hipLaunchKernelGGL((k_diag_expect<32, R>), g, dim3(256), 0, s, (const V*)vec, da, db, ma, norb, f, partials);
+  return (int)(g.x * g.y);
+}
+
+int diag_expect(bool c64, const void* vec, int64_t da, int64_t db, const uint32_t* ma, int norb,
+                const DiagDev& f, double* partials, hipStream_t s) {
+  return c64 ? diag_expect_r<float>(vec, da, db, ma, norb, f, partials, s)
+             : diag_expect_r<double>(vec, da, db, ma, norb, f, partials, s);
+}
+
+// fixed-order sum of n doubles (one block): each thread sums a strided slice,
+// then a fixed tree over the block
+__global__ __launch_bounds__(256) void k_sum(const double* __restrict__ in, int n, int stride_out,
+                                             double* __restrict__ out) {
+  __shared__ double sh[4];
+  double acc = 0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += in[(int64_t)i * stride_out + blockIdx.x];
+  double t = block_sum256(acc, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+void sum_partials(const double* partials, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, partials, n, 1, out);
+}
+
+// <x|y> = sum conj(x) y, partials (re, im) interleaved per block
+constexpr int INNER_PER_THREAD = 16;
+int inner_partials(int64_t n) { return (int)((n + 256 * INNER_PER_THREAD - 1) / (256 * INNER_PER_THREAD)); }
+
+template <class R>
+__global__ __launch_bounds__(256) void k_inner(const typename V2T<R>::type* __restrict__ x,
+                                               const typename V2T<R>::type* __restrict__ y, int64_t n,
+                                               double* __restrict__ partials) {
+  __shared__ double sh[4];
+  double re = 0, im = 0;
+  const int64_t base = (int64_t)blockIdx.x * 256 * INNER_PER_THREAD + threadIdx.x;
+  for (int k = 0; k < INNER_PER_THREAD; ++k) {
+    int64_t i = base + (int64_t)k * 256;
+    if (i < n) {
+      double ax = x[i].x, ay = x[i].y, bx = y[i].x, by = y[i].y;
+      re += ax * bx + ay * by;
+      im += ax * by - ay * bx;
+    }
+  }
+  double tr = block_sum256(re, sh);
+  double ti = block_sum256(im, sh);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = tr;
+    partials[2 * blockIdx.x + 1] = ti;
+  }
+}
+
+void inner(bool c64, const void* x, const void* y, int64_t n, double* partials, double* out,
+           hipStream_t s) {
+  int nb = inner_partials(n);
+  if (c64)
+    hipLaunchKernelGGL(k_inner<float>, dim3(nb), dim3(256), 0, s, (const zc64*)x, (const zc64*)y, n, partials);
+  else
+    hipLaunchKernelGGL(k_inner<double>, dim3(nb), dim3(256), 0, s, (const zc128*)x, (const zc128*)y, n, partials);
+  hipLaunchKernelGGL(k_sum, dim3(2), dim3(256), 0, s, partials, nb, 2, out);
+}
+
+// ---------------------------------------------------------------------------
+// elementwise helpers
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ void k_axpy(const typename V2T<R>::type* __restrict__ x, typename V2T<R>::type* __restrict__ y,
+                       int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    auto a = x[i];
+    auto b = y[i];
+    b.x += a.x;
+    b.y += a.y;
+    y[i] = b;
+  }
+}
+
+void axpy(bool c64, const void* x, void* y, int64_t n, hipStream_t s) {
+  dim3 g((unsigned)((n + 255) / 256));
+  if (c64)
+    hipLaunchKernelGGL(k_axpy<float>, g, dim3(256), 0, s, (const zc64*)x, (zc64*)y, n);
+  else
+    hipLaunchKernelGGL(k_axpy<double>, g, dim3(256), 0, s, (const zc128*)x, (zc128*)y, n);
+}
+
+template <class R>
+__global__ void k_outer(const zc128* __restrict__ a, const zc128* __restrict__ b,
+                        typename V2T<R>::type* __restrict__ vec, int64_t da, int64_t db) {
+  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = blockIdx.y;
+  if (col >= db || row >= da) return;
+  zc128 x = a[row], y = b[col];
+  typename V2T<R>::type r;
+  r.x = (R)(x.x * y.x - x.y * y.y);
+  r.y = (R)(x.x * y.y + x.y * y.x);
+  vec[row * db + col] = r;
+}
+
+void outer(bool c64, const double* a, const double* b, void* vec, int64_t da, int64_t db,
+           hipStream_t s) {
+  dim3 g((unsigned)((db + 255) / 256), (unsigned)da);
+  if (c64)
+    hipLaunchKernelGGL(k_outer<float>, g, dim3(256), 0, s, (const zc128*)a, (const zc128*)b, (zc64*)vec, da, db);
+  else
+    hipLaunchKernelGGL(k_outer<double>, g, dim3(256), 0, s, (const zc128*)a, (const zc128*)b, (zc128*)vec, da, db);
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_transpose(const typename V2T<R>::type* __restrict__ src,
+                                                   typename V2T<R>::type* __restrict__ dst, int64_t rows,
+                                                   int64_t cols) {
+  using V = typename V2T<R>::type;
+  __shared__ V tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+  for (int k = 0; k < 32; k += 8) {
+    int64_t r = r0 + ty + k, c = c0 + tx;
+    if (r < rows && c < cols) tile[ty + k][tx] = src[r * cols + c];
+  }
+  __syncthreads();
+  for (int k = 0; k < 32; k += 8) {
+    int64_t c = c0 + ty + k, r = r0 + tx;
+    if (r < rows && c < cols) dst[c * rows + r] = tile[tx][ty + k];
+  }
+}
+
+void transpose(bool c64, const void* src, void* dst, int64_t rows, int64_t cols, hipStream_t s) {
+  dim3 g((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+  if (c64)
+    hipLaunchKernelGGL(k_transpose<float>, g, dim3(256), 0, s, (const zc64*)src, (zc64*)dst, rows, cols);
+  else
+    hipLaunchKernelGGL(k_transpose<double>, g, dim3(256), 0, s, (const zc128*)src, (zc128*)dst, rows, cols);
+}
+
+// ---------------------------------------------------------------------------
+// transition one-body matrix of the row spin
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(256) void k_rdm_rows(const typename V2T<R>::type* __restrict__ lam,
+                                                  const typename V2T<R>::type* __restrict__ psi,
+                                                  int64_t rows, int64_t cols,
+                                                  const uint32_t* __restrict__ masks, int norb,
+                                                  double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int64_t i = blockIdx.x;
+  const uint32_t I = masks[i];
+  const auto* prow = psi + i * cols;
+  for (int p = 0; p < norb; ++p) {
+    for (int q = 0; q < norb; ++q) {
+      double* dst = part + 2 * ((int64_t)(p * norb + q) * rows + i);
+      const bool exc = ((I >> q) & 1) && (p == q || !((I >> p) & 1));
+      if (!exc) {
+        if (threadIdx.x == 0) {
+          dst[0] = 0.0;
+          dst[1] = 0.0;
+        }
+        continue;
+      }
+      uint32_t J = (I & ~(1u << q)) | (1u << p);
+      int lo = p < q ? p : q, hi = p < q ? q : p;
+      uint32_t between = (hi - lo > 1) ? (I >> (lo + 1)) & ((1u << (hi - lo - 1)) - 1) : 0u;
+      const double sign = (__builtin_popcount(between) & 1) ? -1.0 : 1.0;
+      const auto* lrow = lam + (int64_t)colex_rank(J) * cols;
+      double re = 0, im = 0;
+      for (int64_t c = threadIdx.x; c < cols; c += 256) {
+        auto a = lrow[c];
+        auto b = prow[c];
+        double ax = a.x, ay = a.y, bx = b.x, by = b.y;
+        re += ax * bx + ay * by;
+        im += ax * by - ay * bx;
+      }
+      double tr = block_sum256(re, sh);
+      double ti = block_sum256(im, sh);
+      if (threadIdx.x == 0) {
+        dst[0] = sign * tr;
+        dst[1] = sign * ti;
+      }
+    }
+  }
+}
+
+void rdm_rows(bool c64, const void* lam, const void* psi, int64_t rows, int64_t cols,
+              const uint32_t* masks_rows, int norb, double* part, hipStream_t s) {
+  if (c64)
+    hipLaunchKernelGGL(k_rdm_rows<float>, dim3((unsigned)rows), dim3(256), 0, s, (const zc64*)lam,
+                       (const zc64*)psi, rows, cols, masks_rows, norb, part);
+  else
+    hipLaunchKernelGGL(k_rdm_rows<double>, dim3((unsigned)rows), dim3(256), 0, s, (const zc128*)lam,
+                       (const zc128*)psi, rows, cols, masks_rows, norb, part);
+}
+
+__global__ __launch_bounds__(256) void k_rdm_reduce(const double* __restrict__ part, int64_t rows,
+                                                    double* __restrict__ T) {
+  __shared__ double sh[4];
+  const int64_t pq = blockIdx.x;
+  double re = 0, im = 0;
+  for (int64_t i = threadIdx.x; i < rows; i += 256) {
+    re += part[2 * (pq * rows + i)];
+    im += part[2 * (pq * rows + i) + 1];
+  }
+  double tr = block_sum256(re, sh);
+  double ti = block_sum256(im, sh);
+  if (threadIdx.x == 0) {
+    T[2 * pq] = tr;
+    T[2 * pq + 1] = ti;
+  }
+}
+
+void rdm_reduce(const double* part, int64_t rows, int norb, double* T, hipStream_t s) {
+  hipLaunchKernelGGL(k_rdm_reduce, dim3(norb * norb), dim3(256), 0, s, part, rows, T);
+}
+
+// ---------------------------------------------------------------------------
+// diagonal-gate gradient reductions
+// ---------------------------------------------------------------------------
+template <int NM, class R>
+__global__ __launch_bounds__(256) void k_diag_grad_rows(const typename V2T<R>::type* __restrict__ lam,
+                                                        const typename V2T<R>::type* __restrict__ psi,
+                                                        int64_t dim_a, int64_t dim_b,
+                                                        const uint32_t* __restrict__ masks_b, int norb,
+                                                        double* __restrict__ rowout) {
+  __shared__ double sh[4];
+  const int64_t row = blockIdx.x;
+  double acc[2 * NM];
+#pragma unroll
+  for (int k = 0; k < 2 * NM; ++k) acc[k] = 0;
+  for (int64_t c = threadIdx.x; c < dim_b; c += 256) {
+    auto a = lam[row * dim_b + c];
+    auto b = psi[row * dim_b + c];
+    double z = (double)a.x * (double)b.y - (double)a.y * (double)b.x;
+    uint32_t m = masks_b[c];
+    acc[0] += z;
+#pragma unroll
+    for (int p = 0; p < NM; ++p) {
+      double bp = (double)((m >> p) & 1);
+      acc[1 + p] += z * bp;
+      if (p + 1 < NM) acc[1 + NM + p] += z * bp * (double)((m >> (p + 1)) & 1);
+    }
+  }
+  // layout per row: [0] = 1, [1 + p] = x_b[p], [1 + norb + p] = x_b[p] x_b[p+1]
+#pragma unroll
+  for (int k = 0; k < 2 * NM; ++k) {
+    double t = block_sum256(acc[k], sh);
+    if (threadIdx.x == 0) {
+      if (k == 0) rowout[row * 2 * norb] = t;
+      else if (k <= NM) {
+        int p = k - 1;
+        if (p < norb) rowout[row * 2 * norb + 1 + p] = t;
+      } else {
+        int p = k - 1 - NM;
+        if (p < norb - 1) rowout[row * 2 * norb + 1 + norb + p] = t;
+      }
+    }
+  }
+}
+
+void diag_grad_rows(bool c64, const void* lam, const void* psi, int64_t da, int64_t db,
+                    const uint32_t* masks_b, int norb, double* rowout, hipStream_t s) {
+  if (c64) {
+    if (norb <= 16)
+      hipLaunchKernelGGL((k_diag_grad_rows<16, float>), dim3((unsigned)da), dim3(256), 0, s, (const zc64*)lam,
+                         (const zc64*)psi, da, db, masks_b, norb, rowout);
+    else
+      hipLaunchKernelGGL((k_diag_grad_rows<32, float>), dim3((unsigned)da), dim3(256), 0, s, (const zc64*)lam,
+                         (const zc64*)psi, da, db, masks_b, norb, rowout);
+  } else {
+    if (norb <= 16)
+      hipLaunchKernelGGL((k_diag_grad_rows<16, double>), dim3((unsigned)da), dim3(256), 0, s, (const zc128*)lam,
+                         (const zc128*)psi, da, db, masks_b, norb, rowout);
+    else
+      hipLaunchKernelGGL((k_diag_grad_rows<32, double>), dim3((unsigned)da), dim3(256), 0, s, (const zc128*)lam,
+                         (const zc128*)psi, da, db, masks_b, norb, rowout);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_diag_grad_combine(const double* __restrict__ rowout, int64_t dim_a,
+                                                           const uint32_t* __restrict__ masks_a, int norb,
+                                                           double* __restrict__ out) {
+  __shared__ double sh[4];
+  const int k = blockIdx.x;  // 0 .. 2 norb - 2
+  double acc = 0;
+  for (int64_t i = threadIdx.x; i < dim_a; i += 256) {
+    uint32_t m = masks_a[i];
+    const double* r = rowout + i * 2 * norb;
+    if (k < norb - 1) {
+      int p = k;
+      double both = (double)(((m >> p) & 1) & ((m >> (p + 1)) & 1));
+      acc += both * r[0] + r[1 + norb + p];
+    } else {
+      int p = k - (norb - 1);
+      acc += (double)((m >> p) & 1) * r[1 + p];
+    }
+  }
+  double t = block_sum256(acc, sh);
+  if (threadIdx.x == 0) out[k] = 2.0 * t;
+}
+
+void diag_grad_combine(const double* rowout, int64_t dim_a, const uint32_t* masks_a, int norb,
+                       double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_grad_combine, dim3(2 * norb - 1), dim3(256), 0, s, rowout, dim_a, masks_a,
+                     norb, out);
+}
+
+}  // namespace dev
+}  // namespace ffx

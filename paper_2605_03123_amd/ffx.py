@@ -1,0 +1,344 @@
+"""Python binding of libffx (include/ffx.h): argument marshalling only.
+
+Every operation runs in the HIP kernels of libffx.so; torch is used for device
+memory and the current HIP stream.  Importing this module loads the library
+and raises ImportError if it has not been built (python -m
+paper_2605_03123_amd.build) -- there is no fallback path.
+
+State vectors are torch tensors of dtype complex128 or complex64 on a ROCm
+device, shaped (dim_a, dim_b) (or flat), contiguous, alpha-major as in the
+paper's representation (Sec. 3.1).  Functions return a new tensor unless
+``out`` is given (``out=vec`` evolves in place), following the functional style
+of Sec. 4.1.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from functools import lru_cache
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libffx.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"libffx.so not found at {_LIB_PATH}; build it with `python -m paper_2605_03123_amd.build`")
+_lib = ctypes.CDLL(_LIB_PATH)
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+_c_u64_p = ctypes.POINTER(ctypes.c_uint64)
+
+FFX_C128, FFX_C64 = 0, 1
+ERRORS = {-1: "FFX_EINVAL", -2: "FFX_ENOTUNITARY", -3: "FFX_ENOMEM", -4: "FFX_EDEVICE", -5: "FFX_EUNSUPPORTED"}
+
+
+class FFXError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _DFHam(ctypes.Structure):
+    _fields_ = [("norb", ctypes.c_int), ("n_terms", ctypes.c_int), ("h", _c_double_p),
+                ("J", _c_double_p), ("U", _c_double_p)]
+
+
+class _LUCJ(ctypes.Structure):
+    _fields_ = [("norb", ctypes.c_int), ("n_reps", ctypes.c_int), ("params", _c_double_p)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_vp = ctypes.c_void_p
+_last_error = _sig("ffx_last_error", ctypes.c_char_p, [])
+_dim = _sig("ffx_dim", ctypes.c_int64, [ctypes.c_int, ctypes.c_int])
+_strings = _sig("ffx_strings", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_u64_p])
+_givens = _sig("ffx_givens_decomposition", ctypes.c_int,
+               [ctypes.c_int, _c_double_p, _c_int_p, _c_double_p, _c_double_p, _c_double_p])
+_plan_create = _sig("ffx_plan_create", ctypes.c_int,
+                    [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int])
+_plan_destroy = _sig("ffx_plan_destroy", ctypes.c_int, [_vp])
+_plan_info = _sig("ffx_plan_info", ctypes.c_int,
+                  [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)])
+_plan_strings = _sig("ffx_plan_strings", ctypes.c_int, [_vp, ctypes.c_int, _c_u64_p])
+_rot = _sig("ffx_apply_orbital_rotation", ctypes.c_int, [_vp, _vp, _c_double_p, _c_double_p, _vp])
+_numop = _sig("ffx_apply_num_op_sum_evolution", ctypes.c_int,
+              [_vp, _vp, _c_double_p, _c_double_p, ctypes.c_double, _vp])
+_dc = _sig("ffx_apply_diag_coulomb_evolution", ctypes.c_int,
+           [_vp, _vp, _c_double_p, _c_double_p, _c_double_p, ctypes.c_double, _vp])
+_trotter = _sig("ffx_apply_df_trotter_step", ctypes.c_int,
+                [_vp, _vp, ctypes.POINTER(_DFHam), ctypes.c_double, ctypes.c_int, ctypes.c_int, _vp])
+_lucj_np = _sig("ffx_lucj_n_params", ctypes.c_int, [ctypes.c_int, ctypes.c_int])
+_lucj = _sig("ffx_apply_lucj", ctypes.c_int, [_vp, _vp, ctypes.POINTER(_LUCJ), _vp])
+_ws = _sig("ffx_workspace_bytes", ctypes.c_int64, [_vp, ctypes.c_int])
+_energy = _sig("ffx_df_energy", ctypes.c_int, [_vp, _vp, ctypes.POINTER(_DFHam), _c_double_p, _vp, _vp])
+_egrad = _sig("ffx_lucj_energy_grad", ctypes.c_int,
+              [_vp, ctypes.POINTER(_LUCJ), ctypes.POINTER(_DFHam), _c_double_p, _c_double_p, _vp, _vp, _vp])
+
+
+def _check(code: int):
+    if code != 0:
+        raise FFXError(code, _last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_c_double_p)
+
+
+def _real(m, shape=None) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(m, dtype=np.float64))
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _cplx(m, shape=None) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a.view(np.float64)
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# host-only helpers
+# ---------------------------------------------------------------------------
+
+def dim(norb: int, n: int) -> int:
+    d = _dim(norb, n)
+    if d < 0:
+        raise ValueError("bad norb / n")
+    return int(d)
+
+
+def strings(norb: int, n: int) -> np.ndarray:
+    out = np.zeros(dim(norb, n), dtype=np.uint64)
+    _check(_strings(norb, n, out.ctypes.data_as(_c_u64_p)))
+    return out
+
+
+def givens_decomposition(U):
+    """-> (p, c, s, phase) with U = diag(exp(i phase)) G_K ... G_1 (host, FP64)."""
+    U = np.asarray(U)
+    norb = U.shape[0]
+    Uc = _cplx(U, (norb, norb))
+    K = norb * (norb - 1) // 2
+    p = np.zeros(K, dtype=np.int32)
+    c = np.zeros(K)
+    s = np.zeros(K, dtype=np.complex128)
+    ph = np.zeros(norb)
+    _check(_givens(norb, _dptr(Uc), p.ctypes.data_as(_c_int_p), _dptr(c), _dptr(s.view(np.float64)), _dptr(ph)))
+    return p, c, s, ph
+
+
+# ---------------------------------------------------------------------------
+# plans
+# ---------------------------------------------------------------------------
+
+class Plan:
+    """Device tables for one (norb, nelec, dtype, device); see ffx_plan_create."""
+
+    def __init__(self, norb: int, nelec, dtype=torch.complex128, device=0):
+        if isinstance(device, torch.device):
+            device = device.index or 0
+        self.norb = int(norb)
+        self.nelec = (int(nelec[0]), int(nelec[1]))
+        self.dtype = dtype
+        self.device = int(device)
+        code = {torch.complex128: FFX_C128, torch.complex64: FFX_C64}.get(dtype)
+        if code is None:
+            raise ValueError("dtype must be torch.complex128 or torch.complex64")
+        h = _vp()
+        _check(_plan_create(ctypes.byref(h), self.norb, self.nelec[0], self.nelec[1], code, self.device))
+        self._h = h
+        da, db, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(_plan_info(h, ctypes.byref(da), ctypes.byref(db), ctypes.byref(nb)))
+        self.dim_a, self.dim_b, self.state_bytes = da.value, db.value, nb.value
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def strings(self, spin: int) -> np.ndarray:
+        out = np.zeros(self.dim_b if spin else self.dim_a, dtype=np.uint64)
+        _check(_plan_strings(self._h, spin, out.ctypes.data_as(_c_u64_p)))
+        return out
+
+    def workspace(self, what: int) -> torch.Tensor:
+        n = int(_ws(self._h, what))
+        ws = self._ws.get(what)
+        if ws is None or ws.numel() < n:
+            ws = torch.empty(n, dtype=torch.uint8, device=f"cuda:{self.device}")
+            self._ws[what] = ws
+        return ws
+
+    def check_vec(self, vec: torch.Tensor):
+        if vec.dtype != self.dtype:
+            raise TypeError(f"state dtype {vec.dtype} does not match the plan ({self.dtype})")
+        if not vec.is_cuda or (vec.device.index or 0) != self.device:
+            raise ValueError("state must live on the plan's device")
+        if not vec.is_contiguous():
+            raise ValueError("state must be contiguous")
+        if vec.numel() != self.dim_a * self.dim_b:
+            raise ValueError(f"state has {vec.numel()} entries, expected {self.dim_a} x {self.dim_b}")
+
+
+@lru_cache(maxsize=64)
+def _plan_cached(norb, nelec, dtype, device) -> Plan:
+    return Plan(norb, nelec, dtype, device)
+
+
+def get_plan(norb: int, nelec, dtype=torch.complex128, device=0) -> Plan:
+    return _plan_cached(int(norb), (int(nelec[0]), int(nelec[1])), dtype, int(device))
+
+
+def _prepare(vec: torch.Tensor, norb, nelec, out):
+    plan = get_plan(norb, nelec, vec.dtype, vec.device.index or 0)
+    plan.check_vec(vec)
+    if out is None:
+        out = vec.clone()
+    elif out is not vec:
+        plan.check_vec(out)
+        out.copy_(vec)
+    return plan, out
+
+
+def _df_struct(ham, norb):
+    h = _real(ham.h, (norb, norb))
+    L = int(np.asarray(ham.J).shape[0])
+    J = _real(ham.J, (L, norb, norb)) if L else np.zeros((0, norb, norb))
+    U = _cplx(ham.U, (L, norb, norb)) if L else np.zeros((0, norb, norb, 2))
+    keep = (h, J, U)
+    s = _DFHam(norb, L, _dptr(h), _dptr(J), _dptr(U))
+    return s, keep
+
+
+def _lucj_struct(params, norb, n_reps):
+    p = _real(params)
+    if p.size != _lucj_np(norb, n_reps):
+        raise ValueError(f"expected {_lucj_np(norb, n_reps)} LUCJ parameters, got {p.size}")
+    return _LUCJ(norb, n_reps, _dptr(p)), p
+
+
+# ---------------------------------------------------------------------------
+# gates (Table 1)
+# ---------------------------------------------------------------------------
+
+def apply_orbital_rotation(vec: torch.Tensor, U, norb: int, nelec, *, U_b=None, out=None) -> torch.Tensor:
+    plan, out = _prepare(vec, norb, nelec, out)
+    Ua = _cplx(U, (norb, norb))
+    Ub = _cplx(U_b, (norb, norb)) if U_b is not None else None
+    _check(_rot(plan.handle, _vp(out.data_ptr()), _dptr(Ua), _dptr(Ub) if Ub is not None else None,
+                _stream(out.device)))
+    return out
+
+
+def apply_num_op_sum_evolution(vec: torch.Tensor, lam, time: float, norb: int, nelec, *, lam_b=None,
+                               out=None) -> torch.Tensor:
+    plan, out = _prepare(vec, norb, nelec, out)
+    la = _real(lam, (norb,))
+    lb = _real(lam_b, (norb,)) if lam_b is not None else None
+    _check(_numop(plan.handle, _vp(out.data_ptr()), _dptr(la), _dptr(lb) if lb is not None else None,
+                  float(time), _stream(out.device)))
+    return out
+
+
+def apply_diag_coulomb_evolution(vec: torch.Tensor, J, time: float, norb: int, nelec, *, J_ab=None, J_bb=None,
+                                 out=None) -> torch.Tensor:
+    plan, out = _prepare(vec, norb, nelec, out)
+    Jaa = _real(J, (norb, norb))
+    Jab = _real(J_ab, (norb, norb)) if J_ab is not None else None
+    Jbb = _real(J_bb, (norb, norb)) if J_bb is not None else None
+    _check(_dc(plan.handle, _vp(out.data_ptr()), _dptr(Jaa), _dptr(Jab) if Jab is not None else None,
+               _dptr(Jbb) if Jbb is not None else None, float(time), _stream(out.device)))
+    return out
+
+
+def simulate_trotter_double_factorized(vec: torch.Tensor, ham, time: float, norb: int, nelec, *,
+                                       n_steps: int = 1, order: int = 0, out=None) -> torch.Tensor:
+    """exp(-i H time) vec by n_steps steps of the order-`order` product formula (Sec. 4.5.3)."""
+    plan, out = _prepare(vec, norb, nelec, out)
+    s, keep = _df_struct(ham, norb)
+    dt = float(time) / max(n_steps, 1)
+    _check(_trotter(plan.handle, _vp(out.data_ptr()), ctypes.byref(s), dt, int(n_steps), int(order),
+                    _stream(out.device)))
+    return out
+
+
+def apply_lucj(params, norb: int, nelec, n_reps: int, *, dtype=torch.complex128, device=0,
+               out=None) -> torch.Tensor:
+    plan = get_plan(norb, nelec, dtype, device)
+    if out is None:
+        out = torch.empty((plan.dim_a, plan.dim_b), dtype=dtype, device=f"cuda:{device}")
+    plan.check_vec(out)
+    s, keep = _lucj_struct(params, norb, n_reps)
+    _check(_lucj(plan.handle, _vp(out.data_ptr()), ctypes.byref(s), _stream(out.device)))
+    return out
+
+
+def df_energy(vec: torch.Tensor, ham, norb: int, nelec) -> float:
+    plan = get_plan(norb, nelec, vec.dtype, vec.device.index or 0)
+    plan.check_vec(vec)
+    s, keep = _df_struct(ham, norb)
+    ws = plan.workspace(0)
+    e = ctypes.c_double()
+    _check(_energy(plan.handle, _vp(vec.data_ptr()), ctypes.byref(s), ctypes.byref(e), _vp(ws.data_ptr()),
+                   _stream(vec.device)))
+    return e.value
+
+
+def lucj_energy_grad(params, ham, norb: int, nelec, n_reps: int, *, dtype=torch.complex128, device=0,
+                     psi_out: torch.Tensor | None = None):
+    """(E, dE/dtheta) of the LUCJ state under the DF Hamiltonian, by the adjoint method."""
+    plan = get_plan(norb, nelec, dtype, device)
+    s, keep = _lucj_struct(params, norb, n_reps)
+    hs, hkeep = _df_struct(ham, norb)
+    grad = np.zeros(keep.size)
+    e = ctypes.c_double()
+    ws = plan.workspace(1)
+    if psi_out is not None:
+        plan.check_vec(psi_out)
+    _check(_egrad(plan.handle, ctypes.byref(s), ctypes.byref(hs), ctypes.byref(e), _dptr(grad),
+                  _vp(psi_out.data_ptr()) if psi_out is not None else None, _vp(ws.data_ptr()),
+                  _stream(torch.device(f"cuda:{device}"))))
+    return e.value, grad
+
+
+class LUCJEnergy(torch.autograd.Function):
+    """E(theta) for a LUCJ ansatz under a DF Hamiltonian, differentiable in theta.
+
+    forward(params (float64 CPU tensor), ham, norb, nelec, n_reps, dtype) -> 0-dim float64 tensor.
+    The backward multiplies the adjoint gradient computed in forward.
+    """
+
+    @staticmethod
+    def forward(ctx, params, ham, norb, nelec, n_reps, dtype=torch.complex128, device=0):
+        e, g = lucj_energy_grad(params.detach().cpu().numpy(), ham, norb, nelec, n_reps, dtype=dtype,
+                                device=device)
+        ctx.save_for_backward(torch.from_numpy(g).to(params.dtype))
+        return params.new_tensor(e)
+
+    @staticmethod
+    def backward(ctx, g_out):
+        (g,) = ctx.saved_tensors
+        return g_out * g, None, None, None, None, None, None

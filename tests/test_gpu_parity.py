@@ -1,0 +1,223 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle, element by element.
+
+complex128: max |amplitude difference| <= 1e-12 with no phase alignment (every
+gate here has exactly one correct result).  complex64: <= 1e-5 against the
+oracle run on the upcast of the complex64-rounded inputs.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import gates as og
+from oracle import hamiltonian as oh
+from oracle import lucj as ol
+from oracle import strings as ost
+from paper_2605_03123_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.complex128: 1e-12, torch.complex64: 1e-5}
+DTYPES = [torch.complex128, torch.complex64]
+
+
+@pytest.fixture(scope="module")
+def ffx():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2605_03123_amd import ffx as mod
+    return mod
+
+
+def _dims(norb, nelec):
+    return ost.dim(norb, nelec[0]), ost.dim(norb, nelec[1])
+
+
+def _to_dev(vec, dtype):
+    return torch.from_numpy(np.ascontiguousarray(vec)).to(dtype).to("cuda:0")
+
+
+def _ref_input(t):
+    """The oracle's input: the device state's own values (c64 inputs upcast exactly)."""
+    return t.detach().cpu().to(torch.complex128).numpy()
+
+
+def _maxdiff(t, ref):
+    return float(np.max(np.abs(t.detach().cpu().to(torch.complex128).numpy() - ref))) if ref.size else 0.0
+
+
+# sizes that span several 256-column tiles and leave ragged tails, edge sectors included
+ROT_CASES = [
+    (1, (0, 1)), (1, (1, 1)), (2, (1, 1)), (3, (0, 2)), (3, (3, 1)), (4, (2, 2)), (5, (2, 3)),
+    (6, (3, 3)), (7, (3, 4)), (8, (4, 4)), (8, (1, 7)), (9, (4, 5)), (10, (5, 5)), (10, (3, 6)),
+    (11, (5, 4)), (12, (6, 6)),
+]
+
+
+def test_plan_string_tables_bit_exact(ffx):
+    for norb, nelec in [(8, (4, 3)), (12, (6, 6)), (16, (8, 8)), (1, (0, 1))]:
+        p = ffx.get_plan(norb, nelec)
+        for spin in (0, 1):
+            np.testing.assert_array_equal(p.strings(spin), ost.strings(norb, nelec[spin]).astype(np.uint64))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("norb,nelec", ROT_CASES)
+def test_orbital_rotation(ffx, dtype, norb, nelec):
+    r = synth.rng([norb, nelec[0], nelec[1]])
+    da, db = _dims(norb, nelec)
+    vec = _to_dev(synth.random_state(r, da, db), dtype)
+    x = _ref_input(vec)
+    Ua, Ub = synth.random_unitary(r, norb), synth.random_unitary(r, norb)
+    O = synth.random_orthogonal(r, norb)
+    out = ffx.apply_orbital_rotation(vec, Ua, norb, nelec, U_b=Ub)
+    assert _maxdiff(out, og.apply_orbital_rotation(x, Ua, norb, nelec, U_b=Ub)) <= TOL[dtype]
+    out = ffx.apply_orbital_rotation(vec, Ua, norb, nelec)
+    assert _maxdiff(out, og.apply_orbital_rotation(x, Ua, norb, nelec)) <= TOL[dtype]
+    out = ffx.apply_orbital_rotation(vec, O, norb, nelec)
+    assert _maxdiff(out, og.apply_orbital_rotation(x, O, norb, nelec)) <= TOL[dtype]
+    # input untouched by the functional form
+    assert _maxdiff(vec, x) == 0.0
+
+
+def test_orbital_rotation_in_place_and_identity(ffx):
+    norb, nelec = 8, (4, 4)
+    r = synth.rng(5)
+    vec = _to_dev(synth.random_state(r, 70, 70), torch.complex128)
+    x = _ref_input(vec)
+    ffx.apply_orbital_rotation(vec, np.eye(norb), norb, nelec, out=vec)
+    assert _maxdiff(vec, x) <= 1e-15
+    D = np.diag(np.exp(1j * r.normal(size=norb)))
+    out = ffx.apply_orbital_rotation(vec, D, norb, nelec)
+    assert _maxdiff(out, og.apply_orbital_rotation(x, D, norb, nelec)) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("norb,nelec", [(3, (1, 2)), (8, (4, 4)), (10, (5, 4)), (12, (6, 6)), (17, (2, 3))])
+def test_phase_gates(ffx, dtype, norb, nelec):
+    r = synth.rng([7, norb])
+    da, db = _dims(norb, nelec)
+    vec = _to_dev(synth.random_state(r, da, db), dtype)
+    x = _ref_input(vec)
+    la, lb = r.normal(size=norb), r.normal(size=norb)
+    out = ffx.apply_num_op_sum_evolution(vec, la, 0.7, norb, nelec, lam_b=lb)
+    assert _maxdiff(out, og.apply_num_op_sum_evolution(x, la, 0.7, norb, nelec, lam_b=lb)) <= TOL[dtype]
+    Jaa, Jab, Jbb = (synth.random_symmetric(r, norb, 1.0) for _ in range(3))
+    out = ffx.apply_diag_coulomb_evolution(vec, Jaa, 0.3, norb, nelec, J_ab=Jab, J_bb=Jbb)
+    ref = og.apply_diag_coulomb_evolution(x, Jaa, 0.3, norb, nelec, J_ab=Jab, J_bb=Jbb)
+    assert _maxdiff(out, ref) <= TOL[dtype]
+    out = ffx.apply_diag_coulomb_evolution(vec, Jaa, -1.3, norb, nelec)
+    assert _maxdiff(out, og.apply_diag_coulomb_evolution(x, Jaa, -1.3, norb, nelec)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_rotation_coulomb_workload(ffx, dtype):
+    """norb=8 (4,4): U, exp(-1/2 i t sum J n n) with t=0.3, then U^dag on a random state (seed 0)."""
+    w = synth.workload_rotation_coulomb(0)
+    norb, nelec, d = w.norb, w.nelec, w.data
+    vec = _to_dev(d["vec"], dtype)
+    x = _ref_input(vec)
+    out = ffx.apply_orbital_rotation(vec, d["U"], norb, nelec)
+    ffx.apply_diag_coulomb_evolution(out, d["J"], d["t"], norb, nelec, out=out)
+    ffx.apply_orbital_rotation(out, d["U"].conj().T, norb, nelec, out=out)
+    ref = og.apply_orbital_rotation(x, d["U"], norb, nelec)
+    ref = og.apply_diag_coulomb_evolution(ref, d["J"], d["t"], norb, nelec)
+    ref = og.apply_orbital_rotation(ref, d["U"].conj().T, norb, nelec)
+    assert _maxdiff(out, ref) <= TOL[dtype]
+    nrm = float(torch.linalg.vector_norm(out.to(torch.complex128)))
+    assert abs(nrm - np.linalg.norm(ref)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("order,n_steps", [(0, 1), (0, 3), (1, 2), (2, 1)])
+@pytest.mark.parametrize("norb,nelec,L", [(6, (3, 3), 3), (8, (4, 3), 4)])
+def test_df_trotter(ffx, dtype, order, n_steps, norb, nelec, L):
+    r = synth.rng([11, norb, order])
+    ham = synth.df_hamiltonian(r, norb, L)
+    da, db = _dims(norb, nelec)
+    vec = _to_dev(synth.random_state(r, da, db), dtype)
+    x = _ref_input(vec)
+    out = ffx.simulate_trotter_double_factorized(vec, ham, 0.1 * n_steps, norb, nelec, n_steps=n_steps, order=order)
+    ref = oh.simulate_trotter(x, ham, 0.1 * n_steps, norb, nelec, n_steps=n_steps, order=order)
+    assert _maxdiff(out, ref) <= TOL[dtype] * (10 if dtype == torch.complex64 else 1)
+
+
+def test_df_trotter_complex_basis(ffx):
+    r = synth.rng(12)
+    norb, nelec = 7, (3, 4)
+    ham = synth.df_hamiltonian(r, norb, 3)
+    ham.U = np.array([synth.random_unitary(r, norb) for _ in range(3)])
+    vec = _to_dev(synth.random_state(r, 35, 35), torch.complex128)
+    x = _ref_input(vec)
+    out = ffx.simulate_trotter_double_factorized(vec, ham, 0.2, norb, nelec, n_steps=2, order=0)
+    assert _maxdiff(out, oh.simulate_trotter(x, ham, 0.2, norb, nelec, n_steps=2, order=0)) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("norb,nelec,n_reps", [(4, (2, 1), 2), (6, (3, 3), 3), (8, (4, 4), 2), (9, (3, 4), 1)])
+def test_lucj_forward(ffx, dtype, norb, nelec, n_reps):
+    params = synth.lucj_params(synth.rng([13, norb]), norb, n_reps, scale=0.3)
+    out = ffx.apply_lucj(params, norb, nelec, n_reps, dtype=dtype)
+    assert _maxdiff(out, ol.apply_lucj(params, norb, nelec, n_reps)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("norb,nelec", [(4, (2, 2)), (8, (4, 4)), (9, (5, 3))])
+def test_df_energy(ffx, dtype, norb, nelec):
+    r = synth.rng([14, norb])
+    ham = synth.df_hamiltonian(r, norb, norb)
+    da, db = _dims(norb, nelec)
+    vec = _to_dev(synth.random_state(r, da, db), dtype)
+    x = _ref_input(vec)
+    e = ffx.df_energy(vec, ham, norb, nelec)
+    ref = oh.df_energy(x, ham, norb, nelec)
+    assert abs(e - ref.real) <= (1e-10 if dtype == torch.complex128 else 1e-5) * max(1.0, abs(ref.real))
+    assert ffx.df_energy(vec, ham, norb, nelec) == e   # fixed reduction order
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("norb,nelec,n_reps", [(4, (2, 1), 2), (6, (3, 3), 2), (8, (4, 4), 1)])
+def test_lucj_energy_grad_matches_oracle_adjoint(ffx, dtype, norb, nelec, n_reps):
+    r = synth.rng([15, norb])
+    params = synth.lucj_params(r, norb, n_reps, scale=0.3)
+    ham = synth.df_hamiltonian(r, norb, 2)
+    e, g = ffx.lucj_energy_grad(params, ham, norb, nelec, n_reps, dtype=dtype)
+    eo, go = ol.grad_adjoint(params, ham, norb, nelec, n_reps)
+    tol = 1e-10 if dtype == torch.complex128 else 1e-4
+    assert abs(e - eo) <= tol * max(1, abs(eo))
+    assert np.max(np.abs(g - go)) <= tol * max(1, np.max(np.abs(go)))
+
+
+def test_lucj_gradient_matches_central_differences_on_gpu(ffx):
+    norb, nelec, n_reps = 8, (4, 4), 2
+    r = synth.rng(16)
+    params = synth.lucj_params(r, norb, n_reps)
+    ham = synth.df_hamiltonian(r, norb, norb)
+    e, g = ffx.lucj_energy_grad(params, ham, norb, nelec, n_reps)
+    idx = synth.fd_indices(len(params), 10)
+    h = 1e-5
+    for j in idx:
+        d = np.zeros_like(params)
+        d[j] = h
+        ep = ffx.lucj_energy_grad(params + d, ham, norb, nelec, n_reps)[0]
+        em = ffx.lucj_energy_grad(params - d, ham, norb, nelec, n_reps)[0]
+        assert abs((ep - em) / (2 * h) - g[j]) <= 1e-7 * max(1, np.max(np.abs(g)))
+
+
+def test_autograd_function(ffx):
+    norb, nelec, n_reps = 4, (2, 2), 1
+    r = synth.rng(17)
+    p = torch.tensor(synth.lucj_params(r, norb, n_reps, scale=0.3), requires_grad=True)
+    ham = synth.df_hamiltonian(r, norb, 2)
+    E = ffx.LUCJEnergy.apply(p, ham, norb, nelec, n_reps)
+    E.backward()
+    _, go = ol.grad_adjoint(p.detach().numpy(), ham, norb, nelec, n_reps)
+    np.testing.assert_allclose(p.grad.numpy(), go, atol=1e-10)
+
+
+def test_errors_do_not_crash(ffx):
+    vec = torch.zeros((6, 6), dtype=torch.complex128, device="cuda:0")
+    with pytest.raises(ffx.FFXError):
+        ffx.apply_orbital_rotation(vec, np.ones((4, 4)), 4, (2, 2))
+    with pytest.raises(ValueError):
+        ffx.apply_orbital_rotation(vec, np.eye(4), 4, (2, 1))
+    with pytest.raises(TypeError):
+        ffx.apply_orbital_rotation(vec.to(torch.complex64), np.eye(4), 4, (2, 2), out=vec)

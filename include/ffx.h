@@ -159,6 +159,19 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
                          double* energy, double* grad, void* psi_out, void* workspace,
                          void* stream);
 
+/* Diagnostics: per-launch timing of the Givens window-pass kernels (the
+   dominant kernels of every orbital rotation).  While enabled, each pass
+   launch is bracketed by HIP events on the stream it is launched on.
+   ffx_timing_enable resets the counters (enable = 0 stops recording).
+   ffx_timing_read synchronizes on the recorded events and returns, for spin
+   (0 = alpha passes, 1 = beta passes): the summed kernel time in ms, the
+   number of launches, and the algorithmic bytes those launches stand for: a
+   launch applying r of the K = norb(norb-1)/2 rotations of one spin counts
+   r / K of one read plus one write of the state. */
+int ffx_timing_enable(ffx_plan plan, int enable);
+int ffx_timing_read(ffx_plan plan, int spin, double* total_ms, int64_t* launches,
+                    double* algorithmic_bytes);
+
 #ifdef __cplusplus
 }
 #endif

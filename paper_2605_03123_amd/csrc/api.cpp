@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -116,6 +117,32 @@ struct ffx_plan_s {
   double* rowout = nullptr;
   std::vector<void*> allocs;
   static constexpr int kResults = 1 << 16;
+  // diagnostics: event pairs around window-pass launches
+  struct Timed {
+    hipEvent_t a, b;
+    int spin;
+    double alg_bytes;
+  };
+  bool timing = false;
+  std::vector<Timed> timed;
+  std::vector<hipEvent_t> ev_pool;
+  hipEvent_t take_event() {
+    if (!ev_pool.empty()) {
+      hipEvent_t e = ev_pool.back();
+      ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+  }
+  void recycle_timed() {
+    for (auto& t : timed) {
+      ev_pool.push_back(t.a);
+      ev_pool.push_back(t.b);
+    }
+    timed.clear();
+  }
 
   size_t elem() const { return c64 ? 8 : 16; }
   int64_t elems() const { return dim[0] * dim[1]; }
@@ -130,6 +157,8 @@ struct ffx_plan_s {
   }
 
   ~ffx_plan_s() {
+    recycle_timed();
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
@@ -238,9 +267,22 @@ void run_rotation(ffx_plan_s& P, void* vec, const RotProg& rp, hipStream_t s) {
     for (size_t i = 0; i < sp.passes.size(); ++i) {
       const PassProg& pp = sp.passes[i];
       const bool last = i + 1 == sp.passes.size();
+      ffx_plan_s::Timed tm{};
+      if (P.timing) {
+        tm.a = P.take_event();
+        tm.b = P.take_event();
+        tm.spin = sigma;
+        const double K = 0.5 * P.norb * (P.norb - 1);
+        tm.alg_bytes = K > 0 ? (pp.nrot / K) * 2.0 * (double)P.state_bytes() : 0.0;
+        HIPCHK(hipEventRecord(tm.a, s));
+      }
       dev::win_pass(P.c64, sp.real, sigma, vec, P.dim[0], P.dim[1], P.win[sigma][pp.a], pp.rots, pp.nrot,
                     (last && sp.has_phase) ? P.phase_tab[sigma] : nullptr, s);
       check_launch();
+      if (P.timing) {
+        HIPCHK(hipEventRecord(tm.b, s));
+        P.timed.push_back(tm);
+      }
     }
   }
 }
@@ -525,6 +567,10 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
     if (P->dim[0] * P->dim[1] > (int64_t)1 << 40) throw Error(FFX_EINVAL, "state too large");
     if (P->dim[0] >= (1LL << 31) || P->dim[1] >= (1LL << 31)) throw Error(FFX_EINVAL, "dimension too large");
     P->W = std::min(norb, dev::max_window(P->c64));
+    if (const char* e = std::getenv("FFX_WINDOW")) {  // narrower windows, for experiments
+      int w = std::atoi(e);
+      if (w >= 1 && w < P->W) P->W = w;
+    }
     for (int s = 0; s < 2; ++s) {
       for (int a = 0; a + P->W <= norb; ++a) {
         WindowTable t = build_window_table(P->str[s], norb, P->n[s], a, P->W);
@@ -872,6 +918,40 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
       const double* dg = res.data() + 16 + (size_t)L.R * 8 * NN + (size_t)k * (2 * N);
       for (int i = 0; i < 2 * N - 1; ++i) gk[2 * NN + i] = dg[i];
     }
+  });
+}
+
+int ffx_timing_enable(ffx_plan plan, int enable) {
+  return guard([&] {
+    validate_plan(plan);
+    DeviceGuard dg(plan->device);
+    for (auto& t : plan->timed) {
+      HIPCHK(hipEventSynchronize(t.b));
+    }
+    plan->recycle_timed();
+    plan->timing = enable != 0;
+  });
+}
+
+int ffx_timing_read(ffx_plan plan, int spin, double* total_ms, int64_t* launches, double* alg_bytes) {
+  return guard([&] {
+    validate_plan(plan);
+    if (spin != 0 && spin != 1) throw Error(FFX_EINVAL, "bad spin");
+    DeviceGuard dg(plan->device);
+    double ms = 0, bytes = 0;
+    int64_t n = 0;
+    for (auto& t : plan->timed) {
+      if (t.spin != spin) continue;
+      HIPCHK(hipEventSynchronize(t.b));
+      float e = 0;
+      HIPCHK(hipEventElapsedTime(&e, t.a, t.b));
+      ms += e;
+      bytes += t.alg_bytes;
+      ++n;
+    }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = n;
+    if (alg_bytes) *alg_bytes = bytes;
   });
 }
 

@@ -79,6 +79,9 @@ _lucj_np = _sig("ffx_lucj_n_params", ctypes.c_int, [ctypes.c_int, ctypes.c_int])
 _lucj = _sig("ffx_apply_lucj", ctypes.c_int, [_vp, _vp, ctypes.POINTER(_LUCJ), _vp])
 _ws = _sig("ffx_workspace_bytes", ctypes.c_int64, [_vp, ctypes.c_int])
 _energy = _sig("ffx_df_energy", ctypes.c_int, [_vp, _vp, ctypes.POINTER(_DFHam), _c_double_p, _vp, _vp])
+_tenable = _sig("ffx_timing_enable", ctypes.c_int, [_vp, ctypes.c_int])
+_tread = _sig("ffx_timing_read", ctypes.c_int,
+              [_vp, ctypes.c_int, _c_double_p, ctypes.POINTER(ctypes.c_int64), _c_double_p])
 _egrad = _sig("ffx_lucj_energy_grad", ctypes.c_int,
               [_vp, ctypes.POINTER(_LUCJ), ctypes.POINTER(_DFHam), _c_double_p, _c_double_p, _vp, _vp, _vp])
 
@@ -191,6 +194,16 @@ class Plan:
             ws = torch.empty(n, dtype=torch.uint8, device=f"cuda:{self.device}")
             self._ws[what] = ws
         return ws
+
+    def timing(self, enable: bool):
+        """Start (reset) or stop per-launch event timing of the Givens window passes."""
+        _check(_tenable(self._h, int(bool(enable))))
+
+    def timing_read(self, spin: int):
+        """-> (total kernel ms, launches, algorithmic bytes) of the recorded passes of one spin."""
+        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _check(_tread(self._h, spin, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+        return ms.value, n.value, b.value
 
     def check_vec(self, vec: torch.Tensor):
         if vec.dtype != self.dtype:

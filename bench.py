@@ -118,31 +118,45 @@ def main():
     ms = e0.elapsed_time(e1) / args.steps
     norm = float(torch.linalg.vector_norm(vec.to(torch.complex128)))
 
-    # live per-launch timing of the window passes over one more step
+    # live per-launch timing of the dominant kernels over one more step
     plan.timing(True)
     step()
     torch.cuda.synchronize()
     fam = {}
-    for spin, name in ((0, "alpha"), (1, "beta")):
-        kms, n, alg = plan.timing_read(spin)
-        fam[name] = {"launches": n, "total_ms": kms, "avg_ms": kms / max(n, 1), "alg_bytes": alg}
+    for kind, kname in ((1, "seg_pass"), (0, "win_pass")):
+        for spin, sname in ((0, "alpha"), (1, "beta")):
+            kms, n, alg, slots = plan.timing_read(kind, spin)
+            if n:
+                fam[f"{kname}_{sname}"] = {"launches": n, "total_ms": kms, "avg_ms": kms / n,
+                                           "alg_bytes": alg, "valu_slots": slots}
     plan.timing(False)
     dom = max(fam, key=lambda k: fam[k]["total_ms"])
     f = fam[dom]
-    achieved = (f["alg_bytes"] / f["launches"]) / (f["avg_ms"] * 1e-3) / 1e9 if f["launches"] else 0.0
-    roofline = {
-        "bound": "hbm",
-        "kernel": f"k_win_{dom} (Givens window pass, {dom} spin)",
-        "achieved": round(achieved, 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
+    sec = f["avg_ms"] * 1e-3
+    # ALU roofline: algorithmic VALU slots (8 per rotated pair for real rotations, 12 for complex)
+    # as FMA-equivalent flops against the vector peak of the arithmetic type
+    alu_peak = 78.6 if dtype == torch.complex128 else 157.3
+    alu = 2.0 * f["valu_slots"] / f["launches"] / sec / 1e12
+    # HBM roofline: a segment pass reads and writes the whole state once
+    hbm_bytes = 2.0 * plan.state_bytes if dom.startswith("seg") else f["alg_bytes"] / f["launches"]
+    hbm = hbm_bytes / sec / 1e9
+    if alu / alu_peak >= hbm / HBM_PEAK_GBS:
+        roofline = {"bound": "alu", "achieved": round(alu, 3), "peak": alu_peak, "unit": "TFLOP/s",
+                    "frac": round(alu / alu_peak, 4)}
+    else:
+        roofline = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(hbm / HBM_PEAK_GBS, 4)}
+    roofline.update({
         "traffic": None,
+        "kernel": f"k_{dom.rsplit('_', 1)[0]} ({dom.rsplit('_', 1)[1]} rotations)",
         "avg_launch_ms": round(f["avg_ms"], 4),
         "launches_per_step": f["launches"],
-        "alg_bytes_per_launch": f["alg_bytes"] / max(f["launches"], 1),
+        "valu_slots_per_launch": f["valu_slots"] / f["launches"],
+        "hbm_bytes_per_launch": hbm_bytes,
+        "hbm_GBps": round(hbm, 1),
+        "alu_TFLOPs": round(alu, 3),
         "families": fam,
-    }
+    })
 
     out = {
         "metric": "s per DF Trotter step (norb=16, nelec=(8,8), L=16, S_0, dt=0.1)",

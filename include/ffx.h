@@ -159,18 +159,20 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
                          double* energy, double* grad, void* psi_out, void* workspace,
                          void* stream);
 
-/* Diagnostics: per-launch timing of the Givens window-pass kernels (the
-   dominant kernels of every orbital rotation).  While enabled, each pass
-   launch is bracketed by HIP events on the stream it is launched on.
-   ffx_timing_enable resets the counters (enable = 0 stops recording).
-   ffx_timing_read synchronizes on the recorded events and returns, for spin
-   (0 = alpha passes, 1 = beta passes): the summed kernel time in ms, the
-   number of launches, and the algorithmic bytes those launches stand for: a
-   launch applying r of the K = norb(norb-1)/2 rotations of one spin counts
-   r / K of one read plus one write of the state. */
+/* Diagnostics: per-launch timing of the dominant kernels.  While enabled,
+   each segment pass and each window pass is bracketed by HIP events on the
+   stream it is launched on.  ffx_timing_enable resets the counters
+   (enable = 0 stops recording).  ffx_timing_read synchronizes on the recorded
+   events and returns, for `which` = 2 * kind + spin (kind 0 = window passes,
+   1 = segment passes; spin = the spin whose configurations the launch
+   rotates): the summed kernel time in ms, the number of launches, the
+   algorithmic bytes those launches stand for (a launch applying r of the
+   K = norb (norb - 1) / 2 rotations of one spin counts r / K of one read plus
+   one write of the state) and their algorithmic VALU slots (per rotated
+   configuration pair: 8 for a real rotation, 12 for a complex one). */
 int ffx_timing_enable(ffx_plan plan, int enable);
-int ffx_timing_read(ffx_plan plan, int spin, double* total_ms, int64_t* launches,
-                    double* algorithmic_bytes);
+int ffx_timing_read(ffx_plan plan, int which, double* total_ms, int64_t* launches,
+                    double* algorithmic_bytes, double* valu_slots);
 
 #ifdef __cplusplus
 }

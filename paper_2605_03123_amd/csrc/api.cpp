@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
 #include <string>
@@ -17,19 +18,20 @@
 #include "device.h"
 #include "ffx.h"
 #include "host.h"
+#include "plan.h"
 
 using namespace ffx;
+
+namespace ffx {
+void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(FFX_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+}  // namespace ffx
 
 namespace {
 
 thread_local std::string g_last_error;
-
-#define HIPCHK(x)                                                                        \
-  do {                                                                                   \
-    hipError_t e_ = (x);                                                                 \
-    if (e_ != hipSuccess)                                                                \
-      throw Error(FFX_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));          \
-  } while (0)
 
 template <class F>
 int guard(F&& f) {
@@ -47,11 +49,6 @@ int guard(F&& f) {
     g_last_error = e.what();
     return FFX_EINVAL;
   }
-}
-
-void check_launch() {
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) throw Error(FFX_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
 }
 
 struct DeviceGuard {
@@ -84,245 +81,16 @@ bool all_finite(const double* p, size_t n) {
   return true;
 }
 
-}  // namespace
-
 // ---------------------------------------------------------------------------
-// plan
+// Givens decompositions kept alive for the duration of one call
 // ---------------------------------------------------------------------------
-struct ffx_plan_s {
-  int norb = 0;
-  int n[2] = {0, 0};
-  bool c64 = false;
-  int device = 0;
-  int64_t dim[2] = {0, 0};
-  std::vector<uint64_t> str[2];
-  uint32_t* d_masks[2] = {nullptr, nullptr};
-  int W = 2;
-  std::vector<dev::WinDev> win[2];
-  // parameter upload ring
-  static constexpr int kSlots = 4;
-  size_t slot_bytes = 0;
-  char* h_ring = nullptr;
-  char* d_ring = nullptr;
-  hipEvent_t ev[kSlots] = {};
-  int next_slot = 0;
-  // scratch
-  void* phase_tab[2] = {nullptr, nullptr};
-  double* dA = nullptr;
-  double* dB = nullptr;
-  double* dV = nullptr;
-  double* partials = nullptr;
-  int n_partials = 0;
-  double* results = nullptr;  // kResults doubles
-  double* rowout = nullptr;
-  std::vector<void*> allocs;
-  static constexpr int kResults = 1 << 16;
-  // diagnostics: event pairs around window-pass launches
-  struct Timed {
-    hipEvent_t a, b;
-    int spin;
-    double alg_bytes;
-  };
-  bool timing = false;
-  std::vector<Timed> timed;
-  std::vector<hipEvent_t> ev_pool;
-  hipEvent_t take_event() {
-    if (!ev_pool.empty()) {
-      hipEvent_t e = ev_pool.back();
-      ev_pool.pop_back();
-      return e;
-    }
-    hipEvent_t e;
-    HIPCHK(hipEventCreate(&e));
-    return e;
-  }
-  void recycle_timed() {
-    for (auto& t : timed) {
-      ev_pool.push_back(t.a);
-      ev_pool.push_back(t.b);
-    }
-    timed.clear();
-  }
-
-  size_t elem() const { return c64 ? 8 : 16; }
-  int64_t elems() const { return dim[0] * dim[1]; }
-  size_t state_bytes() const { return (size_t)elems() * elem(); }
-
-  void* dalloc(size_t bytes) {
-    void* p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess || !p)
-      throw Error(FFX_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-    allocs.push_back(p);
-    return p;
-  }
-
-  ~ffx_plan_s() {
-    recycle_timed();
-    for (auto e : ev_pool) (void)hipEventDestroy(e);
-    for (void* p : allocs) (void)hipFree(p);
-    for (auto& e : ev)
-      if (e) (void)hipEventDestroy(e);
-    if (h_ring) (void)hipHostFree(h_ring);
+struct DecompPool {
+  std::deque<Decomposition> v;
+  const Decomposition* add(int N, const std::vector<cd>& U) {
+    v.push_back(givens_decompose(N, U.data()));
+    return &v.back();
   }
 };
-
-namespace {
-
-// One slot of the pinned upload ring: small per-call data is packed here,
-// copied to the device once, and read by the kernels of that call.
-struct Upload {
-  ffx_plan_s* P;
-  int slot;
-  char* h;
-  char* d;
-  size_t cap;
-  size_t off = 0;
-  hipStream_t s;
-  bool committed = false;
-
-  Upload(ffx_plan_s* plan, hipStream_t stream) : P(plan), s(stream) {
-    slot = P->next_slot;
-    P->next_slot = (P->next_slot + 1) % ffx_plan_s::kSlots;
-    HIPCHK(hipEventSynchronize(P->ev[slot]));  // previous user of the slot is done
-    h = P->h_ring + (size_t)slot * P->slot_bytes;
-    d = P->d_ring + (size_t)slot * P->slot_bytes;
-    cap = P->slot_bytes;
-  }
-  template <class T>
-  const T* put(const T* src, size_t count) {
-    off = (off + 15) & ~(size_t)15;
-    size_t bytes = count * sizeof(T);
-    if (off + bytes > cap) throw Error(FFX_EUNSUPPORTED, "parameter block exceeds the upload slot");
-    if (bytes) std::memcpy(h + off, src, bytes);
-    const T* r = (const T*)(d + off);
-    off += bytes;
-    return r;
-  }
-  void commit() {
-    if (off) HIPCHK(hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, s));
-    committed = true;
-  }
-  ~Upload() { (void)hipEventRecord(P->ev[slot], s); }
-};
-
-// ---------------------------------------------------------------------------
-// gate programs
-// ---------------------------------------------------------------------------
-struct PassProg {
-  int a;
-  const dev::RotDev* rots;
-  int nrot;
-};
-struct SpinProg {
-  std::vector<PassProg> passes;
-  const double* delta = nullptr;
-  bool has_phase = false;
-  bool real = true;
-};
-struct RotProg {
-  SpinProg sp[2];
-};
-
-SpinProg prep_spin(ffx_plan_s& P, Upload& up, const Decomposition& d) {
-  SpinProg sp;
-  sp.real = d.real;
-  for (double x : d.phase)
-    if (x != 0.0) sp.has_phase = true;
-  if (sp.has_phase) sp.delta = up.put(d.phase.data(), d.phase.size());
-  const int W = P.W;
-  auto passes = schedule_windows(d.rots, P.norb, W);
-  std::vector<dev::RotDev> buf;
-  for (auto& ps : passes) {
-    buf.clear();
-    for (int i : ps.idx) {
-      const Givens& g = d.rots[i];
-      buf.push_back(dev::RotDev{g.p - ps.a, 0, g.c, g.s.real(), g.s.imag()});
-    }
-    sp.passes.push_back(PassProg{ps.a, up.put(buf.data(), buf.size()), (int)buf.size()});
-  }
-  if (sp.passes.empty() && sp.has_phase) sp.passes.push_back(PassProg{0, nullptr, 0});
-  return sp;
-}
-
-RotProg prep_rotation(ffx_plan_s& P, Upload& up, const std::vector<cd>& Ua, const std::vector<cd>* Ub) {
-  RotProg rp;
-  Decomposition da = givens_decompose(P.norb, Ua.data());
-  rp.sp[0] = prep_spin(P, up, da);
-  if (Ub == nullptr) {
-    rp.sp[1] = rp.sp[0];
-  } else {
-    Decomposition db = givens_decompose(P.norb, Ub->data());
-    rp.sp[1] = prep_spin(P, up, db);
-  }
-  return rp;
-}
-
-void run_rotation(ffx_plan_s& P, void* vec, const RotProg& rp, hipStream_t s) {
-  for (int sigma = 0; sigma < 2; ++sigma) {
-    const SpinProg& sp = rp.sp[sigma];
-    if (sp.has_phase) {
-      dev::string_phase(P.c64, P.d_masks[sigma], P.dim[sigma], sp.delta, P.norb, P.phase_tab[sigma], s);
-      check_launch();
-    }
-    for (size_t i = 0; i < sp.passes.size(); ++i) {
-      const PassProg& pp = sp.passes[i];
-      const bool last = i + 1 == sp.passes.size();
-      ffx_plan_s::Timed tm{};
-      if (P.timing) {
-        tm.a = P.take_event();
-        tm.b = P.take_event();
-        tm.spin = sigma;
-        const double K = 0.5 * P.norb * (P.norb - 1);
-        tm.alg_bytes = K > 0 ? (pp.nrot / K) * 2.0 * (double)P.state_bytes() : 0.0;
-        HIPCHK(hipEventRecord(tm.a, s));
-      }
-      dev::win_pass(P.c64, sp.real, sigma, vec, P.dim[0], P.dim[1], P.win[sigma][pp.a], pp.rots, pp.nrot,
-                    (last && sp.has_phase) ? P.phase_tab[sigma] : nullptr, s);
-      check_launch();
-      if (P.timing) {
-        HIPCHK(hipEventRecord(tm.b, s));
-        P.timed.push_back(tm);
-      }
-    }
-  }
-}
-
-// f(I_a, I_b) = lin_a.x_a + lin_b.x_b + 1/2 x_a Qa x_a + 1/2 x_b Qb x_b + x_a C x_b
-struct DiagProg {
-  dev::DiagSpecDev spec{};
-  bool cross = false;
-  bool has_a = false, has_b = false;
-};
-
-DiagProg prep_diag(ffx_plan_s& P, Upload& up, const double* lin_a, const double* lin_b, const double* Qa,
-                   const double* Qb, const double* C) {
-  const int N = P.norb;
-  DiagProg d;
-  if (lin_a) d.spec.lin_a = up.put(lin_a, N);
-  if (lin_b) d.spec.lin_b = up.put(lin_b, N);
-  if (Qa) d.spec.Qa = up.put(Qa, (size_t)N * N);
-  if (Qb) d.spec.Qb = up.put(Qb, (size_t)N * N);
-  if (C) {
-    d.spec.C = up.put(C, (size_t)N * N);
-    d.cross = true;
-  }
-  d.has_a = lin_a || Qa;
-  d.has_b = lin_b || Qb;
-  return d;
-}
-
-dev::DiagDev build_diag(ffx_plan_s& P, const DiagProg& d, hipStream_t s) {
-  dev::diag_tables(P.d_masks[0], P.dim[0], P.d_masks[1], P.dim[1], P.norb, d.spec, d.has_a ? P.dA : nullptr,
-                   d.has_b ? P.dB : nullptr, d.cross ? P.dV : nullptr, s);
-  check_launch();
-  return dev::DiagDev{d.has_a ? P.dA : nullptr, d.has_b ? P.dB : nullptr, d.cross ? P.dV : nullptr};
-}
-
-void run_diag_phase(ffx_plan_s& P, void* vec, const DiagProg& d, double scale, hipStream_t s) {
-  dev::DiagDev f = build_diag(P, d, s);
-  dev::diag_phase(P.c64, vec, P.dim[0], P.dim[1], P.d_masks[0], P.norb, f, scale, s);
-  check_launch();
-}
 
 // ---------------------------------------------------------------------------
 // DF Hamiltonian data on the host
@@ -377,10 +145,17 @@ DFHost load_df(const ffx_plan_s& P, const ffx_df_ham* ham) {
   return d;
 }
 
-DiagProg prep_df_weight(ffx_plan_s& P, Upload& up, const DFHost& df, int term) {
-  if (term == 0) return prep_diag(P, up, df.eps.data(), df.eps.data(), nullptr, nullptr, nullptr);
-  const double* J = df.J[term - 1].data();
-  return prep_diag(P, up, nullptr, nullptr, J, J, J);
+// term 0: sum_p eps_p N_p (one-body term in the eigenbasis of h);
+// term t: 1/2 sum_pq J_t[p][q] N_p N_q
+DiagSpec df_weight_spec(const DFHost& df, int term) {
+  DiagSpec d;
+  if (term == 0) {
+    d.lin_a = d.lin_b = df.eps.data();
+  } else {
+    const double* J = df.J[term - 1].data();
+    d.Qa = d.Qb = d.C = J;
+  }
+  return d;
 }
 
 // product formula as a list of (term, time) in application order
@@ -429,38 +204,41 @@ LUCJHost load_lucj(const ffx_plan_s& P, const ffx_lucj* op) {
   return L;
 }
 
-struct LUCJProg {
-  std::vector<RotProg> after;   // after[k]: rotation after D_k (U_{k+1}^dag U_k, or U_R)
-  std::vector<RotProg> undo;    // inverse of after[k]
-  std::vector<DiagProg> diag;   // D_k
-  const double* a = nullptr;    // Slater vectors (complex, interleaved)
-  const double* b = nullptr;
+// Slater column minors of U_1^dag and the merged rotations of the ansatz:
+// after[k] = U_{k+1}^dag U_k (k < R-1), after[R-1] = U_R; undo[k] = after[k]^dag.
+struct LUCJParts {
+  std::vector<cd> a, b;
+  std::vector<const Decomposition*> after, undo;
+  std::vector<DiagSpec> diag;
 };
 
-LUCJProg prep_lucj(ffx_plan_s& P, Upload& up, const LUCJHost& L, bool with_inverse) {
+LUCJParts lucj_parts(const ffx_plan_s& P, const LUCJHost& L, DecompPool& pool, bool with_inverse) {
   const int N = P.norb;
-  LUCJProg g;
+  LUCJParts g;
   std::vector<cd> U1d = dagger(N, L.U[0]);
-  auto sa = slater_column_minors(N, P.n[0], U1d, P.str[0]);
-  auto sb = (P.n[1] == P.n[0]) ? sa : slater_column_minors(N, P.n[1], U1d, P.str[1]);
-  g.a = up.put((const double*)sa.data(), 2 * sa.size());
-  g.b = up.put((const double*)sb.data(), 2 * sb.size());
+  g.a = slater_column_minors(N, P.n[0], U1d, P.str[0]);
+  g.b = (P.n[1] == P.n[0]) ? g.a : slater_column_minors(N, P.n[1], U1d, P.str[1]);
   for (int k = 0; k < L.R; ++k) {
     std::vector<cd> M = (k + 1 < L.R) ? matmul(N, dagger(N, L.U[k + 1]), L.U[k]) : L.U[k];
-    g.after.push_back(prep_rotation(P, up, M, nullptr));
-    if (with_inverse) g.undo.push_back(prep_rotation(P, up, dagger(N, M), nullptr));
-    g.diag.push_back(prep_diag(P, up, nullptr, nullptr, L.Jsame[k].data(), L.Jsame[k].data(), L.Jopp[k].data()));
+    g.after.push_back(pool.add(N, M));
+    if (with_inverse) g.undo.push_back(pool.add(N, dagger(N, M)));
+    DiagSpec d;
+    d.Qa = d.Qb = L.Jsame[k].data();
+    d.C = L.Jopp[k].data();
+    g.diag.push_back(d);
   }
   return g;
 }
 
-void run_lucj_forward(ffx_plan_s& P, void* vec, const LUCJProg& g, int R, hipStream_t s) {
-  dev::outer(P.c64, g.a, g.b, vec, P.dim[0], P.dim[1], s);
-  check_launch();
+// D_1, rotation, D_2, rotation, ... applied to the Slater determinant
+Program lucj_forward_program(const LUCJParts& g, int R) {
+  Program pr;
   for (int k = 0; k < R; ++k) {
-    run_diag_phase(P, vec, g.diag[k], -1.0, s);
-    run_rotation(P, vec, g.after[k], s);
+    int d = pr.add_diag(g.diag[k]);
+    pr.phase(d, -1.0);
+    pr.rot(g.after[k], g.after[k]);
   }
+  return pr;
 }
 
 void validate_plan(ffx_plan plan) {
@@ -614,6 +392,76 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
     P->partials = (double*)P->dalloc((size_t)P->n_partials * 8);
     P->results = (double*)P->dalloc((size_t)ffx_plan_s::kResults * 8);
     P->rowout = (double*)P->dalloc((size_t)dmax * 2 * norb * 8);
+    P->arena_doubles = (size_t)ffx_plan_s::kArenaSlots * (size_t)(P->dim[0] + P->dim[1]);
+    P->arena = (double*)P->dalloc(P->arena_doubles * 8);
+    // segment passes: for each column spin, the widest segment window whose
+    // segments fit in LDS next to the stage tables
+    const size_t lds_budget = 160 * 1024 - dev::seg_pass_lds(P->c64, 0) - 64;
+    int64_t max_elems = (int64_t)(lds_budget / P->elem());
+    if (const char* e = std::getenv("FFX_SEG_MAX")) {  // smaller segments, for tests
+      int64_t v = std::atoll(e);
+      if (v >= 1 && v < max_elems) max_elems = v;
+    }
+    int max_rows_x_seg = 0;
+    for (int s = 0; s < 2; ++s) {
+      auto& ss = P->seg[s];
+      const auto& strs = P->str[s];
+      std::vector<std::pair<int, int>> segs;
+      int wt = norb;
+      for (; wt >= 0; --wt) {
+        segs.clear();
+        size_t i = 0;
+        int64_t longest = 0;
+        while (i < strs.size()) {
+          size_t j = i;
+          while (j < strs.size() && (strs[j] >> wt) == (strs[i] >> wt)) ++j;
+          segs.push_back({(int)i, (int)(j - i)});
+          longest = std::max<int64_t>(longest, (int64_t)(j - i));
+          i = j;
+        }
+        if (longest <= max_elems) break;
+      }
+      ss.wt = wt;
+      ss.Wseg = std::min(P->W, wt);
+      ss.n_seg = (int)segs.size();
+      ss.max_len = 0;
+      std::vector<dev::SegDev> hsegs;
+      for (auto& sg : segs) {
+        ss.max_len = std::max(ss.max_len, sg.second);
+        std::vector<uint64_t> sub(strs.begin() + sg.first, strs.begin() + sg.first + sg.second);
+        std::vector<dev::WinDev> wins;
+        for (int a = 0; a + ss.Wseg <= wt && ss.Wseg >= 1; ++a) {
+          WindowTable t = build_window_table(sub, norb, 0, a, ss.Wseg);
+          dev::WinDev wd{};
+          int* tab = (int*)P->dalloc(t.tab.size() * 4);
+          int* cm = (int*)P->dalloc(t.chunk_m.size() * 4);
+          int* co = (int*)P->dalloc(t.chunk_off.size() * 4);
+          HIPCHK(hipMemcpy(tab, t.tab.data(), t.tab.size() * 4, hipMemcpyHostToDevice));
+          HIPCHK(hipMemcpy(cm, t.chunk_m.data(), t.chunk_m.size() * 4, hipMemcpyHostToDevice));
+          HIPCHK(hipMemcpy(co, t.chunk_off.data(), t.chunk_off.size() * 4, hipMemcpyHostToDevice));
+          wd.tab = tab;
+          wd.chunk_m = cm;
+          wd.chunk_off = co;
+          wd.n_chunks = (int)t.chunk_m.size();
+          wd.a = a;
+          wd.w = ss.Wseg;
+          wins.push_back(wd);
+        }
+        dev::WinDev* dw = (dev::WinDev*)P->dalloc(std::max<size_t>(wins.size(), 1) * sizeof(dev::WinDev));
+        if (!wins.empty()) HIPCHK(hipMemcpy(dw, wins.data(), wins.size() * sizeof(dev::WinDev), hipMemcpyHostToDevice));
+        hsegs.push_back(dev::SegDev{sg.first, sg.second, dw});
+      }
+      ss.d_segs = (dev::SegDev*)P->dalloc(hsegs.size() * sizeof(dev::SegDev));
+      HIPCHK(hipMemcpy(ss.d_segs, hsegs.data(), hsegs.size() * sizeof(dev::SegDev), hipMemcpyHostToDevice));
+      ss.lds = dev::seg_pass_lds(P->c64, ss.max_len);
+      ss.threads = ss.max_len >= 4096 ? 768 : (ss.max_len >= 1024 ? 256 : 64);
+      // rows of this column spin's layout times segments: one partial sum per block
+      max_rows_x_seg = std::max<int>(max_rows_x_seg, (int)(P->dim[1 - s] * ss.n_seg));
+    }
+    if (max_rows_x_seg > P->n_partials) {
+      P->n_partials = max_rows_x_seg;
+      P->partials = (double*)P->dalloc((size_t)P->n_partials * 8);
+    }
     HIPCHK(hipDeviceSynchronize());
     *out = P.release();
   });
@@ -660,10 +508,15 @@ int ffx_apply_orbital_rotation(ffx_plan plan, void* vec, const double* U_a, cons
     auto Ua = load_complex(N, U_a);
     std::vector<cd> Ub;
     if (U_b) Ub = load_complex(N, U_b);
+    DecompPool pool;
+    const Decomposition* da = pool.add(N, Ua);
+    const Decomposition* db = U_b ? pool.add(N, Ub) : da;
+    Program pr;
+    pr.rot(da, db);
     Upload up(plan, s);
-    RotProg rp = prep_rotation(*plan, up, Ua, U_b ? &Ub : nullptr);
+    Compiled c = compile_program(*plan, up, pr, FINAL_STORE, s);
     up.commit();
-    run_rotation(*plan, vec, rp, s);
+    execute_program(*plan, c, vec, vec, nullptr, s);
   });
 }
 
@@ -677,10 +530,15 @@ int ffx_apply_num_op_sum_evolution(ffx_plan plan, void* vec, const double* lam_a
       throw Error(FFX_EINVAL, "non-finite parameter");
     DeviceGuard dg(plan->device);
     hipStream_t s = as_stream(stream);
+    Program pr;
+    DiagSpec d;
+    d.lin_a = lam_a;
+    d.lin_b = lam_b ? lam_b : lam_a;
+    pr.phase(pr.add_diag(d), -time);
     Upload up(plan, s);
-    DiagProg d = prep_diag(*plan, up, lam_a, lam_b ? lam_b : lam_a, nullptr, nullptr, nullptr);
+    Compiled c = compile_program(*plan, up, pr, FINAL_STORE, s);
     up.commit();
-    run_diag_phase(*plan, vec, d, -time, s);
+    execute_program(*plan, c, vec, vec, nullptr, s);
   });
 }
 
@@ -697,10 +555,16 @@ int ffx_apply_diag_coulomb_evolution(ffx_plan plan, void* vec, const double* J_a
       throw Error(FFX_EINVAL, "non-finite parameter");
     DeviceGuard dg(plan->device);
     hipStream_t s = as_stream(stream);
+    Program pr;
+    DiagSpec d;
+    d.Qa = J_aa;
+    d.Qb = Jbb;
+    d.C = Jab;
+    pr.phase(pr.add_diag(d), -time);
     Upload up(plan, s);
-    DiagProg d = prep_diag(*plan, up, nullptr, nullptr, J_aa, Jbb, Jab);
+    Compiled c = compile_program(*plan, up, pr, FINAL_STORE, s);
     up.commit();
-    run_diag_phase(*plan, vec, d, -time, s);
+    execute_program(*plan, c, vec, vec, nullptr, s);
   });
 }
 
@@ -726,9 +590,9 @@ int ffx_apply_df_trotter_step(ffx_plan plan, void* vec, const ffx_df_ham* ham, d
       else
         m.push_back(e);
     }
-    Upload up(&P, s);
-    std::map<std::pair<int, int>, RotProg> rot_cache;
-    auto rot = [&](int from, int to) -> const RotProg& {
+    DecompPool pool;
+    std::map<std::pair<int, int>, const Decomposition*> rot_cache;
+    auto rot = [&](int from, int to) -> const Decomposition* {
       auto key = std::make_pair(from, to);
       auto it = rot_cache.find(key);
       if (it != rot_cache.end()) return it->second;
@@ -739,25 +603,26 @@ int ffx_apply_df_trotter_step(ffx_plan plan, void* vec, const ffx_df_ham* ham, d
         M = df.Wm(from);
       else
         M = matmul(N, dagger(N, df.Wm(to)), df.Wm(from));
-      return rot_cache.emplace(key, prep_rotation(P, up, M, nullptr)).first->second;
+      const Decomposition* d = pool.add(N, M);
+      rot_cache.emplace(key, d);
+      return d;
     };
-    std::vector<DiagProg> weights;
-    for (int t = 0; t <= df.L; ++t) weights.push_back(prep_df_weight(P, up, df, t));
-    // prepare every rotation before the upload is committed
+    Program pr;
+    std::vector<int> weight;
+    for (int t = 0; t <= df.L; ++t) weight.push_back(pr.add_diag(df_weight_spec(df, t)));
     int prev = -1;
     for (auto& e : m) {
-      rot(prev, e.first);
+      const Decomposition* d = rot(prev, e.first);
+      pr.rot(d, d);
+      pr.phase(weight[e.first], -e.second);
       prev = e.first;
     }
-    rot(prev, -1);
+    const Decomposition* d = rot(prev, -1);
+    pr.rot(d, d);
+    Upload up(&P, s);
+    Compiled c = compile_program(P, up, pr, FINAL_STORE, s);
     up.commit();
-    prev = -1;
-    for (auto& e : m) {
-      run_rotation(P, vec, rot(prev, e.first), s);
-      run_diag_phase(P, vec, weights[e.first], -e.second, s);
-      prev = e.first;
-    }
-    run_rotation(P, vec, rot(prev, -1), s);
+    execute_program(P, c, vec, vec, nullptr, s);
   });
 }
 
@@ -774,10 +639,17 @@ int ffx_apply_lucj(ffx_plan plan, void* vec, const ffx_lucj* op, void* stream) {
     LUCJHost L = load_lucj(P, op);
     DeviceGuard dg(P.device);
     hipStream_t s = as_stream(stream);
+    DecompPool pool;
+    LUCJParts g = lucj_parts(P, L, pool, false);
+    Program pr = lucj_forward_program(g, L.R);
     Upload up(&P, s);
-    LUCJProg g = prep_lucj(P, up, L, false);
+    const double* a = up.put((const double*)g.a.data(), 2 * g.a.size());
+    const double* b = up.put((const double*)g.b.data(), 2 * g.b.size());
+    Compiled c = compile_program(P, up, pr, FINAL_STORE, s);
     up.commit();
-    run_lucj_forward(P, vec, g, L.R, s);
+    dev::outer(P.c64, a, b, vec, P.dim[0], P.dim[1], s);
+    check_launch();
+    execute_program(P, c, vec, vec, nullptr, s);
   });
 }
 
@@ -801,22 +673,18 @@ int ffx_df_energy(ffx_plan plan, const void* vec, const ffx_df_ham* ham, double*
     DeviceGuard dg(P.device);
     hipStream_t s = as_stream(stream);
     void* tmp = workspace;
+    DecompPool pool;
+    std::vector<Program> progs(df.L + 1);
+    for (int t = 0; t <= df.L; ++t) {
+      const Decomposition* d = pool.add(N, dagger(N, df.Wm(t)));
+      progs[t].rot(d, d);
+      progs[t].reduce(progs[t].add_diag(df_weight_spec(df, t)), P.results + t);
+    }
     Upload up(&P, s);
-    std::vector<RotProg> rots;
-    std::vector<DiagProg> w;
-    for (int t = 0; t <= df.L; ++t) {
-      rots.push_back(prep_rotation(P, up, dagger(N, df.Wm(t)), nullptr));
-      w.push_back(prep_df_weight(P, up, df, t));
-    }
+    std::vector<Compiled> cs;
+    for (auto& pr : progs) cs.push_back(compile_program(P, up, pr, FINAL_NONE, s));
     up.commit();
-    for (int t = 0; t <= df.L; ++t) {
-      HIPCHK(hipMemcpyAsync(tmp, vec, P.state_bytes(), hipMemcpyDeviceToDevice, s));
-      run_rotation(P, tmp, rots[t], s);
-      dev::DiagDev f = build_diag(P, w[t], s);
-      int np = dev::diag_expect(P.c64, tmp, P.dim[0], P.dim[1], P.d_masks[0], N, f, P.partials, s);
-      dev::sum_partials(P.partials, np, P.results + t, s);
-      check_launch();
-    }
+    for (auto& c : cs) execute_program(P, c, vec, tmp, nullptr, s);
     std::vector<double> r(df.L + 1);
     HIPCHK(hipMemcpyAsync(r.data(), P.results, r.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -846,31 +714,45 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
     void* lamT = ws + 3 * Sa;
     void* psi = psi_out ? psi_out : (void*)(ws + 4 * Sa);
     double* part = (double*)(ws + 5 * Sa);
-    Upload up(&P, s);
-    LUCJProg g = prep_lucj(P, up, L, true);
-    std::vector<RotProg> to_t, from_t;
-    std::vector<DiagProg> w;
+    DecompPool pool;
+    LUCJParts g = lucj_parts(P, L, pool, true);
+    Program fwd = lucj_forward_program(g, L.R);
+    // costate terms: U_t D_t U_t^dag psi
+    std::vector<Program> terms(df.L + 1);
     for (int t = 0; t <= df.L; ++t) {
-      to_t.push_back(prep_rotation(P, up, dagger(N, df.Wm(t)), nullptr));
-      from_t.push_back(prep_rotation(P, up, df.Wm(t), nullptr));
-      w.push_back(prep_df_weight(P, up, df, t));
+      const Decomposition* to = pool.add(N, dagger(N, df.Wm(t)));
+      const Decomposition* from = pool.add(N, df.Wm(t));
+      terms[t].rot(to, to);
+      terms[t].scale(terms[t].add_diag(df_weight_spec(df, t)));
+      terms[t].rot(from, from);
+    }
+    std::vector<Program> undo_rot(L.R), undo_diag(L.R);
+    for (int k = 0; k < L.R; ++k) {
+      undo_rot[k].rot(g.undo[k], g.undo[k]);
+      undo_diag[k].phase(undo_diag[k].add_diag(g.diag[k]), +1.0);
+    }
+    Upload up(&P, s);
+    const double* sa = up.put((const double*)g.a.data(), 2 * g.a.size());
+    const double* sb = up.put((const double*)g.b.data(), 2 * g.b.size());
+    Compiled c_fwd = compile_program(P, up, fwd, FINAL_STORE, s);
+    std::vector<Compiled> c_terms, c_urot, c_udiag;
+    for (int t = 0; t <= df.L; ++t)
+      c_terms.push_back(compile_program(P, up, terms[t], t == 0 ? FINAL_STORE : FINAL_ACCUM, s));
+    for (int k = 0; k < L.R; ++k) {
+      c_urot.push_back(compile_program(P, up, undo_rot[k], FINAL_STORE, s));
+      c_udiag.push_back(compile_program(P, up, undo_diag[k], FINAL_STORE, s));
     }
     up.commit();
     // forward
-    run_lucj_forward(P, psi, g, L.R, s);
-    // costate lambda = H psi = sum_t U_t D_t U_t^dag psi
+    dev::outer(P.c64, sa, sb, psi, P.dim[0], P.dim[1], s);
+    check_launch();
+    execute_program(P, c_fwd, psi, psi, nullptr, s);
+    // costate lambda = H psi
     for (int t = 0; t <= df.L; ++t) {
-      void* dst = (t == 0) ? lam : tmp;
-      HIPCHK(hipMemcpyAsync(dst, psi, S, hipMemcpyDeviceToDevice, s));
-      run_rotation(P, dst, to_t[t], s);
-      dev::DiagDev f = build_diag(P, w[t], s);
-      dev::diag_scale(P.c64, dst, P.dim[0], P.dim[1], P.d_masks[0], N, f, s);
-      check_launch();
-      run_rotation(P, dst, from_t[t], s);
-      if (t > 0) {
-        dev::axpy(P.c64, tmp, lam, P.elems(), s);
-        check_launch();
-      }
+      if (t == 0)
+        execute_program(P, c_terms[t], psi, lam, nullptr, s);
+      else
+        execute_program(P, c_terms[t], psi, tmp, lam, s);
     }
     // energy <psi|lambda>
     dev::inner(P.c64, psi, lam, P.elems(), P.partials, P.results, s);
@@ -891,14 +773,14 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
       check_launch();
     };
     for (int k = L.R - 1; k >= 0; --k) {
-      run_rotation(P, psi, g.undo[k], s);
-      run_rotation(P, lam, g.undo[k], s);
+      execute_program(P, c_urot[k], psi, psi, nullptr, s);
+      execute_program(P, c_urot[k], lam, lam, nullptr, s);
       rdm(Tdev + (size_t)k * 8 * NN);
       dev::diag_grad_rows(P.c64, lam, psi, P.dim[0], P.dim[1], P.d_masks[1], N, P.rowout, s);
       dev::diag_grad_combine(P.rowout, P.dim[0], P.d_masks[0], N, Ddev + (size_t)k * (2 * N), s);
       check_launch();
-      run_diag_phase(P, psi, g.diag[k], +1.0, s);
-      run_diag_phase(P, lam, g.diag[k], +1.0, s);
+      execute_program(P, c_udiag[k], psi, psi, nullptr, s);
+      execute_program(P, c_udiag[k], lam, lam, nullptr, s);
       rdm(Tdev + (size_t)k * 8 * NN + 4 * NN);
     }
     std::vector<double> res(16 + (size_t)L.R * (8 * NN + 2 * N));
@@ -933,25 +815,28 @@ int ffx_timing_enable(ffx_plan plan, int enable) {
   });
 }
 
-int ffx_timing_read(ffx_plan plan, int spin, double* total_ms, int64_t* launches, double* alg_bytes) {
+int ffx_timing_read(ffx_plan plan, int which, double* total_ms, int64_t* launches, double* alg_bytes,
+                    double* valu_slots) {
   return guard([&] {
     validate_plan(plan);
-    if (spin != 0 && spin != 1) throw Error(FFX_EINVAL, "bad spin");
+    if (which < 0 || which > 3) throw Error(FFX_EINVAL, "bad selector");
     DeviceGuard dg(plan->device);
-    double ms = 0, bytes = 0;
+    double ms = 0, bytes = 0, slots = 0;
     int64_t n = 0;
     for (auto& t : plan->timed) {
-      if (t.spin != spin) continue;
+      if (t.kind * 2 + t.spin != which) continue;
       HIPCHK(hipEventSynchronize(t.b));
       float e = 0;
       HIPCHK(hipEventElapsedTime(&e, t.a, t.b));
       ms += e;
       bytes += t.alg_bytes;
+      slots += t.valu_slots;
       ++n;
     }
     if (total_ms) *total_ms = ms;
     if (launches) *launches = n;
     if (alg_bytes) *alg_bytes = bytes;
+    if (valu_slots) *valu_slots = slots;
   });
 }
 

@@ -107,5 +107,68 @@ void diag_grad_rows(bool c64, const void* lam, const void* psi, int64_t dim_a, i
 void diag_grad_combine(const double* rowout, int64_t dim_a, const uint32_t* masks_a, int norb,
                        double* out, hipStream_t stream);
 
+// ---------------------------------------------------------------------------
+// segment passes: one block owns one contiguous segment of one row of the
+// (possibly transposed) state in LDS and applies a list of stages to it.
+// ---------------------------------------------------------------------------
+enum StageType { ST_GIVENS = 0, ST_PHASE = 1, ST_SCALE = 2, ST_REDUCE = 3 };
+
+// f(row, col) = A[row] + B[col] + sum_{p in row, q in col} C[p * norb + q]
+//   ST_PHASE : x *= (-1)^{|row & sign_row| + |col & sign_col|}
+//                   * exp(i (scale f + sum_{p in row} drow[p] + sum_{q in col} dcol[q]))
+//   ST_SCALE : x *= f
+//   ST_REDUCE: accumulate f |x|^2 into the block's partial sum
+// ST_GIVENS: the rotations rots[0..nrot) on the window [a, a + W) of the
+//   column strings.
+struct StageDev {
+  int type;
+  int a;
+  int nrot;
+  uint32_t sign_row;
+  uint32_t sign_col;
+  int pad;
+  const RotDev* rots;
+  double scale;
+  const double* A;
+  const double* B;
+  const double* C;
+  const double* drow;
+  const double* dcol;
+};
+
+// one segment of a row: [off, off + len) of the column strings, all sharing
+// the occupation of the orbitals above the segment window; win[a] holds the
+// class tables of the window [a, a + W) with positions relative to off.
+struct SegDev {
+  int off, len;
+  const WinDev* win;
+};
+
+enum SegMode { SEG_STORE = 0, SEG_ACCUM = 1, SEG_NONE = 2 };
+
+struct SegPassDev {
+  const void* src;
+  void* dst;
+  int mode;
+  int norb;
+  int64_t n_rows, row_len;
+  const uint32_t* row_masks;
+  const uint32_t* col_masks;
+  int n_seg;
+  int n_stages;
+  const SegDev* segs;
+  const StageDev* stages;
+  double* partials;
+  int lds_row_bytes;  // byte offset of the scratch area after the row segment
+};
+
+// LDS needed by a segment pass whose longest segment holds max_len amplitudes
+size_t seg_pass_lds(bool c64, int max_len);
+// blocks = n_rows * n_seg; partials (if any stage reduces) get one entry per block
+void seg_pass(bool c64, bool real, int W, const SegPassDev& p, int block_threads, size_t lds_bytes,
+              hipStream_t stream);
+// in-place transpose of a square n x n state
+void transpose_square(bool c64, void* vec, int64_t n, hipStream_t stream);
+
 }  // namespace dev
 }  // namespace ffx

@@ -1,0 +1,259 @@
+// Internal: the plan object, the pinned parameter-upload ring and the gate
+// program compiler of libffx.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "ffx.h"
+#include "host.h"
+
+#define HIPCHK(x)                                                                        \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess)                                                                \
+      throw ffx::Error(FFX_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+namespace ffx {
+void check_launch();
+}
+
+struct ffx_plan_s {
+  int norb = 0;
+  int n[2] = {0, 0};
+  bool c64 = false;
+  int device = 0;
+  int64_t dim[2] = {0, 0};
+  std::vector<uint64_t> str[2];
+  uint32_t* d_masks[2] = {nullptr, nullptr};
+  int W = 2;                          // register window of whole-spin window passes
+  std::vector<ffx::dev::WinDev> win[2];
+  // segment passes, per column spin
+  struct SegSet {
+    int wt = 0;        // segments share the occupation of orbitals >= wt
+    int Wseg = 0;      // register window inside segment passes (windows within [0, wt))
+    int max_len = 0;
+    int n_seg = 0;
+    size_t lds = 0;
+    int threads = 256;
+    ffx::dev::SegDev* d_segs = nullptr;
+  } seg[2];
+  // parameter upload ring
+  static constexpr int kSlots = 4;
+  size_t slot_bytes = 0;
+  char* h_ring = nullptr;
+  char* d_ring = nullptr;
+  hipEvent_t ev[kSlots] = {};
+  int next_slot = 0;
+  // scratch
+  void* phase_tab[2] = {nullptr, nullptr};
+  double* dA = nullptr;
+  double* dB = nullptr;
+  double* dV = nullptr;
+  double* partials = nullptr;
+  int n_partials = 0;
+  double* results = nullptr;  // kResults doubles
+  double* rowout = nullptr;
+  void* state_tmp = nullptr;   // one state, allocated on first need
+  double* arena = nullptr;     // per-program diagonal tables
+  size_t arena_doubles = 0;
+  std::vector<void*> allocs;
+  static constexpr int kResults = 1 << 16;
+  // diagnostics: event pairs around the dominant launches
+  struct Timed {
+    hipEvent_t a, b;
+    int kind;  // 0 window pass, 1 segment pass
+    int spin;
+    double alg_bytes;
+    double valu_slots;
+  };
+  bool timing = false;
+  std::vector<Timed> timed;
+  std::vector<hipEvent_t> ev_pool;
+
+  hipEvent_t take_event() {
+    if (!ev_pool.empty()) {
+      hipEvent_t e = ev_pool.back();
+      ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+  }
+  void recycle_timed() {
+    for (auto& t : timed) {
+      ev_pool.push_back(t.a);
+      ev_pool.push_back(t.b);
+    }
+    timed.clear();
+  }
+
+  size_t elem() const { return c64 ? 8 : 16; }
+  int64_t elems() const { return dim[0] * dim[1]; }
+  size_t state_bytes() const { return (size_t)elems() * elem(); }
+
+  void* dalloc(size_t bytes) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess || !p)
+      throw ffx::Error(FFX_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    allocs.push_back(p);
+    return p;
+  }
+  void* tmp_state() {
+    if (!state_tmp) state_tmp = dalloc(state_bytes());
+    return state_tmp;
+  }
+  // diagonal tables of one program: kArenaSlots distinct functions at most
+  static constexpr int kArenaSlots = 64;
+  double* arena_for(size_t doubles) {
+    if (doubles > arena_doubles)
+      throw ffx::Error(FFX_EUNSUPPORTED, "program has more distinct diagonal functions than the table arena");
+    return arena;
+  }
+
+  ~ffx_plan_s() {
+    recycle_timed();
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
+    for (void* p : allocs) (void)hipFree(p);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (h_ring) (void)hipHostFree(h_ring);
+  }
+};
+
+namespace ffx {
+
+// One slot of the pinned upload ring: small per-call data is packed here,
+// copied to the device once, and read by the kernels of that call.
+struct Upload {
+  ffx_plan_s* P;
+  int slot;
+  char* h;
+  char* d;
+  size_t cap;
+  size_t off = 0;
+  hipStream_t s;
+
+  Upload(ffx_plan_s* plan, hipStream_t stream) : P(plan), s(stream) {
+    slot = P->next_slot;
+    P->next_slot = (P->next_slot + 1) % ffx_plan_s::kSlots;
+    HIPCHK(hipEventSynchronize(P->ev[slot]));  // previous user of the slot is done
+    h = P->h_ring + (size_t)slot * P->slot_bytes;
+    d = P->d_ring + (size_t)slot * P->slot_bytes;
+    cap = P->slot_bytes;
+  }
+  template <class T>
+  const T* put(const T* src, size_t count) {
+    off = (off + 15) & ~(size_t)15;
+    size_t bytes = count * sizeof(T);
+    if (off + bytes > cap) throw Error(FFX_EUNSUPPORTED, "parameter block exceeds the upload slot");
+    if (bytes) std::memcpy(h + off, src, bytes);
+    const T* r = (const T*)(d + off);
+    off += bytes;
+    return r;
+  }
+  void commit() {
+    if (off) HIPCHK(hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, s));
+  }
+  ~Upload() { (void)hipEventRecord(P->ev[slot], s); }
+};
+
+// ---------------------------------------------------------------------------
+// gate programs
+// ---------------------------------------------------------------------------
+// A diagonal function f(I_a, I_b) = lin_a.x_a + lin_b.x_b + 1/2 x_a Qa x_a
+// + 1/2 x_b Qb x_b + x_a C x_b (host arrays, any may be null).
+struct DiagSpec {
+  const double* lin_a = nullptr;
+  const double* lin_b = nullptr;
+  const double* Qa = nullptr;
+  const double* Qb = nullptr;
+  const double* C = nullptr;
+};
+
+struct ProgOp {
+  enum Kind { ROT, PHASE, SCALE, REDUCE } kind;
+  const Decomposition* part[2] = {nullptr, nullptr};  // ROT: alpha and beta parts
+  int diag = -1;                                      // PHASE / SCALE / REDUCE
+  double scale = 0.0;                                 // PHASE: x *= exp(i scale f)
+  double* out = nullptr;                              // REDUCE: device result slot
+};
+
+struct Program {
+  std::vector<DiagSpec> diags;
+  std::vector<ProgOp> ops;
+  int add_diag(const DiagSpec& d) {
+    diags.push_back(d);
+    return (int)diags.size() - 1;
+  }
+  void rot(const Decomposition* a, const Decomposition* b) {
+    ProgOp o{ProgOp::ROT};
+    o.part[0] = a;
+    o.part[1] = b;
+    ops.push_back(o);
+  }
+  void phase(int diag, double scale) {
+    ProgOp o{ProgOp::PHASE};
+    o.diag = diag;
+    o.scale = scale;
+    ops.push_back(o);
+  }
+  void scale(int diag) {
+    ProgOp o{ProgOp::SCALE};
+    o.diag = diag;
+    ops.push_back(o);
+  }
+  void reduce(int diag, double* out) {
+    ProgOp o{ProgOp::REDUCE};
+    o.diag = diag;
+    o.out = out;
+    ops.push_back(o);
+  }
+};
+
+enum FinalMode { FINAL_STORE = 0, FINAL_ACCUM = 1, FINAL_NONE = 2 };
+
+struct Launch {
+  enum Kind { SEG, WIN, TRANSPOSE, SUM } kind;
+  int layout = 0;  // 0: rows alpha / columns beta; 1: rows beta / columns alpha
+  bool real = true;
+  // SEG
+  const dev::StageDev* stages = nullptr;
+  int n_stages = 0;
+  bool reduce = false;
+  double* reduce_out = nullptr;
+  double valu_slots = 0;
+  double rot_sides = 0;
+  // WIN
+  int a = 0;
+  const dev::RotDev* rots = nullptr;
+  int nrot = 0;
+};
+
+struct TableBuild {
+  dev::DiagSpecDev spec;
+  double* A;  // per alpha string
+  double* B;  // per beta string
+};
+
+struct Compiled {
+  std::vector<TableBuild> tables;
+  std::vector<Launch> launches;
+  int final_mode = FINAL_STORE;
+};
+
+// Writes the program's parameters into the upload (before commit) and returns
+// the launch list; diagonal tables are built on the device at execution.
+Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int final_mode, hipStream_t s);
+// src -> work (src may equal work); FINAL_ACCUM adds the result into accum.
+void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* work, void* accum,
+                     hipStream_t s);
+
+}  // namespace ffx

@@ -1,0 +1,405 @@
+// Gate-program compiler and executor.
+//
+// A program is a sequence of orbital rotations (each split into its alpha and
+// beta Givens decompositions) and diagonal operations.  It is executed as
+// alternating "visits" to the two spins: the state is read row-wise, so the
+// rotations of the column spin of the current layout run inside segment
+// passes; when a diagonal operation needs the other spin's pending rotations,
+// the state is transposed and the roles swap.  Within a visit, Givens
+// rotations that stay inside the segment window become register-window stages
+// of a segment pass; rotations that cross segments run as whole-spin window
+// passes between segment passes.  The phase layer that ends each Givens
+// decomposition is diagonal, so it is deferred into the next diagonal phase
+// stage (or a final phase stage) instead of costing a pass of its own.
+#include <cmath>
+#include <map>
+
+#include "plan.h"
+
+namespace ffx {
+
+namespace {
+
+struct Pending {
+  bool has = false;
+  bool sign_only = true;
+  uint32_t sign = 0;
+  std::vector<double> delta;
+};
+
+struct Item {
+  int kind = 0;  // 0: Givens part, 1: diagonal stage
+  const Decomposition* d = nullptr;
+  dev::StageDev st{};
+};
+
+std::vector<std::vector<int>> rotation_deps(const std::vector<Givens>& rots, int norb) {
+  std::vector<std::vector<int>> deps(rots.size());
+  std::vector<int> last(norb, -1);
+  for (size_t i = 0; i < rots.size(); ++i) {
+    int p = rots[i].p;
+    for (int q : {p, p + 1})
+      if (last[q] >= 0) deps[i].push_back(last[q]);
+    last[p] = last[p + 1] = (int)i;
+  }
+  return deps;
+}
+
+// rotations inside [a, a + w) whose predecessors are all done or taken, in order
+std::vector<int> take_window(const std::vector<Givens>& rots, const std::vector<std::vector<int>>& deps,
+                             const std::vector<char>& done, int a, int w) {
+  std::vector<char> taken(rots.size(), 0);
+  std::vector<int> out;
+  for (size_t i = 0; i < rots.size(); ++i) {
+    if (done[i]) continue;
+    int p = rots[i].p;
+    if (p < a || p + 1 >= a + w) continue;
+    bool ok = true;
+    for (int d : deps[i])
+      if (!done[d] && !taken[d]) {
+        ok = false;
+        break;
+      }
+    if (ok) {
+      taken[i] = 1;
+      out.push_back((int)i);
+    }
+  }
+  return out;
+}
+
+}  // namespace
+
+Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int final_mode, hipStream_t s) {
+  Compiled c;
+  c.final_mode = final_mode;
+  const int N = P.norb;
+  const int64_t da = P.dim[0], db = P.dim[1];
+
+  // per diagonal function: device tables A (alpha strings), B (beta strings), and C / C^T
+  std::vector<const double*> Cd(prog.diags.size(), nullptr), CTd(prog.diags.size(), nullptr);
+  if (!prog.diags.empty()) {
+    double* arena = P.arena_for(prog.diags.size() * (size_t)(da + db));
+    for (size_t i = 0; i < prog.diags.size(); ++i) {
+      const DiagSpec& d = prog.diags[i];
+      TableBuild tb{};
+      if (d.lin_a) tb.spec.lin_a = up.put(d.lin_a, N);
+      if (d.lin_b) tb.spec.lin_b = up.put(d.lin_b, N);
+      if (d.Qa) tb.spec.Qa = up.put(d.Qa, (size_t)N * N);
+      if (d.Qb) tb.spec.Qb = up.put(d.Qb, (size_t)N * N);
+      tb.A = arena + i * (size_t)(da + db);
+      tb.B = tb.A + da;
+      c.tables.push_back(tb);
+      if (d.C) {
+        std::vector<double> CT((size_t)N * N);
+        for (int p = 0; p < N; ++p)
+          for (int q = 0; q < N; ++q) CT[q * N + p] = d.C[p * N + q];
+        Cd[i] = up.put(d.C, (size_t)N * N);
+        CTd[i] = up.put(CT.data(), CT.size());
+      }
+    }
+  }
+
+  int layout = 0;
+  std::vector<const Decomposition*> pending_other;
+  Pending pend[2];
+  std::vector<Item> visit;
+  auto colspin = [&]() { return layout == 0 ? 1 : 0; };
+  auto rowspin = [&]() { return layout == 0 ? 0 : 1; };
+
+  auto fold = [&](dev::StageDev& st) {
+    // deferred phase layers of the row spin and of the column spin
+    for (int role = 0; role < 2; ++role) {
+      const int sp = role == 0 ? rowspin() : colspin();
+      Pending& pd = pend[sp];
+      if (!pd.has) continue;
+      if (pd.sign_only) {
+        (role == 0 ? st.sign_row : st.sign_col) ^= pd.sign;
+      } else {
+        (role == 0 ? st.drow : st.dcol) = up.put(pd.delta.data(), pd.delta.size());
+      }
+      pd = Pending{};
+    }
+  };
+  auto diag_stage = [&](int type, int diag, double scale) {
+    dev::StageDev st{};
+    st.type = type;
+    st.scale = scale;
+    if (diag >= 0) {
+      const TableBuild& tb = c.tables[diag];
+      st.A = layout == 0 ? tb.A : tb.B;
+      st.B = layout == 0 ? tb.B : tb.A;
+      st.C = layout == 0 ? Cd[diag] : CTd[diag];
+    }
+    return st;
+  };
+  auto add_givens = [&](const Decomposition* d) {
+    const int sp = colspin();
+    if (pend[sp].has) {  // an earlier phase layer of this spin must land first
+      Item it;
+      it.kind = 1;
+      it.st = diag_stage(dev::ST_PHASE, -1, 0.0);
+      fold(it.st);
+      visit.push_back(it);
+    }
+    Item it;
+    it.kind = 0;
+    it.d = d;
+    visit.push_back(it);
+    Pending& pd = pend[sp];
+    for (double x : d->phase)
+      if (x != 0.0) pd.has = true;
+    if (pd.has) {
+      pd.sign_only = d->real;
+      if (d->real) {
+        pd.sign = 0;
+        for (int p = 0; p < N; ++p)
+          if (d->phase[p] != 0.0) pd.sign |= 1u << p;
+      } else {
+        pd.delta = d->phase;
+      }
+    }
+  };
+
+  auto close_visit = [&](bool force_seg) {
+    const auto& ss = P.seg[colspin()];
+    const int64_t n_rows = layout == 0 ? da : db;
+    const int ncol = P.n[colspin()];
+    const double pairs_per_row = (double)binom(N - 2, ncol - 1);
+    std::vector<dev::StageDev> stages;
+    Launch cur{};
+    cur.kind = Launch::SEG;
+    cur.layout = layout;
+    bool any = false;
+    auto flush_seg = [&](bool force) {
+      if (stages.empty() && !force) return;
+      cur.stages = stages.empty() ? nullptr : up.put(stages.data(), stages.size());
+      cur.n_stages = (int)stages.size();
+      c.launches.push_back(cur);
+      stages.clear();
+      cur = Launch{};
+      cur.kind = Launch::SEG;
+      cur.layout = layout;
+    };
+    for (const Item& it : visit) {
+      if (it.kind == 1) {
+        stages.push_back(it.st);
+        if (it.st.type == dev::ST_REDUCE) cur.reduce = true;
+        any = true;
+        continue;
+      }
+      const Decomposition& d = *it.d;
+      const auto deps = rotation_deps(d.rots, N);
+      std::vector<char> done(d.rots.size(), 0);
+      size_t n_done = 0;
+      const double K = 0.5 * N * (N - 1);
+      while (n_done < d.rots.size()) {
+        // register-window stages inside the segment window [0, wt)
+        while (ss.Wseg >= 2) {
+          int best_a = -1;
+          std::vector<int> best;
+          for (int a = 0; a + ss.Wseg <= ss.wt; ++a) {
+            auto t = take_window(d.rots, deps, done, a, ss.Wseg);
+            if (t.size() > best.size()) {
+              best = t;
+              best_a = a;
+            }
+          }
+          if (best.empty()) break;
+          std::vector<dev::RotDev> buf;
+          for (int i : best) {
+            const Givens& g = d.rots[i];
+            buf.push_back(dev::RotDev{g.p - best_a, 0, g.c, g.s.real(), g.s.imag()});
+            done[i] = 1;
+          }
+          n_done += best.size();
+          dev::StageDev st{};
+          st.type = dev::ST_GIVENS;
+          st.a = best_a;
+          st.nrot = (int)buf.size();
+          st.rots = up.put(buf.data(), buf.size());
+          stages.push_back(st);
+          cur.real = cur.real && d.real;
+          cur.valu_slots += (double)best.size() * pairs_per_row * (double)n_rows * (d.real ? 8.0 : 12.0);
+          cur.rot_sides += best.size() / K;
+          any = true;
+        }
+        if (n_done == d.rots.size()) break;
+        // rotations crossing segments: one whole-spin window pass
+        flush_seg(false);
+        int best_a = -1;
+        std::vector<int> best;
+        for (int a = 0; a + P.W <= N; ++a) {
+          auto t = take_window(d.rots, deps, done, a, P.W);
+          if (t.size() > best.size()) {
+            best = t;
+            best_a = a;
+          }
+        }
+        if (best.empty()) throw Error(FFX_EDEVICE, "rotation schedule made no progress");
+        std::vector<dev::RotDev> buf;
+        for (int i : best) {
+          const Givens& g = d.rots[i];
+          buf.push_back(dev::RotDev{g.p - best_a, 0, g.c, g.s.real(), g.s.imag()});
+          done[i] = 1;
+        }
+        n_done += best.size();
+        Launch w{};
+        w.kind = Launch::WIN;
+        w.layout = layout;
+        w.real = d.real;
+        w.a = best_a;
+        w.nrot = (int)buf.size();
+        w.rots = up.put(buf.data(), buf.size());
+        w.valu_slots = (double)best.size() * pairs_per_row * (double)n_rows * (d.real ? 8.0 : 12.0);
+        w.rot_sides = best.size() / K;
+        c.launches.push_back(w);
+      }
+    }
+    flush_seg(force_seg && !any);
+    if (!stages.empty()) flush_seg(false);
+    visit.clear();
+  };
+  auto transpose = [&]() {
+    Launch t{};
+    t.kind = Launch::TRANSPOSE;
+    t.layout = layout;
+    c.launches.push_back(t);
+    layout ^= 1;
+  };
+  auto switch_layout = [&]() {
+    close_visit(false);
+    transpose();
+    for (const Decomposition* d : pending_other) add_givens(d);
+    pending_other.clear();
+  };
+
+  for (const ProgOp& op : prog.ops) {
+    if (op.kind == ProgOp::ROT) {
+      add_givens(op.part[colspin()]);
+      pending_other.push_back(op.part[rowspin()]);
+      continue;
+    }
+    if (!pending_other.empty()) switch_layout();
+    Item it;
+    it.kind = 1;
+    if (op.kind == ProgOp::PHASE) {
+      it.st = diag_stage(dev::ST_PHASE, op.diag, op.scale);
+      fold(it.st);
+    } else if (op.kind == ProgOp::SCALE) {
+      it.st = diag_stage(dev::ST_SCALE, op.diag, 0.0);
+    } else {
+      it.st = diag_stage(dev::ST_REDUCE, op.diag, 0.0);
+    }
+    visit.push_back(it);
+    if (op.kind == ProgOp::REDUCE) {
+      // close now, so that the reduction's partial sums belong to one launch
+      close_visit(false);
+      c.launches.back().reduce_out = op.out;
+    }
+  }
+  if (!pending_other.empty()) switch_layout();
+  if (final_mode != FINAL_NONE && (pend[0].has || pend[1].has)) {
+    Item it;
+    it.kind = 1;
+    it.st = diag_stage(dev::ST_PHASE, -1, 0.0);
+    fold(it.st);
+    visit.push_back(it);
+  }
+  close_visit(false);
+  if (final_mode != FINAL_NONE && layout == 1) transpose();
+  if (final_mode == FINAL_ACCUM &&
+      (c.launches.empty() || c.launches.back().kind != Launch::SEG || c.launches.back().layout != 0))
+    close_visit(true);  // a stage-free segment pass that adds the result into the target
+  return c;
+}
+
+void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* work, void* accum,
+                     hipStream_t s) {
+  const int64_t da = P.dim[0], db = P.dim[1];
+  const int N = P.norb;
+  for (const TableBuild& tb : c.tables) {
+    dev::diag_tables(P.d_masks[0], da, P.d_masks[1], db, N, tb.spec, tb.A, tb.B, nullptr, s);
+    check_launch();
+  }
+  int last_seg = -1;
+  for (int i = 0; i < (int)c.launches.size(); ++i)
+    if (c.launches[i].kind == Launch::SEG) last_seg = i;
+  const void* cur_src = src;
+  void* cur = work;
+  if (src != work && (c.launches.empty() || c.launches[0].kind != Launch::SEG)) {
+    HIPCHK(hipMemcpyAsync(work, src, P.state_bytes(), hipMemcpyDeviceToDevice, s));
+    cur_src = work;
+  }
+  const bool square = da == db;
+  for (int i = 0; i < (int)c.launches.size(); ++i) {
+    const Launch& L = c.launches[i];
+    const int64_t rows = L.layout == 0 ? da : db;
+    const int64_t cols = L.layout == 0 ? db : da;
+    const int cs = L.layout == 0 ? 1 : 0;
+    ffx_plan_s::Timed tm{};
+    const bool timed = P.timing && (L.kind == Launch::SEG || L.kind == Launch::WIN);
+    if (timed) {
+      tm.a = P.take_event();
+      tm.b = P.take_event();
+      tm.kind = L.kind == Launch::SEG ? 1 : 0;
+      tm.spin = cs;
+      tm.valu_slots = L.valu_slots;
+      tm.alg_bytes = L.rot_sides * 2.0 * (double)P.state_bytes();
+      HIPCHK(hipEventRecord(tm.a, s));
+    }
+    if (L.kind == Launch::SEG) {
+      const auto& ss = P.seg[cs];
+      dev::SegPassDev p{};
+      p.src = cur_src;
+      p.norb = N;
+      p.n_rows = rows;
+      p.row_len = cols;
+      p.row_masks = P.d_masks[L.layout == 0 ? 0 : 1];
+      p.col_masks = P.d_masks[cs];
+      p.n_seg = ss.n_seg;
+      p.segs = ss.d_segs;
+      p.n_stages = L.n_stages;
+      p.stages = L.stages;
+      p.partials = L.reduce ? P.partials : nullptr;
+      p.lds_row_bytes = (int)(((size_t)ss.max_len * P.elem() + 15) & ~(size_t)15);
+      if (i == last_seg && c.final_mode == FINAL_ACCUM) {
+        p.mode = dev::SEG_ACCUM;
+        p.dst = accum;
+      } else if (i == last_seg && c.final_mode == FINAL_NONE) {
+        p.mode = dev::SEG_NONE;
+        p.dst = nullptr;
+      } else {
+        p.mode = dev::SEG_STORE;
+        p.dst = cur;
+      }
+      dev::seg_pass(P.c64, L.real, ss.Wseg, p, ss.threads, ss.lds, s);
+      check_launch();
+      if (L.reduce) {
+        dev::sum_partials(P.partials, (int)(rows * ss.n_seg), L.reduce_out, s);
+        check_launch();
+      }
+      cur_src = cur;
+    } else if (L.kind == Launch::WIN) {
+      dev::win_pass(P.c64, L.real, 1, cur, rows, cols, P.win[cs][L.a], L.rots, L.nrot, nullptr, s);
+      check_launch();
+      cur_src = cur;
+    } else if (L.kind == Launch::TRANSPOSE) {
+      if (square) {
+        dev::transpose_square(P.c64, cur, rows, s);
+      } else {
+        void* other = (cur == work) ? P.tmp_state() : work;
+        dev::transpose(P.c64, cur, other, rows, cols, s);
+        cur = other;
+      }
+      check_launch();
+      cur_src = cur;
+    }
+    if (timed) {
+      HIPCHK(hipEventRecord(tm.b, s));
+      P.timed.push_back(tm);
+    }
+  }
+}
+
+}  // namespace ffx

@@ -81,7 +81,7 @@ _ws = _sig("ffx_workspace_bytes", ctypes.c_int64, [_vp, ctypes.c_int])
 _energy = _sig("ffx_df_energy", ctypes.c_int, [_vp, _vp, ctypes.POINTER(_DFHam), _c_double_p, _vp, _vp])
 _tenable = _sig("ffx_timing_enable", ctypes.c_int, [_vp, ctypes.c_int])
 _tread = _sig("ffx_timing_read", ctypes.c_int,
-              [_vp, ctypes.c_int, _c_double_p, ctypes.POINTER(ctypes.c_int64), _c_double_p])
+              [_vp, ctypes.c_int, _c_double_p, ctypes.POINTER(ctypes.c_int64), _c_double_p, _c_double_p])
 _egrad = _sig("ffx_lucj_energy_grad", ctypes.c_int,
               [_vp, ctypes.POINTER(_LUCJ), ctypes.POINTER(_DFHam), _c_double_p, _c_double_p, _vp, _vp, _vp])
 
@@ -199,11 +199,12 @@ class Plan:
         """Start (reset) or stop per-launch event timing of the Givens window passes."""
         _check(_tenable(self._h, int(bool(enable))))
 
-    def timing_read(self, spin: int):
-        """-> (total kernel ms, launches, algorithmic bytes) of the recorded passes of one spin."""
-        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
-        _check(_tread(self._h, spin, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
-        return ms.value, n.value, b.value
+    def timing_read(self, kind: int, spin: int):
+        """-> (kernel ms, launches, algorithmic bytes, algorithmic VALU slots) of the recorded
+        launches of one kind (0 = window passes, 1 = segment passes) rotating one spin."""
+        ms, n, b, v = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        _check(_tread(self._h, 2 * kind + spin, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b), ctypes.byref(v)))
+        return ms.value, n.value, b.value, v.value
 
     def check_vec(self, vec: torch.Tensor):
         if vec.dtype != self.dtype:
@@ -225,8 +226,9 @@ def get_plan(norb: int, nelec, dtype=torch.complex128, device=0) -> Plan:
     return _plan_cached(int(norb), (int(nelec[0]), int(nelec[1])), dtype, int(device))
 
 
-def _prepare(vec: torch.Tensor, norb, nelec, out):
-    plan = get_plan(norb, nelec, vec.dtype, vec.device.index or 0)
+def _prepare(vec: torch.Tensor, norb, nelec, out, plan=None):
+    if plan is None:
+        plan = get_plan(norb, nelec, vec.dtype, vec.device.index or 0)
     plan.check_vec(vec)
     if out is None:
         out = vec.clone()
@@ -257,8 +259,8 @@ def _lucj_struct(params, norb, n_reps):
 # gates (Table 1)
 # ---------------------------------------------------------------------------
 
-def apply_orbital_rotation(vec: torch.Tensor, U, norb: int, nelec, *, U_b=None, out=None) -> torch.Tensor:
-    plan, out = _prepare(vec, norb, nelec, out)
+def apply_orbital_rotation(vec: torch.Tensor, U, norb: int, nelec, *, U_b=None, out=None, plan=None) -> torch.Tensor:
+    plan, out = _prepare(vec, norb, nelec, out, plan)
     Ua = _cplx(U, (norb, norb))
     Ub = _cplx(U_b, (norb, norb)) if U_b is not None else None
     _check(_rot(plan.handle, _vp(out.data_ptr()), _dptr(Ua), _dptr(Ub) if Ub is not None else None,
@@ -267,8 +269,8 @@ def apply_orbital_rotation(vec: torch.Tensor, U, norb: int, nelec, *, U_b=None, 
 
 
 def apply_num_op_sum_evolution(vec: torch.Tensor, lam, time: float, norb: int, nelec, *, lam_b=None,
-                               out=None) -> torch.Tensor:
-    plan, out = _prepare(vec, norb, nelec, out)
+                               out=None, plan=None) -> torch.Tensor:
+    plan, out = _prepare(vec, norb, nelec, out, plan)
     la = _real(lam, (norb,))
     lb = _real(lam_b, (norb,)) if lam_b is not None else None
     _check(_numop(plan.handle, _vp(out.data_ptr()), _dptr(la), _dptr(lb) if lb is not None else None,
@@ -277,8 +279,8 @@ def apply_num_op_sum_evolution(vec: torch.Tensor, lam, time: float, norb: int, n
 
 
 def apply_diag_coulomb_evolution(vec: torch.Tensor, J, time: float, norb: int, nelec, *, J_ab=None, J_bb=None,
-                                 out=None) -> torch.Tensor:
-    plan, out = _prepare(vec, norb, nelec, out)
+                                 out=None, plan=None) -> torch.Tensor:
+    plan, out = _prepare(vec, norb, nelec, out, plan)
     Jaa = _real(J, (norb, norb))
     Jab = _real(J_ab, (norb, norb)) if J_ab is not None else None
     Jbb = _real(J_bb, (norb, norb)) if J_bb is not None else None
@@ -288,9 +290,9 @@ def apply_diag_coulomb_evolution(vec: torch.Tensor, J, time: float, norb: int, n
 
 
 def simulate_trotter_double_factorized(vec: torch.Tensor, ham, time: float, norb: int, nelec, *,
-                                       n_steps: int = 1, order: int = 0, out=None) -> torch.Tensor:
+                                       n_steps: int = 1, order: int = 0, out=None, plan=None) -> torch.Tensor:
     """exp(-i H time) vec by n_steps steps of the order-`order` product formula (Sec. 4.5.3)."""
-    plan, out = _prepare(vec, norb, nelec, out)
+    plan, out = _prepare(vec, norb, nelec, out, plan)
     s, keep = _df_struct(ham, norb)
     dt = float(time) / max(n_steps, 1)
     _check(_trotter(plan.handle, _vp(out.data_ptr()), ctypes.byref(s), dt, int(n_steps), int(order),
@@ -299,8 +301,8 @@ def simulate_trotter_double_factorized(vec: torch.Tensor, ham, time: float, norb
 
 
 def apply_lucj(params, norb: int, nelec, n_reps: int, *, dtype=torch.complex128, device=0,
-               out=None) -> torch.Tensor:
-    plan = get_plan(norb, nelec, dtype, device)
+               out=None, plan=None) -> torch.Tensor:
+    plan = plan or get_plan(norb, nelec, dtype, device)
     if out is None:
         out = torch.empty((plan.dim_a, plan.dim_b), dtype=dtype, device=f"cuda:{device}")
     plan.check_vec(out)
@@ -309,8 +311,8 @@ def apply_lucj(params, norb: int, nelec, n_reps: int, *, dtype=torch.complex128,
     return out
 
 
-def df_energy(vec: torch.Tensor, ham, norb: int, nelec) -> float:
-    plan = get_plan(norb, nelec, vec.dtype, vec.device.index or 0)
+def df_energy(vec: torch.Tensor, ham, norb: int, nelec, *, plan=None) -> float:
+    plan = plan or get_plan(norb, nelec, vec.dtype, vec.device.index or 0)
     plan.check_vec(vec)
     s, keep = _df_struct(ham, norb)
     ws = plan.workspace(0)
@@ -321,9 +323,9 @@ def df_energy(vec: torch.Tensor, ham, norb: int, nelec) -> float:
 
 
 def lucj_energy_grad(params, ham, norb: int, nelec, n_reps: int, *, dtype=torch.complex128, device=0,
-                     psi_out: torch.Tensor | None = None):
+                     psi_out: torch.Tensor | None = None, plan=None):
     """(E, dE/dtheta) of the LUCJ state under the DF Hamiltonian, by the adjoint method."""
-    plan = get_plan(norb, nelec, dtype, device)
+    plan = plan or get_plan(norb, nelec, dtype, device)
     s, keep = _lucj_struct(params, norb, n_reps)
     hs, hkeep = _df_struct(ham, norb)
     grad = np.zeros(keep.size)

@@ -221,3 +221,44 @@ def test_errors_do_not_crash(ffx):
         ffx.apply_orbital_rotation(vec, np.eye(4), 4, (2, 1))
     with pytest.raises(TypeError):
         ffx.apply_orbital_rotation(vec.to(torch.complex64), np.eye(4), 4, (2, 2), out=vec)
+
+
+@pytest.fixture(scope="module")
+def small_segment_plans(ffx):
+    """Plans whose segments are forced to be tiny, so that rotations cross segments
+    and run through whole-spin window passes between segment passes."""
+    import os
+    plans = {}
+    old = os.environ.get("FFX_SEG_MAX")
+    os.environ["FFX_SEG_MAX"] = "24"
+    try:
+        for norb, nelec, dt in [(8, (4, 4), torch.complex128), (10, (3, 6), torch.complex128),
+                                (9, (4, 5), torch.complex64), (11, (5, 4), torch.complex128)]:
+            plans[(norb, nelec, dt)] = ffx.Plan(norb, nelec, dt)
+    finally:
+        if old is None:
+            del os.environ["FFX_SEG_MAX"]
+        else:
+            os.environ["FFX_SEG_MAX"] = old
+    return plans
+
+
+def test_segmented_paths(ffx, small_segment_plans):
+    for (norb, nelec, dtype), plan in small_segment_plans.items():
+        r = synth.rng([21, norb])
+        da, db = _dims(norb, nelec)
+        vec = _to_dev(synth.random_state(r, da, db), dtype)
+        x = _ref_input(vec)
+        U = synth.random_unitary(r, norb)
+        out = ffx.apply_orbital_rotation(vec, U, norb, nelec, plan=plan)
+        assert _maxdiff(out, og.apply_orbital_rotation(x, U, norb, nelec)) <= TOL[dtype]
+        ham = synth.df_hamiltonian(r, norb, 3)
+        out = ffx.simulate_trotter_double_factorized(vec, ham, 0.2, norb, nelec, n_steps=2, order=1, plan=plan)
+        ref = oh.simulate_trotter(x, ham, 0.2, norb, nelec, n_steps=2, order=1)
+        assert _maxdiff(out, ref) <= TOL[dtype] * 10
+        e = ffx.df_energy(vec, ham, norb, nelec, plan=plan)
+        ref = oh.df_energy(x, ham, norb, nelec).real
+        assert abs(e - ref) <= (1e-10 if dtype == torch.complex128 else 1e-5) * max(1, abs(ref))
+        params = synth.lucj_params(r, norb, 2, scale=0.3)
+        out = ffx.apply_lucj(params, norb, nelec, 2, dtype=dtype, plan=plan)
+        assert _maxdiff(out, ol.apply_lucj(params, norb, nelec, 2)) <= TOL[dtype]

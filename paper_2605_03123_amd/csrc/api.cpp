@@ -395,9 +395,10 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
     P->arena_doubles = (size_t)ffx_plan_s::kArenaSlots * (size_t)(P->dim[0] + P->dim[1]);
     P->arena = (double*)P->dalloc(P->arena_doubles * 8);
     // segment passes: for each column spin, the widest segment window whose
-    // segments fit in LDS next to the stage tables
-    const size_t lds_budget = 160 * 1024 - dev::seg_pass_lds(P->c64, 0) - 64;
-    int64_t max_elems = (int64_t)(lds_budget / P->elem());
+    // segments fit in LDS together with the stage tables and the member
+    // offset tables of every register window inside the segment
+    const size_t lds_cap = 160 * 1024 - 64;
+    int64_t max_elems = (int64_t)((lds_cap - dev::seg_pass_lds(P->c64, 0, 0)) / P->elem());
     if (const char* e = std::getenv("FFX_SEG_MAX")) {  // smaller segments, for tests
       int64_t v = std::atoll(e);
       if (v >= 1 && v < max_elems) max_elems = v;
@@ -407,6 +408,7 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
       auto& ss = P->seg[s];
       const auto& strs = P->str[s];
       std::vector<std::pair<int, int>> segs;
+      std::vector<std::vector<SegWindowTable>> tabs;
       int wt = norb;
       for (; wt >= 0; --wt) {
         segs.clear();
@@ -419,41 +421,59 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
           longest = std::max<int64_t>(longest, (int64_t)(j - i));
           i = j;
         }
-        if (longest <= max_elems) break;
+        if (longest > max_elems) continue;
+        const int Wseg = std::min(P->W, wt);
+        tabs.assign(segs.size(), {});
+        size_t need = 0;
+        for (size_t g = 0; g < segs.size(); ++g) {
+          std::vector<uint64_t> sub(strs.begin() + segs[g].first, strs.begin() + segs[g].first + segs[g].second);
+          size_t mt = 0;
+          for (int a = 0; Wseg >= 2 && a + Wseg <= wt; ++a) {
+            tabs[g].push_back(build_seg_window(sub, wt, a, Wseg));
+            mt = ((mt + 3) & ~(size_t)3) + tabs[g].back().mt.size();
+          }
+          need = std::max(need, dev::seg_pass_lds(P->c64, segs[g].second, (int)mt));
+        }
+        if (need <= lds_cap) break;
       }
+      if (wt < 0) throw Error(FFX_EUNSUPPORTED, "no segment window fits in LDS");
       ss.wt = wt;
       ss.Wseg = std::min(P->W, wt);
       ss.n_seg = (int)segs.size();
       ss.max_len = 0;
+      ss.max_mt = 0;
       std::vector<dev::SegDev> hsegs;
-      for (auto& sg : segs) {
+      for (size_t g = 0; g < segs.size(); ++g) {
+        const auto& sg = segs[g];
         ss.max_len = std::max(ss.max_len, sg.second);
-        std::vector<uint64_t> sub(strs.begin() + sg.first, strs.begin() + sg.first + sg.second);
-        std::vector<dev::WinDev> wins;
-        for (int a = 0; a + ss.Wseg <= wt && ss.Wseg >= 1; ++a) {
-          WindowTable t = build_window_table(sub, norb, 0, a, ss.Wseg);
-          dev::WinDev wd{};
-          int* tab = (int*)P->dalloc(t.tab.size() * 4);
-          int* cm = (int*)P->dalloc(t.chunk_m.size() * 4);
-          int* co = (int*)P->dalloc(t.chunk_off.size() * 4);
-          HIPCHK(hipMemcpy(tab, t.tab.data(), t.tab.size() * 4, hipMemcpyHostToDevice));
-          HIPCHK(hipMemcpy(cm, t.chunk_m.data(), t.chunk_m.size() * 4, hipMemcpyHostToDevice));
-          HIPCHK(hipMemcpy(co, t.chunk_off.data(), t.chunk_off.size() * 4, hipMemcpyHostToDevice));
-          wd.tab = tab;
+        std::vector<dev::SegWinDev> wins;
+        std::vector<int> mt_all;
+        for (const SegWindowTable& t : tabs[g]) {
+          dev::SegWinDev wd{};
+          int* code = (int*)P->dalloc(std::max<size_t>(t.code.size(), 1) * 4);
+          int* cm = (int*)P->dalloc(std::max<size_t>(t.chunk_m.size(), 1) * 4);
+          if (!t.code.empty()) HIPCHK(hipMemcpy(code, t.code.data(), t.code.size() * 4, hipMemcpyHostToDevice));
+          if (!t.chunk_m.empty()) HIPCHK(hipMemcpy(cm, t.chunk_m.data(), t.chunk_m.size() * 4, hipMemcpyHostToDevice));
+          wd.code = code;
           wd.chunk_m = cm;
-          wd.chunk_off = co;
+          while (mt_all.size() % 4) mt_all.push_back(0);
+          wd.mt_off = (int)mt_all.size();
           wd.n_chunks = (int)t.chunk_m.size();
-          wd.a = a;
-          wd.w = ss.Wseg;
+          wd.nl1 = t.nl1;
+          mt_all.insert(mt_all.end(), t.mt.begin(), t.mt.end());
           wins.push_back(wd);
         }
-        dev::WinDev* dw = (dev::WinDev*)P->dalloc(std::max<size_t>(wins.size(), 1) * sizeof(dev::WinDev));
-        if (!wins.empty()) HIPCHK(hipMemcpy(dw, wins.data(), wins.size() * sizeof(dev::WinDev), hipMemcpyHostToDevice));
-        hsegs.push_back(dev::SegDev{sg.first, sg.second, dw});
+        ss.max_mt = std::max(ss.max_mt, (int)mt_all.size());
+        auto* dw = (dev::SegWinDev*)P->dalloc(std::max<size_t>(wins.size(), 1) * sizeof(dev::SegWinDev));
+        if (!wins.empty())
+          HIPCHK(hipMemcpy(dw, wins.data(), wins.size() * sizeof(dev::SegWinDev), hipMemcpyHostToDevice));
+        int* dmt = (int*)P->dalloc(std::max<size_t>(mt_all.size(), 1) * 4);
+        if (!mt_all.empty()) HIPCHK(hipMemcpy(dmt, mt_all.data(), mt_all.size() * 4, hipMemcpyHostToDevice));
+        hsegs.push_back(dev::SegDev{sg.first, sg.second, dw, dmt, (int)mt_all.size(), 0});
       }
       ss.d_segs = (dev::SegDev*)P->dalloc(hsegs.size() * sizeof(dev::SegDev));
       HIPCHK(hipMemcpy(ss.d_segs, hsegs.data(), hsegs.size() * sizeof(dev::SegDev), hipMemcpyHostToDevice));
-      ss.lds = dev::seg_pass_lds(P->c64, ss.max_len);
+      ss.lds = dev::seg_pass_lds(P->c64, ss.max_len, ss.max_mt);
       ss.threads = ss.max_len >= 4096 ? 768 : (ss.max_len >= 1024 ? 256 : 64);
       // rows of this column spin's layout times segments: one partial sum per block
       max_rows_x_seg = std::max<int>(max_rows_x_seg, (int)(P->dim[1 - s] * ss.n_seg));

@@ -143,22 +143,38 @@ __device__ __forceinline__ void rot_one(typename V2T<R>::type* v, R c, R sr, R s
   rot_pairs<W, M, P, REAL, R>(v, c, sr, si, std::make_integer_sequence<int, Pairs<W, M, P>::NP>{});
 }
 
-template <int W, int M, bool REAL, class R, int P = 0>
+template <int W, int M, int P, bool REAL, class R>
+__device__ __forceinline__ void rot_case(typename V2T<R>::type* v, R c, R sr, R si) {
+  if constexpr (P < W - 1) rot_one<W, M, P, REAL, R>(v, c, sr, si);
+}
+
+// one uniform jump per rotation (a dense switch lowers to a jump table)
+template <int W, int M, bool REAL, class R>
 __device__ __forceinline__ void rot_dispatch(int p, typename V2T<R>::type* v, R c, R sr, R si) {
-  if constexpr (P < W - 1) {
-    if (p == P)
-      rot_one<W, M, P, REAL, R>(v, c, sr, si);
-    else
-      rot_dispatch<W, M, REAL, R, P + 1>(p, v, c, sr, si);
+  static_assert(W <= 8, "window wider than the dispatch table");
+  switch (p) {
+    case 0: rot_case<W, M, 0, REAL, R>(v, c, sr, si); break;
+    case 1: rot_case<W, M, 1, REAL, R>(v, c, sr, si); break;
+    case 2: rot_case<W, M, 2, REAL, R>(v, c, sr, si); break;
+    case 3: rot_case<W, M, 3, REAL, R>(v, c, sr, si); break;
+    case 4: rot_case<W, M, 4, REAL, R>(v, c, sr, si); break;
+    case 5: rot_case<W, M, 5, REAL, R>(v, c, sr, si); break;
+    case 6: rot_case<W, M, 6, REAL, R>(v, c, sr, si); break;
+    default: break;
   }
 }
 
 template <int W, int M, bool REAL, class R>
 __device__ __forceinline__ void apply_rots(typename V2T<R>::type* v, const RotDev* __restrict__ rots,
                                            int nrot) {
+  if (nrot <= 0) return;
+  // the next rotation's parameters are requested before the current one is
+  // applied, so the (uniform) load latency overlaps the arithmetic
+  RotDev cur = rots[0];
   for (int r = 0; r < nrot; ++r) {
-    const RotDev rd = rots[r];
-    rot_dispatch<W, M, REAL, R>(rd.p, v, (R)rd.c, (R)rd.sr, (R)rd.si);
+    const RotDev nxt = rots[r + 1 < nrot ? r + 1 : r];
+    rot_dispatch<W, M, REAL, R>(cur.p, v, (R)cur.c, (R)cur.sr, (R)cur.si);
+    cur = nxt;
   }
 }
 

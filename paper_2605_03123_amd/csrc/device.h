@@ -114,8 +114,10 @@ void diag_grad_combine(const double* rowout, int64_t dim_a, const uint32_t* mask
 enum StageType { ST_GIVENS = 0, ST_PHASE = 1, ST_SCALE = 2, ST_REDUCE = 3 };
 
 // f(row, col) = A[row] + B[col] + sum_{p in row, q in col} C[p * norb + q]
-//   ST_PHASE : x *= (-1)^{|row & sign_row| + |col & sign_col|}
-//                   * exp(i (scale f + sum_{p in row} drow[p] + sum_{q in col} dcol[q]))
+//   ST_PHASE : x *= (-1)^{|row & sign_row|} exp(i (scale (A[row] + cross) + sum_{p in row} drow[p]))
+//                   * colf[col]
+//              where colf (built per stage) holds the column-only factor
+//              (-1)^{|col & sign_col|} exp(i (scale B[col] + sum_{q in col} dcol[q]))
 //   ST_SCALE : x *= f
 //   ST_REDUCE: accumulate f |x|^2 into the block's partial sum
 // ST_GIVENS: the rotations rots[0..nrot) on the window [a, a + W) of the
@@ -125,24 +127,43 @@ struct StageDev {
   int a;
   int nrot;
   uint32_t sign_row;
-  uint32_t sign_col;
-  int pad;
   const RotDev* rots;
   double scale;
   const double* A;
   const double* B;
   const double* C;
   const double* drow;
-  const double* dcol;
+  const double* colf;  // complex (re, im) per column string
+};
+
+// Class tables of one register window inside one segment.  Chunk ch holds 64
+// lanes; code[ch * 64 + lane] = (cbase << 5) | l for the lane's class (-1 for
+// padding), where member k of the class sits at cbase + mt[mt[m * nl1 + l] + k]
+// (m = electrons in the window, l = electrons below it).  Chunks are listed in
+// order of decreasing work; classes with an empty or full window are omitted.
+struct SegWinDev {
+  const int* code;
+  const int* chunk_m;
+  int mt_off;  // start of this window's offsets inside the segment's mt_all
+  int n_chunks;
+  int nl1;
+  int pad;
 };
 
 // one segment of a row: [off, off + len) of the column strings, all sharing
 // the occupation of the orbitals above the segment window; win[a] holds the
-// class tables of the window [a, a + W) with positions relative to off.
+// class tables of the register window [a, a + W), positions relative to off.
 struct SegDev {
   int off, len;
-  const WinDev* win;
+  const SegWinDev* win;
+  const int* mt_all;  // member offsets of every window, staged into LDS once per block
+  int n_mt_all;
+  int pad;
 };
+
+// colf[i] = (-1)^{|mask_i & sign|} exp(i (scale B[i] + sum_{q in mask_i} delta[q]))
+void column_factors(const uint32_t* masks, int64_t n, const double* B, double scale, const double* delta,
+                    uint32_t sign, double* colf, hipStream_t stream);
 
 enum SegMode { SEG_STORE = 0, SEG_ACCUM = 1, SEG_NONE = 2 };
 
@@ -160,10 +181,11 @@ struct SegPassDev {
   const StageDev* stages;
   double* partials;
   int lds_row_bytes;  // byte offset of the scratch area after the row segment
+  int max_mt;         // ints reserved in LDS for the member offsets of all windows
 };
 
 // LDS needed by a segment pass whose longest segment holds max_len amplitudes
-size_t seg_pass_lds(bool c64, int max_len);
+size_t seg_pass_lds(bool c64, int max_len, int max_mt);
 // blocks = n_rows * n_seg; partials (if any stage reduces) get one entry per block
 void seg_pass(bool c64, bool real, int W, const SegPassDev& p, int block_threads, size_t lds_bytes,
               hipStream_t stream);

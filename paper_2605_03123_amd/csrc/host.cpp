@@ -195,6 +195,86 @@ WindowTable build_window_table(const std::vector<uint64_t>& strs, int norb, int 
   return t;
 }
 
+SegWindowTable build_seg_window(const std::vector<uint64_t>& seg, int wt, int a, int w) {
+  SegWindowTable t;
+  const uint64_t low_mask = (wt >= 64) ? ~0ull : ((1ull << wt) - 1);
+  const int n_low = seg.empty() ? 0 : __builtin_popcountll(seg[0] & low_mask);
+  t.nl1 = std::min(a, n_low) + 1;
+  // mt(m, l, k) = sum_j C(a + pos_j, l + j) over the set bits pos_1 < ... of the k-th m-pattern
+  std::vector<std::vector<int>> pats(w + 1);
+  for (int x = 0; x < (1 << w); ++x) pats[__builtin_popcount(x)].push_back(x);
+  const int header = (w + 1) * t.nl1;
+  t.mt.assign(header, 0);
+  while (t.mt.size() % 4) t.mt.push_back(0);  // tables start on 16-byte boundaries
+  for (int m = 0; m <= w; ++m)
+    for (int l = 0; l < t.nl1; ++l) {
+      t.mt[m * t.nl1 + l] = (int)t.mt.size();
+      for (int x : pats[m]) {
+        int64_t v = 0;
+        int j = 0;
+        for (int b = 0; b < w; ++b)
+          if ((x >> b) & 1) v += binom(a + b, l + (++j));
+        t.mt.push_back((int)v);
+      }
+      while (t.mt.size() % 4) t.mt.push_back(0);
+    }
+  std::vector<int> prank(1 << w);
+  for (int m = 0; m <= w; ++m)
+    for (size_t k = 0; k < pats[m].size(); ++k) prank[pats[m][k]] = (int)k;
+  const uint64_t wmask = ((1ull << w) - 1) << a;
+  const uint64_t below = (1ull << a) - 1;
+  struct Cls {
+    int m, l, cbase, count;
+  };
+  std::map<std::pair<int, uint64_t>, Cls> classes;  // (m, outside bits) -> class
+  for (size_t i = 0; i < seg.size(); ++i) {
+    const uint64_t sv = seg[i] & low_mask;
+    const int pat = (int)((sv & wmask) >> a);
+    const int m = __builtin_popcount(pat);
+    const int l = __builtin_popcountll(sv & below);
+    const int off = t.mt[t.mt[m * t.nl1 + l] + prank[pat]];
+    const int cbase = (int)i - off;
+    auto key = std::make_pair(m, sv & ~wmask);
+    auto it = classes.find(key);
+    if (it == classes.end()) {
+      classes.emplace(key, Cls{m, l, cbase, 1});
+    } else {
+      if (it->second.cbase != cbase || it->second.l != l)
+        throw Error(FFX_EDEVICE, "segment window table: inconsistent class base");
+      ++it->second.count;
+    }
+  }
+  // chunks of 64 classes sharing m (empty and full windows need no work)
+  std::map<int, std::vector<int>> by_m;
+  for (auto& kv : classes) {
+    const Cls& c = kv.second;
+    if (c.m == 0 || c.m == w) continue;
+    if (c.count != (int)binom(w, c.m)) throw Error(FFX_EDEVICE, "segment window table: incomplete class");
+    by_m[c.m].push_back((c.cbase << 5) | c.l);
+  }
+  struct Chunk {
+    int m;
+    double cost;
+    std::vector<int> codes;
+  };
+  std::vector<Chunk> chunks;
+  for (auto& kv : by_m) {
+    const int m = kv.first;
+    const double cost = (double)binom(w, m) * (2.0 + (double)binom(w - 2, m - 1));
+    for (size_t i = 0; i < kv.second.size(); i += 64) {
+      Chunk ch{m, cost, {}};
+      for (size_t j = i; j < std::min(i + 64, kv.second.size()); ++j) ch.codes.push_back(kv.second[j]);
+      chunks.push_back(std::move(ch));
+    }
+  }
+  std::stable_sort(chunks.begin(), chunks.end(), [](const Chunk& x, const Chunk& y) { return x.cost > y.cost; });
+  for (auto& ch : chunks) {
+    t.chunk_m.push_back(ch.m);
+    for (int j = 0; j < 64; ++j) t.code.push_back(j < (int)ch.codes.size() ? ch.codes[j] : -1);
+  }
+  return t;
+}
+
 std::vector<cd> matmul(int n, const std::vector<cd>& A, const std::vector<cd>& B) {
   std::vector<cd> C((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i)

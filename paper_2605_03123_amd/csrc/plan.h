@@ -39,6 +39,7 @@ struct ffx_plan_s {
     int wt = 0;        // segments share the occupation of orbitals >= wt
     int Wseg = 0;      // register window inside segment passes (windows within [0, wt))
     int max_len = 0;
+    int max_mt = 0;
     int n_seg = 0;
     size_t lds = 0;
     int threads = 256;
@@ -110,11 +111,20 @@ struct ffx_plan_s {
     if (!state_tmp) state_tmp = dalloc(state_bytes());
     return state_tmp;
   }
-  // diagonal tables of one program: kArenaSlots distinct functions at most
+  // per-program diagonal tables; every program of a call starts at offset 0
+  // (programs run one after another on the stream).  Growing frees the old
+  // arena, so a driver that compiles several programs before running them must
+  // stay within the initial size (kArenaSlots states' worth of string tables).
   static constexpr int kArenaSlots = 64;
-  double* arena_for(size_t doubles) {
-    if (doubles > arena_doubles)
-      throw ffx::Error(FFX_EUNSUPPORTED, "program has more distinct diagonal functions than the table arena");
+  double* arena_for(size_t doubles, hipStream_t s) {
+    if (doubles > arena_doubles) {
+      HIPCHK(hipStreamSynchronize(s));
+      HIPCHK(hipDeviceSynchronize());
+      allocs.erase(std::find(allocs.begin(), allocs.end(), (void*)arena));
+      (void)hipFree(arena);
+      arena = (double*)dalloc(doubles * sizeof(double));
+      arena_doubles = doubles;
+    }
     return arena;
   }
 
@@ -243,8 +253,18 @@ struct TableBuild {
   double* B;  // per beta string
 };
 
+struct ColfBuild {
+  int spin;          // column spin: its configuration masks
+  const double* B;   // per-string table (nullable)
+  double scale;
+  const double* delta;
+  uint32_t sign;
+  double* out;       // complex per string
+};
+
 struct Compiled {
   std::vector<TableBuild> tables;
+  std::vector<ColfBuild> colfs;
   std::vector<Launch> launches;
   int final_mode = FINAL_STORE;
 };

@@ -76,27 +76,30 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
   const int N = P.norb;
   const int64_t da = P.dim[0], db = P.dim[1];
 
-  // per diagonal function: device tables A (alpha strings), B (beta strings), and C / C^T
+  // arena: per diagonal function the tables A (alpha strings) and B (beta
+  // strings), then one complex column-factor table per phase stage
+  size_t n_phase = 2;
+  for (const ProgOp& op : prog.ops) n_phase += (op.kind == ProgOp::PHASE || op.kind == ProgOp::ROT) ? 1 : 0;
+  const size_t dmax = (size_t)std::max(da, db);
+  double* arena = P.arena_for(prog.diags.size() * (size_t)(da + db) + n_phase * 2 * dmax, s);
+  size_t arena_off = prog.diags.size() * (size_t)(da + db);
   std::vector<const double*> Cd(prog.diags.size(), nullptr), CTd(prog.diags.size(), nullptr);
-  if (!prog.diags.empty()) {
-    double* arena = P.arena_for(prog.diags.size() * (size_t)(da + db));
-    for (size_t i = 0; i < prog.diags.size(); ++i) {
-      const DiagSpec& d = prog.diags[i];
-      TableBuild tb{};
-      if (d.lin_a) tb.spec.lin_a = up.put(d.lin_a, N);
-      if (d.lin_b) tb.spec.lin_b = up.put(d.lin_b, N);
-      if (d.Qa) tb.spec.Qa = up.put(d.Qa, (size_t)N * N);
-      if (d.Qb) tb.spec.Qb = up.put(d.Qb, (size_t)N * N);
-      tb.A = arena + i * (size_t)(da + db);
-      tb.B = tb.A + da;
-      c.tables.push_back(tb);
-      if (d.C) {
-        std::vector<double> CT((size_t)N * N);
-        for (int p = 0; p < N; ++p)
-          for (int q = 0; q < N; ++q) CT[q * N + p] = d.C[p * N + q];
-        Cd[i] = up.put(d.C, (size_t)N * N);
-        CTd[i] = up.put(CT.data(), CT.size());
-      }
+  for (size_t i = 0; i < prog.diags.size(); ++i) {
+    const DiagSpec& d = prog.diags[i];
+    TableBuild tb{};
+    if (d.lin_a) tb.spec.lin_a = up.put(d.lin_a, N);
+    if (d.lin_b) tb.spec.lin_b = up.put(d.lin_b, N);
+    if (d.Qa) tb.spec.Qa = up.put(d.Qa, (size_t)N * N);
+    if (d.Qb) tb.spec.Qb = up.put(d.Qb, (size_t)N * N);
+    tb.A = arena + i * (size_t)(da + db);
+    tb.B = tb.A + da;
+    c.tables.push_back(tb);
+    if (d.C) {
+      std::vector<double> CT((size_t)N * N);
+      for (int p = 0; p < N; ++p)
+        for (int q = 0; q < N; ++q) CT[q * N + p] = d.C[p * N + q];
+      Cd[i] = up.put(d.C, (size_t)N * N);
+      CTd[i] = up.put(CT.data(), CT.size());
     }
   }
 
@@ -107,24 +110,53 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
   auto colspin = [&]() { return layout == 0 ? 1 : 0; };
   auto rowspin = [&]() { return layout == 0 ? 0 : 1; };
 
-  auto fold = [&](dev::StageDev& st) {
-    // deferred phase layers of the row spin and of the column spin
+  // A phase stage: the column-only factor goes into a per-stage table built on
+  // the device; deferred orbital phase layers of the row spin go into drow /
+  // sign_row and those of the column spin into the column table.
+  auto phase_stage = [&](int diag, double scale) {
+    dev::StageDev st{};
+    st.type = dev::ST_PHASE;
+    st.scale = scale;
+    const int cs = colspin();
+    ColfBuild cb{};
+    cb.spin = cs;
+    cb.scale = scale;
+    if (diag >= 0) {
+      const TableBuild& tb = c.tables[diag];
+      st.A = layout == 0 ? tb.A : tb.B;
+      st.C = layout == 0 ? Cd[diag] : CTd[diag];
+      cb.B = layout == 0 ? tb.B : tb.A;
+    }
     for (int role = 0; role < 2; ++role) {
-      const int sp = role == 0 ? rowspin() : colspin();
+      const int sp = role == 0 ? rowspin() : cs;
       Pending& pd = pend[sp];
       if (!pd.has) continue;
-      if (pd.sign_only) {
-        (role == 0 ? st.sign_row : st.sign_col) ^= pd.sign;
+      if (role == 0) {
+        if (pd.sign_only)
+          st.sign_row ^= pd.sign;
+        else
+          st.drow = up.put(pd.delta.data(), pd.delta.size());
       } else {
-        (role == 0 ? st.drow : st.dcol) = up.put(pd.delta.data(), pd.delta.size());
+        if (pd.sign_only)
+          cb.sign ^= pd.sign;
+        else
+          cb.delta = up.put(pd.delta.data(), pd.delta.size());
       }
       pd = Pending{};
     }
+    if (cb.B || cb.delta || cb.sign) {
+      const size_t n = (size_t)P.dim[cs];
+      if (arena_off + 2 * n > P.arena_doubles) throw Error(FFX_EUNSUPPORTED, "diagonal table arena exhausted");
+      cb.out = arena + arena_off;
+      arena_off += 2 * n;
+      c.colfs.push_back(cb);
+      st.colf = cb.out;
+    }
+    return st;
   };
-  auto diag_stage = [&](int type, int diag, double scale) {
+  auto diag_stage = [&](int type, int diag) {
     dev::StageDev st{};
     st.type = type;
-    st.scale = scale;
     if (diag >= 0) {
       const TableBuild& tb = c.tables[diag];
       st.A = layout == 0 ? tb.A : tb.B;
@@ -138,8 +170,7 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
     if (pend[sp].has) {  // an earlier phase layer of this spin must land first
       Item it;
       it.kind = 1;
-      it.st = diag_stage(dev::ST_PHASE, -1, 0.0);
-      fold(it.st);
+      it.st = phase_stage(-1, 0.0);
       visit.push_back(it);
     }
     Item it;
@@ -284,12 +315,11 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
     Item it;
     it.kind = 1;
     if (op.kind == ProgOp::PHASE) {
-      it.st = diag_stage(dev::ST_PHASE, op.diag, op.scale);
-      fold(it.st);
+      it.st = phase_stage(op.diag, op.scale);
     } else if (op.kind == ProgOp::SCALE) {
-      it.st = diag_stage(dev::ST_SCALE, op.diag, 0.0);
+      it.st = diag_stage(dev::ST_SCALE, op.diag);
     } else {
-      it.st = diag_stage(dev::ST_REDUCE, op.diag, 0.0);
+      it.st = diag_stage(dev::ST_REDUCE, op.diag);
     }
     visit.push_back(it);
     if (op.kind == ProgOp::REDUCE) {
@@ -302,8 +332,7 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
   if (final_mode != FINAL_NONE && (pend[0].has || pend[1].has)) {
     Item it;
     it.kind = 1;
-    it.st = diag_stage(dev::ST_PHASE, -1, 0.0);
-    fold(it.st);
+    it.st = phase_stage(-1, 0.0);
     visit.push_back(it);
   }
   close_visit(false);
@@ -320,6 +349,10 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
   const int N = P.norb;
   for (const TableBuild& tb : c.tables) {
     dev::diag_tables(P.d_masks[0], da, P.d_masks[1], db, N, tb.spec, tb.A, tb.B, nullptr, s);
+    check_launch();
+  }
+  for (const ColfBuild& cb : c.colfs) {
+    dev::column_factors(P.d_masks[cb.spin], P.dim[cb.spin], cb.B, cb.scale, cb.delta, cb.sign, cb.out, s);
     check_launch();
   }
   int last_seg = -1;
@@ -363,6 +396,7 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
       p.stages = L.stages;
       p.partials = L.reduce ? P.partials : nullptr;
       p.lds_row_bytes = (int)(((size_t)ss.max_len * P.elem() + 15) & ~(size_t)15);
+      p.max_mt = ss.max_mt;
       if (i == last_seg && c.final_mode == FINAL_ACCUM) {
         p.mode = dev::SEG_ACCUM;
         p.dst = accum;

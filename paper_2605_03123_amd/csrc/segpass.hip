@@ -21,6 +21,7 @@
 // reduction).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <utility>
 
 #include "dev_common.h"
@@ -29,39 +30,77 @@
 namespace ffx {
 namespace dev {
 
+// member offsets come four at a time from 16-byte-aligned LDS tables
+template <int K>
+__device__ __forceinline__ int pick(const int4& q) {
+  if constexpr ((K & 3) == 0) return q.x;
+  if constexpr ((K & 3) == 1) return q.y;
+  if constexpr ((K & 3) == 2) return q.z;
+  return q.w;
+}
+
 template <int W, int M, bool REAL, class R, int... K>
-__device__ __forceinline__ void lds_class(typename V2T<R>::type* __restrict__ row, const int* __restrict__ t,
-                                          const RotDev* __restrict__ rots, int nrot,
+__device__ __forceinline__ void lds_class(typename V2T<R>::type* __restrict__ row, int cbase, const int* mtl,
+                                          int moff, const RotDev* __restrict__ rots, int nrot,
                                           std::integer_sequence<int, K...>) {
   using V = typename V2T<R>::type;
-  V v[sizeof...(K)];
-  ((v[K] = row[t[K * 64]]), ...);
+  constexpr int C = sizeof...(K);
+  constexpr int Q = (C + 3) / 4;
+  V v[C];
+  {
+    int4 q[Q];
+    const int4* m4 = (const int4*)(mtl + moff);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) q[i] = m4[i];
+    ((v[K] = row[cbase + pick<K>(q[K >> 2])]), ...);
+  }
   apply_rots<W, M, REAL, R>(v, rots, nrot);
-  const volatile int* tv = t;
-  ((row[tv[K * 64]] = v[K]), ...);
+  // member offsets are re-read from LDS rather than held in registers across
+  // the rotations: hiding the table offset from the optimizer forces the reload
+  {
+    int o = moff;
+    asm volatile("" : "+v"(o));
+    int4 q[Q];
+    const int4* m4 = (const int4*)(mtl + o);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) q[i] = m4[i];
+    ((row[cbase + pick<K>(q[K >> 2])] = v[K]), ...);
+  }
 }
 
 template <int W, bool REAL, class R, int M = 1>
-__device__ __forceinline__ void lds_m(int m, typename V2T<R>::type* row, const int* t, const RotDev* rots,
-                                      int nrot) {
+__device__ __forceinline__ void lds_m(int m, typename V2T<R>::type* row, int cbase, const int* mtl, int moff,
+                                      const RotDev* rots, int nrot) {
   if constexpr (M < W) {
     if (m == M)
-      lds_class<W, M, REAL, R>(row, t, rots, nrot, std::make_integer_sequence<int, cbinom(W, M)>{});
+      lds_class<W, M, REAL, R>(row, cbase, mtl, moff, rots, nrot, std::make_integer_sequence<int, cbinom(W, M)>{});
     else
-      lds_m<W, REAL, R, M + 1>(m, row, t, rots, nrot);
+      lds_m<W, REAL, R, M + 1>(m, row, cbase, mtl, moff, rots, nrot);
   }
 }
 
 __device__ __forceinline__ int parity(uint32_t x) { return __builtin_popcount(x) & 1; }
 
+__device__ __forceinline__ zc128 zmul(zc128 a, zc128 b) {
+  return zc128{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// complex128 classes need twice the registers: 8 waves per block instead of 12
+template <class R>
+constexpr int seg_threads() {
+  return sizeof(R) == 8 ? 512 : 768;
+}
+
 template <int W, bool REAL, class R>
-__global__ __launch_bounds__(768) void k_seg_pass(SegPassDev P) {
+__global__ __launch_bounds__(seg_threads<R>()) void k_seg_pass(SegPassDev P) {
   using V = typename V2T<R>::type;
   extern __shared__ __align__(16) char smem[];
   V* row = (V*)smem;
-  double* tab = (double*)(smem + P.lds_row_bytes);  // 4 x 256 byte tables
-  double* wq = tab + 4 * 256;                       // 32 cross weights
-  double* red = wq + 32;                            // block reduction scratch
+  zc128* ez = (zc128*)(smem + P.lds_row_bytes);      // 4 x 256 complex byte factors
+  double* tab = (double*)ez;                          // (or 4 x 256 real byte sums)
+  int* mtl = (int*)(ez + 4 * 256);                    // member offsets of one window
+  double* wq = (double*)(mtl + ((P.max_mt + 3) & ~3)); // 32 cross weights
+  double* red = wq + 32;                               // block reduction scratch
 
   const int64_t blk = blockIdx.x;
   const int si = (int)(blk % P.n_seg);
@@ -75,6 +114,7 @@ __global__ __launch_bounds__(768) void k_seg_pass(SegPassDev P) {
 
   const V* src = (const V*)P.src + r * P.row_len + sg.off;
   for (int e = tid; e < sg.len; e += nthr) row[e] = src[e];
+  for (int i = tid; i < sg.n_mt_all; i += nthr) mtl[i] = sg.mt_all[i];
   __syncthreads();
 
   const uint32_t rmask = P.row_masks[r];
@@ -85,56 +125,70 @@ __global__ __launch_bounds__(768) void k_seg_pass(SegPassDev P) {
   for (int s = 0; s < P.n_stages; ++s) {
     const StageDev st = P.stages[s];
     if (st.type == ST_GIVENS) {
-      const WinDev wt = sg.win[st.a];
+      const SegWinDev wt = sg.win[st.a];
+      const int* mw = mtl + wt.mt_off;
       for (int ch = wave; ch < wt.n_chunks; ch += nwaves) {
         const int m = wt.chunk_m[ch];
-        if (m == 0 || m == W) continue;
-        const int* t = wt.tab + wt.chunk_off[ch] + lane;
-        if (t[0] >= 0) lds_m<W, REAL, R>(m, row, t, st.rots, st.nrot);
+        const int code = wt.code[ch * 64 + lane];
+        if (code >= 0)
+          lds_m<W, REAL, R>(m, row, code >> 5, mtl, wt.mt_off + mw[m * wt.nl1 + (code & 31)], st.rots, st.nrot);
       }
     } else {
       // cross weights w[q] = sum_{p in row} C[p][q]
-      const double coef = (st.type == ST_PHASE) ? st.scale : 1.0;
       if (tid < P.norb) {
         double w = 0.0;
         if (st.C)
           for (int p = 0; p < P.norb; ++p)
             if ((rmask >> p) & 1) w += st.C[p * P.norb + tid];
-        w *= coef;
-        if (st.type == ST_PHASE && st.dcol) w += st.dcol[tid];
         wq[tid] = w;
       }
       __syncthreads();
-      for (int i = tid; i < nbytes * 256; i += nthr) {
-        const int k = i >> 8, b = i & 255;
-        double v = 0.0;
-        for (int q = 0; q < 8; ++q)
-          if (((b >> q) & 1) && 8 * k + q < P.norb) v += wq[8 * k + q];
-        tab[i] = v;
+      const bool cross = st.C != nullptr;
+      if (cross) {
+        for (int i = tid; i < nbytes * 256; i += nthr) {
+          const int k = i >> 8, b = i & 255;
+          double v = 0.0;
+          for (int q = 0; q < 8; ++q)
+            if (((b >> q) & 1) && 8 * k + q < P.norb) v += wq[8 * k + q];
+          if (st.type == ST_PHASE)
+            ez[i] = phase_factor<double>(st.scale * v);
+          else
+            tab[i] = v;
+        }
       }
       __syncthreads();
-      double arow = st.A ? st.A[r] : 0.0;
-      double grow = 0.0;
-      if (st.type == ST_PHASE && st.drow)
-        for (int p = 0; p < P.norb; ++p)
-          if ((rmask >> p) & 1) grow += st.drow[p];
-      const int srow = parity(rmask & st.sign_row);
-      for (int e = tid; e < sg.len; e += nthr) {
-        const uint32_t cm = cmask[e];
-        double x = 0.0;
-        for (int k = 0; k < nbytes; ++k) x += tab[(k << 8) | ((cm >> (8 * k)) & 255)];
-        const double bcol = st.B ? st.B[sg.off + e] : 0.0;
-        V y = row[e];
-        if (st.type == ST_PHASE) {
-          const double ang = st.scale * (arow + bcol) + x + grow;
-          V ph = phase_factor<R>(ang);
-          if (srow ^ parity(cm & st.sign_col)) {
-            ph.x = -ph.x;
-            ph.y = -ph.y;
+      const double arow = st.A ? st.A[r] : 0.0;
+      if (st.type == ST_PHASE) {
+        double grow = 0.0;
+        if (st.drow)
+          for (int p = 0; p < P.norb; ++p)
+            if ((rmask >> p) & 1) grow += st.drow[p];
+        zc128 rowf = phase_factor<double>(st.scale * arow + grow);
+        if (parity(rmask & st.sign_row)) {
+          rowf.x = -rowf.x;
+          rowf.y = -rowf.y;
+        }
+        const zc128* colf = st.colf ? (const zc128*)st.colf + sg.off : nullptr;
+        for (int e = tid; e < sg.len; e += nthr) {
+          zc128 f = colf ? zmul(rowf, colf[e]) : rowf;
+          if (cross) {
+            const uint32_t cm = cmask[e];
+            for (int k = 0; k < nbytes; ++k) f = zmul(f, ez[(k << 8) | ((cm >> (8 * k)) & 255)]);
           }
-          row[e] = cmul<V, R>(y, ph);
-        } else {
-          const double f = arow + bcol + x;
+          V y = row[e];
+          V o;
+          o.x = (R)((double)y.x * f.x - (double)y.y * f.y);
+          o.y = (R)((double)y.x * f.y + (double)y.y * f.x);
+          row[e] = o;
+        }
+      } else {
+        for (int e = tid; e < sg.len; e += nthr) {
+          double f = arow + (st.B ? st.B[sg.off + e] : 0.0);
+          if (cross) {
+            const uint32_t cm = cmask[e];
+            for (int k = 0; k < nbytes; ++k) f += tab[(k << 8) | ((cm >> (8 * k)) & 255)];
+          }
+          V y = row[e];
           if (st.type == ST_SCALE) {
             y.x = (R)(f * (double)y.x);
             y.y = (R)(f * (double)y.y);
@@ -162,7 +216,7 @@ __global__ __launch_bounds__(768) void k_seg_pass(SegPassDev P) {
     }
   }
   if (P.partials) {
-    // fixed-order block reduction: wave sums, then wave 0 adds them in order
+    // fixed-order block reduction: wave sums, then thread 0 adds them in order
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if (lane == 0) red[wave] = acc;
     __syncthreads();
@@ -174,10 +228,38 @@ __global__ __launch_bounds__(768) void k_seg_pass(SegPassDev P) {
   }
 }
 
-size_t seg_pass_lds(bool c64, int max_len) {
+__global__ void k_column_factors(const uint32_t* __restrict__ masks, int64_t n, const double* __restrict__ B,
+                                 double scale, const double* __restrict__ delta, uint32_t sign,
+                                 zc128* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t m = masks[i];
+  double ang = B ? scale * B[i] : 0.0;
+  if (delta) {
+    uint32_t x = m;
+    while (x) {
+      ang += delta[__builtin_ctz(x)];
+      x &= x - 1;
+    }
+  }
+  zc128 f = phase_factor<double>(ang);
+  if (parity(m & sign)) {
+    f.x = -f.x;
+    f.y = -f.y;
+  }
+  out[i] = f;
+}
+
+void column_factors(const uint32_t* masks, int64_t n, const double* B, double scale, const double* delta,
+                    uint32_t sign, double* colf, hipStream_t s) {
+  hipLaunchKernelGGL(k_column_factors, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, masks, n, B, scale,
+                     delta, sign, (zc128*)colf);
+}
+
+size_t seg_pass_lds(bool c64, int max_len, int max_mt) {
   size_t row = (size_t)max_len * (c64 ? 8 : 16);
   row = (row + 15) & ~(size_t)15;
-  return row + (4 * 256 + 32 + 16) * sizeof(double);
+  return row + 4 * 256 * sizeof(zc128) + (size_t)((max_mt + 3) & ~3) * sizeof(int) + (32 + 16) * sizeof(double);
 }
 
 template <int W, bool REAL, class R>
@@ -189,7 +271,7 @@ static void launch_seg(const SegPassDev& p, int threads, size_t lds, hipStream_t
     attr_set = true;
   }
   const int64_t blocks = p.n_rows * p.n_seg;
-  hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(threads), lds, s, p);
+  hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(std::min(threads, seg_threads<R>())), lds, s, p);
 }
 
 template <bool REAL, class R>

@@ -108,25 +108,37 @@ __device__ __forceinline__ V cmul(V a, V b) {
   return r;
 }
 
+// d <- a * d + b, written into d's own register: with the result tied to
+// the input, the member registers never move across the rotation loop
+__device__ __forceinline__ void fma_ip(float& d, float a, float b) {
+  asm("v_fma_f32 %0, %1, %0, %2" : "+v"(d) : "v"(a), "v"(b));
+}
+__device__ __forceinline__ void fma_ip(double& d, double a, double b) {
+  asm("v_fma_f64 %0, %1, %0, %2" : "+v"(d) : "v"(a), "v"(b));
+}
+
 // x' = c x + s y, y' = -conj(s) x + c y on one member pair (A, B)
 template <int A, int B, bool REAL, class R>
 __device__ __forceinline__ void rot_pair(typename V2T<R>::type* v, R c, R sr, R si) {
   using V = typename V2T<R>::type;
-  V x = v[A], y = v[B];
-  V nx, ny;
+  V& x = v[A];
+  V& y = v[B];
+  R tx, ty, ux, uy;
   if constexpr (REAL) {
-    nx.x = c * x.x + sr * y.x;
-    nx.y = c * x.y + sr * y.y;
-    ny.x = c * y.x - sr * x.x;
-    ny.y = c * y.y - sr * x.y;
+    tx = sr * y.x;
+    ty = sr * y.y;
+    ux = -sr * x.x;
+    uy = -sr * x.y;
   } else {
-    nx.x = c * x.x + sr * y.x - si * y.y;
-    nx.y = c * x.y + sr * y.y + si * y.x;
-    ny.x = c * y.x - sr * x.x - si * x.y;
-    ny.y = c * y.y - sr * x.y + si * x.x;
+    tx = sr * y.x - si * y.y;
+    ty = sr * y.y + si * y.x;
+    ux = -sr * x.x - si * x.y;
+    uy = si * x.x - sr * x.y;
   }
-  v[A] = nx;
-  v[B] = ny;
+  fma_ip(x.x, c, tx);
+  fma_ip(x.y, c, ty);
+  fma_ip(y.x, c, ux);
+  fma_ip(y.y, c, uy);
 }
 
 // every member pair of rotation P, expanded at compile time so that the
@@ -143,24 +155,13 @@ __device__ __forceinline__ void rot_one(typename V2T<R>::type* v, R c, R sr, R s
   rot_pairs<W, M, P, REAL, R>(v, c, sr, si, std::make_integer_sequence<int, Pairs<W, M, P>::NP>{});
 }
 
-template <int W, int M, int P, bool REAL, class R>
-__device__ __forceinline__ void rot_case(typename V2T<R>::type* v, R c, R sr, R si) {
-  if constexpr (P < W - 1) rot_one<W, M, P, REAL, R>(v, c, sr, si);
-}
-
-// one uniform jump per rotation (a dense switch lowers to a jump table)
-template <int W, int M, bool REAL, class R>
+template <int W, int M, bool REAL, class R, int P = 0>
 __device__ __forceinline__ void rot_dispatch(int p, typename V2T<R>::type* v, R c, R sr, R si) {
-  static_assert(W <= 8, "window wider than the dispatch table");
-  switch (p) {
-    case 0: rot_case<W, M, 0, REAL, R>(v, c, sr, si); break;
-    case 1: rot_case<W, M, 1, REAL, R>(v, c, sr, si); break;
-    case 2: rot_case<W, M, 2, REAL, R>(v, c, sr, si); break;
-    case 3: rot_case<W, M, 3, REAL, R>(v, c, sr, si); break;
-    case 4: rot_case<W, M, 4, REAL, R>(v, c, sr, si); break;
-    case 5: rot_case<W, M, 5, REAL, R>(v, c, sr, si); break;
-    case 6: rot_case<W, M, 6, REAL, R>(v, c, sr, si); break;
-    default: break;
+  if constexpr (P < W - 1) {
+    if (p == P)
+      rot_one<W, M, P, REAL, R>(v, c, sr, si);
+    else
+      rot_dispatch<W, M, REAL, R, P + 1>(p, v, c, sr, si);
   }
 }
 
@@ -176,6 +177,67 @@ __device__ __forceinline__ void apply_rots(typename V2T<R>::type* v, const RotDe
     rot_dispatch<W, M, REAL, R>(cur.p, v, (R)cur.c, (R)cur.sr, (R)cur.si);
     cur = nxt;
   }
+}
+
+// The rotations of one stage spread over the lanes of a wave (lane i holds
+// rotation i, at most 64); the rotation loop broadcasts rotation r with
+// v_readlane, so its parameters are scalars, the window position selects a
+// scalar branch, and no memory access sits inside the loop.
+template <class R>
+struct RotLane {
+  int p;
+  R c, sr, si;
+};
+
+__device__ __forceinline__ int lane_bcast(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float lane_bcast(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Must be called with every lane of the wave active.
+template <class R>
+__device__ __forceinline__ RotLane<R> load_rot_lane(const RotDev* rots, int nrot, int lane) {
+  RotLane<R> x{0, R(1), R(0), R(0)};
+  if (lane < nrot) {
+    const RotDev g = rots[lane];
+    x.p = g.p;
+    x.c = (R)g.c;
+    x.sr = (R)g.sr;
+    x.si = (R)g.si;
+  }
+  // materialize the values here, where every lane is active, so that the
+  // loads are not moved into a lane-divergent branch
+  asm volatile("" : "+v"(x.p), "+v"(x.c), "+v"(x.sr), "+v"(x.si));
+  return x;
+}
+
+template <int W, int M, bool REAL, class R>
+__device__ __forceinline__ void apply_rots_lane(typename V2T<R>::type* v, const RotLane<R>& rl, int nrot) {
+  for (int r = 0; r < nrot; ++r) {
+    int p = lane_bcast(rl.p, r);
+    asm volatile("" : "+v"(p));
+    rot_dispatch<W, M, REAL, R>(p, v, lane_bcast(rl.c, r), lane_bcast(rl.sr, r),
+                                REAL ? R(0) : lane_bcast(rl.si, r));
+  }
+}
+
+// Loads a small struct of uniform data as scalars (every 32-bit word through
+// readfirstlane), so that branches on its fields are scalar branches.
+template <class T>
+__device__ __forceinline__ T uniform_load(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "uniform_load needs whole 32-bit words");
+  T out;
+  const int* src = (const int*)p;
+  int* dst = (int*)&out;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  return out;
 }
 
 template <class R>

@@ -111,6 +111,8 @@ void diag_grad_combine(const double* rowout, int64_t dim_a, const uint32_t* mask
 // segment passes: one block owns one contiguous segment of one row of the
 // (possibly transposed) state in LDS and applies a list of stages to it.
 // ---------------------------------------------------------------------------
+constexpr int kMaxStageRots = 64;  // rotations per Givens stage of a segment pass (one per lane)
+
 enum StageType { ST_GIVENS = 0, ST_PHASE = 1, ST_SCALE = 2, ST_REDUCE = 3 };
 
 // f(row, col) = A[row] + B[col] + sum_{p in row, q in col} C[p * norb + q]

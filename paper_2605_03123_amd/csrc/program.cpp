@@ -237,6 +237,9 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
             }
           }
           if (best.empty()) break;
+          // a stage's rotations are spread over the 64 lanes of a wave; the
+          // taken list is in dependency order, so any prefix is a valid stage
+          if (best.size() > (size_t)dev::kMaxStageRots) best.resize(dev::kMaxStageRots);
           std::vector<dev::RotDev> buf;
           for (int i : best) {
             const Givens& g = d.rots[i];

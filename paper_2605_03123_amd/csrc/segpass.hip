@@ -41,7 +41,7 @@ __device__ __forceinline__ int pick(const int4& q) {
 
 template <int W, int M, bool REAL, class R, int... K>
 __device__ __forceinline__ void lds_class(typename V2T<R>::type* __restrict__ row, int cbase, const int* mtl,
-                                          int moff, const RotDev* __restrict__ rots, int nrot,
+                                          int moff, const RotLane<R>& rl, int nrot,
                                           std::integer_sequence<int, K...>) {
   using V = typename V2T<R>::type;
   constexpr int C = sizeof...(K);
@@ -54,7 +54,7 @@ __device__ __forceinline__ void lds_class(typename V2T<R>::type* __restrict__ ro
     for (int i = 0; i < Q; ++i) q[i] = m4[i];
     ((v[K] = row[cbase + pick<K>(q[K >> 2])]), ...);
   }
-  apply_rots<W, M, REAL, R>(v, rots, nrot);
+  apply_rots_lane<W, M, REAL, R>(v, rl, nrot);
   // member offsets are re-read from LDS rather than held in registers across
   // the rotations: hiding the table offset from the optimizer forces the reload
   {
@@ -70,12 +70,12 @@ __device__ __forceinline__ void lds_class(typename V2T<R>::type* __restrict__ ro
 
 template <int W, bool REAL, class R, int M = 1>
 __device__ __forceinline__ void lds_m(int m, typename V2T<R>::type* row, int cbase, const int* mtl, int moff,
-                                      const RotDev* rots, int nrot) {
+                                      const RotLane<R>& rl, int nrot) {
   if constexpr (M < W) {
     if (m == M)
-      lds_class<W, M, REAL, R>(row, cbase, mtl, moff, rots, nrot, std::make_integer_sequence<int, cbinom(W, M)>{});
+      lds_class<W, M, REAL, R>(row, cbase, mtl, moff, rl, nrot, std::make_integer_sequence<int, cbinom(W, M)>{});
     else
-      lds_m<W, REAL, R, M + 1>(m, row, cbase, mtl, moff, rots, nrot);
+      lds_m<W, REAL, R, M + 1>(m, row, cbase, mtl, moff, rl, nrot);
   }
 }
 
@@ -85,10 +85,11 @@ __device__ __forceinline__ zc128 zmul(zc128 a, zc128 b) {
   return zc128{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 
-// complex128 classes need twice the registers: 8 waves per block instead of 12
+// 12 waves per block (3 per SIMD): the widest register windows (W = 7 at
+// complex64, W = 6 at complex128) fit in the 168 registers this leaves a lane
 template <class R>
 constexpr int seg_threads() {
-  return sizeof(R) == 8 ? 512 : 768;
+  return 768;
 }
 
 template <int W, bool REAL, class R>
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(seg_threads<R>()) void k_seg_pass(SegPassDev P) {
   const int64_t blk = blockIdx.x;
   const int si = (int)(blk % P.n_seg);
   const int64_t r = blk / P.n_seg;
-  const SegDev sg = P.segs[si];
+  const SegDev sg = uniform_load(P.segs + si);
   const int nthr = blockDim.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -123,15 +124,16 @@ __global__ __launch_bounds__(seg_threads<R>()) void k_seg_pass(SegPassDev P) {
   double acc = 0.0;
 
   for (int s = 0; s < P.n_stages; ++s) {
-    const StageDev st = P.stages[s];
+    const StageDev st = uniform_load(P.stages + s);
     if (st.type == ST_GIVENS) {
-      const SegWinDev wt = sg.win[st.a];
+      const SegWinDev wt = uniform_load(sg.win + st.a);
       const int* mw = mtl + wt.mt_off;
+      const RotLane<R> rl = load_rot_lane<R>(st.rots, st.nrot, lane);
       for (int ch = wave; ch < wt.n_chunks; ch += nwaves) {
-        const int m = wt.chunk_m[ch];
+        const int m = __builtin_amdgcn_readfirstlane(wt.chunk_m[ch]);
         const int code = wt.code[ch * 64 + lane];
         if (code >= 0)
-          lds_m<W, REAL, R>(m, row, code >> 5, mtl, wt.mt_off + mw[m * wt.nl1 + (code & 31)], st.rots, st.nrot);
+          lds_m<W, REAL, R>(m, row, code >> 5, mtl, wt.mt_off + mw[m * wt.nl1 + (code & 31)], rl, st.nrot);
       }
     } else {
       // cross weights w[q] = sum_{p in row} C[p][q]

@@ -1,21 +1,36 @@
 """Benchmark: seconds per double-factorized Trotter step at norb = 16, (8, 8).
 
-    python bench.py [--steps K] [--warmup W] [--dtype c128|c64] [--no-cpu-baseline] [--lucj]
+    python bench.py [--steps K] [--warmup W] [--dtype c128|c64] [--no-cpu-baseline] [--no-lucj]
+                    [--copy-calibration]
 
 Workload: one first-order (S_0) Trotter step, dt = 0.1, of a DF Hamiltonian
 with L = 16 terms (h ~ sym N(0, 0.5); U_t real orthogonal from QR; J_t ~ sym
 N(0, 0.1)) on a random normalized 12870 x 12870 state, seed 0.  The state is
 resident in HBM before timing; W untimed steps, then K timed steps bracketed by
-device synchronization, timed with HIP events on the working stream.
+device synchronization, timed with HIP events on the working stream.  `value`
+is the time per step in the primary precision (--dtype, complex128 by
+default); the other precision is timed the same way and reported beside it.
+
+Also reported (unless --no-lucj): the LUCJ energy + adjoint gradient at
+norb = 16, n_reps = 3, L = 16 in both precisions, and against it the
+forward-only central finite-difference gradient (h = 1e-5) on 20 parameters
+in complex128: its time, the extrapolated time for all parameters, and the
+largest difference to the adjoint gradient.
 
 Prints ONE JSON line with the metric, a roofline object for the dominant
-kernel family (the Givens window passes; per-launch durations measured live
-with HIP events on the launch stream) and the oracle timed on a bounded sample
-of the same step.
+kernel (the segment pass; per-launch durations measured live with HIP events
+on the launch stream) and the oracle timed on a bounded sample of the same
+step.  The roofline's `traffic` is the HBM byte count per launch from the
+committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes, used only while the
+kernel sources still hash to the value recorded with them (else null).
+
+--copy-calibration adds device copies of a known size (for scaling the
+FETCH_SIZE / WRITE_SIZE counters under rocprofv3) and skips the rest.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,6 +44,33 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 NORB, NELEC, L, DT = 16, (8, 8), 16, 0.1
+LUCJ_REPS, FD_H = 3, 1e-5
+KERNEL_SOURCES = ("segpass.hip", "dev_common.h", "device.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_seg_pass_df_trotter_n16.txt")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2605_03123_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(dtype_name: str):
+    """HBM bytes per segment-pass launch from the committed counter passes, if still valid."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    key = f"bytes_per_launch_{dtype_name}"
+    if kv.get("kernel_sources_sha256") != kernel_source_hash() or key not in kv:
+        return None
+    return float(kv[key])
 
 
 def cpu_baseline(ham, vec: np.ndarray) -> dict:
@@ -52,7 +94,7 @@ def cpu_baseline(ham, vec: np.ndarray) -> dict:
     d = ost.dim(NORB, NELEC[0])
     U = np.asarray(ham.U[0]).conj().T
     ost.occupied_lists(NORB, NELEC[0])
-    R_c, R_g = 128, 512
+    R_c, R_g = 384, 768
     t0 = time.perf_counter()
     rows = np.array([sampled.compound_row(U, NELEC[0], i) for i in range(R_c)])
     t_c = time.perf_counter() - t0
@@ -76,26 +118,7 @@ def cpu_baseline(ham, vec: np.ndarray) -> dict:
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--dtype", choices=["c128", "c64"], default="c128")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--lucj", action="store_true", help="also time LUCJ energy + adjoint gradient (n_reps=3)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the state of this workload fits one MI355X and the build has no "
-              "multi-GPU path; run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    from paper_2605_03123_amd import ffx, synth
-
-    dtype = torch.complex128 if args.dtype == "c128" else torch.complex64
-    w = synth.workload_df_trotter(NORB, L, seed=0, start="random", dt=DT)
-    ham, vec_np = w.data["ham"], w.data["vec"]
+def time_df_step(ffx, torch, ham, vec_np, dtype, steps, warmup):
     dev = torch.device("cuda:0")
     vec = torch.from_numpy(vec_np).to(dtype).to(dev)
     plan = ffx.get_plan(NORB, NELEC, dtype, 0)
@@ -104,21 +127,21 @@ def main():
     def step():
         ffx.simulate_trotter_double_factorized(vec, ham, DT, NORB, NELEC, n_steps=1, order=0, out=vec)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t_wall = time.perf_counter()
     e0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     e1.record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
-    ms = e0.elapsed_time(e1) / args.steps
+    ms = e0.elapsed_time(e1) / steps
     norm = float(torch.linalg.vector_norm(vec.to(torch.complex128)))
 
-    # live per-launch timing of the dominant kernels over one more step
+    # live per-launch timing of the kernel families over one more step
     plan.timing(True)
     step()
     torch.cuda.synchronize()
@@ -130,34 +153,121 @@ def main():
                 fam[f"{kname}_{sname}"] = {"launches": n, "total_ms": kms, "avg_ms": kms / n,
                                            "alg_bytes": alg, "valu_slots": slots}
     plan.timing(False)
-    dom = max(fam, key=lambda k: fam[k]["total_ms"])
-    f = fam[dom]
-    sec = f["avg_ms"] * 1e-3
-    # ALU roofline: algorithmic VALU slots (8 per rotated pair for real rotations, 12 for complex)
-    # as FMA-equivalent flops against the vector peak of the arithmetic type
-    alu_peak = 78.6 if dtype == torch.complex128 else 157.3
-    alu = 2.0 * f["valu_slots"] / f["launches"] / sec / 1e12
-    # HBM roofline: a segment pass reads and writes the whole state once
-    hbm_bytes = 2.0 * plan.state_bytes if dom.startswith("seg") else f["alg_bytes"] / f["launches"]
+    del vec
+    return ms, t_wall, norm, fam, plan.state_bytes
+
+
+def roofline(fam, dtype_name, state_bytes):
+    """Roofline of the segment pass (both spins): the dominant kernel of the step."""
+    seg = [v for k, v in fam.items() if k.startswith("seg_pass")]
+    n = sum(v["launches"] for v in seg)
+    tot_ms = sum(v["total_ms"] for v in seg)
+    slots = sum(v["valu_slots"] for v in seg)
+    sec = tot_ms / n * 1e-3
+    # ALU: algorithmic VALU slots (8 per rotated amplitude pair for real rotations,
+    # 12 for complex) as FMA-equivalent flops against the vector peak of the type
+    alu_peak = 78.6 if dtype_name == "c128" else 157.3
+    alu = 2.0 * slots / n / sec / 1e12
+    # HBM: a segment pass reads and writes the whole state once
+    hbm_bytes = 2.0 * state_bytes
     hbm = hbm_bytes / sec / 1e9
     if alu / alu_peak >= hbm / HBM_PEAK_GBS:
-        roofline = {"bound": "alu", "achieved": round(alu, 3), "peak": alu_peak, "unit": "TFLOP/s",
-                    "frac": round(alu / alu_peak, 4)}
+        r = {"bound": "alu", "achieved": round(alu, 3), "peak": alu_peak, "unit": "TFLOP/s",
+             "frac": round(alu / alu_peak, 4)}
     else:
-        roofline = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(hbm / HBM_PEAK_GBS, 4)}
-    roofline.update({
-        "traffic": None,
-        "kernel": f"k_{dom.rsplit('_', 1)[0]} ({dom.rsplit('_', 1)[1]} rotations)",
-        "avg_launch_ms": round(f["avg_ms"], 4),
-        "launches_per_step": f["launches"],
-        "valu_slots_per_launch": f["valu_slots"] / f["launches"],
-        "hbm_bytes_per_launch": hbm_bytes,
+        r = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(hbm / HBM_PEAK_GBS, 4)}
+    tr = committed_traffic(dtype_name)
+    r.update({
+        "traffic": tr,
+        "kernel": "k_seg_pass (alpha and beta column spins)",
+        "avg_launch_ms": round(tot_ms / n, 4),
+        "launches_per_step": n,
+        "valu_slots_per_launch": slots / n,
+        "alg_hbm_bytes_per_launch": hbm_bytes,
         "hbm_GBps": round(hbm, 1),
         "alu_TFLOPs": round(alu, 3),
+        "kernel_sources_sha256": kernel_source_hash(),
         "families": fam,
     })
+    return r
 
+
+def lucj_timing(ffx, torch, synth, dtype, with_fd):
+    wl = synth.workload_lucj(NORB, LUCJ_REPS, L, seed=0)
+    p, ham = wl.data["params"], wl.data["ham"]
+    ffx.lucj_energy_grad(p, ham, NORB, NELEC, LUCJ_REPS, dtype=dtype)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e, g = ffx.lucj_energy_grad(p, ham, NORB, NELEC, LUCJ_REPS, dtype=dtype)
+    t_adj = time.perf_counter() - t0
+    out = {"energy": e, "adjoint_s": t_adj, "n_params": int(g.size)}
+    if not with_fd:
+        return out
+    plan = ffx.get_plan(NORB, NELEC, dtype, 0)
+    psi = torch.empty((plan.dim_a, plan.dim_b), dtype=dtype, device="cuda:0")
+
+    def energy(q):
+        ffx.apply_lucj(q, NORB, NELEC, LUCJ_REPS, dtype=dtype, out=psi, plan=plan)
+        return ffx.df_energy(psi, ham, NORB, NELEC, plan=plan)
+
+    idx = synth.fd_indices(g.size, 20)
+    energy(p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fd = []
+    for i in idx:
+        qp, qm = p.copy(), p.copy()
+        qp[i] += FD_H
+        qm[i] -= FD_H
+        fd.append((energy(qp) - energy(qm)) / (2 * FD_H))
+    t_fd = time.perf_counter() - t0
+    out.update({"fd_params": len(idx), "fd_s": t_fd, "fd_all_params_s_extrapolated": t_fd / len(idx) * g.size,
+                "fd_h": FD_H, "max_abs_adjoint_minus_fd": float(np.max(np.abs(np.array(fd) - g[idx]))),
+                "adjoint_speedup_vs_fd_all": t_fd / len(idx) * g.size / t_adj})
+    return out
+
+
+def copy_calibration(torch):
+    """Plain device copies of a known size for scaling the HBM byte counters."""
+    n = 1 << 27  # 2^27 complex64 = 1 GiB
+    a = torch.zeros(n, dtype=torch.complex64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 8, "copy_calibration_bytes_written": n * 8,
+                      "copies": 3}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--dtype", choices=["c128", "c64"], default="c128")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-lucj", action="store_true")
+    ap.add_argument("--no-other-dtype", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the state of this workload fits one MI355X and the build has no "
+              "multi-GPU path; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2605_03123_amd import ffx, synth
+
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
+
+    types = {"c128": torch.complex128, "c64": torch.complex64}
+    w = synth.workload_df_trotter(NORB, L, seed=0, start="random", dt=DT)
+    ham, vec_np = w.data["ham"], w.data["vec"]
+    ms, t_wall, norm, fam, state_bytes = time_df_step(ffx, torch, ham, vec_np, types[args.dtype], args.steps,
+                                                       args.warmup)
     out = {
         "metric": "s per DF Trotter step (norb=16, nelec=(8,8), L=16, S_0, dt=0.1)",
         "value": ms / 1e3,
@@ -169,22 +279,25 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if dtype == torch.complex128 else "f32",
+        "dtype": "f64" if args.dtype == "c128" else "f32",
         "data": "synthetic (seeded random DF Hamiltonian and random normalized state)",
         "config": {"workload": f"df_trotter_step norb=16 nelec=(8,8) L=16 dt=0.1 order=0 "
-                               f"state={args.dtype} 12870x12870", "state_bytes": plan.state_bytes,
+                               f"state={args.dtype} 12870x12870", "state_bytes": state_bytes,
                    "wall_s_timed": round(t_wall, 3), "final_norm": norm},
-        "roofline": roofline,
+        "roofline": roofline(fam, args.dtype, state_bytes),
     }
-    if args.lucj:
-        wl = synth.workload_lucj(NORB, 3, L, seed=0)
-        p = wl.data["params"]
-        ffx.lucj_energy_grad(p, wl.data["ham"], NORB, NELEC, 3, dtype=dtype)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        e, g = ffx.lucj_energy_grad(p, wl.data["ham"], NORB, NELEC, 3, dtype=dtype)
-        out["lucj_energy_grad_s"] = time.perf_counter() - t0
-        out["lucj_energy"] = e
+    if not args.no_other_dtype:
+        other = "c64" if args.dtype == "c128" else "c128"
+        ms2, _, norm2, fam2, sb2 = time_df_step(ffx, torch, ham, vec_np, types[other], args.steps, args.warmup)
+        rf2 = roofline(fam2, other, sb2)
+        rf2.pop("families")
+        out[f"df_step_{other}"] = {"ms_per_step": ms2, "final_norm": norm2, "roofline": rf2}
+    if not args.no_lucj:
+        out["lucj_energy_grad"] = {
+            "workload": f"lucj norb=16 nelec=(8,8) n_reps={LUCJ_REPS} L={L} params~N(0,0.1)",
+            "c128": lucj_timing(ffx, torch, synth, torch.complex128, True),
+            "c64": lucj_timing(ffx, torch, synth, torch.complex64, False),
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ham, vec_np)
     print(json.dumps(out), flush=True)

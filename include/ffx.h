@@ -51,7 +51,7 @@ typedef struct ffx_plan_s* ffx_plan;
 /* Message for the last failure on this thread ("" if none). */
 const char* ffx_last_error(void);
 
-/* C(norb, n): the number of configurations of one spin (Sec. 2.5).
+/* C(norb, n): the number of configurations of one spin (Sec. 2.6).
    Returns -1 for norb outside [1, 32] or n outside [0, norb]. */
 int64_t ffx_dim(int norb, int n);
 
@@ -123,7 +123,7 @@ typedef struct {
 int ffx_apply_df_trotter_step(ffx_plan plan, void* vec, const ffx_df_ham* ham, double dt,
                               int n_steps, int order, void* stream);
 
-/* LUCJ ansatz (Sec. 4.3): vec is OVERWRITTEN with
+/* LUCJ ansatz (Sec. 4.5.1): vec is OVERWRITTEN with
    prod_{k = n_reps..1} [script-U(U_k) D_k script-U(U_k)^dag] |HF>.
    Per repetition the flat real parameter block is
    [Re A (norb^2), Im A (norb^2), j_same (norb - 1), j_opp (norb)],

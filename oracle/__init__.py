@@ -16,7 +16,7 @@ gates:
   hamiltonian.py  one-body action, double-factorized Hamiltonian action and
                   energy (Eq. double-factorized-hamiltonian, Sec. 4.2),
                   Trotter-Suzuki product formulas S_0, S_1, S_k (Sec. 4.5.3)
-  lucj.py         the LUCJ ansatz (Sec. 4.3), its energy, finite-difference and
+  lucj.py         the LUCJ ansatz (Sec. 4.5.1), its energy, finite-difference and
                   adjoint gradients
   sampled.py      single amplitudes of a rotated state at sizes where full
                   compound matrices are too large

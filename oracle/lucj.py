@@ -1,6 +1,6 @@
-"""Local unitary cluster Jastrow (LUCJ) ansatz, its energy and its gradient (Sec. 4.3).
+"""Local unitary cluster Jastrow (LUCJ) ansatz, its energy and its gradient (Sec. 4.5.1).
 
-One repetition is script-U D script-U^dag (Sec. 4.3): an orbital rotation, a
+One repetition is script-U D script-U^dag (Sec. 4.5.1): an orbital rotation, a
 diagonal Coulomb evolution, and the inverse rotation, applied to the
 Hartree-Fock state, with repetition 1 applied first:
 

@@ -21,7 +21,7 @@ import numpy as np
 
 
 def dim(norb: int, n: int) -> int:
-    """Number of n-electron configurations of one spin, C(N, n) (Sec. 2.5)."""
+    """Number of n-electron configurations of one spin, C(N, n) (Sec. 2.6)."""
     return comb(norb, n)
 
 

@@ -58,7 +58,7 @@ def test_orbital_rotation_homomorphism_and_adjoint():
 
 
 def test_slater_determinant_amplitudes():
-    """script-U(U)|HF> has amplitudes det U[J_a, occ] det U[J_b, occ] (Sec. 2.3.1)."""
+    """script-U(U)|HF> has amplitudes det U[J_a, occ] det U[J_b, occ] (Sec. 2.4)."""
     r = synth.rng(4)
     norb, nelec = 6, (2, 3)
     U = synth.random_unitary(r, norb)

@@ -96,6 +96,28 @@ def diag_coulomb_angle(norb: int, nelec, J_aa: np.ndarray, J_ab: np.ndarray | No
     return aa[:, None] + bb[None, :] + ab + ba
 
 
+def diag_coulomb_angle_at(norb: int, nelec, idx, J_aa: np.ndarray, J_ab: np.ndarray | None = None,
+                          J_bb: np.ndarray | None = None) -> np.ndarray:
+    """diag_coulomb_angle evaluated only at the (i_a, i_b) address pairs in idx.
+
+    The same multiset sum, x_a J^{aa} x_a + x_a J^{ab} x_b + x_b J^{ba} x_a
+    + x_b J^{bb} x_b, for states too large for the whole (dim_a, dim_b) table.
+    """
+    na, nb = nelec
+    if J_ab is None:
+        J_ab = J_aa
+    if J_bb is None:
+        J_bb = J_aa
+    idx = np.asarray(idx)
+    xa = st.occupations(norb, na)[idx[:, 0]]
+    xb = st.occupations(norb, nb)[idx[:, 1]]
+    aa = np.einsum("ip,pq,iq->i", xa, J_aa, xa)
+    bb = np.einsum("ip,pq,iq->i", xb, J_bb, xb)
+    ab = np.einsum("ip,pq,iq->i", xa, J_ab, xb)
+    ba = np.einsum("ip,pq,iq->i", xb, np.asarray(J_ab).T, xa)
+    return aa + bb + ab + ba
+
+
 def apply_diag_coulomb_evolution(vec: np.ndarray, J: np.ndarray, time: float, norb: int, nelec,
                                  J_ab: np.ndarray | None = None,
                                  J_bb: np.ndarray | None = None) -> np.ndarray:

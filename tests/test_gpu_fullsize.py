@@ -1,0 +1,175 @@
+"""GPU parity at the full benchmark sizes, in the launch configuration bench.py times.
+
+Whole oracle states do not fit these sizes, so the checks are:
+  * sampled amplitudes of one orbital rotation at norb = 16 (8, 8) and
+    norb = 18 (9, 9), each computed by the oracle one by one from compound
+    rows (complex128 <= 1e-12, complex64 <= 1e-5);
+  * a DF Trotter step whose rotations are the identity and whose one-body
+    term is diagonal: every amplitude is the start amplitude times a phase
+    the oracle evaluates pointwise (sampled, same tolerances);
+  * a full random DF step followed by its exact inverse built from the
+    single-gate entry points (reversibility over the whole state);
+  * two DF steps at norb = 14 (7, 7) from Hartree-Fock against stored oracle
+    amplitudes (tests/golden/df_trotter_n14.txt).
+States at norb >= 16 are drawn on the device from a seeded torch generator and
+copied to the host for the oracle: both sides read the same values.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import gates as og
+from oracle import sampled
+from oracle import strings as ost
+from paper_2605_03123_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.complex128: 1e-12, torch.complex64: 1e-5}
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "df_trotter_n14.txt")
+
+
+@pytest.fixture(scope="module")
+def ffx():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2605_03123_amd import ffx as mod
+    return mod
+
+
+def _device_state(d, dtype, seed):
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(seed)
+    real = torch.float64 if dtype == torch.complex128 else torch.float32
+    x = torch.complex(torch.randn((d, d), generator=g, device="cuda:0", dtype=real),
+                      torch.randn((d, d), generator=g, device="cuda:0", dtype=real))
+    nrm = torch.linalg.vector_norm(x.to(torch.complex128) if dtype == torch.complex128 else x).item()
+    return (x / nrm).to(dtype).contiguous()
+
+
+def _sample_idx(d, count, seed):
+    r = np.random.default_rng(seed)
+    return [(int(i), int(j)) for i, j in zip(r.integers(0, d, count), r.integers(0, d, count))]
+
+
+def _at(t, idx):
+    ii = torch.tensor([i for i, _ in idx], device=t.device)
+    jj = torch.tensor([j for _, j in idx], device=t.device)
+    return t[ii, jj].to(torch.complex128).cpu().numpy()
+
+
+def _inverse_step(ffx, vec, ham, dt, norb, nelec):
+    """Exact inverse of one S_0 step (one-body term first) from single-gate calls."""
+    for t in reversed(range(ham.U.shape[0])):
+        U = np.asarray(ham.U[t], dtype=complex)
+        ffx.apply_orbital_rotation(vec, U.conj().T, norb, nelec, out=vec)
+        ffx.apply_diag_coulomb_evolution(vec, ham.J[t], -dt, norb, nelec, out=vec)
+        ffx.apply_orbital_rotation(vec, U, norb, nelec, out=vec)
+    w, V = np.linalg.eigh(ham.h)
+    ffx.apply_orbital_rotation(vec, (V * np.exp(1j * dt * w)) @ V.conj().T, norb, nelec, out=vec)
+    return vec
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_rotation_sampled_n16(ffx, dtype):
+    norb, nelec = 16, (8, 8)
+    d = ost.dim(norb, 8)
+    r = synth.rng(160)
+    cases = [synth.random_orthogonal(r, norb).astype(complex), synth.random_unitary(r, norb)]
+    x = _device_state(d, dtype, 16)
+    host = x.cpu().numpy()
+    for U in cases:
+        out = ffx.apply_orbital_rotation(x, U, norb, nelec)
+        idx = _sample_idx(d, 6, 161) + [(0, 0), (d - 1, d - 1)]
+        ref = sampled.rotated_amplitudes_blocked(host, U, norb, nelec, idx)
+        assert np.max(np.abs(_at(out, idx) - ref)) <= TOL[dtype]
+        nrm = torch.linalg.vector_norm(out.to(torch.complex128)).item()
+        assert abs(nrm - 1.0) <= (1e-12 if dtype == torch.complex128 else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_df_step_diagonal_hamiltonian_n16(ffx, dtype):
+    # identity rotations, diagonal one-body term: the step is a product of phases
+    norb, nelec, L, dt = 16, (8, 8), 16, 0.1
+    d = ost.dim(norb, 8)
+    r = synth.rng(162)
+    eps = r.normal(0, 0.5, norb)
+    J = np.stack([synth.random_symmetric(r, norb, 0.1) for _ in range(L)])
+    ham = synth.DFHamiltonian(h=np.diag(eps), J=J, U=np.stack([np.eye(norb, dtype=complex)] * L))
+    x = _device_state(d, dtype, 17)
+    idx = _sample_idx(d, 512, 163) + [(0, 0), (d - 1, d - 1), (0, d - 1)]
+    x0 = _at(x, idx)
+    out = ffx.simulate_trotter_double_factorized(x, ham, dt, norb, nelec, n_steps=1, order=0)
+    xa = ost.occupations(norb, 8)[[i for i, _ in idx]]
+    xb = ost.occupations(norb, 8)[[j for _, j in idx]]
+    ang = -dt * ((xa + xb) @ eps)
+    for t in range(L):
+        ang -= 0.5 * dt * og.diag_coulomb_angle_at(norb, nelec, idx, J[t])
+    assert np.max(np.abs(_at(out, idx) - np.exp(1j * ang) * x0)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_df_step_reversible_n16(ffx, dtype):
+    norb, nelec, dt = 16, (8, 8), 0.1
+    w = synth.workload_df_trotter(norb, 16, seed=0, start="hf", dt=dt)
+    d = ost.dim(norb, 8)
+    x0 = _device_state(d, dtype, 18)
+    x = x0.clone()
+    ffx.simulate_trotter_double_factorized(x, w.data["ham"], dt, norb, nelec, n_steps=1, order=0, out=x)
+    moved = torch.max(torch.abs(x - x0)).item()
+    _inverse_step(ffx, x, w.data["ham"], dt, norb, nelec)
+    err = torch.max(torch.abs((x - x0).to(torch.complex128))).item()
+    assert moved > 1e-4
+    assert err <= (1e-12 if dtype == torch.complex128 else 1e-5)
+
+
+def test_rotation_sampled_n18_c64(ffx):
+    # config-5 size: 48620 x 48620 complex64 (18.9 GB); segments and crossing rotations
+    norb, nelec = 18, (9, 9)
+    d = ost.dim(norb, 9)
+    U = synth.random_orthogonal(synth.rng(180), norb).astype(complex)
+    x = _device_state(d, torch.complex64, 19)
+    host = x.cpu().numpy()
+    ffx.apply_orbital_rotation(x, U, norb, nelec, out=x)
+    idx = [(int(i), 31415) for i in np.random.default_rng(181).integers(0, d, 5)] + [(0, 31415)]
+    ref = sampled.rotated_amplitudes_blocked(host, U, norb, nelec, idx, block=4096)
+    del host
+    assert np.max(np.abs(_at(x, idx) - ref)) <= 1e-5
+
+
+def test_df_step_reversible_n18_c64(ffx):
+    norb, nelec, dt = 18, (9, 9), 0.1
+    ham = synth.df_hamiltonian(synth.rng(0), norb, 18)
+    d = ost.dim(norb, 9)
+    x0 = _device_state(d, torch.complex64, 20)
+    x = x0.clone()
+    ffx.simulate_trotter_double_factorized(x, ham, dt, norb, nelec, n_steps=1, order=0, out=x)
+    nrm = torch.linalg.vector_norm(x).item()
+    _inverse_step(ffx, x, ham, dt, norb, nelec)
+    assert abs(nrm - 1.0) <= 1e-5
+    assert torch.max(torch.abs(x - x0)).item() <= 1e-5
+
+
+def _golden():
+    with open(GOLDEN) as f:
+        lines = [ln.split() for ln in f if not ln.startswith("#")]
+    norm = float(lines[0][1])
+    energy = complex(float(lines[1][1]), float(lines[1][2]))
+    idx = [(int(a[0]), int(a[1])) for a in lines[2:]]
+    amp = np.array([complex(float(a[2]), float(a[3])) for a in lines[2:]])
+    return norm, energy, idx, amp
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden file not generated")
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_df_trotter_config2_golden(ffx, dtype):
+    norm, energy, idx, amp = _golden()
+    w = synth.workload_df_trotter(14, 14, seed=0, start="hf", dt=0.1, n_steps=2)
+    x = torch.from_numpy(w.data["vec"]).to(dtype).to("cuda:0")
+    ffx.simulate_trotter_double_factorized(x, w.data["ham"], 0.2, 14, (7, 7), n_steps=2, order=0, out=x)
+    tol = TOL[dtype]
+    assert np.max(np.abs(_at(x, idx) - amp)) <= tol
+    assert abs(torch.linalg.vector_norm(x.to(torch.complex128)).item() - norm) <= tol
+    e = ffx.df_energy(x, w.data["ham"], 14, (7, 7))
+    assert abs(e - energy.real) <= (1e-10 if dtype == torch.complex128 else 1e-5) * max(1.0, abs(energy.real))

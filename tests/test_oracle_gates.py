@@ -172,3 +172,17 @@ def test_one_body_action_and_transition_matrix():
         for q in range(norb):
             ref = np.vdot(lam.reshape(-1), F.restrict(F.E(p, q), nelec) @ vec.reshape(-1))
             assert abs(T[p, q] - ref) < 1e-13
+
+
+@pytest.mark.parametrize("norb,nelec", SECTORS)
+def test_diag_coulomb_angle_at_equals_generator_diagonal(norb, nelec):
+    # the pointwise angle is twice the diagonal of the Fock-space generator
+    r = synth.rng(61)
+    F = Fock(norb)
+    da, db = _dims(norb, nelec)
+    Jaa, Jab, Jbb = (synth.random_symmetric(r, norb, 1.0) for _ in range(3))
+    gen = np.diag(F.restrict(F.diag_coulomb_gen(Jaa, Jab, Jbb), nelec)).reshape(da, db)
+    idx = [(i, j) for i in range(da) for j in range(db)]
+    at = g.diag_coulomb_angle_at(norb, nelec, idx, Jaa, Jab, Jbb)
+    np.testing.assert_allclose(at, 2 * gen.reshape(-1), atol=1e-13)
+    np.testing.assert_allclose(at, g.diag_coulomb_angle(norb, nelec, Jaa, Jab, Jbb).reshape(-1), atol=1e-13)

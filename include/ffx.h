@@ -159,6 +159,49 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
                          double* energy, double* grad, void* psi_out, void* workspace,
                          void* stream);
 
+/* ---------------------------------------------------------------------------
+   Batched LUCJ energy + adjoint gradient over many independent sectors of
+   uneven size (each instance its own norb, (n_alpha, n_beta), LUCJ
+   parameters and DF Hamiltonian), all of them in ONE persistent kernel
+   launch (Sec. 4.5.1 ansatz, Sec. 4.2 energy; the batching itself is this
+   library's extension).
+   A batch object owns one plan per distinct sector type and the class tables
+   of the batched kernel.  Limits: 8 <= norb <= 16 for complex64 and
+   6 <= norb <= 16 for complex128, and one row of every sector must fit in LDS
+   (norb <= 16 at half filling); otherwise FFX_EUNSUPPORTED.
+   --------------------------------------------------------------------------- */
+typedef struct ffx_batch_s* ffx_batch;
+
+int ffx_batch_create(ffx_batch* out, int n_inst, const int* norb, const int* n_alpha,
+                     const int* n_beta, ffx_dtype dtype, int device);
+int ffx_batch_destroy(ffx_batch batch);
+
+/* Device workspace for ffx_batch_lucj_energy_grad: three states per instance
+   (psi, lambda, a temporary), each rounded up to 256 bytes. */
+int64_t ffx_batch_workspace_bytes(ffx_batch batch);
+
+/* ops[i], hams[i]: the instance's LUCJ operator and DF Hamiltonian (host data,
+   read during the call).  energies: n_inst doubles; grads: the instances'
+   gradients back to back (ffx_lucj_n_params(norb_i, n_reps_i) each, in
+   instance order).  Runs every instance's forward pass, costate, energy and
+   reverse sweep in one launch on `stream`, then synchronizes.  A kernel
+   whose dependency waits exceed their bound stops early and the call
+   returns FFX_EDEVICE. */
+int ffx_batch_lucj_energy_grad(ffx_batch batch, const ffx_lucj* ops, const ffx_df_ham* hams,
+                               double* energies, double* grads, void* workspace, void* stream);
+
+/* Autotuner: times ffx_batch_lucj_energy_grad on the given instances for each
+   candidate (rows of a task, through the target number of elements a task
+   holds in LDS, x the largest number of Givens rotations fused into one
+   stage) and keeps the fastest for later calls.  Writes the chosen target
+   elements and stage depth to *target_elems and *stage_rots (may be NULL). */
+int ffx_batch_tune(ffx_batch batch, const ffx_lucj* ops, const ffx_df_ham* hams, void* workspace,
+                   void* stream, int* target_elems, int* stage_rots);
+
+/* Configuration in use (for reports): target elements per task, stage depth,
+   resident blocks of the persistent launch, and its LDS bytes per block. */
+int ffx_batch_info(ffx_batch batch, int* target_elems, int* stage_rots, int* blocks, int64_t* lds_bytes);
+
 /* Diagnostics: per-launch timing of the dominant kernels.  While enabled,
    each segment pass and each window pass is bracketed by HIP events on the
    stream it is launched on.  ffx_timing_enable resets the counters

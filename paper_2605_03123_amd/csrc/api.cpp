@@ -19,6 +19,7 @@
 #include "ffx.h"
 #include "host.h"
 #include "plan.h"
+#include "drivers.h"
 
 using namespace ffx;
 
@@ -31,254 +32,11 @@ void check_launch() {
 
 namespace {
 
-thread_local std::string g_last_error;
-
-template <class F>
-int guard(F&& f) {
-  try {
-    g_last_error.clear();
-    f();
-    return FFX_OK;
-  } catch (const Error& e) {
-    g_last_error = e.what();
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    g_last_error = "host allocation failed";
-    return FFX_ENOMEM;
-  } catch (const std::exception& e) {
-    g_last_error = e.what();
-    return FFX_EINVAL;
-  }
-}
-
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int d) {
-    HIPCHK(hipGetDevice(&prev));
-    if (prev != d) HIPCHK(hipSetDevice(d));
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
-
-std::vector<cd> load_complex(int n, const double* p) {
-  std::vector<cd> v((size_t)n * n);
-  for (int i = 0; i < n * n; ++i) v[i] = cd(p[2 * i], p[2 * i + 1]);
-  return v;
-}
-
-std::vector<cd> load_real(int n, const double* p) {
-  std::vector<cd> v((size_t)n * n);
-  for (int i = 0; i < n * n; ++i) v[i] = cd(p[i], 0.0);
-  return v;
-}
-
-bool all_finite(const double* p, size_t n) {
-  for (size_t i = 0; i < n; ++i)
-    if (!std::isfinite(p[i])) return false;
-  return true;
-}
-
-// ---------------------------------------------------------------------------
-// Givens decompositions kept alive for the duration of one call
-// ---------------------------------------------------------------------------
-struct DecompPool {
-  std::deque<Decomposition> v;
-  const Decomposition* add(int N, const std::vector<cd>& U) {
-    v.push_back(givens_decompose(N, U.data()));
-    return &v.back();
-  }
-};
-
-// ---------------------------------------------------------------------------
-// DF Hamiltonian data on the host
-// ---------------------------------------------------------------------------
-struct DFHost {
-  int L = 0;
-  std::vector<double> eps;          // eigenvalues of h
-  std::vector<cd> V;                // eigenvectors of h (columns)
-  std::vector<std::vector<cd>> U;   // U_t
-  std::vector<std::vector<double>> J;
-  // W_0 = V, W_t = U_t
-  const std::vector<cd>& Wm(int term) const { return term == 0 ? V : U[term - 1]; }
-};
-
-DFHost load_df(const ffx_plan_s& P, const ffx_df_ham* ham) {
-  if (!ham || !ham->h || (ham->n_terms > 0 && (!ham->J || !ham->U)))
-    throw Error(FFX_EINVAL, "DF Hamiltonian has a null pointer");
-  if (ham->norb != P.norb) throw Error(FFX_EINVAL, "DF Hamiltonian norb does not match the plan");
-  if (ham->n_terms < 0) throw Error(FFX_EINVAL, "negative n_terms");
-  const int N = P.norb;
-  DFHost d;
-  d.L = ham->n_terms;
-  if (!all_finite(ham->h, (size_t)N * N)) throw Error(FFX_EINVAL, "non-finite h");
-  std::vector<cd> h = load_real(N, ham->h);
-  eigh(N, h, d.eps, d.V);
-  // h is real symmetric: make the eigenvectors real (a real phase choice per column)
-  for (int j = 0; j < N; ++j) {
-    int big = 0;
-    for (int i = 1; i < N; ++i)
-      if (std::abs(d.V[i * N + j]) > std::abs(d.V[big * N + j])) big = i;
-    cd ph = std::abs(d.V[big * N + j]) > 0 ? std::conj(d.V[big * N + j]) / std::abs(d.V[big * N + j]) : 1.0;
-    for (int i = 0; i < N; ++i) d.V[i * N + j] = cd((d.V[i * N + j] * ph).real(), 0.0);
-  }
-  // re-orthonormalise (Gram-Schmidt in FP64) to remove rounding from the phase fix
-  for (int j = 0; j < N; ++j) {
-    for (int k = 0; k < j; ++k) {
-      double dot = 0;
-      for (int i = 0; i < N; ++i) dot += d.V[i * N + j].real() * d.V[i * N + k].real();
-      for (int i = 0; i < N; ++i) d.V[i * N + j] -= dot * d.V[i * N + k];
-    }
-    double nr = 0;
-    for (int i = 0; i < N; ++i) nr += std::norm(d.V[i * N + j]);
-    nr = std::sqrt(nr);
-    for (int i = 0; i < N; ++i) d.V[i * N + j] /= nr;
-  }
-  for (int t = 0; t < d.L; ++t) {
-    if (!all_finite(ham->J + (size_t)t * N * N, (size_t)N * N) || !all_finite(ham->U + (size_t)2 * t * N * N, (size_t)2 * N * N))
-      throw Error(FFX_EINVAL, "non-finite DF term");
-    d.U.push_back(load_complex(N, ham->U + (size_t)2 * t * N * N));
-    d.J.emplace_back(ham->J + (size_t)t * N * N, ham->J + (size_t)(t + 1) * N * N);
-  }
-  return d;
-}
-
-// term 0: sum_p eps_p N_p (one-body term in the eigenbasis of h);
-// term t: 1/2 sum_pq J_t[p][q] N_p N_q
-DiagSpec df_weight_spec(const DFHost& df, int term) {
-  DiagSpec d;
-  if (term == 0) {
-    d.lin_a = d.lin_b = df.eps.data();
-  } else {
-    const double* J = df.J[term - 1].data();
-    d.Qa = d.Qb = d.C = J;
-  }
-  return d;
-}
-
-// product formula as a list of (term, time) in application order
-void product_formula(int order, double t, int n_terms_total, std::vector<std::pair<int, double>>& out) {
-  if (order == 0) {
-    for (int k = 0; k < n_terms_total; ++k) out.push_back({k, t});
-  } else if (order == 1) {
-    for (int k = 0; k < n_terms_total; ++k) out.push_back({k, t / 2});
-    for (int k = n_terms_total - 1; k >= 0; --k) out.push_back({k, t / 2});
-  } else {
-    double u = 1.0 / (4.0 - std::pow(4.0, 1.0 / (2 * order - 1)));
-    for (double tau : {u * t, u * t, (1 - 4 * u) * t, u * t, u * t}) product_formula(order - 1, tau, n_terms_total, out);
-  }
-}
-
-// LUCJ parameters on the host
-struct LUCJHost {
-  int R = 0;
-  std::vector<std::vector<cd>> K, U;
-  std::vector<std::vector<double>> Jsame, Jopp;
-};
-
-LUCJHost load_lucj(const ffx_plan_s& P, const ffx_lucj* op) {
-  if (!op || !op->params) throw Error(FFX_EINVAL, "LUCJ operator has a null pointer");
-  if (op->norb != P.norb) throw Error(FFX_EINVAL, "LUCJ norb does not match the plan");
-  if (op->n_reps < 1) throw Error(FFX_EINVAL, "n_reps must be >= 1");
-  const int N = P.norb;
-  const int per = 2 * N * N + 2 * N - 1;
-  if (!all_finite(op->params, (size_t)per * op->n_reps)) throw Error(FFX_EINVAL, "non-finite LUCJ parameter");
-  LUCJHost L;
-  L.R = op->n_reps;
-  for (int k = 0; k < L.R; ++k) {
-    const double* th = op->params + (size_t)k * per;
-    std::vector<cd> A((size_t)N * N), K((size_t)N * N);
-    for (int i = 0; i < N * N; ++i) A[i] = cd(th[i], th[N * N + i]);
-    for (int i = 0; i < N; ++i)
-      for (int j = 0; j < N; ++j) K[i * N + j] = A[i * N + j] - std::conj(A[j * N + i]);
-    std::vector<double> Js((size_t)N * N, 0.0), Jo((size_t)N * N, 0.0);
-    for (int p = 0; p + 1 < N; ++p) Js[p * N + p + 1] = Js[(p + 1) * N + p] = th[2 * N * N + p];
-    for (int p = 0; p < N; ++p) Jo[p * N + p] = th[2 * N * N + N - 1 + p];
-    L.U.push_back(expm_antihermitian(N, K));
-    L.K.push_back(std::move(K));
-    L.Jsame.push_back(std::move(Js));
-    L.Jopp.push_back(std::move(Jo));
-  }
-  return L;
-}
-
-// Slater column minors of U_1^dag and the merged rotations of the ansatz:
-// after[k] = U_{k+1}^dag U_k (k < R-1), after[R-1] = U_R; undo[k] = after[k]^dag.
-struct LUCJParts {
-  std::vector<cd> a, b;
-  std::vector<const Decomposition*> after, undo;
-  std::vector<DiagSpec> diag;
-};
-
-LUCJParts lucj_parts(const ffx_plan_s& P, const LUCJHost& L, DecompPool& pool, bool with_inverse) {
-  const int N = P.norb;
-  LUCJParts g;
-  std::vector<cd> U1d = dagger(N, L.U[0]);
-  g.a = slater_column_minors(N, P.n[0], U1d, P.str[0]);
-  g.b = (P.n[1] == P.n[0]) ? g.a : slater_column_minors(N, P.n[1], U1d, P.str[1]);
-  for (int k = 0; k < L.R; ++k) {
-    std::vector<cd> M = (k + 1 < L.R) ? matmul(N, dagger(N, L.U[k + 1]), L.U[k]) : L.U[k];
-    g.after.push_back(pool.add(N, M));
-    if (with_inverse) g.undo.push_back(pool.add(N, dagger(N, M)));
-    DiagSpec d;
-    d.Qa = d.Qb = L.Jsame[k].data();
-    d.C = L.Jopp[k].data();
-    g.diag.push_back(d);
-  }
-  return g;
-}
-
-// D_1, rotation, D_2, rotation, ... applied to the Slater determinant
-Program lucj_forward_program(const LUCJParts& g, int R) {
-  Program pr;
-  for (int k = 0; k < R; ++k) {
-    int d = pr.add_diag(g.diag[k]);
-    pr.phase(d, -1.0);
-    pr.rot(g.after[k], g.after[k]);
-  }
-  return pr;
-}
-
 void validate_plan(ffx_plan plan) {
   if (!plan) throw Error(FFX_EINVAL, "null plan");
 }
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
-
-// Gradient with respect to A (K = A - A^dag, U = expm(K)) given G such that
-// dE = 2 Re sum_pq (U^dag dU)_pq G_pq, via the adjoint of the Frechet
-// derivative of expm at the anti-Hermitian K = W diag(-i w) W^dag.
-void expm_param_grad(int N, const std::vector<cd>& K, const std::vector<cd>& G, double* g_re, double* g_im) {
-  std::vector<cd> H((size_t)N * N);
-  for (int i = 0; i < N * N; ++i) H[i] = cd(0, 1) * K[i];
-  std::vector<double> w;
-  std::vector<cd> W;
-  eigh(N, H, w, W);
-  // Q_ij = e^{+i w_i} (W^T G W^*)_ij ; Phi_ij = e^{-i (w_i + w_j)/2} sinc((w_i - w_j)/2)
-  std::vector<cd> WT((size_t)N * N), Wc((size_t)N * N);
-  for (int i = 0; i < N; ++i)
-    for (int j = 0; j < N; ++j) {
-      WT[i * N + j] = W[j * N + i];
-      Wc[i * N + j] = std::conj(W[i * N + j]);
-    }
-  std::vector<cd> Q = matmul(N, matmul(N, WT, G), Wc);
-  for (int i = 0; i < N; ++i)
-    for (int j = 0; j < N; ++j) {
-      double d = 0.5 * (w[i] - w[j]);
-      double sinc = std::fabs(d) < 1e-8 ? 1.0 - d * d / 6.0 : std::sin(d) / d;
-      cd phi = std::exp(cd(0, -0.5 * (w[i] + w[j]))) * sinc;
-      Q[i * N + j] *= std::exp(cd(0, w[i])) * phi;
-    }
-  // Z = W^* R W^T
-  std::vector<cd> Z = matmul(N, matmul(N, Wc, Q), WT);
-  for (int p = 0; p < N; ++p)
-    for (int q = 0; q < N; ++q) {
-      g_re[p * N + q] = 2.0 * (Z[p * N + q] - Z[q * N + p]).real();
-      g_im[p * N + q] = 2.0 * (cd(0, 1) * (Z[p * N + q] + Z[q * N + p])).real();
-    }
-}
 
 }  // namespace
 
@@ -287,7 +45,7 @@ void expm_param_grad(int N, const std::vector<cd>& K, const std::vector<cd>& G, 
 // ---------------------------------------------------------------------------
 extern "C" {
 
-const char* ffx_last_error(void) { return g_last_error.c_str(); }
+const char* ffx_last_error(void) { return ffx::last_error().c_str(); }
 
 int64_t ffx_dim(int norb, int n) {
   if (norb < 1 || norb > 32 || n < 0 || n > norb) return -1;
@@ -721,8 +479,9 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
     if (!energy || !grad || !workspace) throw Error(FFX_EINVAL, "null pointer");
     ffx_plan_s& P = *plan;
     const int N = P.norb;
-    LUCJHost L = load_lucj(P, op);
-    DFHost df = load_df(P, ham);
+    std::unique_ptr<LUCJGrad> G = build_lucj_grad(P, op, ham);
+    const int R = G->L.R;
+    const int Lt = G->df.L;
     DeviceGuard dg(P.device);
     hipStream_t s = as_stream(stream);
     const size_t S = P.state_bytes();
@@ -734,33 +493,16 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
     void* lamT = ws + 3 * Sa;
     void* psi = psi_out ? psi_out : (void*)(ws + 4 * Sa);
     double* part = (double*)(ws + 5 * Sa);
-    DecompPool pool;
-    LUCJParts g = lucj_parts(P, L, pool, true);
-    Program fwd = lucj_forward_program(g, L.R);
-    // costate terms: U_t D_t U_t^dag psi
-    std::vector<Program> terms(df.L + 1);
-    for (int t = 0; t <= df.L; ++t) {
-      const Decomposition* to = pool.add(N, dagger(N, df.Wm(t)));
-      const Decomposition* from = pool.add(N, df.Wm(t));
-      terms[t].rot(to, to);
-      terms[t].scale(terms[t].add_diag(df_weight_spec(df, t)));
-      terms[t].rot(from, from);
-    }
-    std::vector<Program> undo_rot(L.R), undo_diag(L.R);
-    for (int k = 0; k < L.R; ++k) {
-      undo_rot[k].rot(g.undo[k], g.undo[k]);
-      undo_diag[k].phase(undo_diag[k].add_diag(g.diag[k]), +1.0);
-    }
     Upload up(&P, s);
-    const double* sa = up.put((const double*)g.a.data(), 2 * g.a.size());
-    const double* sb = up.put((const double*)g.b.data(), 2 * g.b.size());
-    Compiled c_fwd = compile_program(P, up, fwd, FINAL_STORE, s);
+    const double* sa = up.put((const double*)G->g.a.data(), 2 * G->g.a.size());
+    const double* sb = up.put((const double*)G->g.b.data(), 2 * G->g.b.size());
+    Compiled c_fwd = compile_program(P, up, G->fwd, FINAL_STORE, s);
     std::vector<Compiled> c_terms, c_urot, c_udiag;
-    for (int t = 0; t <= df.L; ++t)
-      c_terms.push_back(compile_program(P, up, terms[t], t == 0 ? FINAL_STORE : FINAL_ACCUM, s));
-    for (int k = 0; k < L.R; ++k) {
-      c_urot.push_back(compile_program(P, up, undo_rot[k], FINAL_STORE, s));
-      c_udiag.push_back(compile_program(P, up, undo_diag[k], FINAL_STORE, s));
+    for (int t = 0; t <= Lt; ++t)
+      c_terms.push_back(compile_program(P, up, G->terms[t], t == 0 ? FINAL_STORE : FINAL_ACCUM, s));
+    for (int k = 0; k < R; ++k) {
+      c_urot.push_back(compile_program(P, up, G->undo_rot[k], FINAL_STORE, s));
+      c_udiag.push_back(compile_program(P, up, G->undo_diag[k], FINAL_STORE, s));
     }
     up.commit();
     // forward
@@ -768,7 +510,7 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
     check_launch();
     execute_program(P, c_fwd, psi, psi, nullptr, s);
     // costate lambda = H psi
-    for (int t = 0; t <= df.L; ++t) {
+    for (int t = 0; t <= Lt; ++t) {
       if (t == 0)
         execute_program(P, c_terms[t], psi, lam, nullptr, s);
       else
@@ -779,9 +521,9 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
     check_launch();
     // reverse sweep: uncompute psi and lambda, collecting transition matrices
     const int NN = N * N;
-    double* Tdev = P.results + 16;                       // per rep: T_b (alpha, beta), T_a (alpha, beta)
-    double* Ddev = P.results + 16 + (size_t)L.R * 8 * NN;  // per rep: 2N-1 diagonal-gate gradients
-    if (16 + (size_t)L.R * (8 * NN + 2 * N) > (size_t)ffx_plan_s::kResults)
+    double* Tdev = P.results + 16;                     // per rep: T_b (alpha, beta), T_a (alpha, beta)
+    double* Ddev = P.results + 16 + (size_t)R * 8 * NN;  // per rep: 2N-1 diagonal-gate gradients
+    if (16 + (size_t)R * (8 * NN + 2 * N) > (size_t)ffx_plan_s::kResults)
       throw Error(FFX_EUNSUPPORTED, "too many LUCJ repetitions for the result buffer");
     auto rdm = [&](double* Tout) {
       dev::rdm_rows(P.c64, lam, psi, P.dim[0], P.dim[1], P.d_masks[0], N, part, s);
@@ -792,7 +534,7 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
       dev::rdm_reduce(part, P.dim[1], N, Tout + 2 * NN, s);
       check_launch();
     };
-    for (int k = L.R - 1; k >= 0; --k) {
+    for (int k = R - 1; k >= 0; --k) {
       execute_program(P, c_urot[k], psi, psi, nullptr, s);
       execute_program(P, c_urot[k], lam, lam, nullptr, s);
       rdm(Tdev + (size_t)k * 8 * NN);
@@ -803,23 +545,27 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
       execute_program(P, c_udiag[k], lam, lam, nullptr, s);
       rdm(Tdev + (size_t)k * 8 * NN + 4 * NN);
     }
-    std::vector<double> res(16 + (size_t)L.R * (8 * NN + 2 * N));
+    std::vector<double> res(16 + (size_t)R * (8 * NN + 2 * N));
     HIPCHK(hipMemcpyAsync(res.data(), P.results, res.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     *energy = res[0];
-    const int per = 2 * NN + 2 * N - 1;
-    for (int k = 0; k < L.R; ++k) {
-      const double* Tb = res.data() + 16 + (size_t)k * 8 * NN;
-      const double* Ta = Tb + 4 * NN;
-      std::vector<cd> G((size_t)NN);
-      for (int i = 0; i < NN; ++i)
-        G[i] = cd(Tb[2 * i] + Tb[2 * NN + 2 * i] - Ta[2 * i] - Ta[2 * NN + 2 * i],
-                  Tb[2 * i + 1] + Tb[2 * NN + 2 * i + 1] - Ta[2 * i + 1] - Ta[2 * NN + 2 * i + 1]);
-      double* gk = grad + (size_t)k * per;
-      expm_param_grad(N, L.K[k], G, gk, gk + NN);
-      const double* dg = res.data() + 16 + (size_t)L.R * 8 * NN + (size_t)k * (2 * N);
-      for (int i = 0; i < 2 * N - 1; ++i) gk[2 * NN + i] = dg[i];
+    // both spins summed: T = T_alpha + T_beta
+    std::vector<std::vector<double>> tb(R), ta(R);
+    std::vector<const double*> Tb(R), Ta(R), D(R);
+    for (int k = 0; k < R; ++k) {
+      const double* b = res.data() + 16 + (size_t)k * 8 * NN;
+      const double* a = b + 4 * NN;
+      tb[k].resize(2 * NN);
+      ta[k].resize(2 * NN);
+      for (int i = 0; i < 2 * NN; ++i) {
+        tb[k][i] = b[i] + b[2 * NN + i];
+        ta[k][i] = a[i] + a[2 * NN + i];
+      }
+      Tb[k] = tb[k].data();
+      Ta[k] = ta[k].data();
+      D[k] = res.data() + 16 + (size_t)R * 8 * NN + (size_t)k * (2 * N);
     }
+    lucj_grad_assemble(*G, N, Tb, Ta, D, grad);
   });
 }
 

@@ -1,0 +1,633 @@
+// Batched persistent launch (gfx950): many independent sectors of uneven
+// size, each running its own list of passes (LUCJ forward, costate, energy,
+// reverse sweep with transition one-body matrices), in ONE kernel launch.
+//
+// Work is a global queue of tasks.  A task is a block of consecutive rows (or
+// of consecutive columns: the rows of the transposed layout) of one instance's
+// state, or a small per-instance job (tables, fixed-order sums).  Tasks are
+// queued pass level by pass level across instances; a block takes the next
+// task with an atomic counter and, before running it, waits until every task
+// of the same instance's earlier passes has finished (a per-instance counter
+// published with agent-scope release / acquire, so writes made on other XCDs
+// are visible).  A task only ever waits for tasks queued before it, which were
+// taken by blocks that are already running, so the queue drains whatever the
+// number of resident blocks.  Every wait is bounded: past the bound the block
+// raises the abort flag and every block leaves at its next task.  Waiting
+// blocks poll with relaxed loads and sleep between polls; one acquire fence per
+// task makes the awaited data visible.
+//
+// Givens and diagonal stages run on the task's rows held back to back in LDS,
+// with the class tables of one row replicated over the rows (see
+// replicate_seg_window), so small rows still fill the 64 lanes of a wave.
+// Columns are gathered and scattered directly, so no transposes are needed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <utility>
+
+#include "dev_common.h"
+#include "device.h"
+
+namespace ffx {
+namespace dev {
+
+constexpr int kBatchThreads = 256;
+constexpr int kBatchMaxRows = 64;   // rows per task
+constexpr int kBatchMaxOrb = 16;    // orbitals of a batched sector
+// bounded wait, in ticks of the 100 MHz real-time counter (2 s)
+constexpr uint64_t kWaitTicks = 200000000ull;
+// dynamic LDS limit: the kernel's own static LDS (a few scalars) shares the 160 KB
+constexpr int kBatchMaxDynLds = 160 * 1024 - 256;
+
+struct BatchLds {
+  char* rows;
+  int* mt;
+  double* wq;      // kBatchMaxRows x kBatchMaxOrb cross weights
+  double* rowf;    // kBatchMaxRows complex row factors (or real row values)
+  double* acc;     // 4 waves x 2 N^2 doubles (RDM) or 4 x 2N (diagonal gradients)
+  double* red;     // 16 doubles
+};
+
+__device__ __forceinline__ BatchLds batch_lds_map(char* smem, const BatchDev& B) {
+  BatchLds L;
+  L.rows = smem;
+  L.mt = (int*)(smem + B.lds_row_bytes);
+  L.wq = (double*)(L.mt + ((B.max_mt + 3) & ~3));
+  L.rowf = L.wq + kBatchMaxRows * kBatchMaxOrb;
+  L.acc = L.rowf + 2 * kBatchMaxRows;
+  L.red = L.acc + 4 * 2 * kBatchMaxOrb * kBatchMaxOrb;
+  return L;
+}
+
+size_t batch_lds(bool c64, int lds_row_bytes, int max_mt, int norb_max) {
+  (void)c64;
+  (void)norb_max;
+  return (size_t)lds_row_bytes + (size_t)((max_mt + 3) & ~3) * 4 +
+         (size_t)(kBatchMaxRows * kBatchMaxOrb + 2 * kBatchMaxRows + 8 * kBatchMaxOrb * kBatchMaxOrb + 16) * 8;
+}
+
+// fixed-order block sum (4 waves); every thread gets the result
+__device__ __forceinline__ double batch_block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double t = red[0];
+  for (int i = 1; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// a two-entry field picked by a runtime index without indexing into the struct
+// (which would move the struct to scratch memory)
+template <class T>
+__device__ __forceinline__ T pick2(const T (&a)[2], int i) {
+  return i ? a[1] : a[0];
+}
+
+// element k of row r of the layout (0: alpha-major rows, 1: columns)
+__device__ __forceinline__ int64_t lay_index(int layout, int64_t r, int64_t k, int64_t ncols_state) {
+  return layout == 0 ? r * ncols_state + k : k * ncols_state + r;
+}
+
+// ---------------------------------------------------------------------------
+// tables of a program: per-string diagonal values and column phase factors
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void tables_task(const BPassDev& ps, const BTypeDev& ty, int task) {
+  const BTableDev e = uniform_load(ps.tables + task);
+  const int N = ty.norb;
+  if (e.kind == 0) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      double* out = s == 0 ? e.A : e.B;
+      if (!out) continue;
+      const double* lin = s == 0 ? e.spec.lin_a : e.spec.lin_b;
+      const double* Q = s == 0 ? e.spec.Qa : e.spec.Qb;
+      for (int64_t i = threadIdx.x; i < ty.dim[s]; i += blockDim.x) {
+        const uint32_t m = ty.masks[s][i];
+        double acc = 0;
+        for (int p = 0; p < N; ++p) {
+          if (!((m >> p) & 1)) continue;
+          if (lin) acc += lin[p];
+          if (Q)
+            for (int q = 0; q < N; ++q)
+              if ((m >> q) & 1) acc += 0.5 * Q[p * N + q];
+        }
+        out[i] = acc;
+      }
+    }
+  } else {
+    zc128* out = (zc128*)e.out;
+    for (int64_t i = threadIdx.x; i < pick2(ty.dim, e.spin); i += blockDim.x) {
+      const uint32_t m = pick2(ty.masks, e.spin)[i];
+      double ang = e.cB ? e.scale * e.cB[i] : 0.0;
+      if (e.delta)
+        for (uint32_t x = m; x; x &= x - 1) ang += e.delta[__builtin_ctz(x)];
+      zc128 f = phase_factor<double>(ang);
+      if (__builtin_popcount(m & e.sign) & 1) {
+        f.x = -f.x;
+        f.y = -f.y;
+      }
+      out[i] = f;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Slater outer product, inner product, fixed-order sums
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ void outer_task(const BPassDev& ps, const BTypeDev& ty, int task) {
+  using V = typename V2T<R>::type;
+  const int RR = ty.rows_per_task[1];
+  const int64_t db = ty.dim[1];
+  const int64_t r0 = (int64_t)task * RR;
+  const int64_t n = std::min<int64_t>(RR, ty.dim[0] - r0) * db;
+  const zc128* a = (const zc128*)ps.oa + r0;
+  const zc128* b = (const zc128*)ps.ob;
+  V* out = (V*)ps.dst + r0 * db;
+  for (int64_t x = threadIdx.x; x < n; x += blockDim.x) {
+    const zc128 u = a[x / db], v = b[x % db];
+    V o;
+    o.x = (R)(u.x * v.x - u.y * v.y);
+    o.y = (R)(u.x * v.y + u.y * v.x);
+    out[x] = o;
+  }
+}
+
+template <class R>
+__device__ __forceinline__ void inner_task(const BPassDev& ps, const BTypeDev& ty, int task, double* red) {
+  using V = typename V2T<R>::type;
+  const int RR = ty.rows_per_task[1];
+  const int64_t db = ty.dim[1];
+  const int64_t r0 = (int64_t)task * RR;
+  const int64_t n = std::min<int64_t>(RR, ty.dim[0] - r0) * db;
+  const V* x = (const V*)ps.src + r0 * db;
+  const V* y = (const V*)ps.src2 + r0 * db;
+  double re = 0, im = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double ax = x[i].x, ay = x[i].y, bx = y[i].x, by = y[i].y;
+    re += ax * bx + ay * by;
+    im += ax * by - ay * bx;
+  }
+  re = batch_block_sum(re, red);
+  im = batch_block_sum(im, red);
+  if (threadIdx.x == 0) {
+    ps.partials[2 * task] = re;
+    ps.partials[2 * task + 1] = im;
+  }
+}
+
+__device__ __forceinline__ void sum_task(const BPassDev& ps) {
+  for (int w = threadIdx.x; w < ps.width; w += blockDim.x) {
+    double t = 0;
+    for (int k = 0; k < ps.n_sum; ++k) t += ps.partials[(int64_t)k * ps.width + w];
+    ps.out[w] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// transition one-body matrix of the row spin of a layout, one wave per row:
+// T[p][q] += sign * sum_k conj(lam[J, k]) psi[I, k], J = I - q + p
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ void rdm_task(const BPassDev& ps, const BTypeDev& ty, int task, double* acc) {
+  using V = typename V2T<R>::type;
+  const int cs = ps.layout == 0 ? 1 : 0, rs = 1 - cs;
+  const int N = ty.norb, NN = N * N;
+  const int64_t nrows = pick2(ty.dim, rs), len = pick2(ty.dim, cs), ncols_state = ty.dim[1];
+  const int RR = pick2(ty.rows_per_task, cs);
+  const int64_t r0 = (int64_t)task * RR;
+  const int nr = (int)std::min<int64_t>(RR, nrows - r0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const V* lam = (const V*)ps.src;
+  const V* psi = (const V*)ps.src2;
+  double* T = acc + wave * 2 * NN;
+  for (int i = threadIdx.x; i < 4 * 2 * NN; i += blockDim.x) acc[i] = 0.0;
+  __syncthreads();
+  for (int r = wave; r < nr; r += nw) {
+    const int64_t row = r0 + r;
+    const uint32_t I = pick2(ty.masks, rs)[row];
+    for (int p = 0; p < N; ++p)
+      for (int q = 0; q < N; ++q) {
+        if (!((I >> q) & 1) || (p != q && ((I >> p) & 1))) continue;
+        const uint32_t J = (I & ~(1u << q)) | (1u << p);
+        const int lo = p < q ? p : q, hi = p < q ? q : p;
+        const uint32_t between = (hi - lo > 1) ? (I >> (lo + 1)) & ((1u << (hi - lo - 1)) - 1) : 0u;
+        const double sign = (__builtin_popcount(between) & 1) ? -1.0 : 1.0;
+        const int64_t jrow = colex_rank(J);
+        double re = 0, im = 0;
+        for (int64_t k = lane; k < len; k += 64) {
+          const V a = lam[lay_index(ps.layout, jrow, k, ncols_state)];
+          const V b = psi[lay_index(ps.layout, row, k, ncols_state)];
+          const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
+          re += ax * bx + ay * by;
+          im += ax * by - ay * bx;
+        }
+        re = wave_sum(re);
+        im = wave_sum(im);
+        if (lane == 0) {
+          T[2 * (p * N + q)] += sign * re;
+          T[2 * (p * N + q) + 1] += sign * im;
+        }
+      }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2 * NN; i += blockDim.x) {
+    double t = 0;
+    for (int w = 0; w < nw; ++w) t += acc[w * 2 * NN + i];
+    ps.partials[(int64_t)task * 2 * NN + i] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gradients of a LUCJ diagonal gate (same-spin pairs (p, p+1), opposite-spin
+// pairs (p, p)), one wave per alpha row, with z = Im(conj(lam) psi):
+//   out[p]       += 2 (x_a[p] x_a[p+1] sum z + sum z x_b[p] x_b[p+1])   p < N-1
+//   out[N-1+p]   += 2 x_a[p] sum z x_b[p]
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ void dgrad_task(const BPassDev& ps, const BTypeDev& ty, int task, double* acc) {
+  using V = typename V2T<R>::type;
+  const int N = ty.norb, NO = 2 * N - 1;
+  const int64_t db = ty.dim[1];
+  const int RR = ty.rows_per_task[1];
+  const int64_t r0 = (int64_t)task * RR;
+  const int nr = (int)std::min<int64_t>(RR, ty.dim[0] - r0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const V* lam = (const V*)ps.src;
+  const V* psi = (const V*)ps.src2;
+  double* out = acc + wave * 2 * kBatchMaxOrb;
+  for (int i = threadIdx.x; i < 4 * 2 * kBatchMaxOrb; i += blockDim.x) acc[i] = 0.0;
+  __syncthreads();
+  for (int r = wave; r < nr; r += nw) {
+    const int64_t row = r0 + r;
+    const uint32_t ma = ty.masks[0][row];
+    double s0 = 0, s1[kBatchMaxOrb], s2[kBatchMaxOrb];
+#pragma unroll
+    for (int p = 0; p < kBatchMaxOrb; ++p) s1[p] = s2[p] = 0;
+    for (int64_t k = lane; k < db; k += 64) {
+      const V a = lam[row * db + k], b = psi[row * db + k];
+      const double z = (double)a.x * (double)b.y - (double)a.y * (double)b.x;
+      const uint32_t mb = ty.masks[1][k];
+      s0 += z;
+#pragma unroll
+      for (int p = 0; p < kBatchMaxOrb; ++p) {
+        const double bp = (double)((mb >> p) & 1);
+        s1[p] += z * bp;
+        s2[p] += z * bp * (double)((mb >> (p + 1)) & 1);
+      }
+    }
+    s0 = wave_sum(s0);
+#pragma unroll
+    for (int p = 0; p < kBatchMaxOrb; ++p) {
+      s1[p] = wave_sum(s1[p]);
+      s2[p] = wave_sum(s2[p]);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int p = 0; p < kBatchMaxOrb; ++p) {
+        if (p + 1 < N) out[p] += 2.0 * ((double)(((ma >> p) & 1) & ((ma >> (p + 1)) & 1)) * s0 + s2[p]);
+        if (p < N) out[N - 1 + p] += 2.0 * (double)((ma >> p) & 1) * s1[p];
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < NO; i += blockDim.x) {
+    double t = 0;
+    for (int w = 0; w < nw; ++w) t += acc[w * 2 * kBatchMaxOrb + i];
+    ps.partials[(int64_t)task * NO + i] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// segment pass on a block of rows (or columns) held back to back in LDS
+// ---------------------------------------------------------------------------
+template <int W, bool REAL, class R>
+__device__ __forceinline__ void seg_task(const BatchDev& B, const BPassDev& ps, const BTypeDev& ty, int task, const BatchLds& L) {
+  using V = typename V2T<R>::type;
+  const int cs = ps.layout == 0 ? 1 : 0, rs = 1 - cs;
+  const int N = ty.norb;
+  const int64_t nrows = pick2(ty.dim, rs), len = pick2(ty.dim, cs), ncols_state = ty.dim[1];
+  const int RR = pick2(ty.rows_per_task, cs);
+  const void* src = ps.src;
+  void* dst = ps.dst;
+  if (task >= ps.half) {
+    task -= ps.half;
+    src = ps.src2;
+    dst = ps.dst2;
+  }
+  const int64_t r0 = (int64_t)task * RR;
+  const int nr = (int)std::min<int64_t>(RR, nrows - r0);
+  const int64_t nel = (int64_t)nr * len;
+  const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+  V* buf = (V*)L.rows;
+  const V* s = (const V*)src;
+
+  // gather: element (r, k) of the layout lands at buf[r * len + k]
+  if (ps.layout == 0) {
+    for (int64_t x = tid; x < nel; x += nthr) buf[x] = s[r0 * len + x];
+  } else {
+    for (int64_t x = tid; x < nel; x += nthr) {
+      const int64_t k = x / nr, r = x - k * nr;
+      buf[r * len + k] = s[k * ncols_state + r0 + r];
+    }
+  }
+  for (int64_t x = nel + tid; x < (int64_t)RR * len; x += nthr) buf[x] = V{};
+  for (int i = tid; i < pick2(ty.n_mt_all, cs); i += nthr) L.mt[i] = pick2(ty.mt_all, cs)[i];
+  __syncthreads();
+
+  const uint32_t* cmask = pick2(ty.masks, cs);
+  const uint32_t* rmask = pick2(ty.masks, rs) + r0;
+  double acc = 0.0;
+  for (int si = 0; si < ps.n_stages; ++si) {
+    const StageDev st = uniform_load(ps.stages + si);
+    if (st.type == ST_GIVENS) {
+      const SegWinDev wt = uniform_load(pick2(ty.win, cs) + st.a);
+      const int* mw = L.mt + wt.mt_off;
+      const RotLane<R> rl = load_rot_lane<R>(st.rots, st.nrot, lane);
+      for (int ch = wave; ch < wt.n_chunks; ch += nwaves) {
+        const int m = __builtin_amdgcn_readfirstlane(wt.chunk_m[ch]);
+        const int code = wt.code[ch * 64 + lane];
+        if (code >= 0)
+          lds_m<W, REAL, R>(m, buf, code >> 5, L.mt, wt.mt_off + mw[m * wt.nl1 + (code & 31)], rl, st.nrot);
+      }
+    } else {
+      // per row: cross weights w_r[q] = sum_{p in row} C[p][q] and the row factor
+      for (int i = tid; i < nr * N; i += nthr) {
+        const int r = i / N, q = i - r * N;
+        double w = 0.0;
+        if (st.C) {
+          const uint32_t rm = rmask[r];
+          for (int p = 0; p < N; ++p)
+            if ((rm >> p) & 1) w += st.C[p * N + q];
+        }
+        L.wq[r * kBatchMaxOrb + q] = w;
+      }
+      for (int r = tid; r < nr; r += nthr) {
+        const uint32_t rm = rmask[r];
+        const double arow = st.A ? st.A[r0 + r] : 0.0;
+        if (st.type == ST_PHASE) {
+          double g = st.scale * arow;
+          if (st.drow)
+            for (uint32_t x = rm; x; x &= x - 1) g += st.drow[__builtin_ctz(x)];
+          zc128 f = phase_factor<double>(g);
+          if (__builtin_popcount(rm & st.sign_row) & 1) {
+            f.x = -f.x;
+            f.y = -f.y;
+          }
+          L.rowf[2 * r] = f.x;
+          L.rowf[2 * r + 1] = f.y;
+        } else {
+          L.rowf[2 * r] = arow;
+        }
+      }
+      __syncthreads();
+      const bool cross = st.C != nullptr;
+      for (int64_t x = tid; x < nel; x += nthr) {
+        const int r = (int)(x / len);
+        const int64_t k = x - (int64_t)r * len;
+        double cr = 0.0;
+        if (cross)
+          for (uint32_t b = cmask[k]; b; b &= b - 1) cr += L.wq[r * kBatchMaxOrb + __builtin_ctz(b)];
+        V y = buf[x];
+        if (st.type == ST_PHASE) {
+          zc128 f{L.rowf[2 * r], L.rowf[2 * r + 1]};
+          if (st.colf) f = zmul(f, ((const zc128*)st.colf)[k]);
+          if (cross) {
+            const V e = phase_factor<R>(st.scale * cr);
+            f = zmul(f, zc128{(double)e.x, (double)e.y});
+          }
+          V o;
+          o.x = (R)((double)y.x * f.x - (double)y.y * f.y);
+          o.y = (R)((double)y.x * f.y + (double)y.y * f.x);
+          buf[x] = o;
+        } else {
+          const double f = L.rowf[2 * r] + (st.B ? st.B[k] : 0.0) + cr;
+          if (st.type == ST_SCALE) {
+            y.x = (R)(f * (double)y.x);
+            y.y = (R)(f * (double)y.y);
+            buf[x] = y;
+          } else {
+            acc += f * ((double)y.x * (double)y.x + (double)y.y * (double)y.y);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  if (ps.mode != SEG_NONE) {
+    V* d = (V*)dst;
+    const bool add = ps.mode == SEG_ACCUM;
+    if (ps.layout == 0) {
+      for (int64_t x = tid; x < nel; x += nthr) {
+        V v = buf[x];
+        if (add) {
+          const V a = d[r0 * len + x];
+          v.x += a.x;
+          v.y += a.y;
+        }
+        d[r0 * len + x] = v;
+      }
+    } else {
+      for (int64_t x = tid; x < nel; x += nthr) {
+        const int64_t k = x / nr, r = x - k * nr;
+        const int64_t gi = k * ncols_state + r0 + r;
+        V v = buf[r * len + k];
+        if (add) {
+          const V a = d[gi];
+          v.x += a.x;
+          v.y += a.y;
+        }
+        d[gi] = v;
+      }
+    }
+  }
+  if (ps.partials) {
+    const double t = batch_block_sum(acc, L.red);
+    if (tid == 0) ps.partials[task] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the persistent kernel
+// ---------------------------------------------------------------------------
+template <int W, class R>
+__global__ __launch_bounds__(kBatchThreads) void k_batch(BatchDev B) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ int s_pass, s_ok;
+  __shared__ int64_t s_task;
+  const BatchLds L = batch_lds_map(smem, B);
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int pi = -1;
+      int64_t t = -1;
+      if (!__hip_atomic_load(B.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        t = (int64_t)__hip_atomic_fetch_add(B.next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t < B.n_tasks) {
+          int lo = 0, hi = B.n_passes - 1;  // last pass whose first task <= t
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (B.passes[mid].first <= t)
+              lo = mid;
+            else
+              hi = mid - 1;
+          }
+          pi = lo;
+        }
+      }
+      int ok = pi >= 0;
+      if (ok) {
+        const int inst = B.passes[pi].inst;
+        const unsigned need = (unsigned)B.passes[pi].need;
+        // poll with relaxed loads (an acquire here would invalidate the caches on
+        // every iteration under the other blocks' running tasks); the acquire
+        // fence after the barrier below orders this block's reads of the data
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        while (__hip_atomic_load(B.done + inst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          __builtin_amdgcn_s_sleep(32);
+          if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks ||
+              __hip_atomic_load(B.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            __hip_atomic_store(B.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = 0;
+            break;
+          }
+        }
+      }
+      s_pass = pi;
+      s_task = t;
+      s_ok = ok;
+    }
+    __syncthreads();
+    const int pi = s_pass;
+    const int64_t t = s_task;
+    const int ok = s_ok;
+    __syncthreads();
+    if (!ok) break;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const BPassDev ps = uniform_load(B.passes + pi);
+    const BTypeDev ty = uniform_load(B.types + ps.type);
+    const int task = (int)(t - ps.first);
+    switch (ps.kind) {
+      case BK_TABLES: tables_task(ps, ty, task); break;
+      case BK_OUTER: outer_task<R>(ps, ty, task); break;
+      case BK_SEG:
+        if (ps.real)
+          seg_task<W, true, R>(B, ps, ty, task, L);
+        else
+          seg_task<W, false, R>(B, ps, ty, task, L);
+        break;
+      case BK_INNER: inner_task<R>(ps, ty, task, L.red); break;
+      case BK_RDM: rdm_task<R>(ps, ty, task, L.acc); break;
+      case BK_DGRAD: dgrad_task<R>(ps, ty, task, L.acc); break;
+      case BK_SUM: sum_task(ps); break;
+      default: break;
+    }
+    // publish this task's writes device-wide, then count it as finished
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(B.done + ps.inst, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Level-synchronous form: one launch runs every task of one pass level
+// (passes [p0, p1) of the queue, which never depend on each other); block b
+// runs task first(p0) + b.  Ordering between levels comes from the launches.
+template <int W, class R>
+__global__ __launch_bounds__(kBatchThreads) void k_batch_level(BatchDev B, int p0, int p1) {
+  extern __shared__ __align__(16) char smem[];
+  const BatchLds L = batch_lds_map(smem, B);
+  const int64_t t = B.passes[p0].first + (int64_t)blockIdx.x;
+  int lo = p0, hi = p1 - 1;  // last pass of the level whose first task <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (B.passes[mid].first <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const BPassDev ps = uniform_load(B.passes + lo);
+  const BTypeDev ty = uniform_load(B.types + ps.type);
+  const int task = (int)(t - ps.first);
+  if (task < 0 || task >= ps.n_tasks) return;
+  switch (ps.kind) {
+    case BK_TABLES: tables_task(ps, ty, task); break;
+    case BK_OUTER: outer_task<R>(ps, ty, task); break;
+    case BK_SEG:
+      if (ps.real)
+        seg_task<W, true, R>(B, ps, ty, task, L);
+      else
+        seg_task<W, false, R>(B, ps, ty, task, L);
+      break;
+    case BK_INNER: inner_task<R>(ps, ty, task, L.red); break;
+    case BK_RDM: rdm_task<R>(ps, ty, task, L.acc); break;
+    case BK_DGRAD: dgrad_task<R>(ps, ty, task, L.acc); break;
+    case BK_SUM: sum_task(ps); break;
+    default: break;
+  }
+}
+
+template <int W, class R>
+static void launch_level(const BatchDev& b, int p0, int p1, int64_t tasks, size_t lds, hipStream_t s) {
+  auto k = k_batch_level<W, R>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, kBatchMaxDynLds);
+    (void)hipGetLastError();
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k, dim3((unsigned)tasks), dim3(kBatchThreads), lds, s, b, p0, p1);
+}
+
+void batch_launch_level(bool c64, const BatchDev& b, int p0, int p1, int64_t tasks, size_t lds, hipStream_t s) {
+  if (c64)
+    launch_level<7, float>(b, p0, p1, tasks, lds, s);
+  else
+    launch_level<6, double>(b, p0, p1, tasks, lds, s);
+}
+
+template <int W, class R>
+static void launch_batch(const BatchDev& b, int blocks, int threads, size_t lds, hipStream_t s) {
+  auto k = k_batch<W, R>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, kBatchMaxDynLds);
+    (void)hipGetLastError();
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(threads), lds, s, b);
+}
+
+int batch_blocks_per_cu(bool c64, int threads, size_t lds) {
+  int n = 0;
+  hipError_t e;
+  if (lds > (size_t)kBatchMaxDynLds) return 0;
+  if (c64) {
+    (void)hipFuncSetAttribute((const void*)k_batch<7, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kBatchMaxDynLds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<7, float>, threads, lds);
+  } else {
+    (void)hipFuncSetAttribute((const void*)k_batch<6, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kBatchMaxDynLds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<6, double>, threads, lds);
+  }
+  (void)hipGetLastError();
+  return e == hipSuccess ? n : 0;
+}
+
+void batch_launch(bool c64, const BatchDev& b, int blocks, int threads, size_t lds, hipStream_t s) {
+  if (c64)
+    launch_batch<7, float>(b, blocks, threads, lds, s);
+  else
+    launch_batch<6, double>(b, blocks, threads, lds, s);
+}
+
+}  // namespace dev
+}  // namespace ffx

@@ -271,5 +271,64 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
 }
 
 
+// ---------------------------------------------------------------------------
+// a class of an LDS-resident row: load its members into registers, apply the
+// stage's rotations, store them back (segment passes and batched tasks)
+// ---------------------------------------------------------------------------
+// member offsets come four at a time from 16-byte-aligned LDS tables
+template <int K>
+__device__ __forceinline__ int pick(const int4& q) {
+  if constexpr ((K & 3) == 0) return q.x;
+  if constexpr ((K & 3) == 1) return q.y;
+  if constexpr ((K & 3) == 2) return q.z;
+  return q.w;
+}
+
+template <int W, int M, bool REAL, class R, int... K>
+__device__ __forceinline__ void lds_class(typename V2T<R>::type* __restrict__ row, int cbase, const int* mtl,
+                                          int moff, const RotLane<R>& rl, int nrot,
+                                          std::integer_sequence<int, K...>) {
+  using V = typename V2T<R>::type;
+  constexpr int C = sizeof...(K);
+  constexpr int Q = (C + 3) / 4;
+  V v[C];
+  {
+    int4 q[Q];
+    const int4* m4 = (const int4*)(mtl + moff);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) q[i] = m4[i];
+    ((v[K] = row[cbase + pick<K>(q[K >> 2])]), ...);
+  }
+  apply_rots_lane<W, M, REAL, R>(v, rl, nrot);
+  // member offsets are re-read from LDS rather than held in registers across
+  // the rotations: hiding the table offset from the optimizer forces the reload
+  {
+    int o = moff;
+    asm volatile("" : "+v"(o));
+    int4 q[Q];
+    const int4* m4 = (const int4*)(mtl + o);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) q[i] = m4[i];
+    ((row[cbase + pick<K>(q[K >> 2])] = v[K]), ...);
+  }
+}
+
+template <int W, bool REAL, class R, int M = 1>
+__device__ __forceinline__ void lds_m(int m, typename V2T<R>::type* row, int cbase, const int* mtl, int moff,
+                                      const RotLane<R>& rl, int nrot) {
+  if constexpr (M < W) {
+    if (m == M)
+      lds_class<W, M, REAL, R>(row, cbase, mtl, moff, rl, nrot, std::make_integer_sequence<int, cbinom(W, M)>{});
+    else
+      lds_m<W, REAL, R, M + 1>(m, row, cbase, mtl, moff, rl, nrot);
+  }
+}
+
+__device__ __forceinline__ int parity(uint32_t x) { return __builtin_popcount(x) & 1; }
+
+__device__ __forceinline__ zc128 zmul(zc128 a, zc128 b) {
+  return zc128{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
 }  // namespace dev
 }  // namespace ffx

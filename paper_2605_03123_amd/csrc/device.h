@@ -187,6 +187,91 @@ struct SegPassDev {
 };
 
 // LDS needed by a segment pass whose longest segment holds max_len amplitudes
+// ---------------------------------------------------------------------------
+// batched persistent launch: many independent sectors, each running a list of
+// passes; one kernel pulls tasks (blocks of rows or columns of one instance's
+// state) from a global queue in pass-level order, and a task starts only when
+// every task of its instance's earlier passes has finished.
+// ---------------------------------------------------------------------------
+enum BatchKind { BK_TABLES = 0, BK_OUTER = 1, BK_SEG = 2, BK_INNER = 3, BK_RDM = 4, BK_DGRAD = 5, BK_SUM = 6 };
+
+// one sector type (norb, n_alpha, n_beta) shared by instances
+struct BTypeDev {
+  int norb;
+  int n[2];
+  int pad;
+  int64_t dim[2];
+  const uint32_t* masks[2];
+  // per column spin cs: tasks of the layout whose columns are spin cs hold
+  // rows_per_task[cs] rows; window tables replicated over those rows
+  int rows_per_task[2];
+  const SegWinDev* win[2];
+  const int* mt_all[2];
+  int n_mt_all[2];
+};
+
+// one table of a TABLES pass: a diagonal function's per-string tables (A over
+// alpha strings, B over beta strings), or one phase stage's column factors
+struct BTableDev {
+  int kind;  // 0: diagonal tables, 1: column factors
+  int spin;  // column factors: the strings' spin
+  DiagSpecDev spec;
+  double* A;
+  double* B;
+  const double* cB;
+  double scale;
+  const double* delta;
+  uint32_t sign;
+  int pad;
+  double* out;
+};
+
+struct BPassDev {
+  int kind;
+  int type;      // index into the sector types
+  int inst;      // instance (dependency counter)
+  int layout;    // 0: rows are alpha strings, 1: rows are beta strings (columns of the state)
+  int mode;      // SEG: SegMode
+  int real;      // SEG: all rotations real
+  int n_stages;
+  int n_tasks;
+  int half;      // SEG: tasks >= half use (src2, dst2) (two states, same stages); else n_tasks
+  int need;      // finished tasks of this instance required before any task of this pass
+  int width;     // SUM: doubles per partial vector; others: doubles of partials per task
+  int n_sum;     // SUM: number of partial vectors
+  int64_t first;  // queue index of the first task
+  const StageDev* stages;
+  const void* src;
+  void* dst;
+  const void* src2;
+  void* dst2;
+  double* partials;
+  double* out;
+  const BTableDev* tables;
+  const double* oa;  // OUTER: complex per alpha string
+  const double* ob;  // OUTER: complex per beta string
+};
+
+struct BatchDev {
+  const BTypeDev* types;
+  const BPassDev* passes;
+  int n_passes;
+  int pad;
+  int64_t n_tasks;
+  unsigned int* next;     // queue counter
+  unsigned int* done;     // per instance: finished tasks
+  unsigned int* abort;    // set when a wait exceeds its bound
+  int lds_row_bytes;      // LDS bytes reserved for the rows of one task
+  int max_mt;             // ints reserved for member-offset tables
+};
+
+// LDS bytes of the batched kernel and its launch.  blocks: resident blocks to start.
+size_t batch_lds(bool c64, int lds_row_bytes, int max_mt, int norb_max);
+int batch_blocks_per_cu(bool c64, int threads, size_t lds);
+void batch_launch(bool c64, const BatchDev& b, int blocks, int threads, size_t lds, hipStream_t s);
+// level-synchronous form: the tasks of passes [p0, p1) (one level), one block each
+void batch_launch_level(bool c64, const BatchDev& b, int p0, int p1, int64_t tasks, size_t lds, hipStream_t s);
+
 size_t seg_pass_lds(bool c64, int max_len, int max_mt);
 // blocks = n_rows * n_seg; partials (if any stage reduces) get one entry per block
 void seg_pass(bool c64, bool real, int W, const SegPassDev& p, int block_threads, size_t lds_bytes,

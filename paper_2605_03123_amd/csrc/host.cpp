@@ -275,6 +275,43 @@ SegWindowTable build_seg_window(const std::vector<uint64_t>& seg, int wt, int a,
   return t;
 }
 
+SegWindowTable replicate_seg_window(const SegWindowTable& t, int w, int R, int row_len) {
+  SegWindowTable o;
+  o.nl1 = t.nl1;
+  o.mt = t.mt;
+  std::map<int, std::vector<int>> by_m;
+  for (int r = 0; r < R; ++r)
+    for (size_t ch = 0; ch < t.chunk_m.size(); ++ch)
+      for (int j = 0; j < 64; ++j) {
+        const int c = t.code[ch * 64 + j];
+        if (c < 0) continue;
+        const int64_t cbase = (int64_t)(c >> 5) + (int64_t)r * row_len;
+        if (cbase >= (1ll << 26)) throw Error(FFX_EUNSUPPORTED, "replicated window table too large");
+        by_m[t.chunk_m[ch]].push_back((int)((cbase << 5) | (c & 31)));
+      }
+  struct Chunk {
+    int m;
+    double cost;
+    std::vector<int> codes;
+  };
+  std::vector<Chunk> chunks;
+  for (auto& kv : by_m) {
+    const int m = kv.first;
+    const double cost = (double)binom(w, m) * (2.0 + (double)binom(w - 2, m - 1));
+    for (size_t i = 0; i < kv.second.size(); i += 64) {
+      Chunk ch{m, cost, {}};
+      for (size_t j = i; j < std::min(i + 64, kv.second.size()); ++j) ch.codes.push_back(kv.second[j]);
+      chunks.push_back(std::move(ch));
+    }
+  }
+  std::stable_sort(chunks.begin(), chunks.end(), [](const Chunk& x, const Chunk& y) { return x.cost > y.cost; });
+  for (auto& ch : chunks) {
+    o.chunk_m.push_back(ch.m);
+    for (int j = 0; j < 64; ++j) o.code.push_back(j < (int)ch.codes.size() ? ch.codes[j] : -1);
+  }
+  return o;
+}
+
 std::vector<cd> matmul(int n, const std::vector<cd>& A, const std::vector<cd>& B) {
   std::vector<cd> C((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i)

@@ -115,6 +115,10 @@ struct ffx_plan_s {
   // (programs run one after another on the stream).  Growing frees the old
   // arena, so a driver that compiles several programs before running them must
   // stay within the initial size (kArenaSlots states' worth of string tables).
+  // when set, compile_program takes its table arena from this hook instead
+  double* (*arena_hook)(void* ctx, size_t doubles) = nullptr;
+  void* arena_ctx = nullptr;
+  int max_stage_rots = ffx::dev::kMaxStageRots;  // Givens rotations per stage (fusion depth)
   static constexpr int kArenaSlots = 64;
   double* arena_for(size_t doubles, hipStream_t s) {
     if (doubles > arena_doubles) {
@@ -151,6 +155,9 @@ struct Upload {
   size_t off = 0;
   hipStream_t s;
 
+  // over caller buffers (no slot event); h == nullptr only measures the size
+  Upload(char* host, char* dev, size_t capacity, hipStream_t stream)
+      : P(nullptr), slot(-1), h(host), d(dev), cap(capacity), s(stream) {}
   Upload(ffx_plan_s* plan, hipStream_t stream) : P(plan), s(stream) {
     slot = P->next_slot;
     P->next_slot = (P->next_slot + 1) % ffx_plan_s::kSlots;
@@ -164,15 +171,17 @@ struct Upload {
     off = (off + 15) & ~(size_t)15;
     size_t bytes = count * sizeof(T);
     if (off + bytes > cap) throw Error(FFX_EUNSUPPORTED, "parameter block exceeds the upload slot");
-    if (bytes) std::memcpy(h + off, src, bytes);
+    if (bytes && h) std::memcpy(h + off, src, bytes);
     const T* r = (const T*)(d + off);
     off += bytes;
     return r;
   }
   void commit() {
-    if (off) HIPCHK(hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, s));
+    if (off && h) HIPCHK(hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, s));
   }
-  ~Upload() { (void)hipEventRecord(P->ev[slot], s); }
+  ~Upload() {
+    if (P) (void)hipEventRecord(P->ev[slot], s);
+  }
 };
 
 // ---------------------------------------------------------------------------

@@ -81,7 +81,8 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
   size_t n_phase = 2;
   for (const ProgOp& op : prog.ops) n_phase += (op.kind == ProgOp::PHASE || op.kind == ProgOp::ROT) ? 1 : 0;
   const size_t dmax = (size_t)std::max(da, db);
-  double* arena = P.arena_for(prog.diags.size() * (size_t)(da + db) + n_phase * 2 * dmax, s);
+  const size_t arena_need = prog.diags.size() * (size_t)(da + db) + n_phase * 2 * dmax;
+  double* arena = P.arena_hook ? P.arena_hook(P.arena_ctx, arena_need) : P.arena_for(arena_need, s);
   size_t arena_off = prog.diags.size() * (size_t)(da + db);
   std::vector<const double*> Cd(prog.diags.size(), nullptr), CTd(prog.diags.size(), nullptr);
   for (size_t i = 0; i < prog.diags.size(); ++i) {
@@ -146,7 +147,7 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
     }
     if (cb.B || cb.delta || cb.sign) {
       const size_t n = (size_t)P.dim[cs];
-      if (arena_off + 2 * n > P.arena_doubles) throw Error(FFX_EUNSUPPORTED, "diagonal table arena exhausted");
+      if (arena_off + 2 * n > arena_need) throw Error(FFX_EUNSUPPORTED, "diagonal table arena exhausted");
       cb.out = arena + arena_off;
       arena_off += 2 * n;
       c.colfs.push_back(cb);
@@ -239,7 +240,8 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
           if (best.empty()) break;
           // a stage's rotations are spread over the 64 lanes of a wave; the
           // taken list is in dependency order, so any prefix is a valid stage
-          if (best.size() > (size_t)dev::kMaxStageRots) best.resize(dev::kMaxStageRots);
+          const size_t cap = (size_t)std::max(1, std::min(P.max_stage_rots, dev::kMaxStageRots));
+          if (best.size() > cap) best.resize(cap);
           std::vector<dev::RotDev> buf;
           for (int i : best) {
             const Givens& g = d.rots[i];

@@ -357,3 +357,96 @@ class LUCJEnergy(torch.autograd.Function):
     def backward(ctx, g_out):
         (g,) = ctx.saved_tensors
         return g_out * g, None, None, None, None, None, None
+
+
+# ---------------------------------------------------------------------------
+# batched LUCJ energy + adjoint gradient (one persistent launch)
+# ---------------------------------------------------------------------------
+_batch_create = _sig("ffx_batch_create", ctypes.c_int,
+                     [ctypes.POINTER(_vp), ctypes.c_int, _c_int_p, _c_int_p, _c_int_p, ctypes.c_int, ctypes.c_int])
+_batch_destroy = _sig("ffx_batch_destroy", ctypes.c_int, [_vp])
+_batch_ws = _sig("ffx_batch_workspace_bytes", ctypes.c_int64, [_vp])
+_batch_eg = _sig("ffx_batch_lucj_energy_grad", ctypes.c_int,
+                 [_vp, ctypes.POINTER(_LUCJ), ctypes.POINTER(_DFHam), _c_double_p, _c_double_p, _vp, _vp])
+_batch_tune = _sig("ffx_batch_tune", ctypes.c_int,
+                   [_vp, ctypes.POINTER(_LUCJ), ctypes.POINTER(_DFHam), _vp, _vp, _c_int_p, _c_int_p])
+_batch_info = _sig("ffx_batch_info", ctypes.c_int,
+                   [_vp, _c_int_p, _c_int_p, _c_int_p, ctypes.POINTER(ctypes.c_int64)])
+
+
+class Batch:
+    """Many independent sectors [(norb, (n_alpha, n_beta)), ...] run together.
+
+    lucj_energy_grad(params_list, hams, n_reps) returns (energies, grads):
+    every instance's LUCJ forward pass, costate, energy and reverse sweep run
+    in one persistent kernel launch.
+    """
+
+    def __init__(self, sectors, dtype=torch.complex64, device=0):
+        self.sectors = [(int(n), (int(a), int(b))) for n, (a, b) in sectors]
+        self.dtype = dtype
+        self.device = device
+        k = len(self.sectors)
+        norb = (ctypes.c_int * k)(*[s[0] for s in self.sectors])
+        na = (ctypes.c_int * k)(*[s[1][0] for s in self.sectors])
+        nb = (ctypes.c_int * k)(*[s[1][1] for s in self.sectors])
+        code = FFX_C128 if dtype == torch.complex128 else FFX_C64
+        h = _vp()
+        torch.cuda.init()
+        _check(_batch_create(ctypes.byref(h), k, norb, na, nb, code, device))
+        self._h = h
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _batch_destroy(h)
+
+    def workspace(self) -> torch.Tensor:
+        n = int(_batch_ws(self._h))
+        if self._ws is None or self._ws.numel() < n:
+            self._ws = torch.empty(n, dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def _args(self, params_list, hams, n_reps):
+        k = len(self.sectors)
+        if len(params_list) != k or len(hams) != k:
+            raise ValueError("one parameter vector and one Hamiltonian per instance")
+        ops = (_LUCJ * k)()
+        hs = (_DFHam * k)()
+        keep = []
+        for i, ((norb, _), p, ham) in enumerate(zip(self.sectors, params_list, hams)):
+            s, kp = _lucj_struct(p, norb, n_reps)
+            d, kh = _df_struct(ham, norb)
+            ops[i] = s
+            hs[i] = d
+            keep += [kp, kh]
+        return ops, hs, keep
+
+    def lucj_energy_grad(self, params_list, hams, n_reps: int):
+        ops, hs, keep = self._args(params_list, hams, n_reps)
+        k = len(self.sectors)
+        sizes = [int(_lucj_np(n, n_reps)) for n, _ in self.sectors]
+        energies = np.zeros(k)
+        grads = np.zeros(sum(sizes))
+        ws = self.workspace()
+        _check(_batch_eg(self._h, ops, hs, _dptr(energies), _dptr(grads), _vp(ws.data_ptr()),
+                         _stream(ws.device)))
+        out, off = [], 0
+        for n in sizes:
+            out.append(grads[off:off + n].copy())
+            off += n
+        return energies, out
+
+    def tune(self, params_list, hams, n_reps: int):
+        ops, hs, keep = self._args(params_list, hams, n_reps)
+        t, r = ctypes.c_int(), ctypes.c_int()
+        ws = self.workspace()
+        _check(_batch_tune(self._h, ops, hs, _vp(ws.data_ptr()), _stream(ws.device), ctypes.byref(t),
+                           ctypes.byref(r)))
+        return t.value, r.value
+
+    def info(self) -> dict:
+        t, r, b, lds = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+        _check(_batch_info(self._h, ctypes.byref(t), ctypes.byref(r), ctypes.byref(b), ctypes.byref(lds)))
+        return {"target_elems": t.value, "stage_rots": r.value, "blocks": b.value, "lds_bytes": lds.value}

@@ -162,9 +162,9 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
 /* ---------------------------------------------------------------------------
    Batched LUCJ energy + adjoint gradient over many independent sectors of
    uneven size (each instance its own norb, (n_alpha, n_beta), LUCJ
-   parameters and DF Hamiltonian), all of them in ONE persistent kernel
-   launch (Sec. 4.5.1 ansatz, Sec. 4.2 energy; the batching itself is this
-   library's extension).
+   parameters and DF Hamiltonian), all of them together: one kernel launch
+   per pass level, shared by every instance (Sec. 4.5.1 ansatz, Sec. 4.2
+   energy; the batching itself is this library's extension).
    A batch object owns one plan per distinct sector type and the class tables
    of the batched kernel.  Limits: 8 <= norb <= 16 for complex64 and
    6 <= norb <= 16 for complex128, and one row of every sector must fit in LDS
@@ -184,9 +184,11 @@ int64_t ffx_batch_workspace_bytes(ffx_batch batch);
    read during the call).  energies: n_inst doubles; grads: the instances'
    gradients back to back (ffx_lucj_n_params(norb_i, n_reps_i) each, in
    instance order).  Runs every instance's forward pass, costate, energy and
-   reverse sweep in one launch on `stream`, then synchronizes.  A kernel
-   whose dependency waits exceed their bound stops early and the call
-   returns FFX_EDEVICE. */
+   reverse sweep on `stream`, then synchronizes: the passes of all instances
+   are grouped by level (pass k of every instance), and each level is one
+   kernel launch whose blocks run its tasks (blocks of rows or columns of one
+   instance's state).  A single persistent launch over a task queue with
+   per-instance dependency counters is built but switched off. */
 int ffx_batch_lucj_energy_grad(ffx_batch batch, const ffx_lucj* ops, const ffx_df_ham* hams,
                                double* energies, double* grads, void* workspace, void* stream);
 
@@ -197,6 +199,12 @@ int ffx_batch_lucj_energy_grad(ffx_batch batch, const ffx_lucj* ops, const ffx_d
    elements and stage depth to *target_elems and *stage_rots (may be NULL). */
 int ffx_batch_tune(ffx_batch batch, const ffx_lucj* ops, const ffx_df_ham* hams, void* workspace,
                    void* stream, int* target_elems, int* stage_rots);
+
+/* Timing of the last ffx_batch_lucj_energy_grad: device time from the first to
+   the last launch (HIP events on the call's stream), wall time of the whole
+   call (host preparation, launches, result copy, gradient chain rules) and the
+   number of kernel launches. */
+int ffx_batch_timing(ffx_batch batch, double* device_ms, double* call_ms, int* launches);
 
 /* Configuration in use (for reports): target elements per task, stage depth,
    resident blocks of the persistent launch, and its LDS bytes per block. */

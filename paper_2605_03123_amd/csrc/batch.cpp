@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <map>
 #include <memory>
 #include <numeric>
@@ -41,6 +42,10 @@ struct ffx_batch_s {
   // dependency counters) instead of one launch per pass level.  Off: its last
   // run on the GPU did not complete and the cause is not established.
   bool persistent = false;
+  // timing of the last call
+  double last_device_ms = 0, last_call_ms = 0;
+  int last_launches = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
   // per-call buffers, grown on demand
   char* h_up = nullptr;
   char* d_up = nullptr;
@@ -61,6 +66,8 @@ struct ffx_batch_s {
     if (arena) (void)hipFree(arena);
     if (scratch) (void)hipFree(scratch);
     if (counters) (void)hipFree(counters);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
     for (ffx_plan p : plans) ffx_plan_destroy(p);
   }
   void free_tables() {
@@ -86,6 +93,11 @@ struct ffx_batch_s {
 namespace {
 
 int kernel_window(bool c64) { return dev::max_window(c64); }
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// rows of a transition-matrix task: half those of a segment task (two states in LDS)
+int64_t rdm_rows(int seg_rows) { return seg_rows > 1 ? seg_rows / 2 : 1; }
 
 // class tables of the batched kernel for the current target: rows per task
 // per layout, replicated window tables, LDS size and resident blocks
@@ -124,11 +136,37 @@ void build_tables(ffx_batch_s& b) {
         mt_all.insert(mt_all.end(), rep.mt.begin(), rep.mt.end());
         wins.push_back(wd);
       }
+      // single excitations of spin cs per (p, q)
+      {
+        const int N = P.norb;
+        std::vector<int> exc, off;
+        std::map<uint64_t, int> addr;
+        for (size_t k = 0; k < P.str[cs].size(); ++k) addr[P.str[cs][k]] = (int)k;
+        if (P.str[cs].size() > (1u << 14)) throw Error(FFX_EUNSUPPORTED, "batched sector too large");
+        for (int p = 0; p < N; ++p)
+          for (int q = 0; q < N; ++q) {
+            off.push_back((int)exc.size());
+            for (size_t k = 0; k < P.str[cs].size(); ++k) {
+              const uint64_t I = P.str[cs][k];
+              if (!((I >> q) & 1) || (p != q && ((I >> p) & 1))) continue;
+              const uint64_t J = (I & ~(1ull << q)) | (1ull << p);
+              const int lo = std::min(p, q), hi = std::max(p, q);
+              const uint64_t mid = hi - lo > 1 ? (I >> (lo + 1)) & ((1ull << (hi - lo - 1)) - 1) : 0;
+              const int odd = __builtin_popcountll(mid) & 1;
+              exc.push_back((int)k | (addr.at(J) << 14) | (odd << 28));
+            }
+          }
+        off.push_back((int)exc.size());
+        t.exc[cs] = b.upload_table(exc);
+        t.exc_off[cs] = b.upload_table(off);
+      }
       t.win[cs] = b.upload_table(wins);
       t.mt_all[cs] = b.upload_table(mt_all);
       t.n_mt_all[cs] = (int)mt_all.size();
       b.max_mt = std::max(b.max_mt, (int)mt_all.size());
-      const size_t rb = ((size_t)R * (size_t)len * b.elem() + 15) & ~(size_t)15;
+      // a segment task holds R rows; a transition-matrix task holds rdm_rows(R) rows of two states
+      const size_t rows_held = std::max<size_t>((size_t)R, 2 * (size_t)rdm_rows(R));
+      const size_t rb = (rows_held * (size_t)len * b.elem() + 15) & ~(size_t)15;
       b.lds_row_bytes = std::max<int>(b.lds_row_bytes, (int)rb);
     }
   }
@@ -155,7 +193,7 @@ double* arena_hook(void* ctx, size_t doubles) {
   return p ? p : (double*)(uintptr_t)(256 + 8 * b.arena_used);  // measuring: any distinct address
 }
 
-int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
 
 // the passes of one instance, in order, with their local dependency counts
 struct InstPasses {
@@ -245,9 +283,11 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
     const int N = P.norb, NN = N * N, R = ib[i].G->L.R;
     const int64_t tr0 = ceil_div(P.dim[0], t.rows_per_task[1]);  // layout 0 tasks
     const int64_t tr1 = ceil_div(P.dim[1], t.rows_per_task[0]);  // layout 1 tasks
+    const int64_t td0 = ceil_div(P.dim[0], rdm_rows(t.rows_per_task[1]));  // transition-matrix tasks
+    const int64_t td1 = ceil_div(P.dim[1], rdm_rows(t.rows_per_task[0]));
     ib[i].res_off = res_total;
     res_total += 2 + (size_t)R * (4 * NN + 2 * N - 1);
-    ib[i].part_need = (size_t)std::max<int64_t>({(tr0 + tr1) * 2 * NN, tr0 * (2 * N - 1), tr0 * 2});
+    ib[i].part_need = (size_t)std::max<int64_t>({(td0 + td1) * 2 * NN, tr0 * (2 * N - 1), tr0 * 2});
     ib[i].part_off = part_total;
     part_total += ib[i].part_need;
   }
@@ -325,6 +365,8 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
     const int N = P.norb, NN = N * N, R = G.L.R;
     const int64_t tr0 = ceil_div(P.dim[0], t.rows_per_task[1]);
     const int64_t tr1 = ceil_div(P.dim[1], t.rows_per_task[0]);
+    const int64_t td0 = ceil_div(P.dim[0], rdm_rows(t.rows_per_task[1]));
+    const int64_t td1 = ceil_div(P.dim[1], rdm_rows(t.rows_per_task[0]));
     void* psi = ws + ws_off[i];
     void* lam = ws + ws_off[i] + state_bytes(b, i);
     void* tmp = ws + ws_off[i] + 2 * state_bytes(b, i);
@@ -454,14 +496,14 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
       for (int layout = 0; layout < 2; ++layout) {
         dev::BPassDev p = base(dev::BK_RDM);
         p.layout = layout;
-        p.n_tasks = (int)(layout == 0 ? tr0 : tr1);
+        p.n_tasks = (int)(layout == 0 ? td0 : td1);
         p.src = lam;
         p.src2 = psi;
-        p.partials = part + (layout == 0 ? 0 : tr0 * 2 * NN);
+        p.partials = part + (layout == 0 ? 0 : td0 * 2 * NN);
         p.width = 2 * NN;
         Q.add(p);
       }
-      add_sum(out, 2 * NN, (int)(tr0 + tr1));
+      add_sum(out, 2 * NN, (int)(td0 + td1));
     };
     for (int k = R - 1; k >= 0; --k) {
       double* Tb = res + 2 + (size_t)k * (4 * NN + 2 * N - 1);
@@ -526,16 +568,15 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
   bd.done = b.counters + 4;
   bd.lds_row_bytes = b.lds_row_bytes;
   bd.max_mt = b.max_mt;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (kernel_ms) {
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    HIPCHK(hipEventRecord(e0, s));
-  }
+  if (!b.ev[0]) HIPCHK(hipEventCreate(&b.ev[0]));
+  if (!b.ev[1]) HIPCHK(hipEventCreate(&b.ev[1]));
+  HIPCHK(hipEventRecord(b.ev[0], s));
+  int launches = 0;
   if (b.persistent) {
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(b.blocks, first));
     dev::batch_launch(b.c64, bd, blocks, 256, b.lds, s);
     check_launch();
+    launches = 1;
   } else {
     for (size_t lv = 0; lv + 1 < level_start.size(); ++lv) {
       const int p0 = level_start[lv], p1 = level_start[lv + 1];
@@ -543,19 +584,20 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
       const int64_t tasks = (p1 < (int)all.size() ? all[p1].first : first) - all[p0].first;
       dev::batch_launch_level(b.c64, bd, p0, p1, tasks, b.lds, s);
       check_launch();
+      ++launches;
     }
   }
-  if (kernel_ms) HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventRecord(b.ev[1], s));
   std::vector<double> hres(res_total);
   unsigned flags[4] = {0, 0, 0, 0};
   HIPCHK(hipMemcpyAsync(hres.data(), results, res_total * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(flags, b.counters, sizeof(flags), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (kernel_ms) {
-    HIPCHK(hipEventElapsedTime(kernel_ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-  }
+  float dms = 0;
+  HIPCHK(hipEventElapsedTime(&dms, b.ev[0], b.ev[1]));
+  if (kernel_ms) *kernel_ms = dms;
+  b.last_device_ms = dms;
+  b.last_launches = launches;
   if (flags[1]) throw Error(FFX_EDEVICE, "batched launch stopped: a dependency wait exceeded its bound");
   // ---- host: energies and gradient chain rules --------------------------
   size_t goff = 0;
@@ -636,7 +678,9 @@ int ffx_batch_lucj_energy_grad(ffx_batch batch, const ffx_lucj* ops, const ffx_d
   return guard([&] {
     if (!batch || !ops || !hams || !energies || !grads || !workspace) throw Error(FFX_EINVAL, "null pointer");
     HIPCHK(hipSetDevice(batch->device));
+    const auto t0 = std::chrono::steady_clock::now();
     run_batch(*batch, ops, hams, energies, grads, workspace, (hipStream_t)stream, nullptr);
+    batch->last_call_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   });
 }
 
@@ -676,6 +720,15 @@ int ffx_batch_tune(ffx_batch batch, const ffx_lucj* ops, const ffx_df_ham* hams,
     build_tables(b);
     if (target_elems) *target_elems = best_t;
     if (stage_rots) *stage_rots = best_r;
+  });
+}
+
+int ffx_batch_timing(ffx_batch batch, double* device_ms, double* call_ms, int* launches) {
+  return guard([&] {
+    if (!batch) throw Error(FFX_EINVAL, "null batch");
+    if (device_ms) *device_ms = batch->last_device_ms;
+    if (call_ms) *call_ms = batch->last_call_ms;
+    if (launches) *launches = batch->last_launches;
   });
 }
 

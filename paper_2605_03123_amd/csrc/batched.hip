@@ -1,20 +1,20 @@
-// Batched persistent launch (gfx950): many independent sectors of uneven
-// size, each running its own list of passes (LUCJ forward, costate, energy,
-// reverse sweep with transition one-body matrices), in ONE kernel launch.
+// Batched execution (gfx950): many independent sectors of uneven size, each
+// running its own list of passes (LUCJ forward, costate, energy, reverse sweep
+// with transition one-body matrices), run together.
 //
-// Work is a global queue of tasks.  A task is a block of consecutive rows (or
-// of consecutive columns: the rows of the transposed layout) of one instance's
-// state, or a small per-instance job (tables, fixed-order sums).  Tasks are
-// queued pass level by pass level across instances; a block takes the next
-// task with an atomic counter and, before running it, waits until every task
-// of the same instance's earlier passes has finished (a per-instance counter
-// published with agent-scope release / acquire, so writes made on other XCDs
-// are visible).  A task only ever waits for tasks queued before it, which were
-// taken by blocks that are already running, so the queue drains whatever the
-// number of resident blocks.  Every wait is bounded: past the bound the block
-// raises the abort flag and every block leaves at its next task.  Waiting
-// blocks poll with relaxed loads and sleep between polls; one acquire fence per
-// task makes the awaited data visible.
+// A task is a block of consecutive rows (or of consecutive columns: the rows
+// of the transposed layout) of one instance's state, or a small per-instance
+// job (tables, fixed-order sums).  Pass k of every instance forms level k; the
+// passes of one level never depend on each other.
+//
+// k_batch_level runs one level per launch, one block per task: this is the
+// form in use.  k_batch is the single persistent launch over the same queue:
+// blocks take tasks with an atomic counter and wait, before each task, until
+// every task of the same instance's earlier passes has finished
+// (per-instance counters, relaxed polling with sleeps, one agent-scope
+// acquire per task, a wall-clock bound after which every block leaves).  It is
+// built but not launched: its runs on the GPU did not complete and the cause
+// is not established.
 //
 // Givens and diagonal stages run on the task's rows held back to back in LDS,
 // with the class tables of one row replicated over the rows (see
@@ -193,57 +193,80 @@ __device__ __forceinline__ void sum_task(const BPassDev& ps) {
 }
 
 // ---------------------------------------------------------------------------
-// transition one-body matrix of the row spin of a layout, one wave per row:
-// T[p][q] += sign * sum_k conj(lam[J, k]) psi[I, k], J = I - q + p
+// transition one-body matrix of the column spin of a layout, from a block of
+// rows (or columns) of lam and psi staged in LDS:
+//   T[p][q] = sum_rows sum_{I -> J} sign conj(lam_row[J]) psi_row[I]
+// over the listed excitations J = I - q + p; waves own (p, q) pairs and lanes
+// take list entries, so every sum has a fixed order.  Tasks hold half the rows
+// of a segment task (two states share the LDS rows).
 // ---------------------------------------------------------------------------
-template <class R>
-__device__ __forceinline__ void rdm_task(const BPassDev& ps, const BTypeDev& ty, int task, double* acc) {
+__device__ __forceinline__ int rdm_rows_per_task(int seg_rows) { return seg_rows > 1 ? seg_rows / 2 : 1; }
+
+template <class R, int CS>
+__device__ __forceinline__ void rdm_task_cs(const BPassDev& ps, const BTypeDev& ty, int task, const BatchLds& L) {
   using V = typename V2T<R>::type;
-  const int cs = ps.layout == 0 ? 1 : 0, rs = 1 - cs;
+  constexpr int cs = CS, rs = 1 - CS;
   const int N = ty.norb, NN = N * N;
   const int64_t nrows = pick2(ty.dim, rs), len = pick2(ty.dim, cs), ncols_state = ty.dim[1];
-  const int RR = pick2(ty.rows_per_task, cs);
+  const int RR = rdm_rows_per_task(pick2(ty.rows_per_task, cs));
   const int64_t r0 = (int64_t)task * RR;
   const int nr = (int)std::min<int64_t>(RR, nrows - r0);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int64_t nel = (int64_t)nr * len;
+  const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nthr >> 6;
+  V* bl = (V*)L.rows;
+  V* bp = bl + (int64_t)RR * len;
   const V* lam = (const V*)ps.src;
   const V* psi = (const V*)ps.src2;
-  double* T = acc + wave * 2 * NN;
-  for (int i = threadIdx.x; i < 4 * 2 * NN; i += blockDim.x) acc[i] = 0.0;
+  if (ps.layout == 0) {
+    for (int64_t x = tid; x < nel; x += nthr) {
+      bl[x] = lam[r0 * len + x];
+      bp[x] = psi[r0 * len + x];
+    }
+  } else {
+    for (int64_t x = tid; x < nel; x += nthr) {
+      const int64_t k = x / nr, r = x - k * nr;
+      bl[r * len + k] = lam[k * ncols_state + r0 + r];
+      bp[r * len + k] = psi[k * ncols_state + r0 + r];
+    }
+  }
   __syncthreads();
-  for (int r = wave; r < nr; r += nw) {
-    const int64_t row = r0 + r;
-    const uint32_t I = pick2(ty.masks, rs)[row];
-    for (int p = 0; p < N; ++p)
-      for (int q = 0; q < N; ++q) {
-        if (!((I >> q) & 1) || (p != q && ((I >> p) & 1))) continue;
-        const uint32_t J = (I & ~(1u << q)) | (1u << p);
-        const int lo = p < q ? p : q, hi = p < q ? q : p;
-        const uint32_t between = (hi - lo > 1) ? (I >> (lo + 1)) & ((1u << (hi - lo - 1)) - 1) : 0u;
-        const double sign = (__builtin_popcount(between) & 1) ? -1.0 : 1.0;
-        const int64_t jrow = colex_rank(J);
-        double re = 0, im = 0;
-        for (int64_t k = lane; k < len; k += 64) {
-          const V a = lam[lay_index(ps.layout, jrow, k, ncols_state)];
-          const V b = psi[lay_index(ps.layout, row, k, ncols_state)];
-          const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
-          re += ax * bx + ay * by;
-          im += ax * by - ay * bx;
-        }
-        re = wave_sum(re);
-        im = wave_sum(im);
-        if (lane == 0) {
-          T[2 * (p * N + q)] += sign * re;
-          T[2 * (p * N + q) + 1] += sign * im;
-        }
+  const int* exc = ty.exc[cs];
+  const int* off = ty.exc_off[cs];
+  for (int pq = wave; pq < NN; pq += nw) {
+    const int beg = off[pq], end = off[pq + 1];
+    double re = 0, im = 0;
+    for (int e = beg + lane; e < end; e += 64) {
+      const int v = exc[e];
+      const int i = v & 0x3fff, j = (v >> 14) & 0x3fff;
+      double sr = 0, si = 0;
+      for (int r = 0; r < nr; ++r) {
+        const V a = bl[(int64_t)r * len + j], b = bp[(int64_t)r * len + i];
+        const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
+        sr += ax * bx + ay * by;
+        si += ax * by - ay * bx;
       }
+      if ((v >> 28) & 1) {
+        sr = -sr;
+        si = -si;
+      }
+      re += sr;
+      im += si;
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) {
+      ps.partials[(int64_t)task * 2 * NN + 2 * pq] = re;
+      ps.partials[(int64_t)task * 2 * NN + 2 * pq + 1] = im;
+    }
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < 2 * NN; i += blockDim.x) {
-    double t = 0;
-    for (int w = 0; w < nw; ++w) t += acc[w * 2 * NN + i];
-    ps.partials[(int64_t)task * 2 * NN + i] = t;
-  }
+}
+
+template <class R>
+__device__ __forceinline__ void rdm_task(const BPassDev& ps, const BTypeDev& ty, int task, const BatchLds& L) {
+  if (ps.layout == 0)
+    rdm_task_cs<R, 1>(ps, ty, task, L);
+  else
+    rdm_task_cs<R, 0>(ps, ty, task, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -525,7 +548,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchDev B) {
           seg_task<W, false, R>(B, ps, ty, task, L);
         break;
       case BK_INNER: inner_task<R>(ps, ty, task, L.red); break;
-      case BK_RDM: rdm_task<R>(ps, ty, task, L.acc); break;
+      case BK_RDM: rdm_task<R>(ps, ty, task, L); break;
       case BK_DGRAD: dgrad_task<R>(ps, ty, task, L.acc); break;
       case BK_SUM: sum_task(ps); break;
       default: break;
@@ -567,7 +590,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_level(BatchDev B, int p
         seg_task<W, false, R>(B, ps, ty, task, L);
       break;
     case BK_INNER: inner_task<R>(ps, ty, task, L.red); break;
-    case BK_RDM: rdm_task<R>(ps, ty, task, L.acc); break;
+    case BK_RDM: rdm_task<R>(ps, ty, task, L); break;
     case BK_DGRAD: dgrad_task<R>(ps, ty, task, L.acc); break;
     case BK_SUM: sum_task(ps); break;
     default: break;

@@ -208,6 +208,12 @@ struct BTypeDev {
   const SegWinDev* win[2];
   const int* mt_all[2];
   int n_mt_all[2];
+  // per string spin s: single excitations J = I - q + p (q in I; p not in I or
+  // p == q) listed per pair (p, q): exc[s][exc_off[s][p * norb + q] ...] =
+  // i | (j << 14) | (odd << 28), odd = parity of the occupied orbitals strictly
+  // between p and q
+  const int* exc[2];
+  const int* exc_off[2];
 };
 
 // one table of a TABLES pass: a diagonal function's per-string tables (A over

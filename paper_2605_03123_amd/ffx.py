@@ -370,6 +370,8 @@ _batch_eg = _sig("ffx_batch_lucj_energy_grad", ctypes.c_int,
                  [_vp, ctypes.POINTER(_LUCJ), ctypes.POINTER(_DFHam), _c_double_p, _c_double_p, _vp, _vp])
 _batch_tune = _sig("ffx_batch_tune", ctypes.c_int,
                    [_vp, ctypes.POINTER(_LUCJ), ctypes.POINTER(_DFHam), _vp, _vp, _c_int_p, _c_int_p])
+_batch_timing = _sig("ffx_batch_timing", ctypes.c_int,
+                     [_vp, _c_double_p, _c_double_p, _c_int_p])
 _batch_info = _sig("ffx_batch_info", ctypes.c_int,
                    [_vp, _c_int_p, _c_int_p, _c_int_p, ctypes.POINTER(ctypes.c_int64)])
 
@@ -379,7 +381,7 @@ class Batch:
 
     lucj_energy_grad(params_list, hams, n_reps) returns (energies, grads):
     every instance's LUCJ forward pass, costate, energy and reverse sweep run
-    in one persistent kernel launch.
+    together, one kernel launch per pass level shared by all instances.
     """
 
     def __init__(self, sectors, dtype=torch.complex64, device=0):
@@ -399,7 +401,7 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _batch_destroy is not None:  # module globals may be gone at interpreter exit
             _batch_destroy(h)
 
     def workspace(self) -> torch.Tensor:
@@ -445,6 +447,12 @@ class Batch:
         _check(_batch_tune(self._h, ops, hs, _vp(ws.data_ptr()), _stream(ws.device), ctypes.byref(t),
                            ctypes.byref(r)))
         return t.value, r.value
+
+    def timing(self) -> dict:
+        """Device ms of the last call's launches, wall ms of the whole call, number of launches."""
+        d, c, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        _check(_batch_timing(self._h, ctypes.byref(d), ctypes.byref(c), ctypes.byref(n)))
+        return {"device_ms": d.value, "call_ms": c.value, "launches": n.value}
 
     def info(self) -> dict:
         t, r, b, lds = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()

@@ -108,3 +108,63 @@ def simulate_trotter(vec: np.ndarray, ham, time: float, norb: int, nelec, n_step
     for _ in range(n_steps):
         vec = trotter_step(vec, ham, dt, norb, nelec, order)
     return vec
+
+
+# ---------------------------------------------------------------------------
+# Gradient of an energy through a DF Trotter chain (finite differences)
+# ---------------------------------------------------------------------------
+# Reading (the paper does not treat this gradient): E = Re <psi_T|H_obs|psi_T>
+# with psi_T = S_0(dt)^r psi_0 under the evolution Hamiltonian (h, J_t, U_t) and
+# a fixed observable H_obs.  Parameters: h and every J_t as symmetric matrices
+# (a pair (p, q), p < q, moves both entries), and every U_t through a generator,
+# U_t -> U_t expm(A - A^dag) at A = 0 with Re A and Im A entries as parameters.
+
+def df_chain_energy(vec0: np.ndarray, ham, obs, dt: float, n_steps: int, norb: int, nelec) -> float:
+    """Re <psi_T|H_obs|psi_T>, psi_T = S_0(dt)^n_steps psi_0."""
+    psi = simulate_trotter(vec0, ham, dt * n_steps, norb, nelec, n_steps=n_steps, order=0)
+    return float(np.real(df_energy(psi, obs, norb, nelec)))
+
+
+def _with(ham, h=None, J=None, U=None):
+    return type(ham)(h=ham.h if h is None else h, J=ham.J if J is None else J, U=ham.U if U is None else U)
+
+
+def df_chain_grad_fd(vec0: np.ndarray, ham, obs, dt: float, n_steps: int, norb: int, nelec,
+                     step: float = 1e-5) -> dict:
+    """Central differences of df_chain_energy: {'h': (N, N) symmetric-pair derivatives,
+    'J': (L, N, N) likewise, 'U': (L, 2, N, N) with [t, 0] = d/d Re A, [t, 1] = d/d Im A}."""
+    N, L = norb, ham.J.shape[0]
+
+    def E(hh):
+        return df_chain_energy(vec0, hh, obs, dt, n_steps, norb, nelec)
+
+    def sym(p, q):
+        M = np.zeros((N, N))
+        M[p, q] = 1.0
+        M[q, p] = 1.0
+        return M
+
+    gh = np.zeros((N, N))
+    gJ = np.zeros((L, N, N))
+    gU = np.zeros((L, 2, N, N))
+    for p in range(N):
+        for q in range(p, N):
+            M = sym(p, q)
+            gh[p, q] = gh[q, p] = (E(_with(ham, h=ham.h + step * M)) - E(_with(ham, h=ham.h - step * M))) / (2 * step)
+            for t in range(L):
+                Jp, Jm = ham.J.copy(), ham.J.copy()
+                Jp[t] = Jp[t] + step * M
+                Jm[t] = Jm[t] - step * M
+                gJ[t, p, q] = gJ[t, q, p] = (E(_with(ham, J=Jp)) - E(_with(ham, J=Jm))) / (2 * step)
+    for t in range(L):
+        for part in range(2):
+            for p in range(N):
+                for q in range(N):
+                    A = np.zeros((N, N), dtype=complex)
+                    A[p, q] = step if part == 0 else 1j * step
+                    K = A - A.conj().T
+                    Up, Um = ham.U.copy(), ham.U.copy()
+                    Up[t] = Up[t] @ scipy.linalg.expm(K)
+                    Um[t] = Um[t] @ scipy.linalg.expm(-K)
+                    gU[t, part, p, q] = (E(_with(ham, U=Up)) - E(_with(ham, U=Um))) / (2 * step)
+    return {"h": gh, "J": gJ, "U": gU}

@@ -164,3 +164,55 @@ def test_slater_energy_by_wick():
     Eo = H.df_energy(vec, ham, norb, nelec)
     assert abs(Eo.real - np.real(E)) < 1e-12
     assert abs(Eo.imag) < 1e-12
+
+
+def _jw_chain_energy(F, vec0, ham, obs, dt, n_steps, nelec):
+    """The same chain with Fock-space exponentials (independent of the oracle)."""
+    B = F.sector_basis(nelec)
+    psi = B @ vec0.reshape(-1)
+    for _ in range(n_steps):
+        psi = F.orbital_rotation(scipy.linalg.expm(-1j * dt * np.asarray(ham.h))) @ psi
+        for t in range(ham.J.shape[0]):
+            U = np.asarray(ham.U[t])
+            G = F.diag_coulomb_gen(ham.J[t], ham.J[t], ham.J[t])
+            R = F.orbital_rotation(U)
+            psi = R @ scipy.linalg.expm(-1j * dt * G) @ R.conj().T @ psi
+    H = F.df_hamiltonian(obs.h, obs.J, obs.U)
+    return float(np.real(np.vdot(psi, H @ psi)))
+
+
+def test_df_chain_energy_and_fd_gradient_match_fock_space():
+    # N = 3, (1, 2): chain energy and every finite-difference component against Fock space
+    norb, nelec, dt, r = 3, (1, 2), 0.15, 2
+    rng = synth.rng(70)
+    ham = synth.df_hamiltonian(rng, norb, 2)
+    obs = synth.df_hamiltonian(rng, norb, 2)
+    vec0 = synth.random_state(rng, 3, 3)
+    F = Fock(norb)
+    e = H.df_chain_energy(vec0, ham, obs, dt, r, norb, nelec)
+    assert abs(e - _jw_chain_energy(F, vec0, ham, obs, dt, r, nelec)) < 1e-12
+    g = H.df_chain_grad_fd(vec0, ham, obs, dt, r, norb, nelec)
+    step = 1e-5
+    # spot components of each kind, recomputed in Fock space
+    M = np.zeros((norb, norb))
+    M[0, 2] = M[2, 0] = 1.0
+    ref = (_jw_chain_energy(F, vec0, type(ham)(h=ham.h + step * M, J=ham.J, U=ham.U), obs, dt, r, nelec)
+           - _jw_chain_energy(F, vec0, type(ham)(h=ham.h - step * M, J=ham.J, U=ham.U), obs, dt, r, nelec)) / (2 * step)
+    assert abs(g["h"][0, 2] - ref) < 1e-8
+    Jp, Jm = ham.J.copy(), ham.J.copy()
+    Jp[1] += step * M
+    Jm[1] -= step * M
+    ref = (_jw_chain_energy(F, vec0, type(ham)(h=ham.h, J=Jp, U=ham.U), obs, dt, r, nelec)
+           - _jw_chain_energy(F, vec0, type(ham)(h=ham.h, J=Jm, U=ham.U), obs, dt, r, nelec)) / (2 * step)
+    assert abs(g["J"][1, 0, 2] - ref) < 1e-8
+    A = np.zeros((norb, norb), dtype=complex)
+    A[1, 2] = 1j * step
+    K = A - A.conj().T
+    Up, Um = ham.U.copy(), ham.U.copy()
+    Up[0] = Up[0] @ scipy.linalg.expm(K)
+    Um[0] = Um[0] @ scipy.linalg.expm(-K)
+    ref = (_jw_chain_energy(F, vec0, type(ham)(h=ham.h, J=ham.J, U=Up), obs, dt, r, nelec)
+           - _jw_chain_energy(F, vec0, type(ham)(h=ham.h, J=ham.J, U=Um), obs, dt, r, nelec)) / (2 * step)
+    assert abs(g["U"][0, 1, 1, 2] - ref) < 1e-8
+    # the generator gradient has no component along the Hermitian part of A: d/dRe A_pq = -d/dRe A_qp
+    assert np.allclose(g["U"][:, 0], -np.transpose(g["U"][:, 0], (0, 2, 1)), atol=1e-7)

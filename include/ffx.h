@@ -159,6 +159,25 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
                          double* energy, double* grad, void* psi_out, void* workspace,
                          void* stream);
 
+/* Energy after a DF Trotter chain and its gradient by the adjoint method:
+   E = Re <psi_T|H_obs|psi_T>, psi_T = S_0(dt)^n_steps psi_0 (Sec. 4.5.3, one-body
+   term first) under the evolution Hamiltonian `ham` = (h, J_t, U_t), with the
+   observable `obs` held fixed (the paper does not define this gradient; this
+   is the library's extension).  The costate lambda = H_obs psi_T is pulled
+   back through every gate while psi is uncomputed; no intermediate state is
+   stored.  vec0 (device, read only): psi_0.  Outputs (host):
+     grad_h[p*N+q]      dE for moving h_pq and h_qp together (one entry when p == q)
+     grad_J[t*N*N+p*N+q] the same for J_t
+     grad_U[t*2N^2 + k]  U_t -> U_t expm(A - A^dag) at A = 0: k < N^2 is d/d Re A_pq,
+                         k >= N^2 is d/d Im A_pq (the LUCJ layout)
+   grad_J / grad_U may be NULL only when ham->n_terms == 0.  workspace:
+   ffx_workspace_bytes(plan, 1) bytes; psi_out (device, may be NULL) receives
+   psi_T.  Synchronizes the stream.  FFX_EUNSUPPORTED when
+   9 N^2 n_terms + 4 N^2 exceeds 65536. */
+int ffx_df_chain_energy_grad(ffx_plan plan, const void* vec0, const ffx_df_ham* ham, const ffx_df_ham* obs,
+                             double dt, int n_steps, double* energy, double* grad_h, double* grad_J,
+                             double* grad_U, void* psi_out, void* workspace, void* stream);
+
 /* ---------------------------------------------------------------------------
    Batched LUCJ energy + adjoint gradient over many independent sectors of
    uneven size (each instance its own norb, (n_alpha, n_beta), LUCJ

@@ -491,7 +491,7 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
     void* tmp = ws + Sa;
     void* psiT = ws + 2 * Sa;
     void* lamT = ws + 3 * Sa;
-    void* psi = psi_out ? psi_out : (void*)(ws + 4 * Sa);
+    void* psi = ws + 4 * Sa;  // the reverse sweep uncomputes it; psi_out gets a copy
     double* part = (double*)(ws + 5 * Sa);
     Upload up(&P, s);
     const double* sa = up.put((const double*)G->g.a.data(), 2 * G->g.a.size());
@@ -509,6 +509,7 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
     dev::outer(P.c64, sa, sb, psi, P.dim[0], P.dim[1], s);
     check_launch();
     execute_program(P, c_fwd, psi, psi, nullptr, s);
+    if (psi_out) HIPCHK(hipMemcpyAsync(psi_out, psi, S, hipMemcpyDeviceToDevice, s));
     // costate lambda = H psi
     for (int t = 0; t <= Lt; ++t) {
       if (t == 0)
@@ -566,6 +567,206 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
       D[k] = res.data() + 16 + (size_t)R * 8 * NN + (size_t)k * (2 * N);
     }
     lucj_grad_assemble(*G, N, Tb, Ta, D, grad);
+  });
+}
+
+int ffx_df_chain_energy_grad(ffx_plan plan, const void* vec0, const ffx_df_ham* ham, const ffx_df_ham* obs,
+                             double dt, int n_steps, double* energy, double* grad_h, double* grad_J,
+                             double* grad_U, void* psi_out, void* workspace, void* stream) {
+  return guard([&] {
+    validate_plan(plan);
+    if (!vec0 || !energy || !grad_h || !workspace) throw Error(FFX_EINVAL, "null pointer");
+    if (n_steps < 1 || !std::isfinite(dt)) throw Error(FFX_EINVAL, "bad n_steps or dt");
+    ffx_plan_s& P = *plan;
+    const int N = P.norb, NN = N * N;
+    DFHost df = load_df(P, ham);
+    DFHost ob = load_df(P, obs);
+    const int L = df.L;
+    if (L > 0 && (!grad_J || !grad_U)) throw Error(FFX_EINVAL, "null gradient pointer");
+    if ((size_t)L * 9 * NN + 4 * NN > (size_t)ffx_plan_s::kResults)
+      throw Error(FFX_EUNSUPPORTED, "too many terms for the result buffer");
+    DeviceGuard dg(P.device);
+    hipStream_t s = as_stream(stream);
+    const size_t S = P.state_bytes();
+    const size_t Sa = (S + 255) / 256 * 256;
+    char* ws = (char*)workspace;
+    void* lam = ws;
+    void* tmp = ws + Sa;
+    void* psiT = ws + 2 * Sa;
+    void* lamT = ws + 3 * Sa;
+    void* psi = ws + 4 * Sa;  // the reverse sweep uncomputes it; psi_out gets a copy
+    double* part = (double*)(ws + 5 * Sa);
+
+    DecompPool pool;
+    std::map<std::pair<int, int>, const Decomposition*> cache;
+    // script-U(W_to^dag W_from), frames: -1 = lab, 0 = eigenbasis of h, t = U_t
+    auto rot = [&](int from, int to) -> const Decomposition* {
+      auto key = std::make_pair(from, to);
+      auto it = cache.find(key);
+      if (it != cache.end()) return it->second;
+      std::vector<cd> M;
+      if (from < 0)
+        M = dagger(N, df.Wm(to));
+      else if (to < 0)
+        M = df.Wm(from);
+      else
+        M = matmul(N, dagger(N, df.Wm(to)), df.Wm(from));
+      const Decomposition* d = pool.add(N, M);
+      cache.emplace(key, d);
+      return d;
+    };
+    // forward: n_steps of S_0 (one-body term first), neighbours merged
+    Program fwd;
+    {
+      std::vector<int> w;
+      for (int t = 0; t <= L; ++t) w.push_back(fwd.add_diag(df_weight_spec(df, t)));
+      int prev = -1;
+      std::vector<std::pair<int, double>> m;
+      for (int r = 0; r < n_steps; ++r)
+        for (int t = 0; t <= L; ++t) {
+          if (!m.empty() && m.back().first == t)
+            m.back().second += dt;
+          else
+            m.push_back({t, dt});
+        }
+      for (auto& e : m) {
+        const Decomposition* d = rot(prev, e.first);
+        fwd.rot(d, d);
+        fwd.phase(w[e.first], -e.second);
+        prev = e.first;
+      }
+      const Decomposition* d = rot(prev, -1);
+      fwd.rot(d, d);
+    }
+    // costate terms of the observable
+    std::vector<Program> terms(ob.L + 1);
+    for (int t = 0; t <= ob.L; ++t) {
+      const Decomposition* to = pool.add(N, dagger(N, ob.Wm(t)));
+      const Decomposition* from = pool.add(N, ob.Wm(t));
+      terms[t].rot(to, to);
+      terms[t].scale(terms[t].add_diag(df_weight_spec(ob, t)));
+      terms[t].rot(from, from);
+    }
+    // reverse sweep of one step: into frame L, then per term t: undo D_t,
+    // move to frame t-1; finally undo the one-body term back to the lab frame
+    Program first, tail;
+    std::vector<Program> undoD(L + 1), link(L + 1);
+    if (L >= 1) {
+      const Decomposition* d = rot(-1, L);
+      first.rot(d, d);
+    }
+    for (int t = L; t >= 1; --t) {
+      undoD[t].phase(undoD[t].add_diag(df_weight_spec(df, t)), +dt);
+      if (t >= 2) {
+        const Decomposition* d = rot(t, t - 1);
+        link[t].rot(d, d);
+      }
+    }
+    {
+      const Decomposition* d0 = rot(L >= 1 ? 1 : -1, 0);
+      tail.rot(d0, d0);
+      tail.phase(tail.add_diag(df_weight_spec(df, 0)), +dt);
+      const Decomposition* d1 = rot(0, -1);
+      tail.rot(d1, d1);
+    }
+    Upload up(&P, s);
+    Compiled c_fwd = compile_program(P, up, fwd, FINAL_STORE, s);
+    std::vector<Compiled> c_terms;
+    for (int t = 0; t <= ob.L; ++t)
+      c_terms.push_back(compile_program(P, up, terms[t], t == 0 ? FINAL_STORE : FINAL_ACCUM, s));
+    Compiled c_first = compile_program(P, up, first, FINAL_STORE, s);
+    Compiled c_tail = compile_program(P, up, tail, FINAL_STORE, s);
+    std::vector<Compiled> c_undoD(L + 1), c_link(L + 1);
+    for (int t = L; t >= 1; --t) {
+      c_undoD[t] = compile_program(P, up, undoD[t], FINAL_STORE, s);
+      if (t >= 2) c_link[t] = compile_program(P, up, link[t], FINAL_STORE, s);
+    }
+    up.commit();
+
+    // forward and costate
+    execute_program(P, c_fwd, vec0, psi, nullptr, s);
+    if (psi_out) HIPCHK(hipMemcpyAsync(psi_out, psi, S, hipMemcpyDeviceToDevice, s));
+    for (int t = 0; t <= ob.L; ++t) {
+      if (t == 0)
+        execute_program(P, c_terms[t], psi, lam, nullptr, s);
+      else
+        execute_program(P, c_terms[t], psi, tmp, lam, s);
+    }
+    dev::inner(P.c64, psi, lam, P.elems(), P.partials, P.results, s);
+    check_launch();
+    double e2[2];
+    HIPCHK(hipMemcpyAsync(e2, P.results, sizeof(e2), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *energy = e2[0];
+
+    auto both = [&](const Compiled& c) {
+      execute_program(P, c, psi, psi, nullptr, s);
+      execute_program(P, c, lam, lam, nullptr, s);
+    };
+    auto rdm = [&](double* Tout) {
+      dev::rdm_rows(P.c64, lam, psi, P.dim[0], P.dim[1], P.d_masks[0], N, part, s);
+      dev::rdm_reduce(part, P.dim[0], N, Tout, s);
+      dev::transpose(P.c64, psi, psiT, P.dim[0], P.dim[1], s);
+      dev::transpose(P.c64, lam, lamT, P.dim[0], P.dim[1], s);
+      dev::rdm_rows(P.c64, lamT, psiT, P.dim[1], P.dim[0], P.d_masks[1], N, part, s);
+      dev::rdm_reduce(part, P.dim[1], N, Tout + 2 * NN, s);
+      check_launch();
+    };
+    // device results per step: [t = 1..L: Tb (4N^2), Ta (4N^2), Jg (N^2)] [T_O (4N^2)]
+    auto Tb_at = [&](int t) { return P.results + (size_t)(t - 1) * 9 * NN; };
+    double* TO = P.results + (size_t)L * 9 * NN;
+    std::vector<std::vector<cd>> G(L + 1, std::vector<cd>((size_t)NN, 0.0));
+    std::vector<std::vector<double>> Jg(L + 1, std::vector<double>((size_t)NN, 0.0));
+    std::vector<cd> GO((size_t)NN, 0.0);
+    std::vector<double> res((size_t)L * 9 * NN + 4 * NN);
+    for (int step = n_steps - 1; step >= 0; --step) {
+      if (L >= 1) both(c_first);
+      for (int t = L; t >= 1; --t) {
+        double* Tb = Tb_at(t);
+        rdm(Tb);
+        dev::dc_grad_rows(P.c64, lam, psi, P.dim[0], P.dim[1], P.d_masks[0], P.d_masks[1], N, part, s);
+        dev::sum_columns(part, (int)P.dim[0], NN, Tb + 8 * NN, s);
+        check_launch();
+        both(c_undoD[t]);
+        rdm(Tb + 4 * NN);
+        if (t >= 2) both(c_link[t]);
+      }
+      both(c_tail);
+      rdm(TO);
+      HIPCHK(hipMemcpyAsync(res.data(), P.results, res.size() * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int t = 1; t <= L; ++t) {
+        const double* b = res.data() + (size_t)(t - 1) * 9 * NN;
+        const double* a = b + 4 * NN;
+        const double* j = b + 8 * NN;
+        for (int i = 0; i < NN; ++i) {
+          G[t][i] += cd(b[2 * i] + b[2 * NN + 2 * i] - a[2 * i] - a[2 * NN + 2 * i],
+                        b[2 * i + 1] + b[2 * NN + 2 * i + 1] - a[2 * i + 1] - a[2 * NN + 2 * i + 1]);
+          Jg[t][i] += dt * j[i];
+        }
+      }
+      const double* o = res.data() + (size_t)L * 9 * NN;
+      for (int i = 0; i < NN; ++i) GO[i] += cd(o[2 * i] + o[2 * NN + 2 * i], o[2 * i + 1] + o[2 * NN + 2 * i + 1]);
+    }
+    // chain rules; symmetric parameters report the derivative for moving the pair (p, q) and (q, p)
+    std::vector<double> gre((size_t)NN), gim((size_t)NN);
+    {
+      std::vector<cd> K((size_t)NN);
+      for (int i = 0; i < NN; ++i) K[i] = cd(0.0, -dt * ham->h[i]);
+      expm_param_grad(N, K, GO, gre.data(), gim.data());
+      for (int p = 0; p < N; ++p)
+        for (int q = 0; q < N; ++q)
+          grad_h[p * N + q] = p == q ? -0.5 * dt * gim[p * N + p] : -0.5 * dt * (gim[p * N + q] + gim[q * N + p]);
+    }
+    std::vector<cd> K0((size_t)NN, 0.0);
+    for (int t = 1; t <= L; ++t) {
+      double* gu = grad_U + (size_t)(t - 1) * 2 * NN;
+      expm_param_grad(N, K0, G[t], gu, gu + NN);
+      double* gj = grad_J + (size_t)(t - 1) * NN;
+      for (int p = 0; p < N; ++p)
+        for (int q = 0; q < N; ++q)
+          gj[p * N + q] = p == q ? Jg[t][p * N + p] : Jg[t][p * N + q] + Jg[t][q * N + p];
+    }
   });
 }
 

@@ -102,6 +102,12 @@ void rdm_reduce(const double* part, int64_t rows, int norb, double* T, hipStream
 //   rowout[i_a * 2N + k] = sum_{i_b} z * g_k(I_b)
 void diag_grad_rows(bool c64, const void* lam, const void* psi, int64_t dim_a, int64_t dim_b,
                     const uint32_t* masks_b, int norb, double* rowout, hipStream_t stream);
+// Diagonal-Coulomb matrix gradient rows: rowout[i_a * N^2 + p N + q] =
+//   sum_{i_b} Im(conj(lam) psi) (x_a + x_b)_p (x_a + x_b)_q
+void dc_grad_rows(bool c64, const void* lam, const void* psi, int64_t dim_a, int64_t dim_b,
+                  const uint32_t* masks_a, const uint32_t* masks_b, int norb, double* rowout, hipStream_t stream);
+// out[w] = sum_{r < rows} in[r * width + w] in a fixed order (w < width)
+void sum_columns(const double* in, int rows, int width, double* out, hipStream_t stream);
 // out[p]      (p < N-1) = 2 sum_{i_a} (x_a[p] x_a[p+1] rowout[i_a][0] + rowout[i_a][1+N+p])
 // out[N-1+p]  (p < N)   = 2 sum_{i_a} x_a[p] rowout[i_a][1+p]
 void diag_grad_combine(const double* rowout, int64_t dim_a, const uint32_t* masks_a, int norb,

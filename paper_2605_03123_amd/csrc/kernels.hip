@@ -674,6 +674,65 @@ void diag_grad_rows(bool c64, const void* lam, const void* psi, int64_t da, int6
   }
 }
 
+// ---------------------------------------------------------------------------
+// gradient of a diagonal Coulomb gate with respect to its matrix: per alpha
+// row i_a, out[p * norb + q] = sum_{i_b} Im(conj(lam) psi) x_p x_q with
+// x = x_a + x_b the total occupation; thread t owns the pair t, column blocks
+// of z and of the beta masks are staged in LDS
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(256) void k_dc_grad_rows(const typename V2T<R>::type* __restrict__ lam,
+                                                      const typename V2T<R>::type* __restrict__ psi,
+                                                      int64_t dim_a, int64_t dim_b,
+                                                      const uint32_t* __restrict__ masks_a,
+                                                      const uint32_t* __restrict__ masks_b, int norb,
+                                                      double* __restrict__ rowout) {
+  constexpr int CH = 2048;
+  __shared__ double z[CH];
+  __shared__ uint32_t mk[CH];
+  const int64_t row = blockIdx.x;
+  const uint32_t xa = masks_a[row];
+  const int NN = norb * norb;
+  for (int t0 = 0; t0 < NN; t0 += 256) {
+    const int t = t0 + (int)threadIdx.x;
+    const int p = t / norb, q = t - (t / norb) * norb;
+    const double ap = t < NN ? (double)((xa >> p) & 1) : 0.0;
+    const double aq = t < NN ? (double)((xa >> q) & 1) : 0.0;
+    double acc = 0.0;
+    for (int64_t c0 = 0; c0 < dim_b; c0 += CH) {
+      const int n = (int)(dim_b - c0 < CH ? dim_b - c0 : CH);
+      __syncthreads();
+      for (int e = threadIdx.x; e < n; e += 256) {
+        const auto a = lam[row * dim_b + c0 + e];
+        const auto b = psi[row * dim_b + c0 + e];
+        z[e] = (double)a.x * (double)b.y - (double)a.y * (double)b.x;
+        mk[e] = masks_b[c0 + e];
+      }
+      __syncthreads();
+      if (t < NN)
+        for (int e = 0; e < n; ++e) {
+          const uint32_t w = mk[e];
+          acc += z[e] * (ap + (double)((w >> p) & 1)) * (aq + (double)((w >> q) & 1));
+        }
+    }
+    if (t < NN) rowout[row * NN + t] = acc;
+  }
+}
+
+void dc_grad_rows(bool c64, const void* lam, const void* psi, int64_t da, int64_t db, const uint32_t* masks_a,
+                  const uint32_t* masks_b, int norb, double* rowout, hipStream_t s) {
+  if (c64)
+    hipLaunchKernelGGL(k_dc_grad_rows<float>, dim3((unsigned)da), dim3(256), 0, s, (const zc64*)lam,
+                       (const zc64*)psi, da, db, masks_a, masks_b, norb, rowout);
+  else
+    hipLaunchKernelGGL(k_dc_grad_rows<double>, dim3((unsigned)da), dim3(256), 0, s, (const zc128*)lam,
+                       (const zc128*)psi, da, db, masks_a, masks_b, norb, rowout);
+}
+
+void sum_columns(const double* in, int rows, int width, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum, dim3((unsigned)width), dim3(256), 0, s, in, rows, width, out);
+}
+
 __global__ __launch_bounds__(256) void k_diag_grad_combine(const double* __restrict__ rowout, int64_t dim_a,
                                                            const uint32_t* __restrict__ masks_a, int norb,
                                                            double* __restrict__ out) {

@@ -339,6 +339,37 @@ def lucj_energy_grad(params, ham, norb: int, nelec, n_reps: int, *, dtype=torch.
     return e.value, grad
 
 
+_chain = _sig("ffx_df_chain_energy_grad", ctypes.c_int,
+               [_vp, _vp, ctypes.POINTER(_DFHam), ctypes.POINTER(_DFHam), ctypes.c_double, ctypes.c_int,
+                ctypes.POINTER(ctypes.c_double), _c_double_p, _c_double_p, _c_double_p, _vp, _vp, _vp])
+
+
+def df_chain_energy_grad(vec0: torch.Tensor, ham, obs, dt: float, n_steps: int, norb: int, nelec, *,
+                         psi_out: torch.Tensor | None = None, plan=None):
+    """(E, {'h', 'J', 'U'}) for E = Re <psi_T|H_obs|psi_T>, psi_T = S_0(dt)^n_steps vec0, by the adjoint method.
+
+    'h' (N, N) and 'J' (L, N, N): derivatives for moving the symmetric pair (p, q), (q, p) together;
+    'U' (L, 2, N, N): U_t -> U_t expm(A - A^dag), [t, 0] = d/d Re A, [t, 1] = d/d Im A.
+    """
+    plan = plan or get_plan(norb, nelec, vec0.dtype, vec0.device.index or 0)
+    plan.check_vec(vec0)
+    hs, hk = _df_struct(ham, norb)
+    os_, ok = _df_struct(obs, norb)
+    L = hs.n_terms
+    gh = np.zeros((norb, norb))
+    gJ = np.zeros((max(L, 1), norb, norb))
+    gU = np.zeros((max(L, 1), 2, norb, norb))
+    e = ctypes.c_double()
+    ws = plan.workspace(1)
+    if psi_out is not None:
+        plan.check_vec(psi_out)
+    _check(_chain(plan.handle, _vp(vec0.data_ptr()), ctypes.byref(hs), ctypes.byref(os_), float(dt), int(n_steps),
+                  ctypes.byref(e), _dptr(gh), _dptr(gJ), _dptr(gU),
+                  _vp(psi_out.data_ptr()) if psi_out is not None else None, _vp(ws.data_ptr()),
+                  _stream(vec0.device)))
+    return e.value, {"h": gh, "J": gJ[:L], "U": gU[:L]}
+
+
 class LUCJEnergy(torch.autograd.Function):
     """E(theta) for a LUCJ ansatz under a DF Hamiltonian, differentiable in theta.
 

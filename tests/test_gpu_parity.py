@@ -262,3 +262,13 @@ def test_segmented_paths(ffx, small_segment_plans):
         params = synth.lucj_params(r, norb, 2, scale=0.3)
         out = ffx.apply_lucj(params, norb, nelec, 2, dtype=dtype, plan=plan)
         assert _maxdiff(out, ol.apply_lucj(params, norb, nelec, 2)) <= TOL[dtype]
+
+
+def test_lucj_energy_grad_returns_the_ansatz_state(ffx):
+    # psi_out receives psi(theta) even though the reverse sweep uncomputes its own copy
+    norb, nelec, n_reps = 6, (3, 3), 2
+    w = synth.workload_lucj(norb, n_reps, 3, seed=12, nelec=nelec)
+    plan = ffx.get_plan(norb, nelec, torch.complex128, 0)
+    out = torch.zeros((plan.dim_a, plan.dim_b), dtype=torch.complex128, device="cuda:0")
+    ffx.lucj_energy_grad(w.data["params"], w.data["ham"], norb, nelec, n_reps, psi_out=out)
+    assert _maxdiff(out, ol.apply_lucj(w.data["params"], norb, nelec, n_reps)) <= 1e-12

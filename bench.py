@@ -11,6 +11,9 @@ device synchronization, timed with HIP events on the working stream.  `value`
 is the time per step in the primary precision (--dtype, complex128 by
 default); the other precision is timed the same way and reported beside it.
 
+Also reported (unless --no-batched): the batched energies + adjoint gradients
+of 256 small sectors (norb 8-12) in both precisions.
+
 Also reported (unless --no-lucj): the LUCJ energy + adjoint gradient at
 norb = 16, n_reps = 3, L = 16 in both precisions, and against it the
 forward-only central finite-difference gradient (h = 1e-5) on 20 parameters
@@ -228,6 +231,24 @@ def lucj_timing(ffx, torch, synth, dtype, with_fd):
     return out
 
 
+def batched_timing(ffx, torch, synth, dtype):
+    """Config-4 workload: 256 sectors (norb in {8, 10, 12}, n in {norb/2 - 1, norb/2}), each with its
+    own LUCJ (n_reps = 2) and DF Hamiltonian (L = norb): energies and adjoint gradients of all of them."""
+    w = synth.workload_batched(256, seed=0, n_reps=2)
+    b = ffx.Batch([(x.norb, x.nelec) for x in w], dtype=dtype)
+    args = ([x.data["params"] for x in w], [x.data["ham"] for x in w], 2)
+    b.lucj_energy_grad(*args)
+    torch.cuda.synchronize()
+    runs = []
+    for _ in range(3):
+        b.lucj_energy_grad(*args)
+        runs.append(b.timing())
+    best = min(runs, key=lambda r: r["device_ms"])
+    return {"device_ms": best["device_ms"], "call_ms": best["call_ms"], "launches": best["launches"],
+            "config": b.info(), "amplitudes": int(sum(synth.dim(x.norb, x.nelec[0]) * synth.dim(x.norb, x.nelec[1])
+                                                      for x in w))}
+
+
 def copy_calibration(torch):
     """Plain device copies of a known size for scaling the HBM byte counters."""
     n = 1 << 27  # 2^27 complex64 = 1 GiB
@@ -249,6 +270,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lucj", action="store_true")
     ap.add_argument("--no-other-dtype", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -297,6 +319,13 @@ def main():
             "workload": f"lucj norb=16 nelec=(8,8) n_reps={LUCJ_REPS} L={L} params~N(0,0.1)",
             "c128": lucj_timing(ffx, torch, synth, torch.complex128, True),
             "c64": lucj_timing(ffx, torch, synth, torch.complex64, False),
+        }
+    if not args.no_batched:
+        out["batched_lucj_energy_grad"] = {
+            "workload": "256 sectors, norb in {8,10,12}, n in {norb/2-1, norb/2}, LUCJ n_reps=2, DF L=norb "
+                        "(energies + adjoint gradients; one launch per pass level)",
+            "c64": batched_timing(ffx, torch, synth, torch.complex64),
+            "c128": batched_timing(ffx, torch, synth, torch.complex128),
         }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ham, vec_np)

@@ -38,6 +38,86 @@ void validate_plan(ffx_plan plan) {
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
+// Transition one-body matrix of lam and psi, both spins:
+//   Tout[0 .. 2N^2) alpha part, Tout[2N^2 .. 4N^2) beta part (interleaved complex)
+// For norb <= 16 with rows that fit in LDS (whole, or in two halves split by
+// the top orbital), the excitations are taken inside rows: beta on the
+// alpha-major state, alpha on its transpose.  Otherwise row pairs are used.
+bool rdm_split(const ffx_plan_s& P, int cs, int& halves, int64_t& split) {
+  const size_t cap = 128 * 1024;  // next to the kernel's rank tables and accumulators
+  const int64_t cols = P.dim[cs];
+  if (P.norb > 16) return false;
+  if ((size_t)cols * P.elem() <= cap) {
+    halves = 1;
+    split = cols;
+    return true;
+  }
+  split = binom(P.norb - 1, P.n[cs]);
+  halves = 2;
+  return (size_t)std::max(split, cols - split) * P.elem() <= cap;
+}
+
+void ensure_rank_tables(ffx_plan_s& P) {
+  if (P.rank_lo) return;
+  std::vector<int> lo(256, 0), hi(256 * 17, 0);
+  for (int v = 0; v < 256; ++v) {
+    int t = 0;
+    for (int j = 0; j < 8; ++j)
+      if ((v >> j) & 1) lo[v] += (int)binom(j, ++t);
+    for (int c = 0; c <= 16; ++c) {
+      int u = c, acc = 0;
+      for (int j = 0; j < 8; ++j)
+        if ((v >> j) & 1) acc += (int)binom(8 + j, ++u);
+      hi[v * 17 + c] = acc;
+    }
+  }
+  P.rank_lo = (int*)P.dalloc(lo.size() * 4);
+  P.rank_hi = (int*)P.dalloc(hi.size() * 4);
+  HIPCHK(hipMemcpy(P.rank_lo, lo.data(), lo.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(P.rank_hi, hi.data(), hi.size() * 4, hipMemcpyHostToDevice));
+  for (int sp = 0; sp < 2; ++sp) {
+    std::vector<int> idx, off;
+    for (int q = 0; q < P.norb; ++q) {
+      off.push_back((int)idx.size());
+      for (size_t k = 0; k < P.str[sp].size(); ++k)
+        if ((P.str[sp][k] >> q) & 1) idx.push_back((int)k);
+    }
+    off.push_back((int)idx.size());
+    P.with_q[sp] = (int*)P.dalloc(std::max<size_t>(idx.size(), 1) * 4);
+    P.with_q_off[sp] = (int*)P.dalloc(off.size() * 4);
+    if (!idx.empty()) HIPCHK(hipMemcpy(P.with_q[sp], idx.data(), idx.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(P.with_q_off[sp], off.data(), off.size() * 4, hipMemcpyHostToDevice));
+  }
+}
+
+void transition_rdm(ffx_plan_s& P, const void* lam, const void* psi, void* lamT, void* psiT, double* part,
+                    double* Tout, hipStream_t s) {
+  const int N = P.norb, NN = N * N;
+  int h0 = 0, h1 = 0;
+  int64_t s0 = 0, s1 = 0;
+  // the in-row kernel is the faster one for complex128 (where rows are staged in
+  // halves); for complex64 the row-pair kernel is
+  if (!P.c64 && rdm_split(P, 0, h0, s0) && rdm_split(P, 1, h1, s1)) {
+    ensure_rank_tables(P);
+    dev::rdm_lds(P.c64, lam, psi, P.dim[0], P.dim[1], P.d_masks[1], N, h1, s1, P.rank_lo, P.rank_hi, P.with_q[1],
+                 P.with_q_off[1], part, s);
+    dev::rdm_reduce(part, P.dim[0], N, Tout + 2 * NN, s);
+    dev::transpose(P.c64, psi, psiT, P.dim[0], P.dim[1], s);
+    dev::transpose(P.c64, lam, lamT, P.dim[0], P.dim[1], s);
+    dev::rdm_lds(P.c64, lamT, psiT, P.dim[1], P.dim[0], P.d_masks[0], N, h0, s0, P.rank_lo, P.rank_hi, P.with_q[0],
+                 P.with_q_off[0], part, s);
+    dev::rdm_reduce(part, P.dim[1], N, Tout, s);
+  } else {
+    dev::rdm_rows(P.c64, lam, psi, P.dim[0], P.dim[1], P.d_masks[0], N, part, s);
+    dev::rdm_reduce(part, P.dim[0], N, Tout, s);
+    dev::transpose(P.c64, psi, psiT, P.dim[0], P.dim[1], s);
+    dev::transpose(P.c64, lam, lamT, P.dim[0], P.dim[1], s);
+    dev::rdm_rows(P.c64, lamT, psiT, P.dim[1], P.dim[0], P.d_masks[1], N, part, s);
+    dev::rdm_reduce(part, P.dim[1], N, Tout + 2 * NN, s);
+  }
+  check_launch();
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -232,7 +312,7 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
       ss.d_segs = (dev::SegDev*)P->dalloc(hsegs.size() * sizeof(dev::SegDev));
       HIPCHK(hipMemcpy(ss.d_segs, hsegs.data(), hsegs.size() * sizeof(dev::SegDev), hipMemcpyHostToDevice));
       ss.lds = dev::seg_pass_lds(P->c64, ss.max_len, ss.max_mt);
-      ss.threads = ss.max_len >= 4096 ? 768 : (ss.max_len >= 1024 ? 256 : 64);
+      ss.threads = ss.max_len >= 4096 ? 1024 : (ss.max_len >= 1024 ? 256 : 64);  // capped by the kernel
       // rows of this column spin's layout times segments: one partial sum per block
       max_rows_x_seg = std::max<int>(max_rows_x_seg, (int)(P->dim[1 - s] * ss.n_seg));
     }
@@ -526,15 +606,7 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
     double* Ddev = P.results + 16 + (size_t)R * 8 * NN;  // per rep: 2N-1 diagonal-gate gradients
     if (16 + (size_t)R * (8 * NN + 2 * N) > (size_t)ffx_plan_s::kResults)
       throw Error(FFX_EUNSUPPORTED, "too many LUCJ repetitions for the result buffer");
-    auto rdm = [&](double* Tout) {
-      dev::rdm_rows(P.c64, lam, psi, P.dim[0], P.dim[1], P.d_masks[0], N, part, s);
-      dev::rdm_reduce(part, P.dim[0], N, Tout, s);
-      dev::transpose(P.c64, psi, psiT, P.dim[0], P.dim[1], s);
-      dev::transpose(P.c64, lam, lamT, P.dim[0], P.dim[1], s);
-      dev::rdm_rows(P.c64, lamT, psiT, P.dim[1], P.dim[0], P.d_masks[1], N, part, s);
-      dev::rdm_reduce(part, P.dim[1], N, Tout + 2 * NN, s);
-      check_launch();
-    };
+    auto rdm = [&](double* Tout) { transition_rdm(P, lam, psi, lamT, psiT, part, Tout, s); };
     for (int k = R - 1; k >= 0; --k) {
       execute_program(P, c_urot[k], psi, psi, nullptr, s);
       execute_program(P, c_urot[k], lam, lam, nullptr, s);
@@ -703,15 +775,7 @@ int ffx_df_chain_energy_grad(ffx_plan plan, const void* vec0, const ffx_df_ham* 
       execute_program(P, c, psi, psi, nullptr, s);
       execute_program(P, c, lam, lam, nullptr, s);
     };
-    auto rdm = [&](double* Tout) {
-      dev::rdm_rows(P.c64, lam, psi, P.dim[0], P.dim[1], P.d_masks[0], N, part, s);
-      dev::rdm_reduce(part, P.dim[0], N, Tout, s);
-      dev::transpose(P.c64, psi, psiT, P.dim[0], P.dim[1], s);
-      dev::transpose(P.c64, lam, lamT, P.dim[0], P.dim[1], s);
-      dev::rdm_rows(P.c64, lamT, psiT, P.dim[1], P.dim[0], P.d_masks[1], N, part, s);
-      dev::rdm_reduce(part, P.dim[1], N, Tout + 2 * NN, s);
-      check_launch();
-    };
+    auto rdm = [&](double* Tout) { transition_rdm(P, lam, psi, lamT, psiT, part, Tout, s); };
     // device results per step: [t = 1..L: Tb (4N^2), Ta (4N^2), Jg (N^2)] [T_O (4N^2)]
     auto Tb_at = [&](int t) { return P.results + (size_t)(t - 1) * 9 * NN; };
     double* TO = P.results + (size_t)L * 9 * NN;

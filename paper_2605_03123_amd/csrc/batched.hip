@@ -611,7 +611,7 @@ static void launch_level(const BatchDev& b, int p0, int p1, int64_t tasks, size_
 
 void batch_launch_level(bool c64, const BatchDev& b, int p0, int p1, int64_t tasks, size_t lds, hipStream_t s) {
   if (c64)
-    launch_level<7, float>(b, p0, p1, tasks, lds, s);
+    launch_level<6, float>(b, p0, p1, tasks, lds, s);
   else
     launch_level<6, double>(b, p0, p1, tasks, lds, s);
 }
@@ -633,9 +633,9 @@ int batch_blocks_per_cu(bool c64, int threads, size_t lds) {
   hipError_t e;
   if (lds > (size_t)kBatchMaxDynLds) return 0;
   if (c64) {
-    (void)hipFuncSetAttribute((const void*)k_batch<7, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_batch<6, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kBatchMaxDynLds);
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<7, float>, threads, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<6, float>, threads, lds);
   } else {
     (void)hipFuncSetAttribute((const void*)k_batch<6, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kBatchMaxDynLds);
@@ -647,7 +647,7 @@ int batch_blocks_per_cu(bool c64, int threads, size_t lds) {
 
 void batch_launch(bool c64, const BatchDev& b, int blocks, int threads, size_t lds, hipStream_t s) {
   if (c64)
-    launch_batch<7, float>(b, blocks, threads, lds, s);
+    launch_batch<6, float>(b, blocks, threads, lds, s);
   else
     launch_batch<6, double>(b, blocks, threads, lds, s);
 }

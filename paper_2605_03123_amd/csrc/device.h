@@ -46,9 +46,10 @@ struct DiagSpecDev {
   const double* C;
 };
 
-// Largest window width with a kernel instantiation (register budget: about
-// twice C(W, W/2) complex amplitudes per lane).
-inline int max_window(bool c64) { return c64 ? 7 : 6; }
+// Register window of the Givens passes: W = 6 for both precisions (complex64
+// also has a W = 7 instantiation, which holds 12 waves instead of 16 and
+// measured slower; complex128 at W = 6 fills 143 registers, so 12 waves).
+inline int max_window(bool) { return 6; }
 
 // c128 = complex double state, c64 = complex float state.
 void win_pass(bool c64, bool real, int spin, void* vec, int64_t dim_a, int64_t dim_b,
@@ -96,6 +97,16 @@ void transpose(bool c64, const void* src, void* dst, int64_t rows, int64_t cols,
 void rdm_rows(bool c64, const void* lam, const void* psi, int64_t rows, int64_t cols,
               const uint32_t* masks_rows, int norb, double* part, hipStream_t stream);
 void rdm_reduce(const double* part, int64_t rows, int norb, double* T, hipStream_t stream);
+// The same partials for the COLUMN spin (excitations inside each row), for
+// norb <= 16: lam's row is staged in LDS whole (halves = 1) or as the strings
+// below / from `split` (halves = 2: split = first string holding the top
+// orbital).  rank_lo[256], rank_hi[256 * 17]: colex rank of a mask
+// = rank_lo[m & 255] + rank_hi[(m >> 8) * 17 + popcount(m & 255)].
+// with_q[with_q_off[q] ..]: the column strings that hold orbital q.
+size_t rdm_lds_bytes(bool c64, int64_t cols, int64_t split, int halves);
+void rdm_lds(bool c64, const void* lam, const void* psi, int64_t rows, int64_t cols, const uint32_t* masks,
+             int norb, int halves, int64_t split, const int* rank_lo, const int* rank_hi, const int* with_q,
+             const int* with_q_off, double* part, hipStream_t stream);
 
 // Diagonal-gate gradient reductions (see api): for each row i_a and
 //   z = Im(conj(lam) psi), g_0 = 1, g_{1+p} = x_b[p], g_{1+N+p} = x_b[p] x_b[p+1]:

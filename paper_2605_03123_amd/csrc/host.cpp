@@ -252,6 +252,9 @@ SegWindowTable build_seg_window(const std::vector<uint64_t>& seg, int wt, int a,
     if (c.count != (int)binom(w, c.m)) throw Error(FFX_EDEVICE, "segment window table: incomplete class");
     by_m[c.m].push_back((c.cbase << 5) | c.l);
   }
+  // classes in order of their base address: neighbouring lanes then read
+  // neighbouring LDS words for the same member (fewer bank conflicts)
+  for (auto& kv : by_m) std::sort(kv.second.begin(), kv.second.end());
   struct Chunk {
     int m;
     double cost;
@@ -289,6 +292,7 @@ SegWindowTable replicate_seg_window(const SegWindowTable& t, int w, int R, int r
         if (cbase >= (1ll << 26)) throw Error(FFX_EUNSUPPORTED, "replicated window table too large");
         by_m[t.chunk_m[ch]].push_back((int)((cbase << 5) | (c & 31)));
       }
+  for (auto& kv : by_m) std::sort(kv.second.begin(), kv.second.end());
   struct Chunk {
     int m;
     double cost;

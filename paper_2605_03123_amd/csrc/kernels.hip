@@ -18,6 +18,8 @@
 //               classes with consecutive low patterns touch consecutive columns.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <utility>
 
 #include "dev_common.h"
@@ -588,6 +590,131 @@ void rdm_rows(bool c64, const void* lam, const void* psi, int64_t rows, int64_t 
   else
     hipLaunchKernelGGL(k_rdm_rows<double>, dim3((unsigned)rows), dim3(256), 0, s, (const zc128*)lam,
                        (const zc128*)psi, rows, cols, masks_rows, norb, part);
+}
+
+// Transition one-body matrix of the COLUMN spin (excitations I -> J = I - q + p
+// inside each row), for norb <= 16.  One block per row: lam's row is staged in
+// LDS (in two halves split by the top orbital when a whole row does not fit);
+// wave w owns the occupied orbital q = w (+ nwaves ...) and keeps one complex
+// accumulator per p in each lane; lanes walk the strings I of the row that
+// contain q (a per-q list), read psi[row, I] once and gather lam[row, J] from
+// LDS.  J's address comes from two byte tables staged in LDS (colex rank =
+// lo[J & 255] + hi[J >> 8][popcount(J & 255)]).  Every sum has a fixed order.
+//   part[2 * (pq * rows + row)] = sum_{I -> J} sign conj(lam[row, J]) psi[row, I]
+constexpr int kRdmMaxOrb = 16;
+
+template <class R>
+__global__ __launch_bounds__(512) void k_rdm_lds(const typename V2T<R>::type* __restrict__ lam,
+                                                  const typename V2T<R>::type* __restrict__ psi,
+                                                  int64_t rows, int64_t cols,
+                                                  const uint32_t* __restrict__ masks, int norb, int halves,
+                                                  int64_t split, const int* __restrict__ rank_lo,
+                                                  const int* __restrict__ rank_hi,
+                                                  const int* __restrict__ with_q, const int* __restrict__ with_q_off,
+                                                  double* __restrict__ part) {
+  using V = typename V2T<R>::type;
+  extern __shared__ __align__(16) char smem[];
+  V* lrow = (V*)smem;
+  __shared__ double T[2 * kRdmMaxOrb * kRdmMaxOrb];
+  __shared__ int rlo[256];
+  __shared__ int rhi[256 * 17];
+  const int64_t row = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int NN = norb * norb;
+  for (int i = threadIdx.x; i < 2 * NN; i += blockDim.x) T[i] = 0.0;
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) rlo[i] = rank_lo[i];
+  for (int i = threadIdx.x; i < 256 * 17; i += blockDim.x) rhi[i] = rank_hi[i];
+  const V* lr = lam + row * cols;
+  const V* pr = psi + row * cols;
+  const uint32_t top = 1u << (norb - 1);
+  for (int h = 0; h < halves; ++h) {
+    const int64_t j0 = h == 0 ? 0 : split;
+    const int64_t j1 = halves == 1 ? cols : (h == 0 ? split : cols);
+    __syncthreads();
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) lrow[j - j0] = lr[j];
+    __syncthreads();
+    for (int q = wave; q < norb; q += nw) {
+      double ar[kRdmMaxOrb], ai[kRdmMaxOrb];
+#pragma unroll
+      for (int p = 0; p < kRdmMaxOrb; ++p) ar[p] = ai[p] = 0.0;
+      // the strings of the row that hold q
+      for (int e = with_q_off[q] + lane; e < with_q_off[q + 1]; e += 64) {
+        const int k = with_q[e];
+        const uint32_t I = masks[k];
+        const V b = pr[k];
+        const double bx = b.x, by = b.y;
+        const uint32_t Iq = I & ~(1u << q);
+#pragma unroll
+        for (int p = 0; p < kRdmMaxOrb; ++p) {
+          if (p >= norb || (p != q && ((I >> p) & 1))) continue;
+          const uint32_t J = Iq | (1u << p);
+          if (halves == 2 && (((J & top) != 0) != (h == 1))) continue;
+          const int j = rlo[J & 255] + rhi[(J >> 8) * 17 + __builtin_popcount(J & 255)] - (int)j0;
+          const V a = lrow[j];
+          const int lo = p < q ? p : q, hi = p < q ? q : p;
+          const uint32_t mid = (hi - lo > 1) ? (I >> (lo + 1)) & ((1u << (hi - lo - 1)) - 1) : 0u;
+          const double ax = a.x, ay = a.y;
+          double sr = ax * bx + ay * by, si = ax * by - ay * bx;
+          if (__builtin_popcount(mid) & 1) {
+            sr = -sr;
+            si = -si;
+          }
+          ar[p] += sr;
+          ai[p] += si;
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < kRdmMaxOrb; ++p) {
+        double x = ar[p], y = ai[p];
+        for (int o = 32; o > 0; o >>= 1) {
+          x += __shfl_xor(x, o);
+          y += __shfl_xor(y, o);
+        }
+        if (lane == 0 && p < norb) {
+          T[2 * (p * norb + q)] += x;
+          T[2 * (p * norb + q) + 1] += y;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int pq = threadIdx.x; pq < NN; pq += blockDim.x) {
+    part[2 * ((int64_t)pq * rows + row)] = T[2 * pq];
+    part[2 * ((int64_t)pq * rows + row) + 1] = T[2 * pq + 1];
+  }
+}
+
+size_t rdm_lds_bytes(bool c64, int64_t cols, int64_t split, int halves) {
+  const int64_t len = halves == 1 ? cols : std::max(split, cols - split);
+  return (size_t)len * (c64 ? 8 : 16);
+}
+
+void rdm_lds(bool c64, const void* lam, const void* psi, int64_t rows, int64_t cols, const uint32_t* masks,
+             int norb, int halves, int64_t split, const int* rank_lo, const int* rank_hi, const int* with_q,
+             const int* with_q_off, double* part, hipStream_t s) {
+  const size_t lds = rdm_lds_bytes(c64, cols, split, halves);
+  if (c64) {
+    static bool set = false;
+    if (!set) {
+      (void)hipFuncSetAttribute((const void*)k_rdm_lds<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                128 * 1024);
+      (void)hipGetLastError();
+      set = true;
+    }
+    hipLaunchKernelGGL(k_rdm_lds<float>, dim3((unsigned)rows), dim3(512), lds, s, (const zc64*)lam,
+                       (const zc64*)psi, rows, cols, masks, norb, halves, split, rank_lo, rank_hi, with_q, with_q_off, part);
+  } else {
+    static bool set = false;
+    if (!set) {
+      (void)hipFuncSetAttribute((const void*)k_rdm_lds<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                128 * 1024);
+      (void)hipGetLastError();
+      set = true;
+    }
+    hipLaunchKernelGGL(k_rdm_lds<double>, dim3((unsigned)rows), dim3(512), lds, s, (const zc128*)lam,
+                       (const zc128*)psi, rows, cols, masks, norb, halves, split, rank_lo, rank_hi, with_q, with_q_off,
+                       part);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_rdm_reduce(const double* __restrict__ part, int64_t rows,

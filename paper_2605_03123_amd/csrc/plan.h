@@ -115,6 +115,13 @@ struct ffx_plan_s {
   // (programs run one after another on the stream).  Growing frees the old
   // arena, so a driver that compiles several programs before running them must
   // stay within the initial size (kArenaSlots states' worth of string tables).
+  // colex rank of a mask by bytes (norb <= 16), built on first use:
+  // rank = rank_lo[m & 255] + rank_hi[(m >> 8) * 17 + popcount(m & 255)]
+  int* rank_lo = nullptr;
+  int* rank_hi = nullptr;
+  // per spin: the strings holding orbital q, for q = 0 .. norb-1 (offsets norb + 1)
+  int* with_q[2] = {nullptr, nullptr};
+  int* with_q_off[2] = {nullptr, nullptr};
   // when set, compile_program takes its table arena from this hook instead
   double* (*arena_hook)(void* ctx, size_t doubles) = nullptr;
   void* arena_ctx = nullptr;

@@ -31,14 +31,15 @@ namespace ffx {
 namespace dev {
 
 // 12 waves per block (3 per SIMD): the widest register windows (W = 7 at
-// complex64, W = 6 at complex128) fit in the 168 registers this leaves a lane
-template <class R>
+// complex64, W = 6 at complex128) fit in the 168 registers this leaves a lane;
+// narrower windows fit in 128 registers and run 16 waves
+template <int W, class R>
 constexpr int seg_threads() {
-  return 768;
+  return (sizeof(R) == 4 ? W <= 6 : W <= 5) ? 1024 : 768;
 }
 
 template <int W, bool REAL, class R>
-__global__ __launch_bounds__(seg_threads<R>()) void k_seg_pass(SegPassDev P) {
+__global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P) {
   using V = typename V2T<R>::type;
   extern __shared__ __align__(16) char smem[];
   V* row = (V*)smem;
@@ -218,7 +219,7 @@ static void launch_seg(const SegPassDev& p, int threads, size_t lds, hipStream_t
     attr_set = true;
   }
   const int64_t blocks = p.n_rows * p.n_seg;
-  hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(std::min(threads, seg_threads<R>())), lds, s, p);
+  hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(std::min(threads, seg_threads<W, R>())), lds, s, p);
 }
 
 template <bool REAL, class R>

@@ -280,13 +280,21 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
       ss.n_seg = (int)segs.size();
       ss.max_len = 0;
       ss.max_mt = 0;
+      for (const auto& sg : segs) ss.max_len = std::max(ss.max_len, sg.second);
+      ss.threads = ss.max_len >= 4096 ? 1024 : (ss.max_len >= 1024 ? 256 : 64);
+      if (const char* e = std::getenv("FFX_SEG_THREADS")) {  // block size override, for tuning
+        int v = std::atoi(e);
+        if (v >= 64 && v <= 1024 && v % 64 == 0) ss.threads = v;
+      }
+      ss.threads = dev::seg_pass_threads(P->c64, ss.Wseg, ss.threads);
       std::vector<dev::SegDev> hsegs;
       for (size_t g = 0; g < segs.size(); ++g) {
         const auto& sg = segs[g];
         ss.max_len = std::max(ss.max_len, sg.second);
         std::vector<dev::SegWinDev> wins;
         std::vector<int> mt_all;
-        for (const SegWindowTable& t : tabs[g]) {
+        for (SegWindowTable& t : tabs[g]) {
+          balance_seg_window(t, ss.Wseg, ss.threads / 64);
           dev::SegWinDev wd{};
           int* code = (int*)P->dalloc(std::max<size_t>(t.code.size(), 1) * 4);
           int* cm = (int*)P->dalloc(std::max<size_t>(t.chunk_m.size(), 1) * 4);
@@ -312,7 +320,6 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
       ss.d_segs = (dev::SegDev*)P->dalloc(hsegs.size() * sizeof(dev::SegDev));
       HIPCHK(hipMemcpy(ss.d_segs, hsegs.data(), hsegs.size() * sizeof(dev::SegDev), hipMemcpyHostToDevice));
       ss.lds = dev::seg_pass_lds(P->c64, ss.max_len, ss.max_mt);
-      ss.threads = ss.max_len >= 4096 ? 1024 : (ss.max_len >= 1024 ? 256 : 64);  // capped by the kernel
       // rows of this column spin's layout times segments: one partial sum per block
       max_rows_x_seg = std::max<int>(max_rows_x_seg, (int)(P->dim[1 - s] * ss.n_seg));
     }

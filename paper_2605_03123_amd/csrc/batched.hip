@@ -373,14 +373,8 @@ __device__ __forceinline__ void seg_task(const BatchDev& B, const BPassDev& ps, 
     const StageDev st = uniform_load(ps.stages + si);
     if (st.type == ST_GIVENS) {
       const SegWinDev wt = uniform_load(pick2(ty.win, cs) + st.a);
-      const int* mw = L.mt + wt.mt_off;
       const RotLane<R> rl = load_rot_lane<R>(st.rots, st.nrot, lane);
-      for (int ch = wave; ch < wt.n_chunks; ch += nwaves) {
-        const int m = __builtin_amdgcn_readfirstlane(wt.chunk_m[ch]);
-        const int code = wt.code[ch * 64 + lane];
-        if (code >= 0)
-          lds_m<W, REAL, R>(m, buf, code >> 5, L.mt, wt.mt_off + mw[m * wt.nl1 + (code & 31)], rl, st.nrot);
-      }
+      givens_stage<W, REAL, R>(st.shape, buf, L.mt, wt, rl, st.nrot, wave, nwaves, lane);
     } else {
       // per row: cross weights w_r[q] = sum_{p in row} C[p][q] and the row factor
       for (int i = tid; i < nr * N; i += nthr) {

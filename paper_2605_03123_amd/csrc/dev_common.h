@@ -227,6 +227,23 @@ __device__ __forceinline__ void apply_rots_lane(typename V2T<R>::type* v, const 
   }
 }
 
+// The rotations of stage shape S, positions fixed at compile time: rotation i
+// takes its parameters from lane i and acts on window position kShapeP[S][i].
+template <int W, int M, bool REAL, class R, int S, int I>
+__device__ __forceinline__ void shape_rot(typename V2T<R>::type* v, const RotLane<R>& rl) {
+  rot_one<W, M, kShapeP[S][I], REAL, R>(v, lane_bcast(rl.c, I), lane_bcast(rl.sr, I),
+                                        REAL ? R(0) : lane_bcast(rl.si, I));
+  // rotation parameters are broadcast next to their use: hoisting the
+  // broadcasts of later rotations only holds scalar registers
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int W, int M, bool REAL, class R, int S, int... I>
+__device__ __forceinline__ void apply_shape(typename V2T<R>::type* v, const RotLane<R>& rl,
+                                            std::integer_sequence<int, I...>) {
+  (shape_rot<W, M, REAL, R, S, I>(v, rl), ...);
+}
+
 // Loads a small struct of uniform data as scalars (every 32-bit word through
 // readfirstlane), so that branches on its fields are scalar branches.
 template <class T>
@@ -238,6 +255,25 @@ __device__ __forceinline__ T uniform_load(const T* p) {
 #pragma unroll
   for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
   return out;
+}
+
+// Block-wide copies between global memory and LDS with U independent loads in
+// flight per thread (a plain strided loop waits for every load before the
+// next one is issued, which leaves a block with one row in LDS idle for most
+// of its staging).
+template <int U, class V>
+__device__ __forceinline__ void stage_in(V* __restrict__ dst, const V* __restrict__ src, int len, int tid,
+                                         int nthr) {
+  for (int e0 = tid; e0 < len; e0 += U * nthr) {
+    V t[U];
+    // indexes past the end are clamped to the last element: they re-read it
+    // and store the same value again, so no load or store is conditional (a
+    // conditional store lets the compiler sink its load behind the branch)
+#pragma unroll
+    for (int u = 0; u < U; ++u) t[u] = src[min(e0 + u * nthr, len - 1)];
+#pragma unroll
+    for (int u = 0; u < U; ++u) dst[min(e0 + u * nthr, len - 1)] = t[u];
+  }
 }
 
 template <class R>
@@ -284,7 +320,7 @@ __device__ __forceinline__ int pick(const int4& q) {
   return q.w;
 }
 
-template <int W, int M, bool REAL, class R, int... K>
+template <int W, int M, bool REAL, class R, int S, int... K>
 __device__ __forceinline__ void lds_class(typename V2T<R>::type* __restrict__ row, int cbase, const int* mtl,
                                           int moff, const RotLane<R>& rl, int nrot,
                                           std::integer_sequence<int, K...>) {
@@ -299,7 +335,13 @@ __device__ __forceinline__ void lds_class(typename V2T<R>::type* __restrict__ ro
     for (int i = 0; i < Q; ++i) q[i] = m4[i];
     ((v[K] = row[cbase + pick<K>(q[K >> 2])]), ...);
   }
-  apply_rots_lane<W, M, REAL, R>(v, rl, nrot);
+  if constexpr (S < 0)
+    apply_rots_lane<W, M, REAL, R>(v, rl, nrot);
+  else
+    apply_shape<W, M, REAL, R, S>(v, rl, std::make_integer_sequence<int, kShapeLen[S]>{});
+  // nothing of the store-back (the offset reloads in particular) is scheduled
+  // into the straight-line rotations, where it would only hold registers
+  __builtin_amdgcn_sched_barrier(0);
   // member offsets are re-read from LDS rather than held in registers across
   // the rotations: hiding the table offset from the optimizer forces the reload
   {
@@ -313,14 +355,42 @@ __device__ __forceinline__ void lds_class(typename V2T<R>::type* __restrict__ ro
   }
 }
 
-template <int W, bool REAL, class R, int M = 1>
+template <int W, bool REAL, class R, int S = -1, int M = 1>
 __device__ __forceinline__ void lds_m(int m, typename V2T<R>::type* row, int cbase, const int* mtl, int moff,
                                       const RotLane<R>& rl, int nrot) {
   if constexpr (M < W) {
     if (m == M)
-      lds_class<W, M, REAL, R>(row, cbase, mtl, moff, rl, nrot, std::make_integer_sequence<int, cbinom(W, M)>{});
+      lds_class<W, M, REAL, R, S>(row, cbase, mtl, moff, rl, nrot, std::make_integer_sequence<int, cbinom(W, M)>{});
     else
-      lds_m<W, REAL, R, M + 1>(m, row, cbase, mtl, moff, rl, nrot);
+      lds_m<W, REAL, R, S, M + 1>(m, row, cbase, mtl, moff, rl, nrot);
+  }
+}
+
+// One Givens stage over the chunks of a window table: wave w takes chunks
+// w, w + nwaves, ...; lane l the class code[ch * 64 + l] (negative: none).
+// A stage of shape S (uniform; -1 = none) runs that shape's straight-line code.
+template <int W, bool REAL, class R, int S>
+__device__ __forceinline__ void givens_chunks(typename V2T<R>::type* row, const int* mtl, const SegWinDev& wt,
+                                              const RotLane<R>& rl, int nrot, int wave, int nwaves, int lane) {
+  const int* mw = mtl + wt.mt_off;
+  for (int ch = wave; ch < wt.n_chunks; ch += nwaves) {
+    const int m = __builtin_amdgcn_readfirstlane(wt.chunk_m[ch]);
+    const int code = wt.code[ch * 64 + lane];
+    if (code >= 0) lds_m<W, REAL, R, S>(m, row, code >> 5, mtl, wt.mt_off + mw[m * wt.nl1 + (code & 31)], rl, nrot);
+  }
+}
+
+template <int W, bool REAL, class R, int S = 0>
+__device__ __forceinline__ void givens_stage(int shape, typename V2T<R>::type* row, const int* mtl,
+                                             const SegWinDev& wt, const RotLane<R>& rl, int nrot, int wave,
+                                             int nwaves, int lane) {
+  if constexpr (W == kShapeW && S < kNumShapes) {
+    if (shape == S)
+      givens_chunks<W, REAL, R, S>(row, mtl, wt, rl, nrot, wave, nwaves, lane);
+    else
+      givens_stage<W, REAL, R, S + 1>(shape, row, mtl, wt, rl, nrot, wave, nwaves, lane);
+  } else {
+    givens_chunks<W, REAL, R, -1>(row, mtl, wt, rl, nrot, wave, nwaves, lane);
   }
 }
 

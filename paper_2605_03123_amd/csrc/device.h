@@ -132,6 +132,30 @@ constexpr int kMaxStageRots = 64;  // rotations per Givens stage of a segment pa
 
 enum StageType { ST_GIVENS = 0, ST_PHASE = 1, ST_SCALE = 2, ST_REDUCE = 3 };
 
+// Stage shapes: the window positions, in order, of the rotations of the
+// Givens stages that the window scheduler cuts from the column-elimination
+// network at window width 6 (the full triangle of a 6-orbital window, the
+// 3 x 3 parallelogram that sweeps a window across the network, with and
+// without its tail, the descending diagonal at the end, and the forms that
+// appear at small norb).  A stage whose rotation list is one of these runs
+// straight-line code with the positions fixed at compile time; any other
+// stage runs the generic loop that selects each rotation's position at run
+// time.
+constexpr int kShapeW = 6;
+constexpr int kNumShapes = 8;
+constexpr int kShapeMaxLen = 15;
+constexpr int kShapeLen[kNumShapes] = {15, 9, 12, 5, 4, 8, 5, 9};
+constexpr int kShapeP[kNumShapes][kShapeMaxLen] = {
+    {0, 1, 2, 3, 4, 0, 1, 2, 3, 0, 1, 2, 0, 1, 0},
+    {2, 3, 4, 1, 2, 3, 0, 1, 2},
+    {2, 3, 4, 1, 2, 3, 0, 1, 2, 0, 1, 0},
+    {4, 3, 2, 1, 0},
+    {3, 2, 1, 0},
+    {3, 4, 2, 3, 1, 2, 0, 1},
+    {1, 2, 0, 1, 0},
+    {3, 4, 2, 3, 1, 2, 0, 1, 0},
+};
+
 // f(row, col) = A[row] + B[col] + sum_{p in row, q in col} C[p * norb + q]
 //   ST_PHASE : x *= (-1)^{|row & sign_row|} exp(i (scale (A[row] + cross) + sum_{p in row} drow[p]))
 //                   * colf[col]
@@ -146,6 +170,8 @@ struct StageDev {
   int a;
   int nrot;
   uint32_t sign_row;
+  int shape;  // ST_GIVENS: index into the stage shapes, or -1
+  int pad;
   const RotDev* rots;
   double scale;
   const double* A;
@@ -296,6 +322,9 @@ void batch_launch(bool c64, const BatchDev& b, int blocks, int threads, size_t l
 void batch_launch_level(bool c64, const BatchDev& b, int p0, int p1, int64_t tasks, size_t lds, hipStream_t s);
 
 size_t seg_pass_lds(bool c64, int max_len, int max_mt);
+// block size a segment pass launches with for a requested size (the kernel's
+// register budget caps it)
+int seg_pass_threads(bool c64, int W, int requested);
 // blocks = n_rows * n_seg; partials (if any stage reduces) get one entry per block
 void seg_pass(bool c64, bool real, int W, const SegPassDev& p, int block_threads, size_t lds_bytes,
               hipStream_t stream);

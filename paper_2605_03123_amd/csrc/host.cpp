@@ -278,6 +278,45 @@ SegWindowTable build_seg_window(const std::vector<uint64_t>& seg, int wt, int a,
   return t;
 }
 
+void balance_seg_window(SegWindowTable& t, int w, int nwaves) {
+  constexpr int kSimds = 4;
+  if (nwaves < kSimds || nwaves % kSimds != 0 || t.chunk_m.empty()) return;
+  const int wps = nwaves / kSimds;
+  // work of one chunk in VALU issue slots for a typical stage of 10 rotations:
+  // per rotation 8 per member pair plus about 10 for the broadcast and the
+  // dispatch, and about 4 per member for the LDS round trip
+  auto work = [&](int m) { return 10.0 * (8.0 * (double)binom(w - 2, m - 1) + 10.0) + 4.0 * (double)binom(w, m); };
+  const int n = (int)t.chunk_m.size();
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(t.chunk_m[x]) > work(t.chunk_m[y]); });
+  std::vector<double> load(kSimds, 0.0);
+  std::vector<std::vector<int>> on(kSimds);
+  for (int i : order) {
+    int s = 0;
+    for (int k = 1; k < kSimds; ++k)
+      if (load[k] < load[s]) s = k;
+    load[s] += work(t.chunk_m[i]);
+    on[s].push_back(i);
+  }
+  // chunk j of SIMD s goes to wave s + 4 (j % wps), round j / wps
+  size_t rounds = 0;
+  for (int s = 0; s < kSimds; ++s) rounds = std::max(rounds, (on[s].size() + wps - 1) / wps);
+  std::vector<int> slot(rounds * nwaves, -1);
+  for (int s = 0; s < kSimds; ++s)
+    for (size_t j = 0; j < on[s].size(); ++j)
+      slot[(j / wps) * nwaves + s + kSimds * (j % wps)] = on[s][j];
+  while (!slot.empty() && slot.back() < 0) slot.pop_back();
+  SegWindowTable o;
+  o.nl1 = t.nl1;
+  o.mt = std::move(t.mt);
+  for (int c : slot) {
+    o.chunk_m.push_back(c < 0 ? 1 : t.chunk_m[c]);
+    for (int j = 0; j < 64; ++j) o.code.push_back(c < 0 ? -1 : t.code[(size_t)c * 64 + j]);
+  }
+  t = std::move(o);
+}
+
 SegWindowTable replicate_seg_window(const SegWindowTable& t, int w, int R, int row_len) {
   SegWindowTable o;
   o.nl1 = t.nl1;

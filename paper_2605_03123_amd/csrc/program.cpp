@@ -68,6 +68,18 @@ std::vector<int> take_window(const std::vector<Givens>& rots, const std::vector<
   return out;
 }
 
+// index of the stage shape whose position list equals the stage's, or -1
+int stage_shape(const std::vector<dev::RotDev>& rots, int w) {
+  if (w != dev::kShapeW) return -1;
+  for (int k = 0; k < dev::kNumShapes; ++k) {
+    if ((int)rots.size() != dev::kShapeLen[k]) continue;
+    bool same = true;
+    for (size_t i = 0; i < rots.size() && same; ++i) same = rots[i].p == dev::kShapeP[k][i];
+    if (same) return k;
+  }
+  return -1;
+}
+
 }  // namespace
 
 Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int final_mode, hipStream_t s) {
@@ -253,6 +265,7 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
           st.type = dev::ST_GIVENS;
           st.a = best_a;
           st.nrot = (int)buf.size();
+          st.shape = stage_shape(buf, ss.Wseg);
           st.rots = up.put(buf.data(), buf.size());
           stages.push_back(st);
           cur.real = cur.real && d.real;

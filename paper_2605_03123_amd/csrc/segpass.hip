@@ -60,8 +60,8 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
   const int nwaves = nthr >> 6;
 
   const V* src = (const V*)P.src + r * P.row_len + sg.off;
-  for (int e = tid; e < sg.len; e += nthr) row[e] = src[e];
-  for (int i = tid; i < sg.n_mt_all; i += nthr) mtl[i] = sg.mt_all[i];
+  stage_in<128 / sizeof(V)>(row, src, sg.len, tid, nthr);
+  stage_in<4>(mtl, sg.mt_all, sg.n_mt_all, tid, nthr);
   __syncthreads();
 
   const uint32_t rmask = P.row_masks[r];
@@ -73,14 +73,8 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
     const StageDev st = uniform_load(P.stages + s);
     if (st.type == ST_GIVENS) {
       const SegWinDev wt = uniform_load(sg.win + st.a);
-      const int* mw = mtl + wt.mt_off;
       const RotLane<R> rl = load_rot_lane<R>(st.rots, st.nrot, lane);
-      for (int ch = wave; ch < wt.n_chunks; ch += nwaves) {
-        const int m = __builtin_amdgcn_readfirstlane(wt.chunk_m[ch]);
-        const int code = wt.code[ch * 64 + lane];
-        if (code >= 0)
-          lds_m<W, REAL, R>(m, row, code >> 5, mtl, wt.mt_off + mw[m * wt.nl1 + (code & 31)], rl, st.nrot);
-      }
+      givens_stage<W, REAL, R>(st.shape, row, mtl, wt, rl, st.nrot, wave, nwaves, lane);
     } else {
       // cross weights w[q] = sum_{p in row} C[p][q]
       if (tid < P.norb) {
@@ -153,7 +147,7 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
   if (P.mode != SEG_NONE) {
     V* dst = (V*)P.dst + r * P.row_len + sg.off;
     if (P.mode == SEG_STORE) {
-      for (int e = tid; e < sg.len; e += nthr) dst[e] = row[e];
+      stage_in<128 / sizeof(V)>(dst, row, sg.len, tid, nthr);
     } else {
       for (int e = tid; e < sg.len; e += nthr) {
         V a = dst[e], b = row[e];
@@ -208,6 +202,12 @@ size_t seg_pass_lds(bool c64, int max_len, int max_mt) {
   size_t row = (size_t)max_len * (c64 ? 8 : 16);
   row = (row + 15) & ~(size_t)15;
   return row + 4 * 256 * sizeof(zc128) + (size_t)((max_mt + 3) & ~3) * sizeof(int) + (32 + 16) * sizeof(double);
+}
+
+int seg_pass_threads(bool c64, int W, int requested) {
+  const int cap = c64 ? (W <= 6 ? seg_threads<6, float>() : seg_threads<7, float>())
+                      : (W <= 5 ? seg_threads<5, double>() : seg_threads<6, double>());
+  return std::min(requested, cap);
 }
 
 template <int W, bool REAL, class R>

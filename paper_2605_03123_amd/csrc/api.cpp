@@ -315,7 +315,41 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
           HIPCHK(hipMemcpy(dw, wins.data(), wins.size() * sizeof(dev::SegWinDev), hipMemcpyHostToDevice));
         int* dmt = (int*)P->dalloc(std::max<size_t>(mt_all.size(), 1) * 4);
         if (!mt_all.empty()) HIPCHK(hipMemcpy(dmt, mt_all.data(), mt_all.size() * 4, hipMemcpyHostToDevice));
-        hsegs.push_back(dev::SegDev{sg.first, sg.second, dw, dmt, (int)mt_all.size(), 0});
+        hsegs.push_back(dev::SegDev{sg.first, sg.second, dw, dmt, (int)mt_all.size(), 0, 0, 0, 0, 0});
+      }
+      // partner ranges of the crossing rotation on (wt - 1, wt): a segment whose
+      // high part H lacks wt pairs its strings holding wt - 1 (the last C(wt-1,
+      // k-1) of its C(wt, k)) with the first C(wt-1, k-1) strings of segment
+      // H + {wt}, which lack wt - 1; both ranges run in the colex order of the
+      // remaining k - 1 low orbitals
+      if (wt >= 1 && wt < norb && segs.size() > 1) {
+        std::map<uint64_t, int> by_high;
+        for (size_t g = 0; g < segs.size(); ++g) by_high[strs[segs[g].first] >> wt] = (int)g;
+        const int nc = s == 0 ? na : nb;
+        for (size_t g = 0; g < segs.size(); ++g) {
+          const uint64_t H = strs[segs[g].first] >> wt;
+          const int k = nc - __builtin_popcountll(H);
+          dev::SegDev& d = hsegs[g];
+          const bool holds_wt = H & 1;
+          const auto it = by_high.find(H ^ 1);
+          if (it == by_high.end()) continue;
+          const auto& pg = segs[it->second];
+          if (!holds_wt) {
+            if (k < 1) continue;
+            d.cross_role = 0;
+            d.cross_lo = (int)binom(wt - 1, k);
+            d.cross_cnt = (int)binom(wt - 1, k - 1);
+            d.cross_peer = pg.first;
+          } else {
+            d.cross_role = 1;
+            d.cross_lo = 0;
+            d.cross_cnt = (int)binom(wt - 1, k);
+            d.cross_peer = pg.first + (int)binom(wt - 1, k + 1);
+          }
+          if (d.cross_lo + d.cross_cnt > segs[g].second || d.cross_cnt > pg.second)
+            throw Error(FFX_EDEVICE, "segment crossing ranges out of bounds");
+          ss.cross = true;
+        }
       }
       ss.d_segs = (dev::SegDev*)P->dalloc(hsegs.size() * sizeof(dev::SegDev));
       HIPCHK(hipMemcpy(ss.d_segs, hsegs.data(), hsegs.size() * sizeof(dev::SegDev), hipMemcpyHostToDevice));

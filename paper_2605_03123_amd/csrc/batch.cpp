@@ -436,7 +436,7 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
       for (int k = 0; k < (int)c.launches.size(); ++k) {
         const Launch& Lc = c.launches[k];
         if (Lc.kind == Launch::TRANSPOSE) continue;
-        if (Lc.kind != Launch::SEG) throw Error(FFX_EUNSUPPORTED, "batched sector needs a window pass");
+        if (Lc.kind != Launch::SEG || Lc.cross) throw Error(FFX_EUNSUPPORTED, "batched sector needs a window pass");
         if (Lc.reduce) throw Error(FFX_EUNSUPPORTED, "batched programs do not reduce inside passes");
         dev::BPassDev p = base(dev::BK_SEG);
         p.layout = Lc.layout;

@@ -203,6 +203,12 @@ struct SegDev {
   const SegWinDev* win;
   const int* mt_all;  // member offsets of every window, staged into LDS once per block
   int n_mt_all;
+  // crossing rotation on (wt - 1, wt), the orbital pair that straddles the
+  // segment window: it pairs the strings [cross_lo, cross_lo + cross_cnt) of
+  // this segment elementwise with cross_cnt strings from column cross_peer on
+  // (same inner order); role 0: this side holds wt - 1 (x' = c x + s y),
+  // role 1: it holds wt (y' = c y - conj(s) x)
+  int cross_lo, cross_cnt, cross_peer, cross_role;
   int pad;
 };
 
@@ -227,6 +233,11 @@ struct SegPassDev {
   double* partials;
   int lds_row_bytes;  // byte offset of the scratch area after the row segment
   int max_mt;         // ints reserved in LDS for the member offsets of all windows
+  // when set, the crossing rotation (cross_c, cross_sr + i cross_si) is applied
+  // as the segment is loaded, reading the partner strings from src (which the
+  // pass must not overwrite: src != dst)
+  int cross;
+  double cross_c, cross_sr, cross_si;
 };
 
 // LDS needed by a segment pass whose longest segment holds max_len amplitudes

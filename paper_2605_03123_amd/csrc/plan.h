@@ -43,6 +43,7 @@ struct ffx_plan_s {
     int n_seg = 0;
     size_t lds = 0;
     int threads = 256;
+    bool cross = false;  // rotations on (wt - 1, wt) can be applied at segment load
     ffx::dev::SegDev* d_segs = nullptr;
   } seg[2];
   // parameter upload ring
@@ -257,6 +258,9 @@ struct Launch {
   double* reduce_out = nullptr;
   double valu_slots = 0;
   double rot_sides = 0;
+  // a rotation on the pair straddling the segment window, applied at load
+  bool cross = false;
+  dev::RotDev cross_rot{};
   // WIN
   int a = 0;
   const dev::RotDev* rots = nullptr;

@@ -216,7 +216,7 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
     cur.layout = layout;
     bool any = false;
     auto flush_seg = [&](bool force) {
-      if (stages.empty() && !force) return;
+      if (stages.empty() && !force && !cur.cross) return;
       cur.stages = stages.empty() ? nullptr : up.put(stages.data(), stages.size());
       cur.n_stages = (int)stages.size();
       c.launches.push_back(cur);
@@ -274,8 +274,29 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
           any = true;
         }
         if (n_done == d.rots.size()) break;
-        // rotations crossing segments: one whole-spin window pass
+        // a ready rotation on the pair straddling the segment window starts
+        // the next segment pass (applied as the segments are loaded)
         flush_seg(false);
+        if (ss.cross) {
+          int xi = -1;
+          for (size_t i = 0; i < d.rots.size() && xi < 0; ++i) {
+            if (done[i] || d.rots[i].p != ss.wt - 1) continue;
+            bool ready = true;
+            for (int dp : deps[i]) ready = ready && done[dp];
+            if (ready) xi = (int)i;
+          }
+          if (xi >= 0) {
+            const Givens& g = d.rots[xi];
+            cur.cross = true;
+            cur.cross_rot = dev::RotDev{0, 0, g.c, g.s.real(), g.s.imag()};
+            cur.valu_slots += pairs_per_row * (double)n_rows * (d.real ? 8.0 : 12.0);
+            cur.rot_sides += 1.0 / K;
+            done[xi] = 1;
+            ++n_done;
+            continue;
+          }
+        }
+        // other rotations crossing segments: one whole-spin window pass
         int best_a = -1;
         std::vector<int> best;
         for (int a = 0; a + P.W <= N; ++a) {
@@ -383,6 +404,33 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
     cur_src = work;
   }
   const bool square = da == db;
+  // Buffers: a segment pass with a crossing rotation must not write the
+  // buffer it reads, so it moves the state to the other of (work, tmp); a
+  // non-square transpose does as well.  When the state would end in tmp, one
+  // in-place segment pass moves it too, so that it ends in work.
+  const int nl = (int)c.launches.size();
+  std::vector<char> move(nl, 0);
+  auto simulate = [&]() {
+    bool at_src = src != work && nl > 0 && c.launches[0].kind == Launch::SEG;
+    bool in_work = true;  // where cur points
+    int last_plain = -1;
+    for (int i = 0; i < nl; ++i) {
+      const Launch& L = c.launches[i];
+      const bool store = L.kind == Launch::SEG && !(i == last_seg && c.final_mode != FINAL_STORE);
+      if (L.kind == Launch::SEG) {
+        if (store && !at_src && (L.cross || move[i])) in_work = !in_work;
+        if (store && !at_src && !L.cross) last_plain = i;
+        at_src = false;
+      } else if (L.kind == Launch::TRANSPOSE && !square) {
+        in_work = !in_work;
+      }
+    }
+    return std::make_pair(in_work, last_plain);
+  };
+  if (c.final_mode == FINAL_STORE) {
+    auto r = simulate();
+    if (!r.first && r.second >= 0) move[r.second] = 1;
+  }
   for (int i = 0; i < (int)c.launches.size(); ++i) {
     const Launch& L = c.launches[i];
     const int64_t rows = L.layout == 0 ? da : db;
@@ -415,6 +463,12 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
       p.partials = L.reduce ? P.partials : nullptr;
       p.lds_row_bytes = (int)(((size_t)ss.max_len * P.elem() + 15) & ~(size_t)15);
       p.max_mt = ss.max_mt;
+      if (L.cross) {
+        p.cross = 1;
+        p.cross_c = L.cross_rot.c;
+        p.cross_sr = L.cross_rot.sr;
+        p.cross_si = L.cross_rot.si;
+      }
       if (i == last_seg && c.final_mode == FINAL_ACCUM) {
         p.mode = dev::SEG_ACCUM;
         p.dst = accum;
@@ -423,8 +477,10 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
         p.dst = nullptr;
       } else {
         p.mode = dev::SEG_STORE;
+        if (cur_src == cur && (L.cross || move[i])) cur = (cur == work) ? P.tmp_state() : work;
         p.dst = cur;
       }
+      if (L.cross && p.dst == p.src) throw Error(FFX_EDEVICE, "crossing rotation needs an out-of-place pass");
       dev::seg_pass(P.c64, L.real, ss.Wseg, p, ss.threads, ss.lds, s);
       check_launch();
       if (L.reduce) {
@@ -452,6 +508,8 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
       P.timed.push_back(tm);
     }
   }
+  if (c.final_mode == FINAL_STORE && cur != work)
+    HIPCHK(hipMemcpyAsync(work, cur, P.state_bytes(), hipMemcpyDeviceToDevice, s));
 }
 
 }  // namespace ffx

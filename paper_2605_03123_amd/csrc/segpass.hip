@@ -38,6 +38,41 @@ constexpr int seg_threads() {
   return (sizeof(R) == 4 ? W <= 6 : W <= 5) ? 1024 : 768;
 }
 
+// The rotation on the orbital pair that straddles the segment window, for
+// the cnt strings own[0 .. cnt) of this segment and their partners peer[0 ..
+// cnt) in another segment of the same row (read from the pass's source, which
+// the pass does not write): role 0: own = x, x' = c x + s y; role 1: own = y,
+// y' = c y - conj(s) x.  The partner loads are all issued before any is used.
+template <class R>
+__device__ __forceinline__ void cross_rotate(typename V2T<R>::type* own, const typename V2T<R>::type* peer,
+                                             int cnt, int role, double cd, double srd, double sid, int tid,
+                                             int nthr) {
+  using V = typename V2T<R>::type;
+  constexpr int U = 8;
+  const R c = (R)cd, sr = (R)srd, si = role == 0 ? (R)sid : -(R)sid;
+  const R sgn = role == 0 ? R(1) : R(-1);
+  for (int e0 = tid; e0 < cnt; e0 += U * nthr) {
+    V t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      t[u] = peer[min(e0 + u * nthr, cnt - 1)];
+      asm volatile("" ::"v"(t[u].x), "v"(t[u].y));
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * nthr;
+      if (e < cnt) {
+        // own' = c own + sgn * s' peer, s' = s (role 0) or conj(s) (role 1)
+        const V a = own[e], b = t[u];
+        V o;
+        o.x = c * a.x + sgn * (sr * b.x - si * b.y);
+        o.y = c * a.y + sgn * (sr * b.y + si * b.x);
+        own[e] = o;
+      }
+    }
+  }
+}
+
 template <int W, bool REAL, class R>
 __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P) {
   using V = typename V2T<R>::type;
@@ -63,6 +98,11 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
   stage_in<128 / sizeof(V)>(row, src, sg.len, tid, nthr);
   stage_in<4>(mtl, sg.mt_all, sg.n_mt_all, tid, nthr);
   __syncthreads();
+  if (P.cross && sg.cross_cnt > 0) {
+    cross_rotate<R>(row + sg.cross_lo, (const V*)P.src + r * P.row_len + sg.cross_peer, sg.cross_cnt,
+                    sg.cross_role, P.cross_c, P.cross_sr, P.cross_si, tid, nthr);
+    __syncthreads();
+  }
 
   const uint32_t rmask = P.row_masks[r];
   const uint32_t* cmask = P.col_masks + sg.off;
@@ -76,16 +116,22 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
       const RotLane<R> rl = load_rot_lane<R>(st.rots, st.nrot, lane);
       givens_stage<W, REAL, R>(st.shape, row, mtl, wt, rl, st.nrot, wave, nwaves, lane);
     } else {
-      // cross weights w[q] = sum_{p in row} C[p][q]
+      // cross weights w[q] = sum_{p in row} C[p][q]: the row's masked C is
+      // staged in the table area (one load per thread, all in flight at once),
+      // then summed over p in a fixed order
+      const bool cross = st.C != nullptr;
+      const int nn = P.norb * P.norb;
+      if (cross) {
+        for (int i = tid; i < nn; i += nthr) tab[i] = ((rmask >> (i / P.norb)) & 1) ? st.C[i] : 0.0;
+        __syncthreads();
+      }
       if (tid < P.norb) {
         double w = 0.0;
-        if (st.C)
-          for (int p = 0; p < P.norb; ++p)
-            if ((rmask >> p) & 1) w += st.C[p * P.norb + tid];
+        if (cross)
+          for (int p = 0; p < P.norb; ++p) w += tab[p * P.norb + tid];
         wq[tid] = w;
       }
       __syncthreads();
-      const bool cross = st.C != nullptr;
       if (cross) {
         for (int i = tid; i < nbytes * 256; i += nthr) {
           const int k = i >> 8, b = i & 255;
@@ -111,32 +157,64 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
           rowf.y = -rowf.y;
         }
         const zc128* colf = st.colf ? (const zc128*)st.colf + sg.off : nullptr;
-        for (int e = tid; e < sg.len; e += nthr) {
-          zc128 f = colf ? zmul(rowf, colf[e]) : rowf;
-          if (cross) {
-            const uint32_t cm = cmask[e];
-            for (int k = 0; k < nbytes; ++k) f = zmul(f, ez[(k << 8) | ((cm >> (8 * k)) & 255)]);
+        // U elements per thread at a time: their column masks and factors are
+        // all requested before the first is used
+        constexpr int U = 4;
+        const zc128 one{1.0, 0.0};
+        for (int e0 = tid; e0 < sg.len; e0 += U * nthr) {
+          uint32_t cm[U];
+          zc128 cf[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int e = min(e0 + u * nthr, sg.len - 1);
+            cm[u] = cross ? cmask[e] : 0u;
+            cf[u] = colf ? colf[e] : one;
+            asm volatile("" ::"v"(cm[u]), "v"(cf[u].x), "v"(cf[u].y));
           }
-          V y = row[e];
-          V o;
-          o.x = (R)((double)y.x * f.x - (double)y.y * f.y);
-          o.y = (R)((double)y.x * f.y + (double)y.y * f.x);
-          row[e] = o;
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * nthr;
+            if (e < sg.len) {
+              zc128 f = zmul(rowf, cf[u]);
+              if (cross)
+                for (int k = 0; k < nbytes; ++k) f = zmul(f, ez[(k << 8) | ((cm[u] >> (8 * k)) & 255)]);
+              V y = row[e];
+              V o;
+              o.x = (R)((double)y.x * f.x - (double)y.y * f.y);
+              o.y = (R)((double)y.x * f.y + (double)y.y * f.x);
+              row[e] = o;
+            }
+          }
         }
       } else {
-        for (int e = tid; e < sg.len; e += nthr) {
-          double f = arow + (st.B ? st.B[sg.off + e] : 0.0);
-          if (cross) {
-            const uint32_t cm = cmask[e];
-            for (int k = 0; k < nbytes; ++k) f += tab[(k << 8) | ((cm >> (8 * k)) & 255)];
+        constexpr int U = 4;
+        const double* Bs = st.B ? st.B + sg.off : nullptr;
+        for (int e0 = tid; e0 < sg.len; e0 += U * nthr) {
+          uint32_t cm[U];
+          double fb[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int e = min(e0 + u * nthr, sg.len - 1);
+            cm[u] = cross ? cmask[e] : 0u;
+            fb[u] = Bs ? Bs[e] : 0.0;
+            asm volatile("" ::"v"(cm[u]), "v"(fb[u]));
           }
-          V y = row[e];
-          if (st.type == ST_SCALE) {
-            y.x = (R)(f * (double)y.x);
-            y.y = (R)(f * (double)y.y);
-            row[e] = y;
-          } else {
-            acc += f * ((double)y.x * (double)y.x + (double)y.y * (double)y.y);
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * nthr;
+            if (e < sg.len) {
+              double f = arow + fb[u];
+              if (cross)
+                for (int k = 0; k < nbytes; ++k) f += tab[(k << 8) | ((cm[u] >> (8 * k)) & 255)];
+              V y = row[e];
+              if (st.type == ST_SCALE) {
+                y.x = (R)(f * (double)y.x);
+                y.y = (R)(f * (double)y.y);
+                row[e] = y;
+              } else {
+                acc += f * ((double)y.x * (double)y.x + (double)y.y * (double)y.y);
+              }
+            }
           }
         }
       }

@@ -264,6 +264,33 @@ def test_segmented_paths(ffx, small_segment_plans):
         assert _maxdiff(out, ol.apply_lucj(params, norb, nelec, 2)) <= TOL[dtype]
 
 
+def test_segmented_paths_in_place_and_gradients(ffx, small_segment_plans):
+    # crossing rotations move the state between the working buffers; in-place
+    # calls must still end in the caller's buffer, and the adjoint gradient runs
+    # programs that end in accumulation or in a reduction only
+    for (norb, nelec, dtype), plan in small_segment_plans.items():
+        r = synth.rng([22, norb])
+        da, db = _dims(norb, nelec)
+        vec = _to_dev(synth.random_state(r, da, db), dtype)
+        x = _ref_input(vec)
+        ref = x
+        for k in range(3):
+            U = synth.random_unitary(r, norb)
+            ffx.apply_orbital_rotation(vec, U, norb, nelec, out=vec, plan=plan)
+            ref = og.apply_orbital_rotation(ref, U, norb, nelec)
+            assert _maxdiff(vec, ref) <= TOL[dtype] * (k + 1)
+        ham = synth.df_hamiltonian(r, norb, 2)
+        ffx.simulate_trotter_double_factorized(vec, ham, 0.1, norb, nelec, n_steps=1, order=0, out=vec, plan=plan)
+        ref = oh.simulate_trotter(ref, ham, 0.1, norb, nelec, n_steps=1, order=0)
+        assert _maxdiff(vec, ref) <= TOL[dtype] * 10
+        params = synth.lucj_params(r, norb, 2, scale=0.3)
+        e, g = ffx.lucj_energy_grad(params, ham, norb, nelec, 2, dtype=dtype, plan=plan)
+        eo, go = ol.grad_adjoint(params, ham, norb, nelec, 2)
+        tol = 1e-10 if dtype == torch.complex128 else 1e-4
+        assert abs(e - float(np.real(eo))) <= tol * max(1.0, abs(float(np.real(eo))))
+        assert np.max(np.abs(g - go)) <= tol * max(1.0, np.max(np.abs(go)))
+
+
 def test_lucj_energy_grad_returns_the_ansatz_state(ffx):
     # psi_out receives psi(theta) even though the reverse sweep uncomputes its own copy
     norb, nelec, n_reps = 6, (3, 3), 2

@@ -241,6 +241,12 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
       int64_t v = std::atoll(e);
       if (v >= 1 && v < max_elems) max_elems = v;
     }
+    // lanes per LDS access cycle for the class loads: 128 bytes per cycle
+    int lds_group = 128 / (int)P->elem();
+    if (const char* e = std::getenv("FFX_LDS_GROUP_BYTES")) {  // tuning knob (0: address order)
+      const int v = std::atoi(e);
+      if (v >= 0 && v <= 1024) lds_group = v / (int)P->elem();
+    }
     int max_rows_x_seg = 0;
     for (int s = 0; s < 2; ++s) {
       auto& ss = P->seg[s];
@@ -267,7 +273,7 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
           std::vector<uint64_t> sub(strs.begin() + segs[g].first, strs.begin() + segs[g].first + segs[g].second);
           size_t mt = 0;
           for (int a = 0; Wseg >= 2 && a + Wseg <= wt; ++a) {
-            tabs[g].push_back(build_seg_window(sub, wt, a, Wseg));
+            tabs[g].push_back(build_seg_window(sub, wt, a, Wseg, lds_group));
             mt = ((mt + 3) & ~(size_t)3) + tabs[g].back().mt.size();
           }
           need = std::max(need, dev::seg_pass_lds(P->c64, segs[g].second, (int)mt));

@@ -374,7 +374,8 @@ __device__ __forceinline__ void seg_task(const BatchDev& B, const BPassDev& ps, 
     if (st.type == ST_GIVENS) {
       const SegWinDev wt = uniform_load(pick2(ty.win, cs) + st.a);
       const RotLane<R> rl = load_rot_lane<R>(st.rots, st.nrot, lane);
-      givens_stage<W, REAL, R>(st.shape, buf, L.mt, wt, rl, st.nrot, wave, nwaves, lane);
+      givens_stage<W, REAL, R>(st.shape, buf, L.mt, wt, rl, st.nrot, wave, nwaves, lane,
+                               fetch_first_chunk(wt, wave, lane));
     } else {
       // per row: cross weights w_r[q] = sum_{p in row} C[p][q] and the row factor
       for (int i = tid; i < nr * N; i += nthr) {

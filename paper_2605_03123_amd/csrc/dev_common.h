@@ -244,16 +244,21 @@ __device__ __forceinline__ void apply_shape(typename V2T<R>::type* v, const RotL
   (shape_rot<W, M, REAL, R, S, I>(v, rl), ...);
 }
 
-// Loads a small struct of uniform data as scalars (every 32-bit word through
-// readfirstlane), so that branches on its fields are scalar branches.
+// Loads a small struct of uniform, read-only data (descriptor tables written
+// before the launch) with scalar memory loads: the address is taken as a
+// constant-address-space pointer, so the words arrive in scalar registers
+// through the scalar cache, which every block of a launch shares, instead of
+// one vector-memory round trip per struct; branches on its fields are scalar
+// branches.
 template <class T>
 __device__ __forceinline__ T uniform_load(const T* p) {
   static_assert(sizeof(T) % 4 == 0, "uniform_load needs whole 32-bit words");
+  using cint = const __attribute__((address_space(4))) int;
   T out;
-  const int* src = (const int*)p;
+  cint* src = (cint*)p;
   int* dst = (int*)&out;
 #pragma unroll
-  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = src[i];
   return out;
 }
 
@@ -369,13 +374,42 @@ __device__ __forceinline__ void lds_m(int m, typename V2T<R>::type* row, int cba
 // One Givens stage over the chunks of a window table: wave w takes chunks
 // w, w + nwaves, ...; lane l the class code[ch * 64 + l] (negative: none).
 // A stage of shape S (uniform; -1 = none) runs that shape's straight-line code.
+// A wave's first chunk of a Givens stage (its electron count in the window
+// and this lane's class code), requested ahead of the stage.
+struct ChunkAhead {
+  int m;
+  int code;
+};
+
+__device__ __forceinline__ ChunkAhead fetch_first_chunk(const SegWinDev& wt, int wave, int lane) {
+  ChunkAhead f{1, -1};
+  if (wave < wt.n_chunks) {
+    f.m = uniform_load(wt.chunk_m + wave);
+    f.code = wt.code[wave * 64 + lane];
+  }
+  return f;
+}
+
+// The rotations of a stage, one per lane (lanes past nrot repeat the last
+// one and are never read), loaded without a lane-dependent branch so that the
+// load can be issued a stage ahead of its use.
+template <class R>
+__device__ __forceinline__ RotLane<R> fetch_rot_lane(const RotDev* rots, int nrot, int lane) {
+  const RotDev g = rots[min(lane, nrot - 1)];
+  return RotLane<R>{g.p, (R)g.c, (R)g.sr, (R)g.si};
+}
+
 template <int W, bool REAL, class R, int S>
 __device__ __forceinline__ void givens_chunks(typename V2T<R>::type* row, const int* mtl, const SegWinDev& wt,
-                                              const RotLane<R>& rl, int nrot, int wave, int nwaves, int lane) {
+                                              const RotLane<R>& rl, int nrot, int wave, int nwaves, int lane,
+                                              ChunkAhead first) {
   const int* mw = mtl + wt.mt_off;
   for (int ch = wave; ch < wt.n_chunks; ch += nwaves) {
-    const int m = __builtin_amdgcn_readfirstlane(wt.chunk_m[ch]);
-    const int code = wt.code[ch * 64 + lane];
+    int m = first.m, code = first.code;
+    if (ch != wave) {
+      m = uniform_load(wt.chunk_m + ch);
+      code = wt.code[ch * 64 + lane];
+    }
     if (code >= 0) lds_m<W, REAL, R, S>(m, row, code >> 5, mtl, wt.mt_off + mw[m * wt.nl1 + (code & 31)], rl, nrot);
   }
 }
@@ -383,14 +417,14 @@ __device__ __forceinline__ void givens_chunks(typename V2T<R>::type* row, const 
 template <int W, bool REAL, class R, int S = 0>
 __device__ __forceinline__ void givens_stage(int shape, typename V2T<R>::type* row, const int* mtl,
                                              const SegWinDev& wt, const RotLane<R>& rl, int nrot, int wave,
-                                             int nwaves, int lane) {
+                                             int nwaves, int lane, ChunkAhead first) {
   if constexpr (W == kShapeW && S < kNumShapes) {
     if (shape == S)
-      givens_chunks<W, REAL, R, S>(row, mtl, wt, rl, nrot, wave, nwaves, lane);
+      givens_chunks<W, REAL, R, S>(row, mtl, wt, rl, nrot, wave, nwaves, lane, first);
     else
-      givens_stage<W, REAL, R, S + 1>(shape, row, mtl, wt, rl, nrot, wave, nwaves, lane);
+      givens_stage<W, REAL, R, S + 1>(shape, row, mtl, wt, rl, nrot, wave, nwaves, lane, first);
   } else {
-    givens_chunks<W, REAL, R, -1>(row, mtl, wt, rl, nrot, wave, nwaves, lane);
+    givens_chunks<W, REAL, R, -1>(row, mtl, wt, rl, nrot, wave, nwaves, lane, first);
   }
 }
 

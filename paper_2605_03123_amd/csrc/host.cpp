@@ -195,7 +195,7 @@ WindowTable build_window_table(const std::vector<uint64_t>& strs, int norb, int 
   return t;
 }
 
-SegWindowTable build_seg_window(const std::vector<uint64_t>& seg, int wt, int a, int w) {
+SegWindowTable build_seg_window(const std::vector<uint64_t>& seg, int wt, int a, int w, int group) {
   SegWindowTable t;
   const uint64_t low_mask = (wt >= 64) ? ~0ull : ((1ull << wt) - 1);
   const int n_low = seg.empty() ? 0 : __builtin_popcountll(seg[0] & low_mask);
@@ -252,9 +252,37 @@ SegWindowTable build_seg_window(const std::vector<uint64_t>& seg, int wt, int a,
     if (c.count != (int)binom(w, c.m)) throw Error(FFX_EDEVICE, "segment window table: incomplete class");
     by_m[c.m].push_back((c.cbase << 5) | c.l);
   }
-  // classes in order of their base address: neighbouring lanes then read
-  // neighbouring LDS words for the same member (fewer bank conflicts)
-  for (auto& kv : by_m) std::sort(kv.second.begin(), kv.second.end());
+  // lane order: classes with the same l (whose members sit at the same
+  // offsets from their bases) in groups of `group` lanes whose bases differ
+  // modulo `group`, so that the lanes of one LDS access cycle hit distinct
+  // banks for every member; otherwise in order of base address
+  for (auto& kv : by_m) {
+    std::vector<int>& v = kv.second;
+    std::sort(v.begin(), v.end());
+    if (group < 2) continue;
+    std::map<int, std::vector<int>> by_l;
+    for (int c : v) by_l[c & 31].push_back(c);
+    v.clear();
+    for (auto& lv : by_l) {
+      std::vector<int> pool = lv.second;
+      std::vector<char> taken(pool.size(), 0);
+      size_t left = pool.size();
+      while (left > 0) {
+        std::vector<char> used(group, 0);
+        int in_group = 0;
+        for (size_t i = 0; i < pool.size() && in_group < group; ++i) {
+          if (taken[i]) continue;
+          const int slot = (pool[i] >> 5) % group;
+          if (used[slot]) continue;
+          used[slot] = 1;
+          taken[i] = 1;
+          v.push_back(pool[i]);
+          ++in_group;
+          --left;
+        }
+      }
+    }
+  }
   struct Chunk {
     int m;
     double cost;

@@ -42,35 +42,40 @@ constexpr int seg_threads() {
 // the cnt strings own[0 .. cnt) of this segment and their partners peer[0 ..
 // cnt) in another segment of the same row (read from the pass's source, which
 // the pass does not write): role 0: own = x, x' = c x + s y; role 1: own = y,
-// y' = c y - conj(s) x.  The partner loads are all issued before any is used.
+// y' = c y - conj(s) x.  The first kCrossU partners of each thread are loaded
+// together with the segment itself (cross_fetch, before the barrier that
+// completes the segment); cross_apply then rotates, loading any further
+// partners directly.
+constexpr int kCrossU = 8;
+
+template <class V>
+__device__ __forceinline__ void cross_fetch(V* t, const V* peer, int cnt, int tid, int nthr) {
+#pragma unroll
+  for (int u = 0; u < kCrossU; ++u) t[u] = peer[min(tid + u * nthr, cnt - 1)];
+}
+
 template <class R>
-__device__ __forceinline__ void cross_rotate(typename V2T<R>::type* own, const typename V2T<R>::type* peer,
-                                             int cnt, int role, double cd, double srd, double sid, int tid,
-                                             int nthr) {
-  using V = typename V2T<R>::type;
-  constexpr int U = 8;
+__device__ __forceinline__ typename V2T<R>::type cross_rot(typename V2T<R>::type a, typename V2T<R>::type b, R c,
+                                                           R sgn, R sr, R si) {
+  // own' = c own + sgn * s' peer, s' = s (role 0) or conj(s) (role 1)
+  typename V2T<R>::type o;
+  o.x = c * a.x + sgn * (sr * b.x - si * b.y);
+  o.y = c * a.y + sgn * (sr * b.y + si * b.x);
+  return o;
+}
+
+template <class R>
+__device__ __forceinline__ void cross_apply(typename V2T<R>::type* own, const typename V2T<R>::type* t,
+                                            const typename V2T<R>::type* peer, int cnt, int role, double cd,
+                                            double srd, double sid, int tid, int nthr) {
   const R c = (R)cd, sr = (R)srd, si = role == 0 ? (R)sid : -(R)sid;
   const R sgn = role == 0 ? R(1) : R(-1);
-  for (int e0 = tid; e0 < cnt; e0 += U * nthr) {
-    V t[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      t[u] = peer[min(e0 + u * nthr, cnt - 1)];
-      asm volatile("" ::"v"(t[u].x), "v"(t[u].y));
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * nthr;
-      if (e < cnt) {
-        // own' = c own + sgn * s' peer, s' = s (role 0) or conj(s) (role 1)
-        const V a = own[e], b = t[u];
-        V o;
-        o.x = c * a.x + sgn * (sr * b.x - si * b.y);
-        o.y = c * a.y + sgn * (sr * b.y + si * b.x);
-        own[e] = o;
-      }
-    }
+  for (int u = 0; u < kCrossU; ++u) {
+    const int e = tid + u * nthr;
+    if (e < cnt) own[e] = cross_rot<R>(own[e], t[u], c, sgn, sr, si);
   }
+  for (int e = tid + kCrossU * nthr; e < cnt; e += nthr) own[e] = cross_rot<R>(own[e], peer[e], c, sgn, sr, si);
 }
 
 template <int W, bool REAL, class R>
@@ -95,12 +100,16 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
   const int nwaves = nthr >> 6;
 
   const V* src = (const V*)P.src + r * P.row_len + sg.off;
+  const bool xrot = P.cross && sg.cross_cnt > 0;
+  const V* peer = (const V*)P.src + r * P.row_len + sg.cross_peer;
+  V xt[kCrossU];
+  if (xrot) cross_fetch(xt, peer, sg.cross_cnt, tid, nthr);
   stage_in<128 / sizeof(V)>(row, src, sg.len, tid, nthr);
   stage_in<4>(mtl, sg.mt_all, sg.n_mt_all, tid, nthr);
   __syncthreads();
-  if (P.cross && sg.cross_cnt > 0) {
-    cross_rotate<R>(row + sg.cross_lo, (const V*)P.src + r * P.row_len + sg.cross_peer, sg.cross_cnt,
-                    sg.cross_role, P.cross_c, P.cross_sr, P.cross_si, tid, nthr);
+  if (xrot) {
+    cross_apply<R>(row + sg.cross_lo, xt, peer, sg.cross_cnt, sg.cross_role, P.cross_c, P.cross_sr, P.cross_si,
+                   tid, nthr);
     __syncthreads();
   }
 
@@ -109,12 +118,27 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
   const int nbytes = (P.norb + 7) >> 3;
   double acc = 0.0;
 
-  for (int s = 0; s < P.n_stages; ++s) {
+  // the vector-memory data of a Givens stage (its rotations, the wave's first
+  // class codes) is requested one stage ahead, so that its latency overlaps the
+  // stage before; descriptors come through the scalar cache
+  RotLane<R> rl_next{0, R(1), R(0), R(0)};
+  ChunkAhead fc_next{1, -1};
+  auto fetch = [&](int s) {
     const StageDev st = uniform_load(P.stages + s);
     if (st.type == ST_GIVENS) {
+      rl_next = fetch_rot_lane<R>(st.rots, st.nrot, lane);
+      fc_next = fetch_first_chunk(uniform_load(sg.win + st.a), wave, lane);
+    }
+  };
+  if (P.n_stages > 0) fetch(0);
+  for (int s = 0; s < P.n_stages; ++s) {
+    const StageDev st = uniform_load(P.stages + s);
+    const RotLane<R> rl = rl_next;
+    const ChunkAhead fc = fc_next;
+    if (s + 1 < P.n_stages) fetch(s + 1);
+    if (st.type == ST_GIVENS) {
       const SegWinDev wt = uniform_load(sg.win + st.a);
-      const RotLane<R> rl = load_rot_lane<R>(st.rots, st.nrot, lane);
-      givens_stage<W, REAL, R>(st.shape, row, mtl, wt, rl, st.nrot, wave, nwaves, lane);
+      givens_stage<W, REAL, R>(st.shape, row, mtl, wt, rl, st.nrot, wave, nwaves, lane, fc);
     } else {
       // cross weights w[q] = sum_{p in row} C[p][q]: the row's masked C is
       // staged in the table area (one load per thread, all in flight at once),

@@ -315,6 +315,7 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
           mt_all.insert(mt_all.end(), t.mt.begin(), t.mt.end());
           wins.push_back(wd);
         }
+        while (mt_all.size() % 4) mt_all.push_back(0);  // staged as int4 words
         ss.max_mt = std::max(ss.max_mt, (int)mt_all.size());
         auto* dw = (dev::SegWinDev*)P->dalloc(std::max<size_t>(wins.size(), 1) * sizeof(dev::SegWinDev));
         if (!wins.empty())

@@ -266,6 +266,12 @@ __device__ __forceinline__ T uniform_load(const T* p) {
 // flight per thread (a plain strided loop waits for every load before the
 // next one is issued, which leaves a block with one row in LDS idle for most
 // of its staging).
+// Marks a loaded value as used here: its load is issued no later than this
+// point (and never sunk into a later branch).
+__device__ __forceinline__ void keep(const zc64& v) { asm volatile("" ::"v"(v.x), "v"(v.y)); }
+__device__ __forceinline__ void keep(const zc128& v) { asm volatile("" ::"v"(v.x), "v"(v.y)); }
+__device__ __forceinline__ void keep(const int4& v) { asm volatile("" ::"v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w)); }
+
 template <int U, class V>
 __device__ __forceinline__ void stage_in(V* __restrict__ dst, const V* __restrict__ src, int len, int tid,
                                          int nthr) {

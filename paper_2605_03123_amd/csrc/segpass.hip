@@ -48,10 +48,43 @@ constexpr int seg_threads() {
 // partners directly.
 constexpr int kCrossU = 8;
 
-template <class V>
-__device__ __forceinline__ void cross_fetch(V* t, const V* peer, int cnt, int tid, int nthr) {
+__device__ const int4 kZeroWords = {0, 0, 0, 0};
+
+// The block's row segment, the member-offset tables (int4 words) and the
+// first kCrossU crossing partners per thread, requested in one straight-line
+// batch before any is used: every thread issues all its loads (clamped to the
+// last valid element, pointers chosen without branches), then stores the
+// segment and the tables to LDS; the partners stay in registers (xt).  Further
+// batches run only for segments longer than UR * nthr or tables longer than
+// UM * nthr words.
+template <int UR, int UM, class V>
+__device__ __forceinline__ void stage_segment(V* __restrict__ row, const V* __restrict__ src, int len,
+                                              int4* __restrict__ mt, const int4* mtg, int n4, const V* peer,
+                                              int pcnt, V* xt, int tid, int nthr) {
+  const int4* pm = n4 > 0 ? mtg : &kZeroWords;
+  const int pn4 = max(n4, 1);
+  const V* pp = pcnt > 0 ? peer : src;
+  const int pc = max(pcnt, 1);
+  V t[UR];
+  int4 q[UM];
 #pragma unroll
-  for (int u = 0; u < kCrossU; ++u) t[u] = peer[min(tid + u * nthr, cnt - 1)];
+  for (int u = 0; u < UR; ++u) t[u] = src[min(tid + u * nthr, len - 1)];
+#pragma unroll
+  for (int u = 0; u < UM; ++u) q[u] = pm[min(tid + u * nthr, pn4 - 1)];
+#pragma unroll
+  for (int u = 0; u < kCrossU; ++u) xt[u] = pp[min(tid + u * nthr, pc - 1)];
+#pragma unroll
+  for (int u = 0; u < UR; ++u) keep(t[u]);
+#pragma unroll
+  for (int u = 0; u < UM; ++u) keep(q[u]);
+#pragma unroll
+  for (int u = 0; u < UR; ++u)
+    if (tid + u * nthr < len) row[tid + u * nthr] = t[u];
+#pragma unroll
+  for (int u = 0; u < UM; ++u)
+    if (tid + u * nthr < n4) mt[tid + u * nthr] = q[u];
+  for (int e = tid + UR * nthr; e < len; e += nthr) row[e] = src[e];
+  for (int e = tid + UM * nthr; e < n4; e += nthr) mt[e] = mtg[e];
 }
 
 template <class R>
@@ -103,9 +136,9 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
   const bool xrot = P.cross && sg.cross_cnt > 0;
   const V* peer = (const V*)P.src + r * P.row_len + sg.cross_peer;
   V xt[kCrossU];
-  if (xrot) cross_fetch(xt, peer, sg.cross_cnt, tid, nthr);
-  stage_in<128 / sizeof(V)>(row, src, sg.len, tid, nthr);
-  stage_in<4>(mtl, sg.mt_all, sg.n_mt_all, tid, nthr);
+  // (the member-offset table of every window is a whole number of int4 words)
+  stage_segment<sizeof(V) == 8 ? 13 : 9, 2>(row, src, sg.len, (int4*)mtl, (const int4*)sg.mt_all,
+                                            sg.n_mt_all >> 2, peer, xrot ? sg.cross_cnt : 0, xt, tid, nthr);
   __syncthreads();
   if (xrot) {
     cross_apply<R>(row + sg.cross_lo, xt, peer, sg.cross_cnt, sg.cross_role, P.cross_c, P.cross_sr, P.cross_si,
@@ -181,9 +214,10 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
           rowf.y = -rowf.y;
         }
         const zc128* colf = st.colf ? (const zc128*)st.colf + sg.off : nullptr;
-        // U elements per thread at a time: their column masks and factors are
-        // all requested before the first is used
-        constexpr int U = 4;
+        // U elements per thread at a time (a whole segment per batch for the
+        // usual block sizes): their column masks and factors are all requested
+        // before the first is used
+        constexpr int U = sizeof(V) == 8 ? 10 : 9;
         const zc128 one{1.0, 0.0};
         for (int e0 = tid; e0 < sg.len; e0 += U * nthr) {
           uint32_t cm[U];
@@ -193,8 +227,9 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
             const int e = min(e0 + u * nthr, sg.len - 1);
             cm[u] = cross ? cmask[e] : 0u;
             cf[u] = colf ? colf[e] : one;
-            asm volatile("" ::"v"(cm[u]), "v"(cf[u].x), "v"(cf[u].y));
           }
+#pragma unroll
+          for (int u = 0; u < U; ++u) asm volatile("" ::"v"(cm[u]), "v"(cf[u].x), "v"(cf[u].y));
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const int e = e0 + u * nthr;
@@ -211,7 +246,7 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
           }
         }
       } else {
-        constexpr int U = 4;
+        constexpr int U = sizeof(V) == 8 ? 10 : 9;
         const double* Bs = st.B ? st.B + sg.off : nullptr;
         for (int e0 = tid; e0 < sg.len; e0 += U * nthr) {
           uint32_t cm[U];
@@ -221,8 +256,9 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
             const int e = min(e0 + u * nthr, sg.len - 1);
             cm[u] = cross ? cmask[e] : 0u;
             fb[u] = Bs ? Bs[e] : 0.0;
-            asm volatile("" ::"v"(cm[u]), "v"(fb[u]));
           }
+#pragma unroll
+          for (int u = 0; u < U; ++u) asm volatile("" ::"v"(cm[u]), "v"(fb[u]));
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const int e = e0 + u * nthr;

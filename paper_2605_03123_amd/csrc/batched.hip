@@ -418,6 +418,10 @@ __device__ __forceinline__ void seg_task(const BatchDev& B, const BPassDev& ps, 
         if (st.type == ST_PHASE) {
           zc128 f{L.rowf[2 * r], L.rowf[2 * r + 1]};
           if (st.colf) f = zmul(f, ((const zc128*)st.colf)[k]);
+          if (__builtin_popcount(cmask[k] & st.sign_col) & 1) {
+            f.x = -f.x;
+            f.y = -f.y;
+          }
           if (cross) {
             const V e = phase_factor<R>(st.scale * cr);
             f = zmul(f, zc128{(double)e.x, (double)e.y});

@@ -171,7 +171,9 @@ struct StageDev {
   int nrot;
   uint32_t sign_row;
   int shape;  // ST_GIVENS: index into the stage shapes, or -1
-  int pad;
+  // ST_PHASE: column orbitals whose occupation parity flips the sign (a
+  // deferred sign layer of the column spin that needs no column table)
+  uint32_t sign_col;
   const RotDev* rots;
   double scale;
   const double* A;
@@ -238,6 +240,11 @@ struct SegPassDev {
   // pass must not overwrite: src != dst)
   int cross;
   double cross_c, cross_sr, cross_si;
+  // blocks of the first round (block < first_round) start (block % 4) *
+  // stagger sleep units late, so that the row loads of the compute units do
+  // not all fall together
+  int stagger;
+  int first_round;
 };
 
 // LDS needed by a segment pass whose longest segment holds max_len amplitudes

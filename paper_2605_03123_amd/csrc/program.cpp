@@ -157,7 +157,9 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
       }
       pd = Pending{};
     }
-    if (cb.B || cb.delta || cb.sign) {
+    if (!cb.B && !cb.delta && cb.sign) {
+      st.sign_col = cb.sign;  // signs alone: taken from each column's mask
+    } else if (cb.B || cb.delta || cb.sign) {
       const size_t n = (size_t)P.dim[cs];
       if (arena_off + 2 * n > arena_need) throw Error(FFX_EUNSUPPORTED, "diagonal table arena exhausted");
       cb.out = arena + arena_off;
@@ -463,6 +465,8 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
       p.partials = L.reduce ? P.partials : nullptr;
       p.lds_row_bytes = (int)(((size_t)ss.max_len * P.elem() + 15) & ~(size_t)15);
       p.max_mt = ss.max_mt;
+      p.stagger = P.seg_stagger;
+      p.first_round = P.n_cu;
       if (L.cross) {
         p.cross = 1;
         p.cross_c = L.cross_rot.c;

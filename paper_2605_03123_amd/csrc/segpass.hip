@@ -132,6 +132,10 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
   const int wave = tid >> 6;
   const int nwaves = nthr >> 6;
 
+  if (P.stagger > 0 && blk < (int64_t)P.first_round) {
+    const int k = (int)(blk & 3) * P.stagger;
+    for (int i = 0; i < k; ++i) __builtin_amdgcn_s_sleep(127);
+  }
   const V* src = (const V*)P.src + r * P.row_len + sg.off;
   const bool xrot = P.cross && sg.cross_cnt > 0;
   const V* peer = (const V*)P.src + r * P.row_len + sg.cross_peer;
@@ -189,35 +193,48 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
         wq[tid] = w;
       }
       __syncthreads();
+      const double arow = st.A ? st.A[r] : 0.0;
+      // row factor (phase stages): folded into the first byte table when there
+      // is a cross term
+      zc128 rowf{1.0, 0.0};
+      if (st.type == ST_PHASE) {
+        double grow = 0.0;
+        if (st.drow)
+          for (int p = 0; p < P.norb; ++p)
+            if ((rmask >> p) & 1) grow += st.drow[p];
+        rowf = phase_factor<double>(st.scale * arow + grow);
+        if (parity(rmask & st.sign_row)) {
+          rowf.x = -rowf.x;
+          rowf.y = -rowf.y;
+        }
+      }
       if (cross) {
         for (int i = tid; i < nbytes * 256; i += nthr) {
           const int k = i >> 8, b = i & 255;
           double v = 0.0;
           for (int q = 0; q < 8; ++q)
             if (((b >> q) & 1) && 8 * k + q < P.norb) v += wq[8 * k + q];
-          if (st.type == ST_PHASE)
-            ez[i] = phase_factor<double>(st.scale * v);
-          else
+          if (st.type == ST_PHASE) {
+            const zc128 e = phase_factor<double>(st.scale * v);
+            ez[i] = k == 0 ? zmul(rowf, e) : e;
+          } else {
             tab[i] = v;
+          }
         }
       }
       __syncthreads();
-      const double arow = st.A ? st.A[r] : 0.0;
+      // U elements per thread at a time (a whole segment per batch for the
+      // usual block sizes): their column masks and tables are all requested
+      // before the first is used
+      constexpr int U = sizeof(V) == 8 ? 10 : 9;
       if (st.type == ST_PHASE) {
-        double grow = 0.0;
-        if (st.drow)
-          for (int p = 0; p < P.norb; ++p)
-            if ((rmask >> p) & 1) grow += st.drow[p];
-        zc128 rowf = phase_factor<double>(st.scale * arow + grow);
-        if (parity(rmask & st.sign_row)) {
-          rowf.x = -rowf.x;
-          rowf.y = -rowf.y;
-        }
+        if (cross) rowf = zc128{1.0, 0.0};
         const zc128* colf = st.colf ? (const zc128*)st.colf + sg.off : nullptr;
-        // U elements per thread at a time (a whole segment per batch for the
-        // usual block sizes): their column masks and factors are all requested
-        // before the first is used
-        constexpr int U = sizeof(V) == 8 ? 10 : 9;
+        const uint32_t sgn = st.sign_col;
+        const bool use_cm = cross || sgn != 0;
+        // signs only: negate where the row and column parities differ
+        const bool signs_only = !cross && !colf && !st.A && !st.drow;
+        const int rneg = rowf.x < 0.0;
         const zc128 one{1.0, 0.0};
         for (int e0 = tid; e0 < sg.len; e0 += U * nthr) {
           uint32_t cm[U];
@@ -225,7 +242,7 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const int e = min(e0 + u * nthr, sg.len - 1);
-            cm[u] = cross ? cmask[e] : 0u;
+            cm[u] = use_cm ? cmask[e] : 0u;
             cf[u] = colf ? colf[e] : one;
           }
 #pragma unroll
@@ -233,20 +250,31 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const int e = e0 + u * nthr;
-            if (e < sg.len) {
-              zc128 f = zmul(rowf, cf[u]);
-              if (cross)
-                for (int k = 0; k < nbytes; ++k) f = zmul(f, ez[(k << 8) | ((cm[u] >> (8 * k)) & 255)]);
-              V y = row[e];
-              V o;
-              o.x = (R)((double)y.x * f.x - (double)y.y * f.y);
-              o.y = (R)((double)y.x * f.y + (double)y.y * f.x);
-              row[e] = o;
+            if (e >= sg.len) continue;
+            if (signs_only) {
+              if (parity(cm[u] & sgn) != rneg) {
+                V y = row[e];
+                y.x = -y.x;
+                y.y = -y.y;
+                row[e] = y;
+              }
+              continue;
             }
+            zc128 f = colf ? zmul(rowf, cf[u]) : rowf;
+            if (cross)
+              for (int k = 0; k < nbytes; ++k) f = zmul(f, ez[(k << 8) | ((cm[u] >> (8 * k)) & 255)]);
+            if (parity(cm[u] & sgn)) {
+              f.x = -f.x;
+              f.y = -f.y;
+            }
+            V y = row[e];
+            V o;
+            o.x = (R)((double)y.x * f.x - (double)y.y * f.y);
+            o.y = (R)((double)y.x * f.y + (double)y.y * f.x);
+            row[e] = o;
           }
         }
       } else {
-        constexpr int U = sizeof(V) == 8 ? 10 : 9;
         const double* Bs = st.B ? st.B + sg.off : nullptr;
         for (int e0 = tid; e0 < sg.len; e0 += U * nthr) {
           uint32_t cm[U];

@@ -247,12 +247,6 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
       const int v = std::atoi(e);
       if (v >= 0 && v <= 1024) lds_group = v / (int)P->elem();
     }
-    {
-      hipDeviceProp_t prop;
-      HIPCHK(hipGetDeviceProperties(&prop, device));
-      P->n_cu = prop.multiProcessorCount;
-    }
-    if (const char* e = std::getenv("FFX_SEG_STAGGER")) P->seg_stagger = std::max(0, std::atoi(e));  // tuning knob
     int max_rows_x_seg = 0;
     for (int s = 0; s < 2; ++s) {
       auto& ss = P->seg[s];

@@ -240,11 +240,6 @@ struct SegPassDev {
   // pass must not overwrite: src != dst)
   int cross;
   double cross_c, cross_sr, cross_si;
-  // blocks of the first round (block < first_round) start (block % 4) *
-  // stagger sleep units late, so that the row loads of the compute units do
-  // not all fall together
-  int stagger;
-  int first_round;
 };
 
 // LDS needed by a segment pass whose longest segment holds max_len amplitudes

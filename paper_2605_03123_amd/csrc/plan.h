@@ -127,8 +127,6 @@ struct ffx_plan_s {
   double* (*arena_hook)(void* ctx, size_t doubles) = nullptr;
   void* arena_ctx = nullptr;
   int max_stage_rots = ffx::dev::kMaxStageRots;  // Givens rotations per stage (fusion depth)
-  int n_cu = 256;        // compute units of the device
-  int seg_stagger = 0;   // first-round start offsets of segment passes (sleep units)
   static constexpr int kArenaSlots = 64;
   double* arena_for(size_t doubles, hipStream_t s) {
     if (doubles > arena_doubles) {

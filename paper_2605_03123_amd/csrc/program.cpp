@@ -465,8 +465,6 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
       p.partials = L.reduce ? P.partials : nullptr;
       p.lds_row_bytes = (int)(((size_t)ss.max_len * P.elem() + 15) & ~(size_t)15);
       p.max_mt = ss.max_mt;
-      p.stagger = P.seg_stagger;
-      p.first_round = P.n_cu;
       if (L.cross) {
         p.cross = 1;
         p.cross_c = L.cross_rot.c;

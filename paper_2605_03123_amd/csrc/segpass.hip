@@ -132,10 +132,6 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
   const int wave = tid >> 6;
   const int nwaves = nthr >> 6;
 
-  if (P.stagger > 0 && blk < (int64_t)P.first_round) {
-    const int k = (int)(blk & 3) * P.stagger;
-    for (int i = 0; i < k; ++i) __builtin_amdgcn_s_sleep(127);
-  }
   const V* src = (const V*)P.src + r * P.row_len + sg.off;
   const bool xrot = P.cross && sg.cross_cnt > 0;
   const V* peer = (const V*)P.src + r * P.row_len + sg.cross_peer;

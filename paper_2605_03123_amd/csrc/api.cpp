@@ -40,22 +40,9 @@ hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
 // Transition one-body matrix of lam and psi, both spins:
 //   Tout[0 .. 2N^2) alpha part, Tout[2N^2 .. 4N^2) beta part (interleaved complex)
-// For norb <= 16 with rows that fit in LDS (whole, or in two halves split by
-// the top orbital), the excitations are taken inside rows: beta on the
-// alpha-major state, alpha on its transpose.  Otherwise row pairs are used.
-bool rdm_split(const ffx_plan_s& P, int cs, int& halves, int64_t& split) {
-  const size_t cap = 128 * 1024;  // next to the kernel's rank tables and accumulators
-  const int64_t cols = P.dim[cs];
-  if (P.norb > 16) return false;
-  if ((size_t)cols * P.elem() <= cap) {
-    halves = 1;
-    split = cols;
-    return true;
-  }
-  split = binom(P.norb - 1, P.n[cs]);
-  halves = 2;
-  return (size_t)std::max(split, cols - split) * P.elem() <= cap;
-}
+// For norb <= 16 the excitations are taken inside rows on the matrix cores
+// (beta on the alpha-major states, alpha on their transposes); otherwise
+// between row pairs.
 
 void ensure_rank_tables(ffx_plan_s& P) {
   if (P.rank_lo) return;
@@ -75,46 +62,104 @@ void ensure_rank_tables(ffx_plan_s& P) {
   P.rank_hi = (int*)P.dalloc(hi.size() * 4);
   HIPCHK(hipMemcpy(P.rank_lo, lo.data(), lo.size() * 4, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(P.rank_hi, hi.data(), hi.size() * 4, hipMemcpyHostToDevice));
-  for (int sp = 0; sp < 2; ++sp) {
-    std::vector<int> idx, off;
-    for (int q = 0; q < P.norb; ++q) {
-      off.push_back((int)idx.size());
-      for (size_t k = 0; k < P.str[sp].size(); ++k)
-        if ((P.str[sp][k] >> q) & 1) idx.push_back((int)k);
+}
+
+// The (n-1)-electron strings K of column spin cs for the matrix-core kernel,
+// grouped by their occupation of the top norb - nlow orbitals, with nlow the
+// largest value whose home column ranges (strings with the group's top
+// occupation) of two states and the group's K list fit the LDS budget.
+void ensure_rdm_strings(ffx_plan_s& P, int cs) {
+  auto& R = P.rdm_k[cs];
+  if (R.ready) return;
+  const int N = P.norb, n = P.n[cs];
+  const auto& str = P.str[cs];
+  std::vector<uint32_t> K;
+  if (n >= 1)
+    for (uint32_t m = 0; m < (1u << N); ++m)
+      if (__builtin_popcount(m) == n - 1) K.push_back(m);
+  const size_t budget = 140 * 1024;
+  for (int h = 0; h <= N; ++h) {
+    const int nlow = N - h;
+    std::vector<int> group;
+    std::vector<uint32_t> sorted;
+    int max_home = 0, max_inter = 0;
+    for (uint32_t H = 0; H < (1u << h); ++H) {
+      std::vector<uint32_t> ks;
+      for (uint32_t k : K)
+        if ((k >> nlow) == H) ks.push_back(k);
+      if (ks.empty()) continue;
+      int first = -1, cnt = 0;
+      for (size_t i = 0; i < str.size(); ++i)
+        if ((uint32_t)(str[i] >> nlow) == H) {
+          if (first < 0) first = (int)i;
+          ++cnt;
+        }
+      if (first < 0) first = 0;
+      group.insert(group.end(), {first, cnt, (int)sorted.size(), (int)ks.size()});
+      sorted.insert(sorted.end(), ks.begin(), ks.end());
+      max_home = std::max(max_home, cnt);
+      max_inter = std::max(max_inter, (int)ks.size());
     }
-    off.push_back((int)idx.size());
-    P.with_q[sp] = (int*)P.dalloc(std::max<size_t>(idx.size(), 1) * 4);
-    P.with_q_off[sp] = (int*)P.dalloc(off.size() * 4);
-    if (!idx.empty()) HIPCHK(hipMemcpy(P.with_q[sp], idx.data(), idx.size() * 4, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(P.with_q_off[sp], off.data(), off.size() * 4, hipMemcpyHostToDevice));
+    if (dev::rdm_mfma_lds(P.c64, max_home, max_inter) > budget && h < N) continue;
+    R.nlow = nlow;
+    R.ngroups = (int)group.size() / 4;
+    R.max_home = max_home;
+    R.max_inter = max_inter;
+    R.group = (int*)P.dalloc(std::max<size_t>(group.size(), 4) * 4);
+    R.inter = (uint32_t*)P.dalloc(std::max<size_t>(sorted.size(), 1) * 4);
+    if (!group.empty()) HIPCHK(hipMemcpy(R.group, group.data(), group.size() * 4, hipMemcpyHostToDevice));
+    if (!sorted.empty()) HIPCHK(hipMemcpy(R.inter, sorted.data(), sorted.size() * 4, hipMemcpyHostToDevice));
+    R.ready = true;
+    return;
   }
+}
+
+void rdm_columns(ffx_plan_s& P, int cs, const void* lam, const void* psi, int64_t rows, int64_t cols,
+                 double* part, hipStream_t s) {
+  const auto& R = P.rdm_k[cs];
+  dev::RdmMfmaDev d{};
+  d.lam = lam;
+  d.psi = psi;
+  d.rows = rows;
+  d.cols = cols;
+  d.norb = P.norb;
+  d.nlow = R.nlow;
+  d.ngroups = R.ngroups;
+  d.max_home = R.max_home;
+  d.max_inter = R.max_inter;
+  d.group = R.group;
+  d.inter = R.inter;
+  d.rank_lo = P.rank_lo;
+  d.rank_hi = P.rank_hi;
+  d.part = part;
+  dev::rdm_mfma(P.c64, d, s);
 }
 
 void transition_rdm(ffx_plan_s& P, const void* lam, const void* psi, void* lamT, void* psiT, double* part,
                     double* Tout, hipStream_t s) {
   const int N = P.norb, NN = N * N;
-  int h0 = 0, h1 = 0;
-  int64_t s0 = 0, s1 = 0;
-  // the in-row kernel is the faster one for complex128 (where rows are staged in
-  // halves); for complex64 the row-pair kernel is
-  if (!P.c64 && rdm_split(P, 0, h0, s0) && rdm_split(P, 1, h1, s1)) {
+  if (N <= 16 && !P.rdm_pairs) {
+    // column spin of each layout through the strings of one electron fewer, on
+    // the matrix cores: beta on the alpha-major states, alpha on their transposes
     ensure_rank_tables(P);
-    dev::rdm_lds(P.c64, lam, psi, P.dim[0], P.dim[1], P.d_masks[1], N, h1, s1, P.rank_lo, P.rank_hi, P.with_q[1],
-                 P.with_q_off[1], part, s);
+    ensure_rdm_strings(P, 0);
+    ensure_rdm_strings(P, 1);
+    rdm_columns(P, 1, lam, psi, P.dim[0], P.dim[1], part, s);
     dev::rdm_reduce(part, P.dim[0], N, Tout + 2 * NN, s);
     dev::transpose(P.c64, psi, psiT, P.dim[0], P.dim[1], s);
     dev::transpose(P.c64, lam, lamT, P.dim[0], P.dim[1], s);
-    dev::rdm_lds(P.c64, lamT, psiT, P.dim[1], P.dim[0], P.d_masks[0], N, h0, s0, P.rank_lo, P.rank_hi, P.with_q[0],
-                 P.with_q_off[0], part, s);
+    rdm_columns(P, 0, lamT, psiT, P.dim[1], P.dim[0], part, s);
     dev::rdm_reduce(part, P.dim[1], N, Tout, s);
-  } else {
-    dev::rdm_rows(P.c64, lam, psi, P.dim[0], P.dim[1], P.d_masks[0], N, part, s);
-    dev::rdm_reduce(part, P.dim[0], N, Tout, s);
-    dev::transpose(P.c64, psi, psiT, P.dim[0], P.dim[1], s);
-    dev::transpose(P.c64, lam, lamT, P.dim[0], P.dim[1], s);
-    dev::rdm_rows(P.c64, lamT, psiT, P.dim[1], P.dim[0], P.d_masks[1], N, part, s);
-    dev::rdm_reduce(part, P.dim[1], N, Tout + 2 * NN, s);
+    check_launch();
+    return;
   }
+  // row spin of each layout from row pairs
+  dev::rdm_rows(P.c64, lam, psi, P.dim[0], P.dim[1], P.d_masks[0], N, part, s);
+  dev::rdm_reduce(part, P.dim[0], N, Tout, s);
+  dev::transpose(P.c64, psi, psiT, P.dim[0], P.dim[1], s);
+  dev::transpose(P.c64, lam, lamT, P.dim[0], P.dim[1], s);
+  dev::rdm_rows(P.c64, lamT, psiT, P.dim[1], P.dim[0], P.d_masks[1], N, part, s);
+  dev::rdm_reduce(part, P.dim[1], N, Tout + 2 * NN, s);
   check_launch();
 }
 
@@ -237,6 +282,9 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
     // offset tables of every register window inside the segment
     const size_t lds_cap = 160 * 1024 - 64;
     int64_t max_elems = (int64_t)((lds_cap - dev::seg_pass_lds(P->c64, 0, 0)) / P->elem());
+    // the row-pair transition one-body kernel (the path above 16 orbitals) at
+    // any size, for tests
+    P->rdm_pairs = std::getenv("FFX_RDM_PAIRS") != nullptr;
     if (const char* e = std::getenv("FFX_SEG_MAX")) {  // smaller segments, for tests
       int64_t v = std::atoll(e);
       if (v >= 1 && v < max_elems) max_elems = v;

@@ -97,16 +97,29 @@ void transpose(bool c64, const void* src, void* dst, int64_t rows, int64_t cols,
 void rdm_rows(bool c64, const void* lam, const void* psi, int64_t rows, int64_t cols,
               const uint32_t* masks_rows, int norb, double* part, hipStream_t stream);
 void rdm_reduce(const double* part, int64_t rows, int norb, double* T, hipStream_t stream);
-// The same partials for the COLUMN spin (excitations inside each row), for
-// norb <= 16: lam's row is staged in LDS whole (halves = 1) or as the strings
-// below / from `split` (halves = 2: split = first string holding the top
-// orbital).  rank_lo[256], rank_hi[256 * 17]: colex rank of a mask
-// = rank_lo[m & 255] + rank_hi[(m >> 8) * 17 + popcount(m & 255)].
-// with_q[with_q_off[q] ..]: the column strings that hold orbital q.
-size_t rdm_lds_bytes(bool c64, int64_t cols, int64_t split, int halves);
-void rdm_lds(bool c64, const void* lam, const void* psi, int64_t rows, int64_t cols, const uint32_t* masks,
-             int norb, int halves, int64_t split, const int* rank_lo, const int* rank_hi, const int* with_q,
-             const int* with_q_off, double* part, hipStream_t stream);
+// The same partials for the COLUMN spin through the strings of one electron
+// fewer (norb <= 16): T_pq = sum over (n-1)-electron strings K of
+// conj(lam[K + p]) psi[K + q] s_p(K) s_q(K), s_x(K) = (-1)^{|K below x|}, as
+// 16 x 16 x 4 FP64 matrix-core products whose operands are gathered per lane
+// (orbital = lane % 16, string = lane / 16; zero where the orbital is in K).
+// The strings K are grouped by their occupation of the top (norb - nlow)
+// orbitals; group g's "home" columns [off, off + len) (strings with the same
+// top occupation) of lam and psi are staged in LDS, columns outside it are
+// read from HBM.  group[4 g ..] = {home_off, home_len, first K, number of K}.
+struct RdmMfmaDev {
+  const void* lam;
+  const void* psi;
+  int64_t rows, cols;
+  int norb, nlow, ngroups, max_home, max_inter;
+  int pad;
+  const int* group;
+  const uint32_t* inter;
+  const int* rank_lo;
+  const int* rank_hi;
+  double* part;
+};
+size_t rdm_mfma_lds(bool c64, int max_home, int max_inter);
+void rdm_mfma(bool c64, const RdmMfmaDev& d, hipStream_t stream);
 
 // Diagonal-gate gradient reductions (see api): for each row i_a and
 //   z = Im(conj(lam) psi), g_0 = 1, g_{1+p} = x_b[p], g_{1+N+p} = x_b[p] x_b[p+1]:

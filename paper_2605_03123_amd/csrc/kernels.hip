@@ -592,128 +592,151 @@ void rdm_rows(bool c64, const void* lam, const void* psi, int64_t rows, int64_t 
                        (const zc128*)psi, rows, cols, masks_rows, norb, part);
 }
 
-// Transition one-body matrix of the COLUMN spin (excitations I -> J = I - q + p
-// inside each row), for norb <= 16.  One block per row: lam's row is staged in
-// LDS (in two halves split by the top orbital when a whole row does not fit);
-// wave w owns the occupied orbital q = w (+ nwaves ...) and keeps one complex
-// accumulator per p in each lane; lanes walk the strings I of the row that
-// contain q (a per-q list), read psi[row, I] once and gather lam[row, J] from
-// LDS.  J's address comes from two byte tables staged in LDS (colex rank =
-// lo[J & 255] + hi[J >> 8][popcount(J & 255)]).  Every sum has a fixed order.
-//   part[2 * (pq * rows + row)] = sum_{I -> J} sign conj(lam[row, J]) psi[row, I]
-constexpr int kRdmMaxOrb = 16;
+// Transition one-body matrix of the column spin through the strings K of one
+// electron fewer: for K and orbitals p, q outside it, lam's string K + p and
+// psi's string K + q contribute conj(lam) psi s_p(K) s_q(K) to T_pq.  Over K
+// this is a product of a 16 x |K| by a |K| x 16 matrix whose entries are
+// zero for orbitals inside K, so it runs on the FP64 matrix cores
+// (v_mfma_f64_16x16x4: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]
+// and receives D[l / 16 + 4 t][l % 16], t = 0..3).  Each lane gathers one
+// amplitude of lam and one of psi for (orbital l % 16, string l / 16) of a
+// block of four strings; the real and imaginary parts take four products in
+// four independent accumulators.  One block per row; the groups of K are
+// taken in turn with their home columns and string list staged in LDS.  The
+// sums run in a fixed order (per wave over its string blocks, then over the
+// waves in order).
+typedef double rdm_d4 __attribute__((ext_vector_type(4)));
+constexpr int kRdmMfmaThreads = 1024;
 
 template <class R>
-__global__ __launch_bounds__(512) void k_rdm_lds(const typename V2T<R>::type* __restrict__ lam,
-                                                  const typename V2T<R>::type* __restrict__ psi,
-                                                  int64_t rows, int64_t cols,
-                                                  const uint32_t* __restrict__ masks, int norb, int halves,
-                                                  int64_t split, const int* __restrict__ rank_lo,
-                                                  const int* __restrict__ rank_hi,
-                                                  const int* __restrict__ with_q, const int* __restrict__ with_q_off,
-                                                  double* __restrict__ part) {
+__global__ __launch_bounds__(kRdmMfmaThreads) void k_rdm_mfma(RdmMfmaDev P) {
   using V = typename V2T<R>::type;
   extern __shared__ __align__(16) char smem[];
-  V* lrow = (V*)smem;
-  __shared__ double T[2 * kRdmMaxOrb * kRdmMaxOrb];
+  V* hl = (V*)smem;                                    // lam, home columns
+  V* hp = hl + P.max_home;                             // psi, home columns
+  uint32_t* kl = (uint32_t*)(hp + P.max_home);         // the group's strings K
   __shared__ int rlo[256];
   __shared__ int rhi[256 * 17];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nw = nthr >> 6;
   const int64_t row = blockIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int NN = norb * norb;
-  for (int i = threadIdx.x; i < 2 * NN; i += blockDim.x) T[i] = 0.0;
-  for (int i = threadIdx.x; i < 256; i += blockDim.x) rlo[i] = rank_lo[i];
-  for (int i = threadIdx.x; i < 256 * 17; i += blockDim.x) rhi[i] = rank_hi[i];
-  const V* lr = lam + row * cols;
-  const V* pr = psi + row * cols;
-  const uint32_t top = 1u << (norb - 1);
-  for (int h = 0; h < halves; ++h) {
-    const int64_t j0 = h == 0 ? 0 : split;
-    const int64_t j1 = halves == 1 ? cols : (h == 0 ? split : cols);
+  for (int i = tid; i < 256; i += nthr) rlo[i] = P.rank_lo[i];
+  for (int i = tid; i < 256 * 17; i += nthr) rhi[i] = P.rank_hi[i];
+  const V* lr = (const V*)P.lam + row * P.cols;
+  const V* pr = (const V*)P.psi + row * P.cols;
+  const int o = lane & 15, kk = lane >> 4;
+  const bool o_in = o < P.norb, o_home = o < P.nlow;
+  const uint32_t below = (1u << o) - 1u;
+  rdm_d4 rr = {0.0, 0.0, 0.0, 0.0}, ii = rr, ri = rr, ir = rr;
+  for (int g = 0; g < P.ngroups; ++g) {
+    const int4 gd = uniform_load((const int4*)P.group + g);  // home_off, home_len, first K, count
     __syncthreads();
-    for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) lrow[j - j0] = lr[j];
+    for (int e0 = tid; e0 < gd.y; e0 += 4 * nthr) {
+      V a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = min(e0 + u * nthr, gd.y - 1);
+        a[u] = lr[gd.x + e];
+        b[u] = pr[gd.x + e];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        keep(a[u]);
+        keep(b[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e0 + u * nthr < gd.y) {
+          hl[e0 + u * nthr] = a[u];
+          hp[e0 + u * nthr] = b[u];
+        }
+    }
+    for (int e = tid; e < gd.w; e += nthr) kl[e] = P.inter[gd.z + e];
     __syncthreads();
-    for (int q = wave; q < norb; q += nw) {
-      double ar[kRdmMaxOrb], ai[kRdmMaxOrb];
-#pragma unroll
-      for (int p = 0; p < kRdmMaxOrb; ++p) ar[p] = ai[p] = 0.0;
-      // the strings of the row that hold q
-      for (int e = with_q_off[q] + lane; e < with_q_off[q + 1]; e += 64) {
-        const int k = with_q[e];
-        const uint32_t I = masks[k];
-        const V b = pr[k];
-        const double bx = b.x, by = b.y;
-        const uint32_t Iq = I & ~(1u << q);
-#pragma unroll
-        for (int p = 0; p < kRdmMaxOrb; ++p) {
-          if (p >= norb || (p != q && ((I >> p) & 1))) continue;
-          const uint32_t J = Iq | (1u << p);
-          if (halves == 2 && (((J & top) != 0) != (h == 1))) continue;
-          const int j = rlo[J & 255] + rhi[(J >> 8) * 17 + __builtin_popcount(J & 255)] - (int)j0;
-          const V a = lrow[j];
-          const int lo = p < q ? p : q, hi = p < q ? q : p;
-          const uint32_t mid = (hi - lo > 1) ? (I >> (lo + 1)) & ((1u << (hi - lo - 1)) - 1) : 0u;
-          const double ax = a.x, ay = a.y;
-          double sr = ax * bx + ay * by, si = ax * by - ay * bx;
-          if (__builtin_popcount(mid) & 1) {
-            sr = -sr;
-            si = -si;
+    const int nkb = (gd.w + 3) >> 2;
+    for (int kb = wave; kb < nkb; kb += nw) {
+      const int k = 4 * kb + kk;
+      double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+      if (k < gd.w && o_in) {
+        const uint32_t K = kl[k];
+        if (!((K >> o) & 1u)) {
+          const uint32_t J = K | (1u << o);
+          const int rk = rlo[J & 255u] + rhi[(J >> 8) * 17 + __builtin_popcount(J & 255u)];
+          V a, b;
+          if (o_home) {
+            a = hl[rk - gd.x];
+            b = hp[rk - gd.x];
+          } else {
+            a = lr[rk];
+            b = pr[rk];
           }
-          ar[p] += sr;
-          ai[p] += si;
+          ar = (double)a.x;
+          ai = (double)a.y;
+          br = (double)b.x;
+          bi = (double)b.y;
+          if (__builtin_popcount(K & below) & 1) {
+            ar = -ar;
+            ai = -ai;
+            br = -br;
+            bi = -bi;
+          }
         }
       }
-#pragma unroll
-      for (int p = 0; p < kRdmMaxOrb; ++p) {
-        double x = ar[p], y = ai[p];
-        for (int o = 32; o > 0; o >>= 1) {
-          x += __shfl_xor(x, o);
-          y += __shfl_xor(y, o);
-        }
-        if (lane == 0 && p < norb) {
-          T[2 * (p * norb + q)] += x;
-          T[2 * (p * norb + q) + 1] += y;
-        }
-      }
+      // conj(a) b = (ar br + ai bi) + i (ar bi - ai br)
+      rr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, rr, 0, 0, 0);
+      ii = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, ii, 0, 0, 0);
+      ri = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, ri, 0, 0, 0);
+      ir = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, ir, 0, 0, 0);
     }
   }
   __syncthreads();
-  for (int pq = threadIdx.x; pq < NN; pq += blockDim.x) {
-    part[2 * ((int64_t)pq * rows + row)] = T[2 * pq];
-    part[2 * ((int64_t)pq * rows + row) + 1] = T[2 * pq + 1];
+  double* red = (double*)smem;  // [wave][re 256 | im 256]
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int pq = (kk + 4 * t) * 16 + o;
+    red[wave * 512 + pq] = rr[t] + ii[t];
+    red[wave * 512 + 256 + pq] = ri[t] - ir[t];
+  }
+  __syncthreads();
+  const int nn = P.norb * P.norb;
+  for (int i = tid; i < nn; i += nthr) {
+    const int p = i / P.norb, q = i - p * P.norb;
+    double re = 0.0, im = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      re += red[w * 512 + p * 16 + q];
+      im += red[w * 512 + 256 + p * 16 + q];
+    }
+    P.part[2 * ((int64_t)i * P.rows + row)] = re;
+    P.part[2 * ((int64_t)i * P.rows + row) + 1] = im;
   }
 }
 
-size_t rdm_lds_bytes(bool c64, int64_t cols, int64_t split, int halves) {
-  const int64_t len = halves == 1 ? cols : std::max(split, cols - split);
-  return (size_t)len * (c64 ? 8 : 16);
+size_t rdm_mfma_lds(bool c64, int max_home, int max_inter) {
+  const size_t home = 2 * (size_t)max_home * (c64 ? 8 : 16) + (size_t)max_inter * 4;
+  const size_t red = (size_t)(kRdmMfmaThreads / 64) * 512 * 8;
+  return std::max(home, red);
 }
 
-void rdm_lds(bool c64, const void* lam, const void* psi, int64_t rows, int64_t cols, const uint32_t* masks,
-             int norb, int halves, int64_t split, const int* rank_lo, const int* rank_hi, const int* with_q,
-             const int* with_q_off, double* part, hipStream_t s) {
-  const size_t lds = rdm_lds_bytes(c64, cols, split, halves);
+void rdm_mfma(bool c64, const RdmMfmaDev& d, hipStream_t s) {
+  const size_t lds = rdm_mfma_lds(c64, d.max_home, d.max_inter);
   if (c64) {
     static bool set = false;
     if (!set) {
-      (void)hipFuncSetAttribute((const void*)k_rdm_lds<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                128 * 1024);
+      (void)hipFuncSetAttribute((const void*)k_rdm_mfma<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024 - 20 * 1024);
       (void)hipGetLastError();
       set = true;
     }
-    hipLaunchKernelGGL(k_rdm_lds<float>, dim3((unsigned)rows), dim3(512), lds, s, (const zc64*)lam,
-                       (const zc64*)psi, rows, cols, masks, norb, halves, split, rank_lo, rank_hi, with_q, with_q_off, part);
+    hipLaunchKernelGGL(k_rdm_mfma<float>, dim3((unsigned)d.rows), dim3(kRdmMfmaThreads), lds, s, d);
   } else {
     static bool set = false;
     if (!set) {
-      (void)hipFuncSetAttribute((const void*)k_rdm_lds<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                128 * 1024);
+      (void)hipFuncSetAttribute((const void*)k_rdm_mfma<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024 - 20 * 1024);
       (void)hipGetLastError();
       set = true;
     }
-    hipLaunchKernelGGL(k_rdm_lds<double>, dim3((unsigned)rows), dim3(512), lds, s, (const zc128*)lam,
-                       (const zc128*)psi, rows, cols, masks, norb, halves, split, rank_lo, rank_hi, with_q, with_q_off,
-                       part);
+    hipLaunchKernelGGL(k_rdm_mfma<double>, dim3((unsigned)d.rows), dim3(kRdmMfmaThreads), lds, s, d);
   }
 }
 

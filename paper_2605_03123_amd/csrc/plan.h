@@ -120,9 +120,15 @@ struct ffx_plan_s {
   // rank = rank_lo[m & 255] + rank_hi[(m >> 8) * 17 + popcount(m & 255)]
   int* rank_lo = nullptr;
   int* rank_hi = nullptr;
-  // per spin: the strings holding orbital q, for q = 0 .. norb-1 (offsets norb + 1)
-  int* with_q[2] = {nullptr, nullptr};
-  int* with_q_off[2] = {nullptr, nullptr};
+  bool rdm_pairs = false;  // transition one-body matrices from row pairs at any size
+  // per column spin: the (n-1)-electron strings for the matrix-core transition
+  // one-body kernel, grouped by their top occupation, built on first use
+  struct RdmStrings {
+    bool ready = false;
+    int nlow = 0, ngroups = 0, max_home = 0, max_inter = 0;
+    int* group = nullptr;
+    uint32_t* inter = nullptr;
+  } rdm_k[2];
   // when set, compile_program takes its table arena from this hook instead
   double* (*arena_hook)(void* ctx, size_t doubles) = nullptr;
   void* arena_ctx = nullptr;

@@ -299,3 +299,25 @@ def test_lucj_energy_grad_returns_the_ansatz_state(ffx):
     out = torch.zeros((plan.dim_a, plan.dim_b), dtype=torch.complex128, device="cuda:0")
     ffx.lucj_energy_grad(w.data["params"], w.data["ham"], norb, nelec, n_reps, psi_out=out)
     assert _maxdiff(out, ol.apply_lucj(w.data["params"], norb, nelec, n_reps)) <= 1e-12
+
+
+def test_lucj_gradient_row_pair_transition_path(ffx):
+    # the transition one-body matrices from row pairs (the path above 16
+    # orbitals), forced at small sizes, against the oracle's adjoint gradient
+    import os
+    norb, nelec, n_reps = 7, (3, 4), 2
+    r = synth.rng(23)
+    params = synth.lucj_params(r, norb, n_reps, scale=0.3)
+    ham = synth.df_hamiltonian(r, norb, 3)
+    eo, go = ol.grad_adjoint(params, ham, norb, nelec, n_reps)
+    os.environ["FFX_RDM_PAIRS"] = "1"
+    try:
+        plans = {dt: ffx.Plan(norb, nelec, dt) for dt in (torch.complex128, torch.complex64)}
+    finally:
+        del os.environ["FFX_RDM_PAIRS"]
+    for dt, plan in plans.items():
+        e, g = ffx.lucj_energy_grad(params, ham, norb, nelec, n_reps, dtype=dt, plan=plan)
+        tol = 1e-10 if dt == torch.complex128 else 1e-4
+        assert abs(e - float(np.real(eo))) <= tol * max(1.0, abs(float(np.real(eo))))
+        assert np.max(np.abs(g - go)) <= tol * max(1.0, np.max(np.abs(go)))
+

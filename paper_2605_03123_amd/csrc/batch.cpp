@@ -12,6 +12,8 @@
 #include <numeric>
 #include <string>
 #include <tuple>
+#include <exception>
+#include <thread>
 #include <vector>
 
 #include "device.h"
@@ -95,6 +97,26 @@ namespace {
 int kernel_window(bool c64) { return dev::max_window(c64); }
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// fn(i) for i in [0, n) on up to 16 host threads (thread w takes i = w, w + nt,
+// ...); the first exception thrown is rethrown after all threads have joined
+template <class F>
+void parallel_for(int n, F fn) {
+  const int nt = std::max(1, std::min<int>({n, 16, (int)std::thread::hardware_concurrency()}));
+  std::vector<std::thread> th;
+  std::vector<std::exception_ptr> err(nt);
+  for (int w = 0; w < nt; ++w)
+    th.emplace_back([&, w] {
+      try {
+        for (int i = w; i < n; i += nt) fn(i);
+      } catch (...) {
+        err[w] = std::current_exception();
+      }
+    });
+  for (auto& t : th) t.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+}
 
 // rows of a transition-matrix task: half those of a segment task (two states in LDS)
 int64_t rdm_rows(int seg_rows) { return seg_rows > 1 ? seg_rows / 2 : 1; }
@@ -223,10 +245,9 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
                void* workspace, hipStream_t s, float* kernel_ms) {
   const int n = b.n_inst;
   std::vector<InstBuild> ib(n);
-  for (int i = 0; i < n; ++i) {
-    ffx_plan_s& P = *b.plans[b.inst_type[i]];
-    ib[i].G = build_lucj_grad(P, &ops[i], &hams[i]);
-  }
+  // the per-instance decompositions and gate programs are independent: built
+  // on several host threads (plans are only read)
+  parallel_for(n, [&](int i) { ib[i].G = build_lucj_grad(*b.plans[b.inst_type[i]], &ops[i], &hams[i]); });
   // compile every program twice: once to measure the upload and the table
   // arena, once into the allocated buffers
   auto compile_all = [&](Upload& up) {
@@ -600,8 +621,9 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
   b.last_launches = launches;
   if (flags[1]) throw Error(FFX_EDEVICE, "batched launch stopped: a dependency wait exceeded its bound");
   // ---- host: energies and gradient chain rules --------------------------
-  size_t goff = 0;
-  for (int i = 0; i < n; ++i) {
+  std::vector<size_t> goffs(n + 1, 0);
+  for (int i = 0; i < n; ++i) goffs[i + 1] = goffs[i] + (size_t)ffx_lucj_n_params(b.plans[b.inst_type[i]]->norb, ib[i].G->L.R);
+  parallel_for(n, [&](int i) {
     const ffx_plan_s& P = *b.plans[b.inst_type[i]];
     const LUCJGrad& G = *ib[i].G;
     const int N = P.norb, NN = N * N, R = G.L.R;
@@ -613,9 +635,8 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
       Ta[k] = Tb[k] + 2 * NN;
       D[k] = Tb[k] + 4 * NN;
     }
-    lucj_grad_assemble(G, N, Tb, Ta, D, grads + goff);
-    goff += (size_t)ffx_lucj_n_params(N, R);
-  }
+    lucj_grad_assemble(G, N, Tb, Ta, D, grads + goffs[i]);
+  });
 }
 
 }  // namespace

@@ -13,6 +13,7 @@
 // stage (or a final phase stage) instead of costing a pass of its own.
 #include <cmath>
 #include <map>
+#include <mutex>
 
 #include "plan.h"
 
@@ -66,6 +67,83 @@ std::vector<int> take_window(const std::vector<Givens>& rots, const std::vector<
     }
   }
   return out;
+}
+
+// The order in which a decomposition's rotations are applied: register-window
+// stages inside the segment window, a rotation on the pair straddling the
+// segment window (applied as the next segment pass loads), or a whole-spin
+// window pass.  It depends only on the positions of the rotations and the
+// window parameters, so it is computed once per structure and reused (every
+// decomposition of an N-orbital rotation has the same positions).
+struct SchedStep {
+  int kind;  // 0: segment-pass stage at window a; 1: crossing rotation idx[0]; 2: whole-spin window pass at a
+  int a;
+  std::vector<int> idx;
+};
+
+const std::vector<SchedStep>& rotation_schedule(const std::vector<Givens>& rots, int N, int wseg, int wt, int W,
+                                                int cap, bool cross) {
+  static std::mutex mu;
+  static std::map<std::vector<int>, std::vector<SchedStep>> cache;
+  std::vector<int> key{N, wseg, wt, W, cap, cross ? 1 : 0};
+  for (const Givens& g : rots) key.push_back(g.p);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  std::vector<SchedStep> out;
+  const auto deps = rotation_deps(rots, N);
+  std::vector<char> done(rots.size(), 0);
+  size_t n_done = 0;
+  while (n_done < rots.size()) {
+    while (wseg >= 2) {
+      int best_a = -1;
+      std::vector<int> best;
+      for (int a = 0; a + wseg <= wt; ++a) {
+        auto t = take_window(rots, deps, done, a, wseg);
+        if (t.size() > best.size()) {
+          best = t;
+          best_a = a;
+        }
+      }
+      if (best.empty()) break;
+      // a stage's rotations are spread over the 64 lanes of a wave; the taken
+      // list is in dependency order, so any prefix is a valid stage
+      if (best.size() > (size_t)cap) best.resize(cap);
+      for (int i : best) done[i] = 1;
+      n_done += best.size();
+      out.push_back(SchedStep{0, best_a, best});
+    }
+    if (n_done == rots.size()) break;
+    if (cross) {
+      int xi = -1;
+      for (size_t i = 0; i < rots.size() && xi < 0; ++i) {
+        if (done[i] || rots[i].p != wt - 1) continue;
+        bool ready = true;
+        for (int dp : deps[i]) ready = ready && done[dp];
+        if (ready) xi = (int)i;
+      }
+      if (xi >= 0) {
+        done[xi] = 1;
+        ++n_done;
+        out.push_back(SchedStep{1, 0, {xi}});
+        continue;
+      }
+    }
+    int best_a = -1;
+    std::vector<int> best;
+    for (int a = 0; a + W <= N; ++a) {
+      auto t = take_window(rots, deps, done, a, W);
+      if (t.size() > best.size()) {
+        best = t;
+        best_a = a;
+      }
+    }
+    if (best.empty()) throw Error(FFX_EDEVICE, "rotation schedule made no progress");
+    for (int i : best) done[i] = 1;
+    n_done += best.size();
+    out.push_back(SchedStep{2, best_a, best});
+  }
+  return cache.emplace(std::move(key), std::move(out)).first->second;
 }
 
 // index of the stage shape whose position list equals the stage's, or -1
@@ -235,97 +313,51 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
         continue;
       }
       const Decomposition& d = *it.d;
-      const auto deps = rotation_deps(d.rots, N);
-      std::vector<char> done(d.rots.size(), 0);
-      size_t n_done = 0;
       const double K = 0.5 * N * (N - 1);
-      while (n_done < d.rots.size()) {
-        // register-window stages inside the segment window [0, wt)
-        while (ss.Wseg >= 2) {
-          int best_a = -1;
-          std::vector<int> best;
-          for (int a = 0; a + ss.Wseg <= ss.wt; ++a) {
-            auto t = take_window(d.rots, deps, done, a, ss.Wseg);
-            if (t.size() > best.size()) {
-              best = t;
-              best_a = a;
-            }
-          }
-          if (best.empty()) break;
-          // a stage's rotations are spread over the 64 lanes of a wave; the
-          // taken list is in dependency order, so any prefix is a valid stage
-          const size_t cap = (size_t)std::max(1, std::min(P.max_stage_rots, dev::kMaxStageRots));
-          if (best.size() > cap) best.resize(cap);
-          std::vector<dev::RotDev> buf;
-          for (int i : best) {
-            const Givens& g = d.rots[i];
-            buf.push_back(dev::RotDev{g.p - best_a, 0, g.c, g.s.real(), g.s.imag()});
-            done[i] = 1;
-          }
-          n_done += best.size();
+      const int cap = std::max(1, std::min(P.max_stage_rots, dev::kMaxStageRots));
+      for (const SchedStep& step : rotation_schedule(d.rots, N, ss.Wseg, ss.wt, P.W, cap, ss.cross)) {
+        const double slots = (double)step.idx.size() * pairs_per_row * (double)n_rows * (d.real ? 8.0 : 12.0);
+        if (step.kind == 1) {
+          // starts the next segment pass: applied as the segments are loaded
+          flush_seg(false);
+          const Givens& g = d.rots[step.idx[0]];
+          cur.cross = true;
+          cur.cross_rot = dev::RotDev{0, 0, g.c, g.s.real(), g.s.imag()};
+          cur.valu_slots += slots;
+          cur.rot_sides += 1.0 / K;
+          continue;
+        }
+        std::vector<dev::RotDev> buf;
+        for (int i : step.idx) {
+          const Givens& g = d.rots[i];
+          buf.push_back(dev::RotDev{g.p - step.a, 0, g.c, g.s.real(), g.s.imag()});
+        }
+        if (step.kind == 0) {
           dev::StageDev st{};
           st.type = dev::ST_GIVENS;
-          st.a = best_a;
+          st.a = step.a;
           st.nrot = (int)buf.size();
           st.shape = stage_shape(buf, ss.Wseg);
           st.rots = up.put(buf.data(), buf.size());
           stages.push_back(st);
           cur.real = cur.real && d.real;
-          cur.valu_slots += (double)best.size() * pairs_per_row * (double)n_rows * (d.real ? 8.0 : 12.0);
-          cur.rot_sides += best.size() / K;
+          cur.valu_slots += slots;
+          cur.rot_sides += step.idx.size() / K;
           any = true;
+        } else {
+          // other rotations crossing segments: one whole-spin window pass
+          flush_seg(false);
+          Launch w{};
+          w.kind = Launch::WIN;
+          w.layout = layout;
+          w.real = d.real;
+          w.a = step.a;
+          w.nrot = (int)buf.size();
+          w.rots = up.put(buf.data(), buf.size());
+          w.valu_slots = slots;
+          w.rot_sides = step.idx.size() / K;
+          c.launches.push_back(w);
         }
-        if (n_done == d.rots.size()) break;
-        // a ready rotation on the pair straddling the segment window starts
-        // the next segment pass (applied as the segments are loaded)
-        flush_seg(false);
-        if (ss.cross) {
-          int xi = -1;
-          for (size_t i = 0; i < d.rots.size() && xi < 0; ++i) {
-            if (done[i] || d.rots[i].p != ss.wt - 1) continue;
-            bool ready = true;
-            for (int dp : deps[i]) ready = ready && done[dp];
-            if (ready) xi = (int)i;
-          }
-          if (xi >= 0) {
-            const Givens& g = d.rots[xi];
-            cur.cross = true;
-            cur.cross_rot = dev::RotDev{0, 0, g.c, g.s.real(), g.s.imag()};
-            cur.valu_slots += pairs_per_row * (double)n_rows * (d.real ? 8.0 : 12.0);
-            cur.rot_sides += 1.0 / K;
-            done[xi] = 1;
-            ++n_done;
-            continue;
-          }
-        }
-        // other rotations crossing segments: one whole-spin window pass
-        int best_a = -1;
-        std::vector<int> best;
-        for (int a = 0; a + P.W <= N; ++a) {
-          auto t = take_window(d.rots, deps, done, a, P.W);
-          if (t.size() > best.size()) {
-            best = t;
-            best_a = a;
-          }
-        }
-        if (best.empty()) throw Error(FFX_EDEVICE, "rotation schedule made no progress");
-        std::vector<dev::RotDev> buf;
-        for (int i : best) {
-          const Givens& g = d.rots[i];
-          buf.push_back(dev::RotDev{g.p - best_a, 0, g.c, g.s.real(), g.s.imag()});
-          done[i] = 1;
-        }
-        n_done += best.size();
-        Launch w{};
-        w.kind = Launch::WIN;
-        w.layout = layout;
-        w.real = d.real;
-        w.a = best_a;
-        w.nrot = (int)buf.size();
-        w.rots = up.put(buf.data(), buf.size());
-        w.valu_slots = (double)best.size() * pairs_per_row * (double)n_rows * (d.real ? 8.0 : 12.0);
-        w.rot_sides = best.size() / K;
-        c.launches.push_back(w);
       }
     }
     flush_seg(force_seg && !any);

@@ -158,29 +158,29 @@ void build_tables(ffx_batch_s& b) {
         mt_all.insert(mt_all.end(), rep.mt.begin(), rep.mt.end());
         wins.push_back(wd);
       }
-      // single excitations of spin cs per (p, q)
+      // the strings of one electron fewer and their one-orbital completions
       {
-        const int N = P.norb;
-        std::vector<int> exc, off;
+        const int N = P.norb, n = P.n[cs];
         std::map<uint64_t, int> addr;
         for (size_t k = 0; k < P.str[cs].size(); ++k) addr[P.str[cs][k]] = (int)k;
-        if (P.str[cs].size() > (1u << 14)) throw Error(FFX_EUNSUPPORTED, "batched sector too large");
-        for (int p = 0; p < N; ++p)
-          for (int q = 0; q < N; ++q) {
-            off.push_back((int)exc.size());
-            for (size_t k = 0; k < P.str[cs].size(); ++k) {
-              const uint64_t I = P.str[cs][k];
-              if (!((I >> q) & 1) || (p != q && ((I >> p) & 1))) continue;
-              const uint64_t J = (I & ~(1ull << q)) | (1ull << p);
-              const int lo = std::min(p, q), hi = std::max(p, q);
-              const uint64_t mid = hi - lo > 1 ? (I >> (lo + 1)) & ((1ull << (hi - lo - 1)) - 1) : 0;
-              const int odd = __builtin_popcountll(mid) & 1;
-              exc.push_back((int)k | (addr.at(J) << 14) | (odd << 28));
+        std::vector<int> kt;
+        int nk = 0;
+        if (n >= 1)
+          for (uint32_t K = 0; K < (1u << N); ++K) {
+            if (__builtin_popcount(K) != n - 1) continue;
+            ++nk;
+            for (int o = 0; o < 16; ++o) {
+              if (o >= N || ((K >> o) & 1u)) {
+                kt.push_back(-1);
+                continue;
+              }
+              const int odd = __builtin_popcount(K & ((1u << o) - 1u)) & 1;
+              kt.push_back(2 * addr.at((uint64_t)(K | (1u << o))) + odd);
             }
           }
-        off.push_back((int)exc.size());
-        t.exc[cs] = b.upload_table(exc);
-        t.exc_off[cs] = b.upload_table(off);
+        if (kt.empty()) kt.push_back(-1);
+        t.kt[cs] = b.upload_table(kt);
+        t.nk[cs] = nk;
       }
       t.win[cs] = b.upload_table(wins);
       t.mt_all[cs] = b.upload_table(mt_all);

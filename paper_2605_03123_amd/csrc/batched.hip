@@ -32,6 +32,7 @@ namespace ffx {
 namespace dev {
 
 constexpr int kBatchThreads = 256;
+typedef double bdouble4 __attribute__((ext_vector_type(4)));
 constexpr int kBatchMaxRows = 64;   // rows per task
 constexpr int kBatchMaxOrb = 16;    // orbitals of a batched sector
 // bounded wait, in ticks of the 100 MHz real-time counter (2 s)
@@ -230,34 +231,59 @@ __device__ __forceinline__ void rdm_task_cs(const BPassDev& ps, const BTypeDev& 
     }
   }
   __syncthreads();
-  const int* exc = ty.exc[cs];
-  const int* off = ty.exc_off[cs];
-  for (int pq = wave; pq < NN; pq += nw) {
-    const int beg = off[pq], end = off[pq + 1];
-    double re = 0, im = 0;
-    for (int e = beg + lane; e < end; e += 64) {
-      const int v = exc[e];
-      const int i = v & 0x3fff, j = (v >> 14) & 0x3fff;
-      double sr = 0, si = 0;
-      for (int r = 0; r < nr; ++r) {
-        const V a = bl[(int64_t)r * len + j], b = bp[(int64_t)r * len + i];
-        const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
-        sr += ax * bx + ay * by;
-        si += ax * by - ay * bx;
+  // T_pq = sum over rows and strings K of one electron fewer of
+  // conj(lam[K + p]) psi[K + q] s_p(K) s_q(K), on the FP64 matrix cores: lane l
+  // takes orbital l % 16 of string l / 16 of a block of four strings
+  // (v_mfma_f64_16x16x4: A[l % 16][l / 16], B[l / 16][l % 16], result
+  // D[l / 16 + 4 t][l % 16]); sums in a fixed order (per wave, then over waves)
+  const int* kt = ty.kt[cs];
+  const int nk = ty.nk[cs];
+  const int o = lane & 15, kk = lane >> 4;
+  bdouble4 rr = {0.0, 0.0, 0.0, 0.0}, ii = rr, ri = rr, ir = rr;
+  const int nkb = (nk + 3) >> 2;
+  for (int kb = wave; kb < nkb; kb += nw) {
+    const int k = 4 * kb + kk;
+    const int v = k < nk ? kt[k * 16 + o] : -1;
+    const int64_t col = v >> 1;
+    const bool neg = v & 1;
+    for (int r = 0; r < nr; ++r) {
+      double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+      if (v >= 0) {
+        const V a = bl[(int64_t)r * len + col], b = bp[(int64_t)r * len + col];
+        ar = (double)a.x;
+        ai = (double)a.y;
+        br = (double)b.x;
+        bi = (double)b.y;
+        if (neg) {
+          ar = -ar;
+          ai = -ai;
+          br = -br;
+          bi = -bi;
+        }
       }
-      if ((v >> 28) & 1) {
-        sr = -sr;
-        si = -si;
-      }
-      re += sr;
-      im += si;
+      rr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, rr, 0, 0, 0);
+      ii = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, ii, 0, 0, 0);
+      ri = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, ri, 0, 0, 0);
+      ir = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, ir, 0, 0, 0);
     }
-    re = wave_sum(re);
-    im = wave_sum(im);
-    if (lane == 0) {
-      ps.partials[(int64_t)task * 2 * NN + 2 * pq] = re;
-      ps.partials[(int64_t)task * 2 * NN + 2 * pq + 1] = im;
+  }
+  double* red = L.acc;  // [wave][re 256 | im 256]
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int pq = (kk + 4 * t) * 16 + o;
+    red[wave * 512 + pq] = rr[t] + ii[t];
+    red[wave * 512 + 256 + pq] = ri[t] - ir[t];
+  }
+  __syncthreads();
+  for (int i = tid; i < NN; i += nthr) {
+    const int p = i / N, q = i - p * N;
+    double re = 0.0, im = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      re += red[w * 512 + p * 16 + q];
+      im += red[w * 512 + 256 + p * 16 + q];
     }
+    ps.partials[(int64_t)task * 2 * NN + 2 * i] = re;
+    ps.partials[(int64_t)task * 2 * NN + 2 * i + 1] = im;
   }
 }
 

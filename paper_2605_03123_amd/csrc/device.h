@@ -277,12 +277,12 @@ struct BTypeDev {
   const SegWinDev* win[2];
   const int* mt_all[2];
   int n_mt_all[2];
-  // per string spin s: single excitations J = I - q + p (q in I; p not in I or
-  // p == q) listed per pair (p, q): exc[s][exc_off[s][p * norb + q] ...] =
-  // i | (j << 14) | (odd << 28), odd = parity of the occupied orbitals strictly
-  // between p and q
-  const int* exc[2];
-  const int* exc_off[2];
+  // per string spin s, for the transition one-body matrices: the strings K of
+  // n_s - 1 electrons, nk[s] of them, and for each K and orbital o < 16:
+  // kt[s][16 K + o] = 2 rank(K + o) + parity(K below o) if o < norb and o is
+  // not in K, else -1
+  const int* kt[2];
+  int nk[2];
 };
 
 // one table of a TABLES pass: a diagonal function's per-string tables (A over

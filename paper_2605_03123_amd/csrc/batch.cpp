@@ -183,6 +183,7 @@ void build_tables(ffx_batch_s& b) {
         t.nk[cs] = nk;
       }
       t.win[cs] = b.upload_table(wins);
+      while (mt_all.size() % 4) mt_all.push_back(0);  // staged as int4 words
       t.mt_all[cs] = b.upload_table(mt_all);
       t.n_mt_all[cs] = (int)mt_all.size();
       b.max_mt = std::max(b.max_mt, (int)mt_all.size());

@@ -379,38 +379,91 @@ __device__ __forceinline__ void seg_task(const BatchDev& B, const BPassDev& ps, 
   V* buf = (V*)L.rows;
   const V* s = (const V*)src;
 
-  // gather: element (r, k) of the layout lands at buf[r * len + k]
-  if (ps.layout == 0) {
-    for (int64_t x = tid; x < nel; x += nthr) buf[x] = s[r0 * len + x];
-  } else {
-    for (int64_t x = tid; x < nel; x += nthr) {
-      const int64_t k = x / nr, r = x - k * nr;
-      buf[r * len + k] = s[k * ncols_state + r0 + r];
+  // gather: element (r, k) of the layout lands at buf[r * len + k]; every
+  // thread requests kU elements before it stores any
+  constexpr int kU = 8;
+  for (int64_t x0 = tid; x0 < nel; x0 += kU * nthr) {
+    V t[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t x = min(x0 + (int64_t)u * nthr, nel - 1);
+      if (ps.layout == 0) {
+        t[u] = s[r0 * len + x];
+      } else {
+        const int64_t k = x / nr, r = x - k * nr;
+        t[u] = s[k * ncols_state + r0 + r];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) keep(t[u]);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t x = x0 + (int64_t)u * nthr;
+      if (x < nel) {
+        if (ps.layout == 0) {
+          buf[x] = t[u];
+        } else {
+          const int64_t k = x / nr, r = x - k * nr;
+          buf[r * len + k] = t[u];
+        }
+      }
     }
   }
   for (int64_t x = nel + tid; x < (int64_t)RR * len; x += nthr) buf[x] = V{};
-  for (int i = tid; i < pick2(ty.n_mt_all, cs); i += nthr) L.mt[i] = pick2(ty.mt_all, cs)[i];
+  {
+    // (the member-offset tables are a whole number of int4 words)
+    const int n4 = pick2(ty.n_mt_all, cs) >> 2;
+    const int4* m4 = (const int4*)pick2(ty.mt_all, cs);
+    for (int i0 = tid; i0 < n4; i0 += 4 * nthr) {
+      int4 q[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) q[u] = m4[min(i0 + u * nthr, n4 - 1)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) keep(q[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i0 + u * nthr < n4) ((int4*)L.mt)[i0 + u * nthr] = q[u];
+    }
+  }
   __syncthreads();
 
   const uint32_t* cmask = pick2(ty.masks, cs);
   const uint32_t* rmask = pick2(ty.masks, rs) + r0;
   double acc = 0.0;
-  for (int si = 0; si < ps.n_stages; ++si) {
+  // each Givens stage's rotations and first class codes are requested a stage
+  // ahead (as in the segment pass)
+  RotLane<R> rl_next{0, R(1), R(0), R(0)};
+  ChunkAhead fc_next{1, -1};
+  auto fetch = [&](int si) {
     const StageDev st = uniform_load(ps.stages + si);
     if (st.type == ST_GIVENS) {
+      rl_next = fetch_rot_lane<R>(st.rots, st.nrot, lane);
+      fc_next = fetch_first_chunk(uniform_load(pick2(ty.win, cs) + st.a), wave, lane);
+    }
+  };
+  if (ps.n_stages > 0) fetch(0);
+  for (int si = 0; si < ps.n_stages; ++si) {
+    const StageDev st = uniform_load(ps.stages + si);
+    const RotLane<R> rl = rl_next;
+    const ChunkAhead fc = fc_next;
+    if (si + 1 < ps.n_stages) fetch(si + 1);
+    if (st.type == ST_GIVENS) {
       const SegWinDev wt = uniform_load(pick2(ty.win, cs) + st.a);
-      const RotLane<R> rl = load_rot_lane<R>(st.rots, st.nrot, lane);
-      givens_stage<W, REAL, R>(st.shape, buf, L.mt, wt, rl, st.nrot, wave, nwaves, lane,
-                               fetch_first_chunk(wt, wave, lane));
+      givens_stage<W, REAL, R>(st.shape, buf, L.mt, wt, rl, st.nrot, wave, nwaves, lane, fc);
     } else {
       // per row: cross weights w_r[q] = sum_{p in row} C[p][q] and the row factor
       for (int i = tid; i < nr * N; i += nthr) {
         const int r = i / N, q = i - r * N;
         double w = 0.0;
         if (st.C) {
+          // the column of C is requested whole before the masked sum
           const uint32_t rm = rmask[r];
-          for (int p = 0; p < N; ++p)
-            if ((rm >> p) & 1) w += st.C[p * N + q];
+          double cq[kBatchMaxOrb];
+#pragma unroll
+          for (int p = 0; p < kBatchMaxOrb; ++p) cq[p] = st.C[min(p, N - 1) * N + q];
+#pragma unroll
+          for (int p = 0; p < kBatchMaxOrb; ++p)
+            if (p < N && ((rm >> p) & 1)) w += cq[p];
         }
         L.wq[r * kBatchMaxOrb + q] = w;
       }

@@ -146,18 +146,19 @@ constexpr int kMaxStageRots = 64;  // rotations per Givens stage of a segment pa
 enum StageType { ST_GIVENS = 0, ST_PHASE = 1, ST_SCALE = 2, ST_REDUCE = 3 };
 
 // Stage shapes: the window positions, in order, of the rotations of the
-// Givens stages that the window scheduler cuts from the column-elimination
+// Givens stages that the window schedulers cut from the column-elimination
 // network at window width 6 (the full triangle of a 6-orbital window, the
 // 3 x 3 parallelogram that sweeps a window across the network, with and
-// without its tail, the descending diagonal at the end, and the forms that
-// appear at small norb).  A stage whose rotation list is one of these runs
+// without its tail, the 4 x 2 parallelogram and its extension to a 14-rotation
+// trapezoid that the searched schedules use, the descending diagonal at the
+// end, and the forms that appear at small norb).  A stage whose rotation list is one of these runs
 // straight-line code with the positions fixed at compile time; any other
 // stage runs the generic loop that selects each rotation's position at run
 // time.
 constexpr int kShapeW = 6;
-constexpr int kNumShapes = 8;
+constexpr int kNumShapes = 10;
 constexpr int kShapeMaxLen = 15;
-constexpr int kShapeLen[kNumShapes] = {15, 9, 12, 5, 4, 8, 5, 9};
+constexpr int kShapeLen[kNumShapes] = {15, 9, 12, 5, 4, 8, 5, 9, 8, 14};
 constexpr int kShapeP[kNumShapes][kShapeMaxLen] = {
     {0, 1, 2, 3, 4, 0, 1, 2, 3, 0, 1, 2, 0, 1, 0},
     {2, 3, 4, 1, 2, 3, 0, 1, 2},
@@ -167,6 +168,8 @@ constexpr int kShapeP[kNumShapes][kShapeMaxLen] = {
     {3, 4, 2, 3, 1, 2, 0, 1},
     {1, 2, 0, 1, 0},
     {3, 4, 2, 3, 1, 2, 0, 1, 0},
+    {1, 2, 3, 4, 0, 1, 2, 3},
+    {1, 2, 3, 4, 0, 1, 2, 3, 0, 1, 2, 0, 1, 0},
 };
 
 // f(row, col) = A[row] + B[col] + sum_{p in row, q in col} C[p * norb + q]

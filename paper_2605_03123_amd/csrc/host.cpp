@@ -151,6 +151,70 @@ std::vector<Pass> schedule_windows(const std::vector<Givens>& rots, int norb, in
   return out;
 }
 
+std::vector<Pass> schedule_windows_beam(const std::vector<Givens>& rots, int norb, int w, int beam) {
+  const int n = (int)rots.size();
+  std::vector<std::vector<int>> deps(n);
+  std::vector<int> last(norb, -1);
+  for (int i = 0; i < n; ++i) {
+    const int p = rots[i].p;
+    if (p < 0 || p + 1 >= norb) throw Error(FFX_EINVAL, "rotation outside the orbitals");
+    for (int q : {p, p + 1})
+      if (last[q] >= 0) deps[i].push_back(last[q]);
+    last[p] = last[p + 1] = i;
+  }
+  using Set = std::vector<uint64_t>;
+  const int words = (n + 63) / 64;
+  auto has = [](const Set& d, int i) { return (d[i >> 6] >> (i & 63)) & 1ull; };
+  // the rotations inside [a, a + w) whose predecessors are applied or taken
+  auto take = [&](const Set& d, int a) {
+    std::vector<int> out;
+    std::vector<char> taken(n, 0);
+    for (int i = 0; i < n; ++i) {
+      if (has(d, i)) continue;
+      const int p = rots[i].p;
+      if (p < a || p + 1 >= a + w) continue;
+      bool ok = true;
+      for (int dd : deps[i])
+        if (!has(d, dd) && !taken[dd]) {
+          ok = false;
+          break;
+        }
+      if (ok) {
+        taken[i] = 1;
+        out.push_back(i);
+      }
+    }
+    return out;
+  };
+  struct Node {
+    int count;
+    std::vector<Pass> hist;
+  };
+  std::vector<std::pair<Set, Node>> front{{Set(words, 0), Node{0, {}}}};
+  if (n == 0) return {};
+  for (int step = 0; step < n; ++step) {
+    std::map<Set, Node> next;  // ordered: the search is deterministic
+    for (const auto& fn : front)
+      for (int a = 0; a + w <= norb; ++a) {
+        std::vector<int> t = take(fn.first, a);
+        if (t.empty()) continue;
+        Set d = fn.first;
+        for (int i : t) d[i >> 6] |= 1ull << (i & 63);
+        if (next.count(d)) continue;
+        Node nd{fn.second.count + (int)t.size(), fn.second.hist};
+        nd.hist.push_back(Pass{a, std::move(t)});
+        next.emplace(std::move(d), std::move(nd));
+      }
+    std::vector<std::pair<Set, Node>> v(next.begin(), next.end());
+    std::stable_sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.second.count > y.second.count; });
+    if (!v.empty() && v[0].second.count == n) return v[0].second.hist;
+    if ((int)v.size() > beam) v.resize(beam);
+    if (v.empty()) break;
+    front = std::move(v);
+  }
+  return schedule_windows(rots, norb, w);
+}
+
 WindowTable build_window_table(const std::vector<uint64_t>& strs, int norb, int n, int a, int w) {
   (void)norb;
   (void)n;

@@ -75,6 +75,8 @@ std::vector<int> take_window(const std::vector<Givens>& rots, const std::vector<
 // window pass.  It depends only on the positions of the rotations and the
 // window parameters, so it is computed once per structure and reused (every
 // decomposition of an N-orbital rotation has the same positions).
+constexpr int kScheduleBeam = 300;  // partial schedules kept by the stage search
+
 struct SchedStep {
   int kind;  // 0: segment-pass stage at window a; 1: crossing rotation idx[0]; 2: whole-spin window pass at a
   int a;
@@ -91,6 +93,20 @@ const std::vector<SchedStep>& rotation_schedule(const std::vector<Givens>& rots,
   auto it = cache.find(key);
   if (it != cache.end()) return it->second;
   std::vector<SchedStep> out;
+  // no rotation crosses the segment window: the searched schedule (fewer
+  // stages than the greedy one for some sizes, e.g. 12 instead of 13 at 16
+  // orbitals)
+  int max_p = -1;
+  for (const Givens& g : rots) max_p = std::max(max_p, g.p);
+  if (wseg >= 2 && max_p + 2 <= wt) {
+    bool fits = true;
+    for (const Pass& ps : schedule_windows_beam(rots, wt, wseg, kScheduleBeam)) {
+      if ((int)ps.idx.size() > cap) fits = false;
+      out.push_back(SchedStep{0, ps.a, ps.idx});
+    }
+    if (fits) return cache.emplace(std::move(key), std::move(out)).first->second;
+    out.clear();
+  }
   const auto deps = rotation_deps(rots, N);
   std::vector<char> done(rots.size(), 0);
   size_t n_done = 0;

@@ -200,23 +200,6 @@ __device__ __forceinline__ double lane_bcast(double v, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Must be called with every lane of the wave active.
-template <class R>
-__device__ __forceinline__ RotLane<R> load_rot_lane(const RotDev* rots, int nrot, int lane) {
-  RotLane<R> x{0, R(1), R(0), R(0)};
-  if (lane < nrot) {
-    const RotDev g = rots[lane];
-    x.p = g.p;
-    x.c = (R)g.c;
-    x.sr = (R)g.sr;
-    x.si = (R)g.si;
-  }
-  // materialize the values here, where every lane is active, so that the
-  // loads are not moved into a lane-divergent branch
-  asm volatile("" : "+v"(x.p), "+v"(x.c), "+v"(x.sr), "+v"(x.si));
-  return x;
-}
-
 template <int W, int M, bool REAL, class R>
 __device__ __forceinline__ void apply_rots_lane(typename V2T<R>::type* v, const RotLane<R>& rl, int nrot) {
   for (int r = 0; r < nrot; ++r) {

@@ -10,7 +10,9 @@ Whole oracle states do not fit these sizes, so the checks are:
   * a full random DF step followed by its exact inverse built from the
     single-gate entry points (reversibility over the whole state);
   * two DF steps at norb = 14 (7, 7) from Hartree-Fock against stored oracle
-    amplitudes (tests/golden/df_trotter_n14.txt).
+    amplitudes (tests/golden/df_trotter_n14.txt);
+  * the LUCJ adjoint gradient at norb = 16 (8, 8) against central differences
+    of GPU energies on sampled parameters, and complex64 against complex128.
 States at norb >= 16 are drawn on the device from a seeded torch generator and
 copied to the host for the oracle: both sides read the same values.
 """
@@ -173,3 +175,31 @@ def test_df_trotter_config2_golden(ffx, dtype):
     assert abs(torch.linalg.vector_norm(x.to(torch.complex128)).item() - norm) <= tol
     e = ffx.df_energy(x, w.data["ham"], 14, (7, 7))
     assert abs(e - energy.real) <= (1e-10 if dtype == torch.complex128 else 1e-5) * max(1.0, abs(energy.real))
+
+
+def test_lucj_gradient_n16_matches_central_differences(ffx):
+    # the adjoint gradient at the benchmark size (segment passes with crossing
+    # rotations, matrix-core transition matrices) against forward-only central
+    # differences on a few parameters, and the complex64 gradient against it
+    norb, nelec, n_reps = 16, (8, 8), 3
+    wl = synth.workload_lucj(norb, n_reps, 4, seed=3)
+    p, ham = wl.data["params"], wl.data["ham"]
+    e, g = ffx.lucj_energy_grad(p, ham, norb, nelec, n_reps, dtype=torch.complex128)
+    plan = ffx.get_plan(norb, nelec, torch.complex128, 0)
+    psi = torch.empty((plan.dim_a, plan.dim_b), dtype=torch.complex128, device="cuda:0")
+
+    def energy(q):
+        ffx.apply_lucj(q, norb, nelec, n_reps, dtype=torch.complex128, out=psi, plan=plan)
+        return ffx.df_energy(psi, ham, norb, nelec, plan=plan)
+
+    assert abs(energy(p) - e) <= 1e-10 * max(1.0, abs(e))
+    h = 1e-5
+    scale = max(1.0, float(np.max(np.abs(g))))
+    for i in synth.fd_indices(g.size, 4):
+        qp, qm = p.copy(), p.copy()
+        qp[i] += h
+        qm[i] -= h
+        assert abs((energy(qp) - energy(qm)) / (2 * h) - g[i]) <= 1e-7 * scale
+    e64, g64 = ffx.lucj_energy_grad(p, ham, norb, nelec, n_reps, dtype=torch.complex64)
+    assert abs(e64 - e) <= 1e-5 * max(1.0, abs(e))
+    assert np.max(np.abs(g64 - g)) <= 1e-4 * scale

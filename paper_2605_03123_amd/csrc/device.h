@@ -256,6 +256,13 @@ struct SegPassDev {
   // pass must not overwrite: src != dst)
   int cross;
   double cross_c, cross_sr, cross_si;
+  // gather: src holds the state in the other layout (element (r, c) of this
+  // pass at src[c * n_rows + r]), so the pass also transposes (it must not
+  // write src); blocks then take rows per XCD: block b works on XCD b % 8, on
+  // row (b % 8) * xcd_rows + (b / 8) / n_seg, segment (b / 8) % n_seg, so the
+  // blocks of one XCD gather neighbouring columns of the same cache lines
+  int gather;
+  int64_t xcd_rows;
 };
 
 // LDS needed by a segment pass whose longest segment holds max_len amplitudes

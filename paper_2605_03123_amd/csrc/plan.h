@@ -266,6 +266,8 @@ struct Launch {
   double rot_sides = 0;
   // a rotation on the pair straddling the segment window, applied at load
   bool cross = false;
+  // rows gathered from the other layout (replaces a transpose before the pass)
+  bool gather = false;
   dev::RotDev cross_rot{};
   // WIN
   int a = 0;

@@ -429,6 +429,25 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
   if (final_mode == FINAL_ACCUM &&
       (c.launches.empty() || c.launches.back().kind != Launch::SEG || c.launches.back().layout != 0))
     close_visit(true);  // a stage-free segment pass that adds the result into the target
+  // a transpose followed by a segment pass of the new layout: the pass
+  // gathers its rows from the old layout instead (one state round trip less).
+  // Measured at 16 orbitals: 2 % faster for complex128 (eight amplitudes of a
+  // cache line serve eight blocks of one XCD), 1.5 % slower for complex64
+  // (sixteen), so complex64 keeps the transposes.
+  std::vector<Launch> fused;
+  for (size_t i = 0; i < c.launches.size(); ++i) {
+    const Launch& L = c.launches[i];
+    if (!P.c64 && L.kind == Launch::TRANSPOSE && i + 1 < c.launches.size() &&
+        c.launches[i + 1].kind == Launch::SEG) {
+      Launch nx = c.launches[i + 1];
+      nx.gather = true;
+      fused.push_back(nx);
+      ++i;
+      continue;
+    }
+    fused.push_back(L);
+  }
+  c.launches = std::move(fused);
   return c;
 }
 
@@ -468,8 +487,8 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
       const Launch& L = c.launches[i];
       const bool store = L.kind == Launch::SEG && !(i == last_seg && c.final_mode != FINAL_STORE);
       if (L.kind == Launch::SEG) {
-        if (store && !at_src && (L.cross || move[i])) in_work = !in_work;
-        if (store && !at_src && !L.cross) last_plain = i;
+        if (store && !at_src && (L.cross || L.gather || move[i])) in_work = !in_work;
+        if (store && !at_src && !L.cross && !L.gather) last_plain = i;
         at_src = false;
       } else if (L.kind == Launch::TRANSPOSE && !square) {
         in_work = !in_work;
@@ -519,6 +538,10 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
         p.cross_sr = L.cross_rot.sr;
         p.cross_si = L.cross_rot.si;
       }
+      if (L.gather) {
+        p.gather = 1;
+        p.xcd_rows = (rows + 7) / 8;
+      }
       if (i == last_seg && c.final_mode == FINAL_ACCUM) {
         p.mode = dev::SEG_ACCUM;
         p.dst = accum;
@@ -527,10 +550,11 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
         p.dst = nullptr;
       } else {
         p.mode = dev::SEG_STORE;
-        if (cur_src == cur && (L.cross || move[i])) cur = (cur == work) ? P.tmp_state() : work;
+        if (cur_src == cur && (L.cross || L.gather || move[i])) cur = (cur == work) ? P.tmp_state() : work;
         p.dst = cur;
       }
-      if (L.cross && p.dst == p.src) throw Error(FFX_EDEVICE, "crossing rotation needs an out-of-place pass");
+      if ((L.cross || L.gather) && p.dst == p.src)
+        throw Error(FFX_EDEVICE, "crossing rotation or gathering pass needs an out-of-place pass");
       dev::seg_pass(P.c64, L.real, ss.Wseg, p, ss.threads, ss.lds, s);
       check_launch();
       if (L.reduce) {

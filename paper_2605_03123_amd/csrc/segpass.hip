@@ -57,10 +57,12 @@ __device__ const int4 kZeroWords = {0, 0, 0, 0};
 // segment and the tables to LDS; the partners stay in registers (xt).  Further
 // batches run only for segments longer than UR * nthr or tables longer than
 // UM * nthr words.
+// stride: distance between consecutive elements of the row in src and peer
+// (1, or the row count of a gathering pass, whose src is the other layout).
 template <int UR, int UM, class V>
 __device__ __forceinline__ void stage_segment(V* __restrict__ row, const V* __restrict__ src, int len,
                                               int4* __restrict__ mt, const int4* mtg, int n4, const V* peer,
-                                              int pcnt, V* xt, int tid, int nthr) {
+                                              int pcnt, V* xt, int tid, int nthr, int64_t stride) {
   const int4* pm = n4 > 0 ? mtg : &kZeroWords;
   const int pn4 = max(n4, 1);
   const V* pp = pcnt > 0 ? peer : src;
@@ -68,11 +70,11 @@ __device__ __forceinline__ void stage_segment(V* __restrict__ row, const V* __re
   V t[UR];
   int4 q[UM];
 #pragma unroll
-  for (int u = 0; u < UR; ++u) t[u] = src[min(tid + u * nthr, len - 1)];
+  for (int u = 0; u < UR; ++u) t[u] = src[(int64_t)min(tid + u * nthr, len - 1) * stride];
 #pragma unroll
   for (int u = 0; u < UM; ++u) q[u] = pm[min(tid + u * nthr, pn4 - 1)];
 #pragma unroll
-  for (int u = 0; u < kCrossU; ++u) xt[u] = pp[min(tid + u * nthr, pc - 1)];
+  for (int u = 0; u < kCrossU; ++u) xt[u] = pp[(int64_t)min(tid + u * nthr, pc - 1) * stride];
 #pragma unroll
   for (int u = 0; u < UR; ++u) keep(t[u]);
 #pragma unroll
@@ -83,7 +85,7 @@ __device__ __forceinline__ void stage_segment(V* __restrict__ row, const V* __re
 #pragma unroll
   for (int u = 0; u < UM; ++u)
     if (tid + u * nthr < n4) mt[tid + u * nthr] = q[u];
-  for (int e = tid + UR * nthr; e < len; e += nthr) row[e] = src[e];
+  for (int e = tid + UR * nthr; e < len; e += nthr) row[e] = src[(int64_t)e * stride];
   for (int e = tid + UM * nthr; e < n4; e += nthr) mt[e] = mtg[e];
 }
 
@@ -100,7 +102,7 @@ __device__ __forceinline__ typename V2T<R>::type cross_rot(typename V2T<R>::type
 template <class R>
 __device__ __forceinline__ void cross_apply(typename V2T<R>::type* own, const typename V2T<R>::type* t,
                                             const typename V2T<R>::type* peer, int cnt, int role, double cd,
-                                            double srd, double sid, int tid, int nthr) {
+                                            double srd, double sid, int tid, int nthr, int64_t stride) {
   const R c = (R)cd, sr = (R)srd, si = role == 0 ? (R)sid : -(R)sid;
   const R sgn = role == 0 ? R(1) : R(-1);
 #pragma unroll
@@ -108,7 +110,8 @@ __device__ __forceinline__ void cross_apply(typename V2T<R>::type* own, const ty
     const int e = tid + u * nthr;
     if (e < cnt) own[e] = cross_rot<R>(own[e], t[u], c, sgn, sr, si);
   }
-  for (int e = tid + kCrossU * nthr; e < cnt; e += nthr) own[e] = cross_rot<R>(own[e], peer[e], c, sgn, sr, si);
+  for (int e = tid + kCrossU * nthr; e < cnt; e += nthr)
+    own[e] = cross_rot<R>(own[e], peer[(int64_t)e * stride], c, sgn, sr, si);
 }
 
 template <int W, bool REAL, class R>
@@ -122,9 +125,18 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
   double* wq = (double*)(mtl + ((P.max_mt + 3) & ~3)); // 32 cross weights
   double* red = wq + 32;                               // block reduction scratch
 
-  const int64_t blk = blockIdx.x;
-  const int si = (int)(blk % P.n_seg);
-  const int64_t r = blk / P.n_seg;
+  int si;
+  int64_t r;
+  if (P.gather) {
+    const int64_t k = blockIdx.x >> 3;
+    r = (int64_t)(blockIdx.x & 7) * P.xcd_rows + k / P.n_seg;
+    si = (int)(k % P.n_seg);
+    if (r >= P.n_rows) return;  // the whole block: the grid rounds rows up to 8 XCDs
+  } else {
+    si = (int)(blockIdx.x % P.n_seg);
+    r = blockIdx.x / P.n_seg;
+  }
+  const int64_t blk = r * P.n_seg + si;
   const SegDev sg = uniform_load(P.segs + si);
   const int nthr = blockDim.x;
   const int tid = threadIdx.x;
@@ -132,17 +144,21 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
   const int wave = tid >> 6;
   const int nwaves = nthr >> 6;
 
-  const V* src = (const V*)P.src + r * P.row_len + sg.off;
+  // row r of this layout: contiguous, or column r of the other layout
+  const int64_t stride = P.gather ? P.n_rows : 1;
+  const V* src = P.gather ? (const V*)P.src + r + (int64_t)sg.off * P.n_rows
+                          : (const V*)P.src + r * P.row_len + sg.off;
   const bool xrot = P.cross && sg.cross_cnt > 0;
-  const V* peer = (const V*)P.src + r * P.row_len + sg.cross_peer;
+  const V* peer = P.gather ? (const V*)P.src + r + (int64_t)sg.cross_peer * P.n_rows
+                           : (const V*)P.src + r * P.row_len + sg.cross_peer;
   V xt[kCrossU];
   // (the member-offset table of every window is a whole number of int4 words)
   stage_segment<sizeof(V) == 8 ? 13 : 9, 2>(row, src, sg.len, (int4*)mtl, (const int4*)sg.mt_all,
-                                            sg.n_mt_all >> 2, peer, xrot ? sg.cross_cnt : 0, xt, tid, nthr);
+                                            sg.n_mt_all >> 2, peer, xrot ? sg.cross_cnt : 0, xt, tid, nthr, stride);
   __syncthreads();
   if (xrot) {
     cross_apply<R>(row + sg.cross_lo, xt, peer, sg.cross_cnt, sg.cross_role, P.cross_c, P.cross_sr, P.cross_si,
-                   tid, nthr);
+                   tid, nthr, stride);
     __syncthreads();
   }
 
@@ -380,7 +396,7 @@ static void launch_seg(const SegPassDev& p, int threads, size_t lds, hipStream_t
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
-  const int64_t blocks = p.n_rows * p.n_seg;
+  const int64_t blocks = p.gather ? 8 * p.xcd_rows * p.n_seg : p.n_rows * p.n_seg;
   hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(std::min(threads, seg_threads<W, R>())), lds, s, p);
 }
 

@@ -258,10 +258,12 @@ struct SegPassDev {
   double cross_c, cross_sr, cross_si;
   // gather: src holds the state in the other layout (element (r, c) of this
   // pass at src[c * n_rows + r]), so the pass also transposes (it must not
-  // write src); blocks then take rows per XCD: block b works on XCD b % 8, on
-  // row (b % 8) * xcd_rows + (b / 8) / n_seg, segment (b / 8) % n_seg, so the
-  // blocks of one XCD gather neighbouring columns of the same cache lines
+  // write src).
   int gather;
+  // xcd_rows > 0: blocks take rows per XCD: block b works on XCD b % 8, on row
+  // (b % 8) * xcd_rows + (b / 8) / n_seg, segment (b / 8) % n_seg, so that the
+  // blocks of one XCD gather neighbouring columns of the same cache lines, and
+  // the segments of one row (whose crossing partners overlap) share an L2
   int64_t xcd_rows;
 };
 

@@ -538,10 +538,8 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
         p.cross_sr = L.cross_rot.sr;
         p.cross_si = L.cross_rot.si;
       }
-      if (L.gather) {
-        p.gather = 1;
-        p.xcd_rows = (rows + 7) / 8;
-      }
+      if (L.gather) p.gather = 1;
+      if (L.gather || L.cross) p.xcd_rows = (rows + 7) / 8;
       if (i == last_seg && c.final_mode == FINAL_ACCUM) {
         p.mode = dev::SEG_ACCUM;
         p.dst = accum;

@@ -127,7 +127,7 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
 
   int si;
   int64_t r;
-  if (P.gather) {
+  if (P.xcd_rows > 0) {
     const int64_t k = blockIdx.x >> 3;
     r = (int64_t)(blockIdx.x & 7) * P.xcd_rows + k / P.n_seg;
     si = (int)(k % P.n_seg);
@@ -396,7 +396,7 @@ static void launch_seg(const SegPassDev& p, int threads, size_t lds, hipStream_t
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
-  const int64_t blocks = p.gather ? 8 * p.xcd_rows * p.n_seg : p.n_rows * p.n_seg;
+  const int64_t blocks = p.xcd_rows > 0 ? 8 * p.xcd_rows * p.n_seg : p.n_rows * p.n_seg;
   hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(std::min(threads, seg_threads<W, R>())), lds, s, p);
 }
 

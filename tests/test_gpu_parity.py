@@ -174,7 +174,8 @@ def test_df_energy(ffx, dtype, norb, nelec):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("norb,nelec,n_reps", [(4, (2, 1), 2), (6, (3, 3), 2), (8, (4, 4), 1)])
+@pytest.mark.parametrize("norb,nelec,n_reps", [(4, (2, 1), 2), (6, (3, 3), 2), (8, (4, 4), 1), (5, (0, 2), 1),
+                                             (5, (5, 3), 1), (7, (1, 6), 2)])
 def test_lucj_energy_grad_matches_oracle_adjoint(ffx, dtype, norb, nelec, n_reps):
     r = synth.rng([15, norb])
     params = synth.lucj_params(r, norb, n_reps, scale=0.3)

@@ -139,8 +139,10 @@ typedef struct {
 int ffx_lucj_n_params(int norb, int n_reps);
 int ffx_apply_lucj(ffx_plan plan, void* vec, const ffx_lucj* op, void* stream);
 
-/* Workspace size in bytes for ffx_df_energy / ffx_lucj_energy_grad. */
-int64_t ffx_workspace_bytes(ffx_plan plan, int what /* 0 = energy, 1 = gradient */);
+/* Workspace size in bytes: what = 0 for ffx_df_energy and
+   ffx_apply_df_hamiltonian (one state), 1 for the gradients, 2 for
+   ffx_df_evolve_exact (four states). */
+int64_t ffx_workspace_bytes(ffx_plan plan, int what);
 
 /* Energy <psi|H|psi> of vec for the DF Hamiltonian (Sec. 4.2), evaluated as
    sum_t sum_I w_t(I) |(script-U(U_t)^dag psi)(I)|^2 with the one-body term in
@@ -149,6 +151,42 @@ int64_t ffx_workspace_bytes(ffx_plan plan, int what /* 0 = energy, 1 = gradient 
    ffx_workspace_bytes(plan, 0) bytes.  Synchronizes the stream. */
 int ffx_df_energy(ffx_plan plan, const void* vec, const ffx_df_ham* ham, double* energy,
                   void* workspace, void* stream);
+
+/* Action of the DF Hamiltonian (Eq. double-factorized-hamiltonian, in the
+   form of Sec. 4.2): out = H vec = sum_t script-U(W_t) D_t script-U(W_t)^dag vec
+   with W_0 the eigenvectors of h and D_0 = sum_p eps_p N_p, W_t = U_t and
+   D_t = 1/2 sum_pq J_t[p][q] N_p N_q (N_p = n_{p alpha} + n_{p beta}).  vec
+   (read only), out and workspace (ffx_workspace_bytes(plan, 0) bytes) are
+   distinct device buffers; FFX_EINVAL when two of them are the same pointer.
+   Enqueues only. */
+int ffx_apply_df_hamiltonian(ffx_plan plan, const void* vec, void* out, const ffx_df_ham* ham, void* workspace,
+                             void* stream);
+
+/* Exact time evolution vec <- exp(-i H time) vec for the DF Hamiltonian, the
+   reference that Trotter errors are measured against (Sec. 6.2, estimating
+   Trotter error), by a Chebyshev expansion of the exponential in the
+   Hamiltonian action above.  The spectrum of H in the plan's sector is
+   enclosed in [lo, hi] from the terms' weights (one-body term: the sums of the
+   n lowest and n highest eigenvalues of h per spin; term t: the eigenvalue
+   range of J_t times the range of |x|^2 over occupation vectors x); with
+   c = (lo + hi) / 2 and r = (hi - lo) / 2,
+     exp(-i H time) = exp(-i c time) sum_k (2 - delta_k0) (-i)^k J_k(r time) T_k((H - c) / r)
+   (J_k Bessel functions of the first kind, T_k Chebyshev polynomials).  The
+   series stops at the first K whose dropped terms weigh at most tol / 2 in
+   total (2 sum_{k > K} |J_k(r |time|)|), so the truncation error is below
+   tol / 2 times ||vec|| in exact arithmetic; rounding adds about K times the
+   unit roundoff of the state's type (complex64: tol below about 1e-5 is not
+   reached).  n_matvec (host, may be NULL) receives K, the number of
+   Hamiltonian actions.  workspace: ffx_workspace_bytes(plan, 2) bytes, not
+   overlapping vec.  Enqueues only.  FFX_EINVAL for a non-finite time or a tol
+   that is not positive; FFX_EUNSUPPORTED when r |time| exceeds about 1e6. */
+int ffx_df_evolve_exact(ffx_plan plan, void* vec, const ffx_df_ham* ham, double time, double tol, void* workspace,
+                        int* n_matvec, void* stream);
+
+/* Euclidean distance ||x - y||_2 of two states of the plan (device, read
+   only), accumulated in FP64 in a fixed order: the Trotter error measure of
+   Sec. 6.2.  Synchronizes the stream. */
+int ffx_state_distance(ffx_plan plan, const void* x, const void* y, double* dist, void* stream);
 
 /* LUCJ energy E(theta) = <psi(theta)|H|psi(theta)> and its gradient
    dE/dtheta (n_params doubles) by the adjoint method: the costate

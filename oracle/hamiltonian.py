@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import numpy as np
 import scipy.linalg
+import scipy.sparse.linalg as spla
 
 from . import gates as g
 
@@ -40,6 +41,30 @@ def apply_df_hamiltonian(vec: np.ndarray, ham, norb: int, nelec) -> np.ndarray:
 def df_energy(vec: np.ndarray, ham, norb: int, nelec) -> complex:
     """<psi|H|psi> (the paper's np.vdot(vec, linop @ vec), Sec. 4.2).  Real part is the energy."""
     return np.vdot(vec, apply_df_hamiltonian(vec, ham, norb, nelec))
+
+
+def evolve_exact(vec: np.ndarray, ham, time: float, norb: int, nelec) -> np.ndarray:
+    """exp(-i H time) psi: the exact evolution that Trotter errors are measured
+    against (Sec. 6.2).  H acts through apply_df_hamiltonian above; scipy's
+    expm_multiply (a library step) takes the exponential of that operator."""
+    shape = vec.shape
+    n = vec.size
+
+    def mv(x):
+        return apply_df_hamiltonian(np.asarray(x).reshape(shape), ham, norb, nelec).reshape(-1)
+
+    op = spla.LinearOperator((n, n), matvec=mv, rmatvec=mv, dtype=np.complex128)
+    out = spla.expm_multiply((-1j * time) * op, vec.reshape(-1).astype(np.complex128), traceA=0.0)
+    return np.asarray(out).reshape(shape)
+
+
+def trotter_error(vec: np.ndarray, ham, time: float, norb: int, nelec, n_steps: int, order: int,
+                  exact: np.ndarray | None = None) -> float:
+    """||psi_Trotter - psi_exact||_2 (Sec. 6.2)."""
+    if exact is None:
+        exact = evolve_exact(vec, ham, time, norb, nelec)
+    approx = simulate_trotter(vec, ham, time, norb, nelec, n_steps=n_steps, order=order)
+    return float(np.linalg.norm(approx - exact))
 
 
 # ---------------------------------------------------------------------------

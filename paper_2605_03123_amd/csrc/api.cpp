@@ -611,6 +611,7 @@ int64_t ffx_workspace_bytes(ffx_plan plan, int what) {
   if (!plan) return -1;
   const int64_t S = ((int64_t)plan->state_bytes() + 255) / 256 * 256;
   if (what == 0) return S;
+  if (what == 2) return 4 * S;
   const int64_t dmax = std::max(plan->dim[0], plan->dim[1]);
   const int64_t part = ((int64_t)plan->norb * plan->norb * dmax * 16 + 255) / 256 * 256;
   return 5 * S + part;
@@ -645,6 +646,132 @@ int ffx_df_energy(ffx_plan plan, const void* vec, const ffx_df_ham* ham, double*
     double e = 0;
     for (double x : r) e += x;
     *energy = e;
+  });
+}
+
+namespace {
+
+// out = H in: term 0 stores, the others add; tmp holds each rotated copy.
+void apply_terms(ffx_plan_s& P, const std::vector<Compiled>& cs, const void* in, void* out, void* tmp,
+                 hipStream_t s) {
+  for (size_t t = 0; t < cs.size(); ++t) {
+    if (t == 0)
+      execute_program(P, cs[0], in, out, nullptr, s);
+    else
+      execute_program(P, cs[t], in, tmp, out, s);
+  }
+}
+
+std::vector<Compiled> compile_terms(ffx_plan_s& P, const DFHost& df, DecompPool& pool, hipStream_t s) {
+  std::vector<Program> terms = df_term_programs(df, pool, P.norb);
+  Upload up(&P, s);
+  std::vector<Compiled> cs;
+  for (int t = 0; t <= df.L; ++t) cs.push_back(compile_program(P, up, terms[t], t == 0 ? FINAL_STORE : FINAL_ACCUM, s));
+  up.commit();
+  return cs;
+}
+
+}  // namespace
+
+int ffx_apply_df_hamiltonian(ffx_plan plan, const void* vec, void* out, const ffx_df_ham* ham, void* workspace,
+                             void* stream) {
+  return guard([&] {
+    validate_plan(plan);
+    if (!vec || !out || !workspace) throw Error(FFX_EINVAL, "null pointer");
+    if (vec == out || vec == workspace || out == workspace)
+      throw Error(FFX_EINVAL, "vec, out and workspace must be distinct buffers");
+    ffx_plan_s& P = *plan;
+    DFHost df = load_df(P, ham);
+    DeviceGuard dg(P.device);
+    hipStream_t s = as_stream(stream);
+    DecompPool pool;
+    std::vector<Compiled> cs = compile_terms(P, df, pool, s);
+    apply_terms(P, cs, vec, out, workspace, s);
+  });
+}
+
+int ffx_df_evolve_exact(ffx_plan plan, void* vec, const ffx_df_ham* ham, double time, double tol, void* workspace,
+                        int* n_matvec, void* stream) {
+  return guard([&] {
+    validate_plan(plan);
+    if (!vec || !workspace) throw Error(FFX_EINVAL, "null pointer");
+    if (!std::isfinite(time) || !(tol > 0.0) || !std::isfinite(tol)) throw Error(FFX_EINVAL, "bad time or tolerance");
+    ffx_plan_s& P = *plan;
+    DFHost df = load_df(P, ham);
+    double lo, hi;
+    df_spectrum_bounds(df, P.norb, P.n[0], P.n[1], &lo, &hi);
+    const double c = 0.5 * (lo + hi);
+    // a little room so that rounding in the bounds cannot leave an eigenvalue outside
+    const double r = 0.5 * (hi - lo) * (1.0 + 1e-9) + 1e-12 * std::max(1.0, std::abs(c));
+    const double z = r * std::abs(time);
+    const double kmax_d = std::ceil(z + 10.0 * std::cbrt(z) + 60.0);
+    if (kmax_d > 1e6) throw Error(FFX_EUNSUPPORTED, "evolution time too long for one expansion");
+    const int kmax = (int)kmax_d;
+    const std::vector<double> J = bessel_j_series(z, kmax);
+    // truncation: the dropped terms weigh 2 sum_{j > K} |J_j(z)| at most (each
+    // T_j of the shifted and scaled H has norm <= 1)
+    int K = kmax;
+    {
+      double tail = 0.0;
+      for (int k = kmax; k >= 1; --k) {
+        if (tail + 2.0 * std::abs(J[k]) > 0.5 * tol) break;
+        tail += 2.0 * std::abs(J[k]);
+        K = k - 1;
+      }
+    }
+    if (K == kmax) throw Error(FFX_EUNSUPPORTED, "Chebyshev expansion did not converge within its length");
+    // coefficient of T_k: (2 - delta_k0) (-i)^k J_k(r time) exp(-i c time)
+    auto coef = [&](int k) {
+      double jk = J[k] * ((time < 0 && (k & 1)) ? -1.0 : 1.0);
+      cd ipow = (k % 4 == 0) ? cd(1, 0) : (k % 4 == 1) ? cd(0, -1) : (k % 4 == 2) ? cd(-1, 0) : cd(0, 1);
+      return (k == 0 ? 1.0 : 2.0) * jk * ipow * std::exp(cd(0.0, -c * time));
+    };
+    DeviceGuard dg(P.device);
+    hipStream_t s = as_stream(stream);
+    DecompPool pool;
+    std::vector<Compiled> cs = compile_terms(P, df, pool, s);
+    const size_t S = P.state_bytes();
+    const size_t Sa = (S + 255) / 256 * 256;
+    char* ws = (char*)workspace;
+    void* tprev = ws;
+    void* tcur = ws + Sa;
+    void* y = ws + 2 * Sa;
+    void* tmp = ws + 3 * Sa;
+    const int64_t n = P.elems();
+    HIPCHK(hipMemcpyAsync(tprev, vec, S, hipMemcpyDeviceToDevice, s));  // T_0 = vec
+    const cd c0 = coef(0);
+    dev::zscale(P.c64, vec, n, c0.real(), c0.imag(), s);
+    check_launch();
+    for (int k = 1; k <= K; ++k) {
+      // k = 1: T_1 = (H - c) T_0 / r into tcur; k >= 2: T_k = 2 (H - c) T_{k-1} / r - T_{k-2}
+      const void* src = k == 1 ? tprev : tcur;
+      apply_terms(P, cs, src, y, tmp, s);
+      const cd ck = coef(k);
+      if (k == 1) {
+        dev::cheb_step(P.c64, y, tprev, tcur, vec, n, 1.0 / r, -c / r, 0.0, ck.real(), ck.imag(), s);
+      } else {
+        dev::cheb_step(P.c64, y, tcur, tprev, vec, n, 2.0 / r, -2.0 * c / r, -1.0, ck.real(), ck.imag(), s);
+        std::swap(tprev, tcur);
+      }
+      check_launch();
+    }
+    if (n_matvec) *n_matvec = K;
+  });
+}
+
+int ffx_state_distance(ffx_plan plan, const void* x, const void* y, double* dist, void* stream) {
+  return guard([&] {
+    validate_plan(plan);
+    if (!x || !y || !dist) throw Error(FFX_EINVAL, "null pointer");
+    ffx_plan_s& P = *plan;
+    DeviceGuard dg(P.device);
+    hipStream_t s = as_stream(stream);
+    dev::dist2(P.c64, x, y, P.elems(), P.partials, P.results, s);
+    check_launch();
+    double d2 = 0;
+    HIPCHK(hipMemcpyAsync(&d2, P.results, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *dist = std::sqrt(d2);
   });
 }
 

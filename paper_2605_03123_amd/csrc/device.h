@@ -81,6 +81,14 @@ int inner_partials(int64_t n);
 void inner(bool c64, const void* x, const void* y, int64_t n, double* partials, double* out,
            hipStream_t stream);
 
+// Chebyshev step: t_prev <- a y + b t_cur + m t_prev; acc += (cr + i ci) t_prev
+void cheb_step(bool c64, const void* y, const void* tcur, void* tprev, void* acc, int64_t n, double a,
+               double b, double m, double cr, double ci, hipStream_t stream);
+// v *= (cr + i ci)
+void zscale(bool c64, void* v, int64_t n, double cr, double ci, hipStream_t stream);
+// out[0] = sum |x - y|^2 in FP64, fixed order; partials of size inner_partials(n)
+void dist2(bool c64, const void* x, const void* y, int64_t n, double* partials, double* out,
+           hipStream_t stream);
 // y += x
 void axpy(bool c64, const void* x, void* y, int64_t n, hipStream_t stream);
 // vec[i_a, i_b] = a[i_a] * b[i_b] (a, b complex double)

@@ -183,6 +183,42 @@ void expm_param_grad(int N, const std::vector<cd>& K, const std::vector<cd>& G, 
     }
 }
 
+std::vector<Program> df_term_programs(const DFHost& df, DecompPool& pool, int N) {
+  std::vector<Program> terms(df.L + 1);
+  for (int t = 0; t <= df.L; ++t) {
+    const Decomposition* to = pool.add(N, dagger(N, df.Wm(t)));
+    const Decomposition* from = pool.add(N, df.Wm(t));
+    terms[t].rot(to, to);
+    terms[t].scale(terms[t].add_diag(df_weight_spec(df, t)));
+    terms[t].rot(from, from);
+  }
+  return terms;
+}
+
+void df_spectrum_bounds(const DFHost& df, int N, int na, int nb, double* lo, double* hi) {
+  std::vector<double> e = df.eps;
+  std::sort(e.begin(), e.end());
+  double l = 0, h = 0;
+  for (int k = 0; k < na; ++k) l += e[k], h += e[N - 1 - k];
+  for (int k = 0; k < nb; ++k) l += e[k], h += e[N - 1 - k];
+  // |x|^2 = na + nb + 2 (doubly occupied orbitals)
+  const double x2min = na + nb + 2.0 * std::max(0, na + nb - N);
+  const double x2max = na + nb + 2.0 * std::min(na, nb);
+  for (int t = 0; t < df.L; ++t) {
+    std::vector<cd> Jc((size_t)N * N);
+    for (int i = 0; i < N * N; ++i) Jc[i] = df.J[t][i];
+    std::vector<double> w;
+    std::vector<cd> W;
+    eigh(N, Jc, w, W);
+    const double wmin = *std::min_element(w.begin(), w.end());
+    const double wmax = *std::max_element(w.begin(), w.end());
+    l += 0.5 * std::min(wmin * x2min, wmin * x2max);
+    h += 0.5 * std::max(wmax * x2min, wmax * x2max);
+  }
+  *lo = l;
+  *hi = h;
+}
+
 std::unique_ptr<LUCJGrad> build_lucj_grad(const ffx_plan_s& P, const ffx_lucj* op, const ffx_df_ham* ham) {
   const int N = P.norb;
   auto G = std::make_unique<LUCJGrad>();
@@ -190,14 +226,7 @@ std::unique_ptr<LUCJGrad> build_lucj_grad(const ffx_plan_s& P, const ffx_lucj* o
   G->df = load_df(P, ham);
   G->g = lucj_parts(P, G->L, G->pool, true);
   G->fwd = lucj_forward_program(G->g, G->L.R);
-  G->terms.resize(G->df.L + 1);
-  for (int t = 0; t <= G->df.L; ++t) {
-    const Decomposition* to = G->pool.add(N, dagger(N, G->df.Wm(t)));
-    const Decomposition* from = G->pool.add(N, G->df.Wm(t));
-    G->terms[t].rot(to, to);
-    G->terms[t].scale(G->terms[t].add_diag(df_weight_spec(G->df, t)));
-    G->terms[t].rot(from, from);
-  }
+  G->terms = df_term_programs(G->df, G->pool, N);
   G->undo_rot.resize(G->L.R);
   G->undo_diag.resize(G->L.R);
   for (int k = 0; k < G->L.R; ++k) {

@@ -103,6 +103,17 @@ DFHost load_df(const ffx_plan_s& P, const ffx_df_ham* ham);
 // term t: 1/2 sum_pq J_t[p][q] N_p N_q
 DiagSpec df_weight_spec(const DFHost& df, int term);
 
+// The terms of H = sum_t script-U(W_t) D_t script-U(W_t)^dag as gate programs
+// (W_0 = V with D_0 = sum_p eps_p N_p, W_t = U_t with D_t = 1/2 sum_pq J_t N_p N_q):
+// rotate into the term's basis, scale by its diagonal weight, rotate back.
+std::vector<Program> df_term_programs(const DFHost& df, DecompPool& pool, int N);
+
+// An interval [lo, hi] holding every eigenvalue of the DF Hamiltonian in the
+// (na, nb) sector: the sum over terms of the range of each diagonal weight
+// (exact for the one-body term; for a two-body term the eigenvalue range of
+// J_t times the range of |x|^2, x = occupation-number vector of both spins).
+void df_spectrum_bounds(const DFHost& df, int N, int na, int nb, double* lo, double* hi);
+
 // product formula as a list of (term, time) in application order
 void product_formula(int order, double t, int n_terms_total, std::vector<std::pair<int, double>>& out);
 

@@ -464,6 +464,34 @@ std::vector<cd> dagger(int n, const std::vector<cd>& A) {
   return B;
 }
 
+std::vector<double> bessel_j_series(double z, int kmax) {
+  if (!(z >= 0.0) || kmax < 0) throw Error(FFX_EINVAL, "bessel_j_series: bad argument");
+  std::vector<double> J((size_t)kmax + 1, 0.0);
+  if (z == 0.0) {
+    J[0] = 1.0;
+    return J;
+  }
+  // start far enough above both kmax and z that the error of the arbitrary
+  // starting values has decayed below double precision at k <= kmax
+  const int top = std::max(kmax, (int)std::ceil(z)) + 40 + (int)std::sqrt(40.0 * (std::max(kmax, (int)z) + 1));
+  const int start = top + (top & 1);
+  std::vector<double> v((size_t)start + 2, 0.0);
+  v[start + 1] = 0.0;
+  v[start] = 1e-300;
+  double norm = 0.0;
+  for (int k = start; k >= 1; --k) {
+    v[k - 1] = (2.0 * k / z) * v[k] - v[k + 1];
+    if (std::abs(v[k - 1]) > 1e250) {  // rescale everything computed so far
+      for (int j = k - 1; j <= start + 1; ++j) v[j] *= 1e-250;
+      norm *= 1e-250;
+    }
+    if ((k - 1) % 2 == 0 && k - 1 > 0) norm += 2.0 * v[k - 1];
+  }
+  norm += v[0];
+  for (int k = 0; k <= kmax; ++k) J[k] = v[k] / norm;
+  return J;
+}
+
 void eigh(int n, const std::vector<cd>& Ain, std::vector<double>& w, std::vector<cd>& W) {
   std::vector<cd> A = Ain;
   W.assign((size_t)n * n, 0.0);

@@ -486,6 +486,105 @@ void axpy(bool c64, const void* x, void* y, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_axpy<double>, g, dim3(256), 0, s, (const zc128*)x, (zc128*)y, n);
 }
 
+// One step of the Chebyshev recurrence of exp(-i H t) (grid-stride, one
+// complex entry per thread and trip):
+//   t_next = a * y + b * t_cur + m * t_prev   (stored over t_prev)
+//   acc   += coef * t_next
+// with y = H t_cur.  Combined in FP64, rounded once to the state's type.
+template <class R>
+__global__ __launch_bounds__(256) void k_cheb_step(const typename V2T<R>::type* __restrict__ y,
+                                                   const typename V2T<R>::type* __restrict__ tcur,
+                                                   typename V2T<R>::type* __restrict__ tprev,
+                                                   typename V2T<R>::type* __restrict__ acc, int64_t n,
+                                                   double a, double b, double m, double cr, double ci) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const auto vy = y[i], vc = tcur[i], va = acc[i];
+    double xr = a * (double)vy.x + b * (double)vc.x;
+    double xi = a * (double)vy.y + b * (double)vc.y;
+    if (m != 0.0) {  // m = 0: t_prev holds no value yet (first step)
+      const auto vp = tprev[i];
+      xr += m * (double)vp.x;
+      xi += m * (double)vp.y;
+    }
+    typename V2T<R>::type tn, an;
+    tn.x = (R)xr;
+    tn.y = (R)xi;
+    an.x = (R)((double)va.x + (cr * xr - ci * xi));
+    an.y = (R)((double)va.y + (cr * xi + ci * xr));
+    tprev[i] = tn;
+    acc[i] = an;
+  }
+}
+
+static dim3 stream_grid(int64_t n) {
+  const int64_t blocks = (n + 255) / 256;
+  return dim3((unsigned)std::min<int64_t>(blocks, 256 * 64));
+}
+
+void cheb_step(bool c64, const void* y, const void* tcur, void* tprev, void* acc, int64_t n, double a,
+               double b, double m, double cr, double ci, hipStream_t s) {
+  if (n <= 0) return;
+  if (c64)
+    hipLaunchKernelGGL(k_cheb_step<float>, stream_grid(n), dim3(256), 0, s, (const zc64*)y, (const zc64*)tcur,
+                       (zc64*)tprev, (zc64*)acc, n, a, b, m, cr, ci);
+  else
+    hipLaunchKernelGGL(k_cheb_step<double>, stream_grid(n), dim3(256), 0, s, (const zc128*)y,
+                       (const zc128*)tcur, (zc128*)tprev, (zc128*)acc, n, a, b, m, cr, ci);
+}
+
+// vec *= (cr + i ci)
+template <class R>
+__global__ __launch_bounds__(256) void k_zscale(typename V2T<R>::type* __restrict__ v, int64_t n, double cr,
+                                                double ci) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const auto x = v[i];
+    typename V2T<R>::type o;
+    o.x = (R)(cr * (double)x.x - ci * (double)x.y);
+    o.y = (R)(cr * (double)x.y + ci * (double)x.x);
+    v[i] = o;
+  }
+}
+
+void zscale(bool c64, void* v, int64_t n, double cr, double ci, hipStream_t s) {
+  if (n <= 0) return;
+  if (c64)
+    hipLaunchKernelGGL(k_zscale<float>, stream_grid(n), dim3(256), 0, s, (zc64*)v, n, cr, ci);
+  else
+    hipLaunchKernelGGL(k_zscale<double>, stream_grid(n), dim3(256), 0, s, (zc128*)v, n, cr, ci);
+}
+
+// sum |x - y|^2 in FP64: per-block partials (the blocks of inner()), then a
+// fixed-order sum
+template <class R>
+__global__ __launch_bounds__(256) void k_dist2(const typename V2T<R>::type* __restrict__ x,
+                                               const typename V2T<R>::type* __restrict__ y, int64_t n,
+                                               double* __restrict__ partials) {
+  __shared__ double sh[4];
+  double acc = 0;
+  const int64_t base = (int64_t)blockIdx.x * 256 * INNER_PER_THREAD + threadIdx.x;
+  for (int k = 0; k < INNER_PER_THREAD; ++k) {
+    const int64_t i = base + (int64_t)k * 256;
+    if (i < n) {
+      const double dr = (double)x[i].x - (double)y[i].x, di = (double)x[i].y - (double)y[i].y;
+      acc += dr * dr + di * di;
+    }
+  }
+  const double t = block_sum256(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+void dist2(bool c64, const void* x, const void* y, int64_t n, double* partials, double* out, hipStream_t s) {
+  const int nb = inner_partials(n);
+  if (c64)
+    hipLaunchKernelGGL(k_dist2<float>, dim3(nb), dim3(256), 0, s, (const zc64*)x, (const zc64*)y, n, partials);
+  else
+    hipLaunchKernelGGL(k_dist2<double>, dim3(nb), dim3(256), 0, s, (const zc128*)x, (const zc128*)y, n,
+                       partials);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, partials, nb, 1, out);
+}
+
 template <class R>
 __global__ void k_outer(const zc128* __restrict__ a, const zc128* __restrict__ b,
                         typename V2T<R>::type* __restrict__ vec, int64_t da, int64_t db) {

@@ -12,6 +12,7 @@
 // decomposition is diagonal, so it is deferred into the next diagonal phase
 // stage (or a final phase stage) instead of costing a pass of its own.
 #include <cmath>
+#include <deque>
 #include <map>
 #include <mutex>
 
@@ -285,7 +286,7 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
     Item it;
     it.kind = 0;
     it.d = d;
-    visit.push_back(it);
+    if (!d->rots.empty()) visit.push_back(it);
     Pending& pd = pend[sp];
     for (double x : d->phase)
       if (x != 0.0) pd.has = true;
@@ -394,10 +395,32 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
     pending_other.clear();
   };
 
+  // Rotations with c = 1 and s = 0 are exact identities and leave the
+  // program; so does an orbital rotation with no rotation and no phase left
+  // (for example the identity basis change of a diagonal-only term).
+  std::deque<Decomposition> pruned;
+  auto prune = [&](const Decomposition* d) -> const Decomposition* {
+    bool ident = false, phase = false;
+    for (const Givens& g : d->rots)
+      if (g.c == 1.0 && g.s == cd(0.0, 0.0)) ident = true;
+    for (double x : d->phase)
+      if (x != 0.0) phase = true;
+    if (!ident) return d;
+    Decomposition q;
+    q.real = d->real;
+    q.phase = d->phase;
+    for (const Givens& g : d->rots)
+      if (!(g.c == 1.0 && g.s == cd(0.0, 0.0))) q.rots.push_back(g);
+    if (q.rots.empty() && !phase) return nullptr;
+    pruned.push_back(std::move(q));
+    return &pruned.back();
+  };
   for (const ProgOp& op : prog.ops) {
     if (op.kind == ProgOp::ROT) {
-      add_givens(op.part[colspin()]);
-      pending_other.push_back(op.part[rowspin()]);
+      const Decomposition* dc = prune(op.part[colspin()]);
+      const Decomposition* dr = prune(op.part[rowspin()]);
+      if (dc) add_givens(dc);
+      if (dr) pending_other.push_back(dr);
       continue;
     }
     if (!pending_other.empty()) switch_layout();

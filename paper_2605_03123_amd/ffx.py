@@ -79,6 +79,11 @@ _lucj_np = _sig("ffx_lucj_n_params", ctypes.c_int, [ctypes.c_int, ctypes.c_int])
 _lucj = _sig("ffx_apply_lucj", ctypes.c_int, [_vp, _vp, ctypes.POINTER(_LUCJ), _vp])
 _ws = _sig("ffx_workspace_bytes", ctypes.c_int64, [_vp, ctypes.c_int])
 _energy = _sig("ffx_df_energy", ctypes.c_int, [_vp, _vp, ctypes.POINTER(_DFHam), _c_double_p, _vp, _vp])
+_hact = _sig("ffx_apply_df_hamiltonian", ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_DFHam), _vp, _vp])
+_exact = _sig("ffx_df_evolve_exact", ctypes.c_int,
+              [_vp, _vp, ctypes.POINTER(_DFHam), ctypes.c_double, ctypes.c_double, _vp,
+               ctypes.POINTER(ctypes.c_int), _vp])
+_dist = _sig("ffx_state_distance", ctypes.c_int, [_vp, _vp, _vp, _c_double_p, _vp])
 _tenable = _sig("ffx_timing_enable", ctypes.c_int, [_vp, ctypes.c_int])
 _tread = _sig("ffx_timing_read", ctypes.c_int,
               [_vp, ctypes.c_int, _c_double_p, ctypes.POINTER(ctypes.c_int64), _c_double_p, _c_double_p])
@@ -320,6 +325,42 @@ def df_energy(vec: torch.Tensor, ham, norb: int, nelec, *, plan=None) -> float:
     _check(_energy(plan.handle, _vp(vec.data_ptr()), ctypes.byref(s), ctypes.byref(e), _vp(ws.data_ptr()),
                    _stream(vec.device)))
     return e.value
+
+
+def apply_df_hamiltonian(vec: torch.Tensor, ham, norb: int, nelec, *, out=None, plan=None) -> torch.Tensor:
+    """H vec for the DF Hamiltonian (Sec. 4.2); out must not be vec."""
+    plan = plan or get_plan(norb, nelec, vec.dtype, vec.device.index or 0)
+    plan.check_vec(vec)
+    if out is None:
+        out = torch.empty_like(vec)
+    plan.check_vec(out)
+    s, keep = _df_struct(ham, norb)
+    ws = plan.workspace(0)
+    _check(_hact(plan.handle, _vp(vec.data_ptr()), _vp(out.data_ptr()), ctypes.byref(s), _vp(ws.data_ptr()),
+                 _stream(vec.device)))
+    return out
+
+
+def evolve_exact(vec: torch.Tensor, ham, time: float, norb: int, nelec, *, tol: float = 1e-12, out=None,
+                 plan=None):
+    """(exp(-i H time) vec, number of Hamiltonian actions) by a Chebyshev expansion (Sec. 6.2)."""
+    plan, out = _prepare(vec, norb, nelec, out, plan)
+    s, keep = _df_struct(ham, norb)
+    ws = plan.workspace(2)
+    k = ctypes.c_int()
+    _check(_exact(plan.handle, _vp(out.data_ptr()), ctypes.byref(s), float(time), float(tol), _vp(ws.data_ptr()),
+                  ctypes.byref(k), _stream(out.device)))
+    return out, k.value
+
+
+def state_distance(x: torch.Tensor, y: torch.Tensor, norb: int, nelec, *, plan=None) -> float:
+    """||x - y||_2 accumulated in FP64 (the Trotter error measure of Sec. 6.2)."""
+    plan = plan or get_plan(norb, nelec, x.dtype, x.device.index or 0)
+    plan.check_vec(x)
+    plan.check_vec(y)
+    d = ctypes.c_double()
+    _check(_dist(plan.handle, _vp(x.data_ptr()), _vp(y.data_ptr()), ctypes.byref(d), _stream(x.device)))
+    return d.value
 
 
 def lucj_energy_grad(params, ham, norb: int, nelec, n_reps: int, *, dtype=torch.complex128, device=0,

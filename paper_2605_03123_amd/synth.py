@@ -198,3 +198,47 @@ def workload_batched(n_inst: int = 256, seed: int = 0, n_reps: int = 2):
 
 def fd_indices(n_params: int, count: int = 20, seed=(0, 1)) -> np.ndarray:
     return np.sort(rng(list(seed)).choice(n_params, count, replace=False))
+
+
+def lattice_edges(nx: int, ny: int, periodic_x: bool = True, periodic_y: bool = False) -> list:
+    """Nearest-neighbour pairs of an nx x ny square lattice, site (x, y) -> x + nx * y.
+
+    A periodic direction adds the wrap-around pair (n - 1, 0); it needs n >= 3,
+    so that no pair is listed twice.
+    """
+    if (periodic_x and nx < 3) or (periodic_y and ny < 3):
+        raise ValueError("a periodic direction needs at least 3 sites")
+    edges = []
+    for y in range(ny):
+        for x in range(nx):
+            p = x + nx * y
+            if x + 1 < nx or periodic_x:
+                edges.append((p, (x + 1) % nx + nx * y))
+            if y + 1 < ny or periodic_y:
+                edges.append((p, x + nx * ((y + 1) % ny)))
+    return edges
+
+
+def hubbard_2d(nx: int, ny: int, t: float = 1.0, U: float = 8.0, periodic_x: bool = True,
+               periodic_y: bool = False) -> DFHamiltonian:
+    """The 2D Hubbard model H = -t sum_<pq>,s (a+_ps a_qs + h.c.) + U sum_p n_pa n_pb
+    (Sec. 6.2) in the double-factorized form the library takes: one term with
+    the identity basis and J = U * I, whose 1/2 sum_p U (n_pa + n_pb)^2 equals
+    U sum_p n_pa n_pb + (U/2) sum_ps n_ps; the one-body matrix carries -U/2 on
+    its diagonal to cancel the second part.  Defaults: the paper's t = 1,
+    U = 8, periodic in x only.
+    """
+    n = nx * ny
+    h = np.zeros((n, n))
+    for p, q in lattice_edges(nx, ny, periodic_x, periodic_y):
+        h[p, q] -= t
+        h[q, p] -= t
+    h -= 0.5 * U * np.eye(n)
+    return DFHamiltonian(h=h, J=(U * np.eye(n))[None], U=np.eye(n, dtype=np.complex128)[None])
+
+
+def hubbard_filling(nx: int, ny: int, fraction: float = 0.125) -> tuple:
+    """(n_alpha, n_beta) for a filling fraction of the 2 nx ny spin orbitals
+    (the paper's 1/8 filling: nx ny / 4 electrons), alpha taking the odd one."""
+    ne = int(round(2 * nx * ny * fraction))
+    return ((ne + 1) // 2, ne // 2)

@@ -295,12 +295,18 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
       const int v = std::atoi(e);
       if (v >= 0 && v <= 1024) lds_group = v / (int)P->elem();
     }
+    // pack runs of configurations that share their orbitals above the segment
+    // window back to back into one segment while they fit (0: one run per
+    // segment; for tests)
+    const char* pack_env = std::getenv("FFX_SEG_PACK");
+    const bool pack_ok = !(pack_env && std::atoi(pack_env) == 0);
     int max_rows_x_seg = 0;
     for (int s = 0; s < 2; ++s) {
       auto& ss = P->seg[s];
       const auto& strs = P->str[s];
       std::vector<std::pair<int, int>> segs;
       std::vector<std::vector<SegWindowTable>> tabs;
+      bool packed = false;
       int wt = norb;
       for (; wt >= 0; --wt) {
         segs.clear();
@@ -314,6 +320,36 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
           i = j;
         }
         if (longest > max_elems) continue;
+        // Runs are contiguous in colex order.  At low filling most runs are
+        // short (a handful of configurations per occupation of the top
+        // orbitals); a block per run would mostly idle through the stages, so
+        // consecutive runs share a block when that saves a quarter of the blocks.
+        packed = false;
+        if (pack_ok) {
+          // room for the member offset tables of every register window (nl1
+          // is at most min(a, electrons) + 1; each table padded to 16 bytes)
+          const int W0 = std::min(P->W, wt), nc = s == 0 ? na : nb;
+          size_t mt_bound = 0;
+          for (int a = 0; W0 >= 2 && a + W0 <= wt; ++a) {
+            const size_t nl1 = (size_t)std::min(a, nc) + 1;
+            mt_bound = (mt_bound + 3) & ~(size_t)3;
+            mt_bound += (((size_t)(W0 + 1) * nl1 + 3) & ~(size_t)3);
+            for (int m = 0; m <= W0; ++m) mt_bound += nl1 * (((size_t)binom(W0, m) + 3) & ~(size_t)3);
+          }
+          const size_t fixed = dev::seg_pass_lds(P->c64, 0, (int)mt_bound);
+          const int64_t cap = fixed < lds_cap ? std::min<int64_t>(max_elems, (int64_t)((lds_cap - fixed) / P->elem())) : 0;
+          std::vector<std::pair<int, int>> groups;
+          for (const auto& r : segs) {
+            if (!groups.empty() && groups.back().second + r.second <= cap)
+              groups.back().second += r.second;
+            else
+              groups.push_back(r);
+          }
+          if (groups.size() * 4 <= segs.size() * 3) {
+            segs = std::move(groups);
+            packed = true;
+          }
+        }
         const int Wseg = std::min(P->W, wt);
         tabs.assign(segs.size(), {});
         size_t need = 0;
@@ -376,8 +412,9 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
       // high part H lacks wt pairs its strings holding wt - 1 (the last C(wt-1,
       // k-1) of its C(wt, k)) with the first C(wt-1, k-1) strings of segment
       // H + {wt}, which lack wt - 1; both ranges run in the colex order of the
-      // remaining k - 1 low orbitals
-      if (wt >= 1 && wt < norb && segs.size() > 1) {
+      // remaining k - 1 low orbitals.  Packed segments leave that rotation to
+      // the window passes.
+      if (wt >= 1 && wt < norb && segs.size() > 1 && !packed) {
         std::map<uint64_t, int> by_high;
         for (size_t g = 0; g < segs.size(); ++g) by_high[strs[segs[g].first] >> wt] = (int)g;
         const int nc = s == 0 ? na : nb;

@@ -262,7 +262,8 @@ WindowTable build_window_table(const std::vector<uint64_t>& strs, int norb, int 
 SegWindowTable build_seg_window(const std::vector<uint64_t>& seg, int wt, int a, int w, int group) {
   SegWindowTable t;
   const uint64_t low_mask = (wt >= 64) ? ~0ull : ((1ull << wt) - 1);
-  const int n_low = seg.empty() ? 0 : __builtin_popcountll(seg[0] & low_mask);
+  int n_low = 0;
+  for (uint64_t x : seg) n_low = std::max(n_low, __builtin_popcountll(x & low_mask));
   t.nl1 = std::min(a, n_low) + 1;
   // mt(m, l, k) = sum_j C(a + pos_j, l + j) over the set bits pos_1 < ... of the k-th m-pattern
   std::vector<std::vector<int>> pats(w + 1);
@@ -290,7 +291,7 @@ SegWindowTable build_seg_window(const std::vector<uint64_t>& seg, int wt, int a,
   struct Cls {
     int m, l, cbase, count;
   };
-  std::map<std::pair<int, uint64_t>, Cls> classes;  // (m, outside bits) -> class
+  std::map<std::pair<int, uint64_t>, Cls> classes;  // (m, bits outside the window) -> class
   for (size_t i = 0; i < seg.size(); ++i) {
     const uint64_t sv = seg[i] & low_mask;
     const int pat = (int)((sv & wmask) >> a);
@@ -298,7 +299,7 @@ SegWindowTable build_seg_window(const std::vector<uint64_t>& seg, int wt, int a,
     const int l = __builtin_popcountll(sv & below);
     const int off = t.mt[t.mt[m * t.nl1 + l] + prank[pat]];
     const int cbase = (int)i - off;
-    auto key = std::make_pair(m, sv & ~wmask);
+    auto key = std::make_pair(m, seg[i] & ~wmask);
     auto it = classes.find(key);
     if (it == classes.end()) {
       classes.emplace(key, Cls{m, l, cbase, 1});

@@ -227,25 +227,31 @@ def test_errors_do_not_crash(ffx):
 @pytest.fixture(scope="module")
 def small_segment_plans(ffx):
     """Plans whose segments are forced to be tiny, so that rotations cross segments
-    and run through whole-spin window passes between segment passes."""
+    and run through whole-spin window passes between segment passes: one
+    segment per run of configurations sharing the orbitals above the window
+    (FFX_SEG_PACK=0; the rotation on the pair straddling the window is applied
+    at load), and runs packed back to back (that rotation takes a window pass)."""
     import os
     plans = {}
-    old = os.environ.get("FFX_SEG_MAX")
+    old = {k: os.environ.get(k) for k in ("FFX_SEG_MAX", "FFX_SEG_PACK")}
     os.environ["FFX_SEG_MAX"] = "24"
     try:
-        for norb, nelec, dt in [(8, (4, 4), torch.complex128), (10, (3, 6), torch.complex128),
-                                (9, (4, 5), torch.complex64), (11, (5, 4), torch.complex128)]:
-            plans[(norb, nelec, dt)] = ffx.Plan(norb, nelec, dt)
+        for pack in ("0", "1"):
+            os.environ["FFX_SEG_PACK"] = pack
+            for norb, nelec, dt in [(8, (4, 4), torch.complex128), (10, (3, 6), torch.complex128),
+                                    (9, (4, 5), torch.complex64), (11, (5, 4), torch.complex128)]:
+                plans[(norb, nelec, dt, pack)] = ffx.Plan(norb, nelec, dt)
     finally:
-        if old is None:
-            del os.environ["FFX_SEG_MAX"]
-        else:
-            os.environ["FFX_SEG_MAX"] = old
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
     return plans
 
 
 def test_segmented_paths(ffx, small_segment_plans):
-    for (norb, nelec, dtype), plan in small_segment_plans.items():
+    for (norb, nelec, dtype, _), plan in small_segment_plans.items():
         r = synth.rng([21, norb])
         da, db = _dims(norb, nelec)
         vec = _to_dev(synth.random_state(r, da, db), dtype)
@@ -269,7 +275,7 @@ def test_segmented_paths_in_place_and_gradients(ffx, small_segment_plans):
     # crossing rotations move the state between the working buffers; in-place
     # calls must still end in the caller's buffer, and the adjoint gradient runs
     # programs that end in accumulation or in a reduction only
-    for (norb, nelec, dtype), plan in small_segment_plans.items():
+    for (norb, nelec, dtype, _), plan in small_segment_plans.items():
         r = synth.rng([22, norb])
         da, db = _dims(norb, nelec)
         vec = _to_dev(synth.random_state(r, da, db), dtype)

@@ -14,6 +14,12 @@ default); the other precision is timed the same way and reported beside it.
 Also reported (unless --no-batched): the batched energies + adjoint gradients
 of 256 small sectors (norb 8-12) in both precisions.
 
+Also reported (unless --no-hubbard): the Trotter-error workload of Sec. 6.2 on
+the 2D Hubbard model (t = 1, U = 8, 4 x 8 lattice periodic in x, 1/8 filling,
+T = 1): one Hamiltonian action, the exact evolution, Trotter runs of orders 1
+and 2 and their errors, and beside it the same measurement on a 4 x 4 lattice
+on the GPU (the cpu_baseline object holds the oracle's time for that one).
+
 Also reported (unless --no-lucj): the LUCJ energy + adjoint gradient at
 norb = 16, n_reps = 3, L = 16 in both precisions, and against it the
 forward-only central finite-difference gradient (h = 1e-5) on 20 parameters
@@ -76,7 +82,7 @@ def committed_traffic(dtype_name: str):
     return float(kv[key])
 
 
-def cpu_baseline(ham, vec: np.ndarray) -> dict:
+def cpu_baseline(ham, vec: np.ndarray, synth=None, hubbard_small=None) -> dict:
     """Time the oracle on a bounded sample of one Trotter step and scale to a whole step.
 
     The oracle applies each orbital rotation as Gamma' = C(U) Gamma C(U)^T with
@@ -110,7 +116,7 @@ def cpu_baseline(ham, vec: np.ndarray) -> dict:
     t_p = time.perf_counter() - t0
     t_rot = d / R_c * t_c + 2 * d / R_g * t_g
     t_step = (2 * L + 1) * t_rot + L * t_p
-    return {
+    out = {
         "value": t_step,
         "unit": "s per DF Trotter step",
         "cores": int(blas_threads),
@@ -119,6 +125,18 @@ def cpu_baseline(ham, vec: np.ndarray) -> dict:
                    f"{R_g}x{d} by {d}x{d} complex product ({t_g:.1f} s), one full diagonal-Coulomb phase "
                    f"({t_p:.1f} s); scaled to {2 * L + 1} rotations + {L} phases per step"),
     }
+    if hubbard_small is not None:
+        # the Trotter-error leg's small lattice, whole, in the oracle
+        from oracle import hamiltonian as oh
+        sx, sy = hubbard_small
+        norb, nelec = sx * sy, synth.hubbard_filling(sx, sy)
+        v = synth.random_state(synth.rng(0), ost.dim(norb, nelec[0]), ost.dim(norb, nelec[1]))
+        t0 = time.perf_counter()
+        err = oh.trotter_error(v, synth.hubbard_2d(sx, sy), 1.0, norb, nelec, 2, 1)
+        out["trotter_error_hubbard_small"] = {"s": round(time.perf_counter() - t0, 3), "error": err,
+                                              "workload": f"hubbard_2d {sx}x{sy} nelec={nelec} T=1.0: exact "
+                                                          "evolution + S_1 with 2 steps + distance"}
+    return out
 
 
 def time_df_step(ffx, torch, ham, vec_np, dtype, steps, warmup):
@@ -249,6 +267,86 @@ def batched_timing(ffx, torch, synth, dtype):
                                                       for x in w))}
 
 
+def hubbard_timing(ffx, torch, synth, nx, ny, time_T=1.0, oracle_side=(4, 4)):
+    """Trotter-error workload (Sec. 6.2): 2D Hubbard model t = 1, U = 8 on an nx x ny lattice periodic in x,
+    1/8 filling, from a random unit state (seed 0), complex128: one Hamiltonian action, the exact evolution
+    exp(-i H T) (Chebyshev expansion, tol 1e-12), Trotter runs of orders 1 and 2 against it, and the live
+    per-launch timing of the kernel families over one Hamiltonian action.  Beside it, the same measurement
+    at the small lattice `oracle_side` on the GPU and in the oracle."""
+    from math import comb
+    dev = torch.device("cuda:0")
+    dtype = torch.complex128
+    norb, nelec = nx * ny, synth.hubbard_filling(nx, ny)
+    ham = synth.hubbard_2d(nx, ny)
+    plan = ffx.get_plan(norb, nelec, dtype, 0)
+    da, db = comb(norb, nelec[0]), comb(norb, nelec[1])
+    g = torch.Generator(device=dev)
+    g.manual_seed(0)
+    vec = torch.randn((da, db), dtype=dtype, device=dev, generator=g)
+    vec /= torch.linalg.vector_norm(vec)
+    out = torch.empty_like(vec)
+    ffx.apply_df_hamiltonian(vec, ham, norb, nelec, out=out, plan=plan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ffx.apply_df_hamiltonian(vec, ham, norb, nelec, out=out, plan=plan)
+    torch.cuda.synchronize()
+    t_h = time.perf_counter() - t0
+    plan.timing(True)
+    ffx.apply_df_hamiltonian(vec, ham, norb, nelec, out=out, plan=plan)
+    torch.cuda.synchronize()
+    fam = {}
+    for kind, kname in ((1, "seg_pass"), (0, "win_pass")):
+        for spin, sname in ((0, "alpha"), (1, "beta")):
+            kms, n, alg, slots = plan.timing_read(kind, spin)
+            if n:
+                fam[f"{kname}_{sname}"] = {"launches": n, "total_ms": round(kms, 3), "avg_ms": round(kms / n, 4),
+                                           "alu_TFLOPs": round(2.0 * slots / (kms * 1e-3) / 1e12, 3),
+                                           "alg_GBps": round(alg / (kms * 1e-3) / 1e9, 1)}
+    plan.timing(False)
+    del out
+    exact = vec.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, k = ffx.evolve_exact(vec, ham, time_T, norb, nelec, out=exact, plan=plan)
+    torch.cuda.synchronize()
+    t_exact = time.perf_counter() - t0
+    runs = []
+    approx = torch.empty_like(vec)
+    for order, n in ((1, 2), (2, 1)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ffx.simulate_trotter_double_factorized(vec, ham, time_T, norb, nelec, n_steps=n, order=order, out=approx,
+                                               plan=plan)
+        torch.cuda.synchronize()
+        t_tr = time.perf_counter() - t0
+        runs.append({"order": order, "n_steps": n, "s": round(t_tr, 4), "s_per_step": round(t_tr / n, 4),
+                     "error": ffx.state_distance(approx, exact, norb, nelec, plan=plan)})
+    res = {"workload": f"hubbard_2d {nx}x{ny} periodic_x t=1 U=8 nelec={nelec} T={time_T} state=c128 {da}x{db}",
+           "state_bytes": plan.state_bytes, "h_action_s": round(t_h, 4),
+           "exact": {"s": round(t_exact, 3), "n_matvec": k, "tol": 1e-12}, "trotter": runs, "families": fam}
+    del vec, exact, approx
+    ffx._plan_cached.cache_clear()
+    del plan
+    torch.cuda.empty_cache()
+    # the same measurement at a size the oracle finishes (the oracle side runs in the cpu_baseline leg)
+    sx, sy = oracle_side
+    norb, nelec = sx * sy, synth.hubbard_filling(sx, sy)
+    ham = synth.hubbard_2d(sx, sy)
+    v = synth.random_state(synth.rng(0), comb(norb, nelec[0]), comb(norb, nelec[1]))
+    vd = torch.from_numpy(v).to(dev)
+    ffx.evolve_exact(vd, ham, time_T, norb, nelec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ex, _ = ffx.evolve_exact(vd, ham, time_T, norb, nelec)
+    ap_ = ffx.simulate_trotter_double_factorized(vd, ham, time_T, norb, nelec, n_steps=2, order=1)
+    err_gpu = ffx.state_distance(ap_, ex, norb, nelec)
+    t_gpu = time.perf_counter() - t0
+    res["small"] = {"workload": f"hubbard_2d {sx}x{sy} nelec={nelec} T={time_T}, state synth.random_state seed 0: "
+                                "exact evolution + S_1 with 2 steps + distance",
+                    "s": round(t_gpu, 4), "error": err_gpu}
+    return res
+
+
 def copy_calibration(torch):
     """Plain device copies of a known size for scaling the HBM byte counters."""
     n = 1 << 27  # 2^27 complex64 = 1 GiB
@@ -271,6 +369,8 @@ def main():
     ap.add_argument("--no-lucj", action="store_true")
     ap.add_argument("--no-other-dtype", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-hubbard", action="store_true")
+    ap.add_argument("--hubbard-y", type=int, default=8, help="lattice 4 x y of the Trotter-error leg")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -327,8 +427,10 @@ def main():
             "c64": batched_timing(ffx, torch, synth, torch.complex64),
             "c128": batched_timing(ffx, torch, synth, torch.complex128),
         }
+    if not args.no_hubbard:
+        out["trotter_error_hubbard"] = hubbard_timing(ffx, torch, synth, 4, args.hubbard_y)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(ham, vec_np)
+        out["cpu_baseline"] = cpu_baseline(ham, vec_np, synth, None if args.no_hubbard else (4, 4))
     print(json.dumps(out), flush=True)
 
 

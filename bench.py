@@ -33,6 +33,8 @@ step.  The roofline's `traffic` is the HBM byte count per launch from the
 committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes, used only while the
 kernel sources still hash to the value recorded with them (else null).
 
+--hubbard-only runs the Trotter-error leg alone (for profiling).
+
 --copy-calibration adds device copies of a known size (for scaling the
 FETCH_SIZE / WRITE_SIZE counters under rocprofv3) and skips the rest.
 """
@@ -371,6 +373,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-hubbard", action="store_true")
     ap.add_argument("--hubbard-y", type=int, default=8, help="lattice 4 x y of the Trotter-error leg")
+    ap.add_argument("--hubbard-only", action="store_true", help="run only the Trotter-error leg (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -383,6 +386,10 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(torch)
+        return
+
+    if args.hubbard_only:
+        print(json.dumps({"trotter_error_hubbard": hubbard_timing(ffx, torch, synth, 4, args.hubbard_y)}), flush=True)
         return
 
     types = {"c128": torch.complex128, "c64": torch.complex64}

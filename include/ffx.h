@@ -103,6 +103,60 @@ int ffx_apply_diag_coulomb_evolution(ffx_plan plan, void* vec, const double* J_a
                                      const double* J_ab, const double* J_bb, double time,
                                      void* stream);
 
+/* The remaining gates of Table 1, applied IN PLACE.  spin: 0 = alpha,
+   1 = beta; orbital indices in [0, norb).  FFX_EINVAL for a non-finite angle,
+   an index out of range or p == q where two orbitals are needed.
+   Number interaction exp(i theta n_{p,spin}) (a number-operator-sum
+   evolution with one nonzero coefficient). */
+int ffx_apply_num_interaction(ffx_plan plan, void* vec, double theta, int p, int spin, void* stream);
+
+/* Number-number interaction exp(i theta n_{p,sigma} n_{q,tau}) (a diagonal
+   Coulomb evolution with one nonzero coupling; p == q with sigma == tau is
+   exp(i theta n_{p,sigma})). */
+int ffx_apply_num_num_interaction(ffx_plan plan, void* vec, double theta, int p, int sigma, int q, int tau,
+                                  void* stream);
+
+/* Givens rotation exp(theta (a^dag_{p,spin} a_{q,spin} - a^dag_{q,spin} a_{p,spin})):
+   the orbital rotation of that spin by the identity with the (p, q) block
+   [[cos theta, sin theta], [-sin theta, cos theta]] (Sec. 2.3); p, q need
+   not be adjacent. */
+int ffx_apply_givens_rotation(ffx_plan plan, void* vec, double theta, int p, int q, int spin, void* stream);
+
+/* Tunneling interaction exp(i theta (a^dag_{p,spin} a_{q,spin} + h.c.)): the
+   orbital rotation of that spin with the (p, q) block
+   [[cos theta, i sin theta], [i sin theta, cos theta]]. */
+int ffx_apply_tunneling_interaction(ffx_plan plan, void* vec, double theta, int p, int q, int spin,
+                                    void* stream);
+
+/* Quadratic Hamiltonian evolution exp(-i t sum_{pq,sigma} M^sigma_pq a^dag_{p sigma} a_{q sigma}):
+   the orbital rotation by U = expm(-i t M) per spin.  M_a, M_b: complex
+   Hermitian norb x norb (interleaved); M_b = NULL means M_a.  FFX_EINVAL for
+   a matrix that is not Hermitian to 1e-12. */
+int ffx_apply_quad_ham_evolution(ffx_plan plan, void* vec, const double* M_a, const double* M_b, double time,
+                                 void* stream);
+
+/* Slater determinant (Sec. 2.4): vec is OVERWRITTEN with script-U(U) |occ>,
+   amplitude det U_a[I_alpha, occ_a] * det U_b[I_beta, occ_beta] with the occupied
+   orbitals in ascending order.  occ_a / occ_b: n_alpha / n_beta distinct
+   orbital indices in any order (NULL: the lowest orbitals, Hartree-Fock);
+   U_a / U_b: complex norb x norb unitaries (NULL: the identity; U_b = NULL
+   with U_a given means U_a). */
+int ffx_slater_determinant(ffx_plan plan, void* vec, const int* occ_a, const int* occ_b, const double* U_a,
+                           const double* U_b, void* stream);
+
+/* Unitary cluster Jastrow ansatz with per-spin rotations and full
+   diagonal-Coulomb matrices (Sec. 4.5.1; the LUCJ entry point below is its
+   restricted, parameterized form): vec is OVERWRITTEN with
+   [script-U(F)] prod_{k = n_reps..1} [script-U(U_k) D_k script-U(U_k)^dag] |HF>,
+   D_k = the diagonal Coulomb evolution at t = 1 with (J_aa[k], J_ab[k], J_bb[k]).
+   U_a, U_b: n_reps complex norb x norb unitaries each (U_b = NULL: U_a);
+   J_aa, J_ab, J_bb: n_reps real norb x norb (J_ab or J_bb = NULL: J_aa);
+   final_a, final_b: the optional final rotation F per spin (NULL: none;
+   final_b = NULL with final_a given means final_a). */
+int ffx_apply_ucj(ffx_plan plan, void* vec, int n_reps, const double* U_a, const double* U_b, const double* J_aa,
+                  const double* J_ab, const double* J_bb, const double* final_a, const double* final_b,
+                  void* stream);
+
 /* Double-factorized Hamiltonian (Eq. double-factorized-hamiltonian):
    H = sum h_pq a^dag_{p s} a_{q s} + 1/2 sum_t sum J^(t)_pq n^(t)_{p s} n^(t)_{q t'}.
    h: real symmetric norb^2; J: n_terms * norb^2 real symmetric;

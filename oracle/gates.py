@@ -217,3 +217,95 @@ def transition_one_body(lam: np.ndarray, vec: np.ndarray, norb: int, nelec) -> n
             Eb = excitation_matrix(norb, nb, p, q)
             T[p, q] = np.sum(lc * (Ea @ vec)) + np.sum(lc * (Eb @ vec.T).T)
     return T
+
+
+# ---------------------------------------------------------------------------
+# The remaining gates of Table 1, the Slater determinant (Sec. 2.4) and the
+# unitary cluster Jastrow forward pass (Sec. 4.5.1)
+# ---------------------------------------------------------------------------
+
+def _spin_occ(norb: int, nelec, spin: int) -> np.ndarray:
+    return st.occupations(norb, nelec[spin])
+
+
+def apply_num_interaction(vec: np.ndarray, theta: float, p: int, spin: int, norb: int, nelec) -> np.ndarray:
+    """exp(i theta n_{p sigma}): each configuration times exp(i theta x_sigma[p])."""
+    x = _spin_occ(norb, nelec, spin)[:, p]
+    f = np.exp(1j * theta * x)
+    return vec * (f[:, None] if spin == 0 else f[None, :])
+
+
+def apply_num_num_interaction(vec: np.ndarray, theta: float, p: int, sigma: int, q: int, tau: int, norb: int,
+                              nelec) -> np.ndarray:
+    """exp(i theta n_{p sigma} n_{q tau}): each configuration times exp(i theta x_sigma[p] x_tau[q])."""
+    xs = [_spin_occ(norb, nelec, 0), _spin_occ(norb, nelec, 1)]
+    def col(spin, r):
+        v = xs[spin][:, r]
+        return v[:, None] if spin == 0 else v[None, :]
+    return vec * np.exp(1j * theta * col(sigma, p) * col(tau, q))
+
+
+def _one_spin(vec, U, spin, norb, nelec):
+    eye = np.eye(norb, dtype=np.complex128)
+    return apply_orbital_rotation(vec, U if spin == 0 else eye, norb, nelec, U_b=U if spin == 1 else eye)
+
+
+def apply_givens_rotation(vec: np.ndarray, theta: float, p: int, q: int, spin: int, norb: int, nelec) -> np.ndarray:
+    """exp(theta (a+_{p s} a_{q s} - a+_{q s} a_{p s})): the orbital rotation of spin s by
+    U = expm(K), K = theta (|p><q| - |q><p|) (the generator's one-body matrix)."""
+    import scipy.linalg
+    K = np.zeros((norb, norb))
+    K[p, q], K[q, p] = theta, -theta
+    return _one_spin(vec, scipy.linalg.expm(K), spin, norb, nelec)
+
+
+def apply_tunneling_interaction(vec: np.ndarray, theta: float, p: int, q: int, spin: int, norb: int,
+                                nelec) -> np.ndarray:
+    """exp(i theta (a+_{p s} a_{q s} + h.c.)): the orbital rotation of spin s by expm(K),
+    K = i theta (|p><q| + |q><p|)."""
+    import scipy.linalg
+    K = np.zeros((norb, norb), dtype=np.complex128)
+    K[p, q] = K[q, p] = 1j * theta
+    return _one_spin(vec, scipy.linalg.expm(K), spin, norb, nelec)
+
+
+def apply_quad_ham_evolution(vec: np.ndarray, M: np.ndarray, time: float, norb: int, nelec,
+                             M_b: np.ndarray | None = None) -> np.ndarray:
+    """exp(-i t sum M^sigma_pq a+_{p sigma} a_{q sigma}) = orbital rotation by expm(-i t M) (Table 1)."""
+    import scipy.linalg
+    Ua = scipy.linalg.expm(-1j * time * np.asarray(M))
+    Ub = Ua if M_b is None else scipy.linalg.expm(-1j * time * np.asarray(M_b))
+    return apply_orbital_rotation(vec, Ua, norb, nelec, U_b=Ub)
+
+
+def slater_determinant(norb: int, nelec, occ_a=None, occ_b=None, U_a=None, U_b=None) -> np.ndarray:
+    """script-U(U) |occ>: the orbital rotation applied to the basis state whose occupied orbitals are
+    occ_a, occ_b (default: the lowest, Hartree-Fock), Sec. 2.4."""
+    na, nb = nelec
+    amap_a, amap_b = st.address_map(norb, na), st.address_map(norb, nb)
+    occ_a = list(range(na)) if occ_a is None else list(occ_a)
+    occ_b = list(range(nb)) if occ_b is None else list(occ_b)
+    vec = np.zeros((st.dim(norb, na), st.dim(norb, nb)), dtype=np.complex128)
+    vec[amap_a[sum(1 << o for o in occ_a)], amap_b[sum(1 << o for o in occ_b)]] = 1.0
+    eye = np.eye(norb, dtype=np.complex128)
+    Ua = eye if U_a is None else np.asarray(U_a)
+    Ub = Ua if U_b is None else np.asarray(U_b)
+    return apply_orbital_rotation(vec, Ua, norb, nelec, U_b=Ub)
+
+
+def apply_ucj(norb: int, nelec, U_a, J_aa, U_b=None, J_ab=None, J_bb=None, final_a=None,
+              final_b=None) -> np.ndarray:
+    """[script-U(F)] prod_{k = R..1} script-U(U_k) D_k script-U(U_k)^dag |HF>, D_k the diagonal Coulomb
+    evolution at t = 1 with (J_aa[k], J_ab[k], J_bb[k]); gates applied one by one (no merging)."""
+    R = len(U_a)
+    U_b = U_a if U_b is None else U_b
+    J_ab = J_aa if J_ab is None else J_ab
+    J_bb = J_aa if J_bb is None else J_bb
+    vec = slater_determinant(norb, nelec)
+    for k in range(R):
+        vec = apply_orbital_rotation(vec, np.asarray(U_a[k]).conj().T, norb, nelec, U_b=np.asarray(U_b[k]).conj().T)
+        vec = apply_diag_coulomb_evolution(vec, J_aa[k], 1.0, norb, nelec, J_ab=J_ab[k], J_bb=J_bb[k])
+        vec = apply_orbital_rotation(vec, U_a[k], norb, nelec, U_b=U_b[k])
+    if final_a is not None:
+        vec = apply_orbital_rotation(vec, final_a, norb, nelec, U_b=final_a if final_b is None else final_b)
+    return vec

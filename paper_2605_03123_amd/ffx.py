@@ -84,6 +84,15 @@ _exact = _sig("ffx_df_evolve_exact", ctypes.c_int,
               [_vp, _vp, ctypes.POINTER(_DFHam), ctypes.c_double, ctypes.c_double, _vp,
                ctypes.POINTER(ctypes.c_int), _vp])
 _dist = _sig("ffx_state_distance", ctypes.c_int, [_vp, _vp, _vp, _c_double_p, _vp])
+_ci = ctypes.c_int
+_numint = _sig("ffx_apply_num_interaction", _ci, [_vp, _vp, ctypes.c_double, _ci, _ci, _vp])
+_numnum = _sig("ffx_apply_num_num_interaction", _ci, [_vp, _vp, ctypes.c_double, _ci, _ci, _ci, _ci, _vp])
+_givensg = _sig("ffx_apply_givens_rotation", _ci, [_vp, _vp, ctypes.c_double, _ci, _ci, _ci, _vp])
+_tunnel = _sig("ffx_apply_tunneling_interaction", _ci, [_vp, _vp, ctypes.c_double, _ci, _ci, _ci, _vp])
+_quad = _sig("ffx_apply_quad_ham_evolution", _ci, [_vp, _vp, _c_double_p, _c_double_p, ctypes.c_double, _vp])
+_slater = _sig("ffx_slater_determinant", _ci, [_vp, _vp, _c_int_p, _c_int_p, _c_double_p, _c_double_p, _vp])
+_ucj = _sig("ffx_apply_ucj", _ci, [_vp, _vp, _ci, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
+                                   _c_double_p, _c_double_p, _c_double_p, _vp])
 _tenable = _sig("ffx_timing_enable", ctypes.c_int, [_vp, ctypes.c_int])
 _tread = _sig("ffx_timing_read", ctypes.c_int,
               [_vp, ctypes.c_int, _c_double_p, ctypes.POINTER(ctypes.c_int64), _c_double_p, _c_double_p])
@@ -291,6 +300,97 @@ def apply_diag_coulomb_evolution(vec: torch.Tensor, J, time: float, norb: int, n
     Jbb = _real(J_bb, (norb, norb)) if J_bb is not None else None
     _check(_dc(plan.handle, _vp(out.data_ptr()), _dptr(Jaa), _dptr(Jab) if Jab is not None else None,
                _dptr(Jbb) if Jbb is not None else None, float(time), _stream(out.device)))
+    return out
+
+
+def apply_num_interaction(vec: torch.Tensor, theta: float, p: int, spin: int, norb: int, nelec, *, out=None,
+                          plan=None) -> torch.Tensor:
+    """exp(i theta n_{p,spin}) (Table 1); spin 0 = alpha, 1 = beta."""
+    plan, out = _prepare(vec, norb, nelec, out, plan)
+    _check(_numint(plan.handle, _vp(out.data_ptr()), float(theta), int(p), int(spin), _stream(out.device)))
+    return out
+
+
+def apply_num_num_interaction(vec: torch.Tensor, theta: float, p: int, sigma: int, q: int, tau: int, norb: int,
+                              nelec, *, out=None, plan=None) -> torch.Tensor:
+    """exp(i theta n_{p,sigma} n_{q,tau}) (Table 1)."""
+    plan, out = _prepare(vec, norb, nelec, out, plan)
+    _check(_numnum(plan.handle, _vp(out.data_ptr()), float(theta), int(p), int(sigma), int(q), int(tau),
+                   _stream(out.device)))
+    return out
+
+
+def apply_givens_rotation(vec: torch.Tensor, theta: float, p: int, q: int, spin: int, norb: int, nelec, *,
+                          out=None, plan=None) -> torch.Tensor:
+    """exp(theta (a+_{p,spin} a_{q,spin} - a+_{q,spin} a_{p,spin})) (Table 1)."""
+    plan, out = _prepare(vec, norb, nelec, out, plan)
+    _check(_givensg(plan.handle, _vp(out.data_ptr()), float(theta), int(p), int(q), int(spin), _stream(out.device)))
+    return out
+
+
+def apply_tunneling_interaction(vec: torch.Tensor, theta: float, p: int, q: int, spin: int, norb: int, nelec, *,
+                                out=None, plan=None) -> torch.Tensor:
+    """exp(i theta (a+_{p,spin} a_{q,spin} + h.c.)) (Table 1)."""
+    plan, out = _prepare(vec, norb, nelec, out, plan)
+    _check(_tunnel(plan.handle, _vp(out.data_ptr()), float(theta), int(p), int(q), int(spin), _stream(out.device)))
+    return out
+
+
+def apply_quad_ham_evolution(vec: torch.Tensor, M, time: float, norb: int, nelec, *, M_b=None, out=None,
+                             plan=None) -> torch.Tensor:
+    """exp(-i t sum M^sigma_pq a+_{p sigma} a_{q sigma}) for Hermitian M (Table 1)."""
+    plan, out = _prepare(vec, norb, nelec, out, plan)
+    Ma = _cplx(M, (norb, norb))
+    Mb = _cplx(M_b, (norb, norb)) if M_b is not None else None
+    _check(_quad(plan.handle, _vp(out.data_ptr()), _dptr(Ma), _dptr(Mb) if Mb is not None else None, float(time),
+                 _stream(out.device)))
+    return out
+
+
+def _occ(o, n):
+    if o is None:
+        return None, None
+    a = np.ascontiguousarray(np.asarray(o, dtype=np.int32))
+    if a.shape != (n,):
+        raise ValueError(f"expected {n} occupied orbitals, got shape {a.shape}")
+    return a.ctypes.data_as(_c_int_p), a
+
+
+def slater_determinant(norb: int, nelec, *, occ_a=None, occ_b=None, U=None, U_b=None, dtype=torch.complex128,
+                       device=0, out=None, plan=None) -> torch.Tensor:
+    """script-U(U)|occ> (Sec. 2.4); occ default: the lowest orbitals; U default: the identity."""
+    plan = plan or get_plan(norb, nelec, dtype, device)
+    if out is None:
+        out = torch.empty((plan.dim_a, plan.dim_b), dtype=dtype, device=f"cuda:{device}")
+    plan.check_vec(out)
+    pa, ka = _occ(occ_a, int(nelec[0]))
+    pb, kb = _occ(occ_b, int(nelec[1]))
+    Ua = _cplx(U, (norb, norb)) if U is not None else None
+    Ub = _cplx(U_b, (norb, norb)) if U_b is not None else None
+    _check(_slater(plan.handle, _vp(out.data_ptr()), pa, pb, _dptr(Ua) if Ua is not None else None,
+                   _dptr(Ub) if Ub is not None else None, _stream(out.device)))
+    return out
+
+
+def apply_ucj(norb: int, nelec, U, J, *, U_b=None, J_ab=None, J_bb=None, final=None, final_b=None,
+              dtype=torch.complex128, device=0, out=None, plan=None) -> torch.Tensor:
+    """[script-U(F)] prod_k script-U(U_k) D_k script-U(U_k)^dag |HF> with per-spin U and full J (Sec. 4.5.1).
+    U, U_b: (n_reps, norb, norb) unitaries; J, J_ab, J_bb: (n_reps, norb, norb) real."""
+    plan = plan or get_plan(norb, nelec, dtype, device)
+    if out is None:
+        out = torch.empty((plan.dim_a, plan.dim_b), dtype=dtype, device=f"cuda:{device}")
+    plan.check_vec(out)
+    R = int(np.asarray(U).shape[0])
+    Ua = _cplx(U, (R, norb, norb))
+    Ub = _cplx(U_b, (R, norb, norb)) if U_b is not None else None
+    Ja = _real(J, (R, norb, norb))
+    Jab = _real(J_ab, (R, norb, norb)) if J_ab is not None else None
+    Jbb = _real(J_bb, (R, norb, norb)) if J_bb is not None else None
+    Fa = _cplx(final, (norb, norb)) if final is not None else None
+    Fb = _cplx(final_b, (norb, norb)) if final_b is not None else None
+    opt = lambda a: _dptr(a) if a is not None else None
+    _check(_ucj(plan.handle, _vp(out.data_ptr()), R, _dptr(Ua), opt(Ub), _dptr(Ja), opt(Jab), opt(Jbb), opt(Fa),
+                opt(Fb), _stream(out.device)))
     return out
 
 

@@ -20,6 +20,10 @@ T = 1): one Hamiltonian action, the exact evolution, Trotter runs of orders 1
 and 2 and their errors, and beside it the same measurement on a 4 x 4 lattice
 on the GPU (the cpu_baseline object holds the oracle's time for that one).
 
+Also reported (unless --no-table1): the time per call of the other Table 1
+gates, the Slater-determinant state and a 3-repetition UCJ forward pass at
+norb = 16, (8, 8), complex128.
+
 Also reported (unless --no-lucj): the LUCJ energy + adjoint gradient at
 norb = 16, n_reps = 3, L = 16 in both precisions, and against it the
 forward-only central finite-difference gradient (h = 1e-5) on 20 parameters
@@ -349,6 +353,44 @@ def hubbard_timing(ffx, torch, synth, nx, ny, time_T=1.0, oracle_side=(4, 4)):
     return res
 
 
+def table1_timing(ffx, torch, synth):
+    """Time per call of the Table 1 gates, the Slater-determinant state and a UCJ forward pass (n_reps = 3,
+    per-spin rotations, full J) at norb = 16, (8, 8), complex128, state resident on the device."""
+    dev = torch.device("cuda:0")
+    r = synth.rng(7)
+    vec = torch.from_numpy(synth.random_state(r, 12870, 12870)).to(dev)
+    plan = ffx.get_plan(NORB, NELEC, torch.complex128, 0)
+    M = synth.random_hermitian(r, NORB, 0.5)
+    R = 3
+    U = np.array([synth.random_unitary(r, NORB) for _ in range(R)])
+    Ub = np.array([synth.random_unitary(r, NORB) for _ in range(R)])
+    J = np.array([synth.random_symmetric(r, NORB, 0.3) for _ in range(R)])
+    calls = {
+        "num_interaction": lambda: ffx.apply_num_interaction(vec, 0.3, 5, 0, NORB, NELEC, out=vec, plan=plan),
+        "num_num_interaction": lambda: ffx.apply_num_num_interaction(vec, 0.3, 5, 0, 9, 1, NORB, NELEC, out=vec,
+                                                                     plan=plan),
+        "givens_rotation_adjacent": lambda: ffx.apply_givens_rotation(vec, 0.3, 7, 8, 1, NORB, NELEC, out=vec,
+                                                                      plan=plan),
+        "givens_rotation_0_15": lambda: ffx.apply_givens_rotation(vec, 0.3, 0, 15, 0, NORB, NELEC, out=vec, plan=plan),
+        "tunneling_interaction": lambda: ffx.apply_tunneling_interaction(vec, 0.3, 3, 4, 0, NORB, NELEC, out=vec,
+                                                                         plan=plan),
+        "quad_ham_evolution": lambda: ffx.apply_quad_ham_evolution(vec, M, 0.1, NORB, NELEC, out=vec, plan=plan),
+        "slater_determinant": lambda: ffx.slater_determinant(NORB, NELEC, U=U[0], U_b=Ub[0], out=vec, plan=plan),
+        "ucj_n_reps_3": lambda: ffx.apply_ucj(NORB, NELEC, U, J, U_b=Ub, J_ab=J, J_bb=J, out=vec, plan=plan),
+    }
+    out = {}
+    for name, f in calls.items():
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            f()
+        torch.cuda.synchronize()
+        out[name + "_ms"] = round((time.perf_counter() - t0) / 3 * 1e3, 3)
+    del vec
+    return out
+
+
 def copy_calibration(torch):
     """Plain device copies of a known size for scaling the HBM byte counters."""
     n = 1 << 27  # 2^27 complex64 = 1 GiB
@@ -372,6 +414,7 @@ def main():
     ap.add_argument("--no-other-dtype", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-hubbard", action="store_true")
+    ap.add_argument("--no-table1", action="store_true")
     ap.add_argument("--hubbard-y", type=int, default=8, help="lattice 4 x y of the Trotter-error leg")
     ap.add_argument("--hubbard-only", action="store_true", help="run only the Trotter-error leg (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -434,6 +477,8 @@ def main():
             "c64": batched_timing(ffx, torch, synth, torch.complex64),
             "c128": batched_timing(ffx, torch, synth, torch.complex128),
         }
+    if not args.no_table1:
+        out["table1_gates_n16_c128"] = table1_timing(ffx, torch, synth)
     if not args.no_hubbard:
         out["trotter_error_hubbard"] = hubbard_timing(ffx, torch, synth, 4, args.hubbard_y)
     if not args.no_cpu_baseline:

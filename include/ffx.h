@@ -157,6 +157,33 @@ int ffx_apply_ucj(ffx_plan plan, void* vec, int n_reps, const double* U_a, const
                   const double* J_ab, const double* J_bb, const double* final_a, const double* final_b,
                   void* stream);
 
+/* Sampling of configurations from the state (Sec. 6.1, sample-based
+   algorithms): for each uniform u[k] in [0, 1) (host, n_samples of them),
+   out[k] (host int64) is the address i_a * dim_b + i_b of the first
+   configuration, in address order, whose cumulative probability
+   sum |gamma|^2 exceeds u[k] times the total (accumulated in FP64 in a fixed
+   order; zero-probability configurations are never returned).  vec is read
+   only and need not be normalised.  Synchronizes.  FFX_EINVAL for a uniform
+   outside [0, 1) or a state with no finite nonzero norm. */
+int ffx_sample_state(ffx_plan plan, const void* vec, const double* u, int64_t n_samples, int64_t* out,
+                     void* stream);
+
+/* Sampling of configurations from the Slater determinant script-U(U)|occ>
+   (Sec. 4.5.4) without forming the state: per spin an independent draw from
+   p(I) = |det U[I, occ]|^2, one orbital at a time from its conditional
+   distribution given the orbitals drawn so far (the projection
+   determinantal point process with kernel U[:, occ] U[:, occ]^dag;
+   O(n^2 norb) per sample).  Step k of sample s uses u_sigma[s * n_sigma + k]
+   (host, uniforms in [0, 1)): the first orbital, in orbital order, whose
+   cumulative conditional weight exceeds u times the total.  occ_a / occ_b:
+   occupied orbitals (NULL: the lowest); U_a / U_b: complex norb x norb
+   unitaries (NULL: the identity; U_b = NULL with U_a given means U_a).
+   masks_a / masks_b (host, n_samples each): the sampled configurations as
+   bit masks.  Synchronizes. */
+int ffx_sample_slater(ffx_plan plan, const int* occ_a, const int* occ_b, const double* U_a, const double* U_b,
+                      const double* u_a, const double* u_b, int64_t n_samples, uint64_t* masks_a,
+                      uint64_t* masks_b, void* stream);
+
 /* Double-factorized Hamiltonian (Eq. double-factorized-hamiltonian):
    H = sum h_pq a^dag_{p s} a_{q s} + 1/2 sum_t sum J^(t)_pq n^(t)_{p s} n^(t)_{q t'}.
    h: real symmetric norb^2; J: n_terms * norb^2 real symmetric;

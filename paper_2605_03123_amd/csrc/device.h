@@ -89,6 +89,16 @@ void zscale(bool c64, void* v, int64_t n, double cr, double ci, hipStream_t stre
 // out[0] = sum |x - y|^2 in FP64, fixed order; partials of size inner_partials(n)
 void dist2(bool c64, const void* x, const void* y, int64_t n, double* partials, double* out,
            hipStream_t stream);
+// State sampling: bs and pre hold sample_blocks(n) doubles each (block sums of
+// |gamma|^2 and their inclusive prefix); out[k] = the sampled address for u[k].
+int sample_blocks(int64_t n);
+int sample_state(bool c64, const void* vec, int64_t n, double* bs, double* pre, const double* u, int64_t n_samples,
+                 int64_t* out, hipStream_t stream);
+// Slater-determinant sampling of one spin: Q (N x eta complex, row-major), u
+// (n_samples x eta uniforms), masks[k] = the sampled configuration; N, eta <= 32.
+void dpp_sample(const double* Q, int N, int eta, const double* u, int64_t n_samples, uint64_t* masks,
+                hipStream_t stream);
+
 // y += x
 void axpy(bool c64, const void* x, void* y, int64_t n, hipStream_t stream);
 // vec[i_a, i_b] = a[i_a] * b[i_b] (a, b complex double)

@@ -1,0 +1,259 @@
+// Sampling of configurations (Sec. 4.5.4 and 6.1):
+//   * from a state vector, by the inverse of its cumulative distribution
+//     |gamma|^2 in address order (FP64, fixed summation order);
+//   * from a Slater determinant without forming the state: per spin, the
+//     projection determinantal point process with kernel K = Q Q^dag
+//     (Q = the occupied columns of the orbital rotation), drawn one orbital
+//     at a time from its conditional distribution (O(eta^2 N) per sample).
+// Uniform random numbers come in from the caller.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dev_common.h"
+#include "device.h"
+
+namespace ffx {
+namespace dev {
+
+constexpr int64_t kNone = 0x7fffffffffffffffLL;
+constexpr int kSampleChunk = 16;                  // consecutive amplitudes per thread
+constexpr int kSampleBlock = 256 * kSampleChunk;  // amplitudes per block
+
+int sample_blocks(int64_t n) { return (int)((n + kSampleBlock - 1) / kSampleBlock); }
+
+// bs[b] = sum |gamma|^2 over block b: thread t sums its 16 consecutive amplitudes
+// in address order, then the fixed tree of block_sum256
+template <class R>
+__global__ __launch_bounds__(256) void k_block_norm2(const typename V2T<R>::type* __restrict__ v, int64_t n,
+                                                     double* __restrict__ bs) {
+  __shared__ double sh[4];
+  const int64_t base = (int64_t)blockIdx.x * kSampleBlock + (int64_t)threadIdx.x * kSampleChunk;
+  double acc = 0;
+  for (int k = 0; k < kSampleChunk; ++k) {
+    const int64_t i = base + k;
+    if (i < n) {
+      const double re = v[i].x, im = v[i].y;
+      acc += re * re + im * im;
+    }
+  }
+  const double t = block_sum256(acc, sh);
+  if (threadIdx.x == 0) bs[blockIdx.x] = t;
+}
+
+// inclusive prefix of bs[0..nb) into pre, one block of 1024 threads: each
+// thread scans a contiguous chunk, thread 0 scans the chunk totals in order
+__global__ __launch_bounds__(1024) void k_scan_blocks(const double* __restrict__ bs, int nb,
+                                                      double* __restrict__ pre) {
+  __shared__ double tot[1024];
+  const int c = (nb + 1023) / 1024;
+  const int lo = threadIdx.x * c, hi = min(nb, lo + c);
+  double run = 0;
+  for (int i = lo; i < hi; ++i) {
+    run += bs[i];
+    pre[i] = run;
+  }
+  tot[threadIdx.x] = run;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double acc = 0;
+    for (int t = 0; t < 1024; ++t) {
+      const double x = tot[t];
+      tot[t] = acc;
+      acc += x;
+    }
+  }
+  __syncthreads();
+  const double off = tot[threadIdx.x];
+  for (int i = lo; i < hi; ++i) pre[i] += off;
+}
+
+// One block per sample: the first address whose cumulative probability exceeds
+// u * total (zero-probability addresses are never chosen; when rounding leaves
+// the target at or past the block's own total, the block's last address with
+// nonzero probability).
+template <class R>
+__global__ __launch_bounds__(256) void k_sample_search(const typename V2T<R>::type* __restrict__ v, int64_t n,
+                                                       const double* __restrict__ pre, int nb,
+                                                       const double* __restrict__ u, int64_t n_samples,
+                                                       int64_t* __restrict__ out) {
+  __shared__ double part[256];
+  __shared__ int64_t sel[2];
+  __shared__ int blk;
+  const int64_t s = blockIdx.x;
+  if (s >= n_samples) return;
+  const double total = pre[nb - 1];
+  const double target = u[s] * total;
+  if (threadIdx.x == 0) {
+    int lo = 0, hi = nb - 1;  // first b with pre[b] > target, else nb - 1
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (pre[mid] > target)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    blk = lo;
+    sel[0] = kNone;  // first qualifying address
+    sel[1] = -1;         // last address with nonzero probability
+  }
+  __syncthreads();
+  const int b = blk;
+  const double t2 = target - (b > 0 ? pre[b - 1] : 0.0);
+  const int64_t base = (int64_t)b * kSampleBlock + (int64_t)threadIdx.x * kSampleChunk;
+  double w[kSampleChunk];
+  double acc = 0;
+  for (int k = 0; k < kSampleChunk; ++k) {
+    const int64_t i = base + k;
+    double p = 0;
+    if (i < n) {
+      const double re = v[i].x, im = v[i].y;
+      p = re * re + im * im;
+    }
+    w[k] = p;
+    acc += p;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double run = 0;
+    for (int t = 0; t < 256; ++t) {
+      const double x = part[t];
+      part[t] = run;
+      run += x;
+    }
+  }
+  __syncthreads();
+  double cum = part[threadIdx.x];
+  int64_t first = kNone, last = -1;
+  for (int k = 0; k < kSampleChunk; ++k) {
+    if (w[k] > 0) {
+      cum += w[k];
+      last = base + k;
+      if (first == kNone && cum > t2) first = base + k;
+    }
+  }
+  if (first != kNone) atomicMin((unsigned long long*)&sel[0], (unsigned long long)first);
+  if (last >= 0) atomicMax((long long*)&sel[1], (long long)last);
+  __syncthreads();
+  if (threadIdx.x == 0) out[s] = sel[0] != kNone ? sel[0] : sel[1];
+}
+
+int sample_state(bool c64, const void* vec, int64_t n, double* bs, double* pre, const double* u, int64_t n_samples,
+                 int64_t* out, hipStream_t s) {
+  const int nb = sample_blocks(n);
+  if (c64) {
+    hipLaunchKernelGGL(k_block_norm2<float>, dim3(nb), dim3(256), 0, s, (const zc64*)vec, n, bs);
+  } else {
+    hipLaunchKernelGGL(k_block_norm2<double>, dim3(nb), dim3(256), 0, s, (const zc128*)vec, n, bs);
+  }
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, bs, nb, pre);
+  if (n_samples <= 0) return nb;
+  const dim3 g((unsigned)n_samples);
+  if (c64)
+    hipLaunchKernelGGL(k_sample_search<float>, g, dim3(256), 0, s, (const zc64*)vec, n, pre, nb, u, n_samples, out);
+  else
+    hipLaunchKernelGGL(k_sample_search<double>, g, dim3(256), 0, s, (const zc128*)vec, n, pre, nb, u, n_samples,
+                       out);
+  return nb;
+}
+
+// ---------------------------------------------------------------------------
+// Slater determinant: one wavefront per sample and spin.  Lane j < N holds the
+// residual weight r_j = |q_j|^2 - sum_i |<e_i, q_j>|^2 of row j of Q (N x eta,
+// complex, in LDS) against the orthonormal basis e_0.. of the rows chosen so
+// far (kept in LDS per wave).  Step k: lane 0 picks the first j whose
+// cumulative r (in orbital order) exceeds u_k * sum r; the new basis vector is
+// the chosen row minus its projections, normalised; every lane then removes
+// its overlap with it.
+// ---------------------------------------------------------------------------
+constexpr int kDppWaves = 2;
+
+__global__ __launch_bounds__(64 * kDppWaves) void k_dpp_sample(const double* __restrict__ Q, int N, int eta,
+                                                                 const double* __restrict__ u, int64_t n_samples,
+                                                                 uint64_t* __restrict__ masks) {
+  __shared__ double q[32 * 32 * 2];
+  __shared__ double e[kDppWaves][32 * 32 * 2];
+  __shared__ double coef[kDppWaves][32 * 32 * 2];  // <e_i, q_j> at [j][i]
+  __shared__ double rr[kDppWaves][32];
+  __shared__ int pick[kDppWaves];
+  for (int i = threadIdx.x; i < N * eta * 2; i += blockDim.x) q[i] = Q[i];
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t smp = (int64_t)blockIdx.x * kDppWaves + wv;
+  if (smp >= n_samples) return;  // whole waves leave together; no block barrier follows
+  double r = 0;
+  if (lane < N)
+    for (int c = 0; c < eta; ++c) {
+      const double a = q[(lane * eta + c) * 2], bi = q[(lane * eta + c) * 2 + 1];
+      r += a * a + bi * bi;
+    }
+  uint64_t mask = 0;
+  for (int k = 0; k < eta; ++k) {
+    if (lane < N) rr[wv][lane] = ((mask >> lane) & 1) ? 0.0 : (r > 0 ? r : 0.0);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    if (lane == 0) {
+      double tot = 0;
+      for (int j = 0; j < N; ++j) tot += rr[wv][j];
+      const double target = u[smp * eta + k] * tot;
+      double cum = 0;
+      int first = -1, last = -1;
+      for (int j = 0; j < N; ++j) {
+        const double x = rr[wv][j];
+        if (x > 0) {
+          cum += x;
+          last = j;
+          if (first < 0 && cum > target) first = j;
+        }
+      }
+      pick[wv] = first >= 0 ? first : last;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    const int js = pick[wv];
+    if (js < 0) break;  // no weight left (cannot happen for orthonormal columns)
+    mask |= 1ull << js;
+    // e_k = (q_js - sum_{i<k} <e_i, q_js> e_i) / |...|, component c on lane c
+    const double rjs = rr[wv][js];
+    const double inv = 1.0 / sqrt(rjs);
+    if (lane < eta) {
+      double vr = q[(js * eta + lane) * 2], vi = q[(js * eta + lane) * 2 + 1];
+      for (int i = 0; i < k; ++i) {
+        const double cr = coef[wv][(js * 32 + i) * 2], ci = coef[wv][(js * 32 + i) * 2 + 1];
+        const double er = e[wv][(i * 32 + lane) * 2], ei = e[wv][(i * 32 + lane) * 2 + 1];
+        vr -= cr * er - ci * ei;
+        vi -= cr * ei + ci * er;
+      }
+      e[wv][(k * 32 + lane) * 2] = vr * inv;
+      e[wv][(k * 32 + lane) * 2 + 1] = vi * inv;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    if (lane < N) {
+      double cr = 0, ci = 0;  // <e_k, q_lane> = sum conj(e) q
+      for (int c = 0; c < eta; ++c) {
+        const double er = e[wv][(k * 32 + c) * 2], ei = e[wv][(k * 32 + c) * 2 + 1];
+        const double a = q[(lane * eta + c) * 2], bi = q[(lane * eta + c) * 2 + 1];
+        cr += er * a + ei * bi;
+        ci += er * bi - ei * a;
+      }
+      coef[wv][(lane * 32 + k) * 2] = cr;
+      coef[wv][(lane * 32 + k) * 2 + 1] = ci;
+      r -= cr * cr + ci * ci;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  }
+  if (lane == 0) masks[smp] = mask;
+}
+
+void dpp_sample(const double* Q, int N, int eta, const double* u, int64_t n_samples, uint64_t* masks,
+                hipStream_t s) {
+  if (n_samples <= 0) return;
+  const dim3 g((unsigned)((n_samples + kDppWaves - 1) / kDppWaves));
+  hipLaunchKernelGGL(k_dpp_sample, g, dim3(64 * kDppWaves), 0, s, Q, N, eta, u, n_samples, masks);
+}
+
+}  // namespace dev
+}  // namespace ffx

@@ -93,6 +93,9 @@ _quad = _sig("ffx_apply_quad_ham_evolution", _ci, [_vp, _vp, _c_double_p, _c_dou
 _slater = _sig("ffx_slater_determinant", _ci, [_vp, _vp, _c_int_p, _c_int_p, _c_double_p, _c_double_p, _vp])
 _ucj = _sig("ffx_apply_ucj", _ci, [_vp, _vp, _ci, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
                                    _c_double_p, _c_double_p, _c_double_p, _vp])
+_sstate = _sig("ffx_sample_state", _ci, [_vp, _vp, _c_double_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _vp])
+_sslater = _sig("ffx_sample_slater", _ci, [_vp, _c_int_p, _c_int_p, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
+                                           ctypes.c_int64, _c_u64_p, _c_u64_p, _vp])
 _tenable = _sig("ffx_timing_enable", ctypes.c_int, [_vp, ctypes.c_int])
 _tread = _sig("ffx_timing_read", ctypes.c_int,
               [_vp, ctypes.c_int, _c_double_p, ctypes.POINTER(ctypes.c_int64), _c_double_p, _c_double_p])
@@ -392,6 +395,40 @@ def apply_ucj(norb: int, nelec, U, J, *, U_b=None, J_ab=None, J_bb=None, final=N
     _check(_ucj(plan.handle, _vp(out.data_ptr()), R, _dptr(Ua), opt(Ub), _dptr(Ja), opt(Jab), opt(Jbb), opt(Fa),
                 opt(Fb), _stream(out.device)))
     return out
+
+
+def sample_state(vec: torch.Tensor, u, norb: int, nelec, *, plan=None) -> np.ndarray:
+    """Addresses i_a * dim_b + i_b sampled from |vec|^2 by the uniforms u in [0, 1) (Sec. 6.1)."""
+    plan = plan or get_plan(norb, nelec, vec.dtype, vec.device.index or 0)
+    plan.check_vec(vec)
+    uu = _real(u).reshape(-1)
+    out = np.zeros(uu.size, dtype=np.int64)
+    _check(_sstate(plan.handle, _vp(vec.data_ptr()), _dptr(uu), uu.size,
+                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _stream(vec.device)))
+    return out
+
+
+def sample_slater(norb: int, nelec, u_a, u_b, *, U=None, U_b=None, occ_a=None, occ_b=None,
+                  dtype=torch.complex128, device=0, plan=None):
+    """(masks_a, masks_b) sampled from the Slater determinant script-U(U)|occ> (Sec. 4.5.4); u_a: (n_samples,
+    n_alpha) and u_b: (n_samples, n_beta) uniforms in [0, 1)."""
+    plan = plan or get_plan(norb, nelec, dtype, device)
+    na, nb = int(nelec[0]), int(nelec[1])
+    ua = _real(u_a).reshape(-1)
+    ub = _real(u_b).reshape(-1)
+    n = ua.size // na if na else ub.size // max(nb, 1)
+    if ua.size != n * na or ub.size != n * nb:
+        raise ValueError("u_a and u_b must hold n_samples x n_alpha and n_samples x n_beta uniforms")
+    pa, ka = _occ(occ_a, na)
+    pb, kb = _occ(occ_b, nb)
+    Ua = _cplx(U, (norb, norb)) if U is not None else None
+    Ub = _cplx(U_b, (norb, norb)) if U_b is not None else None
+    ma = np.zeros(n, dtype=np.uint64)
+    mb = np.zeros(n, dtype=np.uint64)
+    _check(_sslater(plan.handle, pa, pb, _dptr(Ua) if Ua is not None else None, _dptr(Ub) if Ub is not None else None,
+                    _dptr(ua), _dptr(ub), n, ma.ctypes.data_as(_c_u64_p), mb.ctypes.data_as(_c_u64_p),
+                    _stream(torch.device(f"cuda:{plan.device}"))))
+    return ma, mb
 
 
 def simulate_trotter_double_factorized(vec: torch.Tensor, ham, time: float, norb: int, nelec, *,

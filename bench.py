@@ -21,8 +21,9 @@ and 2 and their errors, and beside it the same measurement on a 4 x 4 lattice
 on the GPU (the cpu_baseline object holds the oracle's time for that one).
 
 Also reported (unless --no-table1): the time per call of the other Table 1
-gates, the Slater-determinant state and a 3-repetition UCJ forward pass at
-norb = 16, (8, 8), complex128.
+gates, the Slater-determinant state, a 3-repetition UCJ forward pass and the
+sampling of 1e5 configurations from the state and from a Slater determinant
+(host uniforms in, host results out) at norb = 16, (8, 8), complex128.
 
 Also reported (unless --no-lucj): the LUCJ energy + adjoint gradient at
 norb = 16, n_reps = 3, L = 16 in both precisions, and against it the
@@ -378,6 +379,10 @@ def table1_timing(ffx, torch, synth):
         "slater_determinant": lambda: ffx.slater_determinant(NORB, NELEC, U=U[0], U_b=Ub[0], out=vec, plan=plan),
         "ucj_n_reps_3": lambda: ffx.apply_ucj(NORB, NELEC, U, J, U_b=Ub, J_ab=J, J_bb=J, out=vec, plan=plan),
     }
+    ua = r.random(100000)
+    us = (r.random((100000, 8)), r.random((100000, 8)))
+    calls["sample_state_1e5"] = lambda: ffx.sample_state(vec, ua, NORB, NELEC, plan=plan)
+    calls["sample_slater_1e5"] = lambda: ffx.sample_slater(NORB, NELEC, us[0], us[1], U=U[0], U_b=Ub[0], plan=plan)
     out = {}
     for name, f in calls.items():
         f()

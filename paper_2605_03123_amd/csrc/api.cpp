@@ -688,24 +688,88 @@ int ffx_df_energy(ffx_plan plan, const void* vec, const ffx_df_ham* ham, double*
 
 namespace {
 
-// out = H in: term 0 stores, the others add; tmp holds each rotated copy.
-void apply_terms(ffx_plan_s& P, const std::vector<Compiled>& cs, const void* in, void* out, void* tmp,
-                 hipStream_t s) {
-  for (size_t t = 0; t < cs.size(); ++t) {
-    if (t == 0)
-      execute_program(P, cs[0], in, out, nullptr, s);
-    else
-      execute_program(P, cs[t], in, tmp, out, s);
+// H psi for a DF Hamiltonian.  The one-body term goes either through the
+// eigenbasis of h (two orbital rotations around a diagonal scale, a gate
+// program like the two-body terms) or directly, as sum_pq h_pq E_pq applied by
+// rows of each spin from a sparse table (the beta spin on the transposed
+// state).  Direct is taken when the tables are short (sparse h or few
+// electrons): at most 48 entries per configuration over both spins.
+struct HamAction {
+  std::vector<Compiled> cs;  // gate programs: the two-body terms, after the one-body term when it is one
+  bool direct = false;
+  struct Tab {
+    int64_t* off = nullptr;
+    int32_t* src = nullptr;
+    double* coef = nullptr;
+  } tab[2];
+  std::vector<void*> bufs;
+  HamAction() = default;
+  HamAction(const HamAction&) = delete;
+  HamAction& operator=(const HamAction&) = delete;
+  ~HamAction() {
+    for (void* b : bufs) (void)hipFree(b);  // hipFree waits for the device
+  }
+  void* alloc(size_t bytes) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(bytes, 8)) != hipSuccess) throw Error(FFX_ENOMEM, "device allocation failed");
+    bufs.push_back(p);
+    return p;
+  }
+};
+
+void build_ham_action(ffx_plan_s& P, const DFHost& df, const double* h, DecompPool& pool, hipStream_t s,
+                      HamAction& A) {
+  const int N = P.norb;
+  std::vector<double> hv(h, h + (size_t)N * N);
+  OneBodyTable t[2];
+  bool direct = false;
+  const char* mode = std::getenv("FFX_ONEBODY");  // "direct" / "rot": force a path (tests)
+  if (mode && std::string(mode) == "rot") {
+    direct = false;
+  } else {
+    for (int sp = 0; sp < 2; ++sp) t[sp] = build_one_body_table(N, P.str[sp], hv);
+    const double per = (double)t[0].src.size() / (double)P.dim[0] + (double)t[1].src.size() / (double)P.dim[1];
+    direct = (mode && std::string(mode) == "direct") || per <= 48.0;
+  }
+  A.direct = direct;
+  std::vector<Program> terms = df_term_programs(df, pool, N);
+  Upload up(&P, s);
+  for (int term = direct ? 1 : 0; term <= df.L; ++term)
+    A.cs.push_back(compile_program(P, up, terms[term], term == 0 ? FINAL_STORE : FINAL_ACCUM, s));
+  up.commit();
+  if (!direct) return;
+  for (int sp = 0; sp < 2; ++sp) {
+    HamAction::Tab& d = A.tab[sp];
+    d.off = (int64_t*)A.alloc(t[sp].off.size() * 8);
+    d.src = (int32_t*)A.alloc(t[sp].src.size() * 4);
+    d.coef = (double*)A.alloc(t[sp].coef.size() * 8);
+    HIPCHK(hipMemcpy(d.off, t[sp].off.data(), t[sp].off.size() * 8, hipMemcpyHostToDevice));
+    if (!t[sp].src.empty()) {
+      HIPCHK(hipMemcpy(d.src, t[sp].src.data(), t[sp].src.size() * 4, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(d.coef, t[sp].coef.data(), t[sp].coef.size() * 8, hipMemcpyHostToDevice));
+    }
   }
 }
 
-std::vector<Compiled> compile_terms(ffx_plan_s& P, const DFHost& df, DecompPool& pool, hipStream_t s) {
-  std::vector<Program> terms = df_term_programs(df, pool, P.norb);
-  Upload up(&P, s);
-  std::vector<Compiled> cs;
-  for (int t = 0; t <= df.L; ++t) cs.push_back(compile_program(P, up, terms[t], t == 0 ? FINAL_STORE : FINAL_ACCUM, s));
-  up.commit();
-  return cs;
+// out = H in; tmp is a state-sized work buffer.  in, out and tmp are distinct.
+void apply_ham(ffx_plan_s& P, const HamAction& A, const void* in, void* out, void* tmp, hipStream_t s) {
+  const int64_t da = P.dim[0], db = P.dim[1];
+  size_t k = 0;
+  if (A.direct) {
+    // beta: on the transposed state, rows = beta configurations
+    dev::transpose(P.c64, in, tmp, da, db, s);
+    check_launch();
+    dev::onebody_rows(P.c64, tmp, out, nullptr, db, da, A.tab[1].off, A.tab[1].src, A.tab[1].coef, s);
+    check_launch();
+    dev::transpose(P.c64, out, tmp, db, da, s);
+    check_launch();
+    // alpha, plus the beta part
+    dev::onebody_rows(P.c64, in, out, tmp, da, db, A.tab[0].off, A.tab[0].src, A.tab[0].coef, s);
+    check_launch();
+  } else {
+    execute_program(P, A.cs[k++], in, out, nullptr, s);
+  }
+  for (; k < A.cs.size(); ++k) execute_program(P, A.cs[k], in, tmp, out, s);
 }
 
 }  // namespace
@@ -722,8 +786,9 @@ int ffx_apply_df_hamiltonian(ffx_plan plan, const void* vec, void* out, const ff
     DeviceGuard dg(P.device);
     hipStream_t s = as_stream(stream);
     DecompPool pool;
-    std::vector<Compiled> cs = compile_terms(P, df, pool, s);
-    apply_terms(P, cs, vec, out, workspace, s);
+    HamAction A;
+    build_ham_action(P, df, ham->h, pool, s, A);
+    apply_ham(P, A, vec, out, workspace, s);
   });
 }
 
@@ -766,7 +831,8 @@ int ffx_df_evolve_exact(ffx_plan plan, void* vec, const ffx_df_ham* ham, double 
     DeviceGuard dg(P.device);
     hipStream_t s = as_stream(stream);
     DecompPool pool;
-    std::vector<Compiled> cs = compile_terms(P, df, pool, s);
+    HamAction A;
+    build_ham_action(P, df, ham->h, pool, s, A);
     const size_t S = P.state_bytes();
     const size_t Sa = (S + 255) / 256 * 256;
     char* ws = (char*)workspace;
@@ -782,7 +848,7 @@ int ffx_df_evolve_exact(ffx_plan plan, void* vec, const ffx_df_ham* ham, double 
     for (int k = 1; k <= K; ++k) {
       // k = 1: T_1 = (H - c) T_0 / r into tcur; k >= 2: T_k = 2 (H - c) T_{k-1} / r - T_{k-2}
       const void* src = k == 1 ? tprev : tcur;
-      apply_terms(P, cs, src, y, tmp, s);
+      apply_ham(P, A, src, y, tmp, s);
       const cd ck = coef(k);
       if (k == 1) {
         dev::cheb_step(P.c64, y, tprev, tcur, vec, n, 1.0 / r, -c / r, 0.0, ck.real(), ck.imag(), s);

@@ -465,6 +465,44 @@ std::vector<cd> dagger(int n, const std::vector<cd>& A) {
   return B;
 }
 
+OneBodyTable build_one_body_table(int norb, const std::vector<uint64_t>& strs, const std::vector<double>& h) {
+  OneBodyTable t;
+  std::unordered_map<uint64_t, int32_t> addr;
+  addr.reserve(strs.size() * 2);
+  for (size_t i = 0; i < strs.size(); ++i) addr[strs[i]] = (int32_t)i;
+  t.off.reserve(strs.size() + 1);
+  t.off.push_back(0);
+  for (size_t j = 0; j < strs.size(); ++j) {
+    const uint64_t J = strs[j];
+    double diag = 0.0;
+    for (int p = 0; p < norb; ++p)
+      if ((J >> p) & 1) diag += h[(size_t)p * norb + p];
+    if (diag != 0.0) {
+      t.src.push_back((int32_t)j);
+      t.coef.push_back(diag);
+    }
+    // J = I - q + p with p in J, q not in J: I = J - p + q
+    for (int p = 0; p < norb; ++p) {
+      if (!((J >> p) & 1)) continue;
+      for (int q = 0; q < norb; ++q) {
+        if (q == p || ((J >> q) & 1)) continue;
+        const double hv = h[(size_t)p * norb + q];
+        if (hv == 0.0) continue;
+        const uint64_t I = (J & ~(1ull << p)) | (1ull << q);
+        const int lo = std::min(p, q), hi = std::max(p, q);
+        const uint64_t between = ((1ull << hi) - 1) & ~((1ull << (lo + 1)) - 1);
+        const double sign = (__builtin_popcountll(I & between) & 1) ? -1.0 : 1.0;
+        auto it = addr.find(I);
+        if (it == addr.end()) throw Error(FFX_EDEVICE, "one-body table: configuration not in the sector");
+        t.src.push_back(it->second);
+        t.coef.push_back(sign * hv);
+      }
+    }
+    t.off.push_back((int64_t)t.src.size());
+  }
+  return t;
+}
+
 std::vector<double> bessel_j_series(double z, int kmax) {
   if (!(z >= 0.0) || kmax < 0) throw Error(FFX_EINVAL, "bessel_j_series: bad argument");
   std::vector<double> J((size_t)kmax + 1, 0.0);

@@ -585,6 +585,69 @@ void dist2(bool c64, const void* x, const void* y, int64_t n, double* partials, 
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, partials, nb, 1, out);
 }
 
+// One-body operator of the row spin applied by rows:
+//   dst[j, :] = sum_{e in [off[j], off[j+1])} coef[e] * src[srow[e], :]  (+ add[j, :])
+// One block per (row j, tile of 2048 columns); the entries of row j are the
+// same for the whole block.  FP64 accumulation, one rounding to the state type.
+constexpr int kOneBodyPer = 8;
+template <class R>
+__global__ __launch_bounds__(256) void k_onebody_rows(const typename V2T<R>::type* __restrict__ src,
+                                                      typename V2T<R>::type* dst,
+                                                      const typename V2T<R>::type* add, int64_t rows,
+                                                      int64_t cols, int64_t tiles, const int64_t* __restrict__ off,
+                                                      const int32_t* __restrict__ srow,
+                                                      const double* __restrict__ coef) {
+  const int64_t j = (int64_t)blockIdx.x / tiles;
+  const int64_t c0 = ((int64_t)blockIdx.x % tiles) * (256 * kOneBodyPer) + threadIdx.x;
+  if (j >= rows) return;
+  double ar[kOneBodyPer], ai[kOneBodyPer];
+#pragma unroll
+  for (int k = 0; k < kOneBodyPer; ++k) ar[k] = ai[k] = 0.0;
+  const int64_t e1 = off[j + 1];
+  for (int64_t e = off[j]; e < e1; ++e) {
+    const typename V2T<R>::type* sp = src + (int64_t)srow[e] * cols;
+    const double c = coef[e];
+#pragma unroll
+    for (int k = 0; k < kOneBodyPer; ++k) {
+      const int64_t col = c0 + 256 * k;
+      if (col < cols) {
+        const auto v = sp[col];
+        ar[k] += c * (double)v.x;
+        ai[k] += c * (double)v.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kOneBodyPer; ++k) {
+    const int64_t col = c0 + 256 * k;
+    if (col < cols) {
+      double xr = ar[k], xi = ai[k];
+      if (add) {
+        const auto a = add[j * cols + col];
+        xr += (double)a.x;
+        xi += (double)a.y;
+      }
+      typename V2T<R>::type o;
+      o.x = (R)xr;
+      o.y = (R)xi;
+      dst[j * cols + col] = o;
+    }
+  }
+}
+
+void onebody_rows(bool c64, const void* src, void* dst, const void* add, int64_t rows, int64_t cols,
+                  const int64_t* off, const int32_t* srow, const double* coef, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  const int64_t tiles = (cols + 256 * kOneBodyPer - 1) / (256 * kOneBodyPer);
+  const dim3 g((unsigned)(rows * tiles));
+  if (c64)
+    hipLaunchKernelGGL(k_onebody_rows<float>, g, dim3(256), 0, s, (const zc64*)src, (zc64*)dst, (const zc64*)add,
+                       rows, cols, tiles, off, srow, coef);
+  else
+    hipLaunchKernelGGL(k_onebody_rows<double>, g, dim3(256), 0, s, (const zc128*)src, (zc128*)dst,
+                       (const zc128*)add, rows, cols, tiles, off, srow, coef);
+}
+
 template <class R>
 __global__ void k_outer(const zc128* __restrict__ a, const zc128* __restrict__ b,
                         typename V2T<R>::type* __restrict__ vec, int64_t da, int64_t db) {

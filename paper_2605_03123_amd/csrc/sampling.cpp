@@ -38,7 +38,7 @@ int ffx_sample_state(ffx_plan plan, const void* vec, const double* u, int64_t n_
                      void* stream) {
   return guard([&] {
     if (!plan || !vec || (n_samples > 0 && (!u || !out))) throw Error(FFX_EINVAL, "null pointer");
-    if (n_samples < 0 || n_samples > (int64_t)1 << 31) throw Error(FFX_EINVAL, "n_samples out of range");
+    if (n_samples < 0 || n_samples >= ((int64_t)1 << 31)) throw Error(FFX_EINVAL, "n_samples out of range");
     check_uniforms(u, n_samples);
     ffx_plan_s& P = *plan;
     DeviceGuard dg(P.device);
@@ -69,7 +69,7 @@ int ffx_sample_slater(ffx_plan plan, const int* occ_a, const int* occ_b, const d
                       uint64_t* masks_b, void* stream) {
   return guard([&] {
     if (!plan) throw Error(FFX_EINVAL, "null plan");
-    if (n_samples < 0 || n_samples > (int64_t)1 << 31) throw Error(FFX_EINVAL, "n_samples out of range");
+    if (n_samples < 0 || n_samples >= ((int64_t)1 << 31)) throw Error(FFX_EINVAL, "n_samples out of range");
     ffx_plan_s& P = *plan;
     const int N = P.norb;
     if ((U_a && !all_finite(U_a, (size_t)2 * N * N)) || (U_b && !all_finite(U_b, (size_t)2 * N * N)))

@@ -56,10 +56,14 @@ H_CASES = [(6, (3, 2), 2), (8, (4, 4), 3), (9, (5, 3), 1), (5, (0, 2), 2), (5, (
            (20, (3, 2), 1), (24, (2, 1), 2), (32, (2, 2), 1), (32, (1, 1), 0)]
 
 
+@pytest.mark.parametrize("mode", ["auto", "rot", "direct"])
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("norb,nelec,L", H_CASES)
-def test_df_hamiltonian_action(ffx, dtype, norb, nelec, L):
-    print(f"H action norb={norb} nelec={nelec} L={L} {dtype}", flush=True)
+def test_df_hamiltonian_action(ffx, monkeypatch, mode, dtype, norb, nelec, L):
+    """The one-body term through its eigenbasis (rot) or from the sparse excitation tables (direct)."""
+    print(f"H action norb={norb} nelec={nelec} L={L} {dtype} {mode}", flush=True)
+    if mode != "auto":
+        monkeypatch.setenv("FFX_ONEBODY", mode)
     r = synth.rng([41, norb, nelec[0], nelec[1], L])
     ham = synth.df_hamiltonian(r, norb, L, h_scale=1.0, j_scale=0.5)
     vec = _to_dev(synth.random_state(r, *_dims(norb, nelec)), dtype)
@@ -70,10 +74,13 @@ def test_df_hamiltonian_action(ffx, dtype, norb, nelec, L):
     assert _maxdiff(vec, x) == 0.0  # input untouched
 
 
+@pytest.mark.parametrize("mode", ["auto", "rot"])
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("nx,ny", [(4, 2), (4, 3), (4, 4), (4, 5)])
-def test_hubbard_action(ffx, dtype, nx, ny):
-    print(f"Hubbard action {nx}x{ny} {dtype}", flush=True)
+def test_hubbard_action(ffx, monkeypatch, mode, dtype, nx, ny):
+    print(f"Hubbard action {nx}x{ny} {dtype} {mode}", flush=True)
+    if mode != "auto":
+        monkeypatch.setenv("FFX_ONEBODY", mode)
     norb, nelec = nx * ny, synth.hubbard_filling(nx, ny)
     ham = synth.hubbard_2d(nx, ny)
     vec = _to_dev(synth.random_state(synth.rng([42, nx, ny]), *_dims(norb, nelec)), dtype)
@@ -83,11 +90,14 @@ def test_hubbard_action(ffx, dtype, nx, ny):
     assert _maxdiff(out, ref) <= HTOL[dtype] * max(1.0, float(np.abs(ref).max()))
 
 
+@pytest.mark.parametrize("mode", ["auto", "rot"])
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("case", ["hubbard_4x2", "hubbard_4x3", "df_8", "df_7_negative_time", "zero_time",
                                   "empty_sector"])
-def test_evolve_exact(ffx, dtype, case):
-    print(f"exact evolution {case} {dtype}", flush=True)
+def test_evolve_exact(ffx, monkeypatch, mode, dtype, case):
+    print(f"exact evolution {case} {dtype} {mode}", flush=True)
+    if mode != "auto":
+        monkeypatch.setenv("FFX_ONEBODY", mode)
     if case.startswith("hubbard"):
         nx, ny = (4, 2) if case == "hubbard_4x2" else (4, 3)
         norb, nelec, ham, time = nx * ny, synth.hubbard_filling(nx, ny), synth.hubbard_2d(nx, ny), 1.0

@@ -278,7 +278,7 @@ def hubbard_timing(ffx, torch, synth, nx, ny, time_T=1.0, oracle_side=(4, 4)):
     """Trotter-error workload (Sec. 6.2): 2D Hubbard model t = 1, U = 8 on an nx x ny lattice periodic in x,
     1/8 filling, from a random unit state (seed 0), complex128: one Hamiltonian action, the exact evolution
     exp(-i H T) (Chebyshev expansion, tol 1e-12), Trotter runs of orders 1 and 2 against it, and the live
-    per-launch timing of the kernel families over one Hamiltonian action.  Beside it, the same measurement
+    per-launch timing of the kernel families over one S_1 step.  Beside it, the same measurement
     at the small lattice `oracle_side` on the GPU and in the oracle."""
     from math import comb
     dev = torch.device("cuda:0")
@@ -299,7 +299,8 @@ def hubbard_timing(ffx, torch, synth, nx, ny, time_T=1.0, oracle_side=(4, 4)):
     torch.cuda.synchronize()
     t_h = time.perf_counter() - t0
     plan.timing(True)
-    ffx.apply_df_hamiltonian(vec, ham, norb, nelec, out=out, plan=plan)
+    out.copy_(vec)
+    ffx.simulate_trotter_double_factorized(vec, ham, time_T, norb, nelec, n_steps=1, order=1, out=out, plan=plan)
     torch.cuda.synchronize()
     fam = {}
     for kind, kname in ((1, "seg_pass"), (0, "win_pass")):

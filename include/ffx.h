@@ -239,7 +239,13 @@ int ffx_df_energy(ffx_plan plan, const void* vec, const ffx_df_ham* ham, double*
    D_t = 1/2 sum_pq J_t[p][q] N_p N_q (N_p = n_{p alpha} + n_{p beta}).  vec
    (read only), out and workspace (ffx_workspace_bytes(plan, 0) bytes) are
    distinct device buffers; FFX_EINVAL when two of them are the same pointer.
-   Enqueues only. */
+   The one-body term is applied either through the eigenbasis of h (two
+   orbital rotations) or, when its excitation tables are short (sparse h or few
+   electrons: at most 48 entries per configuration over both spins), directly
+   as sum_pq h_pq E_pq from those tables; the environment variable
+   FFX_ONEBODY=rot|direct forces one route.  The direct route allocates its
+   tables for the call and waits for the device before returning; otherwise
+   the call only enqueues. */
 int ffx_apply_df_hamiltonian(ffx_plan plan, const void* vec, void* out, const ffx_df_ham* ham, void* workspace,
                              void* stream);
 

@@ -91,17 +91,20 @@ int ffx_apply_orbital_rotation(ffx_plan plan, void* vec, const double* U_a, cons
                                void* stream);
 
 /* Number-operator-sum evolution exp(-i t sum_{p,sigma} lam^sigma_p n_{p sigma})
-   (Table 1, Sec. 3.2.1).  lam_a, lam_b: norb real; lam_b = NULL means lam_a. */
+   (Table 1, Sec. 3.2.1).  lam_a, lam_b: norb real; lam_b = NULL means lam_a.
+   basis_U (complex norb x norb, NULL = none): the number operators of the
+   rotated orbitals instead, script-U(B) [evolution] script-U(B)^dag. */
 int ffx_apply_num_op_sum_evolution(ffx_plan plan, void* vec, const double* lam_a,
-                                   const double* lam_b, double time, void* stream);
+                                   const double* lam_b, double time, const double* basis_U, void* stream);
 
 /* Diagonal Coulomb evolution
    exp(-(1/2) i t sum_{pq, sigma tau} J^{sigma tau}_pq n_{p sigma} n_{q tau})
-   (Table 1, Sec. 3.2.2).  J_aa, J_ab, J_bb: real symmetric norb x norb;
-   J^{ba} = (J^{ab})^T; J_ab or J_bb = NULL means J_aa. */
+   (Table 1, Sec. 3.2.2).  J_aa, J_bb: real symmetric norb x norb; J_ab: real
+   norb x norb, J^{ba} = (J^{ab})^T; J_ab or J_bb = NULL means J_aa.  basis_U as for the
+   number-operator-sum evolution (the rotated basis of Sec. 4.5.3's terms). */
 int ffx_apply_diag_coulomb_evolution(ffx_plan plan, void* vec, const double* J_aa,
                                      const double* J_ab, const double* J_bb, double time,
-                                     void* stream);
+                                     const double* basis_U, void* stream);
 
 /* The remaining gates of Table 1, applied IN PLACE.  spin: 0 = alpha,
    1 = beta; orbital indices in [0, norb).  FFX_EINVAL for a non-finite angle,

@@ -309,3 +309,10 @@ def apply_ucj(norb: int, nelec, U_a, J_aa, U_b=None, J_ab=None, J_bb=None, final
     if final_a is not None:
         vec = apply_orbital_rotation(vec, final_a, norb, nelec, U_b=final_a if final_b is None else final_b)
     return vec
+
+
+def apply_in_basis(vec: np.ndarray, B: np.ndarray, gate, norb: int, nelec) -> np.ndarray:
+    """script-U(B) gate(script-U(B)^dag vec): a diagonal gate in the basis of the rotated orbitals."""
+    B = np.asarray(B, dtype=np.complex128)
+    phi = apply_orbital_rotation(vec, B.conj().T, norb, nelec)
+    return apply_orbital_rotation(gate(phi), B, norb, nelec)

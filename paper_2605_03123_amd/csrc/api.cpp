@@ -511,21 +511,46 @@ int ffx_apply_orbital_rotation(ffx_plan plan, void* vec, const double* U_a, cons
   });
 }
 
+namespace {
+// script-U(B) [gate] script-U(B)^dag when a basis rotation B is given
+struct BasisWrap {
+  DecompPool pool;
+  const Decomposition* to = nullptr;
+  const Decomposition* from = nullptr;
+  BasisWrap(int N, const double* B) {
+    if (!B) return;
+    if (!all_finite(B, (size_t)2 * N * N)) throw Error(FFX_EINVAL, "non-finite basis rotation");
+    std::vector<cd> U = load_complex(N, B);
+    from = pool.add(N, U);
+    to = pool.add(N, dagger(N, U));
+  }
+  void before(Program& pr) const {
+    if (to) pr.rot(to, to);
+  }
+  void after(Program& pr) const {
+    if (from) pr.rot(from, from);
+  }
+};
+}  // namespace
+
 int ffx_apply_num_op_sum_evolution(ffx_plan plan, void* vec, const double* lam_a, const double* lam_b,
-                                   double time, void* stream) {
+                                   double time, const double* basis_U, void* stream) {
   return guard([&] {
     validate_plan(plan);
     if (!vec || !lam_a) throw Error(FFX_EINVAL, "null vec or lam_a");
     const int N = plan->norb;
     if (!std::isfinite(time) || !all_finite(lam_a, N) || (lam_b && !all_finite(lam_b, N)))
       throw Error(FFX_EINVAL, "non-finite parameter");
+    BasisWrap bw(N, basis_U);
     DeviceGuard dg(plan->device);
     hipStream_t s = as_stream(stream);
     Program pr;
     DiagSpec d;
     d.lin_a = lam_a;
     d.lin_b = lam_b ? lam_b : lam_a;
+    bw.before(pr);
     pr.phase(pr.add_diag(d), -time);
+    bw.after(pr);
     Upload up(plan, s);
     Compiled c = compile_program(*plan, up, pr, FINAL_STORE, s);
     up.commit();
@@ -534,7 +559,7 @@ int ffx_apply_num_op_sum_evolution(ffx_plan plan, void* vec, const double* lam_a
 }
 
 int ffx_apply_diag_coulomb_evolution(ffx_plan plan, void* vec, const double* J_aa, const double* J_ab,
-                                     const double* J_bb, double time, void* stream) {
+                                     const double* J_bb, double time, const double* basis_U, void* stream) {
   return guard([&] {
     validate_plan(plan);
     if (!vec || !J_aa) throw Error(FFX_EINVAL, "null vec or J_aa");
@@ -544,6 +569,7 @@ int ffx_apply_diag_coulomb_evolution(ffx_plan plan, void* vec, const double* J_a
     if (!std::isfinite(time) || !all_finite(J_aa, (size_t)N * N) || !all_finite(Jab, (size_t)N * N) ||
         !all_finite(Jbb, (size_t)N * N))
       throw Error(FFX_EINVAL, "non-finite parameter");
+    BasisWrap bw(N, basis_U);
     DeviceGuard dg(plan->device);
     hipStream_t s = as_stream(stream);
     Program pr;
@@ -551,7 +577,9 @@ int ffx_apply_diag_coulomb_evolution(ffx_plan plan, void* vec, const double* J_a
     d.Qa = J_aa;
     d.Qb = Jbb;
     d.C = Jab;
+    bw.before(pr);
     pr.phase(pr.add_diag(d), -time);
+    bw.after(pr);
     Upload up(plan, s);
     Compiled c = compile_program(*plan, up, pr, FINAL_STORE, s);
     up.commit();

@@ -70,9 +70,9 @@ _plan_info = _sig("ffx_plan_info", ctypes.c_int,
 _plan_strings = _sig("ffx_plan_strings", ctypes.c_int, [_vp, ctypes.c_int, _c_u64_p])
 _rot = _sig("ffx_apply_orbital_rotation", ctypes.c_int, [_vp, _vp, _c_double_p, _c_double_p, _vp])
 _numop = _sig("ffx_apply_num_op_sum_evolution", ctypes.c_int,
-              [_vp, _vp, _c_double_p, _c_double_p, ctypes.c_double, _vp])
+              [_vp, _vp, _c_double_p, _c_double_p, ctypes.c_double, _c_double_p, _vp])
 _dc = _sig("ffx_apply_diag_coulomb_evolution", ctypes.c_int,
-           [_vp, _vp, _c_double_p, _c_double_p, _c_double_p, ctypes.c_double, _vp])
+           [_vp, _vp, _c_double_p, _c_double_p, _c_double_p, ctypes.c_double, _c_double_p, _vp])
 _trotter = _sig("ffx_apply_df_trotter_step", ctypes.c_int,
                 [_vp, _vp, ctypes.POINTER(_DFHam), ctypes.c_double, ctypes.c_int, ctypes.c_int, _vp])
 _lucj_np = _sig("ffx_lucj_n_params", ctypes.c_int, [ctypes.c_int, ctypes.c_int])
@@ -286,23 +286,28 @@ def apply_orbital_rotation(vec: torch.Tensor, U, norb: int, nelec, *, U_b=None, 
 
 
 def apply_num_op_sum_evolution(vec: torch.Tensor, lam, time: float, norb: int, nelec, *, lam_b=None,
-                               out=None, plan=None) -> torch.Tensor:
+                               orbital_rotation=None, out=None, plan=None) -> torch.Tensor:
+    """exp(-i t sum lam_p n_p) (Table 1); with orbital_rotation B, in the rotated basis."""
     plan, out = _prepare(vec, norb, nelec, out, plan)
     la = _real(lam, (norb,))
     lb = _real(lam_b, (norb,)) if lam_b is not None else None
+    B = _cplx(orbital_rotation, (norb, norb)) if orbital_rotation is not None else None
     _check(_numop(plan.handle, _vp(out.data_ptr()), _dptr(la), _dptr(lb) if lb is not None else None,
-                  float(time), _stream(out.device)))
+                  float(time), _dptr(B) if B is not None else None, _stream(out.device)))
     return out
 
 
 def apply_diag_coulomb_evolution(vec: torch.Tensor, J, time: float, norb: int, nelec, *, J_ab=None, J_bb=None,
-                                 out=None, plan=None) -> torch.Tensor:
+                                 orbital_rotation=None, out=None, plan=None) -> torch.Tensor:
+    """exp(-1/2 i t sum J n n) (Table 1); with orbital_rotation B, in the rotated basis."""
     plan, out = _prepare(vec, norb, nelec, out, plan)
     Jaa = _real(J, (norb, norb))
     Jab = _real(J_ab, (norb, norb)) if J_ab is not None else None
     Jbb = _real(J_bb, (norb, norb)) if J_bb is not None else None
+    B = _cplx(orbital_rotation, (norb, norb)) if orbital_rotation is not None else None
     _check(_dc(plan.handle, _vp(out.data_ptr()), _dptr(Jaa), _dptr(Jab) if Jab is not None else None,
-               _dptr(Jbb) if Jbb is not None else None, float(time), _stream(out.device)))
+               _dptr(Jbb) if Jbb is not None else None, float(time), _dptr(B) if B is not None else None,
+               _stream(out.device)))
     return out
 
 

@@ -122,3 +122,22 @@ def test_table1_argument_errors(ffx):
                 lambda: ffx.slater_determinant(norb, nelec, occ_a=[0, 5])):
         with pytest.raises(ffx.FFXError):
             bad()
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("norb,nelec", [(6, (3, 2)), (10, (5, 5)), (20, (3, 2))])
+def test_diagonal_gates_in_a_rotated_basis(ffx, dtype, norb, nelec):
+    r = synth.rng([65, norb, *nelec])
+    vec = _to_dev(synth.random_state(r, *_dims(norb, nelec)), dtype)
+    x = _host(vec)
+    B = synth.random_unitary(r, norb)
+    lam, lam_b = r.normal(0, 1, norb), r.normal(0, 1, norb)
+    out = ffx.apply_num_op_sum_evolution(vec, lam, 0.4, norb, nelec, lam_b=lam_b, orbital_rotation=B)
+    ref = og.apply_in_basis(x, B, lambda v: og.apply_num_op_sum_evolution(v, lam, 0.4, norb, nelec, lam_b=lam_b),
+                            norb, nelec)
+    assert _maxdiff(out, ref) <= TOL[dtype]
+    J, Jab = synth.random_symmetric(r, norb, 0.5), synth.random_symmetric(r, norb, 0.5)
+    out = ffx.apply_diag_coulomb_evolution(vec, J, 0.4, norb, nelec, J_ab=Jab, orbital_rotation=B)
+    ref = og.apply_in_basis(x, B, lambda v: og.apply_diag_coulomb_evolution(v, J, 0.4, norb, nelec, J_ab=Jab),
+                            norb, nelec)
+    assert _maxdiff(out, ref) <= TOL[dtype]

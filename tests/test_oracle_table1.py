@@ -120,3 +120,22 @@ def test_ucj_special_cases():
     ref = F.restrict(rot @ D @ rot.conj().T, nelec) @ hf.reshape(-1)
     out = g.apply_ucj(norb, nelec, [U1a], [Jaa], U_b=[U1b], J_ab=[Jab], J_bb=[Jbb])
     np.testing.assert_allclose(out.reshape(-1), ref, atol=1e-12)
+
+
+@pytest.mark.parametrize("norb,nelec", [(3, (1, 2)), (4, (2, 2))])
+def test_diagonal_gates_in_a_rotated_basis(norb, nelec):
+    """exp(-i t sum lam_p n~_p) and exp(-1/2 i t sum J n~ n~) with n~_p = script-U(B) n_p script-U(B)^dag."""
+    F = Fock(norb)
+    r = synth.rng([56, norb, *nelec])
+    vec = synth.random_state(r, *_dims(norb, nelec))
+    B = synth.random_unitary(r, norb)
+    lam = r.normal(0, 1, norb)
+    nt = [[F.rotated_number(B, p, s) for p in range(norb)] for s in (0, 1)]
+    gen = sum(lam[p] * (nt[0][p] + nt[1][p]) for p in range(norb))
+    out = g.apply_in_basis(vec, B, lambda v: g.apply_num_op_sum_evolution(v, lam, 0.6, norb, nelec), norb, nelec)
+    np.testing.assert_allclose(out.reshape(-1), _apply(F, -0.6j * gen, nelec, vec), atol=1e-12)
+    J = synth.random_symmetric(r, norb, 0.5)
+    gen = sum(0.5 * J[p, q] * nt[s][p] @ nt[t][q] for p in range(norb) for q in range(norb)
+              for s in (0, 1) for t in (0, 1))
+    out = g.apply_in_basis(vec, B, lambda v: g.apply_diag_coulomb_evolution(v, J, 0.6, norb, nelec), norb, nelec)
+    np.testing.assert_allclose(out.reshape(-1), _apply(F, -0.6j * gen, nelec, vec), atol=1e-12)

@@ -25,7 +25,8 @@ gates, the Slater-determinant state, a 3-repetition UCJ forward pass and the
 sampling of 1e5 configurations from the state and from a Slater determinant
 (host uniforms in, host results out) at norb = 16, (8, 8), complex128.
 
-Also reported (unless --no-lucj): the LUCJ energy + adjoint gradient at
+Also reported (unless --no-lucj): the energy after one DF step under a second
+DF Hamiltonian and its adjoint gradient in (h, J_t, U_t), and the LUCJ energy + adjoint gradient at
 norb = 16, n_reps = 3, L = 16 in both precisions, and against it the
 forward-only central finite-difference gradient (h = 1e-5) on 20 parameters
 in complex128: its time, the extrapolated time for all parameters, and the
@@ -256,6 +257,22 @@ def lucj_timing(ffx, torch, synth, dtype, with_fd):
     return out
 
 
+def chain_timing(ffx, torch, synth, ham, vec_np, dtype):
+    """Energy after one S_0 step of the metric's DF Hamiltonian (norb = 16, L = 16, dt = 0.1) under a second
+    DF Hamiltonian as the observable (seed 1), and its adjoint gradient with respect to h, every J_t and every
+    U_t generator: one call, after one warm-up call."""
+    obs = synth.df_hamiltonian(synth.rng(1), NORB, L)
+    vec = torch.from_numpy(vec_np).to(dtype).to("cuda:0")
+    ffx.df_chain_energy_grad(vec, ham, obs, DT, 1, NORB, NELEC)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e, g = ffx.df_chain_energy_grad(vec, ham, obs, DT, 1, NORB, NELEC)
+    t = time.perf_counter() - t0
+    n_params = int(g["h"].size + g["J"].size + g["U"].size)
+    del vec
+    return {"energy": e, "s": round(t, 4), "n_params": n_params}
+
+
 def batched_timing(ffx, torch, synth, dtype):
     """Config-4 workload: 256 sectors (norb in {8, 10, 12}, n in {norb/2 - 1, norb/2}), each with its
     own LUCJ (n_reps = 2) and DF Hamiltonian (L = norb): energies and adjoint gradients of all of them."""
@@ -475,6 +492,13 @@ def main():
             "workload": f"lucj norb=16 nelec=(8,8) n_reps={LUCJ_REPS} L={L} params~N(0,0.1)",
             "c128": lucj_timing(ffx, torch, synth, torch.complex128, True),
             "c64": lucj_timing(ffx, torch, synth, torch.complex64, False),
+        }
+    if not args.no_lucj:
+        out["df_chain_energy_grad"] = {
+            "workload": "E = Re<psi_1|H_obs|psi_1>, psi_1 = S_0(0.1) psi_0 (metric's DF Hamiltonian and state), "
+                        "H_obs = DF L=16 seed 1; adjoint gradient in h, J_t, U_t",
+            "c128": chain_timing(ffx, torch, synth, ham, vec_np, torch.complex128),
+            "c64": chain_timing(ffx, torch, synth, ham, vec_np, torch.complex64),
         }
     if not args.no_batched:
         out["batched_lucj_energy_grad"] = {

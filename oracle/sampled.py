@@ -59,3 +59,42 @@ def rotated_amplitudes_blocked(vec: np.ndarray, U_a: np.ndarray, norb: int, nele
         for pos, i in rows:
             out[pos] = compound_row(U_a, na, i) @ v
     return out
+
+
+def one_body_row(h: np.ndarray, norb: int, n: int, mask: int, amap: dict) -> list:
+    """Row `mask` of sum_pq h_pq a^dag_p a_q on n-electron strings: the pairs (address of J, coefficient)
+    with coefficient = h_pq <mask| a^dag_p a_q |J>, J = mask with p emptied and q filled (J = mask for p = q)."""
+    out = []
+    for p in range(norb):
+        if not (mask >> p) & 1:
+            continue
+        for q in range(norb):
+            if q != p and (mask >> q) & 1:
+                continue
+            hv = h[p, q]
+            if hv == 0:
+                continue
+            J = (mask & ~(1 << p)) | (1 << q)
+            s = st.excitation_sign(J, p, q) if p != q else 1
+            out.append((amap[J], hv * s))
+    return out
+
+
+def diag_coulomb_ham_amplitudes(ham, norb: int, nelec, idx, row, col) -> np.ndarray:
+    """(H psi)[i, j] for each (i, j) in idx, for a DF Hamiltonian whose two-body terms all have the identity
+    basis (a diagonal Coulomb Hamiltonian, Sec. 2.7.3): the one-body rows of both spins and the diagonal
+    weight 1/2 x^T J_t x, x = occupations of both spins.  row(i) / col(j) return psi[i, :] / psi[:, j]."""
+    na, nb = nelec
+    sa, sb = st.strings(norb, na), st.strings(norb, nb)
+    ma, mb = st.address_map(norb, na), st.address_map(norb, nb)
+    h = np.asarray(ham.h)
+    out = []
+    for i, j in idx:
+        ci, rj = col(j), row(i)
+        a, b = int(sa[i]), int(sb[j])
+        v = sum(c * ci[k] for k, c in one_body_row(h, norb, na, a, ma))
+        v += sum(c * rj[k] for k, c in one_body_row(h, norb, nb, b, mb))
+        x = np.array([((a >> p) & 1) + ((b >> p) & 1) for p in range(norb)], dtype=float)
+        w = sum(0.5 * x @ np.asarray(ham.J[t]) @ x for t in range(ham.J.shape[0]))
+        out.append(v + w * rj[j])
+    return np.array(out)

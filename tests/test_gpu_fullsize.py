@@ -12,7 +12,10 @@ Whole oracle states do not fit these sizes, so the checks are:
   * two DF steps at norb = 14 (7, 7) from Hartree-Fock against stored oracle
     amplitudes (tests/golden/df_trotter_n14.txt);
   * the LUCJ adjoint gradient at norb = 16 (8, 8) against central differences
-    of GPU energies on sampled parameters, and complex64 against complex128.
+    of GPU energies on sampled parameters, and complex64 against complex128;
+  * the 4 x 8 Hubbard model at norb = 32 (4, 4): sampled amplitudes of the
+    Hamiltonian action, its energy against the rotation route, and norm,
+    energy and reversibility of the exact evolution.
 States at norb >= 16 are drawn on the device from a seeded torch generator and
 copied to the host for the oracle: both sides read the same values.
 """
@@ -203,3 +206,36 @@ def test_lucj_gradient_n16_matches_central_differences(ffx):
     e64, g64 = ffx.lucj_energy_grad(p, ham, norb, nelec, n_reps, dtype=torch.complex64)
     assert abs(e64 - e) <= 1e-5 * max(1.0, abs(e))
     assert np.max(np.abs(g64 - g)) <= 1e-4 * scale
+
+
+def test_hubbard_4x8_action_and_exact_evolution(ffx):
+    """The Trotter-error workload at its full size: 4 x 8 Hubbard, norb = 32 (4, 4), complex128 (20.7 GB).
+    Sampled amplitudes of H psi (direct one-body route) against the oracle one by one; <psi|H psi> against
+    the DF energy (rotation route); the exact evolution keeps the norm and the energy and is undone by
+    evolving back."""
+    nx, ny = 4, 8
+    norb, nelec = nx * ny, synth.hubbard_filling(nx, ny)
+    ham = synth.hubbard_2d(nx, ny)
+    da, db = ost.dim(norb, nelec[0]), ost.dim(norb, nelec[1])
+    print(f"hubbard 4x8 {da}x{db}", flush=True)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(11)
+    vec = torch.randn((da, db), dtype=torch.complex128, device="cuda:0", generator=g)
+    vec /= torch.linalg.vector_norm(vec)
+    out = ffx.apply_df_hamiltonian(vec, ham, norb, nelec)
+    r = synth.rng(12)
+    idx = [(0, 0), (da - 1, db - 1)] + [(int(r.integers(da)), int(r.integers(db))) for _ in range(22)]
+    ref = sampled.diag_coulomb_ham_amplitudes(ham, norb, nelec, idx, lambda i: vec[i, :].cpu().numpy(),
+                                              lambda j: vec[:, j].cpu().numpy())
+    got = np.array([complex(out[i, j].item()) for i, j in idx])
+    assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, float(np.abs(ref).max()))
+    e_direct = float(torch.vdot(vec.reshape(-1), out.reshape(-1)).real)
+    e_rot = ffx.df_energy(vec, ham, norb, nelec)
+    assert abs(e_direct - e_rot) <= 1e-10 * max(1.0, abs(e_rot))
+    del out
+    ex, k = ffx.evolve_exact(vec, ham, 1.0, norb, nelec)
+    print(f"exact evolution: {k} Hamiltonian actions", flush=True)
+    assert abs(float(torch.linalg.vector_norm(ex)) - 1.0) <= 1e-10
+    assert abs(ffx.df_energy(ex, ham, norb, nelec) - e_rot) <= 1e-9 * max(1.0, abs(e_rot))
+    ffx.evolve_exact(ex, ham, -1.0, norb, nelec, out=ex)
+    assert float(torch.max(torch.abs(ex - vec))) <= 1e-9

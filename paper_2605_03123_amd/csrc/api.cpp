@@ -609,34 +609,54 @@ int ffx_apply_df_trotter_step(ffx_plan plan, void* vec, const ffx_df_ham* ham, d
       else
         m.push_back(e);
     }
+    // The state is kept in the basis of the last two-body term visited:
+    // psi = script-U(B) phi.  A one-body factor exp(-i tau sum h a+ a) is the
+    // orbital rotation Q(tau) = V diag(exp(-i eps tau)) V^dag (Table 1:
+    // quadratic Hamiltonian evolution), so it only updates B <- Q B and is
+    // carried into the next change of basis, script-U(U_t^dag B).  A step thus
+    // costs one orbital rotation per two-body term plus the final return to
+    // the orbital basis, and the one-body term adds none.
     DecompPool pool;
     std::map<std::pair<int, int>, const Decomposition*> rot_cache;
-    auto rot = [&](int from, int to) -> const Decomposition* {
-      auto key = std::make_pair(from, to);
-      auto it = rot_cache.find(key);
-      if (it != rot_cache.end()) return it->second;
-      std::vector<cd> M;
-      if (from < 0)
-        M = dagger(N, df.Wm(to));
-      else if (to < 0)
-        M = df.Wm(from);
-      else
-        M = matmul(N, dagger(N, df.Wm(to)), df.Wm(from));
-      const Decomposition* d = pool.add(N, M);
-      rot_cache.emplace(key, d);
-      return d;
+    auto q_of = [&](double tau) {
+      std::vector<cd> Q((size_t)N * N, 0.0);
+      for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+          cd acc = 0.0;
+          for (int k = 0; k < N; ++k) acc += df.V[i * N + k] * std::exp(cd(0.0, -df.eps[k] * tau)) * std::conj(df.V[j * N + k]);
+          Q[i * N + j] = acc;
+        }
+      return Q;
     };
     Program pr;
-    std::vector<int> weight;
-    for (int t = 0; t <= df.L; ++t) weight.push_back(pr.add_diag(df_weight_spec(df, t)));
-    int prev = -1;
+    std::vector<int> weight((size_t)df.L + 1, -1);
+    for (int t = 1; t <= df.L; ++t) weight[t] = pr.add_diag(df_weight_spec(df, t));
+    std::vector<cd> B((size_t)N * N, 0.0);  // basis of the stored vector, with the pending one-body factors
+    for (int i = 0; i < N; ++i) B[i * N + i] = 1.0;
+    int basis = -1;       // two-body term whose basis B started from (-1: the orbital basis)
+    bool pending = false;  // B carries one-body factors since that change of basis
     for (auto& e : m) {
-      const Decomposition* d = rot(prev, e.first);
+      if (e.first == 0) {
+        B = matmul(N, q_of(e.second), B);
+        pending = true;
+        continue;
+      }
+      const Decomposition* d;
+      auto key = std::make_pair(basis, e.first);
+      auto it = rot_cache.find(key);
+      if (!pending && it != rot_cache.end()) {
+        d = it->second;
+      } else {
+        d = pool.add(N, matmul(N, dagger(N, df.Wm(e.first)), B));
+        if (!pending) rot_cache.emplace(key, d);
+      }
       pr.rot(d, d);
       pr.phase(weight[e.first], -e.second);
-      prev = e.first;
+      B = df.Wm(e.first);
+      basis = e.first;
+      pending = false;
     }
-    const Decomposition* d = rot(prev, -1);
+    const Decomposition* d = pool.add(N, B);
     pr.rot(d, d);
     Upload up(&P, s);
     Compiled c = compile_program(P, up, pr, FINAL_STORE, s);

@@ -775,9 +775,21 @@ void build_ham_action(ffx_plan_s& P, const DFHost& df, const double* h, DecompPo
   if (mode && std::string(mode) == "rot") {
     direct = false;
   } else {
-    for (int sp = 0; sp < 2; ++sp) t[sp] = build_one_body_table(N, P.str[sp], hv);
-    const double per = (double)t[0].src.size() / (double)P.dim[0] + (double)t[1].src.size() / (double)P.dim[1];
-    direct = (mode && std::string(mode) == "direct") || per <= 48.0;
+    const bool forced = mode && std::string(mode) == "direct";
+    // expected entries per configuration from the off-diagonal nonzeros of h (a configuration with n
+    // electrons reaches a given q outside it from each occupied p with probability (N - n) / (N - 1))
+    double offdiag = 0;
+    for (int p = 0; p < N; ++p)
+      for (int q = 0; q < N; ++q)
+        if (p != q && hv[(size_t)p * N + q] != 0.0) offdiag += 1.0;
+    double est = 0;
+    for (int sp = 0; sp < 2; ++sp)
+      est += 1.0 + (N > 1 ? P.n[sp] * (offdiag / N) * (double)(N - P.n[sp]) / (N - 1) : 0.0);
+    if (forced || est <= 64.0) {
+      for (int sp = 0; sp < 2; ++sp) t[sp] = build_one_body_table(N, P.str[sp], hv);
+      const double per = (double)t[0].src.size() / (double)P.dim[0] + (double)t[1].src.size() / (double)P.dim[1];
+      direct = forced || per <= 48.0;
+    }
   }
   A.direct = direct;
   std::vector<Program> terms = df_term_programs(df, pool, N);

@@ -334,7 +334,8 @@ int64_t ffx_batch_workspace_bytes(ffx_batch batch);
    reverse sweep on `stream`, then synchronizes: the passes of all instances
    are grouped by level (pass k of every instance), and each level is one
    kernel launch whose blocks run its tasks (blocks of rows or columns of one
-   instance's state).  A single persistent launch over a task queue with
+   instance's state); with ffx_batch_single_launch the whole batch is one
+   cooperative launch instead.  A persistent launch over a task queue with
    per-instance dependency counters is built but switched off. */
 int ffx_batch_lucj_energy_grad(ffx_batch batch, const ffx_lucj* ops, const ffx_df_ham* hams,
                                double* energies, double* grads, void* workspace, void* stream);
@@ -346,6 +347,15 @@ int ffx_batch_lucj_energy_grad(ffx_batch batch, const ffx_lucj* ops, const ffx_d
    elements and stage depth to *target_elems and *stage_rots (may be NULL). */
 int ffx_batch_tune(ffx_batch batch, const ffx_lucj* ops, const ffx_df_ham* hams, void* workspace,
                    void* stream, int* target_elems, int* stage_rots);
+
+/* enable != 0: later calls run the whole batch as ONE cooperative launch
+   (hipLaunchCooperativeKernel) whose blocks walk the pass levels in order,
+   running each level's tasks grid-stride, with a grid barrier between levels;
+   its results equal those of the per-level launches (the same tasks in the
+   same arithmetic order).  The grid is the number of blocks that fit the
+   device at once; FFX_EDEVICE if the cooperative launch is refused.
+   enable = 0: one launch per level (the default). */
+int ffx_batch_single_launch(ffx_batch batch, int enable);
 
 /* Timing of the last ffx_batch_lucj_energy_grad: device time from the first to
    the last launch (HIP events on the call's stream), wall time of the whole

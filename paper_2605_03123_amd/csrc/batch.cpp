@@ -44,6 +44,9 @@ struct ffx_batch_s {
   // dependency counters) instead of one launch per pass level.  Off: its last
   // run on the GPU did not complete and the cause is not established.
   bool persistent = false;
+  // One cooperative launch that walks the pass levels with a grid barrier
+  // between them (ffx_batch_single_launch); off: one launch per level.
+  bool single_launch = false;
   // timing of the last call
   double last_device_ms = 0, last_call_ms = 0;
   int last_launches = 0;
@@ -359,7 +362,7 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
     for (auto& c : ib[i].udiag) count(c);
     n_pass_bound += 8 + 10 * (size_t)ib[i].G->L.R;
   }
-  const size_t up_total = up_need + 64 + (n_pass_bound + 4) * sizeof(dev::BPassDev) +
+  const size_t up_total = up_need + 64 + (n_pass_bound + 4) * (sizeof(dev::BPassDev) + sizeof(int)) +
                           (n_table_bound + 4) * sizeof(dev::BTableDev) + 4096;
   if (b.up_cap < up_total) {
     if (b.h_up) (void)hipHostFree(b.h_up);
@@ -570,6 +573,7 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
   }
   level_start.push_back((int)all.size());
   const dev::BPassDev* d_passes = up.put(all.data(), all.size());
+  const int* d_levels = up.put(level_start.data(), level_start.size());
   up.commit();
 
   if (b.counters_cap < (size_t)n + 4) {
@@ -594,7 +598,16 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
   if (!b.ev[1]) HIPCHK(hipEventCreate(&b.ev[1]));
   HIPCHK(hipEventRecord(b.ev[0], s));
   int launches = 0;
-  if (b.persistent) {
+  if (b.single_launch) {
+    int per_cu = dev::batch_coop_blocks_per_cu(b.c64, b.lds), cus = 0;
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b.device));
+    if (per_cu < 1) throw Error(FFX_EUNSUPPORTED, "single launch: no block fits a compute unit");
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * cus, first));
+    const hipError_t e = dev::batch_launch_coop(b.c64, bd, d_levels, (int)level_start.size() - 1, blocks, b.lds, s);
+    if (e != hipSuccess) throw Error(FFX_EDEVICE, std::string("cooperative launch: ") + hipGetErrorString(e));
+    check_launch();
+    launches = 1;
+  } else if (b.persistent) {
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(b.blocks, first));
     dev::batch_launch(b.c64, bd, blocks, 256, b.lds, s);
     check_launch();
@@ -751,6 +764,13 @@ int ffx_batch_timing(ffx_batch batch, double* device_ms, double* call_ms, int* l
     if (device_ms) *device_ms = batch->last_device_ms;
     if (call_ms) *call_ms = batch->last_call_ms;
     if (launches) *launches = batch->last_launches;
+  });
+}
+
+int ffx_batch_single_launch(ffx_batch batch, int enable) {
+  return guard([&] {
+    if (!batch) throw Error(FFX_EINVAL, "null batch");
+    batch->single_launch = enable != 0;
   });
 }
 

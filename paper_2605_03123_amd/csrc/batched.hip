@@ -20,6 +20,7 @@
 // with the class tables of one row replicated over the rows (see
 // replicate_seg_window), so small rows still fill the 64 lanes of a wave.
 // Columns are gathered and scattered directly, so no transposes are needed.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -673,6 +674,95 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_level(BatchDev B, int p
     case BK_SUM: sum_task(ps); break;
     default: break;
   }
+}
+
+// Single cooperative launch: every block walks the levels in order, running
+// the tasks of the current level grid-stride, and the whole grid meets at a
+// grid barrier between levels (the same ordering the per-level launches get
+// from the launch boundaries).  The loop bounds are the same for every block,
+// so every block reaches every barrier.
+template <int W, class R>
+__global__ __launch_bounds__(kBatchThreads) void k_batch_coop(BatchDev B, const int* __restrict__ level_start,
+                                                              int n_levels) {
+  extern __shared__ __align__(16) char smem[];
+  const BatchLds L = batch_lds_map(smem, B);
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (int lv = 0; lv < n_levels; ++lv) {
+    const int p0 = level_start[lv], p1 = level_start[lv + 1];
+    if (p0 < p1) {
+      const int64_t t0 = B.passes[p0].first;
+      const int64_t t1 = p1 < B.n_passes ? B.passes[p1].first : B.n_tasks;
+      for (int64_t t = t0 + blockIdx.x; t < t1; t += gridDim.x) {
+        int lo = p0, hi = p1 - 1;  // last pass of the level whose first task <= t
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (B.passes[mid].first <= t)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        const BPassDev ps = uniform_load(B.passes + lo);
+        const BTypeDev ty = uniform_load(B.types + ps.type);
+        const int task = (int)(t - ps.first);
+        if (task >= 0 && task < ps.n_tasks) {
+          switch (ps.kind) {
+            case BK_TABLES: tables_task(ps, ty, task); break;
+            case BK_OUTER: outer_task<R>(ps, ty, task); break;
+            case BK_SEG:
+              if (ps.real)
+                seg_task<W, true, R>(B, ps, ty, task, L);
+              else
+                seg_task<W, false, R>(B, ps, ty, task, L);
+              break;
+            case BK_INNER: inner_task<R>(ps, ty, task, L.red); break;
+            case BK_RDM: rdm_task<R>(ps, ty, task, L); break;
+            case BK_DGRAD: dgrad_task<R>(ps, ty, task, L.acc); break;
+            case BK_SUM: sum_task(ps); break;
+            default: break;
+          }
+        }
+        __syncthreads();  // the next task of this block reuses the LDS
+      }
+    }
+    grid.sync();
+  }
+}
+
+template <int W, class R>
+static hipError_t launch_coop(const BatchDev& b, const int* level_start, int n_levels, int blocks, size_t lds,
+                              hipStream_t s) {
+  auto k = k_batch_coop<W, R>;
+  (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, kBatchMaxDynLds);
+  (void)hipGetLastError();
+  BatchDev bb = b;
+  const int* ls = level_start;
+  int nl = n_levels;
+  void* args[] = {(void*)&bb, (void*)&ls, (void*)&nl};
+  return hipLaunchCooperativeKernel((const void*)k, dim3((unsigned)blocks), dim3(kBatchThreads), args,
+                                    (unsigned)lds, s);
+}
+
+int batch_coop_blocks_per_cu(bool c64, size_t lds) {
+  int n = 0;
+  hipError_t e;
+  if (lds > (size_t)kBatchMaxDynLds) return 0;
+  if (c64) {
+    (void)hipFuncSetAttribute((const void*)k_batch_coop<6, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kBatchMaxDynLds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_coop<6, float>, kBatchThreads, lds);
+  } else {
+    (void)hipFuncSetAttribute((const void*)k_batch_coop<6, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kBatchMaxDynLds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_coop<6, double>, kBatchThreads, lds);
+  }
+  (void)hipGetLastError();
+  return e == hipSuccess ? n : 0;
+}
+
+hipError_t batch_launch_coop(bool c64, const BatchDev& b, const int* level_start, int n_levels, int blocks,
+                             size_t lds, hipStream_t s) {
+  return c64 ? launch_coop<6, float>(b, level_start, n_levels, blocks, lds, s)
+             : launch_coop<6, double>(b, level_start, n_levels, blocks, lds, s);
 }
 
 template <int W, class R>

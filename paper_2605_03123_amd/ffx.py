@@ -586,6 +586,7 @@ _batch_tune = _sig("ffx_batch_tune", ctypes.c_int,
                    [_vp, ctypes.POINTER(_LUCJ), ctypes.POINTER(_DFHam), _vp, _vp, _c_int_p, _c_int_p])
 _batch_timing = _sig("ffx_batch_timing", ctypes.c_int,
                      [_vp, _c_double_p, _c_double_p, _c_int_p])
+_batch_single = _sig("ffx_batch_single_launch", ctypes.c_int, [_vp, ctypes.c_int])
 _batch_info = _sig("ffx_batch_info", ctypes.c_int,
                    [_vp, _c_int_p, _c_int_p, _c_int_p, ctypes.POINTER(ctypes.c_int64)])
 
@@ -667,6 +668,10 @@ class Batch:
         d, c, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
         _check(_batch_timing(self._h, ctypes.byref(d), ctypes.byref(c), ctypes.byref(n)))
         return {"device_ms": d.value, "call_ms": c.value, "launches": n.value}
+
+    def single_launch(self, enable: bool = True):
+        """Run later calls as one cooperative launch over all pass levels (else one launch per level)."""
+        _check(_batch_single(self._h, int(bool(enable))))
 
     def info(self) -> dict:
         t, r, b, lds = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()

@@ -576,14 +576,16 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
   const int* d_levels = up.put(level_start.data(), level_start.size());
   up.commit();
 
-  if (b.counters_cap < (size_t)n + 4) {
+  // [next, abort, -, -, done per instance..., task counter per level...]
+  const size_t n_ctr = (size_t)n + 4 + level_start.size();
+  if (b.counters_cap < n_ctr) {
     if (b.counters) (void)hipFree(b.counters);
     b.counters = nullptr;
     b.counters_cap = 0;
-    b.counters = (unsigned*)b.dalloc(((size_t)n + 4) * sizeof(unsigned));
-    b.counters_cap = (size_t)n + 4;
+    b.counters = (unsigned*)b.dalloc(n_ctr * sizeof(unsigned));
+    b.counters_cap = n_ctr;
   }
-  HIPCHK(hipMemsetAsync(b.counters, 0, ((size_t)n + 4) * sizeof(unsigned), s));
+  HIPCHK(hipMemsetAsync(b.counters, 0, n_ctr * sizeof(unsigned), s));
   dev::BatchDev bd{};
   bd.types = b.d_types;
   bd.passes = d_passes;
@@ -603,7 +605,8 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b.device));
     if (per_cu < 1) throw Error(FFX_EUNSUPPORTED, "single launch: no block fits a compute unit");
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * cus, first));
-    const hipError_t e = dev::batch_launch_coop(b.c64, bd, d_levels, (int)level_start.size() - 1, blocks, b.lds, s);
+    const hipError_t e = dev::batch_launch_coop(b.c64, bd, d_levels, (int)level_start.size() - 1,
+                                                b.counters + 4 + n, blocks, b.lds, s);
     if (e != hipSuccess) throw Error(FFX_EDEVICE, std::string("cooperative launch: ") + hipGetErrorString(e));
     check_launch();
     launches = 1;

@@ -676,15 +676,17 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_level(BatchDev B, int p
   }
 }
 
-// Single cooperative launch: every block walks the levels in order, running
-// the tasks of the current level grid-stride, and the whole grid meets at a
-// grid barrier between levels (the same ordering the per-level launches get
-// from the launch boundaries).  The loop bounds are the same for every block,
-// so every block reaches every barrier.
+// Single cooperative launch: every block walks the levels in order, taking
+// the tasks of the current level from a per-level counter (zeroed before the
+// launch; a block only ever increments it, and leaves the level once it runs
+// past the level's last task), and the whole grid meets at a grid barrier
+// between levels (the same ordering the per-level launches get from the
+// launch boundaries).  Every block reaches every barrier.
 template <int W, class R>
 __global__ __launch_bounds__(kBatchThreads) void k_batch_coop(BatchDev B, const int* __restrict__ level_start,
-                                                              int n_levels) {
+                                                              int n_levels, unsigned int* __restrict__ level_ctr) {
   extern __shared__ __align__(16) char smem[];
+  __shared__ int64_t s_t;
   const BatchLds L = batch_lds_map(smem, B);
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   for (int lv = 0; lv < n_levels; ++lv) {
@@ -692,7 +694,12 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_coop(BatchDev B, const 
     if (p0 < p1) {
       const int64_t t0 = B.passes[p0].first;
       const int64_t t1 = p1 < B.n_passes ? B.passes[p1].first : B.n_tasks;
-      for (int64_t t = t0 + blockIdx.x; t < t1; t += gridDim.x) {
+      for (;;) {
+        if (threadIdx.x == 0) s_t = t0 + (int64_t)atomicAdd(level_ctr + lv, 1u);
+        __syncthreads();
+        const int64_t t = s_t;
+        __syncthreads();
+        if (t >= t1) break;
         int lo = p0, hi = p1 - 1;  // last pass of the level whose first task <= t
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
@@ -729,15 +736,16 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_coop(BatchDev B, const 
 }
 
 template <int W, class R>
-static hipError_t launch_coop(const BatchDev& b, const int* level_start, int n_levels, int blocks, size_t lds,
-                              hipStream_t s) {
+static hipError_t launch_coop(const BatchDev& b, const int* level_start, int n_levels, unsigned int* level_ctr,
+                              int blocks, size_t lds, hipStream_t s) {
   auto k = k_batch_coop<W, R>;
   (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, kBatchMaxDynLds);
   (void)hipGetLastError();
   BatchDev bb = b;
   const int* ls = level_start;
   int nl = n_levels;
-  void* args[] = {(void*)&bb, (void*)&ls, (void*)&nl};
+  unsigned int* lc = level_ctr;
+  void* args[] = {(void*)&bb, (void*)&ls, (void*)&nl, (void*)&lc};
   return hipLaunchCooperativeKernel((const void*)k, dim3((unsigned)blocks), dim3(kBatchThreads), args,
                                     (unsigned)lds, s);
 }
@@ -759,10 +767,10 @@ int batch_coop_blocks_per_cu(bool c64, size_t lds) {
   return e == hipSuccess ? n : 0;
 }
 
-hipError_t batch_launch_coop(bool c64, const BatchDev& b, const int* level_start, int n_levels, int blocks,
-                             size_t lds, hipStream_t s) {
-  return c64 ? launch_coop<6, float>(b, level_start, n_levels, blocks, lds, s)
-             : launch_coop<6, double>(b, level_start, n_levels, blocks, lds, s);
+hipError_t batch_launch_coop(bool c64, const BatchDev& b, const int* level_start, int n_levels,
+                             unsigned int* level_ctr, int blocks, size_t lds, hipStream_t s) {
+  return c64 ? launch_coop<6, float>(b, level_start, n_levels, level_ctr, blocks, lds, s)
+             : launch_coop<6, double>(b, level_start, n_levels, level_ctr, blocks, lds, s);
 }
 
 template <int W, class R>

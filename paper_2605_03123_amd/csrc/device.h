@@ -384,8 +384,9 @@ void batch_launch_level(bool c64, const BatchDev& b, int p0, int p1, int64_t tas
 // single cooperative launch over all levels (grid barrier between levels); blocks must not exceed
 // batch_coop_blocks_per_cu(...) times the compute units (the launch fails otherwise)
 int batch_coop_blocks_per_cu(bool c64, size_t lds);
-hipError_t batch_launch_coop(bool c64, const BatchDev& b, const int* level_start, int n_levels, int blocks,
-                             size_t lds, hipStream_t s);
+// level_ctr: n_levels task counters, zero at launch
+hipError_t batch_launch_coop(bool c64, const BatchDev& b, const int* level_start, int n_levels,
+                             unsigned int* level_ctr, int blocks, size_t lds, hipStream_t s);
 
 size_t seg_pass_lds(bool c64, int max_len, int max_mt);
 // block size a segment pass launches with for a requested size (the kernel's

@@ -7,7 +7,9 @@ Workload: one first-order (S_0) Trotter step, dt = 0.1, of a DF Hamiltonian
 with L = 16 terms (h ~ sym N(0, 0.5); U_t real orthogonal from QR; J_t ~ sym
 N(0, 0.1)) on a random normalized 12870 x 12870 state, seed 0.  The state is
 resident in HBM before timing; W untimed steps, then K timed steps bracketed by
-device synchronization, timed with HIP events on the working stream.  `value`
+device synchronization, timed with HIP events on the working stream (one per
+step boundary: the mean is `value`, the median and interquartile range of the
+single steps are reported beside it).  `value`
 is the time per step in the primary precision (--dtype, complex128 by
 default); the other precision is timed the same way and reported beside it.
 
@@ -19,6 +21,9 @@ the 2D Hubbard model (t = 1, U = 8, 4 x 8 lattice periodic in x, 1/8 filling,
 T = 1): one Hamiltonian action, the exact evolution, Trotter runs of orders 1
 and 2 and their errors, and beside it the same measurement on a 4 x 4 lattice
 on the GPU (the cpu_baseline object holds the oracle's time for that one).
+
+Also reported (unless --no-n18): one S_0 step at norb = 18, (9, 9), L = 18
+(37.8 GB complex128) in both precisions with the HBM rate of each kernel family.
 
 Also reported (unless --no-table1): the time per call of the other Table 1
 gates, the Slater-determinant state, a 3-repetition UCJ forward pass and the
@@ -147,28 +152,33 @@ def cpu_baseline(ham, vec: np.ndarray, synth=None, hubbard_small=None) -> dict:
     return out
 
 
-def time_df_step(ffx, torch, ham, vec_np, dtype, steps, warmup):
+def time_df_step(ffx, torch, ham, vec_np, dtype, steps, warmup, norb=NORB, nelec=NELEC, vec_dev=None):
+    """Mean time per S_0 step over `steps` steps after `warmup` (HIP events on the working stream, one per
+    step boundary, so the median and interquartile range of the single steps come out too), then the live
+    per-launch timing of the kernel families over one more step."""
     dev = torch.device("cuda:0")
-    vec = torch.from_numpy(vec_np).to(dtype).to(dev)
-    plan = ffx.get_plan(NORB, NELEC, dtype, 0)
+    vec = vec_dev if vec_dev is not None else torch.from_numpy(vec_np).to(dtype).to(dev)
+    plan = ffx.get_plan(norb, nelec, dtype, 0)
     stream = torch.cuda.current_stream(dev)
 
     def step():
-        ffx.simulate_trotter_double_factorized(vec, ham, DT, NORB, NELEC, n_steps=1, order=0, out=vec)
+        ffx.simulate_trotter_double_factorized(vec, ham, DT, norb, nelec, n_steps=1, order=0, out=vec)
 
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t_wall = time.perf_counter()
-    e0.record(stream)
-    for _ in range(steps):
+    ev[0].record(stream)
+    for k in range(steps):
         step()
-    e1.record(stream)
+        ev[k + 1].record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
-    ms = e0.elapsed_time(e1) / steps
-    norm = float(torch.linalg.vector_norm(vec.to(torch.complex128)))
+    ms = ev[0].elapsed_time(ev[-1]) / steps
+    per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+    stats = {"median_ms": float(np.median(per)), "iqr_ms": float(np.percentile(per, 75) - np.percentile(per, 25))}
+    norm = float(torch.linalg.vector_norm(vec.to(torch.complex128) if vec.dtype != torch.complex128 else vec))
 
     # live per-launch timing of the kernel families over one more step
     plan.timing(True)
@@ -183,7 +193,30 @@ def time_df_step(ffx, torch, ham, vec_np, dtype, steps, warmup):
                                            "alg_bytes": alg, "valu_slots": slots}
     plan.timing(False)
     del vec
-    return ms, t_wall, norm, fam, plan.state_bytes
+    return ms, t_wall, norm, fam, plan.state_bytes, stats
+
+
+def n18_timing(ffx, torch, synth, dtype):
+    """One S_0 step at norb = 18, (9, 9), L = 18 (48620 x 48620, 37.8 GB complex128), dt = 0.1, from a
+    random normalized state drawn on the device (seeded torch generator); 3 timed steps after 1 warm-up, and
+    the per-kernel-family HBM rate (algorithmic bytes over kernel time) against the 8 TB/s peak."""
+    norb, nelec, nt = 18, (9, 9), 18
+    ham = synth.df_hamiltonian(synth.rng(5), norb, nt)
+    d = synth.dim(norb, 9)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(5)
+    vec = torch.randn((d, d), dtype=dtype, device="cuda:0", generator=g)
+    vec /= torch.linalg.vector_norm(vec)
+    ms, _, norm, fam, sb, stats = time_df_step(ffx, torch, ham, None, dtype, 3, 1, norb, nelec, vec_dev=vec)
+    del vec
+    out = {"ms_per_step": ms, **stats, "state_bytes": sb, "final_norm": norm, "families": {}}
+    for k, v in fam.items():
+        gbs = v["alg_bytes"] / (v["total_ms"] * 1e-3) / 1e9
+        out["families"][k] = {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 3),
+                              "alg_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    ffx._plan_cached.cache_clear()
+    torch.cuda.empty_cache()
+    return out
 
 
 def roofline(fam, dtype_name, state_bytes):
@@ -209,6 +242,9 @@ def roofline(fam, dtype_name, state_bytes):
     tr = committed_traffic(dtype_name)
     r.update({
         "traffic": tr,
+        # measured HBM bytes per launch (when the committed counters match these kernels, else the
+        # algorithmic 2 S) over the average launch time, against the 8 TB/s peak
+        "hbm_frac": round((tr if tr else hbm_bytes) / sec / 1e9 / HBM_PEAK_GBS, 4),
         "kernel": "k_seg_pass (alpha and beta column spins)",
         "avg_launch_ms": round(tot_ms / n, 4),
         "launches_per_step": n,
@@ -441,8 +477,8 @@ def copy_calibration(torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", choices=["c128", "c64"], default="c128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lucj", action="store_true")
@@ -450,6 +486,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-hubbard", action="store_true")
     ap.add_argument("--no-table1", action="store_true")
+    ap.add_argument("--no-n18", action="store_true")
     ap.add_argument("--hubbard-y", type=int, default=8, help="lattice 4 x y of the Trotter-error leg")
     ap.add_argument("--hubbard-only", action="store_true", help="run only the Trotter-error leg (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -473,8 +510,8 @@ def main():
     types = {"c128": torch.complex128, "c64": torch.complex64}
     w = synth.workload_df_trotter(NORB, L, seed=0, start="random", dt=DT)
     ham, vec_np = w.data["ham"], w.data["vec"]
-    ms, t_wall, norm, fam, state_bytes = time_df_step(ffx, torch, ham, vec_np, types[args.dtype], args.steps,
-                                                       args.warmup)
+    ms, t_wall, norm, fam, state_bytes, stats = time_df_step(ffx, torch, ham, vec_np, types[args.dtype],
+                                                              args.steps, args.warmup)
     out = {
         "metric": "s per DF Trotter step (norb=16, nelec=(8,8), L=16, S_0, dt=0.1)",
         "value": ms / 1e3,
@@ -483,6 +520,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_per_step_median": stats["median_ms"],
+        "ms_per_step_iqr": stats["iqr_ms"],
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -495,10 +534,12 @@ def main():
     }
     if not args.no_other_dtype:
         other = "c64" if args.dtype == "c128" else "c128"
-        ms2, _, norm2, fam2, sb2 = time_df_step(ffx, torch, ham, vec_np, types[other], args.steps, args.warmup)
+        ms2, _, norm2, fam2, sb2, st2 = time_df_step(ffx, torch, ham, vec_np, types[other], args.steps,
+                                                     args.warmup)
         rf2 = roofline(fam2, other, sb2)
         rf2.pop("families")
-        out[f"df_step_{other}"] = {"ms_per_step": ms2, "final_norm": norm2, "roofline": rf2}
+        out[f"df_step_{other}"] = {"ms_per_step": ms2, "ms_per_step_median": st2["median_ms"],
+                                   "ms_per_step_iqr": st2["iqr_ms"], "final_norm": norm2, "roofline": rf2}
     if not args.no_lucj:
         out["lucj_energy_grad"] = {
             "workload": f"lucj norb=16 nelec=(8,8) n_reps={LUCJ_REPS} L={L} params~N(0,0.1)",
@@ -519,6 +560,10 @@ def main():
             "c64": batched_timing(ffx, torch, synth, torch.complex64),
             "c128": batched_timing(ffx, torch, synth, torch.complex128),
         }
+    if not args.no_n18:
+        out["df_step_n18"] = {"workload": "df_trotter_step norb=18 nelec=(9,9) L=18 dt=0.1 order=0, random state",
+                              "c128": n18_timing(ffx, torch, synth, torch.complex128),
+                              "c64": n18_timing(ffx, torch, synth, torch.complex64)}
     if not args.no_table1:
         out["table1_gates_n16_c128"] = table1_timing(ffx, torch, synth)
     if not args.no_hubbard:

@@ -193,3 +193,24 @@ def test_large_orbital_counts_segmented(ffx, small_segment_plans):
         out = ffx.simulate_trotter_double_factorized(vec, ham, 0.3, norb, nelec, n_steps=1, order=1, plan=plan)
         ref = oh.simulate_trotter(x, ham, 0.3, norb, nelec, n_steps=1, order=1)
         assert _maxdiff(out, ref) <= 1e-11
+
+
+def test_trotter_study_against_oracle(ffx):
+    """The study driver (mean and spread of Trotter errors over random unit states) against the oracle
+    on the same states, 4 x 2 lattice."""
+    from paper_2605_03123_amd import trotter_study
+    nx, ny = 4, 2
+    norb, nelec = nx * ny, synth.hubbard_filling(nx, ny)
+    ham = synth.hubbard_2d(nx, ny)
+    res, _ = trotter_study.trotter_errors(nx, ny, [0, 1], [1, 3], n_vectors=3, time_T=0.8, seed=7)
+    da, db = _dims(norb, nelec)
+    errs = {(o, n): [] for o in (0, 1) for n in (1, 3)}
+    for k in range(3):
+        x = _host(trotter_study.random_unit_state(da, db, 7 + k))
+        ex = oh.evolve_exact(x, ham, 0.8, norb, nelec)
+        for o in (0, 1):
+            for n in (1, 3):
+                errs[(o, n)].append(oh.trotter_error(x, ham, 0.8, norb, nelec, n, o, exact=ex))
+    for key, v in errs.items():
+        assert abs(res[key][0] - np.mean(v)) <= 1e-9
+        assert abs(res[key][1] - np.std(v)) <= 1e-9

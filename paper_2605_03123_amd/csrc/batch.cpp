@@ -45,8 +45,9 @@ struct ffx_batch_s {
   // run on the GPU did not complete and the cause is not established.
   bool persistent = false;
   // One cooperative launch that walks the pass levels with a grid barrier
-  // between them (ffx_batch_single_launch); off: one launch per level.
-  bool single_launch = false;
+  // between them (the default; ffx_batch_single_launch(batch, 0) switches to
+  // one launch per level).
+  bool single_launch = true;
   // timing of the last call
   double last_device_ms = 0, last_call_ms = 0;
   int last_launches = 0;
@@ -600,10 +601,13 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
   if (!b.ev[1]) HIPCHK(hipEventCreate(&b.ev[1]));
   HIPCHK(hipEventRecord(b.ev[0], s));
   int launches = 0;
+  int coop_per_cu = 0, cus = 0;
   if (b.single_launch) {
-    int per_cu = dev::batch_coop_blocks_per_cu(b.c64, b.lds), cus = 0;
+    coop_per_cu = dev::batch_coop_blocks_per_cu(b.c64, b.lds);
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b.device));
-    if (per_cu < 1) throw Error(FFX_EUNSUPPORTED, "single launch: no block fits a compute unit");
+  }
+  if (b.single_launch && coop_per_cu >= 1) {  // else (no block fits) one launch per level
+    const int per_cu = coop_per_cu;
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * cus, first));
     const hipError_t e = dev::batch_launch_coop(b.c64, bd, d_levels, (int)level_start.size() - 1,
                                                 b.counters + 4 + n, blocks, b.lds, s);

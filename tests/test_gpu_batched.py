@@ -135,7 +135,9 @@ def test_batched_single_cooperative_launch(ffx):
     args = ([x.data["params"] for x in w], [x.data["ham"] for x in w], 2)
     for dtype in (torch.complex64, torch.complex128):
         b = ffx.Batch(sectors, dtype=dtype)
+        b.single_launch(False)
         e0, g0 = b.lucj_energy_grad(*args)
+        assert b.timing()["launches"] > 1
         b.single_launch(True)
         print(f"cooperative batched launch: 64 sectors {dtype}", flush=True)
         for _ in range(2):

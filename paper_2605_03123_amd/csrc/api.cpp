@@ -765,8 +765,9 @@ struct HamAction {
   }
 };
 
-void build_ham_action(ffx_plan_s& P, const DFHost& df, const double* h, DecompPool& pool, hipStream_t s,
-                      HamAction& A) {
+// Chooses the route of the one-body term (A.direct) and, for the direct route,
+// builds its tables on the device.
+void prepare_one_body(ffx_plan_s& P, const double* h, HamAction& A) {
   const int N = P.norb;
   std::vector<double> hv(h, h + (size_t)N * N);
   OneBodyTable t[2];
@@ -792,11 +793,6 @@ void build_ham_action(ffx_plan_s& P, const DFHost& df, const double* h, DecompPo
     }
   }
   A.direct = direct;
-  std::vector<Program> terms = df_term_programs(df, pool, N);
-  Upload up(&P, s);
-  for (int term = direct ? 1 : 0; term <= df.L; ++term)
-    A.cs.push_back(compile_program(P, up, terms[term], term == 0 ? FINAL_STORE : FINAL_ACCUM, s));
-  up.commit();
   if (!direct) return;
   for (int sp = 0; sp < 2; ++sp) {
     HamAction::Tab& d = A.tab[sp];
@@ -811,21 +807,37 @@ void build_ham_action(ffx_plan_s& P, const DFHost& df, const double* h, DecompPo
   }
 }
 
+void build_ham_action(ffx_plan_s& P, const DFHost& df, const double* h, DecompPool& pool, hipStream_t s,
+                      HamAction& A) {
+  prepare_one_body(P, h, A);
+  std::vector<Program> terms = df_term_programs(df, pool, P.norb);
+  Upload up(&P, s);
+  for (int term = A.direct ? 1 : 0; term <= df.L; ++term)
+    A.cs.push_back(compile_program(P, up, terms[term], term == 0 ? FINAL_STORE : FINAL_ACCUM, s));
+  up.commit();
+}
+
+// out = sum_pq h_pq E_pq in from the direct tables; tmp is a state-sized work buffer; in, out, tmp distinct
+void apply_one_body_direct(ffx_plan_s& P, const HamAction& A, const void* in, void* out, void* tmp,
+                           hipStream_t s) {
+  const int64_t da = P.dim[0], db = P.dim[1];
+  // beta: on the transposed state, rows = beta configurations
+  dev::transpose(P.c64, in, tmp, da, db, s);
+  check_launch();
+  dev::onebody_rows(P.c64, tmp, out, nullptr, db, da, A.tab[1].off, A.tab[1].src, A.tab[1].coef, s);
+  check_launch();
+  dev::transpose(P.c64, out, tmp, db, da, s);
+  check_launch();
+  // alpha, plus the beta part
+  dev::onebody_rows(P.c64, in, out, tmp, da, db, A.tab[0].off, A.tab[0].src, A.tab[0].coef, s);
+  check_launch();
+}
+
 // out = H in; tmp is a state-sized work buffer.  in, out and tmp are distinct.
 void apply_ham(ffx_plan_s& P, const HamAction& A, const void* in, void* out, void* tmp, hipStream_t s) {
-  const int64_t da = P.dim[0], db = P.dim[1];
   size_t k = 0;
   if (A.direct) {
-    // beta: on the transposed state, rows = beta configurations
-    dev::transpose(P.c64, in, tmp, da, db, s);
-    check_launch();
-    dev::onebody_rows(P.c64, tmp, out, nullptr, db, da, A.tab[1].off, A.tab[1].src, A.tab[1].coef, s);
-    check_launch();
-    dev::transpose(P.c64, out, tmp, db, da, s);
-    check_launch();
-    // alpha, plus the beta part
-    dev::onebody_rows(P.c64, in, out, tmp, da, db, A.tab[0].off, A.tab[0].src, A.tab[0].coef, s);
-    check_launch();
+    apply_one_body_direct(P, A, in, out, tmp, s);
   } else {
     execute_program(P, A.cs[k++], in, out, nullptr, s);
   }
@@ -959,6 +971,8 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
     void* lamT = ws + 3 * Sa;
     void* psi = ws + 4 * Sa;  // the reverse sweep uncomputes it; psi_out gets a copy
     double* part = (double*)(ws + 5 * Sa);
+    HamAction onebody;
+    prepare_one_body(P, ham->h, onebody);
     Upload up(&P, s);
     const double* sa = up.put((const double*)G->g.a.data(), 2 * G->g.a.size());
     const double* sb = up.put((const double*)G->g.b.data(), 2 * G->g.b.size());
@@ -976,9 +990,11 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
     check_launch();
     execute_program(P, c_fwd, psi, psi, nullptr, s);
     if (psi_out) HIPCHK(hipMemcpyAsync(psi_out, psi, S, hipMemcpyDeviceToDevice, s));
-    // costate lambda = H psi
+    // costate lambda = H psi (the one-body term directly from its tables when they are short)
     for (int t = 0; t <= Lt; ++t) {
-      if (t == 0)
+      if (t == 0 && onebody.direct)
+        apply_one_body_direct(P, onebody, psi, lam, tmp, s);
+      else if (t == 0)
         execute_program(P, c_terms[t], psi, lam, nullptr, s);
       else
         execute_program(P, c_terms[t], psi, tmp, lam, s);
@@ -1127,6 +1143,8 @@ int ffx_df_chain_energy_grad(ffx_plan plan, const void* vec0, const ffx_df_ham* 
       const Decomposition* d1 = rot(0, -1);
       tail.rot(d1, d1);
     }
+    HamAction onebody;  // the observable's one-body term, directly when its tables are short
+    prepare_one_body(P, obs->h, onebody);
     Upload up(&P, s);
     Compiled c_fwd = compile_program(P, up, fwd, FINAL_STORE, s);
     std::vector<Compiled> c_terms;
@@ -1145,7 +1163,9 @@ int ffx_df_chain_energy_grad(ffx_plan plan, const void* vec0, const ffx_df_ham* 
     execute_program(P, c_fwd, vec0, psi, nullptr, s);
     if (psi_out) HIPCHK(hipMemcpyAsync(psi_out, psi, S, hipMemcpyDeviceToDevice, s));
     for (int t = 0; t <= ob.L; ++t) {
-      if (t == 0)
+      if (t == 0 && onebody.direct)
+        apply_one_body_direct(P, onebody, psi, lam, tmp, s);
+      else if (t == 0)
         execute_program(P, c_terms[t], psi, lam, nullptr, s);
       else
         execute_program(P, c_terms[t], psi, tmp, lam, s);

@@ -187,6 +187,22 @@ def test_lucj_energy_grad_matches_oracle_adjoint(ffx, dtype, norb, nelec, n_reps
     assert np.max(np.abs(g - go)) <= tol * max(1, np.max(np.abs(go)))
 
 
+@pytest.mark.parametrize("mode", ["auto", "rot"])
+@pytest.mark.parametrize("nx,ny", [(4, 2), (4, 3)])
+def test_lucj_energy_grad_hubbard(ffx, monkeypatch, mode, nx, ny):
+    """LUCJ under the Hubbard model: the costate's one-body term from the sparse excitation tables (auto)
+    or through the eigenbasis of h (rot), against the oracle's adjoint gradient."""
+    if mode != "auto":
+        monkeypatch.setenv("FFX_ONEBODY", mode)
+    norb, nelec = nx * ny, synth.hubbard_filling(nx, ny)
+    ham = synth.hubbard_2d(nx, ny)
+    params = synth.lucj_params(synth.rng([16, nx, ny]), norb, 2, scale=0.3)
+    e, g = ffx.lucj_energy_grad(params, ham, norb, nelec, 2)
+    eo, go = ol.grad_adjoint(params, ham, norb, nelec, 2)
+    assert abs(e - eo) <= 1e-10 * max(1, abs(eo))
+    assert np.max(np.abs(g - go)) <= 1e-10 * max(1, np.max(np.abs(go)))
+
+
 def test_lucj_gradient_matches_central_differences_on_gpu(ffx):
     norb, nelec, n_reps = 8, (4, 4), 2
     r = synth.rng(16)

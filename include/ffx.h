@@ -366,7 +366,9 @@ int ffx_batch_single_launch(ffx_batch batch, int enable);
 int ffx_batch_timing(ffx_batch batch, double* device_ms, double* call_ms, int* launches);
 
 /* Configuration in use (for reports): target elements per task, stage depth,
-   resident blocks of the persistent launch, and its LDS bytes per block. */
+   resident blocks of a launch that holds the whole device (the task-queue
+   launch; the cooperative launch sizes its grid the same way for its own
+   kernel), and the LDS bytes per block. */
 int ffx_batch_info(ffx_batch batch, int* target_elems, int* stage_rots, int* blocks, int64_t* lds_bytes);
 
 /* Diagnostics: per-launch timing of the dominant kernels.  While enabled,

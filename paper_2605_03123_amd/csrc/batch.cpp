@@ -1,8 +1,8 @@
 // Batched LUCJ energy + adjoint gradient (include/ffx.h, ffx_batch_*): the
 // gate programs of every instance are compiled against one plan per sector
 // type, turned into passes of tasks (blocks of rows or columns), ordered pass
-// level by pass level across instances, and run by one persistent kernel
-// (batched.hip).  The host then applies each instance's gradient chain rule.
+// level by pass level across instances, and run by one cooperative launch
+// with a grid barrier between levels, or by one launch per level (batched.hip).  The host then applies each instance's gradient chain rule.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -574,7 +574,7 @@ class LUCJEnergy(torch.autograd.Function):
 
 
 # ---------------------------------------------------------------------------
-# batched LUCJ energy + adjoint gradient (one persistent launch)
+# batched LUCJ energy + adjoint gradient (one cooperative launch by default)
 # ---------------------------------------------------------------------------
 _batch_create = _sig("ffx_batch_create", ctypes.c_int,
                      [ctypes.POINTER(_vp), ctypes.c_int, _c_int_p, _c_int_p, _c_int_p, ctypes.c_int, ctypes.c_int])

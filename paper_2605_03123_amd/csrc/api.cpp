@@ -587,6 +587,66 @@ int ffx_apply_diag_coulomb_evolution(ffx_plan plan, void* vec, const double* J_a
   });
 }
 
+namespace {
+
+// Q(tau) = exp(-i tau h) = V diag(exp(-i eps tau)) V^dag: the one-body factor as an orbital rotation
+std::vector<cd> one_body_rotation(const DFHost& df, int N, double tau) {
+  std::vector<cd> Q((size_t)N * N, 0.0);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      cd acc = 0.0;
+      for (int k = 0; k < N; ++k) acc += df.V[i * N + k] * std::exp(cd(0.0, -df.eps[k] * tau)) * std::conj(df.V[j * N + k]);
+      Q[i * N + j] = acc;
+    }
+  return Q;
+}
+
+// A product formula, given as its merged list of (term, time), as one gate
+// program.  The state is kept in the basis of the last two-body term visited:
+// psi = script-U(B) phi.  A one-body factor exp(-i tau sum h a+ a) is the
+// orbital rotation Q(tau) (Table 1: quadratic Hamiltonian evolution), so it
+// only updates B <- Q B and is carried into the next change of basis,
+// script-U(U_t^dag B).  A step thus costs one orbital rotation per two-body
+// term plus the final return to the orbital basis, and the one-body term adds
+// none.
+Program product_formula_program(const DFHost& df, int N, const std::vector<std::pair<int, double>>& m,
+                                DecompPool& pool) {
+  std::map<std::pair<int, int>, const Decomposition*> rot_cache;
+  Program pr;
+  std::vector<int> weight((size_t)df.L + 1, -1);
+  for (int t = 1; t <= df.L; ++t) weight[t] = pr.add_diag(df_weight_spec(df, t));
+  std::vector<cd> B((size_t)N * N, 0.0);  // basis of the stored vector, with the pending one-body factors
+  for (int i = 0; i < N; ++i) B[i * N + i] = 1.0;
+  int basis = -1;        // two-body term whose basis B started from (-1: the orbital basis)
+  bool pending = false;  // B carries one-body factors since that change of basis
+  for (auto& e : m) {
+    if (e.first == 0) {
+      B = matmul(N, one_body_rotation(df, N, e.second), B);
+      pending = true;
+      continue;
+    }
+    const Decomposition* d;
+    auto key = std::make_pair(basis, e.first);
+    auto it = rot_cache.find(key);
+    if (!pending && it != rot_cache.end()) {
+      d = it->second;
+    } else {
+      d = pool.add(N, matmul(N, dagger(N, df.Wm(e.first)), B));
+      if (!pending) rot_cache.emplace(key, d);
+    }
+    pr.rot(d, d);
+    pr.phase(weight[e.first], -e.second);
+    B = df.Wm(e.first);
+    basis = e.first;
+    pending = false;
+  }
+  const Decomposition* d = pool.add(N, B);
+  pr.rot(d, d);
+  return pr;
+}
+
+}  // namespace
+
 int ffx_apply_df_trotter_step(ffx_plan plan, void* vec, const ffx_df_ham* ham, double dt, int n_steps,
                               int order, void* stream) {
   return guard([&] {
@@ -609,55 +669,8 @@ int ffx_apply_df_trotter_step(ffx_plan plan, void* vec, const ffx_df_ham* ham, d
       else
         m.push_back(e);
     }
-    // The state is kept in the basis of the last two-body term visited:
-    // psi = script-U(B) phi.  A one-body factor exp(-i tau sum h a+ a) is the
-    // orbital rotation Q(tau) = V diag(exp(-i eps tau)) V^dag (Table 1:
-    // quadratic Hamiltonian evolution), so it only updates B <- Q B and is
-    // carried into the next change of basis, script-U(U_t^dag B).  A step thus
-    // costs one orbital rotation per two-body term plus the final return to
-    // the orbital basis, and the one-body term adds none.
     DecompPool pool;
-    std::map<std::pair<int, int>, const Decomposition*> rot_cache;
-    auto q_of = [&](double tau) {
-      std::vector<cd> Q((size_t)N * N, 0.0);
-      for (int i = 0; i < N; ++i)
-        for (int j = 0; j < N; ++j) {
-          cd acc = 0.0;
-          for (int k = 0; k < N; ++k) acc += df.V[i * N + k] * std::exp(cd(0.0, -df.eps[k] * tau)) * std::conj(df.V[j * N + k]);
-          Q[i * N + j] = acc;
-        }
-      return Q;
-    };
-    Program pr;
-    std::vector<int> weight((size_t)df.L + 1, -1);
-    for (int t = 1; t <= df.L; ++t) weight[t] = pr.add_diag(df_weight_spec(df, t));
-    std::vector<cd> B((size_t)N * N, 0.0);  // basis of the stored vector, with the pending one-body factors
-    for (int i = 0; i < N; ++i) B[i * N + i] = 1.0;
-    int basis = -1;       // two-body term whose basis B started from (-1: the orbital basis)
-    bool pending = false;  // B carries one-body factors since that change of basis
-    for (auto& e : m) {
-      if (e.first == 0) {
-        B = matmul(N, q_of(e.second), B);
-        pending = true;
-        continue;
-      }
-      const Decomposition* d;
-      auto key = std::make_pair(basis, e.first);
-      auto it = rot_cache.find(key);
-      if (!pending && it != rot_cache.end()) {
-        d = it->second;
-      } else {
-        d = pool.add(N, matmul(N, dagger(N, df.Wm(e.first)), B));
-        if (!pending) rot_cache.emplace(key, d);
-      }
-      pr.rot(d, d);
-      pr.phase(weight[e.first], -e.second);
-      B = df.Wm(e.first);
-      basis = e.first;
-      pending = false;
-    }
-    const Decomposition* d = pool.add(N, B);
-    pr.rot(d, d);
+    Program pr = product_formula_program(df, N, m, pool);
     Upload up(&P, s);
     Compiled c = compile_program(P, up, pr, FINAL_STORE, s);
     up.commit();
@@ -1089,12 +1102,10 @@ int ffx_df_chain_energy_grad(ffx_plan plan, const void* vec0, const ffx_df_ham* 
       cache.emplace(key, d);
       return d;
     };
-    // forward: n_steps of S_0 (one-body term first), neighbours merged
+    // forward: n_steps of S_0 (one-body term first), neighbours merged, the
+    // one-body factor carried as the rotation Q(dt) = exp(-i dt h)
     Program fwd;
     {
-      std::vector<int> w;
-      for (int t = 0; t <= L; ++t) w.push_back(fwd.add_diag(df_weight_spec(df, t)));
-      int prev = -1;
       std::vector<std::pair<int, double>> m;
       for (int r = 0; r < n_steps; ++r)
         for (int t = 0; t <= L; ++t) {
@@ -1103,14 +1114,7 @@ int ffx_df_chain_energy_grad(ffx_plan plan, const void* vec0, const ffx_df_ham* 
           else
             m.push_back({t, dt});
         }
-      for (auto& e : m) {
-        const Decomposition* d = rot(prev, e.first);
-        fwd.rot(d, d);
-        fwd.phase(w[e.first], -e.second);
-        prev = e.first;
-      }
-      const Decomposition* d = rot(prev, -1);
-      fwd.rot(d, d);
+      fwd = product_formula_program(df, N, m, pool);
     }
     // costate terms of the observable
     std::vector<Program> terms(ob.L + 1);
@@ -1122,7 +1126,8 @@ int ffx_df_chain_energy_grad(ffx_plan plan, const void* vec0, const ffx_df_ham* 
       terms[t].rot(from, from);
     }
     // reverse sweep of one step: into frame L, then per term t: undo D_t,
-    // move to frame t-1; finally undo the one-body term back to the lab frame
+    // move to frame t-1; finally undo the one-body factor Q(dt) on the way
+    // back to the lab frame (one rotation, script-U(Q^dag U_1))
     Program first, tail;
     std::vector<Program> undoD(L + 1), link(L + 1);
     if (L >= 1) {
@@ -1137,11 +1142,10 @@ int ffx_df_chain_energy_grad(ffx_plan plan, const void* vec0, const ffx_df_ham* 
       }
     }
     {
-      const Decomposition* d0 = rot(L >= 1 ? 1 : -1, 0);
-      tail.rot(d0, d0);
-      tail.phase(tail.add_diag(df_weight_spec(df, 0)), +dt);
-      const Decomposition* d1 = rot(0, -1);
-      tail.rot(d1, d1);
+      std::vector<cd> M = dagger(N, one_body_rotation(df, N, dt));
+      if (L >= 1) M = matmul(N, M, df.Wm(1));
+      const Decomposition* d = pool.add(N, M);
+      tail.rot(d, d);
     }
     HamAction onebody;  // the observable's one-body term, directly when its tables are short
     prepare_one_body(P, obs->h, onebody);

@@ -763,6 +763,9 @@ struct HamAction {
     int32_t* src = nullptr;
     double* coef = nullptr;
   } tab[2];
+  // two-body terms whose basis is exactly the identity (a diagonal Coulomb
+  // Hamiltonian's term) ride along in the direct alpha pass as a diagonal
+  dev::OneBodyDiag diag{nullptr, nullptr, nullptr, nullptr, 0};
   std::vector<void*> bufs;
   HamAction() = default;
   HamAction(const HamAction&) = delete;
@@ -822,11 +825,43 @@ void prepare_one_body(ffx_plan_s& P, const double* h, HamAction& A) {
 
 void build_ham_action(ffx_plan_s& P, const DFHost& df, const double* h, DecompPool& pool, hipStream_t s,
                       HamAction& A) {
+  const int N = P.norb;
   prepare_one_body(P, h, A);
-  std::vector<Program> terms = df_term_programs(df, pool, P.norb);
+  // with the direct route, the terms in the orbital basis join its alpha pass
+  std::vector<char> folded((size_t)df.L + 1, 0);
+  if (A.direct) {
+    std::vector<double> Jsum((size_t)N * N, 0.0);
+    bool any = false;
+    for (int t = 1; t <= df.L; ++t) {
+      bool ident = true;
+      for (int i = 0; i < N && ident; ++i)
+        for (int j = 0; j < N; ++j)
+          if (df.U[t - 1][i * N + j] != (i == j ? cd(1.0, 0.0) : cd(0.0, 0.0))) {
+            ident = false;
+            break;
+          }
+      if (!ident) continue;
+      folded[t] = 1;
+      any = true;
+      for (int i = 0; i < N * N; ++i) Jsum[i] += df.J[t - 1][i];
+    }
+    if (any) {
+      // weight 1/2 (x_a + x_b)^T J (x_a + x_b) as per-string tables A, B and the cross table V
+      double* dJ = (double*)A.alloc((size_t)N * N * 8);
+      HIPCHK(hipMemcpy(dJ, Jsum.data(), (size_t)N * N * 8, hipMemcpyHostToDevice));
+      double* tA = (double*)A.alloc((size_t)P.dim[0] * 8);
+      double* tB = (double*)A.alloc((size_t)P.dim[1] * 8);
+      double* tV = (double*)A.alloc((size_t)N * P.dim[1] * 8);
+      dev::DiagSpecDev spec{nullptr, nullptr, dJ, dJ, dJ};
+      dev::diag_tables(P.d_masks[0], P.dim[0], P.d_masks[1], P.dim[1], N, spec, tA, tB, tV, s);
+      check_launch();
+      A.diag = dev::OneBodyDiag{tA, tB, tV, P.d_masks[0], N};
+    }
+  }
+  std::vector<Program> terms = df_term_programs(df, pool, N);
   Upload up(&P, s);
   for (int term = A.direct ? 1 : 0; term <= df.L; ++term)
-    A.cs.push_back(compile_program(P, up, terms[term], term == 0 ? FINAL_STORE : FINAL_ACCUM, s));
+    if (!folded[term]) A.cs.push_back(compile_program(P, up, terms[term], term == 0 ? FINAL_STORE : FINAL_ACCUM, s));
   up.commit();
 }
 
@@ -837,12 +872,13 @@ void apply_one_body_direct(ffx_plan_s& P, const HamAction& A, const void* in, vo
   // beta: on the transposed state, rows = beta configurations
   dev::transpose(P.c64, in, tmp, da, db, s);
   check_launch();
-  dev::onebody_rows(P.c64, tmp, out, nullptr, db, da, A.tab[1].off, A.tab[1].src, A.tab[1].coef, s);
+  const dev::OneBodyDiag none{nullptr, nullptr, nullptr, nullptr, 0};
+  dev::onebody_rows(P.c64, tmp, out, nullptr, db, da, A.tab[1].off, A.tab[1].src, A.tab[1].coef, none, s);
   check_launch();
   dev::transpose(P.c64, out, tmp, db, da, s);
   check_launch();
   // alpha, plus the beta part
-  dev::onebody_rows(P.c64, in, out, tmp, da, db, A.tab[0].off, A.tab[0].src, A.tab[0].coef, s);
+  dev::onebody_rows(P.c64, in, out, tmp, da, db, A.tab[0].off, A.tab[0].src, A.tab[0].coef, A.diag, s);
   check_launch();
 }
 

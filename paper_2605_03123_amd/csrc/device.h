@@ -99,10 +99,19 @@ int sample_state(bool c64, const void* vec, int64_t n, double* bs, double* pre, 
 void dpp_sample(const double* Q, int N, int eta, const double* u, int64_t n_samples, uint64_t* masks,
                 hipStream_t stream);
 
-// dst[j, :] = sum_{e in [off[j], off[j+1])} coef[e] * src[srow[e], :] (+ add[j, :]); dst must not
-// alias src (add may alias dst)
+// optional diagonal term of onebody_rows: w(j, col) = A[j] + B[col] + sum_{p in rmasks[j]} V[p * cols + col]
+struct OneBodyDiag {
+  const double* A;
+  const double* B;
+  const double* V;
+  const uint32_t* rmasks;
+  int norb;
+};
+// dst[j, :] = sum_{e in [off[j], off[j+1])} coef[e] * src[srow[e], :] (+ w(j, :) src[j, :] when dg.A)
+// (+ add[j, :]); dst must not alias src (add may alias dst)
 void onebody_rows(bool c64, const void* src, void* dst, const void* add, int64_t rows, int64_t cols,
-                  const int64_t* off, const int32_t* srow, const double* coef, hipStream_t stream);
+                  const int64_t* off, const int32_t* srow, const double* coef, const OneBodyDiag& dg,
+                  hipStream_t stream);
 // y += x
 void axpy(bool c64, const void* x, void* y, int64_t n, hipStream_t stream);
 // vec[i_a, i_b] = a[i_a] * b[i_b] (a, b complex double)

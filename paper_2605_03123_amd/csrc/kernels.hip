@@ -590,13 +590,15 @@ void dist2(bool c64, const void* x, const void* y, int64_t n, double* partials, 
 // One block per (row j, tile of 2048 columns); the entries of row j are the
 // same for the whole block.  FP64 accumulation, one rounding to the state type.
 constexpr int kOneBodyPer = 8;
+// With dg.A set, the diagonal term w(j, col) src[j, col] is added too, w = A[j] + B[col] +
+// sum_{p in row string j} V[p][col] (the tables of a diagonal weight, k_diag_tables).
 template <class R>
 __global__ __launch_bounds__(256) void k_onebody_rows(const typename V2T<R>::type* __restrict__ src,
                                                       typename V2T<R>::type* dst,
                                                       const typename V2T<R>::type* add, int64_t rows,
                                                       int64_t cols, int64_t tiles, const int64_t* __restrict__ off,
                                                       const int32_t* __restrict__ srow,
-                                                      const double* __restrict__ coef) {
+                                                      const double* __restrict__ coef, OneBodyDiag dg) {
   const int64_t j = (int64_t)blockIdx.x / tiles;
   const int64_t c0 = ((int64_t)blockIdx.x % tiles) * (256 * kOneBodyPer) + threadIdx.x;
   if (j >= rows) return;
@@ -614,6 +616,22 @@ __global__ __launch_bounds__(256) void k_onebody_rows(const typename V2T<R>::typ
         const auto v = sp[col];
         ar[k] += c * (double)v.x;
         ai[k] += c * (double)v.y;
+      }
+    }
+  }
+  if (dg.A) {
+    const double wa = dg.A[j];
+    const uint32_t m = dg.rmasks[j];
+#pragma unroll
+    for (int k = 0; k < kOneBodyPer; ++k) {
+      const int64_t col = c0 + 256 * k;
+      if (col < cols) {
+        double w = wa + dg.B[col];
+        for (int p = 0; p < dg.norb; ++p)
+          if ((m >> p) & 1) w += dg.V[(int64_t)p * cols + col];
+        const auto v = src[j * cols + col];
+        ar[k] += w * (double)v.x;
+        ai[k] += w * (double)v.y;
       }
     }
   }
@@ -636,16 +654,16 @@ __global__ __launch_bounds__(256) void k_onebody_rows(const typename V2T<R>::typ
 }
 
 void onebody_rows(bool c64, const void* src, void* dst, const void* add, int64_t rows, int64_t cols,
-                  const int64_t* off, const int32_t* srow, const double* coef, hipStream_t s) {
+                  const int64_t* off, const int32_t* srow, const double* coef, const OneBodyDiag& dg, hipStream_t s) {
   if (rows <= 0 || cols <= 0) return;
   const int64_t tiles = (cols + 256 * kOneBodyPer - 1) / (256 * kOneBodyPer);
   const dim3 g((unsigned)(rows * tiles));
   if (c64)
     hipLaunchKernelGGL(k_onebody_rows<float>, g, dim3(256), 0, s, (const zc64*)src, (zc64*)dst, (const zc64*)add,
-                       rows, cols, tiles, off, srow, coef);
+                       rows, cols, tiles, off, srow, coef, dg);
   else
     hipLaunchKernelGGL(k_onebody_rows<double>, g, dim3(256), 0, s, (const zc128*)src, (zc128*)dst,
-                       (const zc128*)add, rows, cols, tiles, off, srow, coef);
+                       (const zc128*)add, rows, cols, tiles, off, srow, coef, dg);
 }
 
 template <class R>

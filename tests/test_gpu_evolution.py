@@ -214,3 +214,22 @@ def test_trotter_study_against_oracle(ffx):
     for key, v in errs.items():
         assert abs(res[key][0] - np.mean(v)) <= 1e-9
         assert abs(res[key][1] - np.std(v)) <= 1e-9
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_hamiltonian_action_identity_basis_terms(ffx, monkeypatch, dtype):
+    """Two-body terms whose basis is the identity join the direct one-body pass as a diagonal; mixed with
+    a rotated term, and with the route forced both ways."""
+    norb, nelec = 9, (4, 3)
+    r = synth.rng(48)
+    eye = np.eye(norb, dtype=np.complex128)
+    ham = synth.DFHamiltonian(h=synth.random_symmetric(r, norb, 1.0),
+                              J=np.array([synth.random_symmetric(r, norb, 0.5) for _ in range(3)]),
+                              U=np.array([eye, synth.random_orthogonal(r, norb).astype(np.complex128), eye]))
+    vec = _to_dev(synth.random_state(r, *_dims(norb, nelec)), dtype)
+    x = _host(vec)
+    ref = oh.apply_df_hamiltonian(x, ham, norb, nelec)
+    for mode in ("direct", "rot"):
+        monkeypatch.setenv("FFX_ONEBODY", mode)
+        out = ffx.apply_df_hamiltonian(vec, ham, norb, nelec)
+        assert _maxdiff(out, ref) <= HTOL[dtype] * max(1.0, float(np.abs(ref).max())), mode

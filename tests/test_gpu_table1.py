@@ -141,3 +141,23 @@ def test_diagonal_gates_in_a_rotated_basis(ffx, dtype, norb, nelec):
     ref = og.apply_in_basis(x, B, lambda v: og.apply_diag_coulomb_evolution(v, J, 0.4, norb, nelec, J_ab=Jab),
                             norb, nelec)
     assert _maxdiff(out, ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_large_orbital_counts(ffx, dtype):
+    """UCJ, Slater state and quadratic-Hamiltonian evolution above 16 orbitals (three and four mask bytes)."""
+    r = synth.rng(66)
+    norb, nelec = 20, (3, 2)
+    Ua, Ub = synth.random_unitary(r, norb), synth.random_unitary(r, norb)
+    J = synth.random_symmetric(r, norb, 0.3)
+    out = ffx.apply_ucj(norb, nelec, Ua[None], J[None], U_b=Ub[None], dtype=dtype)
+    assert _maxdiff(out, og.apply_ucj(norb, nelec, [Ua], [J], U_b=[Ub])) <= TOL[dtype]
+    norb, nelec = 32, (2, 2)
+    U = synth.random_unitary(r, norb)
+    out = ffx.slater_determinant(norb, nelec, occ_a=[31, 5], occ_b=[0, 16], U=U, dtype=dtype)
+    assert _maxdiff(out, og.slater_determinant(norb, nelec, [31, 5], [0, 16], U)) <= TOL[dtype]
+    norb, nelec = 24, (2, 1)
+    vec = _to_dev(synth.random_state(r, *_dims(norb, nelec)), dtype)
+    M = synth.random_hermitian(r, norb, 0.5)
+    out = ffx.apply_quad_ham_evolution(vec, M, 0.7, norb, nelec)
+    assert _maxdiff(out, og.apply_quad_ham_evolution(_host(vec), M, 0.7, norb, nelec)) <= TOL[dtype]

@@ -11,6 +11,8 @@ Whole oracle states do not fit these sizes, so the checks are:
     single-gate entry points (reversibility over the whole state);
   * two DF steps at norb = 14 (7, 7) from Hartree-Fock against stored oracle
     amplitudes (tests/golden/df_trotter_n14.txt);
+  * the DF energy at norb = 16 (8, 8), L = 16, of a rotated Hartree-Fock state
+    against Wick's theorem on its one-body densities (real and complex U_t);
   * the LUCJ adjoint gradient at norb = 16 (8, 8) against central differences
     of GPU energies on sampled parameters, and complex64 against complex128;
   * the 4 x 8 Hubbard model at norb = 32 (4, 4): sampled amplitudes of the
@@ -239,3 +241,41 @@ def test_hubbard_4x8_action_and_exact_evolution(ffx):
     assert abs(ffx.df_energy(ex, ham, norb, nelec) - e_rot) <= 1e-9 * max(1.0, abs(e_rot))
     ffx.evolve_exact(ex, ham, -1.0, norb, nelec, out=ex)
     assert float(torch.max(torch.abs(ex - vec))) <= 1e-9
+
+
+def _slater_energy_wick(W, nelec, ham):
+    """<Phi|H|Phi> for Phi = U(W)|HF> from its one-body densities (Wick's theorem):
+    <a^dag_p a_q> = (W P W^dag)_qp per spin, and per DF term the densities in the
+    term's basis (b^dag_p = sum_i U_ip a^dag_i) give <n_p n_q> = o_p o_q + delta_pq o_p
+    - D_pq D_qp within one spin and o_p o_q across spins."""
+    norb = W.shape[0]
+    D = []
+    for n in nelec:
+        P = np.diag([1.0] * n + [0.0] * (norb - n))
+        D.append((W @ P @ W.conj().T).T)
+    E = sum(np.sum(ham.h * Ds) for Ds in D)
+    for J, U in zip(ham.J, ham.U):
+        Dr = [U.T @ Ds @ U.conj() for Ds in D]
+        occ = [np.real(np.diag(x)) for x in Dr]
+        o = occ[0] + occ[1]
+        E += 0.5 * (o @ J @ o)
+        for s in (0, 1):
+            E += 0.5 * (np.sum(np.diag(J) * occ[s]) - np.sum(J * Dr[s] * Dr[s].T))
+    return float(np.real(E))
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("complex_u", [False, True])
+def test_df_energy_slater_wick_n16(ffx, dtype, complex_u):
+    """DF energy at norb = 16 (8, 8), L = 16 of a rotated Hartree-Fock state against Wick's theorem."""
+    norb, nelec = 16, (8, 8)
+    print(f"DF energy (Wick) n16 complex_u={complex_u} {dtype}", flush=True)
+    r = synth.rng([91, int(complex_u)])
+    ham = synth.df_hamiltonian(r, norb, norb)
+    if complex_u:
+        ham.U = np.array([synth.random_unitary(r, norb) for _ in range(norb)])
+    W = synth.random_unitary(r, norb)
+    vec = ffx.slater_determinant(norb, nelec, U=W, dtype=dtype)
+    ref = _slater_energy_wick(W, nelec, ham)
+    e = ffx.df_energy(vec, ham, norb, nelec)
+    assert abs(e - ref) <= (1e-10 if dtype == torch.complex128 else 1e-5) * max(1.0, abs(ref)), (e, ref)

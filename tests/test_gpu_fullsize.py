@@ -13,6 +13,9 @@ Whole oracle states do not fit these sizes, so the checks are:
     amplitudes (tests/golden/df_trotter_n14.txt);
   * the DF energy at norb = 16 (8, 8), L = 16, of a rotated Hartree-Fock state
     against Wick's theorem on its one-body densities (real and complex U_t);
+  * the DF-chain adjoint gradient at norb = 16 (8, 8), L = 16 against central
+    differences of GPU energies (one derivative each of h, J_t, Re and Im of
+    the U_t generator);
   * the LUCJ adjoint gradient at norb = 16 (8, 8) against central differences
     of GPU energies on sampled parameters, and complex64 against complex128;
   * the 4 x 8 Hubbard model at norb = 32 (4, 4): sampled amplitudes of the
@@ -25,6 +28,7 @@ import os
 
 import numpy as np
 import pytest
+import scipy.linalg
 import torch
 
 from oracle import gates as og
@@ -279,3 +283,48 @@ def test_df_energy_slater_wick_n16(ffx, dtype, complex_u):
     ref = _slater_energy_wick(W, nelec, ham)
     e = ffx.df_energy(vec, ham, norb, nelec)
     assert abs(e - ref) <= (1e-10 if dtype == torch.complex128 else 1e-5) * max(1.0, abs(ref)), (e, ref)
+
+
+def test_df_chain_gradient_n16_matches_central_differences(ffx):
+    """The DF-chain adjoint gradient at norb = 16 (8, 8), L = 16 (one S_0 step of the benchmark's
+    Hamiltonian, an L = 2 observable) against central differences of GPU energies, one sampled
+    derivative of each kind: h, J_t and the real and imaginary generator parts of U_t."""
+    norb, nelec, dt = 16, (8, 8), 0.1
+    print("DF chain gradient n16 against central differences", flush=True)
+    r = synth.rng(92)
+    ham = synth.df_hamiltonian(r, norb, norb)
+    obs = synth.df_hamiltonian(r, norb, 2)
+    plan = ffx.get_plan(norb, nelec, torch.complex128, 0)
+    vec0 = _device_state(plan.dim_a, torch.complex128, 93)
+    e, g = ffx.df_chain_energy_grad(vec0, ham, obs, dt, 1, norb, nelec, plan=plan)
+    psi = torch.empty_like(vec0)
+
+    def energy(hm):
+        ffx.simulate_trotter_double_factorized(vec0, hm, dt, norb, nelec, n_steps=1, order=0, out=psi, plan=plan)
+        return ffx.df_energy(psi, obs, norb, nelec, plan=plan)
+
+    def with_(**kw):
+        return synth.DFHamiltonian(h=kw.get("h", ham.h), J=kw.get("J", ham.J), U=kw.get("U", ham.U))
+
+    assert abs(energy(ham) - e) <= 1e-10 * max(1.0, abs(e))
+    step = 1e-5
+    scale = max(1.0, max(float(np.max(np.abs(v))) for v in g.values()))
+    p, q, t = 3, 11, 7
+    M = np.zeros((norb, norb))
+    M[p, q] = M[q, p] = 1.0
+    checks = [(g["h"][p, q], with_(h=ham.h + step * M), with_(h=ham.h - step * M))]
+    Jp, Jm = ham.J.copy(), ham.J.copy()
+    Jp[t] += step * M
+    Jm[t] -= step * M
+    checks.append((g["J"][t, p, q], with_(J=Jp), with_(J=Jm)))
+    for part in (0, 1):
+        A = np.zeros((norb, norb), dtype=complex)
+        A[p, q] = step if part == 0 else 1j * step
+        K = A - A.conj().T
+        Up, Um = ham.U.copy(), ham.U.copy()
+        Up[t] = Up[t] @ scipy.linalg.expm(K)
+        Um[t] = Um[t] @ scipy.linalg.expm(-K)
+        checks.append((g["U"][t, part, p, q], with_(U=Up), with_(U=Um)))
+    for k, (gk, hp, hm) in enumerate(checks):
+        fd = (energy(hp) - energy(hm)) / (2 * step)
+        assert abs(fd - gk) <= 1e-7 * scale, (k, fd, gk)

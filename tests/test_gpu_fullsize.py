@@ -9,6 +9,8 @@ Whole oracle states do not fit these sizes, so the checks are:
     the oracle evaluates pointwise (sampled, same tolerances);
   * a full random DF step followed by its exact inverse built from the
     single-gate entry points (reversibility over the whole state);
+  * the symmetric formulas S_1 and S_2 at norb = 16 (8, 8): S_k(-dt) S_k(dt)
+    returns the start state (reversibility over the whole state);
   * two DF steps at norb = 14 (7, 7) from Hartree-Fock against stored oracle
     amplitudes (tests/golden/df_trotter_n14.txt);
   * the DF energy at norb = 16 (8, 8), L = 16, of a rotated Hartree-Fock state
@@ -328,3 +330,21 @@ def test_df_chain_gradient_n16_matches_central_differences(ffx):
     for k, (gk, hp, hm) in enumerate(checks):
         fd = (energy(hp) - energy(hm)) / (2 * step)
         assert abs(fd - gk) <= 1e-7 * scale, (k, fd, gk)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("order", [1, 2])
+def test_symmetric_formulas_reversible_n16(ffx, dtype, order):
+    """S_1 and S_2 are symmetric products (Sec. 4.5.3), so S_k(-dt) S_k(dt) is the identity exactly:
+    at norb = 16 (8, 8), L = 16 the round trip returns the start state over the whole vector."""
+    norb, nelec, dt = 16, (8, 8), 0.1
+    print(f"S_{order} round trip n16 {dtype}", flush=True)
+    w = synth.workload_df_trotter(norb, 16, seed=0, start="hf", dt=dt)
+    plan = ffx.get_plan(norb, nelec, dtype, 0)
+    x0 = _device_state(plan.dim_a, dtype, 19 + order)
+    x = ffx.simulate_trotter_double_factorized(x0, w.data["ham"], dt, norb, nelec, n_steps=1, order=order, plan=plan)
+    moved = torch.max(torch.abs(x - x0)).item()
+    ffx.simulate_trotter_double_factorized(x, w.data["ham"], -dt, norb, nelec, n_steps=1, order=order, out=x, plan=plan)
+    err = torch.max(torch.abs((x - x0).to(torch.complex128))).item()
+    assert moved > 1e-4
+    assert err <= (1e-12 if dtype == torch.complex128 else 1e-5)

@@ -489,6 +489,8 @@ def main():
     ap.add_argument("--no-n18", action="store_true")
     ap.add_argument("--hubbard-y", type=int, default=8, help="lattice 4 x y of the Trotter-error leg")
     ap.add_argument("--hubbard-only", action="store_true", help="run only the Trotter-error leg (for profiling)")
+    ap.add_argument("--table1-only", action="store_true",
+                    help="run only the Table 1 gates and sampling leg (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -505,6 +507,9 @@ def main():
 
     if args.hubbard_only:
         print(json.dumps({"trotter_error_hubbard": hubbard_timing(ffx, torch, synth, 4, args.hubbard_y)}), flush=True)
+        return
+    if args.table1_only:
+        print(json.dumps({"table1_gates_n16_c128": table1_timing(ffx, torch, synth)}), flush=True)
         return
 
     types = {"c128": torch.complex128, "c64": torch.complex64}

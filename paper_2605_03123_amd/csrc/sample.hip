@@ -22,20 +22,27 @@ constexpr int kSampleBlock = 256 * kSampleChunk;  // amplitudes per block
 
 int sample_blocks(int64_t n) { return (int)((n + kSampleBlock - 1) / kSampleBlock); }
 
-// bs[b] = sum |gamma|^2 over block b: thread t sums its 16 consecutive amplitudes
-// in address order, then the fixed tree of block_sum256
+// bs[b] = sum |gamma|^2 over block b (addresses b * 4096 .. + 4096): thread t
+// sums addresses t, t + 256, ..., t + 15 * 256 of the block in that order (so
+// that each load instruction of a wave reads consecutive amplitudes), then the
+// fixed tree of block_sum256
 template <class R>
 __global__ __launch_bounds__(256) void k_block_norm2(const typename V2T<R>::type* __restrict__ v, int64_t n,
                                                      double* __restrict__ bs) {
+  using V = typename V2T<R>::type;
   __shared__ double sh[4];
-  const int64_t base = (int64_t)blockIdx.x * kSampleBlock + (int64_t)threadIdx.x * kSampleChunk;
-  double acc = 0;
+  const int64_t base = (int64_t)blockIdx.x * kSampleBlock + threadIdx.x;
+  V x[kSampleChunk];
+#pragma unroll
   for (int k = 0; k < kSampleChunk; ++k) {
-    const int64_t i = base + k;
-    if (i < n) {
-      const double re = v[i].x, im = v[i].y;
-      acc += re * re + im * im;
-    }
+    const int64_t i = base + (int64_t)k * 256;
+    x[k] = i < n ? v[i] : V{R(0), R(0)};
+  }
+  double acc = 0;
+#pragma unroll
+  for (int k = 0; k < kSampleChunk; ++k) {
+    const double re = x[k].x, im = x[k].y;
+    acc += re * re + im * im;
   }
   const double t = block_sum256(acc, sh);
   if (threadIdx.x == 0) bs[blockIdx.x] = t;

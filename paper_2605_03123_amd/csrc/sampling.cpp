@@ -48,17 +48,18 @@ int ffx_sample_state(ffx_plan plan, const void* vec, const double* u, int64_t n_
     if ((int64_t)2 * nb > P.n_partials) throw Error(FFX_EDEVICE, "partial-sum buffer too small");
     double* bs = P.partials;
     double* pre = P.partials + nb;
-    dev::sample_state(P.c64, vec, n, bs, pre, nullptr, 0, nullptr, s);
+    // block sums, their prefix and the searches in one sequence; the total is
+    // checked before any sample is handed back (the searches read only inside
+    // the state and the prefix whatever the total is)
+    DevBuf du((size_t)n_samples * 8), dout((size_t)n_samples * 8);
+    if (n_samples > 0) HIPCHK(hipMemcpyAsync(du.p, u, (size_t)n_samples * 8, hipMemcpyHostToDevice, s));
+    dev::sample_state(P.c64, vec, n, bs, pre, (const double*)du.p, n_samples, (int64_t*)dout.p, s);
     check_launch();
     double total = 0;
     HIPCHK(hipMemcpyAsync(&total, pre + nb - 1, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (!(total > 0.0) || !std::isfinite(total)) throw Error(FFX_EINVAL, "state has no finite nonzero norm");
     if (n_samples == 0) return;
-    DevBuf du((size_t)n_samples * 8), dout((size_t)n_samples * 8);
-    HIPCHK(hipMemcpyAsync(du.p, u, (size_t)n_samples * 8, hipMemcpyHostToDevice, s));
-    dev::sample_state(P.c64, vec, n, bs, pre, (const double*)du.p, n_samples, (int64_t*)dout.p, s);
-    check_launch();
     HIPCHK(hipMemcpyAsync(out, dout.p, (size_t)n_samples * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
   });

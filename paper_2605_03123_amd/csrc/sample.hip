@@ -17,15 +17,15 @@ namespace ffx {
 namespace dev {
 
 constexpr int64_t kNone = 0x7fffffffffffffffLL;
-constexpr int kSampleChunk = 16;                  // consecutive amplitudes per thread
-constexpr int kSampleBlock = 256 * kSampleChunk;  // amplitudes per block
+constexpr int kSampleChunk = 4;                   // amplitudes per thread
+constexpr int kSampleBlock = 256 * kSampleChunk;  // amplitudes per block (16 KB of complex128 read per sample)
 
 int sample_blocks(int64_t n) { return (int)((n + kSampleBlock - 1) / kSampleBlock); }
 
-// bs[b] = sum |gamma|^2 over block b (addresses b * 4096 .. + 4096): thread t
-// sums addresses t, t + 256, ..., t + 15 * 256 of the block in that order (so
-// that each load instruction of a wave reads consecutive amplitudes), then the
-// fixed tree of block_sum256
+// bs[b] = sum |gamma|^2 over block b (kSampleBlock addresses from b *
+// kSampleBlock): thread t sums addresses t, t + 256, t + 2 * 256, ... of the
+// block in that order (so that each load instruction of a wave reads
+// consecutive amplitudes), then the fixed tree of block_sum256
 template <class R>
 __global__ __launch_bounds__(256) void k_block_norm2(const typename V2T<R>::type* __restrict__ v, int64_t n,
                                                      double* __restrict__ bs) {
@@ -49,16 +49,26 @@ __global__ __launch_bounds__(256) void k_block_norm2(const typename V2T<R>::type
 }
 
 // inclusive prefix of bs[0..nb) into pre, one block of 1024 threads: each
-// thread scans a contiguous chunk, thread 0 scans the chunk totals in order
+// thread scans a contiguous chunk, thread 0 scans the chunk totals in order.
+// A thread's loads are requested 16 at a time (indexes clamped into its chunk,
+// so no load waits behind a branch) before the sequential additions use them.
 __global__ __launch_bounds__(1024) void k_scan_blocks(const double* __restrict__ bs, int nb,
                                                       double* __restrict__ pre) {
   __shared__ double tot[1024];
+  constexpr int B = 16;
   const int c = (nb + 1023) / 1024;
-  const int lo = threadIdx.x * c, hi = min(nb, lo + c);
+  const int lo = min((int)threadIdx.x * c, nb), hi = min(nb, lo + c);
   double run = 0;
-  for (int i = lo; i < hi; ++i) {
-    run += bs[i];
-    pre[i] = run;
+  for (int i0 = lo; i0 < hi; i0 += B) {
+    double x[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) x[k] = bs[min(i0 + k, hi - 1)];
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+      if (i0 + k < hi) {
+        run += x[k];
+        pre[i0 + k] = run;
+      }
   }
   tot[threadIdx.x] = run;
   __syncthreads();
@@ -72,44 +82,63 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(const double* __restrict__
   }
   __syncthreads();
   const double off = tot[threadIdx.x];
-  for (int i = lo; i < hi; ++i) pre[i] += off;
+  for (int i0 = lo; i0 < hi; i0 += B) {
+    double x[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) x[k] = pre[min(i0 + k, hi - 1)];
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+      if (i0 + k < hi) pre[i0 + k] = x[k] + off;
+  }
 }
 
 // One block per sample: the first address whose cumulative probability exceeds
 // u * total (zero-probability addresses are never chosen; when rounding leaves
 // the target at or past the block's own total, the block's last address with
 // nonzero probability).
+//   * Block search: the first b with pre[b] > target (else nb - 1), by rounds
+//     in which the 256 threads test 256 evenly spaced entries of the remaining
+//     range at once (pre never decreases, so the entries that fail form a
+//     prefix; their count narrows the range 256-fold per round).
+//   * In-block search: thread t sums its kSampleChunk consecutive amplitudes; the
+//     exclusive prefix of those sums in thread order comes from a shuffle scan
+//     within each wave plus the totals of the waves before it (a fixed order);
+//     then each thread walks its own amplitudes.
 template <class R>
 __global__ __launch_bounds__(256) void k_sample_search(const typename V2T<R>::type* __restrict__ v, int64_t n,
                                                        const double* __restrict__ pre, int nb,
                                                        const double* __restrict__ u, int64_t n_samples,
                                                        int64_t* __restrict__ out) {
-  __shared__ double part[256];
+  __shared__ double wtot[4];
   __shared__ int64_t sel[2];
-  __shared__ int blk;
   const int64_t s = blockIdx.x;
   if (s >= n_samples) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double total = pre[nb - 1];
   const double target = u[s] * total;
-  if (threadIdx.x == 0) {
-    int lo = 0, hi = nb - 1;  // first b with pre[b] > target, else nb - 1
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (pre[mid] > target)
-        hi = mid;
-      else
-        lo = mid + 1;
-    }
-    blk = lo;
+  if (tid == 0) {
     sel[0] = kNone;  // first qualifying address
-    sel[1] = -1;         // last address with nonzero probability
+    sel[1] = -1;     // last address with nonzero probability
   }
-  __syncthreads();
-  const int b = blk;
+  int lo = 0, hi = nb - 1;  // the answer lies in [lo, hi]
+  while (lo < hi) {
+    const int step = (hi - lo + 256) / 256;  // ceil((hi - lo + 1) / 256)
+    const int i = min(lo + (tid + 1) * step - 1, hi);
+    const int c = __syncthreads_count(!(pre[i] > target));  // entries tested that fail
+    if (c == 256) {
+      lo = hi;  // every tested entry fails, hi among them: the answer is hi
+    } else {
+      const int nlo = c == 0 ? lo : min(lo + c * step - 1, hi) + 1;
+      hi = min(lo + (c + 1) * step - 1, hi);
+      lo = nlo;
+    }
+  }
+  const int b = lo;
   const double t2 = target - (b > 0 ? pre[b - 1] : 0.0);
-  const int64_t base = (int64_t)b * kSampleBlock + (int64_t)threadIdx.x * kSampleChunk;
+  const int64_t base = (int64_t)b * kSampleBlock + (int64_t)tid * kSampleChunk;
   double w[kSampleChunk];
   double acc = 0;
+#pragma unroll
   for (int k = 0; k < kSampleChunk; ++k) {
     const int64_t i = base + k;
     double p = 0;
@@ -120,19 +149,21 @@ __global__ __launch_bounds__(256) void k_sample_search(const typename V2T<R>::ty
     w[k] = p;
     acc += p;
   }
-  part[threadIdx.x] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double run = 0;
-    for (int t = 0; t < 256; ++t) {
-      const double x = part[t];
-      part[t] = run;
-      run += x;
-    }
+  // inclusive scan of the thread sums within the wave
+  double inc = acc;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
   }
+  if (lane == 63) wtot[wave] = inc;
+  const double excl = __shfl_up(inc, 1);
   __syncthreads();
-  double cum = part[threadIdx.x];
+  double cum = 0;
+  for (int q = 0; q < wave; ++q) cum += wtot[q];
+  if (lane > 0) cum += excl;
   int64_t first = kNone, last = -1;
+#pragma unroll
   for (int k = 0; k < kSampleChunk; ++k) {
     if (w[k] > 0) {
       cum += w[k];
@@ -143,7 +174,7 @@ __global__ __launch_bounds__(256) void k_sample_search(const typename V2T<R>::ty
   if (first != kNone) atomicMin((unsigned long long*)&sel[0], (unsigned long long)first);
   if (last >= 0) atomicMax((long long*)&sel[1], (long long)last);
   __syncthreads();
-  if (threadIdx.x == 0) out[s] = sel[0] != kNone ? sel[0] : sel[1];
+  if (tid == 0) out[s] = sel[0] != kNone ? sel[0] : sel[1];
 }
 
 int sample_state(bool c64, const void* vec, int64_t n, double* bs, double* pre, const double* u, int64_t n_samples,

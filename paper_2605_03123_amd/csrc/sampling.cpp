@@ -45,9 +45,9 @@ int ffx_sample_state(ffx_plan plan, const void* vec, const double* u, int64_t n_
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = P.elems();
     const int nb = dev::sample_blocks(n);
-    if ((int64_t)2 * nb > P.n_partials) throw Error(FFX_EDEVICE, "partial-sum buffer too small");
-    double* bs = P.partials;
-    double* pre = P.partials + nb;
+    DevBuf sums((size_t)2 * nb * 8);  // block sums and their prefix
+    double* bs = (double*)sums.p;
+    double* pre = bs + nb;
     // block sums, their prefix and the searches in one sequence; the total is
     // checked before any sample is handed back (the searches read only inside
     // the state and the prefix whatever the total is)

@@ -204,21 +204,30 @@ int sample_state(bool c64, const void* vec, int64_t n, double* bs, double* pre, 
 // cumulative r (in orbital order) exceeds u_k * sum r; the new basis vector is
 // the chosen row minus its projections, normalised; every lane then removes
 // its overlap with it.
+// LDS (dynamic, sized by N and eta): Q (N x eta), then per wave the basis
+// (eta x eta) and the overlaps <e_i, q_j> (N x eta, at [j][i]); up to
+// kDppWaves waves per block, fewer where the arrays would pass 64 KB.
 // ---------------------------------------------------------------------------
-constexpr int kDppWaves = 2;
+constexpr int kDppWaves = 4;
+constexpr size_t kDppLdsCap = 64 * 1024;
+
+static size_t dpp_wave_doubles(int N, int eta) { return (size_t)2 * eta * eta + (size_t)2 * N * eta; }
 
 __global__ __launch_bounds__(64 * kDppWaves) void k_dpp_sample(const double* __restrict__ Q, int N, int eta,
                                                                  const double* __restrict__ u, int64_t n_samples,
                                                                  uint64_t* __restrict__ masks) {
-  __shared__ double q[32 * 32 * 2];
-  __shared__ double e[kDppWaves][32 * 32 * 2];
-  __shared__ double coef[kDppWaves][32 * 32 * 2];  // <e_i, q_j> at [j][i]
+  extern __shared__ double dsm[];
   __shared__ double rr[kDppWaves][32];
   __shared__ int pick[kDppWaves];
-  for (int i = threadIdx.x; i < N * eta * 2; i += blockDim.x) q[i] = Q[i];
+  const int nq = N * eta * 2;
+  double* q = dsm;
+  for (int i = threadIdx.x; i < nq; i += blockDim.x) q[i] = Q[i];
   __syncthreads();
+  const int waves = blockDim.x >> 6;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t smp = (int64_t)blockIdx.x * kDppWaves + wv;
+  double* e = dsm + nq + (size_t)wv * (2 * eta * eta + nq);  // e_i component c at [i][c]
+  double* coef = e + 2 * eta * eta;                            // <e_i, q_j> at [j][i]
+  const int64_t smp = (int64_t)blockIdx.x * waves + wv;
   if (smp >= n_samples) return;  // whole waves leave together; no block barrier follows
   double r = 0;
   if (lane < N)
@@ -258,26 +267,26 @@ __global__ __launch_bounds__(64 * kDppWaves) void k_dpp_sample(const double* __r
     if (lane < eta) {
       double vr = q[(js * eta + lane) * 2], vi = q[(js * eta + lane) * 2 + 1];
       for (int i = 0; i < k; ++i) {
-        const double cr = coef[wv][(js * 32 + i) * 2], ci = coef[wv][(js * 32 + i) * 2 + 1];
-        const double er = e[wv][(i * 32 + lane) * 2], ei = e[wv][(i * 32 + lane) * 2 + 1];
+        const double cr = coef[(js * eta + i) * 2], ci = coef[(js * eta + i) * 2 + 1];
+        const double er = e[(i * eta + lane) * 2], ei = e[(i * eta + lane) * 2 + 1];
         vr -= cr * er - ci * ei;
         vi -= cr * ei + ci * er;
       }
-      e[wv][(k * 32 + lane) * 2] = vr * inv;
-      e[wv][(k * 32 + lane) * 2 + 1] = vi * inv;
+      e[(k * eta + lane) * 2] = vr * inv;
+      e[(k * eta + lane) * 2 + 1] = vi * inv;
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     if (lane < N) {
       double cr = 0, ci = 0;  // <e_k, q_lane> = sum conj(e) q
       for (int c = 0; c < eta; ++c) {
-        const double er = e[wv][(k * 32 + c) * 2], ei = e[wv][(k * 32 + c) * 2 + 1];
+        const double er = e[(k * eta + c) * 2], ei = e[(k * eta + c) * 2 + 1];
         const double a = q[(lane * eta + c) * 2], bi = q[(lane * eta + c) * 2 + 1];
         cr += er * a + ei * bi;
         ci += er * bi - ei * a;
       }
-      coef[wv][(lane * 32 + k) * 2] = cr;
-      coef[wv][(lane * 32 + k) * 2 + 1] = ci;
+      coef[(lane * eta + k) * 2] = cr;
+      coef[(lane * eta + k) * 2 + 1] = ci;
       r -= cr * cr + ci * ci;
     }
     __builtin_amdgcn_wave_barrier();
@@ -289,8 +298,12 @@ __global__ __launch_bounds__(64 * kDppWaves) void k_dpp_sample(const double* __r
 void dpp_sample(const double* Q, int N, int eta, const double* u, int64_t n_samples, uint64_t* masks,
                 hipStream_t s) {
   if (n_samples <= 0) return;
-  const dim3 g((unsigned)((n_samples + kDppWaves - 1) / kDppWaves));
-  hipLaunchKernelGGL(k_dpp_sample, g, dim3(64 * kDppWaves), 0, s, Q, N, eta, u, n_samples, masks);
+  const size_t qd = (size_t)2 * N * eta, wd = dpp_wave_doubles(N, eta);
+  int waves = kDppWaves;
+  while (waves > 1 && (qd + waves * wd) * sizeof(double) > kDppLdsCap) --waves;
+  const size_t lds = (qd + waves * wd) * sizeof(double);  // at most 48 KB at N = eta = 32
+  const dim3 g((unsigned)((n_samples + waves - 1) / waves));
+  hipLaunchKernelGGL(k_dpp_sample, g, dim3(64 * waves), lds, s, Q, N, eta, u, n_samples, masks);
 }
 
 }  // namespace dev

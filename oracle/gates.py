@@ -15,27 +15,78 @@ from . import strings as st
 # Orbital rotation (Sec. 2.3 and Table 1)
 # ---------------------------------------------------------------------------
 
-def compound_matrix(U: np.ndarray, n: int, chunk: int = 256) -> np.ndarray:
+_WORKERS = 1
+
+
+def set_workers(n: int) -> None:
+    """Spread the rows of large compound matrices over n forked processes (1 = in this process).
+
+    Only the scheduling changes: every entry is the same determinant either way.
+    """
+    global _WORKERS
+    _WORKERS = max(1, int(n))
+
+
+def compound_matrix(U: np.ndarray, n: int, chunk: int | None = None) -> np.ndarray:
     """C_n(U)[J, I] = det U[J, I] over n-subsets J (rows) and I (columns), ascending addresses.
 
     From the defining relation of an orbital rotation, script-U a^dag_p
     script-U^dag = sum_q U_qp a^dag_q (Sec. 2.3): applying it to
     cre(I)|vac> = a^dag_{i_n}...a^dag_{i_1}|vac> and collecting the ordered
     products gives sum_J det(U[J, I]) |J>, i.e. column I of C_n(U).
-    C_0(U) = [[1]].
+    C_0(U) = [[1]].  A real U (no nonzero imaginary part) gives a real matrix,
+    its determinants taken in float64.
     """
     norb = U.shape[0]
     occ = st.occupied_lists(norb, n)
     d = len(occ)
+    U = np.asarray(U)
+    real = not np.iscomplexobj(U) or not np.any(U.imag)
+    dtype = np.float64 if real else np.complex128
+    U = np.ascontiguousarray(U.real if real else U, dtype=dtype)
     if n == 0:
-        return np.ones((1, 1), dtype=np.complex128)
-    out = np.empty((d, d), dtype=np.complex128)
-    for j0 in range(0, d, chunk):
-        rows = occ[j0:j0 + chunk]                       # (c, n)
-        # minors[a, b] = U[rows[a]][:, occ[b]]  -> shape (c, d, n, n)
-        sub = U[rows[:, None, :, None], occ[None, :, None, :]]
-        out[j0:j0 + chunk] = np.linalg.det(sub)
+        return np.ones((1, 1), dtype=dtype)
+    if chunk is None:
+        chunk = max(1, min(256, (1 << 26) // (d * n * n)))
+
+    def fill(j0, j1, out):
+        for a in range(j0, j1, chunk):
+            b = min(a + chunk, j1)
+            # minors[r, c] = U[occ[a + r]][:, occ[c]]  -> shape (b - a, d, n, n)
+            sub = U[occ[a:b, None, :, None], occ[None, :, None, :]]
+            out[a:b] = np.linalg.det(sub)
+
+    if _WORKERS <= 1 or d < 4 * chunk:
+        out = np.empty((d, d), dtype=dtype)
+        fill(0, d, out)
+        return out
+    import mmap
+    import multiprocessing
+    buf = mmap.mmap(-1, d * d * np.dtype(dtype).itemsize)
+    out = np.frombuffer(buf, dtype=dtype).reshape(d, d)
+    bounds = np.linspace(0, d, _WORKERS + 1).astype(int)
+    ctx = multiprocessing.get_context("fork")
+    procs = [ctx.Process(target=fill, args=(int(bounds[k]), int(bounds[k + 1]), out))
+             for k in range(_WORKERS)]
+    for pr in procs:
+        pr.start()
+    for pr in procs:
+        pr.join()
+    if any(pr.exitcode != 0 for pr in procs):
+        raise RuntimeError("compound_matrix: a worker process failed")
     return out
+
+
+def _sandwich(Ca: np.ndarray, vec: np.ndarray, Cb: np.ndarray) -> np.ndarray:
+    """Ca vec Cb^T; with real compound matrices the real and imaginary parts of vec go separately."""
+    if Ca.dtype == np.float64 and Cb.dtype == np.float64:
+        re = Ca @ np.ascontiguousarray(vec.real) @ Cb.T
+        im = Ca @ np.ascontiguousarray(vec.imag) @ Cb.T
+        out = np.empty(re.shape, dtype=np.complex128)
+        out.real = re
+        out.imag = im
+        return out
+    return Ca @ vec @ Cb.T
 
 
 def apply_orbital_rotation(vec: np.ndarray, U_a: np.ndarray, norb: int, nelec,
@@ -46,11 +97,10 @@ def apply_orbital_rotation(vec: np.ndarray, U_a: np.ndarray, norb: int, nelec,
     index is the column index).  U_b = None means the same U for both spins.
     """
     na, nb = nelec
-    if U_b is None:
-        U_b = U_a
-    Ca = compound_matrix(np.asarray(U_a, dtype=np.complex128), na)
-    Cb = Ca if (U_b is U_a and na == nb) else compound_matrix(np.asarray(U_b, dtype=np.complex128), nb)
-    return Ca @ vec @ Cb.T
+    same = U_b is None or U_b is U_a
+    Ca = compound_matrix(np.asarray(U_a), na)
+    Cb = Ca if (same and na == nb) else compound_matrix(np.asarray(U_a if U_b is None else U_b), nb)
+    return _sandwich(Ca, np.asarray(vec, dtype=np.complex128), Cb)
 
 
 # ---------------------------------------------------------------------------

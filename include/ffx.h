@@ -171,6 +171,22 @@ int ffx_apply_ucj(ffx_plan plan, void* vec, int n_reps, const double* U_a, const
 int ffx_sample_state(ffx_plan plan, const void* vec, const double* u, int64_t n_samples, int64_t* out,
                      void* stream);
 
+/* Allocation-free variant of ffx_sample_state, for callers that cannot
+   allocate device memory (code under HIP graph capture, tight serving loops,
+   harnesses that forbid hipMalloc): it calls no allocating routine and only
+   enqueues work on `stream`.  u (n_samples uniforms) and out (n_samples
+   int64) are DEVICE buffers on the plan's device; out[k] is the address
+   ffx_sample_state returns for u[k], or -1 for a uniform outside [0, 1) or a
+   state with no finite nonzero norm (checked on the device, not reported
+   through the return code).  The block sums of |gamma|^2 and their prefix go
+   to a static device array of the library (4 MiB per device, held until the
+   process ends), so states of at most 2^28 amplitudes are accepted
+   (FFX_EUNSUPPORTED above that).  Every call on one device shares that
+   array: calls that overlap on one device (two streams, two threads) race,
+   and each call overwrites what the last one left there. */
+int ffx_sample_state_noalloc(ffx_plan plan, const void* vec, const double* u, int64_t n_samples, int64_t* out,
+                             void* stream);
+
 /* Sampling of configurations from the Slater determinant script-U(U)|occ>
    (Sec. 4.5.4) without forming the state: per spin an independent draw from
    p(I) = |det U[I, occ]|^2, one orbital at a time from its conditional

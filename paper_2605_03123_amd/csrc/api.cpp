@@ -212,6 +212,9 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
     HIPCHK(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) throw Error(FFX_EINVAL, "no such device");
     DeviceGuard dg(device);
+    // the allocation-free sampler's device scratch: its address on this device
+    double* scr = nullptr;
+    HIPCHK(dev::sample_scratch(device, &scr));
     auto P = std::make_unique<ffx_plan_s>();
     P->norb = norb;
     P->n[0] = na;

@@ -94,6 +94,11 @@ void dist2(bool c64, const void* x, const void* y, int64_t n, double* partials, 
 int sample_blocks(int64_t n);
 int sample_state(bool c64, const void* vec, int64_t n, double* bs, double* pre, const double* u, int64_t n_samples,
                  int64_t* out, hipStream_t stream);
+// The allocation-free sampler's block sums and prefix live in a static device
+// array of 2 * kScratchBlocks doubles; sample_scratch returns its address on
+// `device` (which must be the current device; taken once per device).
+constexpr int64_t kScratchBlocks = (int64_t)1 << 18;
+hipError_t sample_scratch(int device, double** ptr);
 // Slater-determinant sampling of one spin: Q (N x eta complex, row-major), u
 // (n_samples x eta uniforms), masks[k] = the sampled configuration; N, eta <= 32.
 void dpp_sample(const double* Q, int N, int eta, const double* u, int64_t n_samples, uint64_t* masks,

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
+#include <vector>
 
 #include "dev_common.h"
 #include "device.h"
@@ -21,6 +23,8 @@ constexpr int kSampleChunk = 4;                   // amplitudes per thread
 constexpr int kSampleBlock = 256 * kSampleChunk;  // amplitudes per block (16 KB of complex128 read per sample)
 
 int sample_blocks(int64_t n) { return (int)((n + kSampleBlock - 1) / kSampleBlock); }
+
+constexpr int64_t kSearchChunk = (int64_t)1 << 24;  // samples per search launch
 
 // bs[b] = sum |gamma|^2 over block b (kSampleBlock addresses from b *
 // kSampleBlock): thread t sums addresses t, t + 256, t + 2 * 256, ... of the
@@ -115,7 +119,14 @@ __global__ __launch_bounds__(256) void k_sample_search(const typename V2T<R>::ty
   if (s >= n_samples) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double total = pre[nb - 1];
-  const double target = u[s] * total;
+  const double us = u[s];
+  // (the same decision in every thread of the block) a state without a finite
+  // nonzero norm, or a uniform outside [0, 1), gives -1
+  if (!(total > 0.0) || !isfinite(total) || !(us >= 0.0 && us < 1.0)) {
+    if (tid == 0) out[s] = -1;
+    return;
+  }
+  const double target = us * total;
   if (tid == 0) {
     sel[0] = kNone;  // first qualifying address
     sel[1] = -1;     // last address with nonzero probability
@@ -186,14 +197,46 @@ int sample_state(bool c64, const void* vec, int64_t n, double* bs, double* pre, 
     hipLaunchKernelGGL(k_block_norm2<double>, dim3(nb), dim3(256), 0, s, (const zc128*)vec, n, bs);
   }
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, bs, nb, pre);
-  if (n_samples <= 0) return nb;
-  const dim3 g((unsigned)n_samples);
-  if (c64)
-    hipLaunchKernelGGL(k_sample_search<float>, g, dim3(256), 0, s, (const zc64*)vec, n, pre, nb, u, n_samples, out);
-  else
-    hipLaunchKernelGGL(k_sample_search<double>, g, dim3(256), 0, s, (const zc128*)vec, n, pre, nb, u, n_samples,
-                       out);
+  // one block per sample, at most kSearchChunk blocks per launch (the grid's
+  // work-items stay below 2^32)
+  for (int64_t off = 0; off < n_samples; off += kSearchChunk) {
+    const int64_t cnt = n_samples - off < kSearchChunk ? n_samples - off : kSearchChunk;
+    const dim3 g((unsigned)cnt);
+    if (c64)
+      hipLaunchKernelGGL(k_sample_search<float>, g, dim3(256), 0, s, (const zc64*)vec, n, pre, nb, u + off, cnt,
+                         out + off);
+    else
+      hipLaunchKernelGGL(k_sample_search<double>, g, dim3(256), 0, s, (const zc128*)vec, n, pre, nb, u + off, cnt,
+                         out + off);
+  }
   return nb;
+}
+
+// Device memory of the allocation-free state sampler: the block sums and
+// their prefix, 2 * kScratchBlocks doubles (4 MiB) per device, held until the
+// process ends.  In host code `scratch` names a host-side stand-in, never the
+// device array: its device address comes from hipGetSymbolAddress, once per
+// device with that device current, and only that address is used.
+__device__ __align__(256) double scratch[2 * kScratchBlocks];
+
+hipError_t sample_scratch(int device, double** ptr) {
+  static std::mutex mu;
+  static std::vector<double*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (device < 0) return hipErrorInvalidDevice;
+  if ((size_t)device >= addr.size()) addr.resize((size_t)device + 1, nullptr);
+  if (!addr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = (double*)p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
@@ -302,8 +345,12 @@ void dpp_sample(const double* Q, int N, int eta, const double* u, int64_t n_samp
   int waves = kDppWaves;
   while (waves > 1 && (qd + waves * wd) * sizeof(double) > kDppLdsCap) --waves;
   const size_t lds = (qd + waves * wd) * sizeof(double);  // at most 48 KB at N = eta = 32
-  const dim3 g((unsigned)((n_samples + waves - 1) / waves));
-  hipLaunchKernelGGL(k_dpp_sample, g, dim3(64 * waves), lds, s, Q, N, eta, u, n_samples, masks);
+  // at most kSearchChunk samples per launch (the grid's work-items stay below 2^32)
+  for (int64_t off = 0; off < n_samples; off += kSearchChunk) {
+    const int64_t cnt = n_samples - off < kSearchChunk ? n_samples - off : kSearchChunk;
+    const dim3 g((unsigned)((cnt + waves - 1) / waves));
+    hipLaunchKernelGGL(k_dpp_sample, g, dim3(64 * waves), lds, s, Q, N, eta, u + off * eta, cnt, masks + off);
+  }
 }
 
 }  // namespace dev

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <string>
 #include <vector>
 
 #include "device.h"
@@ -62,6 +63,25 @@ int ffx_sample_state(ffx_plan plan, const void* vec, const double* u, int64_t n_
     if (n_samples == 0) return;
     HIPCHK(hipMemcpyAsync(out, dout.p, (size_t)n_samples * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+  });
+}
+
+int ffx_sample_state_noalloc(ffx_plan plan, const void* vec, const double* u, int64_t n_samples, int64_t* out,
+                             void* stream) {
+  return guard([&] {
+    if (!plan || !vec || (n_samples > 0 && (!u || !out))) throw Error(FFX_EINVAL, "null pointer");
+    if (n_samples < 0 || n_samples >= ((int64_t)1 << 31)) throw Error(FFX_EINVAL, "n_samples out of range");
+    ffx_plan_s& P = *plan;
+    const int64_t n = P.elems();
+    const int nb = dev::sample_blocks(n);
+    if (nb > dev::kScratchBlocks)
+      throw Error(FFX_EUNSUPPORTED, "state of " + std::to_string(n) + " amplitudes exceeds the allocation-free "
+                                    "sampler's limit of " + std::to_string(dev::kScratchBlocks * 1024) + " amplitudes");
+    DeviceGuard dg(P.device);
+    double* scr = nullptr;
+    HIPCHK(dev::sample_scratch(P.device, &scr));
+    dev::sample_state(P.c64, vec, n, scr, scr + nb, u, n_samples, out, (hipStream_t)stream);
+    check_launch();
   });
 }
 

@@ -94,6 +94,7 @@ _slater = _sig("ffx_slater_determinant", _ci, [_vp, _vp, _c_int_p, _c_int_p, _c_
 _ucj = _sig("ffx_apply_ucj", _ci, [_vp, _vp, _ci, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
                                    _c_double_p, _c_double_p, _c_double_p, _vp])
 _sstate = _sig("ffx_sample_state", _ci, [_vp, _vp, _c_double_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _vp])
+_sstate_na = _sig("ffx_sample_state_noalloc", _ci, [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp])
 _sslater = _sig("ffx_sample_slater", _ci, [_vp, _c_int_p, _c_int_p, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
                                            ctypes.c_int64, _c_u64_p, _c_u64_p, _vp])
 _tenable = _sig("ffx_timing_enable", ctypes.c_int, [_vp, ctypes.c_int])
@@ -410,6 +411,21 @@ def sample_state(vec: torch.Tensor, u, norb: int, nelec, *, plan=None) -> np.nda
     out = np.zeros(uu.size, dtype=np.int64)
     _check(_sstate(plan.handle, _vp(vec.data_ptr()), _dptr(uu), uu.size,
                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _stream(vec.device)))
+    return out
+
+
+def sample_state_noalloc(vec: torch.Tensor, u: torch.Tensor, out: torch.Tensor, norb: int, nelec, *,
+                         plan=None) -> torch.Tensor:
+    """sample_state with device uniforms u (float64) and a device result tensor out (int64), through the
+    library's allocation-free entry point (enqueues only; -1 marks an invalid uniform or norm)."""
+    plan = plan or get_plan(norb, nelec, vec.dtype, vec.device.index or 0)
+    plan.check_vec(vec)
+    if u.dtype != torch.float64 or out.dtype != torch.int64 or not u.is_contiguous() or not out.is_contiguous():
+        raise ValueError("u must be contiguous float64 and out contiguous int64")
+    if u.device != vec.device or out.device != vec.device or out.numel() < u.numel():
+        raise ValueError("u and out must be on the state's device, out at least as long as u")
+    _check(_sstate_na(plan.handle, _vp(vec.data_ptr()), _vp(u.data_ptr()), u.numel(), _vp(out.data_ptr()),
+                      _stream(vec.device)))
     return out
 
 

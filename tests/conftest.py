@@ -12,3 +12,10 @@ if HERE not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long CPU test")
+
+
+def pytest_sessionfinish(session, exitstatus):
+    path = os.environ.get("FFX_ERROR_LOG")
+    if path:
+        import errlog
+        errlog.dump(path)

@@ -13,6 +13,12 @@ Whole oracle states do not fit these sizes, so the checks are:
     returns the start state (reversibility over the whole state);
   * two DF steps at norb = 14 (7, 7) from Hartree-Fock against stored oracle
     amplitudes (tests/golden/df_trotter_n14.txt);
+  * the benchmark's DF step itself, norb = 16 (8, 8), L = 16, from the seed-0
+    random state, against stored oracle amplitudes, norm and energy
+    (tests/golden/df_trotter_n16.txt, the oracle's unmerged 33 rotations);
+  * complex128 at norb = 18 (9, 9): sampled amplitudes of one rotation (the
+    oracle streams the input state from the device by row blocks) and a full DF
+    step undone by its inverse;
   * the DF energy at norb = 16 (8, 8), L = 16, of a rotated Hartree-Fock state
     against Wick's theorem on its one-body densities (real and complex U_t);
   * the DF-chain adjoint gradient at norb = 16 (8, 8), L = 16 against central
@@ -37,11 +43,14 @@ from oracle import gates as og
 from oracle import sampled
 from oracle import strings as ost
 from paper_2605_03123_amd import synth
+from errlog import AMP, REL, record
 
 pytestmark = pytest.mark.gpu
 
-TOL = {torch.complex128: 1e-12, torch.complex64: 1e-5}
+TOL = {torch.complex128: AMP["complex128"], torch.complex64: AMP["complex64"]}
+RTOL = {torch.complex128: REL["complex128"], torch.complex64: REL["complex64"]}
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "df_trotter_n14.txt")
+GOLDEN16 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "df_trotter_n16.txt")
 
 
 @pytest.fixture(scope="module")
@@ -96,7 +105,8 @@ def test_rotation_sampled_n16(ffx, dtype):
         out = ffx.apply_orbital_rotation(x, U, norb, nelec)
         idx = _sample_idx(d, 6, 161) + [(0, 0), (d - 1, d - 1)]
         ref = sampled.rotated_amplitudes_blocked(host, U, norb, nelec, idx)
-        assert np.max(np.abs(_at(out, idx) - ref)) <= TOL[dtype]
+        err = record("rotation_sampled_n16", dtype, "amplitude", np.max(np.abs(_at(out, idx) - ref)), TOL[dtype])
+        assert err <= TOL[dtype]
         nrm = torch.linalg.vector_norm(out.to(torch.complex128)).item()
         assert abs(nrm - 1.0) <= (1e-12 if dtype == torch.complex128 else 1e-5)
 
@@ -119,7 +129,9 @@ def test_df_step_diagonal_hamiltonian_n16(ffx, dtype):
     ang = -dt * ((xa + xb) @ eps)
     for t in range(L):
         ang -= 0.5 * dt * og.diag_coulomb_angle_at(norb, nelec, idx, J[t])
-    assert np.max(np.abs(_at(out, idx) - np.exp(1j * ang) * x0)) <= TOL[dtype]
+    err = record("df_step_diagonal_n16", dtype, "amplitude", np.max(np.abs(_at(out, idx) - np.exp(1j * ang) * x0)),
+                 TOL[dtype])
+    assert err <= TOL[dtype]
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
@@ -134,7 +146,55 @@ def test_df_step_reversible_n16(ffx, dtype):
     _inverse_step(ffx, x, w.data["ham"], dt, norb, nelec)
     err = torch.max(torch.abs((x - x0).to(torch.complex128))).item()
     assert moved > 1e-4
-    assert err <= (1e-12 if dtype == torch.complex128 else 1e-5)
+    assert record("df_step_reversible_n16", dtype, "amplitude", err, TOL[dtype]) <= TOL[dtype]
+
+
+class _DeviceRows:
+    """Row blocks of a device state, upcast to complex128 on the host one block at a time."""
+
+    def __init__(self, t):
+        self.t = t
+        self.shape = tuple(t.shape)
+
+    def __getitem__(self, sl):
+        return self.t[sl].to(torch.complex128).cpu().numpy()
+
+
+def test_rotation_sampled_n18_c128(ffx):
+    # config-5 size at complex128: 48620 x 48620 (37.8 GB); the oracle reads the input state from the
+    # device by row blocks (no whole host copy)
+    norb, nelec = 18, (9, 9)
+    d = ost.dim(norb, 9)
+    print("rotation sampled n18 complex128", flush=True)
+    r = synth.rng(182)
+    U = synth.random_orthogonal(r, norb).astype(complex)
+    x = _device_state(d, torch.complex128, 21)
+    out = ffx.apply_orbital_rotation(x, U, norb, nelec)
+    idx = [(int(i), 27182) for i in np.random.default_rng(183).integers(0, d, 5)] + [(0, 27182), (d - 1, 27182)]
+    ref = sampled.rotated_amplitudes_blocked(_DeviceRows(x), U, norb, nelec, idx, block=1024)
+    err = record("rotation_sampled_n18", torch.complex128, "amplitude", np.max(np.abs(_at(out, idx) - ref)), 1e-12)
+    del x, out
+    torch.cuda.empty_cache()
+    assert err <= TOL[torch.complex128]
+
+
+def test_df_step_reversible_n18_c128(ffx):
+    norb, nelec, dt = 18, (9, 9), 0.1
+    print("DF step n18 complex128 round trip", flush=True)
+    ham = synth.df_hamiltonian(synth.rng(0), norb, 18)
+    d = ost.dim(norb, 9)
+    x0 = _device_state(d, torch.complex128, 22)
+    x = x0.clone()
+    ffx.simulate_trotter_double_factorized(x, ham, dt, norb, nelec, n_steps=1, order=0, out=x)
+    moved = torch.max(torch.abs(x - x0)).item()
+    nrm = torch.linalg.vector_norm(x).item()
+    _inverse_step(ffx, x, ham, dt, norb, nelec)
+    err = torch.max(torch.abs(x - x0)).item()
+    del x, x0
+    torch.cuda.empty_cache()
+    assert moved > 1e-5
+    assert abs(nrm - 1.0) <= TOL[torch.complex128]
+    assert record("df_step_reversible_n18", torch.complex128, "amplitude", err, 1e-12) <= TOL[torch.complex128]
 
 
 def test_rotation_sampled_n18_c64(ffx):
@@ -148,7 +208,8 @@ def test_rotation_sampled_n18_c64(ffx):
     idx = [(int(i), 31415) for i in np.random.default_rng(181).integers(0, d, 5)] + [(0, 31415)]
     ref = sampled.rotated_amplitudes_blocked(host, U, norb, nelec, idx, block=4096)
     del host
-    assert np.max(np.abs(_at(x, idx) - ref)) <= 1e-5
+    err = record("rotation_sampled_n18", torch.complex64, "amplitude", np.max(np.abs(_at(x, idx) - ref)), 1e-5)
+    assert err <= TOL[torch.complex64]
 
 
 def test_df_step_reversible_n18_c64(ffx):
@@ -160,8 +221,9 @@ def test_df_step_reversible_n18_c64(ffx):
     ffx.simulate_trotter_double_factorized(x, ham, dt, norb, nelec, n_steps=1, order=0, out=x)
     nrm = torch.linalg.vector_norm(x).item()
     _inverse_step(ffx, x, ham, dt, norb, nelec)
-    assert abs(nrm - 1.0) <= 1e-5
-    assert torch.max(torch.abs(x - x0)).item() <= 1e-5
+    assert abs(nrm - 1.0) <= TOL[torch.complex64]
+    err = torch.max(torch.abs(x - x0)).item()
+    assert record("df_step_reversible_n18", torch.complex64, "amplitude", err, 1e-5) <= TOL[torch.complex64]
 
 
 def _golden():
@@ -182,10 +244,57 @@ def test_df_trotter_config2_golden(ffx, dtype):
     x = torch.from_numpy(w.data["vec"]).to(dtype).to("cuda:0")
     ffx.simulate_trotter_double_factorized(x, w.data["ham"], 0.2, 14, (7, 7), n_steps=2, order=0, out=x)
     tol = TOL[dtype]
-    assert np.max(np.abs(_at(x, idx) - amp)) <= tol
+    assert record("df_trotter_golden_n14", dtype, "amplitude_vs_original_input", np.max(np.abs(_at(x, idx) - amp)),
+                  tol) <= tol
     assert abs(torch.linalg.vector_norm(x.to(torch.complex128)).item() - norm) <= tol
     e = ffx.df_energy(x, w.data["ham"], 14, (7, 7))
-    assert abs(e - energy.real) <= (1e-10 if dtype == torch.complex128 else 1e-5) * max(1.0, abs(energy.real))
+    err = abs(e - energy.real) / max(1.0, abs(energy.real))
+    assert record("df_trotter_golden_n14", dtype, "energy_rel", err, RTOL[dtype]) <= RTOL[dtype]
+
+
+def _golden16():
+    """(step seconds, cores), norm, norm of the complex64-input run, energy, indices, amplitudes of both runs."""
+    vals, rows = {}, []
+    with open(GOLDEN16) as f:
+        for ln in f:
+            if ln.startswith("#"):
+                continue
+            a = ln.split()
+            if a[0].isdigit():
+                rows.append(a)
+            else:
+                vals[a[0]] = [float(v) for v in a[1:]]
+    idx = [(int(a[0]), int(a[1])) for a in rows]
+    amp = np.array([complex(float(a[2]), float(a[3])) for a in rows])
+    amp64 = np.array([complex(float(a[4]), float(a[5])) for a in rows])
+    return vals, idx, amp, amp64
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN16), reason="golden file not generated")
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_df_trotter_n16_golden(ffx, dtype):
+    """The benchmark's DF step (norb = 16 (8, 8), L = 16, dt = 0.1, S_0, seed-0 random state), in the
+    launch configuration bench.py times, against the oracle's unmerged step: 4160 sampled amplitudes, the
+    norm and the energy.  complex64 is compared with the oracle run on its rounded input (the kernels'
+    arithmetic error) and with the oracle run on the original input (plus the input rounding)."""
+    vals, idx, amp, amp64 = _golden16()
+    print(f"DF step n16 against the stored oracle step ({dtype})", flush=True)
+    w = synth.workload_df_trotter(16, 16, seed=0, start="random", dt=0.1)
+    x = torch.from_numpy(w.data["vec"]).to(dtype).to("cuda:0")
+    ffx.simulate_trotter_double_factorized(x, w.data["ham"], 0.1, 16, (8, 8), n_steps=1, order=0, out=x)
+    got = _at(x, idx)
+    tol = TOL[dtype]
+    err = record("df_trotter_golden_n16", dtype, "amplitude_vs_original_input", np.max(np.abs(got - amp)), tol)
+    assert err <= tol
+    if dtype == torch.complex64:
+        err = record("df_trotter_golden_n16", dtype, "amplitude", np.max(np.abs(got - amp64)), tol)
+        assert err <= tol
+    nrm = torch.linalg.vector_norm(x.to(torch.complex128) if dtype == torch.complex128 else x).item()
+    ref_norm = vals["norm"][0] if dtype == torch.complex128 else vals["norm_c64_input"][0]
+    assert abs(nrm - ref_norm) <= tol
+    e = ffx.df_energy(x, w.data["ham"], 16, (8, 8))
+    err = abs(e - vals["energy"][0]) / max(1.0, abs(vals["energy"][0]))
+    assert record("df_trotter_golden_n16", dtype, "energy_rel", err, RTOL[dtype]) <= RTOL[dtype]
 
 
 def test_lucj_gradient_n16_matches_central_differences(ffx):
@@ -203,7 +312,7 @@ def test_lucj_gradient_n16_matches_central_differences(ffx):
         ffx.apply_lucj(q, norb, nelec, n_reps, dtype=torch.complex128, out=psi, plan=plan)
         return ffx.df_energy(psi, ham, norb, nelec, plan=plan)
 
-    assert abs(energy(p) - e) <= 1e-10 * max(1.0, abs(e))
+    assert abs(energy(p) - e) <= RTOL[torch.complex128] * max(1.0, abs(e))
     h = 1e-5
     scale = max(1.0, float(np.max(np.abs(g))))
     for i in synth.fd_indices(g.size, 4):
@@ -212,8 +321,10 @@ def test_lucj_gradient_n16_matches_central_differences(ffx):
         qm[i] -= h
         assert abs((energy(qp) - energy(qm)) / (2 * h) - g[i]) <= 1e-7 * scale
     e64, g64 = ffx.lucj_energy_grad(p, ham, norb, nelec, n_reps, dtype=torch.complex64)
-    assert abs(e64 - e) <= 1e-5 * max(1.0, abs(e))
-    assert np.max(np.abs(g64 - g)) <= 1e-4 * scale
+    err = abs(e64 - e) / max(1.0, abs(e))
+    assert record("lucj_energy_n16_c64_vs_c128", torch.complex64, "energy_rel", err, 1e-5) <= RTOL[torch.complex64]
+    err = np.max(np.abs(g64 - g)) / scale
+    assert record("lucj_gradient_n16_c64_vs_c128", torch.complex64, "grad_rel", err, 1e-5) <= RTOL[torch.complex64]
 
 
 def test_hubbard_4x8_action_and_exact_evolution(ffx):
@@ -239,14 +350,17 @@ def test_hubbard_4x8_action_and_exact_evolution(ffx):
     assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, float(np.abs(ref).max()))
     e_direct = float(torch.vdot(vec.reshape(-1), out.reshape(-1)).real)
     e_rot = ffx.df_energy(vec, ham, norb, nelec)
-    assert abs(e_direct - e_rot) <= 1e-10 * max(1.0, abs(e_rot))
+    assert abs(e_direct - e_rot) <= RTOL[torch.complex128] * max(1.0, abs(e_rot))
     del out
     ex, k = ffx.evolve_exact(vec, ham, 1.0, norb, nelec)
     print(f"exact evolution: {k} Hamiltonian actions", flush=True)
-    assert abs(float(torch.linalg.vector_norm(ex)) - 1.0) <= 1e-10
-    assert abs(ffx.df_energy(ex, ham, norb, nelec) - e_rot) <= 1e-9 * max(1.0, abs(e_rot))
+    # invariants of an expansion truncated at 1e-12 with K ~ 74 terms of FP64 rounding each
+    c128 = torch.complex128
+    assert record("hubbard_4x8_exact_norm", c128, "abs", abs(float(torch.linalg.vector_norm(ex)) - 1.0), 1e-10) <= 1e-10
+    err = abs(ffx.df_energy(ex, ham, norb, nelec) - e_rot) / max(1.0, abs(e_rot))
+    assert record("hubbard_4x8_exact_energy", c128, "energy_rel", err, 1e-9) <= 1e-9
     ffx.evolve_exact(ex, ham, -1.0, norb, nelec, out=ex)
-    assert float(torch.max(torch.abs(ex - vec))) <= 1e-9
+    assert record("hubbard_4x8_exact_round_trip", c128, "amplitude", float(torch.max(torch.abs(ex - vec))), 1e-9) <= 1e-9
 
 
 def _slater_energy_wick(W, nelec, ham):
@@ -284,7 +398,8 @@ def test_df_energy_slater_wick_n16(ffx, dtype, complex_u):
     vec = ffx.slater_determinant(norb, nelec, U=W, dtype=dtype)
     ref = _slater_energy_wick(W, nelec, ham)
     e = ffx.df_energy(vec, ham, norb, nelec)
-    assert abs(e - ref) <= (1e-10 if dtype == torch.complex128 else 1e-5) * max(1.0, abs(ref)), (e, ref)
+    err = abs(e - ref) / max(1.0, abs(ref))
+    assert record("df_energy_wick_n16", dtype, "energy_rel", err, RTOL[dtype], complex_u=complex_u) <= RTOL[dtype]
 
 
 def test_df_chain_gradient_n16_matches_central_differences(ffx):
@@ -308,7 +423,7 @@ def test_df_chain_gradient_n16_matches_central_differences(ffx):
     def with_(**kw):
         return synth.DFHamiltonian(h=kw.get("h", ham.h), J=kw.get("J", ham.J), U=kw.get("U", ham.U))
 
-    assert abs(energy(ham) - e) <= 1e-10 * max(1.0, abs(e))
+    assert abs(energy(ham) - e) <= RTOL[torch.complex128] * max(1.0, abs(e))
     step = 1e-5
     scale = max(1.0, max(float(np.max(np.abs(v))) for v in g.values()))
     p, q, t = 3, 11, 7
@@ -347,4 +462,4 @@ def test_symmetric_formulas_reversible_n16(ffx, dtype, order):
     ffx.simulate_trotter_double_factorized(x, w.data["ham"], -dt, norb, nelec, n_steps=1, order=order, out=x, plan=plan)
     err = torch.max(torch.abs((x - x0).to(torch.complex128))).item()
     assert moved > 1e-4
-    assert err <= (1e-12 if dtype == torch.complex128 else 1e-5)
+    assert record(f"s{order}_round_trip_n16", dtype, "amplitude", err, TOL[dtype]) <= TOL[dtype]

@@ -2,7 +2,13 @@
 
 complex128: max |amplitude difference| <= 1e-12 with no phase alignment (every
 gate here has exactly one correct result).  complex64: <= 1e-5 against the
-oracle run on the upcast of the complex64-rounded inputs.
+oracle run on the upcast of the complex64-rounded inputs (the kernel's own
+arithmetic error); for the rotation, the config-1 chain and the DF steps the
+error against the oracle on the original complex128 input (which adds the input
+rounding) is asserted to the same bound and recorded beside it.  Energies and
+gradients: 1e-12 (complex128) / 1e-5 (complex64) relative to max(1, |reference|).
+Every chain here, multi-step and symmetric product formulas included, is held to
+these single-gate bounds.
 """
 import numpy as np
 import pytest
@@ -13,10 +19,12 @@ from oracle import hamiltonian as oh
 from oracle import lucj as ol
 from oracle import strings as ost
 from paper_2605_03123_amd import synth
+from errlog import AMP, REL, record
 
 pytestmark = pytest.mark.gpu
 
-TOL = {torch.complex128: 1e-12, torch.complex64: 1e-5}
+TOL = {torch.complex128: AMP["complex128"], torch.complex64: AMP["complex64"]}
+RTOL = {torch.complex128: REL["complex128"], torch.complex64: REL["complex64"]}
 DTYPES = [torch.complex128, torch.complex64]
 
 
@@ -64,12 +72,20 @@ def test_plan_string_tables_bit_exact(ffx):
 def test_orbital_rotation(ffx, dtype, norb, nelec):
     r = synth.rng([norb, nelec[0], nelec[1]])
     da, db = _dims(norb, nelec)
-    vec = _to_dev(synth.random_state(r, da, db), dtype)
+    v0 = synth.random_state(r, da, db)
+    vec = _to_dev(v0, dtype)
     x = _ref_input(vec)
     Ua, Ub = synth.random_unitary(r, norb), synth.random_unitary(r, norb)
     O = synth.random_orthogonal(r, norb)
     out = ffx.apply_orbital_rotation(vec, Ua, norb, nelec, U_b=Ub)
-    assert _maxdiff(out, og.apply_orbital_rotation(x, Ua, norb, nelec, U_b=Ub)) <= TOL[dtype]
+    err = record("orbital_rotation", dtype, "amplitude", _maxdiff(out, og.apply_orbital_rotation(x, Ua, norb, nelec, U_b=Ub)),
+                 TOL[dtype], norb=norb, nelec=list(nelec))
+    assert err <= TOL[dtype]
+    if dtype == torch.complex64:
+        err = record("orbital_rotation", dtype, "amplitude_vs_original_input",
+                     _maxdiff(out, og.apply_orbital_rotation(v0, Ua, norb, nelec, U_b=Ub)), TOL[dtype], norb=norb,
+                     nelec=list(nelec))
+        assert err <= TOL[dtype]
     out = ffx.apply_orbital_rotation(vec, Ua, norb, nelec)
     assert _maxdiff(out, og.apply_orbital_rotation(x, Ua, norb, nelec)) <= TOL[dtype]
     out = ffx.apply_orbital_rotation(vec, O, norb, nelec)
@@ -103,7 +119,7 @@ def test_phase_gates(ffx, dtype, norb, nelec):
     Jaa, Jab, Jbb = (synth.random_symmetric(r, norb, 1.0) for _ in range(3))
     out = ffx.apply_diag_coulomb_evolution(vec, Jaa, 0.3, norb, nelec, J_ab=Jab, J_bb=Jbb)
     ref = og.apply_diag_coulomb_evolution(x, Jaa, 0.3, norb, nelec, J_ab=Jab, J_bb=Jbb)
-    assert _maxdiff(out, ref) <= TOL[dtype]
+    assert record("diag_coulomb", dtype, "amplitude", _maxdiff(out, ref), TOL[dtype], norb=norb) <= TOL[dtype]
     out = ffx.apply_diag_coulomb_evolution(vec, Jaa, -1.3, norb, nelec)
     assert _maxdiff(out, og.apply_diag_coulomb_evolution(x, Jaa, -1.3, norb, nelec)) <= TOL[dtype]
 
@@ -118,10 +134,18 @@ def test_rotation_coulomb_workload(ffx, dtype):
     out = ffx.apply_orbital_rotation(vec, d["U"], norb, nelec)
     ffx.apply_diag_coulomb_evolution(out, d["J"], d["t"], norb, nelec, out=out)
     ffx.apply_orbital_rotation(out, d["U"].conj().T, norb, nelec, out=out)
-    ref = og.apply_orbital_rotation(x, d["U"], norb, nelec)
-    ref = og.apply_diag_coulomb_evolution(ref, d["J"], d["t"], norb, nelec)
-    ref = og.apply_orbital_rotation(ref, d["U"].conj().T, norb, nelec)
-    assert _maxdiff(out, ref) <= TOL[dtype]
+
+    def chain(v):
+        ref = og.apply_orbital_rotation(v, d["U"], norb, nelec)
+        ref = og.apply_diag_coulomb_evolution(ref, d["J"], d["t"], norb, nelec)
+        return og.apply_orbital_rotation(ref, d["U"].conj().T, norb, nelec)
+
+    ref = chain(x)
+    assert record("config1_rotation_coulomb", dtype, "amplitude", _maxdiff(out, ref), TOL[dtype]) <= TOL[dtype]
+    if dtype == torch.complex64:
+        err = record("config1_rotation_coulomb", dtype, "amplitude_vs_original_input", _maxdiff(out, chain(d["vec"])),
+                     TOL[dtype])
+        assert err <= TOL[dtype]
     nrm = float(torch.linalg.vector_norm(out.to(torch.complex128)))
     assert abs(nrm - np.linalg.norm(ref)) <= TOL[dtype]
 
@@ -133,11 +157,17 @@ def test_df_trotter(ffx, dtype, order, n_steps, norb, nelec, L):
     r = synth.rng([11, norb, order])
     ham = synth.df_hamiltonian(r, norb, L)
     da, db = _dims(norb, nelec)
-    vec = _to_dev(synth.random_state(r, da, db), dtype)
+    v0 = synth.random_state(r, da, db)
+    vec = _to_dev(v0, dtype)
     x = _ref_input(vec)
     out = ffx.simulate_trotter_double_factorized(vec, ham, 0.1 * n_steps, norb, nelec, n_steps=n_steps, order=order)
     ref = oh.simulate_trotter(x, ham, 0.1 * n_steps, norb, nelec, n_steps=n_steps, order=order)
-    assert _maxdiff(out, ref) <= TOL[dtype] * (10 if dtype == torch.complex64 else 1)
+    tag = dict(norb=norb, nelec=list(nelec), L=L, order=order, n_steps=n_steps)
+    assert record("df_trotter", dtype, "amplitude", _maxdiff(out, ref), TOL[dtype], **tag) <= TOL[dtype]
+    if dtype == torch.complex64:
+        ref0 = oh.simulate_trotter(v0, ham, 0.1 * n_steps, norb, nelec, n_steps=n_steps, order=order)
+        err = record("df_trotter", dtype, "amplitude_vs_original_input", _maxdiff(out, ref0), TOL[dtype], **tag)
+        assert err <= TOL[dtype]
 
 
 def test_df_trotter_complex_basis(ffx):
@@ -156,7 +186,8 @@ def test_df_trotter_complex_basis(ffx):
 def test_lucj_forward(ffx, dtype, norb, nelec, n_reps):
     params = synth.lucj_params(synth.rng([13, norb]), norb, n_reps, scale=0.3)
     out = ffx.apply_lucj(params, norb, nelec, n_reps, dtype=dtype)
-    assert _maxdiff(out, ol.apply_lucj(params, norb, nelec, n_reps)) <= TOL[dtype]
+    err = _maxdiff(out, ol.apply_lucj(params, norb, nelec, n_reps))
+    assert record("lucj_forward", dtype, "amplitude", err, TOL[dtype], norb=norb, n_reps=n_reps) <= TOL[dtype]
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -169,7 +200,8 @@ def test_df_energy(ffx, dtype, norb, nelec):
     x = _ref_input(vec)
     e = ffx.df_energy(vec, ham, norb, nelec)
     ref = oh.df_energy(x, ham, norb, nelec)
-    assert abs(e - ref.real) <= (1e-10 if dtype == torch.complex128 else 1e-5) * max(1.0, abs(ref.real))
+    err = abs(e - ref.real) / max(1.0, abs(ref.real))
+    assert record("df_energy", dtype, "energy_rel", err, RTOL[dtype], norb=norb) <= RTOL[dtype]
     assert ffx.df_energy(vec, ham, norb, nelec) == e   # fixed reduction order
 
 
@@ -182,9 +214,11 @@ def test_lucj_energy_grad_matches_oracle_adjoint(ffx, dtype, norb, nelec, n_reps
     ham = synth.df_hamiltonian(r, norb, 2)
     e, g = ffx.lucj_energy_grad(params, ham, norb, nelec, n_reps, dtype=dtype)
     eo, go = ol.grad_adjoint(params, ham, norb, nelec, n_reps)
-    tol = 1e-10 if dtype == torch.complex128 else 1e-4
-    assert abs(e - eo) <= tol * max(1, abs(eo))
-    assert np.max(np.abs(g - go)) <= tol * max(1, np.max(np.abs(go)))
+    tol = RTOL[dtype]
+    tag = dict(norb=norb, nelec=list(nelec), n_reps=n_reps)
+    assert record("lucj_energy", dtype, "energy_rel", abs(e - eo) / max(1, abs(eo)), tol, **tag) <= tol
+    err = np.max(np.abs(g - go)) / max(1, np.max(np.abs(go)))
+    assert record("lucj_gradient_vs_oracle_adjoint", dtype, "grad_rel", err, tol, **tag) <= tol
 
 
 @pytest.mark.parametrize("mode", ["auto", "rot"])
@@ -199,8 +233,10 @@ def test_lucj_energy_grad_hubbard(ffx, monkeypatch, mode, nx, ny):
     params = synth.lucj_params(synth.rng([16, nx, ny]), norb, 2, scale=0.3)
     e, g = ffx.lucj_energy_grad(params, ham, norb, nelec, 2)
     eo, go = ol.grad_adjoint(params, ham, norb, nelec, 2)
-    assert abs(e - eo) <= 1e-10 * max(1, abs(eo))
-    assert np.max(np.abs(g - go)) <= 1e-10 * max(1, np.max(np.abs(go)))
+    tol = RTOL[torch.complex128]
+    assert abs(e - eo) <= tol * max(1, abs(eo))
+    err = np.max(np.abs(g - go)) / max(1, np.max(np.abs(go)))
+    assert record("lucj_gradient_hubbard_" + mode, torch.complex128, "grad_rel", err, tol, lattice=[nx, ny]) <= tol
 
 
 def test_lucj_gradient_matches_central_differences_on_gpu(ffx):
@@ -227,7 +263,7 @@ def test_autograd_function(ffx):
     E = ffx.LUCJEnergy.apply(p, ham, norb, nelec, n_reps)
     E.backward()
     _, go = ol.grad_adjoint(p.detach().numpy(), ham, norb, nelec, n_reps)
-    np.testing.assert_allclose(p.grad.numpy(), go, atol=1e-10)
+    np.testing.assert_allclose(p.grad.numpy(), go, atol=RTOL[torch.complex128] * max(1.0, np.max(np.abs(go))))
 
 
 def test_errors_do_not_crash(ffx):
@@ -278,10 +314,11 @@ def test_segmented_paths(ffx, small_segment_plans):
         ham = synth.df_hamiltonian(r, norb, 3)
         out = ffx.simulate_trotter_double_factorized(vec, ham, 0.2, norb, nelec, n_steps=2, order=1, plan=plan)
         ref = oh.simulate_trotter(x, ham, 0.2, norb, nelec, n_steps=2, order=1)
-        assert _maxdiff(out, ref) <= TOL[dtype] * 10
+        err = record("segmented_df_trotter_s1", dtype, "amplitude", _maxdiff(out, ref), TOL[dtype], norb=norb)
+        assert err <= TOL[dtype]
         e = ffx.df_energy(vec, ham, norb, nelec, plan=plan)
         ref = oh.df_energy(x, ham, norb, nelec).real
-        assert abs(e - ref) <= (1e-10 if dtype == torch.complex128 else 1e-5) * max(1, abs(ref))
+        assert abs(e - ref) <= RTOL[dtype] * max(1, abs(ref))
         params = synth.lucj_params(r, norb, 2, scale=0.3)
         out = ffx.apply_lucj(params, norb, nelec, 2, dtype=dtype, plan=plan)
         assert _maxdiff(out, ol.apply_lucj(params, norb, nelec, 2)) <= TOL[dtype]
@@ -301,15 +338,16 @@ def test_segmented_paths_in_place_and_gradients(ffx, small_segment_plans):
             U = synth.random_unitary(r, norb)
             ffx.apply_orbital_rotation(vec, U, norb, nelec, out=vec, plan=plan)
             ref = og.apply_orbital_rotation(ref, U, norb, nelec)
-            assert _maxdiff(vec, ref) <= TOL[dtype] * (k + 1)
+            assert _maxdiff(vec, ref) <= TOL[dtype]
         ham = synth.df_hamiltonian(r, norb, 2)
         ffx.simulate_trotter_double_factorized(vec, ham, 0.1, norb, nelec, n_steps=1, order=0, out=vec, plan=plan)
         ref = oh.simulate_trotter(ref, ham, 0.1, norb, nelec, n_steps=1, order=0)
-        assert _maxdiff(vec, ref) <= TOL[dtype] * 10
+        err = record("segmented_in_place_chain", dtype, "amplitude", _maxdiff(vec, ref), TOL[dtype], norb=norb)
+        assert err <= TOL[dtype]
         params = synth.lucj_params(r, norb, 2, scale=0.3)
         e, g = ffx.lucj_energy_grad(params, ham, norb, nelec, 2, dtype=dtype, plan=plan)
         eo, go = ol.grad_adjoint(params, ham, norb, nelec, 2)
-        tol = 1e-10 if dtype == torch.complex128 else 1e-4
+        tol = RTOL[dtype]
         assert abs(e - float(np.real(eo))) <= tol * max(1.0, abs(float(np.real(eo))))
         assert np.max(np.abs(g - go)) <= tol * max(1.0, np.max(np.abs(go)))
 
@@ -340,7 +378,7 @@ def test_lucj_gradient_row_pair_transition_path(ffx):
         del os.environ["FFX_RDM_PAIRS"]
     for dt, plan in plans.items():
         e, g = ffx.lucj_energy_grad(params, ham, norb, nelec, n_reps, dtype=dt, plan=plan)
-        tol = 1e-10 if dt == torch.complex128 else 1e-4
+        tol = RTOL[dt]
         assert abs(e - float(np.real(eo))) <= tol * max(1.0, abs(float(np.real(eo))))
         assert np.max(np.abs(g - go)) <= tol * max(1.0, np.max(np.abs(go)))
 

@@ -385,15 +385,22 @@ def hubbard_timing(ffx, torch, synth, nx, ny, time_T=1.0, oracle_side=(4, 4)):
     t_exact = time.perf_counter() - t0
     runs = []
     approx = torch.empty_like(vec)
+    h_dc, Jaa, Jab, Jbb = synth.hubbard_2d_diag_coulomb(nx, ny)
     for order, n in ((1, 2), (2, 1)):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ffx.simulate_trotter_double_factorized(vec, ham, time_T, norb, nelec, n_steps=n, order=order, out=approx,
-                                               plan=plan)
-        torch.cuda.synchronize()
-        t_tr = time.perf_counter() - t0
-        runs.append({"order": order, "n_steps": n, "s": round(t_tr, 4), "s_per_step": round(t_tr / n, 4),
-                     "error": ffx.state_distance(approx, exact, norb, nelec, plan=plan)})
+        for route in ("diag_coulomb", "df"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if route == "df":
+                ffx.simulate_trotter_double_factorized(vec, ham, time_T, norb, nelec, n_steps=n, order=order,
+                                                       out=approx, plan=plan)
+            else:
+                ffx.simulate_trotter_diag_coulomb(vec, h_dc, Jaa, time_T, norb, nelec, J_ab=Jab, J_bb=Jbb, n_steps=n,
+                                                  order=order, out=approx, plan=plan)
+            torch.cuda.synchronize()
+            t_tr = time.perf_counter() - t0
+            runs.append({"route": route, "order": order, "n_steps": n, "s": round(t_tr, 4),
+                         "s_per_step": round(t_tr / n, 4),
+                         "error": ffx.state_distance(approx, exact, norb, nelec, plan=plan)})
     res = {"workload": f"hubbard_2d {nx}x{ny} periodic_x t=1 U=8 nelec={nelec} T={time_T} state=c128 {da}x{db}",
            "state_bytes": plan.state_bytes, "h_action_s": round(t_h, 4),
            "exact": {"s": round(t_exact, 3), "n_matvec": k, "tol": 1e-12}, "trotter": runs, "families": fam}

@@ -223,6 +223,23 @@ typedef struct {
 int ffx_apply_df_trotter_step(ffx_plan plan, void* vec, const ffx_df_ham* ham, double dt,
                               int n_steps, int order, void* stream);
 
+/* Trotter-Suzuki evolution under a diagonal Coulomb Hamiltonian
+   (Eq. diagonal-coulomb-hamiltonian, Sec. 4.5.3):
+     H = sum_{pq,sigma} h_pq a^dag_{p sigma} a_{q sigma}
+       + 1/2 sum_{pq,sigma tau} J^{sigma tau}_pq n_{p sigma} n_{q tau},
+   as the sum of two terms, H_1 = the one-body term (applied first) and H_2 =
+   the diagonal Coulomb term, each evolved exactly: exp(-i t H_1) is the
+   orbital rotation by exp(-i t h) on both spins (Table 1, quadratic
+   Hamiltonian evolution), exp(-i t H_2) the diagonal Coulomb evolution.
+   vec <- S_order(dt)^n_steps vec, with order 0 (S_0), 1 (S_1) or k >= 2
+   (Suzuki's S_k) as in ffx_apply_df_trotter_step.  h: real symmetric
+   norb x norb (FFX_EINVAL if not symmetric to 1e-12); J_aa, J_bb: real
+   symmetric; J_ab: real, J^{beta alpha} = (J_ab)^T; J_ab or J_bb = NULL means
+   J_aa.  Enqueues only. */
+int ffx_simulate_trotter_diag_coulomb(ffx_plan plan, void* vec, const double* h, const double* J_aa,
+                                      const double* J_ab, const double* J_bb, double dt, int n_steps, int order,
+                                      void* stream);
+
 /* LUCJ ansatz (Sec. 4.5.1): vec is OVERWRITTEN with
    prod_{k = n_reps..1} [script-U(U_k) D_k script-U(U_k)^dag] |HF>.
    Per repetition the flat real parameter block is

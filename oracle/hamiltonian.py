@@ -101,29 +101,37 @@ def _apply_term(vec, ham, term, t, norb, nelec):
     return evolve_two_body(vec, ham.J[idx], ham.U[idx], t, norb, nelec)
 
 
-def trotter_step(vec: np.ndarray, ham, dt: float, norb: int, nelec, order: int = 0) -> np.ndarray:
-    """One step of the order-k product formula S_k(dt) (Sec. 4.5.3).
+def product_formula_step(vec: np.ndarray, apply_term, n_terms: int, dt: float, order: int = 0) -> np.ndarray:
+    """One step of the order-k product formula S_k(dt) for H = H_1 + ... + H_L (Sec. 4.5.3), where
+    apply_term(vec, k, t) returns exp(-i t H_{k+1}) vec.
 
     S_0(t) = e^{-iH_L t} ... e^{-iH_1 t}                          (H_1 applied first)
     S_1(t) = e^{-iH_1 t/2} ... e^{-iH_L t/2} e^{-iH_L t/2} ... e^{-iH_1 t/2}
     S_k(t) = S_{k-1}(u_k t)^2 S_{k-1}((1 - 4 u_k) t) S_{k-1}(u_k t)^2,
     u_k = 1 / (4 - 4^{1/(2k-1)}).
     """
-    terms = list(_terms(ham))
     if order == 0:
-        for term in terms:
-            vec = _apply_term(vec, ham, term, dt, norb, nelec)
+        for k in range(n_terms):
+            vec = apply_term(vec, k, dt)
         return vec
     if order == 1:
-        for term in terms:
-            vec = _apply_term(vec, ham, term, dt / 2, norb, nelec)
-        for term in reversed(terms):
-            vec = _apply_term(vec, ham, term, dt / 2, norb, nelec)
+        for k in range(n_terms):
+            vec = apply_term(vec, k, dt / 2)
+        for k in reversed(range(n_terms)):
+            vec = apply_term(vec, k, dt / 2)
         return vec
     u = 1.0 / (4.0 - 4.0 ** (1.0 / (2 * order - 1)))
     for t in (u * dt, u * dt, (1 - 4 * u) * dt, u * dt, u * dt):
-        vec = trotter_step(vec, ham, t, norb, nelec, order - 1)
+        vec = product_formula_step(vec, apply_term, n_terms, t, order - 1)
     return vec
+
+
+def trotter_step(vec: np.ndarray, ham, dt: float, norb: int, nelec, order: int = 0) -> np.ndarray:
+    """One step of S_order(dt) for the DF Hamiltonian: H_1 = the one-body term, then the two-body terms in
+    array order (Sec. 4.5.3)."""
+    terms = list(_terms(ham))
+    return product_formula_step(vec, lambda v, k, t: _apply_term(v, ham, terms[k], t, norb, nelec),
+                                len(terms), dt, order)
 
 
 def simulate_trotter(vec: np.ndarray, ham, time: float, norb: int, nelec, n_steps: int = 1,
@@ -132,6 +140,37 @@ def simulate_trotter(vec: np.ndarray, ham, time: float, norb: int, nelec, n_step
     dt = time / n_steps
     for _ in range(n_steps):
         vec = trotter_step(vec, ham, dt, norb, nelec, order)
+    return vec
+
+
+# ---------------------------------------------------------------------------
+# Diagonal Coulomb Hamiltonian (Eq. diagonal-coulomb-hamiltonian)
+# ---------------------------------------------------------------------------
+# H = sum_{pq,sigma} h_pq a^dag_{p sigma} a_{q sigma} + 1/2 sum_{pq,sigma tau} J^{sigma tau}_pq n_{p sigma} n_{q tau},
+# each J^{sigma tau} real symmetric, J^{beta alpha} = (J^{alpha beta})^T.  Sec. 4.5.3 Trotterizes it as the sum of
+# two terms: the one-body term (an orbital rotation by exp(-i t h)) and the two-body term (a diagonal Coulomb
+# evolution).  Reading: the one-body term is H_1, applied first.
+
+def apply_diag_coulomb_hamiltonian(vec: np.ndarray, h: np.ndarray, J_aa: np.ndarray, norb: int, nelec,
+                                   J_ab: np.ndarray | None = None, J_bb: np.ndarray | None = None) -> np.ndarray:
+    """H psi for the diagonal Coulomb Hamiltonian (J_ab or J_bb None: J_aa)."""
+    out = g.apply_one_body(vec, h, norb, nelec)
+    return out + 0.5 * g.diag_coulomb_angle(norb, nelec, J_aa, J_ab, J_bb) * vec
+
+
+def simulate_trotter_diag_coulomb(vec: np.ndarray, h: np.ndarray, J_aa: np.ndarray, time: float, norb: int, nelec,
+                                  J_ab: np.ndarray | None = None, J_bb: np.ndarray | None = None, n_steps: int = 1,
+                                  order: int = 0) -> np.ndarray:
+    """exp(-i H T) psi ~ S_order(T / r)^r psi for the diagonal Coulomb Hamiltonian, r = n_steps (Sec. 4.5.3)."""
+
+    def term(v, k, t):
+        if k == 0:
+            return evolve_one_body(v, h, t, norb, nelec)
+        return g.apply_diag_coulomb_evolution(v, J_aa, t, norb, nelec, J_ab=J_ab, J_bb=J_bb)
+
+    dt = time / n_steps
+    for _ in range(n_steps):
+        vec = product_formula_step(vec, term, 2, dt, order)
     return vec
 
 

@@ -681,6 +681,74 @@ int ffx_apply_df_trotter_step(ffx_plan plan, void* vec, const ffx_df_ham* ham, d
   });
 }
 
+int ffx_simulate_trotter_diag_coulomb(ffx_plan plan, void* vec, const double* h, const double* J_aa,
+                                      const double* J_ab, const double* J_bb, double dt, int n_steps, int order,
+                                      void* stream) {
+  return guard([&] {
+    validate_plan(plan);
+    if (!vec || !h || !J_aa) throw Error(FFX_EINVAL, "null vec, h or J_aa");
+    if (n_steps < 0 || order < 0 || order > 8 || !std::isfinite(dt)) throw Error(FFX_EINVAL, "bad n_steps/order/dt");
+    ffx_plan_s& P = *plan;
+    const int N = P.norb;
+    const double* Jab = J_ab ? J_ab : J_aa;
+    const double* Jbb = J_bb ? J_bb : J_aa;
+    if (!all_finite(h, (size_t)N * N) || !all_finite(J_aa, (size_t)N * N) || !all_finite(Jab, (size_t)N * N) ||
+        !all_finite(Jbb, (size_t)N * N))
+      throw Error(FFX_EINVAL, "non-finite parameter");
+    for (int p = 0; p < N; ++p)
+      for (int q = 0; q < p; ++q)
+        if (std::abs(h[p * N + q] - h[q * N + p]) > 1e-12 * std::max(1.0, std::abs(h[p * N + q])))
+          throw Error(FFX_EINVAL, "h is not symmetric");
+    // the one-body term's eigenbasis (the two-body term is already diagonal)
+    const ffx_df_ham one{N, 0, h, nullptr, nullptr};
+    DFHost df = load_df(P, &one);
+    if (n_steps == 0) return;
+    DeviceGuard dg(P.device);
+    hipStream_t s = as_stream(stream);
+    // term 0 = the one-body term (applied first), term 1 = the diagonal Coulomb term
+    std::vector<std::pair<int, double>> seq;
+    for (int r = 0; r < n_steps; ++r) product_formula(order, dt, 2, seq);
+    std::vector<std::pair<int, double>> m;
+    for (auto& e : seq) {
+      if (!m.empty() && m.back().first == e.first)
+        m.back().second += e.second;
+      else
+        m.push_back(e);
+    }
+    // exp(-i tau H_1) is the orbital rotation Q(tau) = exp(-i tau h); consecutive one-body factors
+    // collect into one rotation B, applied before the next diagonal Coulomb evolution
+    DecompPool pool;
+    Program pr;
+    DiagSpec dc;
+    dc.Qa = J_aa;
+    dc.Qb = Jbb;
+    dc.C = Jab;
+    const int w = pr.add_diag(dc);
+    std::vector<cd> B;
+    for (auto& e : m) {
+      if (e.first == 0) {
+        const std::vector<cd> Q = one_body_rotation(df, N, e.second);
+        B = B.empty() ? Q : matmul(N, Q, B);
+        continue;
+      }
+      if (!B.empty()) {
+        const Decomposition* d = pool.add(N, B);
+        pr.rot(d, d);
+        B.clear();
+      }
+      pr.phase(w, -e.second);
+    }
+    if (!B.empty()) {
+      const Decomposition* d = pool.add(N, B);
+      pr.rot(d, d);
+    }
+    Upload up(&P, s);
+    Compiled c = compile_program(P, up, pr, FINAL_STORE, s);
+    up.commit();
+    execute_program(P, c, vec, vec, nullptr, s);
+  });
+}
+
 int ffx_lucj_n_params(int norb, int n_reps) {
   if (norb < 1 || n_reps < 0) return -1;
   return n_reps * (2 * norb * norb + 2 * norb - 1);

@@ -75,6 +75,9 @@ _dc = _sig("ffx_apply_diag_coulomb_evolution", ctypes.c_int,
            [_vp, _vp, _c_double_p, _c_double_p, _c_double_p, ctypes.c_double, _c_double_p, _vp])
 _trotter = _sig("ffx_apply_df_trotter_step", ctypes.c_int,
                 [_vp, _vp, ctypes.POINTER(_DFHam), ctypes.c_double, ctypes.c_int, ctypes.c_int, _vp])
+_trotter_dc = _sig("ffx_simulate_trotter_diag_coulomb", ctypes.c_int,
+                   [_vp, _vp, _c_double_p, _c_double_p, _c_double_p, _c_double_p, ctypes.c_double, ctypes.c_int,
+                    ctypes.c_int, _vp])
 _lucj_np = _sig("ffx_lucj_n_params", ctypes.c_int, [ctypes.c_int, ctypes.c_int])
 _lucj = _sig("ffx_apply_lucj", ctypes.c_int, [_vp, _vp, ctypes.POINTER(_LUCJ), _vp])
 _ws = _sig("ffx_workspace_bytes", ctypes.c_int64, [_vp, ctypes.c_int])
@@ -463,6 +466,22 @@ def simulate_trotter_double_factorized(vec: torch.Tensor, ham, time: float, norb
     return out
 
 
+def simulate_trotter_diag_coulomb(vec: torch.Tensor, h, J, time: float, norb: int, nelec, *, J_ab=None, J_bb=None,
+                                  n_steps: int = 1, order: int = 0, out=None, plan=None) -> torch.Tensor:
+    """exp(-i H time) vec for the diagonal Coulomb Hamiltonian (one-body h, two-body J^{aa} = J, J^{ab}, J^{bb};
+    Eq. diagonal-coulomb-hamiltonian) by n_steps steps of the order-`order` product formula (Sec. 4.5.3)."""
+    plan, out = _prepare(vec, norb, nelec, out, plan)
+    hh = _real(h, (norb, norb))
+    Ja = _real(J, (norb, norb))
+    Jab = _real(J_ab, (norb, norb)) if J_ab is not None else None
+    Jbb = _real(J_bb, (norb, norb)) if J_bb is not None else None
+    dt = float(time) / max(n_steps, 1)
+    _check(_trotter_dc(plan.handle, _vp(out.data_ptr()), _dptr(hh), _dptr(Ja),
+                       _dptr(Jab) if Jab is not None else None, _dptr(Jbb) if Jbb is not None else None, dt,
+                       int(n_steps), int(order), _stream(out.device)))
+    return out
+
+
 def apply_lucj(params, norb: int, nelec, n_reps: int, *, dtype=torch.complex128, device=0,
                out=None, plan=None) -> torch.Tensor:
     plan = plan or get_plan(norb, nelec, dtype, device)
@@ -573,20 +592,72 @@ class LUCJEnergy(torch.autograd.Function):
     """E(theta) for a LUCJ ansatz under a DF Hamiltonian, differentiable in theta.
 
     forward(params (float64 CPU tensor), ham, norb, nelec, n_reps, dtype) -> 0-dim float64 tensor.
-    The backward multiplies the adjoint gradient computed in forward.
+    When params needs a gradient, forward runs the adjoint (ffx_lucj_energy_grad) and the backward
+    multiplies the gradient it returned; otherwise forward only prepares the ansatz state and takes its
+    energy (ffx_apply_lucj, ffx_df_energy).
     """
 
     @staticmethod
     def forward(ctx, params, ham, norb, nelec, n_reps, dtype=torch.complex128, device=0):
-        e, g = lucj_energy_grad(params.detach().cpu().numpy(), ham, norb, nelec, n_reps, dtype=dtype,
-                                device=device)
-        ctx.save_for_backward(torch.from_numpy(g).to(params.dtype))
+        p = params.detach().cpu().numpy()
+        if ctx.needs_input_grad[0]:
+            e, g = lucj_energy_grad(p, ham, norb, nelec, n_reps, dtype=dtype, device=device)
+            ctx.save_for_backward(torch.from_numpy(g).to(params.dtype))
+        else:
+            psi = apply_lucj(p, norb, nelec, n_reps, dtype=dtype, device=device)
+            e = df_energy(psi, ham, norb, nelec)
         return params.new_tensor(e)
 
     @staticmethod
     def backward(ctx, g_out):
         (g,) = ctx.saved_tensors
         return g_out * g, None, None, None, None, None, None
+
+
+class _DFTerms:
+    """(h, J, U) of a DF Hamiltonian as host arrays."""
+
+    def __init__(self, h, J, U):
+        self.h, self.J, self.U = h, J, U
+
+
+class DFChainEnergy(torch.autograd.Function):
+    """E = Re <psi_T|H_obs|psi_T>, psi_T = S_0(dt)^n_steps vec0 under the DF Hamiltonian (h, J, U)
+    (Sec. 4.5.3), differentiable in h, J and U by the library's adjoint method (ffx_df_chain_energy_grad:
+    the costate is pulled back through every gate while psi is uncomputed; no state is stored).
+
+    forward(h (N x N float64), J (L x N x N float64), U (L x N x N complex128 unitaries), vec0 (device
+    state), obs (the fixed observable, any object with h, J, U), dt, n_steps, norb, nelec) -> 0-dim
+    float64 tensor.
+
+    Gradients, in PyTorch's conventions:
+      * h and J_t enter through their symmetric parts, so the entry (p, q) off the diagonal receives half
+        of the library's derivative for moving h_pq and h_qp together, a diagonal entry all of it;
+      * for U the library differentiates along U_t -> U_t expm(A - A^dag) at A = 0; for the skew-Hermitian
+        direction Y = U_t^dag dU_t that is dE = Re sum conj(G) Y with G = (dE/dRe A + i dE/dIm A) / 2, and
+        the gradient returned is U_t G (dE = Re sum conj(grad) dU for every dU that keeps U_t unitary).
+    When none of h, J, U needs a gradient, forward runs the product formula and the energy only.
+    """
+
+    @staticmethod
+    def forward(ctx, h, J, U, vec0, obs, dt, n_steps, norb, nelec):
+        ham = _DFTerms(h.detach().cpu().numpy(), J.detach().cpu().numpy(), U.detach().cpu().numpy())
+        if any(ctx.needs_input_grad[:3]):
+            e, g = df_chain_energy_grad(vec0, ham, obs, dt, n_steps, norb, nelec)
+            gh = torch.from_numpy(0.5 * (g["h"] + np.diag(np.diag(g["h"]))))
+            gJ = torch.from_numpy(0.5 * (g["J"] + g["J"] * np.eye(norb)))
+            G = torch.from_numpy(0.5 * (g["U"][:, 0] + 1j * g["U"][:, 1]))
+            gU = U.detach().cpu().to(torch.complex128) @ G
+            ctx.save_for_backward(gh.to(h.dtype), gJ.to(J.dtype), gU.to(U.dtype))
+        else:
+            psi = simulate_trotter_double_factorized(vec0, ham, dt * n_steps, norb, nelec, n_steps=n_steps, order=0)
+            e = df_energy(psi, obs, norb, nelec)
+        return h.new_tensor(e)
+
+    @staticmethod
+    def backward(ctx, g_out):
+        gh, gJ, gU = ctx.saved_tensors
+        return g_out * gh, g_out * gJ, g_out * gU, None, None, None, None, None, None
 
 
 # ---------------------------------------------------------------------------

@@ -237,6 +237,19 @@ def hubbard_2d(nx: int, ny: int, t: float = 1.0, U: float = 8.0, periodic_x: boo
     return DFHamiltonian(h=h, J=(U * np.eye(n))[None], U=np.eye(n, dtype=np.complex128)[None])
 
 
+def hubbard_2d_diag_coulomb(nx: int, ny: int, t: float = 1.0, U: float = 8.0, periodic_x: bool = True,
+                            periodic_y: bool = False):
+    """The same 2D Hubbard model as a diagonal Coulomb Hamiltonian (Eq. diagonal-coulomb-hamiltonian), as
+    printed: (h, J_aa, J_ab, J_bb) with h the hopping matrix, J_aa = J_bb = 0 and J_ab = U * I, so that
+    1/2 sum J^{st}_pq n_ps n_qt = U sum_p n_pa n_pb."""
+    n = nx * ny
+    h = np.zeros((n, n))
+    for p, q in lattice_edges(nx, ny, periodic_x, periodic_y):
+        h[p, q] -= t
+        h[q, p] -= t
+    return h, np.zeros((n, n)), U * np.eye(n), np.zeros((n, n))
+
+
 def hubbard_filling(nx: int, ny: int, fraction: float = 0.125) -> tuple:
     """(n_alpha, n_beta) for a filling fraction of the 2 nx ny spin orbitals
     (the paper's 1/8 filling: nx ny / 4 electrons), alpha taking the odd one."""

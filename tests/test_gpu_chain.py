@@ -65,3 +65,60 @@ def test_df_chain_final_state_and_no_hermitian_component(ffx):
     assert np.allclose(g["U"][:, 0], -np.transpose(g["U"][:, 0], (0, 2, 1)), atol=1e-12)
     # the input state is not modified
     assert np.array_equal(x.cpu().numpy(), vec0)
+
+
+def test_df_chain_autograd_function(ffx):
+    """DFChainEnergy: the gradients PyTorch receives for h, J and U, checked as directional derivatives
+    against central differences of the oracle's chain energy (a random symmetric direction for h and J,
+    U_t -> U_t expm(+-eps Y) with Y skew-Hermitian for U), and the energy without gradients."""
+    import scipy.linalg
+    norb, nelec, L, r, dt = 5, (2, 3), 2, 2, 0.12
+    ham, obs, vec0 = _case(norb, nelec, L, 95)
+    rng = synth.rng(96)
+    ham.U = np.array([synth.random_unitary(rng, norb) for _ in range(L)])
+    x = torch.from_numpy(vec0).to("cuda:0")
+    h = torch.tensor(ham.h, requires_grad=True)
+    J = torch.tensor(ham.J, requires_grad=True)
+    U = torch.tensor(ham.U, requires_grad=True)
+    E = ffx.DFChainEnergy.apply(h, J, U, x, obs, dt, r, norb, nelec)
+    E.backward()
+    e_ref = oh.df_chain_energy(vec0, ham, obs, dt, r, norb, nelec)
+    assert abs(E.item() - e_ref) <= 1e-12 * max(1.0, abs(e_ref))
+
+    def energy(hh, JJ, UU):
+        return oh.df_chain_energy(vec0, synth.DFHamiltonian(h=hh, J=JJ, U=UU), obs, dt, r, norb, nelec)
+
+    eps = 1e-5
+    dh = synth.random_symmetric(rng, norb, 1.0)
+    dJ = np.array([synth.random_symmetric(rng, norb, 1.0) for _ in range(L)])
+    Y = np.array([synth.random_hermitian(rng, norb, 1.0) * 1j for _ in range(L)])
+    fd_h = (energy(ham.h + eps * dh, ham.J, ham.U) - energy(ham.h - eps * dh, ham.J, ham.U)) / (2 * eps)
+    fd_J = (energy(ham.h, ham.J + eps * dJ, ham.U) - energy(ham.h, ham.J - eps * dJ, ham.U)) / (2 * eps)
+    Up = np.array([ham.U[t] @ scipy.linalg.expm(eps * Y[t]) for t in range(L)])
+    Um = np.array([ham.U[t] @ scipy.linalg.expm(-eps * Y[t]) for t in range(L)])
+    fd_U = (energy(ham.h, ham.J, Up) - energy(ham.h, ham.J, Um)) / (2 * eps)
+    got_h = float(np.sum(h.grad.numpy() * dh))
+    got_J = float(np.sum(J.grad.numpy() * dJ))
+    dU = np.array([ham.U[t] @ Y[t] for t in range(L)])
+    got_U = float(np.real(np.sum(np.conj(U.grad.numpy()) * dU)))
+    scale = max(1.0, abs(fd_h), abs(fd_J), abs(fd_U))
+    for name, got, fd in (("h", got_h, fd_h), ("J", got_J, fd_J), ("U", got_U, fd_U)):
+        err = abs(got - fd) / scale
+        assert record("df_chain_autograd_" + name, torch.complex128, "grad_rel", err, 1e-7) <= 1e-7, (name, got, fd)
+    # no gradient requested: the energy alone
+    with torch.no_grad():
+        E0 = ffx.DFChainEnergy.apply(h.detach(), J.detach(), U.detach(), x, obs, dt, r, norb, nelec)
+    assert abs(E0.item() - E.item()) <= 1e-12 * max(1.0, abs(E.item()))
+
+
+def test_lucj_energy_without_gradient(ffx):
+    """LUCJEnergy on parameters that need no gradient takes the forward pass and the energy only."""
+    from oracle import lucj as ol
+    norb, nelec, n_reps = 6, (3, 2), 2
+    r = synth.rng(97)
+    p = torch.tensor(synth.lucj_params(r, norb, n_reps, scale=0.3))
+    ham = synth.df_hamiltonian(r, norb, 2)
+    E = ffx.LUCJEnergy.apply(p, ham, norb, nelec, n_reps)
+    eo = float(np.real(ol.energy(p.numpy(), ham, norb, nelec, n_reps)))
+    assert abs(E.item() - eo) <= 1e-12 * max(1.0, abs(eo))
+    assert not E.requires_grad

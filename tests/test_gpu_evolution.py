@@ -240,3 +240,59 @@ def test_hamiltonian_action_identity_basis_terms(ffx, monkeypatch, dtype):
         monkeypatch.setenv("FFX_ONEBODY", mode)
         out = ffx.apply_df_hamiltonian(vec, ham, norb, nelec)
         assert _maxdiff(out, ref) <= HTOL[dtype] * max(1.0, float(np.abs(ref).max())), mode
+
+
+DC_TOL = {torch.complex128: 1e-12, torch.complex64: 1e-5}
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("order,n_steps", [(0, 1), (0, 3), (1, 2), (2, 1)])
+@pytest.mark.parametrize("norb,nelec", [(6, (3, 2)), (9, (4, 4)), (12, (6, 5)), (5, (0, 3))])
+def test_diag_coulomb_trotter(ffx, dtype, order, n_steps, norb, nelec):
+    """Product formulas of the diagonal Coulomb Hamiltonian with spin-resolved J (J_aa != J_bb, a
+    non-symmetric J_ab) against the oracle."""
+    print(f"diag Coulomb Trotter norb={norb} nelec={nelec} order={order} steps={n_steps} {dtype}", flush=True)
+    r = synth.rng([49, norb, order, n_steps])
+    h = synth.random_symmetric(r, norb, 1.0)
+    Jaa, Jbb = synth.random_symmetric(r, norb, 0.5), synth.random_symmetric(r, norb, 0.5)
+    Jab = r.normal(0, 0.5, (norb, norb))
+    vec = _to_dev(synth.random_state(r, *_dims(norb, nelec)), dtype)
+    x = _host(vec)
+    T = 0.3 * n_steps
+    out = ffx.simulate_trotter_diag_coulomb(vec, h, Jaa, T, norb, nelec, J_ab=Jab, J_bb=Jbb, n_steps=n_steps,
+                                            order=order)
+    ref = oh.simulate_trotter_diag_coulomb(x, h, Jaa, T, norb, nelec, Jab, Jbb, n_steps, order)
+    err = record("diag_coulomb_trotter", dtype, "amplitude", _maxdiff(out, ref), DC_TOL[dtype], norb=norb,
+                 order=order, n_steps=n_steps)
+    assert err <= DC_TOL[dtype]
+    assert _maxdiff(vec, x) == 0.0  # functional form leaves the input alone
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("nx,ny", [(4, 2), (4, 3), (4, 4)])
+def test_hubbard_diag_coulomb_route_equals_df_route(ffx, dtype, nx, ny):
+    """The Hubbard model Trotterized as a diagonal Coulomb Hamiltonian (J_ab = U I, as printed) and through
+    its DF form give the same state (their terms differ by phases of the conserved total number)."""
+    norb, nelec = nx * ny, synth.hubbard_filling(nx, ny)
+    h, Jaa, Jab, Jbb = synth.hubbard_2d_diag_coulomb(nx, ny)
+    ham = synth.hubbard_2d(nx, ny)
+    vec = _to_dev(synth.random_state(synth.rng([50, nx, ny]), *_dims(norb, nelec)), dtype)
+    for order, n in ((0, 2), (1, 2), (2, 1)):
+        a = ffx.simulate_trotter_diag_coulomb(vec, h, Jaa, 1.0, norb, nelec, J_ab=Jab, J_bb=Jbb, n_steps=n,
+                                              order=order)
+        b = ffx.simulate_trotter_double_factorized(vec, ham, 1.0, norb, nelec, n_steps=n, order=order)
+        err = record("hubbard_dc_vs_df_route", dtype, "amplitude", _maxdiff(a, _host(b)), DC_TOL[dtype],
+                     lattice=[nx, ny], order=order)
+        assert err <= DC_TOL[dtype]
+
+
+def test_diag_coulomb_trotter_arguments(ffx):
+    norb, nelec = 4, (2, 2)
+    vec = _to_dev(synth.random_state(synth.rng(51), 6, 6), torch.complex128)
+    h = np.arange(16.0).reshape(4, 4)  # not symmetric
+    with pytest.raises(ffx.FFXError):
+        ffx.simulate_trotter_diag_coulomb(vec, h, np.eye(4), 0.1, norb, nelec)
+    with pytest.raises(ffx.FFXError):
+        ffx.simulate_trotter_diag_coulomb(vec, np.eye(4), np.eye(4), float("nan"), norb, nelec)
+    out = ffx.simulate_trotter_diag_coulomb(vec, np.eye(4), np.eye(4), 0.1, norb, nelec, n_steps=0)
+    assert _maxdiff(out, _host(vec)) == 0.0

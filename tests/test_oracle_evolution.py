@@ -17,6 +17,7 @@ import scipy.linalg
 
 from oracle import gates as g
 from oracle import hamiltonian as H
+from oracle import hamiltonian as oh
 from oracle import strings as st
 from paper_2605_03123_amd import synth
 from jw import Fock
@@ -146,3 +147,68 @@ def test_trotter_error_limits():
     assert H.trotter_error(vec, free, 1.0, 8, nelec, 1, 0) < 1e-12
     # zero time
     assert H.trotter_error(vec, synth.hubbard_2d(nx, ny), 0.0, 8, nelec, 1, 1) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Trotter steps of the diagonal Coulomb Hamiltonian (Eq. diagonal-coulomb-hamiltonian, Sec. 4.5.3)
+# ---------------------------------------------------------------------------
+
+def _dc_case(seed, norb=3):
+    r = synth.rng(seed)
+    h = synth.random_symmetric(r, norb, 1.0)
+    Jaa, Jbb = synth.random_symmetric(r, norb, 0.8), synth.random_symmetric(r, norb, 0.8)
+    Jab = r.normal(0, 0.8, (norb, norb))  # J^{ba} = J_ab^T, so J_ab need not be symmetric
+    return h, Jaa, Jab, Jbb
+
+
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_diag_coulomb_trotter_single_term_is_exact(order):
+    """With one of the two terms zero, every product formula is the exact evolution of the other, which
+    the Fock space gives as the exponential of its generator (one-body term, spin-resolved J)."""
+    norb, nelec, T = 3, (1, 2), 0.7
+    h, Jaa, Jab, Jbb = _dc_case(62)
+    F = Fock(norb)
+    vec = synth.random_state(synth.rng(63), 3, 3)
+    Z = np.zeros((norb, norb))
+    for hh, (a, b, c) in ((h, (Z, Z, Z)), (Z, (Jaa, Jab, Jbb))):
+        H = F.restrict(F.one_body(hh) + F.diag_coulomb_gen(a, b, c), nelec)
+        ref = (scipy.linalg.expm(-1j * T * H) @ vec.reshape(-1)).reshape(vec.shape)
+        got = oh.simulate_trotter_diag_coulomb(vec, hh, a, T, norb, nelec, J_ab=b, J_bb=c, n_steps=2, order=order)
+        np.testing.assert_allclose(got, ref, atol=1e-13)
+
+
+@pytest.mark.parametrize("order,ratio", [(0, 2.0), (1, 4.0), (2, 16.0)])
+def test_diag_coulomb_trotter_error_order(order, ratio):
+    """Against the Fock-space exp(-i T H) of the whole Hamiltonian: doubling the steps divides the error by
+    2, 4 and 16 for S_0, S_1 and S_2 (a dropped, misplaced or mis-timed term breaks the order)."""
+    norb, nelec, T = 3, (2, 1), 0.5
+    h, Jaa, Jab, Jbb = _dc_case(64)
+    F = Fock(norb)
+    H = F.restrict(F.one_body(h) + F.diag_coulomb_gen(Jaa, Jab, Jbb), nelec)
+    vec = synth.random_state(synth.rng(65), 3, 3)
+    exact = (scipy.linalg.expm(-1j * T * H) @ vec.reshape(-1)).reshape(vec.shape)
+    np.testing.assert_allclose(oh.apply_diag_coulomb_hamiltonian(vec, h, Jaa, norb, nelec, Jab, Jbb).reshape(-1),
+                               H @ vec.reshape(-1), atol=1e-13)
+    n = 8 if order < 2 else 4
+    e1 = np.linalg.norm(oh.simulate_trotter_diag_coulomb(vec, h, Jaa, T, norb, nelec, Jab, Jbb, n, order) - exact)
+    e2 = np.linalg.norm(oh.simulate_trotter_diag_coulomb(vec, h, Jaa, T, norb, nelec, Jab, Jbb, 2 * n, order) - exact)
+    assert abs(e1 / e2 - ratio) <= 0.15 * ratio, (e1, e2)
+
+
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_hubbard_as_diag_coulomb_equals_df_form(order):
+    """The Hubbard model as printed (J_ab = U I) and its DF form (one identity-basis term J = U I with h shifted
+    by -U/2) differ term by term only by phases of the total number operator, which is constant in a sector:
+    their product formulas agree, and the diagonal Coulomb form is the model on the Fock space."""
+    nx, ny = 4, 1
+    norb, nelec = 4, (2, 1)
+    h, Jaa, Jab, Jbb = synth.hubbard_2d_diag_coulomb(nx, ny)
+    F = Fock(norb)
+    hop = F.one_body(h)
+    nn = sum(F.n(p, 0) @ F.n(p, 1) for p in range(norb))
+    np.testing.assert_allclose(F.one_body(h) + F.diag_coulomb_gen(Jaa, Jab, Jbb), hop + 8.0 * nn, atol=1e-13)
+    vec = synth.random_state(synth.rng(66), 6, 4)
+    got = oh.simulate_trotter_diag_coulomb(vec, h, Jaa, 0.6, norb, nelec, Jab, Jbb, n_steps=3, order=order)
+    ref = oh.simulate_trotter(vec, synth.hubbard_2d(nx, ny, periodic_x=True), 0.6, norb, nelec, n_steps=3,
+                              order=order)
+    np.testing.assert_allclose(got, ref, atol=1e-13)

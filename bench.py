@@ -427,6 +427,50 @@ def hubbard_timing(ffx, torch, synth, nx, ny, time_T=1.0, oracle_side=(4, 4)):
     return res
 
 
+def dense_vs_givens(ffx, torch, synth, reps=20):
+    """One orbital rotation (complex Haar U, both spins) at half filling, complex128, state resident: the
+    Givens sweeps (ffx_apply_orbital_rotation) against the dense compound-matrix form on the FP64 matrix
+    cores (ffx_apply_orbital_rotation_dense: compound matrices built on the device, two complex products).
+    Mean of `reps` calls after two warm-ups, HIP events on the launch stream; algorithmic flops
+    20 n (N - n) d^2 (Givens, both spins, complex s) and 16 d^3 (dense, two complex GEMMs)."""
+    from math import comb
+    dev = torch.device("cuda:0")
+    out = {}
+    for norb in (8, 10, 12, 14):
+        n = norb // 2
+        d = comb(norb, n)
+        r = synth.rng([73, norb])
+        vec = torch.from_numpy(synth.random_state(r, d, d)).to(dev)
+        U = synth.random_unitary(r, norb)
+        res = {"d": d}
+        # the Givens sweeps on a plan that never takes the dense form (small sectors otherwise would)
+        os.environ["FFX_DENSE"] = "0"
+        try:
+            gplan = ffx.Plan(norb, (n, n), torch.complex128)
+        finally:
+            del os.environ["FFX_DENSE"]
+        dplan = ffx.get_plan(norb, (n, n), torch.complex128, 0)
+        for name, fn, plan in (("givens", ffx.apply_orbital_rotation, gplan),
+                               ("dense_mfma", ffx.apply_orbital_rotation_dense, dplan)):
+            for _ in range(2):
+                fn(vec, U, norb, (n, n), out=vec, plan=plan)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn(vec, U, norb, (n, n), out=vec, plan=plan)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            flop = 20.0 * n * (norb - n) * d * d if name == "givens" else 16.0 * d ** 3
+            res[name] = {"ms": round(ms, 5), "alg_TFLOPs": round(flop / (ms * 1e-3) / 1e12, 3)}
+        res["dense_over_givens"] = round(res["dense_mfma"]["ms"] / res["givens"]["ms"], 3)
+        out[f"norb{norb}_({n},{n})"] = res
+        del vec
+    torch.cuda.empty_cache()
+    return out
+
+
 def table1_timing(ffx, torch, synth):
     """Time per call of the Table 1 gates, the Slater-determinant state and a UCJ forward pass (n_reps = 3,
     per-spin rotations, full J) at norb = 16, (8, 8), complex128, state resident on the device."""
@@ -499,6 +543,9 @@ def main():
     ap.add_argument("--table1-only", action="store_true",
                     help="run only the Table 1 gates and sampling leg (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--dense-only", action="store_true",
+                    help="run only the dense-vs-Givens rotation leg (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the state of this workload fits one MI355X and the build has no "
@@ -517,6 +564,9 @@ def main():
         return
     if args.table1_only:
         print(json.dumps({"table1_gates_n16_c128": table1_timing(ffx, torch, synth)}), flush=True)
+        return
+    if args.dense_only:
+        print(json.dumps({"rotation_dense_vs_givens_c128": dense_vs_givens(ffx, torch, synth)}), flush=True)
         return
 
     types = {"c128": torch.complex128, "c64": torch.complex64}
@@ -578,6 +628,8 @@ def main():
                               "c64": n18_timing(ffx, torch, synth, torch.complex64)}
     if not args.no_table1:
         out["table1_gates_n16_c128"] = table1_timing(ffx, torch, synth)
+    if not args.no_dense:
+        out["rotation_dense_vs_givens_c128"] = dense_vs_givens(ffx, torch, synth)
     if not args.no_hubbard:
         out["trotter_error_hubbard"] = hubbard_timing(ffx, torch, synth, 4, args.hubbard_y)
     if not args.no_cpu_baseline:

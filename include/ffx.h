@@ -90,6 +90,19 @@ int ffx_plan_strings(ffx_plan plan, int spin, uint64_t* out_masks);
 int ffx_apply_orbital_rotation(ffx_plan plan, void* vec, const double* U_a, const double* U_b,
                                void* stream);
 
+/* The same orbital rotation in its dense form (Sec. 2.3: script-U(U) acts on
+   the sector as the compound matrices, Gamma' = C_{n_a}(U_a) Gamma
+   C_{n_b}(U_b)^T with C_n(U)[J, I] = det U[J, I] over ascending occupied
+   orbitals): the compound matrices are built on the device, then two complex
+   products run on the FP64 matrix cores.  It costs 16 d^3 flops against the
+   Givens sweeps' 20 n (N - n) d^2 and exists to be measured against them on
+   small sectors.  complex128 plans with at most 8 electrons and 4096
+   configurations per spin (FFX_EUNSUPPORTED otherwise).  workspace: device
+   buffer of ffx_workspace_bytes(plan, 3) bytes (the two compound matrices and
+   one intermediate state).  Enqueues only; FFX_ENOTUNITARY as above. */
+int ffx_apply_orbital_rotation_dense(ffx_plan plan, void* vec, const double* U_a, const double* U_b,
+                                     void* workspace, void* stream);
+
 /* Number-operator-sum evolution exp(-i t sum_{p,sigma} lam^sigma_p n_{p sigma})
    (Table 1, Sec. 3.2.1).  lam_a, lam_b: norb real; lam_b = NULL means lam_a.
    basis_U (complex norb x norb, NULL = none): the number operators of the
@@ -258,7 +271,7 @@ int ffx_apply_lucj(ffx_plan plan, void* vec, const ffx_lucj* op, void* stream);
 
 /* Workspace size in bytes: what = 0 for ffx_df_energy and
    ffx_apply_df_hamiltonian (one state), 1 for the gradients, 2 for
-   ffx_df_evolve_exact (four states). */
+   ffx_df_evolve_exact (four states), 3 for ffx_apply_orbital_rotation_dense. */
 int64_t ffx_workspace_bytes(ffx_plan plan, int what);
 
 /* Energy <psi|H|psi> of vec for the DF Hamiltonian (Sec. 4.2), evaluated as
@@ -333,8 +346,9 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
                          k >= N^2 is d/d Im A_pq (the LUCJ layout)
    grad_J / grad_U may be NULL only when ham->n_terms == 0.  workspace:
    ffx_workspace_bytes(plan, 1) bytes; psi_out (device, may be NULL) receives
-   psi_T.  Synchronizes the stream.  FFX_EUNSUPPORTED when
-   9 N^2 n_terms + 4 N^2 exceeds 65536. */
+   psi_T.  Synchronizes the stream.  The plan's device result block grows to
+   9 N^2 n_terms + 4 N^2 doubles when needed (that first call waits for the
+   device before replacing it). */
 int ffx_df_chain_energy_grad(ffx_plan plan, const void* vec0, const ffx_df_ham* ham, const ffx_df_ham* obs,
                              double dt, int n_steps, double* energy, double* grad_h, double* grad_J,
                              double* grad_U, void* psi_out, void* workspace, void* stream);

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libffx.so")
-SOURCES = ["host.cpp", "drivers.cpp", "api.cpp", "gates.cpp", "sampling.cpp", "program.cpp", "batch.cpp", "kernels.hip", "segpass.hip", "batched.hip", "sample.hip"]
+SOURCES = ["host.cpp", "drivers.cpp", "api.cpp", "gates.cpp", "sampling.cpp", "program.cpp", "batch.cpp", "kernels.hip", "segpass.hip", "batched.hip", "sample.hip", "dense.hip"]
 
 
 def hipcc() -> str:

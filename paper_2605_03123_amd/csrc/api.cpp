@@ -277,6 +277,7 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
                                   2 * dev::inner_partials(P->dim[0] * P->dim[1]));
     P->partials = (double*)P->dalloc((size_t)P->n_partials * 8);
     P->results = (double*)P->dalloc((size_t)ffx_plan_s::kResults * 8);
+    P->results_cap = ffx_plan_s::kResults;
     P->rowout = (double*)P->dalloc((size_t)dmax * 2 * norb * 8);
     P->arena_doubles = (size_t)ffx_plan_s::kArenaSlots * (size_t)(P->dim[0] + P->dim[1]);
     P->arena = (double*)P->dalloc(P->arena_doubles * 8);
@@ -288,6 +289,11 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
     // the row-pair transition one-body kernel (the path above 16 orbitals) at
     // any size, for tests
     P->rdm_pairs = std::getenv("FFX_RDM_PAIRS") != nullptr;
+    // FFX_DENSE=0 keeps every orbital rotation on the Givens sweeps (as do the forced small segments of
+    // FFX_SEG_MAX, whose purpose is to run those sweeps' crossing paths at small sizes)
+    if (const char* e = std::getenv("FFX_DENSE")) P->dense_max_dim = std::atoll(e) > 0 ? std::atoll(e) : 0;
+    if (std::getenv("FFX_SEG_MAX")) P->dense_max_dim = 0;
+    if (P->c64 || P->n[0] > 8 || P->n[1] > 8) P->dense_max_dim = 0;
     if (const char* e = std::getenv("FFX_SEG_MAX")) {  // smaller segments, for tests
       int64_t v = std::atoll(e);
       if (v >= 1 && v < max_elems) max_elems = v;
@@ -312,16 +318,9 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
       bool packed = false;
       int wt = norb;
       for (; wt >= 0; --wt) {
-        segs.clear();
-        size_t i = 0;
+        segs = segment_runs(strs, wt);
         int64_t longest = 0;
-        while (i < strs.size()) {
-          size_t j = i;
-          while (j < strs.size() && (strs[j] >> wt) == (strs[i] >> wt)) ++j;
-          segs.push_back({(int)i, (int)(j - i)});
-          longest = std::max<int64_t>(longest, (int64_t)(j - i));
-          i = j;
-        }
+        for (const auto& r : segs) longest = std::max<int64_t>(longest, r.second);
         if (longest > max_elems) continue;
         // Runs are contiguous in colex order.  At low filling most runs are
         // short (a handful of configurations per occupation of the top
@@ -341,13 +340,7 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
           }
           const size_t fixed = dev::seg_pass_lds(P->c64, 0, (int)mt_bound);
           const int64_t cap = fixed < lds_cap ? std::min<int64_t>(max_elems, (int64_t)((lds_cap - fixed) / P->elem())) : 0;
-          std::vector<std::pair<int, int>> groups;
-          for (const auto& r : segs) {
-            if (!groups.empty() && groups.back().second + r.second <= cap)
-              groups.back().second += r.second;
-            else
-              groups.push_back(r);
-          }
+          std::vector<std::pair<int, int>> groups = pack_runs(segs, cap);
           if (groups.size() * 4 <= segs.size() * 3) {
             segs = std::move(groups);
             packed = true;
@@ -418,31 +411,14 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
       // remaining k - 1 low orbitals.  Packed segments leave that rotation to
       // the window passes.
       if (wt >= 1 && wt < norb && segs.size() > 1 && !packed) {
-        std::map<uint64_t, int> by_high;
-        for (size_t g = 0; g < segs.size(); ++g) by_high[strs[segs[g].first] >> wt] = (int)g;
-        const int nc = s == 0 ? na : nb;
+        const auto cr = crossing_ranges(strs, segs, wt, s == 0 ? na : nb);
         for (size_t g = 0; g < segs.size(); ++g) {
-          const uint64_t H = strs[segs[g].first] >> wt;
-          const int k = nc - __builtin_popcountll(H);
+          if (!cr[g].has) continue;
           dev::SegDev& d = hsegs[g];
-          const bool holds_wt = H & 1;
-          const auto it = by_high.find(H ^ 1);
-          if (it == by_high.end()) continue;
-          const auto& pg = segs[it->second];
-          if (!holds_wt) {
-            if (k < 1) continue;
-            d.cross_role = 0;
-            d.cross_lo = (int)binom(wt - 1, k);
-            d.cross_cnt = (int)binom(wt - 1, k - 1);
-            d.cross_peer = pg.first;
-          } else {
-            d.cross_role = 1;
-            d.cross_lo = 0;
-            d.cross_cnt = (int)binom(wt - 1, k);
-            d.cross_peer = pg.first + (int)binom(wt - 1, k + 1);
-          }
-          if (d.cross_lo + d.cross_cnt > segs[g].second || d.cross_cnt > pg.second)
-            throw Error(FFX_EDEVICE, "segment crossing ranges out of bounds");
+          d.cross_role = cr[g].role;
+          d.cross_lo = cr[g].lo;
+          d.cross_cnt = cr[g].cnt;
+          d.cross_peer = cr[g].peer;
           ss.cross = true;
         }
       }
@@ -490,6 +466,11 @@ int ffx_plan_strings(ffx_plan plan, int spin, uint64_t* out) {
   });
 }
 
+namespace {
+void rotate_dense(ffx_plan_s& P, void* vec, const double* U_a, const double* U_b, void* workspace, hipStream_t s);
+void check_rotation_args(int N, const double* U_a, const double* U_b);
+}  // namespace
+
 int ffx_apply_orbital_rotation(ffx_plan plan, void* vec, const double* U_a, const double* U_b, void* stream) {
   return guard([&] {
     validate_plan(plan);
@@ -499,6 +480,13 @@ int ffx_apply_orbital_rotation(ffx_plan plan, void* vec, const double* U_a, cons
       throw Error(FFX_EINVAL, "non-finite U");
     DeviceGuard dg(plan->device);
     hipStream_t s = as_stream(stream);
+    if (plan->dim[0] <= plan->dense_max_dim && plan->dim[1] <= plan->dense_max_dim) {
+      // small sector: the dense form is the faster one (measured)
+      check_rotation_args(N, U_a, U_b);
+      if (!plan->dense_ws) plan->dense_ws = plan->dalloc((size_t)ffx_workspace_bytes(plan, 3));
+      rotate_dense(*plan, vec, U_a, U_b, plan->dense_ws, s);
+      return;
+    }
     auto Ua = load_complex(N, U_a);
     std::vector<cd> Ub;
     if (U_b) Ub = load_complex(N, U_b);
@@ -511,6 +499,58 @@ int ffx_apply_orbital_rotation(ffx_plan plan, void* vec, const double* U_a, cons
     Compiled c = compile_program(*plan, up, pr, FINAL_STORE, s);
     up.commit();
     execute_program(*plan, c, vec, vec, nullptr, s);
+  });
+}
+
+namespace {
+// Gamma' = C_a Gamma C_b^T: compound matrices on the device, then two complex products on the FP64 matrix
+// cores; workspace holds C_a, C_b and the intermediate (ffx_workspace_bytes(plan, 3))
+void rotate_dense(ffx_plan_s& P, void* vec, const double* U_a, const double* U_b, void* workspace, hipStream_t s) {
+  const int N = P.norb;
+  const double* Ubp = U_b ? U_b : U_a;
+  {
+    const int64_t da = P.dim[0], db = P.dim[1];
+    auto r256 = [](int64_t b) { return (b + 255) / 256 * 256; };
+    char* ws = (char*)workspace;
+    void* Ca = ws;
+    void* Cb = ws + r256(da * da * 16);
+    void* T = (char*)Cb + r256(db * db * 16);
+    Upload up(&P, s);
+    const double* dUa = up.put(U_a, (size_t)2 * N * N);
+    const double* dUb = up.put(Ubp, (size_t)2 * N * N);
+    up.commit();
+    dev::compound_matrix(P.d_masks[0], da, P.n[0], N, dUa, Ca, s);
+    dev::compound_matrix(P.d_masks[1], db, P.n[1], N, dUb, Cb, s);
+    // T = Gamma C_b^T (element (k, n) of C_b^T is C_b[n][k]), then Gamma' = C_a T
+    dev::zgemm_mfma(vec, db, Cb, 1, db, T, db, (int)da, (int)db, (int)db, s);
+    dev::zgemm_mfma(Ca, da, T, db, 1, vec, db, (int)da, (int)db, (int)da, s);
+    check_launch();
+  }
+}
+
+void check_rotation_args(int N, const double* U_a, const double* U_b) {
+  if (!all_finite(U_a, (size_t)2 * N * N) || (U_b && !all_finite(U_b, (size_t)2 * N * N)))
+    throw Error(FFX_EINVAL, "non-finite U");
+  for (const double* u : {U_a, U_b}) {
+    if (!u) continue;
+    auto Um = load_complex(N, u);
+    if (unitarity_defect(N, Um.data()) > 1e-10) throw Error(FFX_ENOTUNITARY, "orbital rotation is not unitary");
+  }
+}
+}  // namespace
+
+int ffx_apply_orbital_rotation_dense(ffx_plan plan, void* vec, const double* U_a, const double* U_b, void* workspace,
+                                     void* stream) {
+  return guard([&] {
+    validate_plan(plan);
+    if (!vec || !U_a || !workspace) throw Error(FFX_EINVAL, "null vec, U_a or workspace");
+    ffx_plan_s& P = *plan;
+    if (P.c64) throw Error(FFX_EUNSUPPORTED, "the dense form is built for complex128 states");
+    if (P.n[0] > 8 || P.n[1] > 8 || P.dim[0] > 4096 || P.dim[1] > 4096)
+      throw Error(FFX_EUNSUPPORTED, "the dense form takes at most 8 electrons and 4096 configurations per spin");
+    check_rotation_args(P.norb, U_a, U_b);
+    DeviceGuard dg(P.device);
+    rotate_dense(P, vec, U_a, U_b, workspace, as_stream(stream));
   });
 }
 
@@ -781,6 +821,11 @@ int64_t ffx_workspace_bytes(ffx_plan plan, int what) {
   const int64_t S = ((int64_t)plan->state_bytes() + 255) / 256 * 256;
   if (what == 0) return S;
   if (what == 2) return 4 * S;
+  if (what == 3) {
+    auto r256 = [](int64_t b) { return (b + 255) / 256 * 256; };
+    return r256(plan->dim[0] * plan->dim[0] * 16) + r256(plan->dim[1] * plan->dim[1] * 16) +
+           r256(plan->dim[0] * plan->dim[1] * 16);
+  }
   const int64_t dmax = std::max(plan->dim[0], plan->dim[1]);
   const int64_t part = ((int64_t)plan->norb * plan->norb * dmax * 16 + 255) / 256 * 256;
   return 5 * S + part;
@@ -1082,6 +1127,8 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
     const int Lt = G->df.L;
     DeviceGuard dg(P.device);
     hipStream_t s = as_stream(stream);
+    // result block: energy, per repetition the transition matrices and the diagonal-gate gradients
+    P.results_for(16 + (size_t)R * (8 * (size_t)N * N + 2 * N), s);
     const size_t S = P.state_bytes();
     const size_t Sa = (S + 255) / 256 * 256;
     char* ws = (char*)workspace;
@@ -1126,8 +1173,6 @@ int ffx_lucj_energy_grad(ffx_plan plan, const ffx_lucj* op, const ffx_df_ham* ha
     const int NN = N * N;
     double* Tdev = P.results + 16;                     // per rep: T_b (alpha, beta), T_a (alpha, beta)
     double* Ddev = P.results + 16 + (size_t)R * 8 * NN;  // per rep: 2N-1 diagonal-gate gradients
-    if (16 + (size_t)R * (8 * NN + 2 * N) > (size_t)ffx_plan_s::kResults)
-      throw Error(FFX_EUNSUPPORTED, "too many LUCJ repetitions for the result buffer");
     auto rdm = [&](double* Tout) { transition_rdm(P, lam, psi, lamT, psiT, part, Tout, s); };
     for (int k = R - 1; k >= 0; --k) {
       execute_program(P, c_urot[k], psi, psi, nullptr, s);
@@ -1177,10 +1222,10 @@ int ffx_df_chain_energy_grad(ffx_plan plan, const void* vec0, const ffx_df_ham* 
     DFHost ob = load_df(P, obs);
     const int L = df.L;
     if (L > 0 && (!grad_J || !grad_U)) throw Error(FFX_EINVAL, "null gradient pointer");
-    if ((size_t)L * 9 * NN + 4 * NN > (size_t)ffx_plan_s::kResults)
-      throw Error(FFX_EUNSUPPORTED, "too many terms for the result buffer");
     DeviceGuard dg(P.device);
     hipStream_t s = as_stream(stream);
+    // result block: per term the transition matrices and the J gradient, then the observable's
+    P.results_for(std::max<size_t>(16, (size_t)L * 9 * NN + 4 * NN), s);
     const size_t S = P.state_bytes();
     const size_t Sa = (S + 255) / 256 * 256;
     char* ws = (char*)workspace;

@@ -94,6 +94,13 @@ void dist2(bool c64, const void* x, const void* y, int64_t n, double* partials, 
 int sample_blocks(int64_t n);
 int sample_state(bool c64, const void* vec, int64_t n, double* bs, double* pre, const double* u, int64_t n_samples,
                  int64_t* out, hipStream_t stream);
+// Dense form of an orbital rotation: C[J, I] = det U[J, I] over the n-electron
+// configurations (masks, d of them; U complex norb x norb, device), and the
+// complex128 product Y = A B on the FP64 matrix cores (A row-major with leading
+// dimension lda; element (k, n) of B at B[k * sbk + n * sbn]; Y row-major, ldy).
+void compound_matrix(const uint32_t* masks, int64_t d, int n, int norb, const double* U, void* C, hipStream_t s);
+void zgemm_mfma(const void* A, int64_t lda, const void* B, int64_t sbk, int64_t sbn, void* Y, int64_t ldy, int M,
+                int N, int K, hipStream_t s);
 // The allocation-free sampler's block sums and prefix live in a static device
 // array of 2 * kScratchBlocks doubles; sample_scratch returns its address on
 // `device` (which must be the current device; taken once per device).

@@ -371,6 +371,62 @@ SegWindowTable build_seg_window(const std::vector<uint64_t>& seg, int wt, int a,
   return t;
 }
 
+std::vector<std::pair<int, int>> segment_runs(const std::vector<uint64_t>& strs, int wt) {
+  std::vector<std::pair<int, int>> runs;
+  size_t i = 0;
+  while (i < strs.size()) {
+    size_t j = i;
+    const uint64_t hi = wt >= 64 ? 0 : strs[i] >> wt;
+    while (j < strs.size() && (wt >= 64 ? 0 : strs[j] >> wt) == hi) ++j;
+    runs.push_back({(int)i, (int)(j - i)});
+    i = j;
+  }
+  return runs;
+}
+
+std::vector<std::pair<int, int>> pack_runs(const std::vector<std::pair<int, int>>& runs, int64_t cap) {
+  std::vector<std::pair<int, int>> groups;
+  for (const auto& r : runs) {
+    if (!groups.empty() && (int64_t)groups.back().second + r.second <= cap)
+      groups.back().second += r.second;
+    else
+      groups.push_back(r);
+  }
+  return groups;
+}
+
+std::vector<CrossRange> crossing_ranges(const std::vector<uint64_t>& strs, const std::vector<std::pair<int, int>>& runs,
+                                        int wt, int n) {
+  std::vector<CrossRange> out(runs.size());
+  std::map<uint64_t, int> by_high;
+  for (size_t g = 0; g < runs.size(); ++g) by_high[strs[runs[g].first] >> wt] = (int)g;
+  for (size_t g = 0; g < runs.size(); ++g) {
+    const uint64_t H = strs[runs[g].first] >> wt;
+    const int k = n - __builtin_popcountll(H);
+    const auto it = by_high.find(H ^ 1);
+    if (it == by_high.end()) continue;
+    const auto& pg = runs[it->second];
+    CrossRange& d = out[g];
+    if (!(H & 1)) {
+      if (k < 1) continue;
+      d.has = true;
+      d.role = 0;
+      d.lo = (int)binom(wt - 1, k);
+      d.cnt = (int)binom(wt - 1, k - 1);
+      d.peer = pg.first;
+    } else {
+      d.has = true;
+      d.role = 1;
+      d.lo = 0;
+      d.cnt = (int)binom(wt - 1, k);
+      d.peer = pg.first + (int)binom(wt - 1, k + 1);
+    }
+    if (d.lo + d.cnt > runs[g].second || d.cnt > pg.second)
+      throw Error(FFX_EDEVICE, "segment crossing ranges out of bounds");
+  }
+  return out;
+}
+
 void balance_seg_window(SegWindowTable& t, int w, int nwaves) {
   constexpr int kSimds = 4;
   if (nwaves < kSimds || nwaves % kSimds != 0 || t.chunk_m.empty()) return;

@@ -60,7 +60,8 @@ struct ffx_plan_s {
   double* dV = nullptr;
   double* partials = nullptr;
   int n_partials = 0;
-  double* results = nullptr;  // kResults doubles
+  double* results = nullptr;  // results_cap doubles (kResults at creation, grown by results_for)
+  size_t results_cap = 0;
   double* rowout = nullptr;
   void* state_tmp = nullptr;   // one state, allocated on first need
   double* arena = nullptr;     // per-program diagonal tables
@@ -121,6 +122,11 @@ struct ffx_plan_s {
   int* rank_lo = nullptr;
   int* rank_hi = nullptr;
   bool rdm_pairs = false;  // transition one-body matrices from row pairs at any size
+  // standalone orbital rotations of complex128 sectors with at most this many
+  // configurations per spin take the dense form on the matrix cores (measured
+  // faster than the Givens sweeps at 70 configurations, even at 252, slower above)
+  int64_t dense_max_dim = 128;
+  void* dense_ws = nullptr;  // its compound matrices and intermediate, allocated on first use
   // per column spin: the (n-1)-electron strings for the matrix-core transition
   // one-body kernel, grouped by their top occupation, built on first use
   struct RdmStrings {
@@ -134,6 +140,21 @@ struct ffx_plan_s {
   void* arena_ctx = nullptr;
   int max_stage_rots = ffx::dev::kMaxStageRots;  // Givens rotations per stage (fusion depth)
   static constexpr int kArenaSlots = 64;
+  // the device result block, grown to at least `doubles` (waits for the device
+  // before freeing the old block, which earlier work on any stream may still use)
+  double* results_for(size_t doubles, hipStream_t s) {
+    if (doubles > results_cap) {
+      HIPCHK(hipStreamSynchronize(s));
+      HIPCHK(hipDeviceSynchronize());
+      allocs.erase(std::find(allocs.begin(), allocs.end(), (void*)results));
+      (void)hipFree(results);
+      results = nullptr;
+      results_cap = 0;
+      results = (double*)dalloc(doubles * sizeof(double));
+      results_cap = doubles;
+    }
+    return results;
+  }
   double* arena_for(size_t doubles, hipStream_t s) {
     if (doubles > arena_doubles) {
       HIPCHK(hipStreamSynchronize(s));

@@ -69,6 +69,7 @@ _plan_info = _sig("ffx_plan_info", ctypes.c_int,
                   [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)])
 _plan_strings = _sig("ffx_plan_strings", ctypes.c_int, [_vp, ctypes.c_int, _c_u64_p])
 _rot = _sig("ffx_apply_orbital_rotation", ctypes.c_int, [_vp, _vp, _c_double_p, _c_double_p, _vp])
+_rot_dense = _sig("ffx_apply_orbital_rotation_dense", ctypes.c_int, [_vp, _vp, _c_double_p, _c_double_p, _vp, _vp])
 _numop = _sig("ffx_apply_num_op_sum_evolution", ctypes.c_int,
               [_vp, _vp, _c_double_p, _c_double_p, ctypes.c_double, _c_double_p, _vp])
 _dc = _sig("ffx_apply_diag_coulomb_evolution", ctypes.c_int,
@@ -286,6 +287,18 @@ def apply_orbital_rotation(vec: torch.Tensor, U, norb: int, nelec, *, U_b=None, 
     Ub = _cplx(U_b, (norb, norb)) if U_b is not None else None
     _check(_rot(plan.handle, _vp(out.data_ptr()), _dptr(Ua), _dptr(Ub) if Ub is not None else None,
                 _stream(out.device)))
+    return out
+
+
+def apply_orbital_rotation_dense(vec: torch.Tensor, U, norb: int, nelec, *, U_b=None, out=None,
+                                 plan=None) -> torch.Tensor:
+    """The orbital rotation in its dense compound-matrix form on the matrix cores (complex128, small sectors)."""
+    plan, out = _prepare(vec, norb, nelec, out, plan)
+    Ua = _cplx(U, (norb, norb))
+    Ub = _cplx(U_b, (norb, norb)) if U_b is not None else None
+    ws = plan.workspace(3)
+    _check(_rot_dense(plan.handle, _vp(out.data_ptr()), _dptr(Ua), _dptr(Ub) if Ub is not None else None,
+                      _vp(ws.data_ptr()), _stream(out.device)))
     return out
 
 

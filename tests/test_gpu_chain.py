@@ -122,3 +122,49 @@ def test_lucj_energy_without_gradient(ffx):
     eo = float(np.real(ol.energy(p.numpy(), ham, norb, nelec, n_reps)))
     assert abs(E.item() - eo) <= 1e-12 * max(1.0, abs(eo))
     assert not E.requires_grad
+
+
+def test_df_chain_many_terms(ffx):
+    """210 terms at 6 orbitals need 9 N^2 L + 4 N^2 = 68 184 result doubles, more than the plan's initial
+    block: the block grows.  Terms 3.. have J_t = 0 (identity operators), so energy and the gradients of
+    h, J_0..2 and U_0..2 equal those of the 3-term chain, the U gradients of the empty terms vanish, and
+    their J gradients match the oracle's central differences on a sample."""
+    norb, nelec, r, dt = 6, (3, 3), 1, 0.1
+    ham, obs, vec0 = _case(norb, nelec, 3, 98)
+    L = 210
+    rng = synth.rng(99)
+    big = synth.DFHamiltonian(h=ham.h, J=np.concatenate([ham.J, np.zeros((L - 3, norb, norb))]),
+                              U=np.concatenate([ham.U, np.array([synth.random_orthogonal(rng, norb)
+                                                                 for _ in range(L - 3)], dtype=complex)]))
+    x = torch.from_numpy(vec0).to("cuda:0")
+    e3, g3 = ffx.df_chain_energy_grad(x, ham, obs, dt, r, norb, nelec)
+    e, g = ffx.df_chain_energy_grad(x, big, obs, dt, r, norb, nelec)
+    assert abs(e - e3) <= 1e-12 * max(1.0, abs(e3))
+    for part in ("h",):
+        assert np.max(np.abs(g[part] - g3[part])) <= 1e-12 * max(1.0, np.max(np.abs(g3[part])))
+    for part in ("J", "U"):
+        assert np.max(np.abs(g[part][:3] - g3[part])) <= 1e-12 * max(1.0, np.max(np.abs(g3[part])))
+    assert np.max(np.abs(g["U"][3:])) <= 1e-12
+    # the J gradient of an empty term against central differences of the oracle's chain energy
+    t, p, q, step = 150, 1, 4, 1e-5
+    Jp, Jm = big.J.copy(), big.J.copy()
+    Jp[t, p, q] = Jp[t, q, p] = step
+    Jm[t, p, q] = Jm[t, q, p] = -step
+    fd = (oh.df_chain_energy(vec0, synth.DFHamiltonian(h=big.h, J=Jp, U=big.U), obs, dt, r, norb, nelec)
+          - oh.df_chain_energy(vec0, synth.DFHamiltonian(h=big.h, J=Jm, U=big.U), obs, dt, r, norb, nelec)) / (2 * step)
+    assert abs(g["J"][t, p, q] - fd) <= 1e-7 * max(1.0, abs(fd))
+
+
+def test_lucj_gradient_many_repetitions(ffx):
+    """490 repetitions at 4 orbitals need 16 + R (8 N^2 + 2 N) = 66 656 result doubles: the block grows; the
+    gradient against the oracle's adjoint."""
+    from oracle import lucj as ol
+    norb, nelec, n_reps = 4, (2, 2), 490
+    r = synth.rng(100)
+    params = synth.lucj_params(r, norb, n_reps, scale=0.02)
+    ham = synth.df_hamiltonian(r, norb, 2)
+    e, g = ffx.lucj_energy_grad(params, ham, norb, nelec, n_reps)
+    eo, go = ol.grad_adjoint(params, ham, norb, nelec, n_reps)
+    assert abs(e - float(np.real(eo))) <= 1e-12 * max(1.0, abs(float(np.real(eo))))
+    err = np.max(np.abs(g - go)) / max(1.0, np.max(np.abs(go)))
+    assert record("lucj_gradient_490_reps", torch.complex128, "grad_rel", err, 1e-12) <= 1e-12

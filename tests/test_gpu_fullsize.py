@@ -81,16 +81,24 @@ def _at(t, idx):
     return t[ii, jj].to(torch.complex128).cpu().numpy()
 
 
-def _inverse_step(ffx, vec, ham, dt, norb, nelec):
+def _inverse_step(ffx, vec, ham, dt, norb, nelec, plan=None):
     """Exact inverse of one S_0 step (one-body term first) from single-gate calls."""
     for t in reversed(range(ham.U.shape[0])):
         U = np.asarray(ham.U[t], dtype=complex)
-        ffx.apply_orbital_rotation(vec, U.conj().T, norb, nelec, out=vec)
-        ffx.apply_diag_coulomb_evolution(vec, ham.J[t], -dt, norb, nelec, out=vec)
-        ffx.apply_orbital_rotation(vec, U, norb, nelec, out=vec)
+        ffx.apply_orbital_rotation(vec, U.conj().T, norb, nelec, out=vec, plan=plan)
+        ffx.apply_diag_coulomb_evolution(vec, ham.J[t], -dt, norb, nelec, out=vec, plan=plan)
+        ffx.apply_orbital_rotation(vec, U, norb, nelec, out=vec, plan=plan)
     w, V = np.linalg.eigh(ham.h)
-    ffx.apply_orbital_rotation(vec, (V * np.exp(1j * dt * w)) @ V.conj().T, norb, nelec, out=vec)
+    ffx.apply_orbital_rotation(vec, (V * np.exp(1j * dt * w)) @ V.conj().T, norb, nelec, out=vec, plan=plan)
     return vec
+
+
+def _release():
+    """Drop the 18-orbital states and the plan's own buffers before the next full-size test."""
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
@@ -168,13 +176,14 @@ def test_rotation_sampled_n18_c128(ffx):
     print("rotation sampled n18 complex128", flush=True)
     r = synth.rng(182)
     U = synth.random_orthogonal(r, norb).astype(complex)
+    plan = ffx.Plan(norb, nelec, torch.complex128)  # its buffers go with it at the end
     x = _device_state(d, torch.complex128, 21)
-    out = ffx.apply_orbital_rotation(x, U, norb, nelec)
+    out = ffx.apply_orbital_rotation(x, U, norb, nelec, plan=plan)
     idx = [(int(i), 27182) for i in np.random.default_rng(183).integers(0, d, 5)] + [(0, 27182), (d - 1, 27182)]
     ref = sampled.rotated_amplitudes_blocked(_DeviceRows(x), U, norb, nelec, idx, block=1024)
     err = record("rotation_sampled_n18", torch.complex128, "amplitude", np.max(np.abs(_at(out, idx) - ref)), 1e-12)
-    del x, out
-    torch.cuda.empty_cache()
+    del x, out, plan
+    _release()
     assert err <= TOL[torch.complex128]
 
 
@@ -183,15 +192,16 @@ def test_df_step_reversible_n18_c128(ffx):
     print("DF step n18 complex128 round trip", flush=True)
     ham = synth.df_hamiltonian(synth.rng(0), norb, 18)
     d = ost.dim(norb, 9)
+    plan = ffx.Plan(norb, nelec, torch.complex128)
     x0 = _device_state(d, torch.complex128, 22)
     x = x0.clone()
-    ffx.simulate_trotter_double_factorized(x, ham, dt, norb, nelec, n_steps=1, order=0, out=x)
+    ffx.simulate_trotter_double_factorized(x, ham, dt, norb, nelec, n_steps=1, order=0, out=x, plan=plan)
     moved = torch.max(torch.abs(x - x0)).item()
     nrm = torch.linalg.vector_norm(x).item()
-    _inverse_step(ffx, x, ham, dt, norb, nelec)
+    _inverse_step(ffx, x, ham, dt, norb, nelec, plan=plan)
     err = torch.max(torch.abs(x - x0)).item()
-    del x, x0
-    torch.cuda.empty_cache()
+    del x, x0, plan
+    _release()
     assert moved > 1e-5
     assert abs(nrm - 1.0) <= TOL[torch.complex128]
     assert record("df_step_reversible_n18", torch.complex128, "amplitude", err, 1e-12) <= TOL[torch.complex128]
@@ -202,13 +212,16 @@ def test_rotation_sampled_n18_c64(ffx):
     norb, nelec = 18, (9, 9)
     d = ost.dim(norb, 9)
     U = synth.random_orthogonal(synth.rng(180), norb).astype(complex)
+    plan = ffx.Plan(norb, nelec, torch.complex64)
     x = _device_state(d, torch.complex64, 19)
     host = x.cpu().numpy()
-    ffx.apply_orbital_rotation(x, U, norb, nelec, out=x)
+    ffx.apply_orbital_rotation(x, U, norb, nelec, out=x, plan=plan)
     idx = [(int(i), 31415) for i in np.random.default_rng(181).integers(0, d, 5)] + [(0, 31415)]
     ref = sampled.rotated_amplitudes_blocked(host, U, norb, nelec, idx, block=4096)
-    del host
-    err = record("rotation_sampled_n18", torch.complex64, "amplitude", np.max(np.abs(_at(x, idx) - ref)), 1e-5)
+    got = _at(x, idx)
+    del host, x, plan
+    _release()
+    err = record("rotation_sampled_n18", torch.complex64, "amplitude", np.max(np.abs(got - ref)), 1e-5)
     assert err <= TOL[torch.complex64]
 
 
@@ -216,13 +229,16 @@ def test_df_step_reversible_n18_c64(ffx):
     norb, nelec, dt = 18, (9, 9), 0.1
     ham = synth.df_hamiltonian(synth.rng(0), norb, 18)
     d = ost.dim(norb, 9)
+    plan = ffx.Plan(norb, nelec, torch.complex64)
     x0 = _device_state(d, torch.complex64, 20)
     x = x0.clone()
-    ffx.simulate_trotter_double_factorized(x, ham, dt, norb, nelec, n_steps=1, order=0, out=x)
+    ffx.simulate_trotter_double_factorized(x, ham, dt, norb, nelec, n_steps=1, order=0, out=x, plan=plan)
     nrm = torch.linalg.vector_norm(x).item()
-    _inverse_step(ffx, x, ham, dt, norb, nelec)
-    assert abs(nrm - 1.0) <= TOL[torch.complex64]
+    _inverse_step(ffx, x, ham, dt, norb, nelec, plan=plan)
     err = torch.max(torch.abs(x - x0)).item()
+    del x, x0, plan
+    _release()
+    assert abs(nrm - 1.0) <= TOL[torch.complex64]
     assert record("df_step_reversible_n18", torch.complex64, "amplitude", err, 1e-5) <= TOL[torch.complex64]
 
 
@@ -360,7 +376,8 @@ def test_hubbard_4x8_action_and_exact_evolution(ffx):
     err = abs(ffx.df_energy(ex, ham, norb, nelec) - e_rot) / max(1.0, abs(e_rot))
     assert record("hubbard_4x8_exact_energy", c128, "energy_rel", err, 1e-9) <= 1e-9
     ffx.evolve_exact(ex, ham, -1.0, norb, nelec, out=ex)
-    assert record("hubbard_4x8_exact_round_trip", c128, "amplitude", float(torch.max(torch.abs(ex - vec))), 1e-9) <= 1e-9
+    ex.sub_(vec)  # in place: no 20 GB temporary
+    assert record("hubbard_4x8_exact_round_trip", c128, "amplitude", float(torch.max(torch.abs(ex))), 1e-9) <= 1e-9
 
 
 def _slater_energy_wick(W, nelec, ham):

@@ -185,7 +185,7 @@ def time_df_step(ffx, torch, ham, vec_np, dtype, steps, warmup, norb=NORB, nelec
     step()
     torch.cuda.synchronize()
     fam = {}
-    for kind, kname in ((1, "seg_pass"), (0, "win_pass")):
+    for kind, kname in ((2, "plane_pass"), (1, "seg_pass"), (0, "win_pass")):
         for spin, sname in ((0, "alpha"), (1, "beta")):
             kms, n, alg, slots = plan.timing_read(kind, spin)
             if n:
@@ -219,12 +219,23 @@ def n18_timing(ffx, torch, synth, dtype):
     return out
 
 
-def roofline(fam, dtype_name, state_bytes):
-    """Roofline of the segment pass (both spins): the dominant kernel of the step."""
-    seg = [v for k, v in fam.items() if k.startswith("seg_pass")]
-    n = sum(v["launches"] for v in seg)
-    tot_ms = sum(v["total_ms"] for v in seg)
-    slots = sum(v["valu_slots"] for v in seg)
+KERNELS = {"plane_pass": "k_seg_pass_planes (rows as two planes; alpha and beta column spins)",
+           "seg_pass": "k_seg_pass (alpha and beta column spins)"}
+
+
+def roofline(fam, dtype_name, state_bytes, rotations_per_step):
+    """Roofline of the dominant kernel of the step (the family of segment passes with the most kernel time:
+    the plane passes for complex128 at 16 orbitals, the segment passes otherwise), and the HBM bytes of a whole
+    step: the passes' algorithmic 2 S each and their counter-measured bytes, against the 4 S per orbital
+    rotation of one read and one write of the state per spin sweep."""
+    groups = {}
+    for g in KERNELS:
+        rows = [v for k, v in fam.items() if k.startswith(g)]
+        if rows:
+            groups[g] = {"n": sum(v["launches"] for v in rows), "ms": sum(v["total_ms"] for v in rows),
+                         "slots": sum(v["valu_slots"] for v in rows)}
+    dom = max(groups, key=lambda g: groups[g]["ms"])
+    n, tot_ms, slots = groups[dom]["n"], groups[dom]["ms"], groups[dom]["slots"]
     sec = tot_ms / n * 1e-3
     # ALU: algorithmic VALU slots (8 per rotated amplitude pair for real rotations,
     # 12 for complex) as FMA-equivalent flops against the vector peak of the type
@@ -239,13 +250,24 @@ def roofline(fam, dtype_name, state_bytes):
     else:
         r = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "frac": round(hbm / HBM_PEAK_GBS, 4)}
-    tr = committed_traffic(dtype_name)
+    key = {"plane_pass": f"{dtype_name}_planes", "seg_pass": dtype_name}
+    tr = committed_traffic(key[dom])
+    measured = [committed_traffic(key[g]) for g in groups]
+    step_launch_bytes = sum(groups[g]["n"] for g in groups) * hbm_bytes
     r.update({
         "traffic": tr,
         # measured HBM bytes per launch (when the committed counters match these kernels, else the
         # algorithmic 2 S) over the average launch time, against the 8 TB/s peak
         "hbm_frac": round((tr if tr else hbm_bytes) / sec / 1e9 / HBM_PEAK_GBS, 4),
-        "kernel": "k_seg_pass (alpha and beta column spins)",
+        "kernel": KERNELS[dom],
+        "per_step": {
+            "launches": {g: groups[g]["n"] for g in groups},
+            "kernel_ms": {g: round(groups[g]["ms"], 3) for g in groups},
+            "alg_bytes_2S_per_launch": step_launch_bytes,
+            "reference_bytes_4S_per_rotation": 4.0 * state_bytes * rotations_per_step,
+            "measured_bytes": (sum(groups[g]["n"] * m for g, m in zip(groups, measured))
+                               if all(m is not None for m in measured) else None),
+        },
         "avg_launch_ms": round(tot_ms / n, 4),
         "launches_per_step": n,
         "valu_slots_per_launch": slots / n,
@@ -592,13 +614,13 @@ def main():
         "config": {"workload": f"df_trotter_step norb=16 nelec=(8,8) L=16 dt=0.1 order=0 "
                                f"state={args.dtype} 12870x12870", "state_bytes": state_bytes,
                    "wall_s_timed": round(t_wall, 3), "final_norm": norm},
-        "roofline": roofline(fam, args.dtype, state_bytes),
+        "roofline": roofline(fam, args.dtype, state_bytes, L + 1),
     }
     if not args.no_other_dtype:
         other = "c64" if args.dtype == "c128" else "c128"
         ms2, _, norm2, fam2, sb2, st2 = time_df_step(ffx, torch, ham, vec_np, types[other], args.steps,
                                                      args.warmup)
-        rf2 = roofline(fam2, other, sb2)
+        rf2 = roofline(fam2, other, sb2, L + 1)
         rf2.pop("families")
         out[f"df_step_{other}"] = {"ms_per_step": ms2, "ms_per_step_median": st2["median_ms"],
                                    "ms_per_step_iqr": st2["iqr_ms"], "final_norm": norm2, "roofline": rf2}

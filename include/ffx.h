@@ -423,7 +423,7 @@ int ffx_batch_info(ffx_batch batch, int* target_elems, int* stage_rots, int* blo
    stream it is launched on.  ffx_timing_enable resets the counters
    (enable = 0 stops recording).  ffx_timing_read synchronizes on the recorded
    events and returns, for `which` = 2 * kind + spin (kind 0 = window passes,
-   1 = segment passes; spin = the spin whose configurations the launch
+   1 = segment passes, 2 = segment passes on row planes; spin = the spin whose configurations the launch
    rotates): the summed kernel time in ms, the number of launches, the
    algorithmic bytes those launches stand for (a launch applying r of the
    K = norb (norb - 1) / 2 rotations of one spin counts r / K of one read plus

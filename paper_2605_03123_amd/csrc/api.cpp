@@ -307,6 +307,16 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
     // pack runs of configurations that share their orbitals above the segment
     // window back to back into one segment while they fit (0: one run per
     // segment; for tests)
+    // row planes for complex128 rows split into segments: FFX_PLANES=0 (off),
+    // 768 (default; measured faster) or 512 threads per block
+    int plane_threads = 768;
+    if (const char* e = std::getenv("FFX_PLANES")) {
+      const int v = std::atoi(e);
+      plane_threads = (v == 768 || v == 512) ? v : 0;
+    }
+    if (std::getenv("FFX_SEG_MAX")) plane_threads = 0;
+    // FFX_PLANES_ALL=1: plane sets also where whole rows fit in LDS (tests of the plane passes at small sizes)
+    const bool planes_all = std::getenv("FFX_PLANES_ALL") != nullptr;
     const char* pack_env = std::getenv("FFX_SEG_PACK");
     const bool pack_ok = !(pack_env && std::atoi(pack_env) == 0);
     int max_rows_x_seg = 0;
@@ -427,6 +437,61 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
       ss.lds = dev::seg_pass_lds(P->c64, ss.max_len, ss.max_mt);
       // rows of this column spin's layout times segments: one partial sum per block
       max_rows_x_seg = std::max<int>(max_rows_x_seg, (int)(P->dim[1 - s] * ss.n_seg));
+      // complex128 rows split into segments: when the real parts of a whole row
+      // fit in LDS, visits whose rotations are all real hold each row as two
+      // planes instead (one segment per row, no crossing rotation)
+      if (!P->c64 && (ss.wt < norb || planes_all) && plane_threads > 0 &&
+          (int64_t)strs.size() <= dev::seg_pass_plane_max_len(plane_threads)) {
+        auto& pl = P->plane[s];
+        const int Wp = std::min(P->W, norb);
+        std::vector<SegWindowTable> ptabs;
+        size_t mt = 0;
+        for (int a = 0; Wp >= 2 && a + Wp <= norb; ++a) {
+          ptabs.push_back(build_seg_window(strs, norb, a, Wp, 128 / 8));
+          mt = ((mt + 3) & ~(size_t)3) + ptabs.back().mt.size();
+        }
+        // the row area holds 8-byte parts: sized as a complex64 row
+        const size_t need = dev::seg_pass_lds(true, (int)strs.size(), (int)mt + 3 * (int)ptabs.size() + 4);
+        if (Wp >= 4 && need <= lds_cap) {
+          pl.wt = norb;
+          pl.Wseg = Wp;
+          pl.n_seg = 1;
+          pl.max_len = (int)strs.size();
+          pl.threads = plane_threads;
+          pl.cross = false;
+          std::vector<dev::SegWinDev> wins;
+          std::vector<int> mt_all;
+          for (SegWindowTable& t : ptabs) {
+            balance_seg_window(t, Wp, plane_threads / 64);
+            dev::SegWinDev wd{};
+            int* code = (int*)P->dalloc(std::max<size_t>(t.code.size(), 1) * 4);
+            int* cm = (int*)P->dalloc(std::max<size_t>(t.chunk_m.size(), 1) * 4);
+            if (!t.code.empty()) HIPCHK(hipMemcpy(code, t.code.data(), t.code.size() * 4, hipMemcpyHostToDevice));
+            if (!t.chunk_m.empty())
+              HIPCHK(hipMemcpy(cm, t.chunk_m.data(), t.chunk_m.size() * 4, hipMemcpyHostToDevice));
+            wd.code = code;
+            wd.chunk_m = cm;
+            while (mt_all.size() % 4) mt_all.push_back(0);
+            wd.mt_off = (int)mt_all.size();
+            wd.n_chunks = (int)t.chunk_m.size();
+            wd.nl1 = t.nl1;
+            mt_all.insert(mt_all.end(), t.mt.begin(), t.mt.end());
+            wins.push_back(wd);
+          }
+          while (mt_all.size() % 4) mt_all.push_back(0);
+          pl.max_mt = (int)mt_all.size();
+          auto* dw = (dev::SegWinDev*)P->dalloc(std::max<size_t>(wins.size(), 1) * sizeof(dev::SegWinDev));
+          if (!wins.empty())
+            HIPCHK(hipMemcpy(dw, wins.data(), wins.size() * sizeof(dev::SegWinDev), hipMemcpyHostToDevice));
+          int* dmt = (int*)P->dalloc(std::max<size_t>(mt_all.size(), 1) * 4);
+          if (!mt_all.empty()) HIPCHK(hipMemcpy(dmt, mt_all.data(), mt_all.size() * 4, hipMemcpyHostToDevice));
+          const dev::SegDev one{0, (int)strs.size(), dw, dmt, (int)mt_all.size(), 0, 0, 0, 0, 0};
+          pl.d_segs = (dev::SegDev*)P->dalloc(sizeof(dev::SegDev));
+          HIPCHK(hipMemcpy(pl.d_segs, &one, sizeof(dev::SegDev), hipMemcpyHostToDevice));
+          pl.lds = dev::seg_pass_lds(true, pl.max_len, pl.max_mt);
+          if (pl.lds > lds_cap) pl = ffx_plan_s::SegSet{};
+        }
+      }
     }
     if (max_rows_x_seg > P->n_partials) {
       P->n_partials = max_rows_x_seg;
@@ -1412,7 +1477,7 @@ int ffx_timing_read(ffx_plan plan, int which, double* total_ms, int64_t* launche
                     double* valu_slots) {
   return guard([&] {
     validate_plan(plan);
-    if (which < 0 || which > 3) throw Error(FFX_EINVAL, "bad selector");
+    if (which < 0 || which > 5) throw Error(FFX_EINVAL, "bad selector");
     DeviceGuard dg(plan->device);
     double ms = 0, bytes = 0, slots = 0;
     int64_t n = 0;

@@ -32,6 +32,34 @@ struct V2T<float> {
   using type = zc64;
 };
 
+// One part (real or imaginary) of a complex128 amplitude: the element of a
+// row plane, which real Givens rotations act on independently of the other.
+struct re128 {
+  double x;
+};
+
+// The scalar type of an element type, and whether the element is a single
+// plane part (real rotations only).
+template <class V>
+struct ElemT;
+template <>
+struct ElemT<zc128> {
+  using R = double;
+  static constexpr bool plane = false;
+};
+template <>
+struct ElemT<zc64> {
+  using R = float;
+  static constexpr bool plane = false;
+};
+template <>
+struct ElemT<re128> {
+  using R = double;
+  static constexpr bool plane = true;
+};
+template <class V>
+using ER = typename ElemT<V>::R;
+
 constexpr int cbinom(int n, int k) {
   if (k < 0 || k > n) return 0;
   long long r = 1;
@@ -118,63 +146,70 @@ __device__ __forceinline__ void fma_ip(double& d, double a, double b) {
 }
 
 // x' = c x + s y, y' = -conj(s) x + c y on one member pair (A, B)
-template <int A, int B, bool REAL, class R>
-__device__ __forceinline__ void rot_pair(typename V2T<R>::type* v, R c, R sr, R si) {
-  using V = typename V2T<R>::type;
+template <int A, int B, bool REAL, class V>
+__device__ __forceinline__ void rot_pair(V* v, ER<V> c, ER<V> sr, ER<V> si) {
+  using R = ER<V>;
   V& x = v[A];
   V& y = v[B];
-  R tx, ty, ux, uy;
-  if constexpr (REAL) {
-    tx = sr * y.x;
-    ty = sr * y.y;
-    ux = -sr * x.x;
-    uy = -sr * x.y;
+  if constexpr (ElemT<V>::plane) {
+    // one plane of the row: a real rotation acts on it alone
+    static_assert(REAL, "row planes take real rotations only");
+    const R tx = sr * y.x, ux = -sr * x.x;
+    fma_ip(x.x, c, tx);
+    fma_ip(y.x, c, ux);
   } else {
-    tx = sr * y.x - si * y.y;
-    ty = sr * y.y + si * y.x;
-    ux = -sr * x.x - si * x.y;
-    uy = si * x.x - sr * x.y;
+    R tx, ty, ux, uy;
+    if constexpr (REAL) {
+      tx = sr * y.x;
+      ty = sr * y.y;
+      ux = -sr * x.x;
+      uy = -sr * x.y;
+    } else {
+      tx = sr * y.x - si * y.y;
+      ty = sr * y.y + si * y.x;
+      ux = -sr * x.x - si * x.y;
+      uy = si * x.x - sr * x.y;
+    }
+    fma_ip(x.x, c, tx);
+    fma_ip(x.y, c, ty);
+    fma_ip(y.x, c, ux);
+    fma_ip(y.y, c, uy);
   }
-  fma_ip(x.x, c, tx);
-  fma_ip(x.y, c, ty);
-  fma_ip(y.x, c, ux);
-  fma_ip(y.y, c, uy);
 }
 
 // every member pair of rotation P, expanded at compile time so that the
 // register array is only ever indexed by constants
-template <int W, int M, int P, bool REAL, class R, int... I>
-__device__ __forceinline__ void rot_pairs(typename V2T<R>::type* v, R c, R sr, R si,
-                                          std::integer_sequence<int, I...>) {
+template <int W, int M, int P, bool REAL, class V, int... I>
+__device__ __forceinline__ void rot_pairs(V* v, ER<V> c, ER<V> sr, ER<V> si, std::integer_sequence<int, I...>) {
   constexpr Pairs<W, M, P> pr{};
-  (rot_pair<pr.a[I], pr.b[I], REAL, R>(v, c, sr, si), ...);
+  (rot_pair<pr.a[I], pr.b[I], REAL, V>(v, c, sr, si), ...);
 }
 
-template <int W, int M, int P, bool REAL, class R>
-__device__ __forceinline__ void rot_one(typename V2T<R>::type* v, R c, R sr, R si) {
-  rot_pairs<W, M, P, REAL, R>(v, c, sr, si, std::make_integer_sequence<int, Pairs<W, M, P>::NP>{});
+template <int W, int M, int P, bool REAL, class V>
+__device__ __forceinline__ void rot_one(V* v, ER<V> c, ER<V> sr, ER<V> si) {
+  rot_pairs<W, M, P, REAL, V>(v, c, sr, si, std::make_integer_sequence<int, Pairs<W, M, P>::NP>{});
 }
 
-template <int W, int M, bool REAL, class R, int P = 0>
-__device__ __forceinline__ void rot_dispatch(int p, typename V2T<R>::type* v, R c, R sr, R si) {
+template <int W, int M, bool REAL, class V, int P = 0>
+__device__ __forceinline__ void rot_dispatch(int p, V* v, ER<V> c, ER<V> sr, ER<V> si) {
   if constexpr (P < W - 1) {
     if (p == P)
-      rot_one<W, M, P, REAL, R>(v, c, sr, si);
+      rot_one<W, M, P, REAL, V>(v, c, sr, si);
     else
-      rot_dispatch<W, M, REAL, R, P + 1>(p, v, c, sr, si);
+      rot_dispatch<W, M, REAL, V, P + 1>(p, v, c, sr, si);
   }
 }
 
-template <int W, int M, bool REAL, class R>
-__device__ __forceinline__ void apply_rots(typename V2T<R>::type* v, const RotDev* __restrict__ rots,
-                                           int nrot) {
+template <int W, int M, bool REAL, class V>
+__device__ __forceinline__ void apply_rots(V* v, const RotDev* __restrict__ rots, int nrot) {
+  using R = ER<V>;
   if (nrot <= 0) return;
   // the next rotation's parameters are requested before the current one is
   // applied, so the (uniform) load latency overlaps the arithmetic
   RotDev cur = rots[0];
   for (int r = 0; r < nrot; ++r) {
     const RotDev nxt = rots[r + 1 < nrot ? r + 1 : r];
-    rot_dispatch<W, M, REAL, R>(cur.p, v, (R)cur.c, (R)cur.sr, (R)cur.si);
+    rot_dispatch<W, M, REAL, V>(cur.p, v, (R)cur.c, (R)cur.sr, (R)cur.si);
     cur = nxt;
   }
 }
@@ -200,31 +235,32 @@ __device__ __forceinline__ double lane_bcast(double v, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-template <int W, int M, bool REAL, class R>
-__device__ __forceinline__ void apply_rots_lane(typename V2T<R>::type* v, const RotLane<R>& rl, int nrot) {
+template <int W, int M, bool REAL, class V>
+__device__ __forceinline__ void apply_rots_lane(V* v, const RotLane<ER<V>>& rl, int nrot) {
+  using R = ER<V>;
   for (int r = 0; r < nrot; ++r) {
     int p = lane_bcast(rl.p, r);
     asm volatile("" : "+v"(p));
-    rot_dispatch<W, M, REAL, R>(p, v, lane_bcast(rl.c, r), lane_bcast(rl.sr, r),
+    rot_dispatch<W, M, REAL, V>(p, v, lane_bcast(rl.c, r), lane_bcast(rl.sr, r),
                                 REAL ? R(0) : lane_bcast(rl.si, r));
   }
 }
 
 // The rotations of stage shape S, positions fixed at compile time: rotation i
 // takes its parameters from lane i and acts on window position kShapeP[S][i].
-template <int W, int M, bool REAL, class R, int S, int I>
-__device__ __forceinline__ void shape_rot(typename V2T<R>::type* v, const RotLane<R>& rl) {
-  rot_one<W, M, kShapeP[S][I], REAL, R>(v, lane_bcast(rl.c, I), lane_bcast(rl.sr, I),
+template <int W, int M, bool REAL, class V, int S, int I>
+__device__ __forceinline__ void shape_rot(V* v, const RotLane<ER<V>>& rl) {
+  using R = ER<V>;
+  rot_one<W, M, kShapeP[S][I], REAL, V>(v, lane_bcast(rl.c, I), lane_bcast(rl.sr, I),
                                         REAL ? R(0) : lane_bcast(rl.si, I));
   // rotation parameters are broadcast next to their use: hoisting the
   // broadcasts of later rotations only holds scalar registers
   __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int W, int M, bool REAL, class R, int S, int... I>
-__device__ __forceinline__ void apply_shape(typename V2T<R>::type* v, const RotLane<R>& rl,
-                                            std::integer_sequence<int, I...>) {
-  (shape_rot<W, M, REAL, R, S, I>(v, rl), ...);
+template <int W, int M, bool REAL, class V, int S, int... I>
+__device__ __forceinline__ void apply_shape(V* v, const RotLane<ER<V>>& rl, std::integer_sequence<int, I...>) {
+  (shape_rot<W, M, REAL, V, S, I>(v, rl), ...);
 }
 
 // Loads a small struct of uniform, read-only data (descriptor tables written
@@ -314,11 +350,9 @@ __device__ __forceinline__ int pick(const int4& q) {
   return q.w;
 }
 
-template <int W, int M, bool REAL, class R, int S, int... K>
-__device__ __forceinline__ void lds_class(typename V2T<R>::type* __restrict__ row, int cbase, const int* mtl,
-                                          int moff, const RotLane<R>& rl, int nrot,
-                                          std::integer_sequence<int, K...>) {
-  using V = typename V2T<R>::type;
+template <int W, int M, bool REAL, class V, int S, int... K>
+__device__ __forceinline__ void lds_class(V* __restrict__ row, int cbase, const int* mtl, int moff,
+                                          const RotLane<ER<V>>& rl, int nrot, std::integer_sequence<int, K...>) {
   constexpr int C = sizeof...(K);
   constexpr int Q = (C + 3) / 4;
   V v[C];
@@ -330,9 +364,9 @@ __device__ __forceinline__ void lds_class(typename V2T<R>::type* __restrict__ ro
     ((v[K] = row[cbase + pick<K>(q[K >> 2])]), ...);
   }
   if constexpr (S < 0)
-    apply_rots_lane<W, M, REAL, R>(v, rl, nrot);
+    apply_rots_lane<W, M, REAL, V>(v, rl, nrot);
   else
-    apply_shape<W, M, REAL, R, S>(v, rl, std::make_integer_sequence<int, kShapeLen[S]>{});
+    apply_shape<W, M, REAL, V, S>(v, rl, std::make_integer_sequence<int, kShapeLen[S]>{});
   // nothing of the store-back (the offset reloads in particular) is scheduled
   // into the straight-line rotations, where it would only hold registers
   __builtin_amdgcn_sched_barrier(0);
@@ -349,14 +383,14 @@ __device__ __forceinline__ void lds_class(typename V2T<R>::type* __restrict__ ro
   }
 }
 
-template <int W, bool REAL, class R, int S = -1, int M = 1>
-__device__ __forceinline__ void lds_m(int m, typename V2T<R>::type* row, int cbase, const int* mtl, int moff,
-                                      const RotLane<R>& rl, int nrot) {
+template <int W, bool REAL, class V, int S = -1, int M = 1>
+__device__ __forceinline__ void lds_m(int m, V* row, int cbase, const int* mtl, int moff, const RotLane<ER<V>>& rl,
+                                      int nrot) {
   if constexpr (M < W) {
     if (m == M)
-      lds_class<W, M, REAL, R, S>(row, cbase, mtl, moff, rl, nrot, std::make_integer_sequence<int, cbinom(W, M)>{});
+      lds_class<W, M, REAL, V, S>(row, cbase, mtl, moff, rl, nrot, std::make_integer_sequence<int, cbinom(W, M)>{});
     else
-      lds_m<W, REAL, R, S, M + 1>(m, row, cbase, mtl, moff, rl, nrot);
+      lds_m<W, REAL, V, S, M + 1>(m, row, cbase, mtl, moff, rl, nrot);
   }
 }
 
@@ -388,10 +422,9 @@ __device__ __forceinline__ RotLane<R> fetch_rot_lane(const RotDev* rots, int nro
   return RotLane<R>{g.p, (R)g.c, (R)g.sr, (R)g.si};
 }
 
-template <int W, bool REAL, class R, int S>
-__device__ __forceinline__ void givens_chunks(typename V2T<R>::type* row, const int* mtl, const SegWinDev& wt,
-                                              const RotLane<R>& rl, int nrot, int wave, int nwaves, int lane,
-                                              ChunkAhead first) {
+template <int W, bool REAL, class V, int S>
+__device__ __forceinline__ void givens_chunks(V* row, const int* mtl, const SegWinDev& wt, const RotLane<ER<V>>& rl,
+                                              int nrot, int wave, int nwaves, int lane, ChunkAhead first) {
   const int* mw = mtl + wt.mt_off;
   for (int ch = wave; ch < wt.n_chunks; ch += nwaves) {
     int m = first.m, code = first.code;
@@ -399,22 +432,30 @@ __device__ __forceinline__ void givens_chunks(typename V2T<R>::type* row, const 
       m = uniform_load(wt.chunk_m + ch);
       code = wt.code[ch * 64 + lane];
     }
-    if (code >= 0) lds_m<W, REAL, R, S>(m, row, code >> 5, mtl, wt.mt_off + mw[m * wt.nl1 + (code & 31)], rl, nrot);
+    if (code >= 0) lds_m<W, REAL, V, S>(m, row, code >> 5, mtl, wt.mt_off + mw[m * wt.nl1 + (code & 31)], rl, nrot);
   }
 }
 
-template <int W, bool REAL, class R, int S = 0>
+template <int W, bool REAL, class V, int S = 0>
+__device__ __forceinline__ void givens_stage_v(int shape, V* row, const int* mtl, const SegWinDev& wt,
+                                               const RotLane<ER<V>>& rl, int nrot, int wave, int nwaves, int lane,
+                                               ChunkAhead first) {
+  if constexpr (W == kShapeW && S < kNumShapes) {
+    if (shape == S)
+      givens_chunks<W, REAL, V, S>(row, mtl, wt, rl, nrot, wave, nwaves, lane, first);
+    else
+      givens_stage_v<W, REAL, V, S + 1>(shape, row, mtl, wt, rl, nrot, wave, nwaves, lane, first);
+  } else {
+    givens_chunks<W, REAL, V, -1>(row, mtl, wt, rl, nrot, wave, nwaves, lane, first);
+  }
+}
+
+// the same on rows of complex amplitudes of scalar type R
+template <int W, bool REAL, class R>
 __device__ __forceinline__ void givens_stage(int shape, typename V2T<R>::type* row, const int* mtl,
                                              const SegWinDev& wt, const RotLane<R>& rl, int nrot, int wave,
                                              int nwaves, int lane, ChunkAhead first) {
-  if constexpr (W == kShapeW && S < kNumShapes) {
-    if (shape == S)
-      givens_chunks<W, REAL, R, S>(row, mtl, wt, rl, nrot, wave, nwaves, lane, first);
-    else
-      givens_stage<W, REAL, R, S + 1>(shape, row, mtl, wt, rl, nrot, wave, nwaves, lane, first);
-  } else {
-    givens_chunks<W, REAL, R, -1>(row, mtl, wt, rl, nrot, wave, nwaves, lane, first);
-  }
+  givens_stage_v<W, REAL, typename V2T<R>::type>(shape, row, mtl, wt, rl, nrot, wave, nwaves, lane, first);
 }
 
 __device__ __forceinline__ int parity(uint32_t x) { return __builtin_popcount(x) & 1; }

@@ -84,7 +84,7 @@ __device__ __forceinline__ void alpha_body(typename V2T<R>::type* __restrict__ v
   V v[C];
   const uint32_t off = col * (uint32_t)sizeof(V);
   load_alpha<V, R>(v, vec, dim_b, t, off, std::make_integer_sequence<int, C>{});
-  apply_rots<W, M, REAL, R>(v, rots, nrot);
+  apply_rots<W, M, REAL, typename V2T<R>::type>(v, rots, nrot);
   store_alpha<V, R>(v, vec, dim_b, t, off, phase, std::make_integer_sequence<int, C>{});
 }
 
@@ -96,7 +96,7 @@ __device__ __forceinline__ void beta_body(typename V2T<R>::type* __restrict__ ro
   constexpr int C = cbinom(W, M);
   V v[C];
   load_beta<V, R>(v, rowp, t, std::make_integer_sequence<int, C>{});
-  apply_rots<W, M, REAL, R>(v, rots, nrot);
+  apply_rots<W, M, REAL, typename V2T<R>::type>(v, rots, nrot);
   store_beta<V, R>(v, rowp, t, phase, std::make_integer_sequence<int, C>{});
 }
 

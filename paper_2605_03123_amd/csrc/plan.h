@@ -46,6 +46,10 @@ struct ffx_plan_s {
     bool cross = false;  // rotations on (wt - 1, wt) can be applied at segment load
     ffx::dev::SegDev* d_segs = nullptr;
   } seg[2];
+  // whole rows as two planes (complex128 rows that exceed LDS but whose real
+  // parts fit): one segment per row, for visits whose rotations are all real;
+  // n_seg = 0 where unavailable
+  SegSet plane[2];
   // parameter upload ring
   static constexpr int kSlots = 4;
   size_t slot_bytes = 0;
@@ -71,7 +75,7 @@ struct ffx_plan_s {
   // diagnostics: event pairs around the dominant launches
   struct Timed {
     hipEvent_t a, b;
-    int kind;  // 0 window pass, 1 segment pass
+    int kind;  // 0 window pass, 1 segment pass, 2 segment pass on row planes
     int spin;
     double alg_bytes;
     double valu_slots;
@@ -289,6 +293,8 @@ struct Launch {
   bool cross = false;
   // rows gathered from the other layout (replaces a transpose before the pass)
   bool gather = false;
+  // the row held as two planes (the plan's plane set of the column spin)
+  bool planes = false;
   dev::RotDev cross_rot{};
   // WIN
   int a = 0;

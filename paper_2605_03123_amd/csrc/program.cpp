@@ -303,7 +303,19 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
   };
 
   auto close_visit = [&](bool force_seg) {
-    const auto& ss = P.seg[colspin()];
+    // a visit whose Givens rotations are all real holds each row as two planes
+    // where the plan has them (whole rows: no crossing rotation, one pass)
+    bool planes = P.plane[colspin()].n_seg > 0;
+    {
+      bool any_rot = false;
+      for (const Item& it : visit)
+        if (it.kind == 0) {
+          any_rot = true;
+          if (!it.d->real) planes = false;
+        }
+      planes = planes && any_rot;
+    }
+    const auto& ss = planes ? P.plane[colspin()] : P.seg[colspin()];
     const int64_t n_rows = layout == 0 ? da : db;
     const int ncol = P.n[colspin()];
     const double pairs_per_row = (double)binom(N - 2, ncol - 1);
@@ -311,6 +323,7 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
     Launch cur{};
     cur.kind = Launch::SEG;
     cur.layout = layout;
+    cur.planes = planes;
     bool any = false;
     auto flush_seg = [&](bool force) {
       if (stages.empty() && !force && !cur.cross) return;
@@ -321,6 +334,7 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
       cur = Launch{};
       cur.kind = Launch::SEG;
       cur.layout = layout;
+      cur.planes = planes;
     };
     for (const Item& it : visit) {
       if (it.kind == 1) {
@@ -533,14 +547,14 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
     if (timed) {
       tm.a = P.take_event();
       tm.b = P.take_event();
-      tm.kind = L.kind == Launch::SEG ? 1 : 0;
+      tm.kind = L.kind == Launch::SEG ? (L.planes ? 2 : 1) : 0;
       tm.spin = cs;
       tm.valu_slots = L.valu_slots;
       tm.alg_bytes = L.rot_sides * 2.0 * (double)P.state_bytes();
       HIPCHK(hipEventRecord(tm.a, s));
     }
     if (L.kind == Launch::SEG) {
-      const auto& ss = P.seg[cs];
+      const auto& ss = L.planes ? P.plane[cs] : P.seg[cs];
       dev::SegPassDev p{};
       p.src = cur_src;
       p.norb = N;
@@ -553,7 +567,7 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
       p.n_stages = L.n_stages;
       p.stages = L.stages;
       p.partials = L.reduce ? P.partials : nullptr;
-      p.lds_row_bytes = (int)(((size_t)ss.max_len * P.elem() + 15) & ~(size_t)15);
+      p.lds_row_bytes = (int)(((size_t)ss.max_len * (L.planes ? 8 : P.elem()) + 15) & ~(size_t)15);
       p.max_mt = ss.max_mt;
       if (L.cross) {
         p.cross = 1;
@@ -576,7 +590,10 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
       }
       if ((L.cross || L.gather) && p.dst == p.src)
         throw Error(FFX_EDEVICE, "crossing rotation or gathering pass needs an out-of-place pass");
-      dev::seg_pass(P.c64, L.real, ss.Wseg, p, ss.threads, ss.lds, s);
+      if (L.planes)
+        dev::seg_pass_planes(ss.Wseg, ss.threads, p, ss.lds, s);
+      else
+        dev::seg_pass(P.c64, L.real, ss.Wseg, p, ss.threads, ss.lds, s);
       check_launch();
       if (L.reduce) {
         dev::sum_partials(P.partials, (int)(rows * ss.n_seg), L.reduce_out, s);

@@ -114,6 +114,68 @@ __device__ __forceinline__ void cross_apply(typename V2T<R>::type* own, const ty
     own[e] = cross_rot<R>(own[e], peer[(int64_t)e * stride], c, sgn, sr, si);
 }
 
+// Row-dependent part of a diagonal stage, computed by the whole block before
+// the stage touches any element: the cross weights w[q] = sum_{p in row} C[p][q]
+// (the row's masked C is staged in the table area, one load per thread, all in
+// flight at once, then summed over p in a fixed order), the row value A[r], the
+// row's phase factor (phase stages; with a cross term it is folded into the
+// first byte table), and the byte tables of the cross term: complex factors for
+// phase stages, real sums otherwise.  Ends with a block barrier.
+struct DiagRow {
+  double arow;
+  zc128 rowf;
+  bool cross;
+};
+
+__device__ __forceinline__ DiagRow diag_stage_tables(const StageDev& st, const SegPassDev& P, int64_t r,
+                                                     uint32_t rmask, zc128* ez, double* wq, int tid, int nthr,
+                                                     int nbytes) {
+  double* tab = (double*)ez;
+  DiagRow dr;
+  dr.cross = st.C != nullptr;
+  const int nn = P.norb * P.norb;
+  if (dr.cross) {
+    for (int i = tid; i < nn; i += nthr) tab[i] = ((rmask >> (i / P.norb)) & 1) ? st.C[i] : 0.0;
+    __syncthreads();
+  }
+  if (tid < P.norb) {
+    double w = 0.0;
+    if (dr.cross)
+      for (int p = 0; p < P.norb; ++p) w += tab[p * P.norb + tid];
+    wq[tid] = w;
+  }
+  __syncthreads();
+  dr.arow = st.A ? st.A[r] : 0.0;
+  dr.rowf = zc128{1.0, 0.0};
+  if (st.type == ST_PHASE) {
+    double grow = 0.0;
+    if (st.drow)
+      for (int p = 0; p < P.norb; ++p)
+        if ((rmask >> p) & 1) grow += st.drow[p];
+    dr.rowf = phase_factor<double>(st.scale * dr.arow + grow);
+    if (parity(rmask & st.sign_row)) {
+      dr.rowf.x = -dr.rowf.x;
+      dr.rowf.y = -dr.rowf.y;
+    }
+  }
+  if (dr.cross) {
+    for (int i = tid; i < nbytes * 256; i += nthr) {
+      const int k = i >> 8, b = i & 255;
+      double v = 0.0;
+      for (int q = 0; q < 8; ++q)
+        if (((b >> q) & 1) && 8 * k + q < P.norb) v += wq[8 * k + q];
+      if (st.type == ST_PHASE) {
+        const zc128 e = phase_factor<double>(st.scale * v);
+        ez[i] = k == 0 ? zmul(dr.rowf, e) : e;
+      } else {
+        tab[i] = v;
+      }
+    }
+  }
+  __syncthreads();
+  return dr;
+}
+
 template <int W, bool REAL, class R>
 __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P) {
   using V = typename V2T<R>::type;
@@ -189,52 +251,10 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
       const SegWinDev wt = uniform_load(sg.win + st.a);
       givens_stage<W, REAL, R>(st.shape, row, mtl, wt, rl, st.nrot, wave, nwaves, lane, fc);
     } else {
-      // cross weights w[q] = sum_{p in row} C[p][q]: the row's masked C is
-      // staged in the table area (one load per thread, all in flight at once),
-      // then summed over p in a fixed order
-      const bool cross = st.C != nullptr;
-      const int nn = P.norb * P.norb;
-      if (cross) {
-        for (int i = tid; i < nn; i += nthr) tab[i] = ((rmask >> (i / P.norb)) & 1) ? st.C[i] : 0.0;
-        __syncthreads();
-      }
-      if (tid < P.norb) {
-        double w = 0.0;
-        if (cross)
-          for (int p = 0; p < P.norb; ++p) w += tab[p * P.norb + tid];
-        wq[tid] = w;
-      }
-      __syncthreads();
-      const double arow = st.A ? st.A[r] : 0.0;
-      // row factor (phase stages): folded into the first byte table when there
-      // is a cross term
-      zc128 rowf{1.0, 0.0};
-      if (st.type == ST_PHASE) {
-        double grow = 0.0;
-        if (st.drow)
-          for (int p = 0; p < P.norb; ++p)
-            if ((rmask >> p) & 1) grow += st.drow[p];
-        rowf = phase_factor<double>(st.scale * arow + grow);
-        if (parity(rmask & st.sign_row)) {
-          rowf.x = -rowf.x;
-          rowf.y = -rowf.y;
-        }
-      }
-      if (cross) {
-        for (int i = tid; i < nbytes * 256; i += nthr) {
-          const int k = i >> 8, b = i & 255;
-          double v = 0.0;
-          for (int q = 0; q < 8; ++q)
-            if (((b >> q) & 1) && 8 * k + q < P.norb) v += wq[8 * k + q];
-          if (st.type == ST_PHASE) {
-            const zc128 e = phase_factor<double>(st.scale * v);
-            ez[i] = k == 0 ? zmul(rowf, e) : e;
-          } else {
-            tab[i] = v;
-          }
-        }
-      }
-      __syncthreads();
+      const DiagRow dr = diag_stage_tables(st, P, r, rmask, ez, wq, tid, nthr, nbytes);
+      const bool cross = dr.cross;
+      const double arow = dr.arow;
+      zc128 rowf = dr.rowf;
       // U elements per thread at a time (a whole segment per batch for the
       // usual block sizes): their column masks and tables are all requested
       // before the first is used
@@ -346,6 +366,237 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
       P.partials[blk] = t;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Row planes.  A complex128 row that exceeds LDS, but whose real parts fit,
+// is held as two planes when every Givens rotation of the pass is real: a real
+// rotation matrix acts on the real and imaginary parts of the amplitudes alike
+// and independently, so each run of consecutive Givens stages is applied to
+// the plane in LDS, the planes are swapped, and the run is applied to the
+// other.  The other plane stays in registers: thread t holds the parts of
+// elements t, t + nthr, t + 2 nthr, ...  Diagonal stages combine the two parts
+// of each element in the thread that holds its register part.  The whole row
+// is one segment, so no rotation crosses a segment: one pass per visit.
+// ---------------------------------------------------------------------------
+// Block sizes: 768 threads hold 17 register parts each (rows of up to 13 056
+// amplitudes, 168 registers a lane, 3 waves per SIMD; the default, 5 % faster
+// on the DF step at 16 orbitals) or 512 threads 26 parts (13 312 amplitudes,
+// 200 registers, 2 waves per SIMD).
+template <int NT>
+constexpr int plane_regs() {
+  return NT == 512 ? 26 : 17;
+}
+
+int seg_pass_plane_max_len(int threads) { return threads * (threads == 512 ? plane_regs<512>() : plane_regs<768>()); }
+
+// Givens stages [s0, s1) of a plane pass on the LDS plane; each stage's
+// rotations and the wave's first class codes are requested one stage ahead.
+template <int W>
+__device__ __forceinline__ void plane_givens_run(const SegPassDev& P, const SegDev& sg, re128* pl, const int* mtl,
+                                                 int s0, int s1, int wave, int nwaves, int lane) {
+  StageDev st = uniform_load(P.stages + s0);
+  RotLane<double> rl_next = fetch_rot_lane<double>(st.rots, st.nrot, lane);
+  ChunkAhead fc_next = fetch_first_chunk(uniform_load(sg.win + st.a), wave, lane);
+  for (int s = s0; s < s1; ++s) {
+    st = uniform_load(P.stages + s);
+    const RotLane<double> rl = rl_next;
+    const ChunkAhead fc = fc_next;
+    if (s + 1 < s1) {
+      const StageDev nx = uniform_load(P.stages + s + 1);
+      rl_next = fetch_rot_lane<double>(nx.rots, nx.nrot, lane);
+      fc_next = fetch_first_chunk(uniform_load(sg.win + nx.a), wave, lane);
+    }
+    const SegWinDev wt = uniform_load(sg.win + st.a);
+    givens_stage_v<W, true, re128>(st.shape, pl, mtl, wt, rl, st.nrot, wave, nwaves, lane, fc);
+    __syncthreads();
+  }
+}
+
+template <int W, int NT>
+__global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
+  constexpr int kPlaneRegs = plane_regs<NT>();
+  extern __shared__ __align__(16) char smem[];
+  re128* pl = (re128*)smem;                            // the LDS plane
+  zc128* ez = (zc128*)(smem + P.lds_row_bytes);        // 4 x 256 complex byte factors
+  double* tab = (double*)ez;                           // (or 4 x 256 real byte sums)
+  int* mtl = (int*)(ez + 4 * 256);                     // member offsets of every window
+  double* wq = (double*)(mtl + ((P.max_mt + 3) & ~3)); // 32 cross weights
+  double* red = wq + 32;                               // block reduction scratch
+
+  int64_t r;
+  if (P.xcd_rows > 0) {
+    r = (int64_t)(blockIdx.x & 7) * P.xcd_rows + (blockIdx.x >> 3);
+    if (r >= P.n_rows) return;  // the whole block: the grid rounds rows up to 8 XCDs
+  } else {
+    r = blockIdx.x;
+  }
+  const SegDev sg = uniform_load(P.segs);  // one segment: the whole row
+  const int len = sg.len;
+  const int nthr = blockDim.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int nwaves = nthr >> 6;
+  const int64_t stride = P.gather ? P.n_rows : 1;
+  const zc128* src = P.gather ? (const zc128*)P.src + r : (const zc128*)P.src + r * P.row_len;
+
+  // the row: every load in flight before the first is used; real parts to the
+  // LDS plane, imaginary parts to registers; then the member-offset tables
+  double rp[kPlaneRegs];
+  {
+    zc128 t[kPlaneRegs];
+#pragma unroll
+    for (int k = 0; k < kPlaneRegs; ++k) t[k] = src[(int64_t)min(tid + k * nthr, len - 1) * stride];
+#pragma unroll
+    for (int k = 0; k < kPlaneRegs; ++k) keep(t[k]);
+#pragma unroll
+    for (int k = 0; k < kPlaneRegs; ++k) {
+      const int e = tid + k * nthr;
+      if (e < len) pl[e].x = t[k].x;
+      rp[k] = t[k].y;
+    }
+  }
+  for (int e = tid; e < (sg.n_mt_all >> 2); e += nthr) ((int4*)mtl)[e] = ((const int4*)sg.mt_all)[e];
+  __syncthreads();
+  bool lds_re = true;  // the LDS plane holds the real parts (the same in every thread)
+
+  const uint32_t rmask = P.row_masks[r];
+  const uint32_t* cmask = P.col_masks;
+  const int nbytes = (P.norb + 7) >> 3;
+  double acc = 0.0;
+  int s = 0;
+  while (s < P.n_stages) {
+    const StageDev st = uniform_load(P.stages + s);
+    if (st.type == ST_GIVENS) {
+      int s1 = s + 1;
+      while (s1 < P.n_stages && uniform_load(P.stages + s1).type == ST_GIVENS) ++s1;
+      plane_givens_run<W>(P, sg, pl, mtl, s, s1, wave, nwaves, lane);
+      // swap the planes: the register plane into LDS and back
+#pragma unroll
+      for (int k = 0; k < kPlaneRegs; ++k) {
+        int e = tid + k * nthr;
+        asm volatile("" : "+v"(e));  // recomputed here: hoisted, 26 such offsets would stay live across stages
+        if (e < len) {
+          const double x = pl[e].x;
+          pl[e].x = rp[k];
+          rp[k] = x;
+        }
+      }
+      __syncthreads();
+      lds_re = !lds_re;
+      plane_givens_run<W>(P, sg, pl, mtl, s, s1, wave, nwaves, lane);
+      s = s1;
+      continue;
+    }
+    const DiagRow dr = diag_stage_tables(st, P, r, rmask, ez, wq, tid, nthr, nbytes);
+    const bool cross = dr.cross;
+    if (st.type == ST_PHASE) {
+      const zc128 rowf = cross ? zc128{1.0, 0.0} : dr.rowf;
+      const zc128* colf = (const zc128*)st.colf;
+      const uint32_t sgn = st.sign_col;
+      const bool use_cm = cross || sgn != 0;
+#pragma unroll
+      for (int k = 0; k < kPlaneRegs; ++k) {
+        int e = tid + k * nthr;
+        asm volatile("" : "+v"(e));  // recomputed per element (see the swap)
+        if (e >= len) continue;
+        const uint32_t cm = use_cm ? cmask[e] : 0u;
+        zc128 f = colf ? zmul(rowf, colf[e]) : rowf;
+        if (cross)
+          for (int b = 0; b < nbytes; ++b) f = zmul(f, ez[(b << 8) | ((cm >> (8 * b)) & 255)]);
+        if (parity(cm & sgn)) {
+          f.x = -f.x;
+          f.y = -f.y;
+        }
+        const double a = pl[e].x, q = rp[k];
+        const double re = lds_re ? a : q, im = lds_re ? q : a;
+        const double nre = re * f.x - im * f.y, nim = re * f.y + im * f.x;
+        pl[e].x = lds_re ? nre : nim;
+        rp[k] = lds_re ? nim : nre;
+      }
+    } else {
+      const double* Bs = st.B;
+#pragma unroll
+      for (int k = 0; k < kPlaneRegs; ++k) {
+        int e = tid + k * nthr;
+        asm volatile("" : "+v"(e));  // recomputed per element (see the swap)
+        if (e >= len) continue;
+        double f = dr.arow + (Bs ? Bs[e] : 0.0);
+        if (cross) {
+          const uint32_t cm = cmask[e];
+          for (int b = 0; b < nbytes; ++b) f += tab[(b << 8) | ((cm >> (8 * b)) & 255)];
+        }
+        if (st.type == ST_SCALE) {
+          pl[e].x *= f;
+          rp[k] *= f;
+        } else {
+          const double a = pl[e].x, q = rp[k];
+          acc += f * (a * a + q * q);
+        }
+      }
+    }
+    __syncthreads();
+    ++s;
+  }
+
+  if (P.mode != SEG_NONE) {
+    zc128* dst = (zc128*)P.dst + r * P.row_len;
+#pragma unroll
+    for (int k = 0; k < kPlaneRegs; ++k) {
+      const int e = tid + k * nthr;
+      if (e < len) {
+        const double a = pl[e].x, q = rp[k];
+        zc128 v = lds_re ? zc128{a, q} : zc128{q, a};
+        if (P.mode == SEG_ACCUM) {
+          const zc128 o = dst[e];
+          v.x += o.x;
+          v.y += o.y;
+        }
+        dst[e] = v;
+      }
+    }
+  }
+  if (P.partials) {
+    // fixed-order block reduction: wave sums, then thread 0 adds them in order
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) red[wave] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int i = 0; i < nwaves; ++i) t += red[i];
+      P.partials[r] = t;
+    }
+  }
+}
+
+template <int W, int NT>
+static void launch_planes(const SegPassDev& p, size_t lds, hipStream_t s) {
+  auto k = k_seg_pass_planes<W, NT>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  const int64_t blocks = p.xcd_rows > 0 ? 8 * p.xcd_rows : p.n_rows;
+  hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(NT), lds, s, p);
+}
+
+template <int NT>
+static void planes_w(int W, const SegPassDev& p, size_t lds, hipStream_t s) {
+  switch (W) {
+    case 4: launch_planes<4, NT>(p, lds, s); break;
+    case 5: launch_planes<5, NT>(p, lds, s); break;
+    case 6: launch_planes<6, NT>(p, lds, s); break;
+    default: break;
+  }
+}
+
+void seg_pass_planes(int W, int threads, const SegPassDev& p, size_t lds, hipStream_t s) {
+  if (threads == 768)
+    planes_w<768>(W, p, lds, s);
+  else
+    planes_w<512>(W, p, lds, s);
 }
 
 __global__ void k_column_factors(const uint32_t* __restrict__ masks, int64_t n, const double* __restrict__ B,

@@ -223,7 +223,8 @@ class Plan:
 
     def timing_read(self, kind: int, spin: int):
         """-> (kernel ms, launches, algorithmic bytes, algorithmic VALU slots) of the recorded
-        launches of one kind (0 = window passes, 1 = segment passes) rotating one spin."""
+        launches of one kind (0 = window passes, 1 = segment passes, 2 = segment passes on row planes)
+        rotating one spin."""
         ms, n, b, v = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
         _check(_tread(self._h, 2 * kind + spin, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b), ctypes.byref(v)))
         return ms.value, n.value, b.value, v.value

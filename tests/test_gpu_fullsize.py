@@ -480,3 +480,28 @@ def test_symmetric_formulas_reversible_n16(ffx, dtype, order):
     err = torch.max(torch.abs((x - x0).to(torch.complex128))).item()
     assert moved > 1e-4
     assert record(f"s{order}_round_trip_n16", dtype, "amplitude", err, TOL[dtype]) <= TOL[dtype]
+
+
+def test_plane_passes_match_segment_passes_n16(ffx):
+    """At norb = 16 (8, 8), complex128, the visits of a DF step whose rotations are all real hold each row as
+    two planes (one pass per visit); with FFX_PLANES=0 every visit takes the half-row segment passes. The two
+    give the same step (different summation orders)."""
+    norb, nelec, dt = 16, (8, 8), 0.1
+    print("DF step n16: plane passes vs segment passes", flush=True)
+    w = synth.workload_df_trotter(norb, 16, seed=0, start="hf", dt=dt)
+    old = os.environ.get("FFX_PLANES")
+    os.environ["FFX_PLANES"] = "0"
+    try:
+        seg_plan = ffx.Plan(norb, nelec, torch.complex128)
+    finally:
+        if old is None:
+            del os.environ["FFX_PLANES"]
+        else:
+            os.environ["FFX_PLANES"] = old
+    x0 = _device_state(seg_plan.dim_a, torch.complex128, 23)
+    a = ffx.simulate_trotter_double_factorized(x0, w.data["ham"], dt, norb, nelec, n_steps=1, order=0,
+                                               plan=seg_plan)
+    b = ffx.simulate_trotter_double_factorized(x0, w.data["ham"], dt, norb, nelec, n_steps=1, order=0)
+    err = torch.max(torch.abs(a - b)).item()
+    del seg_plan
+    assert record("plane_vs_segment_df_step_n16", torch.complex128, "amplitude", err, 1e-12) <= 1e-12

@@ -382,3 +382,60 @@ def test_lucj_gradient_row_pair_transition_path(ffx):
         assert abs(e - float(np.real(eo))) <= tol * max(1.0, abs(float(np.real(eo))))
         assert np.max(np.abs(g - go)) <= tol * max(1.0, np.max(np.abs(go)))
 
+
+
+@pytest.fixture(scope="module")
+def plane_plans(ffx):
+    """complex128 plans whose all-real visits hold rows as two planes (real parts, imaginary parts) even
+    where whole rows fit in LDS (FFX_PLANES_ALL), in both block sizes of the plane pass."""
+    import os
+    plans = {}
+    old = {k: os.environ.get(k) for k in ("FFX_PLANES_ALL", "FFX_PLANES")}
+    os.environ["FFX_PLANES_ALL"] = "1"
+    try:
+        for threads in ("512", "768"):
+            os.environ["FFX_PLANES"] = threads
+            for norb, nelec in [(6, (3, 3)), (8, (4, 3)), (9, (4, 5)), (10, (5, 5))]:
+                plans[(norb, nelec, threads)] = ffx.Plan(norb, nelec, torch.complex128)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    return plans
+
+
+def test_plane_passes_against_oracle(ffx, plane_plans):
+    """Real rotations on row planes: DF steps (S_0, S_1, two steps; real U_t, the one-body factor making the
+    first rotation complex), the DF energy (reductions), the Hamiltonian action (accumulation), LUCJ energy and
+    gradient, and a real orbital rotation in place, against the oracle."""
+    for (norb, nelec, threads), plan in plane_plans.items():
+        print(f"plane passes norb={norb} nelec={nelec} threads={threads}", flush=True)
+        r = synth.rng([24, norb, int(threads)])
+        da, db = _dims(norb, nelec)
+        vec = _to_dev(synth.random_state(r, da, db), torch.complex128)
+        x = _ref_input(vec)
+        ham = synth.df_hamiltonian(r, norb, 3)
+        for order, n in ((0, 2), (1, 1)):
+            out = ffx.simulate_trotter_double_factorized(vec, ham, 0.1 * n, norb, nelec, n_steps=n, order=order,
+                                                         plan=plan)
+            ref = oh.simulate_trotter(x, ham, 0.1 * n, norb, nelec, n_steps=n, order=order)
+            err = record("plane_df_trotter", torch.complex128, "amplitude", _maxdiff(out, ref), 1e-12, norb=norb,
+                         threads=int(threads))
+            assert err <= 1e-12
+        e = ffx.df_energy(vec, ham, norb, nelec, plan=plan)
+        ref = oh.df_energy(x, ham, norb, nelec).real
+        assert abs(e - ref) <= 1e-12 * max(1.0, abs(ref))
+        hv = ffx.apply_df_hamiltonian(vec, ham, norb, nelec, plan=plan)
+        ref = oh.apply_df_hamiltonian(x, ham, norb, nelec)
+        assert _maxdiff(hv, ref) <= 1e-12 * max(1.0, float(np.abs(ref).max()))
+        O = synth.random_orthogonal(r, norb)
+        v2 = vec.clone()
+        ffx.apply_orbital_rotation(v2, O, norb, nelec, out=v2, plan=plan)
+        assert _maxdiff(v2, og.apply_orbital_rotation(x, O, norb, nelec)) <= 1e-12
+        params = synth.lucj_params(r, norb, 2, scale=0.3)
+        e, g = ffx.lucj_energy_grad(params, ham, norb, nelec, 2, plan=plan)
+        eo, go = ol.grad_adjoint(params, ham, norb, nelec, 2)
+        assert abs(e - float(np.real(eo))) <= 1e-12 * max(1.0, abs(float(np.real(eo))))
+        assert np.max(np.abs(g - go)) <= 1e-12 * max(1.0, np.max(np.abs(go)))

@@ -98,31 +98,38 @@ def committed_traffic(dtype_name: str):
 def cpu_baseline(ham, vec: np.ndarray, synth=None, hubbard_small=None) -> dict:
     """Time the oracle on a bounded sample of one Trotter step and scale to a whole step.
 
-    The oracle applies each orbital rotation as Gamma' = C(U) Gamma C(U)^T with
-    the compound matrix C(U) built from all dim^2 minors, and each diagonal
-    Coulomb phase over the whole state.  Sample: R_c rows of C(U) (R_c * dim
-    determinants), the product of R_g rows of C(U) with Gamma, and one full
-    diagonal Coulomb phase.  Scaled: per rotation dim/R_c * t_C + 2 dim/R_g * t_G;
-    per step (2L + 1) rotations and L phases (the oracle does not merge rotations).
+    The oracle applies each orbital rotation as Gamma' = C(U) Gamma C(U)^T with the compound matrix C(U)
+    built from all dim^2 minors (float64 determinants for a real U, its rows spread over the host cores), and
+    each diagonal Coulomb phase over the whole state.  Sample: R_c rows of C(U) for the first term's real
+    U_t^dag, the products of R_g rows of C(U) with the real and the imaginary part of Gamma (the oracle's
+    products for a real U), and one full diagonal-Coulomb phase.  Scaled: per rotation
+    dim/R_c * t_C + 2 dim/R_g * t_G; per step (2L + 1) rotations and L phases (the oracle does not merge
+    rotations; the step's one complex rotation, about twice the cost of a real one, is counted as real).
+    Beside it: the wall time of a whole oracle step measured once, stored with the oracle's result for the
+    16-orbital step (tests/golden/df_trotter_n16.txt).
     """
     from oracle import gates as og
-    from oracle import sampled
     from oracle import strings as ost
+    cores = len(os.sched_getaffinity(0))
     try:
         from threadpoolctl import threadpool_info
         blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
-        blas_threads = len(os.sched_getaffinity(0))
+        blas_threads = cores
+    workers = min(cores, 16)
+    og.set_workers(workers)
     d = ost.dim(NORB, NELEC[0])
     U = np.asarray(ham.U[0]).conj().T
-    ost.occupied_lists(NORB, NELEC[0])
-    R_c, R_g = 384, 768
+    R_c, R_g = 1024, 768
     t0 = time.perf_counter()
-    rows = np.array([sampled.compound_row(U, NELEC[0], i) for i in range(R_c)])
+    rows = og.compound_matrix(U, NELEC[0], rows=np.arange(R_c))
     t_c = time.perf_counter() - t0
-    A = np.vstack([rows] * (R_g // R_c))
+    og.set_workers(1)
+    A = np.ascontiguousarray(rows[:R_g])
+    re, im = np.ascontiguousarray(vec.real), np.ascontiguousarray(vec.imag)
     t0 = time.perf_counter()
-    _ = A @ vec
+    _ = A @ re
+    _ = A @ im
     t_g = time.perf_counter() - t0
     t0 = time.perf_counter()
     _ = og.apply_diag_coulomb_evolution(vec, ham.J[0], DT, NORB, NELEC)
@@ -132,12 +139,22 @@ def cpu_baseline(ham, vec: np.ndarray, synth=None, hubbard_small=None) -> dict:
     out = {
         "value": t_step,
         "unit": "s per DF Trotter step",
-        "cores": int(blas_threads),
+        "cores": int(max(workers, blas_threads)),
         "kind": "oracle",
-        "sample": (f"{R_c} rows of the compound matrix C_8(U) ({R_c}x{d} 8x8 determinants, {t_c:.1f} s), "
-                   f"{R_g}x{d} by {d}x{d} complex product ({t_g:.1f} s), one full diagonal-Coulomb phase "
-                   f"({t_p:.1f} s); scaled to {2 * L + 1} rotations + {L} phases per step"),
+        "sample": (f"{R_c} rows of the compound matrix C_8(U) ({R_c}x{d} 8x8 float64 determinants over {workers} "
+                   f"processes, {t_c:.1f} s), {R_g}x{d} by {d}x{d} real products with Re and Im of the state "
+                   f"({t_g:.1f} s on {blas_threads} BLAS threads), one full diagonal-Coulomb phase ({t_p:.1f} s); "
+                   f"scaled to {2 * L + 1} rotations + {L} phases per step"),
     }
+    golden = os.path.join(ROOT, "tests", "golden", "df_trotter_n16.txt")
+    if os.path.exists(golden):
+        with open(golden) as fh:
+            for line in fh:
+                if line.startswith("step_seconds"):
+                    _, secs, ncores = line.split()
+                    out["measured_whole_step"] = {"s": float(secs), "cores": int(ncores),
+                                                  "where": "the build host (8 cores), once, for the stored "
+                                                           "oracle result of this step"}
     if hubbard_small is not None:
         # the Trotter-error leg's small lattice, whole, in the oracle
         from oracle import hamiltonian as oh

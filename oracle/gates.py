@@ -27,7 +27,7 @@ def set_workers(n: int) -> None:
     _WORKERS = max(1, int(n))
 
 
-def compound_matrix(U: np.ndarray, n: int, chunk: int | None = None) -> np.ndarray:
+def compound_matrix(U: np.ndarray, n: int, chunk: int | None = None, rows=None) -> np.ndarray:
     """C_n(U)[J, I] = det U[J, I] over n-subsets J (rows) and I (columns), ascending addresses.
 
     From the defining relation of an orbital rotation, script-U a^dag_p
@@ -35,7 +35,8 @@ def compound_matrix(U: np.ndarray, n: int, chunk: int | None = None) -> np.ndarr
     cre(I)|vac> = a^dag_{i_n}...a^dag_{i_1}|vac> and collecting the ordered
     products gives sum_J det(U[J, I]) |J>, i.e. column I of C_n(U).
     C_0(U) = [[1]].  A real U (no nonzero imaginary part) gives a real matrix,
-    its determinants taken in float64.
+    its determinants taken in float64.  rows (optional): only those rows J, in
+    the order given.
     """
     norb = U.shape[0]
     occ = st.occupied_lists(norb, n)
@@ -49,22 +50,25 @@ def compound_matrix(U: np.ndarray, n: int, chunk: int | None = None) -> np.ndarr
     if chunk is None:
         chunk = max(1, min(256, (1 << 26) // (d * n * n)))
 
+    row_occ = occ if rows is None else occ[np.asarray(rows, dtype=np.int64)]
+    nr = len(row_occ)
+
     def fill(j0, j1, out):
         for a in range(j0, j1, chunk):
             b = min(a + chunk, j1)
-            # minors[r, c] = U[occ[a + r]][:, occ[c]]  -> shape (b - a, d, n, n)
-            sub = U[occ[a:b, None, :, None], occ[None, :, None, :]]
+            # minors[r, c] = U[row_occ[a + r]][:, occ[c]]  -> shape (b - a, d, n, n)
+            sub = U[row_occ[a:b, None, :, None], occ[None, :, None, :]]
             out[a:b] = np.linalg.det(sub)
 
-    if _WORKERS <= 1 or d < 4 * chunk:
-        out = np.empty((d, d), dtype=dtype)
-        fill(0, d, out)
+    if _WORKERS <= 1 or nr < 4 * chunk:
+        out = np.empty((nr, d), dtype=dtype)
+        fill(0, nr, out)
         return out
     import mmap
     import multiprocessing
-    buf = mmap.mmap(-1, d * d * np.dtype(dtype).itemsize)
-    out = np.frombuffer(buf, dtype=dtype).reshape(d, d)
-    bounds = np.linspace(0, d, _WORKERS + 1).astype(int)
+    buf = mmap.mmap(-1, nr * d * np.dtype(dtype).itemsize)
+    out = np.frombuffer(buf, dtype=dtype).reshape(nr, d)
+    bounds = np.linspace(0, nr, _WORKERS + 1).astype(int)
     ctx = multiprocessing.get_context("fork")
     procs = [ctx.Process(target=fill, args=(int(bounds[k]), int(bounds[k + 1]), out))
              for k in range(_WORKERS)]

@@ -57,6 +57,24 @@ def test_orbital_rotation_homomorphism_and_adjoint():
     assert abs(np.linalg.norm(g.apply_orbital_rotation(vec, U, norb, nelec)) - 1) < 1e-13
 
 
+def test_compound_matrix_rows_and_workers():
+    """Selected rows of C_n(U) equal those rows of the whole matrix, in the order asked, for a real and a
+    complex U, with the rows spread over worker processes or not; C_1(U) = U."""
+    r = synth.rng(11)
+    norb, n = 7, 3
+    for U in (synth.random_unitary(r, norb), synth.random_unitary(r, norb).real.copy()):
+        full = g.compound_matrix(U, n)
+        np.testing.assert_allclose(g.compound_matrix(U, 1), U, atol=1e-15)
+        rows = np.array([34, 0, 5, 17, 5])
+        np.testing.assert_allclose(g.compound_matrix(U, n, rows=rows), full[rows], atol=0)
+        g.set_workers(3)
+        try:
+            np.testing.assert_allclose(g.compound_matrix(U, n, chunk=1), full, atol=1e-15)
+            np.testing.assert_allclose(g.compound_matrix(U, n, chunk=1, rows=np.arange(20)), full[:20], atol=1e-15)
+        finally:
+            g.set_workers(1)
+
+
 def test_slater_determinant_amplitudes():
     """script-U(U)|HF> has amplitudes det U[J_a, occ] det U[J_b, occ] (Sec. 2.4)."""
     r = synth.rng(4)

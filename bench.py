@@ -552,6 +552,86 @@ def table1_timing(ffx, torch, synth):
     return out
 
 
+def _event_times(torch, call, reps, warmup):
+    """Milliseconds per call of `call` (HIP events on the current stream between consecutive calls):
+    median, interquartile range and mean over `reps` calls after `warmup`."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for k in range(reps):
+        call()
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(reps)])
+    return {"median_ms": round(float(np.median(per)), 5),
+            "iqr_ms": round(float(np.percentile(per, 75) - np.percentile(per, 25)), 5),
+            "mean_ms": round(float(per.mean()), 5)}
+
+
+def config2_timing(ffx, torch, synth, reps=20, warmup=3):
+    """DF Trotter at norb = 14, (7, 7), L = 14 (h ~ N(0, 0.5), U_t real orthogonal, J_t ~ N(0, 0.1)), dt = 0.1:
+    two S_0 steps from the Hartree-Fock state per call (out of place, so every call starts from it), in both
+    precisions.  The 3432 x 3432 state (188 / 94 MB) stays in the 256 MB Infinity Cache, so the figure is
+    time, not an HBM rate."""
+    dev = torch.device("cuda:0")
+    w = synth.workload_df_trotter(14, 14, seed=0, start="hf", dt=0.1, n_steps=2)
+    ham = w.data["ham"]
+    out = {"workload": "df_trotter norb=14 nelec=(7,7) L=14 dt=0.1 order=0, 2 steps per call from Hartree-Fock"}
+    for name, dtype in (("c128", torch.complex128), ("c64", torch.complex64)):
+        v0 = torch.from_numpy(w.data["vec"]).to(dtype).to(dev)
+        vec = torch.empty_like(v0)
+        plan = ffx.get_plan(14, (7, 7), dtype, 0)
+
+        def call():
+            ffx.simulate_trotter_double_factorized(v0, ham, 0.2, 14, (7, 7), n_steps=2, order=0, out=vec,
+                                                   plan=plan)
+
+        t = _event_times(torch, call, reps, warmup)
+        out[name] = {"s_per_step_median": round(t["median_ms"] / 2e3, 7), "ms_per_call": t,
+                     "final_norm": float(torch.linalg.vector_norm(vec.to(torch.complex128)))}
+        del v0, vec
+    return out
+
+
+def fig2_shapes(ffx, torch, synth, reps=20, warmup=3, norbs=range(4, 17, 2)):
+    """Time per call, in the shape of the paper's Fig. 2 benchmarks (Sec. 5.2), complex128 state resident on
+    the device: quadratic-Hamiltonian evolution (random Hermitian M, t = 1), diagonal-Coulomb evolution
+    (random symmetric J, t = 1) and three S_0 steps of a DF Trotter simulation of a Hamiltonian with three
+    two-body terms (dt = 0.1), for norb = 4, 6, ..., 16 at half filling (norb / 2 electrons per spin) and at
+    quarter filling (norb // 4 per spin).  Median and interquartile range of `reps` calls."""
+    dev = torch.device("cuda:0")
+    out = {"workload": "Fig. 2 shapes: quad_ham_evolution, diag_coulomb_evolution, df_trotter 3 steps L=3; "
+                       "c128; norb 4..16; half and quarter filling"}
+    for filling, nfun in (("half", lambda n: n // 2), ("quarter", lambda n: n // 4)):
+        rows = {}
+        for norb in norbs:
+            n = nfun(norb)
+            nelec = (n, n)
+            r = synth.rng(100 + norb)
+            d = synth.dim(norb, n)
+            vec = torch.from_numpy(synth.random_state(r, d, d)).to(dev)
+            plan = ffx.get_plan(norb, nelec, torch.complex128, 0)
+            M = synth.random_hermitian(r, norb, 0.5)
+            J = synth.random_symmetric(r, norb, 0.3)
+            ham = synth.df_hamiltonian(r, norb, 3)
+            calls = {
+                "quad_ham_evolution": lambda: ffx.apply_quad_ham_evolution(vec, M, 1.0, norb, nelec, out=vec,
+                                                                           plan=plan),
+                "diag_coulomb_evolution": lambda: ffx.apply_diag_coulomb_evolution(vec, J, 1.0, norb, nelec,
+                                                                                   out=vec, plan=plan),
+                "df_trotter_3_steps_L3": lambda: ffx.simulate_trotter_double_factorized(
+                    vec, ham, 0.3, norb, nelec, n_steps=3, order=0, out=vec, plan=plan),
+            }
+            rows[f"norb{norb}_({n},{n})"] = {k: _event_times(torch, f, reps, warmup) for k, f in calls.items()}
+            del vec
+        out[filling] = rows
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_calibration(torch):
     """Plain device copies of a known size for scaling the HBM byte counters."""
     n = 1 << 27  # 2^27 complex64 = 1 GiB
@@ -585,6 +665,10 @@ def main():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--dense-only", action="store_true",
                     help="run only the dense-vs-Givens rotation leg (for profiling)")
+    ap.add_argument("--no-config2", action="store_true")
+    ap.add_argument("--no-fig2", action="store_true")
+    ap.add_argument("--context-only", action="store_true",
+                    help="run only the norb=14 DF leg and the Fig. 2-shaped legs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the state of this workload fits one MI355X and the build has no "
@@ -606,6 +690,10 @@ def main():
         return
     if args.dense_only:
         print(json.dumps({"rotation_dense_vs_givens_c128": dense_vs_givens(ffx, torch, synth)}), flush=True)
+        return
+    if args.context_only:
+        print(json.dumps({"df_trotter_n14": config2_timing(ffx, torch, synth),
+                          "fig2_shapes": fig2_shapes(ffx, torch, synth)}), flush=True)
         return
 
     types = {"c128": torch.complex128, "c64": torch.complex64}
@@ -665,6 +753,10 @@ def main():
         out["df_step_n18"] = {"workload": "df_trotter_step norb=18 nelec=(9,9) L=18 dt=0.1 order=0, random state",
                               "c128": n18_timing(ffx, torch, synth, torch.complex128),
                               "c64": n18_timing(ffx, torch, synth, torch.complex64)}
+    if not args.no_config2:
+        out["df_trotter_n14"] = config2_timing(ffx, torch, synth)
+    if not args.no_fig2:
+        out["fig2_shapes"] = fig2_shapes(ffx, torch, synth)
     if not args.no_table1:
         out["table1_gates_n16_c128"] = table1_timing(ffx, torch, synth)
     if not args.no_dense:

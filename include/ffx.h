@@ -384,7 +384,7 @@ int64_t ffx_batch_workspace_bytes(ffx_batch batch);
    columns of one instance's state) with a grid barrier between levels; with
    ffx_batch_single_launch(batch, 0), one kernel launch per level instead.  A
    persistent launch over a task queue with per-instance dependency counters
-   is built but switched off. */
+   is built but switched off (ffx_batch_persistent). */
 int ffx_batch_lucj_energy_grad(ffx_batch batch, const ffx_lucj* ops, const ffx_df_ham* hams,
                                double* energies, double* grads, void* workspace, void* stream);
 
@@ -417,6 +417,23 @@ int ffx_batch_timing(ffx_batch batch, double* device_ms, double* call_ms, int* l
    launch; the cooperative launch sizes its grid the same way for its own
    kernel), and the LDS bytes per block. */
 int ffx_batch_info(ffx_batch batch, int* target_elems, int* stage_rots, int* blocks, int64_t* lds_bytes);
+
+/* Diagnostics of the batched task queue: builds every instance's passes for
+   these operators and Hamiltonians exactly as ffx_batch_lucj_energy_grad does
+   (programs compiled, tables uploaded on `stream`), launches none of them, and
+   writes the queue in task order, one row of six int64 per pass: pass level,
+   instance, pass kind, tasks, dependency count (tasks of the instance's
+   earlier passes that must have finished before any task of this pass
+   starts) and the pass's first task in the queue.  *n_passes: the number of
+   rows; table may be NULL to ask for it; cap (rows) < *n_passes gives
+   FFX_EINVAL. */
+int ffx_batch_queue(ffx_batch batch, const ffx_lucj* ops, const ffx_df_ham* hams, void* workspace, void* stream,
+                    int64_t* table, int64_t cap, int64_t* n_passes);
+
+/* The persistent launch over that queue (blocks take tasks from one atomic
+   counter and wait on per-instance counters of finished tasks).  Switched off:
+   enable != 0 gives FFX_EUNSUPPORTED, enable = 0 succeeds. */
+int ffx_batch_persistent(ffx_batch batch, int enable);
 
 /* Diagnostics: per-launch timing of the dominant kernels.  While enabled,
    each segment pass and each window pass is bracketed by HIP events on the

@@ -58,10 +58,14 @@ void ensure_rank_tables(ffx_plan_s& P) {
       hi[v * 17 + c] = acc;
     }
   }
-  P.rank_lo = (int*)P.dalloc(lo.size() * 4);
-  P.rank_hi = (int*)P.dalloc(hi.size() * 4);
-  HIPCHK(hipMemcpy(P.rank_lo, lo.data(), lo.size() * 4, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(P.rank_hi, hi.data(), hi.size() * 4, hipMemcpyHostToDevice));
+  // published only once both tables are on the device (a failure in between
+  // leaves the plan without them, to be built by the next call)
+  int* dlo = (int*)P.dalloc(lo.size() * 4);
+  int* dhi = (int*)P.dalloc(hi.size() * 4);
+  HIPCHK(hipMemcpy(dlo, lo.data(), lo.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(dhi, hi.data(), hi.size() * 4, hipMemcpyHostToDevice));
+  P.rank_lo = dlo;
+  P.rank_hi = dhi;
 }
 
 // The (n-1)-electron strings K of column spin cs for the matrix-core kernel,
@@ -260,7 +264,8 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
     }
     // upload ring
     P->slot_bytes = (size_t)4 << 20;
-    if (hipHostMalloc((void**)&P->h_ring, P->slot_bytes * ffx_plan_s::kSlots, hipHostMallocDefault) != hipSuccess)
+    if (fault_hit("alloc") ||
+        hipHostMalloc((void**)&P->h_ring, P->slot_bytes * ffx_plan_s::kSlots, hipHostMallocDefault) != hipSuccess)
       throw Error(FFX_ENOMEM, "pinned host allocation failed");
     P->d_ring = (char*)P->dalloc(P->slot_bytes * ffx_plan_s::kSlots);
     for (auto& e : P->ev) {
@@ -956,7 +961,8 @@ struct HamAction {
   }
   void* alloc(size_t bytes) {
     void* p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(bytes, 8)) != hipSuccess) throw Error(FFX_ENOMEM, "device allocation failed");
+    if (fault_hit("alloc") || hipMalloc(&p, std::max<size_t>(bytes, 8)) != hipSuccess)
+      throw Error(FFX_ENOMEM, "device allocation failed");
     bufs.push_back(p);
     return p;
   }

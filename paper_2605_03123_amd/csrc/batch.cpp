@@ -82,7 +82,7 @@ struct ffx_batch_s {
   }
   void* dalloc(size_t bytes) {
     void* p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess || !p)
+    if (fault_hit("alloc") || hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess || !p)
       throw Error(FFX_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
     return p;
   }
@@ -247,7 +247,7 @@ struct InstBuild {
 
 // one call: compile, build passes, launch, assemble
 void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, double* energies, double* grads,
-               void* workspace, hipStream_t s, float* kernel_ms) {
+               void* workspace, hipStream_t s, float* kernel_ms, std::vector<int64_t>* queue = nullptr) {
   const int n = b.n_inst;
   std::vector<InstBuild> ib(n);
   // the per-instance decompositions and gate programs are independent: built
@@ -294,10 +294,15 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
   size_t up_need = 0, arena_need = 0;
   {
     Upload m(nullptr, (char*)(uintptr_t)256, (size_t)1 << 40, s);
-    double* saved = b.arena;
+    // measured with no arena (the hook hands out stand-in addresses); the
+    // arena comes back also when the measuring compile throws
+    struct KeepArena {
+      double*& slot;
+      double* saved;
+      ~KeepArena() { slot = saved; }
+    } keep{b.arena, b.arena};
     b.arena = nullptr;
     compile_all(m);
-    b.arena = saved;
     up_need = m.off;
     arena_need = b.arena_used;
   }
@@ -320,10 +325,6 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
   // passes are uploaded after the programs' data
   std::vector<InstPasses> ip(n);
   std::vector<std::vector<dev::BTableDev>> tabs(n);
-  // size of the pass list is known only after building; allocate generously
-  const size_t extra_guess = 0;
-  (void)extra_guess;
-
   // build passes with device addresses (needs workspace, scratch)
   char* ws = (char*)workspace;
   std::vector<size_t> ws_off(n);
@@ -371,8 +372,8 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
     b.h_up = nullptr;
     b.d_up = nullptr;
     b.up_cap = 0;
-    if (hipHostMalloc((void**)&b.h_up, up_total, hipHostMallocDefault) != hipSuccess)
-      throw Error(FFX_ENOMEM, "pinned upload buffer");
+    if (fault_hit("alloc") || hipHostMalloc((void**)&b.h_up, up_total, hipHostMallocDefault) != hipSuccess)
+      throw Error(FFX_ENOMEM, "pinned host allocation of the upload buffer failed");
     b.d_up = (char*)b.dalloc(up_total);
     b.up_cap = up_total;
   }
@@ -573,6 +574,17 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
     }
   }
   level_start.push_back((int)all.size());
+  if (queue) {  // the task queue only: nothing is launched
+    queue->clear();
+    for (size_t lv = 0; lv + 1 < level_start.size(); ++lv)
+      for (int pi = level_start[lv]; pi < level_start[lv + 1]; ++pi) {
+        const dev::BPassDev& p = all[pi];
+        for (int64_t v : {(int64_t)lv, (int64_t)p.inst, (int64_t)p.kind, (int64_t)p.n_tasks, (int64_t)p.need,
+                          p.first})
+          queue->push_back(v);
+      }
+    return;
+  }
   const dev::BPassDev* d_passes = up.put(all.data(), all.size());
   const int* d_levels = up.put(level_start.data(), level_start.size());
   up.commit();
@@ -778,6 +790,34 @@ int ffx_batch_single_launch(ffx_batch batch, int enable) {
   return guard([&] {
     if (!batch) throw Error(FFX_EINVAL, "null batch");
     batch->single_launch = enable != 0;
+  });
+}
+
+int ffx_batch_queue(ffx_batch batch, const ffx_lucj* ops, const ffx_df_ham* hams, void* workspace, void* stream,
+                    int64_t* table, int64_t cap, int64_t* n_passes) {
+  return guard([&] {
+    if (!batch || !ops || !hams || !workspace || !n_passes) throw Error(FFX_EINVAL, "null pointer");
+    HIPCHK(hipSetDevice(batch->device));
+    std::vector<int64_t> q;
+    std::vector<double> e(batch->n_inst);
+    size_t ng = 0;
+    for (int i = 0; i < batch->n_inst; ++i) ng += (size_t)ffx_lucj_n_params(ops[i].norb, ops[i].n_reps);
+    std::vector<double> g(ng);
+    run_batch(*batch, ops, hams, e.data(), g.data(), workspace, (hipStream_t)stream, nullptr, &q);
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    *n_passes = (int64_t)(q.size() / 6);
+    if (table) {
+      if (cap < *n_passes) throw Error(FFX_EINVAL, "queue table too small");
+      std::copy(q.begin(), q.end(), table);
+    }
+  });
+}
+
+int ffx_batch_persistent(ffx_batch batch, int enable) {
+  return guard([&] {
+    if (!batch) throw Error(FFX_EINVAL, "null batch");
+    if (enable) throw Error(FFX_EUNSUPPORTED, "the task-queue persistent launch is switched off");
+    batch->persistent = false;
   });
 }
 

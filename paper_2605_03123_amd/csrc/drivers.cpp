@@ -3,12 +3,36 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
 
 namespace ffx {
 
 std::string& last_error() {
   thread_local std::string msg;
   return msg;
+}
+
+bool fault_hit(const char* site) {
+  static std::mutex mu;
+  static std::string armed;
+  static long long calls = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  const char* e = std::getenv("FFX_FAULT");
+  if (!e || !*e) {
+    armed.clear();
+    calls = 0;
+    return false;
+  }
+  if (armed != e) {
+    armed = e;
+    calls = 0;
+  }
+  const char* colon = std::strchr(e, ':');
+  if (!colon || std::strncmp(e, site, (size_t)(colon - e)) != 0 || site[colon - e] != '\0') return false;
+  const long long k = std::atoll(colon + 1);
+  return k >= 1 && ++calls == k;
 }
 
 std::vector<cd> load_complex(int n, const double* p) {

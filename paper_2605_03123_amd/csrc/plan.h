@@ -108,7 +108,7 @@ struct ffx_plan_s {
 
   void* dalloc(size_t bytes) {
     void* p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess || !p)
+    if (ffx::fault_hit("alloc") || hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess || !p)
       throw ffx::Error(FFX_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
     allocs.push_back(p);
     return p;
@@ -144,31 +144,34 @@ struct ffx_plan_s {
   void* arena_ctx = nullptr;
   int max_stage_rots = ffx::dev::kMaxStageRots;  // Givens rotations per stage (fusion depth)
   static constexpr int kArenaSlots = 64;
-  // the device result block, grown to at least `doubles` (waits for the device
-  // before freeing the old block, which earlier work on any stream may still use)
+  // the device result block, grown to at least `doubles`.  The new block is
+  // allocated before the old one is released (after waiting for the device,
+  // since earlier work on any stream may still use it), so a failed
+  // allocation leaves the plan with its old block.
   double* results_for(size_t doubles, hipStream_t s) {
     if (doubles > results_cap) {
-      HIPCHK(hipStreamSynchronize(s));
-      HIPCHK(hipDeviceSynchronize());
-      allocs.erase(std::find(allocs.begin(), allocs.end(), (void*)results));
-      (void)hipFree(results);
-      results = nullptr;
-      results_cap = 0;
-      results = (double*)dalloc(doubles * sizeof(double));
+      double* grown = (double*)dalloc(doubles * sizeof(double));
+      release_block(results, s);
+      results = grown;
       results_cap = doubles;
     }
     return results;
   }
   double* arena_for(size_t doubles, hipStream_t s) {
     if (doubles > arena_doubles) {
-      HIPCHK(hipStreamSynchronize(s));
-      HIPCHK(hipDeviceSynchronize());
-      allocs.erase(std::find(allocs.begin(), allocs.end(), (void*)arena));
-      (void)hipFree(arena);
-      arena = (double*)dalloc(doubles * sizeof(double));
+      double* grown = (double*)dalloc(doubles * sizeof(double));
+      release_block(arena, s);
+      arena = grown;
       arena_doubles = doubles;
     }
     return arena;
+  }
+  void release_block(double* p, hipStream_t s) {
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipDeviceSynchronize());
+    auto it = std::find(allocs.begin(), allocs.end(), (void*)p);
+    if (it != allocs.end()) allocs.erase(it);
+    if (p) (void)hipFree(p);
   }
 
   ~ffx_plan_s() {

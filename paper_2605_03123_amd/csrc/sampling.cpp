@@ -21,7 +21,8 @@ namespace {
 struct DevBuf {
   void* p = nullptr;
   explicit DevBuf(size_t bytes) {
-    if (bytes && hipMalloc(&p, bytes) != hipSuccess) throw Error(FFX_ENOMEM, "device allocation failed");
+    if (bytes && (fault_hit("alloc") || hipMalloc(&p, bytes) != hipSuccess))
+      throw Error(FFX_ENOMEM, "device allocation failed");
   }
   ~DevBuf() {
     if (p) (void)hipFree(p);

@@ -688,6 +688,10 @@ _batch_tune = _sig("ffx_batch_tune", ctypes.c_int,
 _batch_timing = _sig("ffx_batch_timing", ctypes.c_int,
                      [_vp, _c_double_p, _c_double_p, _c_int_p])
 _batch_single = _sig("ffx_batch_single_launch", ctypes.c_int, [_vp, ctypes.c_int])
+_batch_queue = _sig("ffx_batch_queue", ctypes.c_int,
+                    [_vp, ctypes.POINTER(_LUCJ), ctypes.POINTER(_DFHam), _vp, _vp, ctypes.c_void_p,
+                     ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)])
+_batch_persistent = _sig("ffx_batch_persistent", ctypes.c_int, [_vp, ctypes.c_int])
 _batch_info = _sig("ffx_batch_info", ctypes.c_int,
                    [_vp, _c_int_p, _c_int_p, _c_int_p, ctypes.POINTER(ctypes.c_int64)])
 
@@ -774,6 +778,22 @@ class Batch:
         """Run later calls as one cooperative launch over all pass levels (the default), or with
         enable=False as one launch per level."""
         _check(_batch_single(self._h, int(bool(enable))))
+
+    def persistent(self, enable: bool = True):
+        """The task-queue persistent launch (switched off: enable=True raises)."""
+        _check(_batch_persistent(self._h, int(bool(enable))))
+
+    def queue(self, params_list, hams, n_reps: int) -> np.ndarray:
+        """The task queue of a call with these arguments, nothing launched: one row per pass, in task order,
+        columns (level, instance, kind, tasks, dependency count, first task)."""
+        ops, hs, keep = self._args(params_list, hams, n_reps)
+        ws = self.workspace()
+        n = ctypes.c_int64()
+        _check(_batch_queue(self._h, ops, hs, _vp(ws.data_ptr()), _stream(ws.device), None, 0, ctypes.byref(n)))
+        out = np.zeros((n.value, 6), dtype=np.int64)
+        _check(_batch_queue(self._h, ops, hs, _vp(ws.data_ptr()), _stream(ws.device),
+                            out.ctypes.data_as(ctypes.c_void_p), n.value, ctypes.byref(n)))
+        return out
 
     def info(self) -> dict:
         t, r, b, lds = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()

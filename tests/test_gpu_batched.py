@@ -153,8 +153,45 @@ def test_batched_single_cooperative_launch(ffx):
         np.testing.assert_array_equal(e2, e0)
 
 
+def test_batched_queue_protocol(ffx):
+    """The task queue of the 256-sector workload, as the library builds it (nothing launched), run through
+    the host model of the persistent launch's protocol at the launch's resident block count: the queue lists
+    every pass after the passes it depends on, each dependency count equals the instance's earlier tasks, the
+    model finishes without a stuck wait and counts every task of every instance."""
+    import queue_sim as qs
+    w = synth.workload_batched(256, seed=0, n_reps=2)
+    b = ffx.Batch([(x.norb, x.nelec) for x in w], dtype=torch.complex64)
+    q = b.queue([x.data["params"] for x in w], [x.data["ham"] for x in w], 2)
+    blocks = b.info()["blocks"]
+    assert len(q) and blocks > 0
+    assert qs.static_checks(q) == []
+    r = qs.simulate(q, blocks)
+    assert r["finished"] and r["counts_match"] and not r["deadlock"], r
+    n_tasks, levels = int(q[:, qs.TASKS].sum()), len(np.unique(q[:, qs.LEVEL]))
+    print(f"batched queue: {len(q)} passes, {n_tasks} tasks, {levels} levels, {blocks} resident blocks; "
+          f"unit-time makespan {r['makespan']:.0f} (level-synchronous {qs.level_makespan(q, blocks)}), "
+          f"at most {r['max_waiting']} blocks waiting", flush=True)
+
+
 @pytest.mark.skip(reason="the single persistent launch (task queue with per-instance dependency counters) is "
-                         "switched off: its last GPU run did not complete and the cause is not established; "
-                         "batches run one launch per pass level")
+                         "switched off: its GPU runs did not complete, and the cause is not established (the "
+                         "queue protocol is shown deadlock-free on the host by test_batched_queue_protocol); "
+                         "batches run as one cooperative launch or one launch per pass level")
 def test_batched_persistent_single_launch(ffx):
-    pass
+    """The persistent launch gives the per-level launches' energies and gradients bit for bit, in both
+    precisions, over two calls in a row, and ends in one launch."""
+    w = synth.workload_batched(16, seed=5, n_reps=1)
+    sectors = [(x.norb, x.nelec) for x in w]
+    args = ([x.data["params"] for x in w], [x.data["ham"] for x in w], 1)
+    for dtype in (torch.complex64, torch.complex128):
+        b = ffx.Batch(sectors, dtype=dtype)
+        b.single_launch(False)
+        e0, g0 = b.lucj_energy_grad(*args)
+        b.persistent(True)
+        for _ in range(2):
+            e1, g1 = b.lucj_energy_grad(*args)
+            assert b.timing()["launches"] == 1
+            np.testing.assert_array_equal(e1, e0)
+            for a, c in zip(g1, g0):
+                np.testing.assert_array_equal(a, c)
+        b.persistent(False)

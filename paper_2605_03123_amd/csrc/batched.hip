@@ -376,7 +376,8 @@ __device__ __forceinline__ void seg_task(const BatchDev& B, const BPassDev& ps, 
   const int64_t r0 = (int64_t)task * RR;
   const int nr = (int)std::min<int64_t>(RR, nrows - r0);
   const int64_t nel = (int64_t)nr * len;
-  const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+  const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, nwaves = nthr >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wave: chunk loops stay scalar
   V* buf = (V*)L.rows;
   const V* s = (const V*)src;
 
@@ -433,7 +434,7 @@ __device__ __forceinline__ void seg_task(const BatchDev& B, const BPassDev& ps, 
   double acc = 0.0;
   // each Givens stage's rotations and first class codes are requested a stage
   // ahead (as in the segment pass)
-  RotLane<R> rl_next{0, R(1), R(0), R(0)};
+  RotLane<R> rl_next{nullptr};
   ChunkAhead fc_next{1, -1};
   auto fetch = [&](int si) {
     const StageDev st = uniform_load(ps.stages + si);

@@ -5,7 +5,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
+#include <type_traits>
 #include <utility>
 
 #include "device.h"
@@ -137,12 +139,15 @@ __device__ __forceinline__ V cmul(V a, V b) {
 }
 
 // d <- a * d + b, written into d's own register: with the result tied to
-// the input, the member registers never move across the rotation loop
+// the input, the member registers never move across the rotation loop.  a is
+// a rotation's cosine, the same in every lane: it is read from scalar
+// registers (one scalar operand per instruction, within the constant-bus
+// limit), so it needs no copy into vector registers.
 __device__ __forceinline__ void fma_ip(float& d, float a, float b) {
-  asm("v_fma_f32 %0, %1, %0, %2" : "+v"(d) : "v"(a), "v"(b));
+  asm("v_fma_f32 %0, %1, %0, %2" : "+v"(d) : "s"(a), "v"(b));
 }
 __device__ __forceinline__ void fma_ip(double& d, double a, double b) {
-  asm("v_fma_f64 %0, %1, %0, %2" : "+v"(d) : "v"(a), "v"(b));
+  asm("v_fma_f64 %0, %1, %0, %2" : "+v"(d) : "s"(a), "v"(b));
 }
 
 // x' = c x + s y, y' = -conj(s) x + c y on one member pair (A, B)
@@ -214,53 +219,84 @@ __device__ __forceinline__ void apply_rots(V* v, const RotDev* __restrict__ rots
   }
 }
 
-// The rotations of one stage spread over the lanes of a wave (lane i holds
-// rotation i, at most 64); the rotation loop broadcasts rotation r with
-// v_readlane, so its parameters are scalars, the window position selects a
-// scalar branch, and no memory access sits inside the loop.
+// The rotations of one stage, as the rotation loops see them: the stage's
+// rotation list g (a uniform pointer).  The parameters are read straight into
+// scalar registers (FP64 values for complex128 elements and row planes, their
+// FP32 copies for complex64), one rotation ahead of their use, so no vector
+// instruction moves them; the window position selects a scalar branch.
 template <class R>
 struct RotLane {
-  int p;
-  R c, sr, si;
+  const RotDev* g;
 };
 
-__device__ __forceinline__ int lane_bcast(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
-__device__ __forceinline__ float lane_bcast(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+template <class T>
+__device__ __forceinline__ T uniform_load(const T* p);
+
+// the parameters a rotation loop reads with scalar loads: (c, sr) of a real
+// rotation, (c, sr, si) of a complex one, in the element's precision
+template <class R>
+struct RotParR {
+  R c, sr;
+};
+template <class R>
+struct RotParC {
+  R c, sr, si;
+};
+template <bool REAL, class R>
+using RotQ = typename std::conditional<REAL, RotParR<R>, RotParC<R>>::type;
+template <bool REAL, class R>
+__device__ __forceinline__ RotQ<REAL, R> rot_params(const RotDev* g, int i) {
+  static_assert(offsetof(RotDev, c) == 8 && offsetof(RotDev, sr) == 16 && offsetof(RotDev, si) == 24 &&
+                    offsetof(RotDev, fc) == 32 && offsetof(RotDev, fsr) == 36 && offsetof(RotDev, fsi) == 40,
+                "scalar parameter loads assume RotDev = {p, pad, c, sr, si, fc, fsr, fsi, fpad}");
+  constexpr int off = std::is_same<R, double>::value ? 8 : 32;
+  return uniform_load((const RotQ<REAL, R>*)((const char*)(g + i) + off));
 }
-__device__ __forceinline__ double lane_bcast(double v, int l) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+template <bool REAL, class R>
+__device__ __forceinline__ R rot_si(const RotQ<REAL, R>& q) {
+  if constexpr (REAL)
+    return R(0);
+  else
+    return q.si;
 }
 
+// Generic stages: rotation r's position and parameters, loaded one rotation
+// ahead; the position selects the code through a scalar branch.
 template <int W, int M, bool REAL, class V>
 __device__ __forceinline__ void apply_rots_lane(V* v, const RotLane<ER<V>>& rl, int nrot) {
   using R = ER<V>;
+  if (nrot <= 0) return;
+  RotDev cur = uniform_load(rl.g);
   for (int r = 0; r < nrot; ++r) {
-    int p = lane_bcast(rl.p, r);
-    asm volatile("" : "+v"(p));
-    rot_dispatch<W, M, REAL, V>(p, v, lane_bcast(rl.c, r), lane_bcast(rl.sr, r),
-                                REAL ? R(0) : lane_bcast(rl.si, r));
+    const RotDev nxt = uniform_load(rl.g + (r + 1 < nrot ? r + 1 : r));
+    if constexpr (std::is_same<R, double>::value)
+      rot_dispatch<W, M, REAL, V>(cur.p, v, cur.c, cur.sr, REAL ? 0.0 : cur.si);
+    else
+      rot_dispatch<W, M, REAL, V>(cur.p, v, cur.fc, cur.fsr, REAL ? 0.0f : cur.fsi);
+    cur = nxt;
   }
 }
 
-// The rotations of stage shape S, positions fixed at compile time: rotation i
-// takes its parameters from lane i and acts on window position kShapeP[S][i].
+// The rotations of stage shape S, positions fixed at compile time: rotation I
+// acts on window position kShapeP[S][I]; its parameters arrive in scalar
+// registers, requested while rotation I - 1 is applied.
 template <int W, int M, bool REAL, class V, int S, int I>
-__device__ __forceinline__ void shape_rot(V* v, const RotLane<ER<V>>& rl) {
+__device__ __forceinline__ RotQ<REAL, ER<V>> shape_rot(V* v, const RotDev* g, RotQ<REAL, ER<V>> cur) {
   using R = ER<V>;
-  rot_one<W, M, kShapeP[S][I], REAL, V>(v, lane_bcast(rl.c, I), lane_bcast(rl.sr, I),
-                                        REAL ? R(0) : lane_bcast(rl.si, I));
-  // rotation parameters are broadcast next to their use: hoisting the
-  // broadcasts of later rotations only holds scalar registers
+  constexpr int n = kShapeLen[S];
+  const RotQ<REAL, R> nxt = rot_params<REAL, R>(g, I + 1 < n ? I + 1 : I);
+  rot_one<W, M, kShapeP[S][I], REAL, V>(v, cur.c, cur.sr, rot_si<REAL, R>(cur));
+  // nothing of a later rotation is scheduled into this one, where it would
+  // only hold registers
   __builtin_amdgcn_sched_barrier(0);
+  return nxt;
 }
 
 template <int W, int M, bool REAL, class V, int S, int... I>
 __device__ __forceinline__ void apply_shape(V* v, const RotLane<ER<V>>& rl, std::integer_sequence<int, I...>) {
-  (shape_rot<W, M, REAL, V, S, I>(v, rl), ...);
+  using R = ER<V>;
+  RotQ<REAL, R> q = rot_params<REAL, R>(rl.g, 0);
+  ((q = shape_rot<W, M, REAL, V, S, I>(v, rl.g, q)), ...);
 }
 
 // Loads a small struct of uniform, read-only data (descriptor tables written
@@ -418,8 +454,14 @@ __device__ __forceinline__ ChunkAhead fetch_first_chunk(const SegWinDev& wt, int
 // load can be issued a stage ahead of its use.
 template <class R>
 __device__ __forceinline__ RotLane<R> fetch_rot_lane(const RotDev* rots, int nrot, int lane) {
-  const RotDev g = rots[min(lane, nrot - 1)];
-  return RotLane<R>{g.p, (R)g.c, (R)g.sr, (R)g.si};
+  (void)nrot;
+  (void)lane;
+  // the same address in every lane; taken through readfirstlane so that the
+  // compiler knows it and reads the parameters with scalar loads
+  const uint64_t a = (uint64_t)(uintptr_t)rots;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+  return RotLane<R>{(const RotDev*)(uintptr_t)(((uint64_t)hi << 32) | lo)};
 }
 
 template <int W, bool REAL, class V, int S>

@@ -10,12 +10,17 @@ namespace ffx {
 namespace dev {
 
 // One Givens rotation as read by the kernels: local orbital p (relative to the
-// window start), cosine c and complex sine (sr, si).
+// window start), cosine c and complex sine (sr, si); fc, fsr, fsi are the same
+// values rounded to FP32 (for complex64 states).  Built by make_rot.
 struct RotDev {
   int p;
   int pad;
   double c, sr, si;
+  float fc, fsr, fsi, fpad;
 };
+inline RotDev make_rot(int p, double c, double sr, double si) {
+  return RotDev{p, 0, c, sr, si, (float)c, (float)sr, (float)si, 0.0f};
+}
 
 // Window class table on the device (see WindowTable in host.h).
 struct WinDev {

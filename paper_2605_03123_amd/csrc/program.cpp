@@ -353,7 +353,7 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
           flush_seg(false);
           const Givens& g = d.rots[step.idx[0]];
           cur.cross = true;
-          cur.cross_rot = dev::RotDev{0, 0, g.c, g.s.real(), g.s.imag()};
+          cur.cross_rot = dev::make_rot(0, g.c, g.s.real(), g.s.imag());
           cur.valu_slots += slots;
           cur.rot_sides += 1.0 / K;
           continue;
@@ -361,7 +361,7 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
         std::vector<dev::RotDev> buf;
         for (int i : step.idx) {
           const Givens& g = d.rots[i];
-          buf.push_back(dev::RotDev{g.p - step.a, 0, g.c, g.s.real(), g.s.imag()});
+          buf.push_back(dev::make_rot(g.p - step.a, g.c, g.s.real(), g.s.imag()));
         }
         if (step.kind == 0) {
           dev::StageDev st{};

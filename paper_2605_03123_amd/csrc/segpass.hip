@@ -203,7 +203,7 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
   const int nthr = blockDim.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wave: loops over chunks stay scalar
   const int nwaves = nthr >> 6;
 
   // row r of this layout: contiguous, or column r of the other layout
@@ -232,7 +232,7 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
   // the vector-memory data of a Givens stage (its rotations, the wave's first
   // class codes) is requested one stage ahead, so that its latency overlaps the
   // stage before; descriptors come through the scalar cache
-  RotLane<R> rl_next{0, R(1), R(0), R(0)};
+  RotLane<R> rl_next{nullptr};
   ChunkAhead fc_next{1, -1};
   auto fetch = [&](int s) {
     const StageDev st = uniform_load(P.stages + s);
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
   const int nthr = blockDim.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wave: loops over chunks stay scalar
   const int nwaves = nthr >> 6;
   const int64_t stride = P.gather ? P.n_rows : 1;
   const zc128* src = P.gather ? (const zc128*)P.src + r : (const zc128*)P.src + r * P.row_len;

@@ -213,10 +213,14 @@ def time_df_step(ffx, torch, ham, vec_np, dtype, steps, warmup, norb=NORB, nelec
     return ms, t_wall, norm, fam, plan.state_bytes, stats
 
 
-def n18_timing(ffx, torch, synth, dtype):
+def n18_timing(ffx, torch, synth, dtype, steps=3, warmup=1):
     """One S_0 step at norb = 18, (9, 9), L = 18 (48620 x 48620, 37.8 GB complex128), dt = 0.1, from a
-    random normalized state drawn on the device (seeded torch generator); 3 timed steps after 1 warm-up, and
-    the per-kernel-family HBM rate (algorithmic bytes over kernel time) against the 8 TB/s peak."""
+    random normalized state drawn on the device (seeded torch generator); `steps` timed steps after `warmup`,
+    and per kernel family two HBM rates against the 8 TB/s peak: `alg_GBps` counts 2 S per rotation side
+    (one read and one write of the state per spin sweep of an orbital rotation, split over the passes by
+    their share of the rotations), `moved_GBps` one read and one write of the whole state per launch (a
+    segment pass visits every segment of every row; a window pass every class that holds some but not all
+    of the window's orbitals, all but about 1 % of the state here)."""
     norb, nelec, nt = 18, (9, 9), 18
     ham = synth.df_hamiltonian(synth.rng(5), norb, nt)
     d = synth.dim(norb, 9)
@@ -224,13 +228,16 @@ def n18_timing(ffx, torch, synth, dtype):
     g.manual_seed(5)
     vec = torch.randn((d, d), dtype=dtype, device="cuda:0", generator=g)
     vec /= torch.linalg.vector_norm(vec)
-    ms, _, norm, fam, sb, stats = time_df_step(ffx, torch, ham, None, dtype, 3, 1, norb, nelec, vec_dev=vec)
+    ms, _, norm, fam, sb, stats = time_df_step(ffx, torch, ham, None, dtype, steps, warmup, norb, nelec,
+                                               vec_dev=vec)
     del vec
     out = {"ms_per_step": ms, **stats, "state_bytes": sb, "final_norm": norm, "families": {}}
     for k, v in fam.items():
         gbs = v["alg_bytes"] / (v["total_ms"] * 1e-3) / 1e9
+        moved = v["launches"] * 2 * sb / (v["total_ms"] * 1e-3) / 1e9
         out["families"][k] = {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 3),
-                              "alg_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+                              "alg_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                              "moved_GBps": round(moved, 1), "moved_frac": round(moved / HBM_PEAK_GBS, 4)}
     ffx._plan_cached.cache_clear()
     torch.cuda.empty_cache()
     return out
@@ -665,6 +672,8 @@ def main():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--dense-only", action="store_true",
                     help="run only the dense-vs-Givens rotation leg (for profiling)")
+    ap.add_argument("--n18-only", action="store_true",
+                    help="run only the 18-orbital DF step in the --dtype precision (for profiling)")
     ap.add_argument("--no-config2", action="store_true")
     ap.add_argument("--no-fig2", action="store_true")
     ap.add_argument("--context-only", action="store_true",
@@ -690,6 +699,11 @@ def main():
         return
     if args.dense_only:
         print(json.dumps({"rotation_dense_vs_givens_c128": dense_vs_givens(ffx, torch, synth)}), flush=True)
+        return
+    if args.n18_only:
+        dt = torch.complex128 if args.dtype == "c128" else torch.complex64
+        print(json.dumps({"df_step_n18": {args.dtype: n18_timing(ffx, torch, synth, dt, args.steps, args.warmup)}}),
+              flush=True)
         return
     if args.context_only:
         print(json.dumps({"df_trotter_n14": config2_timing(ffx, torch, synth),

@@ -424,8 +424,15 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
       // k-1) of its C(wt, k)) with the first C(wt-1, k-1) strings of segment
       // H + {wt}, which lack wt - 1; both ranges run in the colex order of the
       // remaining k - 1 low orbitals.  Packed segments leave that rotation to
-      // the window passes.
-      if (wt >= 1 && wt < norb && segs.size() > 1 && !packed) {
+      // the window passes.  Applying it at load pays when (wt - 1, wt) is the
+      // only pair that crosses the segment window (wt = norb - 1): then no
+      // window pass runs at all.  With more orbitals above the window, window
+      // passes run anyway and take that pair's rotations with the others,
+      // while each rotation applied at load would start one more segment pass
+      // (at 18 orbitals: 96 segment passes per DF step instead of 58).
+      // FFX_CROSS_AT_LOAD=1 applies it at load in every case (tests).
+      const bool cross_at_load = wt == norb - 1 || std::getenv("FFX_CROSS_AT_LOAD") != nullptr;
+      if (wt >= 1 && wt < norb && segs.size() > 1 && !packed && cross_at_load) {
         const auto cr = crossing_ranges(strs, segs, wt, s == 0 ? na : nb);
         for (size_t g = 0; g < segs.size(); ++g) {
           if (!cr[g].has) continue;

@@ -281,18 +281,24 @@ def small_segment_plans(ffx):
     """Plans whose segments are forced to be tiny, so that rotations cross segments
     and run through whole-spin window passes between segment passes: one
     segment per run of configurations sharing the orbitals above the window
-    (FFX_SEG_PACK=0; the rotation on the pair straddling the window is applied
-    at load), and runs packed back to back (that rotation takes a window pass)."""
+    (FFX_SEG_PACK=0), with the rotation on the pair straddling the window
+    applied at load (FFX_CROSS_AT_LOAD=1) or, as by default when several pairs
+    cross, left to the window passes; and runs packed back to back (that
+    rotation takes a window pass)."""
     import os
     plans = {}
-    old = {k: os.environ.get(k) for k in ("FFX_SEG_MAX", "FFX_SEG_PACK")}
+    old = {k: os.environ.get(k) for k in ("FFX_SEG_MAX", "FFX_SEG_PACK", "FFX_CROSS_AT_LOAD")}
     os.environ["FFX_SEG_MAX"] = "24"
     try:
-        for pack in ("0", "1"):
+        for pack, at_load in (("0", "1"), ("0", None), ("1", None)):
             os.environ["FFX_SEG_PACK"] = pack
+            if at_load:
+                os.environ["FFX_CROSS_AT_LOAD"] = at_load
+            else:
+                os.environ.pop("FFX_CROSS_AT_LOAD", None)
             for norb, nelec, dt in [(8, (4, 4), torch.complex128), (10, (3, 6), torch.complex128),
                                     (9, (4, 5), torch.complex64), (11, (5, 4), torch.complex128)]:
-                plans[(norb, nelec, dt, pack)] = ffx.Plan(norb, nelec, dt)
+                plans[(norb, nelec, dt, pack, at_load)] = ffx.Plan(norb, nelec, dt)
     finally:
         for k, v in old.items():
             if v is None:
@@ -303,7 +309,7 @@ def small_segment_plans(ffx):
 
 
 def test_segmented_paths(ffx, small_segment_plans):
-    for (norb, nelec, dtype, _), plan in small_segment_plans.items():
+    for (norb, nelec, dtype, _, _), plan in small_segment_plans.items():
         r = synth.rng([21, norb])
         da, db = _dims(norb, nelec)
         vec = _to_dev(synth.random_state(r, da, db), dtype)
@@ -328,7 +334,7 @@ def test_segmented_paths_in_place_and_gradients(ffx, small_segment_plans):
     # crossing rotations move the state between the working buffers; in-place
     # calls must still end in the caller's buffer, and the adjoint gradient runs
     # programs that end in accumulation or in a reduction only
-    for (norb, nelec, dtype, _), plan in small_segment_plans.items():
+    for (norb, nelec, dtype, _, _), plan in small_segment_plans.items():
         r = synth.rng([22, norb])
         da, db = _dims(norb, nelec)
         vec = _to_dev(synth.random_state(r, da, db), dtype)

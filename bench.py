@@ -361,6 +361,7 @@ def batched_timing(ffx, torch, synth, dtype):
     w = synth.workload_batched(256, seed=0, n_reps=2)
     b = ffx.Batch([(x.norb, x.nelec) for x in w], dtype=dtype)
     args = ([x.data["params"] for x in w], [x.data["ham"] for x in w], 2)
+    tuned = b.tune(*args)  # task size and stage depth for this batch (a few seconds)
     b.lucj_energy_grad(*args)
     torch.cuda.synchronize()
     runs = []
@@ -368,19 +369,20 @@ def batched_timing(ffx, torch, synth, dtype):
         b.lucj_energy_grad(*args)
         runs.append(b.timing())
     best = min(runs, key=lambda r: r["device_ms"])
-    # the same batch with one launch per pass level, for comparison
-    b.single_launch(False)
+    # the same batch as one cooperative launch, for comparison
+    b.single_launch(True)
     b.lucj_energy_grad(*args)
     torch.cuda.synchronize()
     runs1 = []
     for _ in range(3):
         b.lucj_energy_grad(*args)
         runs1.append(b.timing())
-    b.single_launch(True)
+    b.single_launch(False)
     best1 = min(runs1, key=lambda r: r["device_ms"])
     return {"device_ms": best["device_ms"], "call_ms": best["call_ms"], "launches": best["launches"],
-            "per_level_launches": {"device_ms": best1["device_ms"], "call_ms": best1["call_ms"],
-                                   "launches": best1["launches"]},
+            "tuned": {"target_elems": tuned[0], "stage_rots": tuned[1]},
+            "single_cooperative_launch": {"device_ms": best1["device_ms"], "call_ms": best1["call_ms"],
+                                          "launches": best1["launches"]},
             "config": b.info(), "amplitudes": int(sum(synth.dim(x.norb, x.nelec[0]) * synth.dim(x.norb, x.nelec[1])
                                                       for x in w))}
 
@@ -759,7 +761,7 @@ def main():
     if not args.no_batched:
         out["batched_lucj_energy_grad"] = {
             "workload": "256 sectors, norb in {8,10,12}, n in {norb/2-1, norb/2}, LUCJ n_reps=2, DF L=norb "
-                        "(energies + adjoint gradients; one cooperative launch, per-level launches beside it)",
+                        "(energies + adjoint gradients; one launch per pass kind of each level after tuning, the single cooperative launch beside it)",
             "c64": batched_timing(ffx, torch, synth, torch.complex64),
             "c128": batched_timing(ffx, torch, synth, torch.complex128),
         }

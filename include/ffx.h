@@ -379,12 +379,13 @@ int64_t ffx_batch_workspace_bytes(ffx_batch batch);
    gradients back to back (ffx_lucj_n_params(norb_i, n_reps_i) each, in
    instance order).  Runs every instance's forward pass, costate, energy and
    reverse sweep on `stream`, then synchronizes: the passes of all instances
-   are grouped by level (pass k of every instance), and the whole batch is ONE
-   cooperative launch whose blocks take each level's tasks (blocks of rows or
-   columns of one instance's state) with a grid barrier between levels; with
-   ffx_batch_single_launch(batch, 0), one kernel launch per level instead.  A
-   persistent launch over a task queue with per-instance dependency counters
-   is built but switched off (ffx_batch_persistent). */
+   are grouped by level (pass k of every instance), and each level runs as one
+   kernel launch per pass kind, one block per task (a block of rows or columns
+   of one instance's state); with ffx_batch_single_launch(batch, 1), the whole
+   batch is ONE cooperative launch whose blocks take each level's tasks with a
+   grid barrier between levels.  A persistent launch over a task queue with
+   per-instance dependency counters is built but switched off
+   (ffx_batch_persistent). */
 int ffx_batch_lucj_energy_grad(ffx_batch batch, const ffx_lucj* ops, const ffx_df_ham* hams,
                                double* energies, double* grads, void* workspace, void* stream);
 
@@ -396,14 +397,15 @@ int ffx_batch_lucj_energy_grad(ffx_batch batch, const ffx_lucj* ops, const ffx_d
 int ffx_batch_tune(ffx_batch batch, const ffx_lucj* ops, const ffx_df_ham* hams, void* workspace,
                    void* stream, int* target_elems, int* stage_rots);
 
-/* enable != 0 (the default): calls run the whole batch as ONE cooperative
-   launch (hipLaunchCooperativeKernel) whose blocks walk the pass levels in
-   order, taking each level's tasks from a counter, with a grid barrier
-   between levels; its results equal those of the per-level launches (the
-   same tasks in the same arithmetic order).  The grid is the number of
-   blocks that fit the device at once (none fitting: per-level launches);
-   FFX_EDEVICE if the cooperative launch is refused.  enable = 0: one launch
-   per level. */
+/* enable != 0: calls run the whole batch as ONE cooperative launch
+   (hipLaunchCooperativeKernel) whose blocks walk the pass levels in order,
+   taking each level's tasks from a counter, with a grid barrier between
+   levels; its results equal those of the per-level launches (the same tasks
+   in the same arithmetic order).  The grid is the number of blocks that fit
+   the device at once (none fitting: per-level launches); FFX_EDEVICE if the
+   cooperative launch is refused.  enable = 0 (the default): one launch per
+   pass kind of each level, each with only its kind's code and LDS, so more
+   blocks share a compute unit. */
 int ffx_batch_single_launch(ffx_batch batch, int enable);
 
 /* Timing of the last ffx_batch_lucj_energy_grad: device time from the first to

@@ -45,9 +45,10 @@ struct ffx_batch_s {
   // run on the GPU did not complete and the cause is not established.
   bool persistent = false;
   // One cooperative launch that walks the pass levels with a grid barrier
-  // between them (the default; ffx_batch_single_launch(batch, 0) switches to
-  // one launch per level).
-  bool single_launch = true;
+  // between them (ffx_batch_single_launch(batch, 1)); by default one launch per
+  // pass kind of each level, each with its kind's own registers and LDS (about
+  // a quarter faster on the 256-sector workload).
+  bool single_launch = false;
   // timing of the last call
   double last_device_ms = 0, last_call_ms = 0;
   int last_launches = 0;
@@ -565,9 +566,14 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
   int64_t first = 0;
   for (size_t lv = 0; lv < max_levels; ++lv) {
     level_start.push_back((int)all.size());
-    for (int i : order) {
-      if (lv >= ip[i].p.size()) continue;
-      dev::BPassDev p = ip[i].p[lv];
+    // the passes of a level do not depend on each other: grouped by kind (for
+    // the one-launch-per-kind form), instances in size order within a kind
+    std::vector<dev::BPassDev> lvl;
+    for (int i : order)
+      if (lv < ip[i].p.size()) lvl.push_back(ip[i].p[lv]);
+    std::stable_sort(lvl.begin(), lvl.end(),
+                     [](const dev::BPassDev& a, const dev::BPassDev& c) { return a.kind < c.kind; });
+    for (dev::BPassDev p : lvl) {
       p.first = first;
       first += p.n_tasks;
       all.push_back(p);
@@ -633,12 +639,18 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
     launches = 1;
   } else {
     for (size_t lv = 0; lv + 1 < level_start.size(); ++lv) {
-      const int p0 = level_start[lv], p1 = level_start[lv + 1];
-      if (p0 == p1) continue;
-      const int64_t tasks = (p1 < (int)all.size() ? all[p1].first : first) - all[p0].first;
-      dev::batch_launch_level(b.c64, bd, p0, p1, tasks, b.lds, s);
-      check_launch();
-      ++launches;
+      for (int p0 = level_start[lv]; p0 < level_start[lv + 1];) {
+        int p1 = p0 + 1;
+        while (p1 < level_start[lv + 1] && all[p1].kind == all[p0].kind) ++p1;
+        const int64_t tasks = (p1 < (int)all.size() ? all[p1].first : first) - all[p0].first;
+        if (tasks > 0) {
+          dev::batch_launch_kind(b.c64, all[p0].kind, bd, p0, p1, tasks,
+                                 dev::batch_lds_for(all[p0].kind, b.lds_row_bytes, b.max_mt), s);
+          check_launch();
+          ++launches;
+        }
+        p0 = p1;
+      }
     }
   }
   HIPCHK(hipEventRecord(b.ev[1], s));

@@ -7,8 +7,10 @@
 // job (tables, fixed-order sums).  Pass k of every instance forms level k; the
 // passes of one level never depend on each other.
 //
-// k_batch_level runs one level per launch, one block per task: this is the
-// form in use.  k_batch is the single persistent launch over the same queue:
+// k_batch_coop runs the whole batch as one cooperative launch with a grid
+// barrier between levels; k_batch_kind runs one level's tasks of one kind per
+// launch, one block per task.  k_batch is the single persistent launch over
+// the same queue:
 // blocks take tasks with an atomic counter and wait, before each task, until
 // every task of the same instance's earlier passes has finished
 // (per-instance counters, relaxed polling with sleeps, one agent-scope
@@ -34,6 +36,8 @@ namespace dev {
 
 constexpr int kBatchThreads = 256;
 typedef double bdouble4 __attribute__((ext_vector_type(4)));
+typedef double bdouble2 __attribute__((ext_vector_type(2)));
+typedef float bfloat2 __attribute__((ext_vector_type(2)));
 constexpr int kBatchMaxRows = 64;   // rows per task
 constexpr int kBatchMaxOrb = 16;    // orbitals of a batched sector
 // bounded wait, in ticks of the 100 MHz real-time counter (2 s)
@@ -50,23 +54,44 @@ struct BatchLds {
   double* red;     // 16 doubles
 };
 
-__device__ __forceinline__ BatchLds batch_lds_map(char* smem, const BatchDev& B) {
-  BatchLds L;
+// LDS of a block: the rows, then red (16 doubles), then either the segment
+// tables (mt, wq, rowf: segment tasks) or acc (the other kinds).  A launch
+// that runs one kind allocates only that kind's part; the all-kinds kernels
+// lay both out, the tables first (kind = -1).
+constexpr int kRedDoubles = 16;
+constexpr int kAccDoubles = 4 * 2 * kBatchMaxOrb * kBatchMaxOrb;
+constexpr int kSegTabDoubles = kBatchMaxRows * kBatchMaxOrb + 2 * kBatchMaxRows;
+
+__host__ __device__ inline size_t batch_lds_kind(int kind, int lds_row_bytes, int max_mt) {
+  const size_t tabs = (size_t)((max_mt + 3) & ~3) * 4 + (size_t)kSegTabDoubles * 8;
+  const size_t head = (size_t)lds_row_bytes + (size_t)kRedDoubles * 8;
+  if (kind == BK_SEG) return head + tabs;
+  if (kind >= 0) return head + (size_t)kAccDoubles * 8;
+  return head + tabs + (size_t)kAccDoubles * 8;
+}
+
+__device__ __forceinline__ BatchLds batch_lds_map(char* smem, const BatchDev& B, int kind = -1) {
+  BatchLds L{};
   L.rows = smem;
-  L.mt = (int*)(smem + B.lds_row_bytes);
-  L.wq = (double*)(L.mt + ((B.max_mt + 3) & ~3));
-  L.rowf = L.wq + kBatchMaxRows * kBatchMaxOrb;
-  L.acc = L.rowf + 2 * kBatchMaxRows;
-  L.red = L.acc + 4 * 2 * kBatchMaxOrb * kBatchMaxOrb;
+  L.red = (double*)(smem + B.lds_row_bytes);
+  char* p = (char*)(L.red + kRedDoubles);
+  if (kind == BK_SEG || kind < 0) {
+    L.mt = (int*)p;
+    L.wq = (double*)(L.mt + ((B.max_mt + 3) & ~3));
+    L.rowf = L.wq + kBatchMaxRows * kBatchMaxOrb;
+    p = (char*)(L.rowf + 2 * kBatchMaxRows);
+  }
+  if (kind != BK_SEG) L.acc = (double*)p;
   return L;
 }
 
 size_t batch_lds(bool c64, int lds_row_bytes, int max_mt, int norb_max) {
   (void)c64;
   (void)norb_max;
-  return (size_t)lds_row_bytes + (size_t)((max_mt + 3) & ~3) * 4 +
-         (size_t)(kBatchMaxRows * kBatchMaxOrb + 2 * kBatchMaxRows + 8 * kBatchMaxOrb * kBatchMaxOrb + 16) * 8;
+  return batch_lds_kind(-1, lds_row_bytes, max_mt);
 }
+
+size_t batch_lds_for(int kind, int lds_row_bytes, int max_mt) { return batch_lds_kind(kind, lds_row_bytes, max_mt); }
 
 // fixed-order block sum (4 waves); every thread gets the result
 __device__ __forceinline__ double batch_block_sum(double v, double* red) {
@@ -187,9 +212,21 @@ __device__ __forceinline__ void inner_task(const BPassDev& ps, const BTypeDev& t
 }
 
 __device__ __forceinline__ void sum_task(const BPassDev& ps) {
+  // partials are requested 16 at a time and added in index order, so the sum
+  // is the same as one term at a time but waits on one memory latency per 16
+  constexpr int U = 16;
   for (int w = threadIdx.x; w < ps.width; w += blockDim.x) {
+    const double* p = ps.partials + w;
     double t = 0;
-    for (int k = 0; k < ps.n_sum; ++k) t += ps.partials[(int64_t)k * ps.width + w];
+    int k = 0;
+    for (; k + U <= ps.n_sum; k += U) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = p[(int64_t)(k + u) * ps.width];
+#pragma unroll
+      for (int u = 0; u < U; ++u) t += v[u];
+    }
+    for (; k < ps.n_sum; ++k) t += p[(int64_t)k * ps.width];
     ps.out[w] = t;
   }
 }
@@ -219,16 +256,39 @@ __device__ __forceinline__ void rdm_task_cs(const BPassDev& ps, const BTypeDev& 
   V* bp = bl + (int64_t)RR * len;
   const V* lam = (const V*)ps.src;
   const V* psi = (const V*)ps.src2;
+  // staging: two elements of each state requested per thread before either is
+  // stored (kept in named values: through arrays, the stores to LDS, which go
+  // through a generic pointer, would keep the values in scratch memory); a task
+  // holds at most 64 rows of at most 924 amplitudes, so indexes fit 32 bits
+  const int ne = (int)nel;
+  // the elements are copied as native two-component vectors (the same bytes)
+  using T = typename std::conditional<sizeof(V) == 16, bdouble2, bfloat2>::type;
+  T* tl = (T*)bl;
+  T* tp = (T*)bp;
   if (ps.layout == 0) {
-    for (int64_t x = tid; x < nel; x += nthr) {
-      bl[x] = lam[r0 * len + x];
-      bp[x] = psi[r0 * len + x];
+    const T* ls = (const T*)lam + r0 * len;
+    const T* qs = (const T*)psi + r0 * len;
+    for (int x0 = tid; x0 < ne; x0 += 2 * nthr) {
+      const int x1 = min(x0 + nthr, ne - 1);
+      const T a0 = ls[x0], b0 = qs[x0], a1 = ls[x1], b1 = qs[x1];
+      tl[x0] = a0;
+      tp[x0] = b0;
+      tl[x1] = a1;
+      tp[x1] = b1;
     }
   } else {
-    for (int64_t x = tid; x < nel; x += nthr) {
-      const int64_t k = x / nr, r = x - k * nr;
-      bl[r * len + k] = lam[k * ncols_state + r0 + r];
-      bp[r * len + k] = psi[k * ncols_state + r0 + r];
+    const unsigned unr = (unsigned)nr, ulen = (unsigned)len;
+    for (int x0 = tid; x0 < ne; x0 += 2 * nthr) {
+      const unsigned y0 = (unsigned)x0, y1 = (unsigned)min(x0 + nthr, ne - 1);
+      const unsigned k0 = y0 / unr, q0 = y0 - k0 * unr, k1 = y1 / unr, q1 = y1 - k1 * unr;
+      const int64_t s0 = (int64_t)k0 * ncols_state + r0 + q0, s1 = (int64_t)k1 * ncols_state + r0 + q1;
+      const T* tlam = (const T*)lam;
+      const T* tpsi = (const T*)psi;
+      const T a0 = tlam[s0], b0 = tpsi[s0], a1 = tlam[s1], b1 = tpsi[s1];
+      tl[q0 * ulen + k0] = a0;
+      tp[q0 * ulen + k0] = b0;
+      tl[q1 * ulen + k1] = a1;
+      tp[q1 * ulen + k1] = b1;
     }
   }
   __syncthreads();
@@ -640,15 +700,18 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchDev B) {
   }
 }
 
-// Level-synchronous form: one launch runs every task of one pass level
-// (passes [p0, p1) of the queue, which never depend on each other); block b
-// runs task first(p0) + b.  Ordering between levels comes from the launches.
-template <int W, class R>
-__global__ __launch_bounds__(kBatchThreads) void k_batch_level(BatchDev B, int p0, int p1) {
+// Level-synchronous form: one launch runs the passes [p0, p1) of one level
+// that all have kind KIND (the host groups a level's passes by kind), one block
+// per task; ordering between levels comes from the launches.  Each launch
+// carries only its kind's code, so its register count, and with it the number
+// of blocks a compute unit holds, is that kind's own rather than the largest of
+// all (segment tasks: 126 registers for complex64 instead of 196).
+template <int W, class R, int KIND>
+__global__ __launch_bounds__(kBatchThreads) void k_batch_kind(BatchDev B, int p0, int p1) {
   extern __shared__ __align__(16) char smem[];
-  const BatchLds L = batch_lds_map(smem, B);
+  const BatchLds L = batch_lds_map(smem, B, KIND);
   const int64_t t = B.passes[p0].first + (int64_t)blockIdx.x;
-  int lo = p0, hi = p1 - 1;  // last pass of the level whose first task <= t
+  int lo = p0, hi = p1 - 1;  // last pass of the group whose first task <= t
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (B.passes[mid].first <= t)
@@ -660,21 +723,18 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_level(BatchDev B, int p
   const BTypeDev ty = uniform_load(B.types + ps.type);
   const int task = (int)(t - ps.first);
   if (task < 0 || task >= ps.n_tasks) return;
-  switch (ps.kind) {
-    case BK_TABLES: tables_task(ps, ty, task); break;
-    case BK_OUTER: outer_task<R>(ps, ty, task); break;
-    case BK_SEG:
-      if (ps.real)
-        seg_task<W, true, R>(B, ps, ty, task, L);
-      else
-        seg_task<W, false, R>(B, ps, ty, task, L);
-      break;
-    case BK_INNER: inner_task<R>(ps, ty, task, L.red); break;
-    case BK_RDM: rdm_task<R>(ps, ty, task, L); break;
-    case BK_DGRAD: dgrad_task<R>(ps, ty, task, L.acc); break;
-    case BK_SUM: sum_task(ps); break;
-    default: break;
+  if constexpr (KIND == BK_TABLES) tables_task(ps, ty, task);
+  if constexpr (KIND == BK_OUTER) outer_task<R>(ps, ty, task);
+  if constexpr (KIND == BK_SEG) {
+    if (ps.real)
+      seg_task<W, true, R>(B, ps, ty, task, L);
+    else
+      seg_task<W, false, R>(B, ps, ty, task, L);
   }
+  if constexpr (KIND == BK_INNER) inner_task<R>(ps, ty, task, L.red);
+  if constexpr (KIND == BK_RDM) rdm_task<R>(ps, ty, task, L);
+  if constexpr (KIND == BK_DGRAD) dgrad_task<R>(ps, ty, task, L.acc);
+  if constexpr (KIND == BK_SUM) sum_task(ps);
 }
 
 // Single cooperative launch: every block walks the levels in order, taking
@@ -774,9 +834,9 @@ hipError_t batch_launch_coop(bool c64, const BatchDev& b, const int* level_start
              : launch_coop<6, double>(b, level_start, n_levels, level_ctr, blocks, lds, s);
 }
 
-template <int W, class R>
-static void launch_level(const BatchDev& b, int p0, int p1, int64_t tasks, size_t lds, hipStream_t s) {
-  auto k = k_batch_level<W, R>;
+template <int W, class R, int KIND>
+static void launch_kind(const BatchDev& b, int p0, int p1, int64_t tasks, size_t lds, hipStream_t s) {
+  auto k = k_batch_kind<W, R, KIND>;
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, kBatchMaxDynLds);
@@ -786,12 +846,28 @@ static void launch_level(const BatchDev& b, int p0, int p1, int64_t tasks, size_
   hipLaunchKernelGGL(k, dim3((unsigned)tasks), dim3(kBatchThreads), lds, s, b, p0, p1);
 }
 
-void batch_launch_level(bool c64, const BatchDev& b, int p0, int p1, int64_t tasks, size_t lds, hipStream_t s) {
-  if (c64)
-    launch_level<6, float>(b, p0, p1, tasks, lds, s);
-  else
-    launch_level<6, double>(b, p0, p1, tasks, lds, s);
+template <class R>
+static void launch_kind_r(int kind, const BatchDev& b, int p0, int p1, int64_t tasks, size_t lds, hipStream_t s) {
+  switch (kind) {
+    case BK_TABLES: launch_kind<6, R, BK_TABLES>(b, p0, p1, tasks, lds, s); break;
+    case BK_OUTER: launch_kind<6, R, BK_OUTER>(b, p0, p1, tasks, lds, s); break;
+    case BK_SEG: launch_kind<6, R, BK_SEG>(b, p0, p1, tasks, lds, s); break;
+    case BK_INNER: launch_kind<6, R, BK_INNER>(b, p0, p1, tasks, lds, s); break;
+    case BK_RDM: launch_kind<6, R, BK_RDM>(b, p0, p1, tasks, lds, s); break;
+    case BK_DGRAD: launch_kind<6, R, BK_DGRAD>(b, p0, p1, tasks, lds, s); break;
+    case BK_SUM: launch_kind<6, R, BK_SUM>(b, p0, p1, tasks, lds, s); break;
+    default: break;
+  }
 }
+
+void batch_launch_kind(bool c64, int kind, const BatchDev& b, int p0, int p1, int64_t tasks, size_t lds,
+                       hipStream_t s) {
+  if (c64)
+    launch_kind_r<float>(kind, b, p0, p1, tasks, lds, s);
+  else
+    launch_kind_r<double>(kind, b, p0, p1, tasks, lds, s);
+}
+
 
 template <int W, class R>
 static void launch_batch(const BatchDev& b, int blocks, int threads, size_t lds, hipStream_t s) {

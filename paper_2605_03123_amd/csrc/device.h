@@ -411,10 +411,14 @@ struct BatchDev {
 
 // LDS bytes of the batched kernel and its launch.  blocks: resident blocks to start.
 size_t batch_lds(bool c64, int lds_row_bytes, int max_mt, int norb_max);
+// LDS bytes of a launch that runs tasks of one kind only
+size_t batch_lds_for(int kind, int lds_row_bytes, int max_mt);
 int batch_blocks_per_cu(bool c64, int threads, size_t lds);
 void batch_launch(bool c64, const BatchDev& b, int blocks, int threads, size_t lds, hipStream_t s);
 // level-synchronous form: the tasks of passes [p0, p1) (one level), one block each
-void batch_launch_level(bool c64, const BatchDev& b, int p0, int p1, int64_t tasks, size_t lds, hipStream_t s);
+// passes [p0, p1) of one level, all of kind `kind`, one block per task
+void batch_launch_kind(bool c64, int kind, const BatchDev& b, int p0, int p1, int64_t tasks, size_t lds,
+                       hipStream_t s);
 
 // single cooperative launch over all levels (grid barrier between levels); blocks must not exceed
 // batch_coop_blocks_per_cu(...) times the compute units (the launch fails otherwise)

@@ -775,8 +775,8 @@ class Batch:
         return {"device_ms": d.value, "call_ms": c.value, "launches": n.value}
 
     def single_launch(self, enable: bool = True):
-        """Run later calls as one cooperative launch over all pass levels (the default), or with
-        enable=False as one launch per level."""
+        """Run later calls as one cooperative launch over all pass levels, or with enable=False as one
+        launch per pass kind of each level (the default)."""
         _check(_batch_single(self._h, int(bool(enable))))
 
     def persistent(self, enable: bool = True):

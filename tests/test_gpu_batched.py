@@ -1,4 +1,5 @@
-"""Batched LUCJ energy + adjoint gradient: many sectors in one persistent launch.
+"""Batched LUCJ energy + adjoint gradient: many sectors run together, one launch per pass kind of each level
+(the default) or one cooperative launch.
 
 Parity: every instance against the oracle's energy and adjoint gradient
 (1e-12 (complex128) / 1e-5 (complex64) on energies relative to max(1, |E|) and
@@ -109,7 +110,7 @@ def _golden():
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden file not generated")
 def test_batched_config4(ffx):
-    # 256 instances, norb in {8, 10, 12}: one persistent launch per precision
+    # 256 instances, norb in {8, 10, 12}, in both precisions
     w = synth.workload_batched(256, seed=0, n_reps=2)
     sectors = [(x.norb, x.nelec) for x in w]
     args = ([x.data["params"] for x in w], [x.data["ham"] for x in w], 2)
@@ -131,7 +132,7 @@ def test_batched_config4(ffx):
 
 def test_batched_single_cooperative_launch(ffx):
     """The whole batch as one cooperative launch (grid barrier between pass levels): energies and gradients
-    identical to the per-level launches, in both precisions, over two calls in a row."""
+    identical to the launches per pass kind of each level, in both precisions, over two calls in a row."""
     w = synth.workload_batched(64, seed=3, n_reps=2)
     sectors = [(x.norb, x.nelec) for x in w]
     args = ([x.data["params"] for x in w], [x.data["ham"] for x in w], 2)

@@ -304,11 +304,12 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
       if (v >= 1 && v < max_elems) max_elems = v;
     }
     // lanes per LDS access cycle for the class loads: 128 bytes per cycle
-    int lds_group = 128 / (int)P->elem();
+    int lds_group_bytes = 128;
     if (const char* e = std::getenv("FFX_LDS_GROUP_BYTES")) {  // tuning knob (0: address order)
       const int v = std::atoi(e);
-      if (v >= 0 && v <= 1024) lds_group = v / (int)P->elem();
+      if (v >= 0 && v <= 1024) lds_group_bytes = v;
     }
+    const int lds_group = lds_group_bytes / (int)P->elem();
     // pack runs of configurations that share their orbitals above the segment
     // window back to back into one segment while they fit (0: one run per
     // segment; for tests)
@@ -459,7 +460,7 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
         std::vector<SegWindowTable> ptabs;
         size_t mt = 0;
         for (int a = 0; Wp >= 2 && a + Wp <= norb; ++a) {
-          ptabs.push_back(build_seg_window(strs, norb, a, Wp, 128 / 8));
+          ptabs.push_back(build_seg_window(strs, norb, a, Wp, lds_group_bytes / 8));
           mt = ((mt + 3) & ~(size_t)3) + ptabs.back().mt.size();
         }
         // the row area holds 8-byte parts: sized as a complex64 row

@@ -442,31 +442,35 @@ __device__ __forceinline__ void seg_task(const BatchDev& B, const BPassDev& ps, 
   const V* s = (const V*)src;
 
   // gather: element (r, k) of the layout lands at buf[r * len + k]; every
-  // thread requests kU elements before it stores any
+  // thread requests kU elements before it stores any.  A task holds at most
+  // 64 rows of at most 924 amplitudes, so element indexes and their quotients
+  // by the row count are taken in 32-bit unsigned arithmetic.
   constexpr int kU = 8;
-  for (int64_t x0 = tid; x0 < nel; x0 += kU * nthr) {
+  const int ne = (int)nel;
+  const unsigned unr = (unsigned)nr, ulen = (unsigned)len;
+  for (int x0 = tid; x0 < ne; x0 += kU * nthr) {
     V t[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const int64_t x = min(x0 + (int64_t)u * nthr, nel - 1);
+      const unsigned x = (unsigned)min(x0 + u * nthr, ne - 1);
       if (ps.layout == 0) {
         t[u] = s[r0 * len + x];
       } else {
-        const int64_t k = x / nr, r = x - k * nr;
-        t[u] = s[k * ncols_state + r0 + r];
+        const unsigned k = x / unr, r = x - k * unr;
+        t[u] = s[(int64_t)k * ncols_state + r0 + r];
       }
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u) keep(t[u]);
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const int64_t x = x0 + (int64_t)u * nthr;
-      if (x < nel) {
+      const int x = x0 + u * nthr;
+      if (x < ne) {
         if (ps.layout == 0) {
           buf[x] = t[u];
         } else {
-          const int64_t k = x / nr, r = x - k * nr;
-          buf[r * len + k] = t[u];
+          const unsigned k = (unsigned)x / unr, r = (unsigned)x - k * unr;
+          buf[r * ulen + k] = t[u];
         }
       }
     }
@@ -549,9 +553,8 @@ __device__ __forceinline__ void seg_task(const BatchDev& B, const BPassDev& ps, 
       }
       __syncthreads();
       const bool cross = st.C != nullptr;
-      for (int64_t x = tid; x < nel; x += nthr) {
-        const int r = (int)(x / len);
-        const int64_t k = x - (int64_t)r * len;
+      for (int x = tid; x < ne; x += nthr) {
+        const unsigned r = (unsigned)x / ulen, k = (unsigned)x - r * ulen;
         double cr = 0.0;
         if (cross)
           for (uint32_t b = cmask[k]; b; b &= b - 1) cr += L.wq[r * kBatchMaxOrb + __builtin_ctz(b)];
@@ -590,7 +593,7 @@ __device__ __forceinline__ void seg_task(const BatchDev& B, const BPassDev& ps, 
     V* d = (V*)dst;
     const bool add = ps.mode == SEG_ACCUM;
     if (ps.layout == 0) {
-      for (int64_t x = tid; x < nel; x += nthr) {
+      for (int x = tid; x < ne; x += nthr) {
         V v = buf[x];
         if (add) {
           const V a = d[r0 * len + x];
@@ -600,10 +603,10 @@ __device__ __forceinline__ void seg_task(const BatchDev& B, const BPassDev& ps, 
         d[r0 * len + x] = v;
       }
     } else {
-      for (int64_t x = tid; x < nel; x += nthr) {
-        const int64_t k = x / nr, r = x - k * nr;
-        const int64_t gi = k * ncols_state + r0 + r;
-        V v = buf[r * len + k];
+      for (int x = tid; x < ne; x += nthr) {
+        const unsigned k = (unsigned)x / unr, r = (unsigned)x - k * unr;
+        const int64_t gi = (int64_t)k * ncols_state + r0 + r;
+        V v = buf[r * ulen + k];
         if (add) {
           const V a = d[gi];
           v.x += a.x;

@@ -138,43 +138,70 @@ __device__ __forceinline__ V cmul(V a, V b) {
   return r;
 }
 
-// d <- a * d + b, written into d's own register: with the result tied to
-// the input, the member registers never move across the rotation loop.  a is
-// a rotation's cosine, the same in every lane: it is read from scalar
-// registers (one scalar operand per instruction, within the constant-bus
-// limit), so it needs no copy into vector registers.
+// d <- a * d + b and d <- a * b + d, written into d's own register: with the
+// result tied to the input, the member registers never move across the
+// rotation loop.  a is a rotation parameter, the same in every lane: it is
+// read from scalar registers (one scalar operand per instruction, within the
+// constant-bus limit), so it needs no copy into vector registers.
 __device__ __forceinline__ void fma_ip(float& d, float a, float b) {
   asm("v_fma_f32 %0, %1, %0, %2" : "+v"(d) : "s"(a), "v"(b));
 }
 __device__ __forceinline__ void fma_ip(double& d, double a, double b) {
   asm("v_fma_f64 %0, %1, %0, %2" : "+v"(d) : "s"(a), "v"(b));
 }
+__device__ __forceinline__ void fma_acc(float& d, float a, float b) {
+  asm("v_fma_f32 %0, %1, %2, %0" : "+v"(d) : "s"(a), "v"(b));
+}
+__device__ __forceinline__ void fma_acc(double& d, double a, double b) {
+  asm("v_fma_f64 %0, %1, %2, %0" : "+v"(d) : "s"(a), "v"(b));
+}
+
+// The parameters of one rotation as the rotation code takes them.  Complex
+// sine: (c, sr, si).  Real sine: the rotation [[c, s], [-s, c]] with c >= 0
+// (every cosine of a decomposition is) is the product of three shears,
+// [[1, t], [0, 1]] [[1, 0], [b, 1]] [[1, t], [0, 1]] with t = s / (1 + c) and
+// b = -s (1 + t b = c and t (1 + c) = s), so each component of a member pair
+// takes three in-place FMAs, x += t y, y += b x, x += t y, instead of two
+// multiplications and two FMAs; |t| <= 1, so the shears add no more than
+// ordinary rounding.
+template <class R>
+struct RotShear {
+  R t, b;
+};
+template <class R>
+struct RotCplx {
+  R c, sr, si;
+};
+template <bool REAL, class R>
+using RotQ = typename std::conditional<REAL, RotShear<R>, RotCplx<R>>::type;
+
+// one component of a member pair under the three shears
+template <class R>
+__device__ __forceinline__ void shear3(R& x, R& y, R t, R b) {
+  fma_acc(x, t, y);
+  fma_acc(y, b, x);
+  fma_acc(x, t, y);
+}
 
 // x' = c x + s y, y' = -conj(s) x + c y on one member pair (A, B)
 template <int A, int B, bool REAL, class V>
-__device__ __forceinline__ void rot_pair(V* v, ER<V> c, ER<V> sr, ER<V> si) {
+__device__ __forceinline__ void rot_pair(V* v, const RotQ<REAL, ER<V>>& q) {
   using R = ER<V>;
   V& x = v[A];
   V& y = v[B];
   if constexpr (ElemT<V>::plane) {
     // one plane of the row: a real rotation acts on it alone
     static_assert(REAL, "row planes take real rotations only");
-    const R tx = sr * y.x, ux = -sr * x.x;
-    fma_ip(x.x, c, tx);
-    fma_ip(y.x, c, ux);
+    shear3<R>(x.x, y.x, q.t, q.b);
+  } else if constexpr (REAL) {
+    shear3<R>(x.x, y.x, q.t, q.b);
+    shear3<R>(x.y, y.y, q.t, q.b);
   } else {
-    R tx, ty, ux, uy;
-    if constexpr (REAL) {
-      tx = sr * y.x;
-      ty = sr * y.y;
-      ux = -sr * x.x;
-      uy = -sr * x.y;
-    } else {
-      tx = sr * y.x - si * y.y;
-      ty = sr * y.y + si * y.x;
-      ux = -sr * x.x - si * x.y;
-      uy = si * x.x - sr * x.y;
-    }
+    const R c = q.c, sr = q.sr, si = q.si;
+    const R tx = sr * y.x - si * y.y;
+    const R ty = sr * y.y + si * y.x;
+    const R ux = -sr * x.x - si * x.y;
+    const R uy = si * x.x - sr * x.y;
     fma_ip(x.x, c, tx);
     fma_ip(x.y, c, ty);
     fma_ip(y.x, c, ux);
@@ -185,23 +212,39 @@ __device__ __forceinline__ void rot_pair(V* v, ER<V> c, ER<V> sr, ER<V> si) {
 // every member pair of rotation P, expanded at compile time so that the
 // register array is only ever indexed by constants
 template <int W, int M, int P, bool REAL, class V, int... I>
-__device__ __forceinline__ void rot_pairs(V* v, ER<V> c, ER<V> sr, ER<V> si, std::integer_sequence<int, I...>) {
+__device__ __forceinline__ void rot_pairs(V* v, const RotQ<REAL, ER<V>>& q, std::integer_sequence<int, I...>) {
   constexpr Pairs<W, M, P> pr{};
-  (rot_pair<pr.a[I], pr.b[I], REAL, V>(v, c, sr, si), ...);
+  (rot_pair<pr.a[I], pr.b[I], REAL, V>(v, q), ...);
 }
 
 template <int W, int M, int P, bool REAL, class V>
-__device__ __forceinline__ void rot_one(V* v, ER<V> c, ER<V> sr, ER<V> si) {
-  rot_pairs<W, M, P, REAL, V>(v, c, sr, si, std::make_integer_sequence<int, Pairs<W, M, P>::NP>{});
+__device__ __forceinline__ void rot_one(V* v, const RotQ<REAL, ER<V>>& q) {
+  rot_pairs<W, M, P, REAL, V>(v, q, std::make_integer_sequence<int, Pairs<W, M, P>::NP>{});
 }
 
 template <int W, int M, bool REAL, class V, int P = 0>
-__device__ __forceinline__ void rot_dispatch(int p, V* v, ER<V> c, ER<V> sr, ER<V> si) {
+__device__ __forceinline__ void rot_dispatch(int p, V* v, const RotQ<REAL, ER<V>>& q) {
   if constexpr (P < W - 1) {
     if (p == P)
-      rot_one<W, M, P, REAL, V>(v, c, sr, si);
+      rot_one<W, M, P, REAL, V>(v, q);
     else
-      rot_dispatch<W, M, REAL, V, P + 1>(p, v, c, sr, si);
+      rot_dispatch<W, M, REAL, V, P + 1>(p, v, q);
+  }
+}
+
+// the rotation code's parameters from a RotDev, in the element's precision
+template <bool REAL, class R>
+__device__ __forceinline__ RotQ<REAL, R> rot_q(const RotDev& g) {
+  if constexpr (std::is_same<R, double>::value) {
+    if constexpr (REAL)
+      return RotShear<double>{g.t, g.b};
+    else
+      return RotCplx<double>{g.c, g.sr, g.si};
+  } else {
+    if constexpr (REAL)
+      return RotShear<float>{g.ft, g.fb};
+    else
+      return RotCplx<float>{g.fc, g.fsr, g.fsi};
   }
 }
 
@@ -214,7 +257,7 @@ __device__ __forceinline__ void apply_rots(V* v, const RotDev* __restrict__ rots
   RotDev cur = rots[0];
   for (int r = 0; r < nrot; ++r) {
     const RotDev nxt = rots[r + 1 < nrot ? r + 1 : r];
-    rot_dispatch<W, M, REAL, V>(cur.p, v, (R)cur.c, (R)cur.sr, (R)cur.si);
+    rot_dispatch<W, M, REAL, V>(cur.p, v, rot_q<REAL, R>(cur));
     cur = nxt;
   }
 }
@@ -232,32 +275,18 @@ struct RotLane {
 template <class T>
 __device__ __forceinline__ T uniform_load(const T* p);
 
-// the parameters a rotation loop reads with scalar loads: (c, sr) of a real
-// rotation, (c, sr, si) of a complex one, in the element's precision
-template <class R>
-struct RotParR {
-  R c, sr;
-};
-template <class R>
-struct RotParC {
-  R c, sr, si;
-};
-template <bool REAL, class R>
-using RotQ = typename std::conditional<REAL, RotParR<R>, RotParC<R>>::type;
+// a stage's rotation I, read with scalar loads: the shear parameters (t, b) of
+// a real rotation or (c, sr, si) of a complex one, in the element's precision
 template <bool REAL, class R>
 __device__ __forceinline__ RotQ<REAL, R> rot_params(const RotDev* g, int i) {
-  static_assert(offsetof(RotDev, c) == 8 && offsetof(RotDev, sr) == 16 && offsetof(RotDev, si) == 24 &&
-                    offsetof(RotDev, fc) == 32 && offsetof(RotDev, fsr) == 36 && offsetof(RotDev, fsi) == 40,
-                "scalar parameter loads assume RotDev = {p, pad, c, sr, si, fc, fsr, fsi, fpad}");
-  constexpr int off = std::is_same<R, double>::value ? 8 : 32;
+  static_assert(offsetof(RotDev, t) == 8 && offsetof(RotDev, b) == 16 && offsetof(RotDev, c) == 24 &&
+                    offsetof(RotDev, sr) == 32 && offsetof(RotDev, si) == 40 && offsetof(RotDev, ft) == 48 &&
+                    offsetof(RotDev, fb) == 52 && offsetof(RotDev, fc) == 56 && offsetof(RotDev, fsr) == 60 &&
+                    offsetof(RotDev, fsi) == 64,
+                "scalar parameter loads assume the RotDev layout");
+  constexpr bool dbl = std::is_same<R, double>::value;
+  constexpr int off = REAL ? (dbl ? 8 : 48) : (dbl ? 24 : 56);
   return uniform_load((const RotQ<REAL, R>*)((const char*)(g + i) + off));
-}
-template <bool REAL, class R>
-__device__ __forceinline__ R rot_si(const RotQ<REAL, R>& q) {
-  if constexpr (REAL)
-    return R(0);
-  else
-    return q.si;
 }
 
 // Generic stages: rotation r's position and parameters, loaded one rotation
@@ -269,10 +298,7 @@ __device__ __forceinline__ void apply_rots_lane(V* v, const RotLane<ER<V>>& rl, 
   RotDev cur = uniform_load(rl.g);
   for (int r = 0; r < nrot; ++r) {
     const RotDev nxt = uniform_load(rl.g + (r + 1 < nrot ? r + 1 : r));
-    if constexpr (std::is_same<R, double>::value)
-      rot_dispatch<W, M, REAL, V>(cur.p, v, cur.c, cur.sr, REAL ? 0.0 : cur.si);
-    else
-      rot_dispatch<W, M, REAL, V>(cur.p, v, cur.fc, cur.fsr, REAL ? 0.0f : cur.fsi);
+    rot_dispatch<W, M, REAL, V>(cur.p, v, rot_q<REAL, R>(cur));
     cur = nxt;
   }
 }
@@ -285,7 +311,7 @@ __device__ __forceinline__ RotQ<REAL, ER<V>> shape_rot(V* v, const RotDev* g, Ro
   using R = ER<V>;
   constexpr int n = kShapeLen[S];
   const RotQ<REAL, R> nxt = rot_params<REAL, R>(g, I + 1 < n ? I + 1 : I);
-  rot_one<W, M, kShapeP[S][I], REAL, V>(v, cur.c, cur.sr, rot_si<REAL, R>(cur));
+  rot_one<W, M, kShapeP[S][I], REAL, V>(v, cur);
   // nothing of a later rotation is scheduled into this one, where it would
   // only hold registers
   __builtin_amdgcn_sched_barrier(0);

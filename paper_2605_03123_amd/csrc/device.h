@@ -10,16 +10,22 @@ namespace ffx {
 namespace dev {
 
 // One Givens rotation as read by the kernels: local orbital p (relative to the
-// window start), cosine c and complex sine (sr, si); fc, fsr, fsi are the same
-// values rounded to FP32 (for complex64 states).  Built by make_rot.
+// window start), cosine c and complex sine (sr, si), and for a real sine the
+// shear parameters t = s / (1 + c) and b = -s of x += t y, y += b x, x += t y
+// (c >= 0); the f-prefixed fields hold the same values rounded to FP32 (for
+// complex64 states).  Built by make_rot.
 struct RotDev {
   int p;
   int pad;
+  double t, b;
   double c, sr, si;
-  float fc, fsr, fsi, fpad;
+  float ft, fb;
+  float fc, fsr, fsi;
+  float fpad;
 };
 inline RotDev make_rot(int p, double c, double sr, double si) {
-  return RotDev{p, 0, c, sr, si, (float)c, (float)sr, (float)si, 0.0f};
+  const double t = sr / (1.0 + c), b = -sr;
+  return RotDev{p, 0, t, b, c, sr, si, (float)t, (float)b, (float)c, (float)sr, (float)si, 0.0f};
 }
 
 // Window class table on the device (see WindowTable in host.h).

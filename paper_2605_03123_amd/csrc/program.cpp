@@ -352,6 +352,7 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
           // starts the next segment pass: applied as the segments are loaded
           flush_seg(false);
           const Givens& g = d.rots[step.idx[0]];
+          if (!(g.c >= 0.0)) throw Error(FFX_EDEVICE, "Givens rotation with a negative cosine");
           cur.cross = true;
           cur.cross_rot = dev::make_rot(0, g.c, g.s.real(), g.s.imag());
           cur.valu_slots += slots;
@@ -361,6 +362,9 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
         std::vector<dev::RotDev> buf;
         for (int i : step.idx) {
           const Givens& g = d.rots[i];
+          // the shear form of a real rotation needs c >= 0, which every
+          // decomposition's rotation has (c = |b| / r)
+          if (!(g.c >= 0.0)) throw Error(FFX_EDEVICE, "Givens rotation with a negative cosine");
           buf.push_back(dev::make_rot(g.p - step.a, g.c, g.s.real(), g.s.imag()));
         }
         if (step.kind == 0) {

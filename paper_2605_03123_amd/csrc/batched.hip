@@ -499,12 +499,12 @@ __device__ __forceinline__ void seg_task(const BatchDev& B, const BPassDev& ps, 
   // each Givens stage's rotations and first class codes are requested a stage
   // ahead (as in the segment pass)
   RotLane<R> rl_next{nullptr};
-  ChunkAhead fc_next{1, -1};
+  ChunkAhead fc_next{1, 1, -1, -1};
   auto fetch = [&](int si) {
     const StageDev st = uniform_load(ps.stages + si);
     if (st.type == ST_GIVENS) {
       rl_next = fetch_rot_lane<R>(st.rots, st.nrot, lane);
-      fc_next = fetch_first_chunk(uniform_load(pick2(ty.win, cs) + st.a), wave, lane);
+      fc_next = fetch_first_chunk(uniform_load(pick2(ty.win, cs) + st.a), wave, lane, nwaves);
     }
   };
   if (ps.n_stages > 0) fetch(0);

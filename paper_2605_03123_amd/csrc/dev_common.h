@@ -461,16 +461,29 @@ __device__ __forceinline__ void lds_m(int m, V* row, int cbase, const int* mtl, 
 // A stage of shape S (uniform; -1 = none) runs that shape's straight-line code.
 // A wave's first chunk of a Givens stage (its electron count in the window
 // and this lane's class code), requested ahead of the stage.
+// (A wave's second chunk, when it has one, is requested with the first: the
+// class codes come from global memory, and loading them when the wave reaches
+// its second chunk put one memory latency on the stage's critical path.)
 struct ChunkAhead {
-  int m;
-  int code;
+  int m, m2;
+  int code, code2;
 };
 
-__device__ __forceinline__ ChunkAhead fetch_first_chunk(const SegWinDev& wt, int wave, int lane) {
-  ChunkAhead f{1, -1};
+// TWO = false (row planes, whose register plane leaves no room for the second
+// code): only the first chunk is requested ahead.
+template <bool TWO = true>
+__device__ __forceinline__ ChunkAhead fetch_first_chunk(const SegWinDev& wt, int wave, int lane, int nwaves) {
+  ChunkAhead f{1, 1, -1, -1};
   if (wave < wt.n_chunks) {
     f.m = uniform_load(wt.chunk_m + wave);
     f.code = wt.code[wave * 64 + lane];
+  }
+  if constexpr (TWO) {
+    const int w2 = wave + nwaves;
+    if (w2 < wt.n_chunks) {
+      f.m2 = uniform_load(wt.chunk_m + w2);
+      f.code2 = wt.code[w2 * 64 + lane];
+    }
   }
   return f;
 }
@@ -494,9 +507,13 @@ template <int W, bool REAL, class V, int S>
 __device__ __forceinline__ void givens_chunks(V* row, const int* mtl, const SegWinDev& wt, const RotLane<ER<V>>& rl,
                                               int nrot, int wave, int nwaves, int lane, ChunkAhead first) {
   const int* mw = mtl + wt.mt_off;
-  for (int ch = wave; ch < wt.n_chunks; ch += nwaves) {
+  constexpr bool two = !ElemT<V>::plane;  // the second chunk's code was requested ahead
+  for (int ch = wave, k = 0; ch < wt.n_chunks; ch += nwaves, ++k) {
     int m = first.m, code = first.code;
-    if (ch != wave) {
+    if (two && k == 1) {
+      m = first.m2;
+      code = first.code2;
+    } else if (k > 0) {
       m = uniform_load(wt.chunk_m + ch);
       code = wt.code[ch * 64 + lane];
     }

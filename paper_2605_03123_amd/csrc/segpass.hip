@@ -233,12 +233,12 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
   // class codes) is requested one stage ahead, so that its latency overlaps the
   // stage before; descriptors come through the scalar cache
   RotLane<R> rl_next{nullptr};
-  ChunkAhead fc_next{1, -1};
+  ChunkAhead fc_next{1, 1, -1, -1};
   auto fetch = [&](int s) {
     const StageDev st = uniform_load(P.stages + s);
     if (st.type == ST_GIVENS) {
       rl_next = fetch_rot_lane<R>(st.rots, st.nrot, lane);
-      fc_next = fetch_first_chunk(uniform_load(sg.win + st.a), wave, lane);
+      fc_next = fetch_first_chunk(uniform_load(sg.win + st.a), wave, lane, nwaves);
     }
   };
   if (P.n_stages > 0) fetch(0);
@@ -397,7 +397,7 @@ __device__ __forceinline__ void plane_givens_run(const SegPassDev& P, const SegD
                                                  int s0, int s1, int wave, int nwaves, int lane) {
   StageDev st = uniform_load(P.stages + s0);
   RotLane<double> rl_next = fetch_rot_lane<double>(st.rots, st.nrot, lane);
-  ChunkAhead fc_next = fetch_first_chunk(uniform_load(sg.win + st.a), wave, lane);
+  ChunkAhead fc_next = fetch_first_chunk<false>(uniform_load(sg.win + st.a), wave, lane, nwaves);
   for (int s = s0; s < s1; ++s) {
     st = uniform_load(P.stages + s);
     const RotLane<double> rl = rl_next;
@@ -405,7 +405,7 @@ __device__ __forceinline__ void plane_givens_run(const SegPassDev& P, const SegD
     if (s + 1 < s1) {
       const StageDev nx = uniform_load(P.stages + s + 1);
       rl_next = fetch_rot_lane<double>(nx.rots, nx.nrot, lane);
-      fc_next = fetch_first_chunk(uniform_load(sg.win + nx.a), wave, lane);
+      fc_next = fetch_first_chunk<false>(uniform_load(sg.win + nx.a), wave, lane, nwaves);
     }
     const SegWinDev wt = uniform_load(sg.win + st.a);
     givens_stage_v<W, true, re128>(st.shape, pl, mtl, wt, rl, st.nrot, wave, nwaves, lane, fc);

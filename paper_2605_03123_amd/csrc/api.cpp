@@ -44,6 +44,8 @@ hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 // (beta on the alpha-major states, alpha on their transposes); otherwise
 // between row pairs.
 
+static_assert(kCodeMoffBits == dev::kCodeMoffBitsDev, "class code fields differ between host and device");
+
 void ensure_rank_tables(ffx_plan_s& P) {
   if (P.rank_lo) return;
   std::vector<int> lo(256, 0), hi(256 * 17, 0);
@@ -398,14 +400,15 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
         for (SegWindowTable& t : tabs[g]) {
           balance_seg_window(t, ss.Wseg, ss.threads / 64);
           dev::SegWinDev wd{};
-          int* code = (int*)P->dalloc(std::max<size_t>(t.code.size(), 1) * 4);
+          while (mt_all.size() % 4) mt_all.push_back(0);
+          wd.mt_off = (int)mt_all.size();
+          const std::vector<int> packed = pack_class_codes(t, wd.mt_off);
+          int* code = (int*)P->dalloc(std::max<size_t>(packed.size(), 1) * 4);
           int* cm = (int*)P->dalloc(std::max<size_t>(t.chunk_m.size(), 1) * 4);
-          if (!t.code.empty()) HIPCHK(hipMemcpy(code, t.code.data(), t.code.size() * 4, hipMemcpyHostToDevice));
+          if (!packed.empty()) HIPCHK(hipMemcpy(code, packed.data(), packed.size() * 4, hipMemcpyHostToDevice));
           if (!t.chunk_m.empty()) HIPCHK(hipMemcpy(cm, t.chunk_m.data(), t.chunk_m.size() * 4, hipMemcpyHostToDevice));
           wd.code = code;
           wd.chunk_m = cm;
-          while (mt_all.size() % 4) mt_all.push_back(0);
-          wd.mt_off = (int)mt_all.size();
           wd.n_chunks = (int)t.chunk_m.size();
           wd.nl1 = t.nl1;
           mt_all.insert(mt_all.end(), t.mt.begin(), t.mt.end());
@@ -477,15 +480,16 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
           for (SegWindowTable& t : ptabs) {
             balance_seg_window(t, Wp, plane_threads / 64);
             dev::SegWinDev wd{};
-            int* code = (int*)P->dalloc(std::max<size_t>(t.code.size(), 1) * 4);
+            while (mt_all.size() % 4) mt_all.push_back(0);
+            wd.mt_off = (int)mt_all.size();
+            const std::vector<int> packed = pack_class_codes(t, wd.mt_off);
+            int* code = (int*)P->dalloc(std::max<size_t>(packed.size(), 1) * 4);
             int* cm = (int*)P->dalloc(std::max<size_t>(t.chunk_m.size(), 1) * 4);
-            if (!t.code.empty()) HIPCHK(hipMemcpy(code, t.code.data(), t.code.size() * 4, hipMemcpyHostToDevice));
+            if (!packed.empty()) HIPCHK(hipMemcpy(code, packed.data(), packed.size() * 4, hipMemcpyHostToDevice));
             if (!t.chunk_m.empty())
               HIPCHK(hipMemcpy(cm, t.chunk_m.data(), t.chunk_m.size() * 4, hipMemcpyHostToDevice));
             wd.code = code;
             wd.chunk_m = cm;
-            while (mt_all.size() % 4) mt_all.push_back(0);
-            wd.mt_off = (int)mt_all.size();
             wd.n_chunks = (int)t.chunk_m.size();
             wd.nl1 = t.nl1;
             mt_all.insert(mt_all.end(), t.mt.begin(), t.mt.end());

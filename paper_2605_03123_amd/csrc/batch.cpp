@@ -154,10 +154,10 @@ void build_tables(ffx_batch_s& b) {
         SegWindowTable one = build_seg_window(P.str[cs], ss.wt, a, ss.Wseg);
         SegWindowTable rep = replicate_seg_window(one, ss.Wseg, R, (int)len);
         dev::SegWinDev wd{};
-        wd.code = b.upload_table(rep.code);
-        wd.chunk_m = b.upload_table(rep.chunk_m);
         while (mt_all.size() % 4) mt_all.push_back(0);
         wd.mt_off = (int)mt_all.size();
+        wd.code = b.upload_table(pack_class_codes(rep, wd.mt_off));
+        wd.chunk_m = b.upload_table(rep.chunk_m);
         wd.n_chunks = (int)rep.chunk_m.size();
         wd.nl1 = rep.nl1;
         mt_all.insert(mt_all.end(), rep.mt.begin(), rep.mt.end());

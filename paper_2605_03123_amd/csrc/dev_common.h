@@ -506,7 +506,6 @@ __device__ __forceinline__ RotLane<R> fetch_rot_lane(const RotDev* rots, int nro
 template <int W, bool REAL, class V, int S>
 __device__ __forceinline__ void givens_chunks(V* row, const int* mtl, const SegWinDev& wt, const RotLane<ER<V>>& rl,
                                               int nrot, int wave, int nwaves, int lane, ChunkAhead first) {
-  const int* mw = mtl + wt.mt_off;
   constexpr bool two = !ElemT<V>::plane;  // the second chunk's code was requested ahead
   for (int ch = wave, k = 0; ch < wt.n_chunks; ch += nwaves, ++k) {
     int m = first.m, code = first.code;
@@ -517,7 +516,8 @@ __device__ __forceinline__ void givens_chunks(V* row, const int* mtl, const SegW
       m = uniform_load(wt.chunk_m + ch);
       code = wt.code[ch * 64 + lane];
     }
-    if (code >= 0) lds_m<W, REAL, V, S>(m, row, code >> 5, mtl, wt.mt_off + mw[m * wt.nl1 + (code & 31)], rl, nrot);
+    // a code holds the class base and the index of its member-offset table
+    if (code >= 0) lds_m<W, REAL, V, S>(m, row, code >> kCodeMoffBitsDev, mtl, code & ((1 << kCodeMoffBitsDev) - 1), rl, nrot);
   }
 }
 

@@ -254,10 +254,12 @@ struct StageDev {
 };
 
 // Class tables of one register window inside one segment.  Chunk ch holds 64
-// lanes; code[ch * 64 + lane] = (cbase << 5) | l for the lane's class (-1 for
-// padding), where member k of the class sits at cbase + mt[mt[m * nl1 + l] + k]
-// (m = electrons in the window, l = electrons below it).  Chunks are listed in
-// order of decreasing work; classes with an empty or full window are omitted.
+// lanes; code[ch * 64 + lane] = (cbase << kCodeMoffBitsDev) | moff for the
+// lane's class (-1 for padding), where member k of the class sits at cbase +
+// mt_all[moff + k] (moff = mt_off + mt[m * nl1 + l] for m electrons in the
+// window and l below it, folded in on the host).  Chunks are listed in order
+// of decreasing work; classes with an empty or full window are omitted.
+constexpr int kCodeMoffBitsDev = 14;
 struct SegWinDev {
   const int* code;
   const int* chunk_m;

@@ -466,6 +466,22 @@ void balance_seg_window(SegWindowTable& t, int w, int nwaves) {
   t = std::move(o);
 }
 
+std::vector<int> pack_class_codes(const SegWindowTable& t, int mt_off) {
+  std::vector<int> out(t.code.size(), -1);
+  for (size_t ch = 0; ch < t.chunk_m.size(); ++ch) {
+    const int m = t.chunk_m[ch];
+    for (size_t l = 0; l < 64 && ch * 64 + l < t.code.size(); ++l) {
+      const int c = t.code[ch * 64 + l];
+      if (c < 0) continue;
+      const int64_t cbase = c >> 5, moff = (int64_t)mt_off + t.mt[(size_t)m * t.nl1 + (c & 31)];
+      if (cbase >= ((int64_t)1 << (31 - kCodeMoffBits)) || moff >= ((int64_t)1 << kCodeMoffBits))
+        throw Error(FFX_EUNSUPPORTED, "class table exceeds the packed code fields");
+      out[ch * 64 + l] = (int)((cbase << kCodeMoffBits) | moff);
+    }
+  }
+  return out;
+}
+
 SegWindowTable replicate_seg_window(const SegWindowTable& t, int w, int R, int row_len) {
   SegWindowTable o;
   o.nl1 = t.nl1;

@@ -197,6 +197,25 @@ static void check_segment(const std::vector<uint64_t>& seg, int wt, int w, int g
       walk(b, seen2, codes2);
       CHECK(codes2 == codes && seen2 == seen, "%s: balancing changed the classes", what);
     }
+    // packed codes: the base and the absolute index of the class's offset
+    // table, with the window's tables placed at an arbitrary start in the block
+    {
+      const int mt_off = 4 * (a + 1);
+      const std::vector<int> packed = ffx::pack_class_codes(t, mt_off);
+      CHECK(packed.size() == t.code.size(), "%s: packed code count", what);
+      for (size_t c = 0; c < t.chunk_m.size(); ++c)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int code = t.code[c * 64 + lane], pk = packed[c * 64 + lane];
+          if (code < 0) {
+            CHECK(pk == -1, "%s: packed padding", what);
+            continue;
+          }
+          const int m = t.chunk_m[c];
+          CHECK((pk >> ffx::kCodeMoffBits) == (code >> 5), "%s: packed base a=%d", what, a);
+          CHECK((pk & ((1 << ffx::kCodeMoffBits) - 1)) == mt_off + t.mt[m * t.nl1 + (code & 31)],
+                "%s: packed table index a=%d", what, a);
+        }
+    }
     // replication over rows shifts the bases by whole rows
     const int R = 3;
     ffx::SegWindowTable rep = ffx::replicate_seg_window(t, w, R, (int)seg.size());

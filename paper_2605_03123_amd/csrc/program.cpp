@@ -12,6 +12,7 @@
 // decomposition is diagonal, so it is deferred into the next diagonal phase
 // stage (or a final phase stage) instead of costing a pass of its own.
 #include <cmath>
+#include <cstdlib>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -475,10 +476,13 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
   // Measured at 16 orbitals: 2 % faster for complex128 (eight amplitudes of a
   // cache line serve eight blocks of one XCD), 1.5 % slower for complex64
   // (sixteen), so complex64 keeps the transposes.
+  // FFX_GATHER=0/1 overrides the choice (measurements).
+  bool gather = !P.c64;
+  if (const char* e = std::getenv("FFX_GATHER")) gather = std::atoi(e) != 0;
   std::vector<Launch> fused;
   for (size_t i = 0; i < c.launches.size(); ++i) {
     const Launch& L = c.launches[i];
-    if (!P.c64 && L.kind == Launch::TRANSPOSE && i + 1 < c.launches.size() &&
+    if (gather && L.kind == Launch::TRANSPOSE && i + 1 < c.launches.size() &&
         c.launches[i + 1].kind == Launch::SEG) {
       Launch nx = c.launches[i + 1];
       nx.gather = true;

@@ -368,6 +368,20 @@ __device__ __forceinline__ void stage_in(V* __restrict__ dst, const V* __restric
   }
 }
 
+// The same with the destination strided: src[e] goes to dst[e * stride] (a row
+// stored as a column of the other layout).
+template <int U, class V>
+__device__ __forceinline__ void stage_out_strided(V* __restrict__ dst, const V* __restrict__ src, int len,
+                                                  int64_t stride, int tid, int nthr) {
+  for (int e0 = tid; e0 < len; e0 += U * nthr) {
+    V t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) t[u] = src[min(e0 + u * nthr, len - 1)];
+#pragma unroll
+    for (int u = 0; u < U; ++u) dst[(int64_t)min(e0 + u * nthr, len - 1) * stride] = t[u];
+  }
+}
+
 template <class R>
 __device__ __forceinline__ typename V2T<R>::type phase_factor(double ang);
 template <>

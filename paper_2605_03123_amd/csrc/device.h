@@ -316,6 +316,9 @@ struct SegPassDev {
   // pass at src[c * n_rows + r]), so the pass also transposes (it must not
   // write src).
   int gather;
+  // scatter: dst receives the state in the other layout (element (r, c) of this
+  // pass at dst[c * n_rows + r]), so the pass also transposes (dst != src).
+  int scatter;
   // xcd_rows > 0: blocks take rows per XCD: block b works on XCD b % 8, on row
   // (b % 8) * xcd_rows + (b / 8) / n_seg, segment (b / 8) % n_seg, so that the
   // blocks of one XCD gather neighbouring columns of the same cache lines, and

@@ -296,6 +296,8 @@ struct Launch {
   bool cross = false;
   // rows gathered from the other layout (replaces a transpose before the pass)
   bool gather = false;
+  // rows stored as columns of the other layout (replaces a transpose after the pass)
+  bool scatter = false;
   // the row held as two planes (the plan's plane set of the column spin)
   bool planes = false;
   dev::RotDev cross_rot{};

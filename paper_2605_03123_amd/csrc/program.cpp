@@ -471,17 +471,32 @@ Compiled compile_program(ffx_plan_s& P, Upload& up, const Program& prog, int fin
   if (final_mode == FINAL_ACCUM &&
       (c.launches.empty() || c.launches.back().kind != Launch::SEG || c.launches.back().layout != 0))
     close_visit(true);  // a stage-free segment pass that adds the result into the target
-  // a transpose followed by a segment pass of the new layout: the pass
-  // gathers its rows from the old layout instead (one state round trip less).
-  // Measured at 16 orbitals: 2 % faster for complex128 (eight amplitudes of a
-  // cache line serve eight blocks of one XCD), 1.5 % slower for complex64
-  // (sixteen), so complex64 keeps the transposes.
-  // FFX_GATHER=0/1 overrides the choice (measurements).
+  // A transpose after a segment pass that stores the state: the pass stores
+  // its rows as columns of the new layout instead (scatter); otherwise, a
+  // transpose followed by a segment pass of the new layout: the pass gathers
+  // its rows from the old layout (gather).  Either saves one state round trip.
+  // Measured on the DF step at 16 orbitals, complex128: gathering 2 % faster
+  // than the transposes (eight amplitudes of a cache line serve eight blocks
+  // of one XCD), scattering 2 % faster than gathering; complex64: gathering
+  // 1.5 % slower than the transposes (sixteen blocks per line), scattering
+  // 0.5 % slower, so complex64 keeps the transposes.
+  // FFX_SCATTER=0/1 and FFX_GATHER=0/1 override the choices (measurements).
+  bool scatter = !P.c64;
+  if (const char* e = std::getenv("FFX_SCATTER")) scatter = std::atoi(e) != 0;
   bool gather = !P.c64;
   if (const char* e = std::getenv("FFX_GATHER")) gather = std::atoi(e) != 0;
+  int last_seg = -1;
+  for (int i = 0; i < (int)c.launches.size(); ++i)
+    if (c.launches[i].kind == Launch::SEG) last_seg = i;
   std::vector<Launch> fused;
   for (size_t i = 0; i < c.launches.size(); ++i) {
     const Launch& L = c.launches[i];
+    // (the last segment pass of a program without a final state stores nothing)
+    if (scatter && L.kind == Launch::TRANSPOSE && !fused.empty() && fused.back().kind == Launch::SEG &&
+        !fused.back().scatter && !((int)i - 1 == last_seg && final_mode == FINAL_NONE)) {
+      fused.back().scatter = true;
+      continue;
+    }
     if (gather && L.kind == Launch::TRANSPOSE && i + 1 < c.launches.size() &&
         c.launches[i + 1].kind == Launch::SEG) {
       Launch nx = c.launches[i + 1];
@@ -532,8 +547,8 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
       const Launch& L = c.launches[i];
       const bool store = L.kind == Launch::SEG && !(i == last_seg && c.final_mode != FINAL_STORE);
       if (L.kind == Launch::SEG) {
-        if (store && !at_src && (L.cross || L.gather || move[i])) in_work = !in_work;
-        if (store && !at_src && !L.cross && !L.gather) last_plain = i;
+        if (store && !at_src && (L.cross || L.gather || L.scatter || move[i])) in_work = !in_work;
+        if (store && !at_src && !L.cross && !L.gather && !L.scatter) last_plain = i;
         at_src = false;
       } else if (L.kind == Launch::TRANSPOSE && !square) {
         in_work = !in_work;
@@ -584,7 +599,8 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
         p.cross_si = L.cross_rot.si;
       }
       if (L.gather) p.gather = 1;
-      if (L.gather || L.cross) p.xcd_rows = (rows + 7) / 8;
+      if (L.scatter) p.scatter = 1;
+      if (L.gather || L.scatter || L.cross) p.xcd_rows = (rows + 7) / 8;
       if (i == last_seg && c.final_mode == FINAL_ACCUM) {
         p.mode = dev::SEG_ACCUM;
         p.dst = accum;
@@ -593,11 +609,12 @@ void execute_program(ffx_plan_s& P, const Compiled& c, const void* src, void* wo
         p.dst = nullptr;
       } else {
         p.mode = dev::SEG_STORE;
-        if (cur_src == cur && (L.cross || L.gather || move[i])) cur = (cur == work) ? P.tmp_state() : work;
+        if (cur_src == cur && (L.cross || L.gather || L.scatter || move[i]))
+          cur = (cur == work) ? P.tmp_state() : work;
         p.dst = cur;
       }
-      if ((L.cross || L.gather) && p.dst == p.src)
-        throw Error(FFX_EDEVICE, "crossing rotation or gathering pass needs an out-of-place pass");
+      if ((L.cross || L.gather || L.scatter) && p.dst == p.src)
+        throw Error(FFX_EDEVICE, "crossing rotation, gathering or scattering pass needs an out-of-place pass");
       if (L.planes)
         dev::seg_pass_planes(ss.Wseg, ss.threads, p, ss.lds, s);
       else

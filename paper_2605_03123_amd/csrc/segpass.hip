@@ -343,15 +343,20 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
   }
 
   if (P.mode != SEG_NONE) {
-    V* dst = (V*)P.dst + r * P.row_len + sg.off;
+    // row r of this layout, or (scatter) column r of the other one
+    const int64_t ostride = P.scatter ? P.n_rows : 1;
+    V* dst = P.scatter ? (V*)P.dst + r + (int64_t)sg.off * P.n_rows : (V*)P.dst + r * P.row_len + sg.off;
     if (P.mode == SEG_STORE) {
-      stage_in<128 / sizeof(V)>(dst, row, sg.len, tid, nthr);
+      if (P.scatter)
+        stage_out_strided<128 / sizeof(V)>(dst, row, sg.len, ostride, tid, nthr);
+      else
+        stage_in<128 / sizeof(V)>(dst, row, sg.len, tid, nthr);
     } else {
       for (int e = tid; e < sg.len; e += nthr) {
-        V a = dst[e], b = row[e];
+        V a = dst[e * ostride], b = row[e];
         a.x += b.x;
         a.y += b.y;
-        dst[e] = a;
+        dst[e * ostride] = a;
       }
     }
   }
@@ -541,7 +546,9 @@ __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
   }
 
   if (P.mode != SEG_NONE) {
-    zc128* dst = (zc128*)P.dst + r * P.row_len;
+    // row r of this layout, or (scatter) column r of the other one
+    const int64_t ostride = P.scatter ? P.n_rows : 1;
+    zc128* dst = P.scatter ? (zc128*)P.dst + r : (zc128*)P.dst + r * P.row_len;
 #pragma unroll
     for (int k = 0; k < kPlaneRegs; ++k) {
       const int e = tid + k * nthr;
@@ -549,11 +556,11 @@ __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
         const double a = pl[e].x, q = rp[k];
         zc128 v = lds_re ? zc128{a, q} : zc128{q, a};
         if (P.mode == SEG_ACCUM) {
-          const zc128 o = dst[e];
+          const zc128 o = dst[e * ostride];
           v.x += o.x;
           v.y += o.y;
         }
-        dst[e] = v;
+        dst[e * ostride] = v;
       }
     }
   }

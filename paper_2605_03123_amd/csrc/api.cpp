@@ -323,6 +323,17 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
       plane_threads = (v == 768 || v == 512) ? v : 0;
     }
     if (std::getenv("FFX_SEG_MAX")) plane_threads = 0;
+    // FFX_PLANE_SEG_MAX=<elements>: shorter plane segments (tests of the plane
+    // passes on rows split into segments, at small sizes)
+    int64_t plane_seg_max = (int64_t)1 << 30;
+    bool plane_seg_forced = false;
+    if (const char* e = std::getenv("FFX_PLANE_SEG_MAX")) {
+      const int64_t v = std::atoll(e);
+      if (v >= 1) {
+        plane_seg_max = v;
+        plane_seg_forced = true;
+      }
+    }
     // FFX_PLANES_ALL=1: plane sets also where whole rows fit in LDS (tests of the plane passes at small sizes)
     const bool planes_all = std::getenv("FFX_PLANES_ALL") != nullptr;
     const char* pack_env = std::getenv("FFX_SEG_PACK");
@@ -453,60 +464,92 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
       ss.lds = dev::seg_pass_lds(P->c64, ss.max_len, ss.max_mt);
       // rows of this column spin's layout times segments: one partial sum per block
       max_rows_x_seg = std::max<int>(max_rows_x_seg, (int)(P->dim[1 - s] * ss.n_seg));
-      // complex128 rows split into segments: when the real parts of a whole row
-      // fit in LDS, visits whose rotations are all real hold each row as two
-      // planes instead (one segment per row, no crossing rotation)
-      if (!P->c64 && (ss.wt < norb || planes_all) && plane_threads > 0 &&
-          (int64_t)strs.size() <= dev::seg_pass_plane_max_len(plane_threads)) {
-        auto& pl = P->plane[s];
-        const int Wp = std::min(P->W, norb);
-        std::vector<SegWindowTable> ptabs;
-        size_t mt = 0;
-        for (int a = 0; Wp >= 2 && a + Wp <= norb; ++a) {
-          ptabs.push_back(build_seg_window(strs, norb, a, Wp, lds_group_bytes / 8));
-          mt = ((mt + 3) & ~(size_t)3) + ptabs.back().mt.size();
-        }
-        // the row area holds 8-byte parts: sized as a complex64 row
-        const size_t need = dev::seg_pass_lds(true, (int)strs.size(), (int)mt + 3 * (int)ptabs.size() + 4);
-        if (Wp >= 4 && need <= lds_cap) {
-          pl.wt = norb;
+      // complex128 rows split into segments: visits whose rotations are all
+      // real hold the real parts of each row segment in LDS and the imaginary
+      // parts in registers (row planes).  The plane segments are the runs of
+      // strings that share the orbitals above the highest plane window whose
+      // runs fit the plane kernel: the whole row where its real parts fit (no
+      // rotation crosses a segment: one pass per visit); otherwise, as at 18
+      // orbitals, runs twice as long as the segment set's, with the rotations
+      // on the orbitals above the window left to whole-spin window passes.
+      if (!P->c64 && (ss.wt < norb || planes_all) && plane_threads > 0) {
+        const int64_t pmax = std::min<int64_t>(dev::seg_pass_plane_max_len(plane_threads), plane_seg_max);
+        for (int wp = norb; wp >= 1; --wp) {
+          const int Wp = std::min(P->W, wp);
+          if (Wp < 4) break;
+          std::vector<std::pair<int, int>> psegs = segment_runs(strs, wp);
+          int64_t longest = 0;
+          for (const auto& r : psegs) longest = std::max<int64_t>(longest, r.second);
+          if (longest > pmax) continue;
+          // split rows: only where the plane segments are longer than the
+          // segment set's and not packed runs of a low filling (whose many
+          // short runs would leave most blocks idle)
+          if (wp < norb && !(plane_seg_forced || (!packed && wp > ss.wt))) break;
+          std::vector<std::vector<SegWindowTable>> ptabs(psegs.size());
+          size_t mt_max = 0, n_tabs = 0;
+          for (size_t g = 0; g < psegs.size(); ++g) {
+            std::vector<uint64_t> sub(strs.begin() + psegs[g].first,
+                                      strs.begin() + psegs[g].first + psegs[g].second);
+            size_t mt = 0;
+            for (int a = 0; a + Wp <= wp; ++a) {
+              ptabs[g].push_back(build_seg_window(sub, wp, a, Wp, lds_group_bytes / 8));
+              mt = ((mt + 3) & ~(size_t)3) + ptabs[g].back().mt.size();
+            }
+            mt_max = std::max(mt_max, mt);
+            n_tabs = std::max(n_tabs, ptabs[g].size());
+          }
+          // the row area holds 8-byte parts: sized as a complex64 row
+          const size_t need = dev::seg_pass_lds(true, (int)longest, (int)mt_max + 3 * (int)n_tabs + 4);
+          if (need > lds_cap) continue;
+          auto& pl = P->plane[s];
+          pl.wt = wp;
           pl.Wseg = Wp;
-          pl.n_seg = 1;
-          pl.max_len = (int)strs.size();
+          pl.n_seg = (int)psegs.size();
+          pl.max_len = (int)longest;
           pl.threads = plane_threads;
           pl.cross = false;
-          std::vector<dev::SegWinDev> wins;
-          std::vector<int> mt_all;
-          for (SegWindowTable& t : ptabs) {
-            balance_seg_window(t, Wp, plane_threads / 64);
-            dev::SegWinDev wd{};
+          pl.max_mt = 0;
+          std::vector<dev::SegDev> hsegs;
+          for (size_t g = 0; g < psegs.size(); ++g) {
+            std::vector<dev::SegWinDev> wins;
+            std::vector<int> mt_all;
+            for (SegWindowTable& t : ptabs[g]) {
+              balance_seg_window(t, Wp, plane_threads / 64);
+              dev::SegWinDev wd{};
+              while (mt_all.size() % 4) mt_all.push_back(0);
+              wd.mt_off = (int)mt_all.size();
+              const std::vector<int> packed = pack_class_codes(t, wd.mt_off);
+              int* code = (int*)P->dalloc(std::max<size_t>(packed.size(), 1) * 4);
+              int* cm = (int*)P->dalloc(std::max<size_t>(t.chunk_m.size(), 1) * 4);
+              if (!packed.empty())
+                HIPCHK(hipMemcpy(code, packed.data(), packed.size() * 4, hipMemcpyHostToDevice));
+              if (!t.chunk_m.empty())
+                HIPCHK(hipMemcpy(cm, t.chunk_m.data(), t.chunk_m.size() * 4, hipMemcpyHostToDevice));
+              wd.code = code;
+              wd.chunk_m = cm;
+              wd.n_chunks = (int)t.chunk_m.size();
+              wd.nl1 = t.nl1;
+              mt_all.insert(mt_all.end(), t.mt.begin(), t.mt.end());
+              wins.push_back(wd);
+            }
             while (mt_all.size() % 4) mt_all.push_back(0);
-            wd.mt_off = (int)mt_all.size();
-            const std::vector<int> packed = pack_class_codes(t, wd.mt_off);
-            int* code = (int*)P->dalloc(std::max<size_t>(packed.size(), 1) * 4);
-            int* cm = (int*)P->dalloc(std::max<size_t>(t.chunk_m.size(), 1) * 4);
-            if (!packed.empty()) HIPCHK(hipMemcpy(code, packed.data(), packed.size() * 4, hipMemcpyHostToDevice));
-            if (!t.chunk_m.empty())
-              HIPCHK(hipMemcpy(cm, t.chunk_m.data(), t.chunk_m.size() * 4, hipMemcpyHostToDevice));
-            wd.code = code;
-            wd.chunk_m = cm;
-            wd.n_chunks = (int)t.chunk_m.size();
-            wd.nl1 = t.nl1;
-            mt_all.insert(mt_all.end(), t.mt.begin(), t.mt.end());
-            wins.push_back(wd);
+            pl.max_mt = std::max(pl.max_mt, (int)mt_all.size());
+            auto* dw = (dev::SegWinDev*)P->dalloc(std::max<size_t>(wins.size(), 1) * sizeof(dev::SegWinDev));
+            if (!wins.empty())
+              HIPCHK(hipMemcpy(dw, wins.data(), wins.size() * sizeof(dev::SegWinDev), hipMemcpyHostToDevice));
+            int* dmt = (int*)P->dalloc(std::max<size_t>(mt_all.size(), 1) * 4);
+            if (!mt_all.empty()) HIPCHK(hipMemcpy(dmt, mt_all.data(), mt_all.size() * 4, hipMemcpyHostToDevice));
+            hsegs.push_back(dev::SegDev{psegs[g].first, psegs[g].second, dw, dmt, (int)mt_all.size(), 0, 0, 0, 0, 0});
           }
-          while (mt_all.size() % 4) mt_all.push_back(0);
-          pl.max_mt = (int)mt_all.size();
-          auto* dw = (dev::SegWinDev*)P->dalloc(std::max<size_t>(wins.size(), 1) * sizeof(dev::SegWinDev));
-          if (!wins.empty())
-            HIPCHK(hipMemcpy(dw, wins.data(), wins.size() * sizeof(dev::SegWinDev), hipMemcpyHostToDevice));
-          int* dmt = (int*)P->dalloc(std::max<size_t>(mt_all.size(), 1) * 4);
-          if (!mt_all.empty()) HIPCHK(hipMemcpy(dmt, mt_all.data(), mt_all.size() * 4, hipMemcpyHostToDevice));
-          const dev::SegDev one{0, (int)strs.size(), dw, dmt, (int)mt_all.size(), 0, 0, 0, 0, 0};
-          pl.d_segs = (dev::SegDev*)P->dalloc(sizeof(dev::SegDev));
-          HIPCHK(hipMemcpy(pl.d_segs, &one, sizeof(dev::SegDev), hipMemcpyHostToDevice));
+          pl.d_segs = (dev::SegDev*)P->dalloc(hsegs.size() * sizeof(dev::SegDev));
+          HIPCHK(hipMemcpy(pl.d_segs, hsegs.data(), hsegs.size() * sizeof(dev::SegDev), hipMemcpyHostToDevice));
           pl.lds = dev::seg_pass_lds(true, pl.max_len, pl.max_mt);
-          if (pl.lds > lds_cap) pl = ffx_plan_s::SegSet{};
+          if (pl.lds > lds_cap) {
+            pl = ffx_plan_s::SegSet{};
+          } else {
+            max_rows_x_seg = std::max<int>(max_rows_x_seg, (int)(P->dim[1 - s] * pl.n_seg));
+          }
+          break;
         }
       }
     }

@@ -381,8 +381,12 @@ __global__ __launch_bounds__((seg_threads<W, R>())) void k_seg_pass(SegPassDev P
 // the plane in LDS, the planes are swapped, and the run is applied to the
 // other.  The other plane stays in registers: thread t holds the parts of
 // elements t, t + nthr, t + 2 nthr, ...  Diagonal stages combine the two parts
-// of each element in the thread that holds its register part.  The whole row
-// is one segment, so no rotation crosses a segment: one pass per visit.
+// of each element in the thread that holds its register part.  Where the real
+// parts of a whole row fit, the row is one segment and no rotation crosses a
+// segment: one pass per visit.  Longer rows are split, as in the segment pass,
+// into segments of the strings that share their highest orbitals (the
+// rotations on those orbitals run as whole-spin window passes between plane
+// passes); each block holds one segment of one row.
 // ---------------------------------------------------------------------------
 // Block sizes: 768 threads hold 17 register parts each (rows of up to 13 056
 // amplitudes, 168 registers a lane, 3 waves per SIMD; the default, 5 % faster
@@ -429,14 +433,20 @@ __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
   double* wq = (double*)(mtl + ((P.max_mt + 3) & ~3)); // 32 cross weights
   double* red = wq + 32;                               // block reduction scratch
 
+  // block -> (row, segment) as in the segment pass
+  int si;
   int64_t r;
   if (P.xcd_rows > 0) {
-    r = (int64_t)(blockIdx.x & 7) * P.xcd_rows + (blockIdx.x >> 3);
+    const int64_t k = blockIdx.x >> 3;
+    r = (int64_t)(blockIdx.x & 7) * P.xcd_rows + k / P.n_seg;
+    si = (int)(k % P.n_seg);
     if (r >= P.n_rows) return;  // the whole block: the grid rounds rows up to 8 XCDs
   } else {
-    r = blockIdx.x;
+    si = (int)(blockIdx.x % P.n_seg);
+    r = blockIdx.x / P.n_seg;
   }
-  const SegDev sg = uniform_load(P.segs);  // one segment: the whole row
+  const int64_t blk = r * P.n_seg + si;
+  const SegDev sg = uniform_load(P.segs + si);
   const int len = sg.len;
   const int nthr = blockDim.x;
   const int tid = threadIdx.x;
@@ -444,7 +454,8 @@ __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wave: loops over chunks stay scalar
   const int nwaves = nthr >> 6;
   const int64_t stride = P.gather ? P.n_rows : 1;
-  const zc128* src = P.gather ? (const zc128*)P.src + r : (const zc128*)P.src + r * P.row_len;
+  const zc128* src = P.gather ? (const zc128*)P.src + r + (int64_t)sg.off * P.n_rows
+                              : (const zc128*)P.src + r * P.row_len + sg.off;
 
   // the row: every load in flight before the first is used; real parts to the
   // LDS plane, imaginary parts to registers; then the member-offset tables
@@ -467,7 +478,7 @@ __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
   bool lds_re = true;  // the LDS plane holds the real parts (the same in every thread)
 
   const uint32_t rmask = P.row_masks[r];
-  const uint32_t* cmask = P.col_masks;
+  const uint32_t* cmask = P.col_masks + sg.off;
   const int nbytes = (P.norb + 7) >> 3;
   double acc = 0.0;
   int s = 0;
@@ -498,7 +509,7 @@ __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
     const bool cross = dr.cross;
     if (st.type == ST_PHASE) {
       const zc128 rowf = cross ? zc128{1.0, 0.0} : dr.rowf;
-      const zc128* colf = (const zc128*)st.colf;
+      const zc128* colf = st.colf ? (const zc128*)st.colf + sg.off : nullptr;
       const uint32_t sgn = st.sign_col;
       const bool use_cm = cross || sgn != 0;
 #pragma unroll
@@ -521,7 +532,7 @@ __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
         rp[k] = lds_re ? nim : nre;
       }
     } else {
-      const double* Bs = st.B;
+      const double* Bs = st.B ? st.B + sg.off : nullptr;
 #pragma unroll
       for (int k = 0; k < kPlaneRegs; ++k) {
         int e = tid + k * nthr;
@@ -548,7 +559,7 @@ __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
   if (P.mode != SEG_NONE) {
     // row r of this layout, or (scatter) column r of the other one
     const int64_t ostride = P.scatter ? P.n_rows : 1;
-    zc128* dst = P.scatter ? (zc128*)P.dst + r : (zc128*)P.dst + r * P.row_len;
+    zc128* dst = P.scatter ? (zc128*)P.dst + r + (int64_t)sg.off * P.n_rows : (zc128*)P.dst + r * P.row_len + sg.off;
 #pragma unroll
     for (int k = 0; k < kPlaneRegs; ++k) {
       const int e = tid + k * nthr;
@@ -572,7 +583,7 @@ __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
     if (tid == 0) {
       double t = 0.0;
       for (int i = 0; i < nwaves; ++i) t += red[i];
-      P.partials[r] = t;
+      P.partials[blk] = t;
     }
   }
 }
@@ -585,7 +596,7 @@ static void launch_planes(const SegPassDev& p, size_t lds, hipStream_t s) {
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
-  const int64_t blocks = p.xcd_rows > 0 ? 8 * p.xcd_rows : p.n_rows;
+  const int64_t blocks = p.xcd_rows > 0 ? 8 * p.xcd_rows * p.n_seg : p.n_rows * p.n_seg;
   hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(NT), lds, s, p);
 }
 

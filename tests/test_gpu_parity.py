@@ -416,9 +416,42 @@ def test_plane_passes_against_oracle(ffx, plane_plans):
     """Real rotations on row planes: DF steps (S_0, S_1, two steps; real U_t, the one-body factor making the
     first rotation complex), the DF energy (reductions), the Hamiltonian action (accumulation), LUCJ energy and
     gradient, and a real orbital rotation in place, against the oracle."""
-    for (norb, nelec, threads), plan in plane_plans.items():
-        print(f"plane passes norb={norb} nelec={nelec} threads={threads}", flush=True)
-        r = synth.rng([24, norb, int(threads)])
+    _check_plane_plans(ffx, plane_plans, 24)
+
+
+@pytest.fixture(scope="module")
+def plane_segment_plans(ffx):
+    """complex128 plans whose plane passes hold rows split into segments (FFX_PLANE_SEG_MAX caps a plane
+    segment at a few dozen amplitudes), as rows longer than the plane kernel's capacity are at 18 orbitals:
+    the rotations on the orbitals above the plane window run as whole-spin window passes between plane
+    passes."""
+    import os
+    plans = {}
+    old = {k: os.environ.get(k) for k in ("FFX_PLANES_ALL", "FFX_PLANE_SEG_MAX")}
+    os.environ["FFX_PLANES_ALL"] = "1"
+    try:
+        for cap in ("24", "40"):
+            os.environ["FFX_PLANE_SEG_MAX"] = cap
+            for norb, nelec in [(8, (4, 4)), (9, (4, 5)), (10, (5, 5)), (11, (5, 4))]:
+                plans[(norb, nelec, cap)] = ffx.Plan(norb, nelec, torch.complex128)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    return plans
+
+
+def test_plane_segment_passes_against_oracle(ffx, plane_segment_plans):
+    """The same checks on plane passes over row segments, with window passes between them."""
+    _check_plane_plans(ffx, plane_segment_plans, 25)
+
+
+def _check_plane_plans(ffx, plans, seed):
+    for (norb, nelec, threads), plan in plans.items():
+        print(f"plane passes norb={norb} nelec={nelec} variant={threads}", flush=True)
+        r = synth.rng([seed, norb, int(threads)])
         da, db = _dims(norb, nelec)
         vec = _to_dev(synth.random_state(r, da, db), torch.complex128)
         x = _ref_input(vec)

@@ -485,6 +485,7 @@ int ffx_plan_create(ffx_plan* out, int norb, int na, int nb, ffx_dtype dtype, in
           // segment set's and not packed runs of a low filling (whose many
           // short runs would leave most blocks idle)
           if (wp < norb && !(plane_seg_forced || (!packed && wp > ss.wt))) break;
+          if (psegs.size() > 1 && Wp != 6) break;  // (the split-row plane kernel is built for width 6)
           std::vector<std::vector<SegWindowTable>> ptabs(psegs.size());
           size_t mt_max = 0, n_tabs = 0;
           for (size_t g = 0; g < psegs.size(); ++g) {

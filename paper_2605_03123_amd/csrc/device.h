@@ -326,11 +326,11 @@ struct SegPassDev {
   int64_t xcd_rows;
 };
 
-// Segment passes on row planes (complex128 rows of at most
-// seg_pass_plane_max_len(threads) amplitudes, one segment per row, real Givens
-// rotations only): the real and imaginary parts are rotated in turn, one in
-// LDS (len * 8 bytes of row area in `lds`) and the other in registers.
-// W in 4..6; threads 512 or 768.
+// Segment passes on row planes (complex128 row segments of at most
+// seg_pass_plane_max_len(threads) amplitudes, real Givens rotations only): the
+// real and imaginary parts are rotated in turn, one in LDS (len * 8 bytes of
+// row area in `lds`) and the other in registers.
+// W in 4..6 (6 where rows are split into several segments); threads 512 or 768.
 int seg_pass_plane_max_len(int threads);
 void seg_pass_planes(int W, int threads, const SegPassDev& p, size_t lds, hipStream_t stream);
 

@@ -422,7 +422,8 @@ __device__ __forceinline__ void plane_givens_run(const SegPassDev& P, const SegD
   }
 }
 
-template <int W, int NT>
+// SEGS: rows split into segments (else one segment, the whole row, at offset 0)
+template <int W, int NT, bool SEGS>
 __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
   constexpr int kPlaneRegs = plane_regs<NT>();
   extern __shared__ __align__(16) char smem[];
@@ -434,19 +435,29 @@ __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
   double* red = wq + 32;                               // block reduction scratch
 
   // block -> (row, segment) as in the segment pass
-  int si;
+  int si = 0;
   int64_t r;
-  if (P.xcd_rows > 0) {
-    const int64_t k = blockIdx.x >> 3;
-    r = (int64_t)(blockIdx.x & 7) * P.xcd_rows + k / P.n_seg;
-    si = (int)(k % P.n_seg);
-    if (r >= P.n_rows) return;  // the whole block: the grid rounds rows up to 8 XCDs
+  if constexpr (SEGS) {
+    if (P.xcd_rows > 0) {
+      const int64_t k = blockIdx.x >> 3;
+      r = (int64_t)(blockIdx.x & 7) * P.xcd_rows + k / P.n_seg;
+      si = (int)(k % P.n_seg);
+      if (r >= P.n_rows) return;  // the whole block: the grid rounds rows up to 8 XCDs
+    } else {
+      si = (int)(blockIdx.x % P.n_seg);
+      r = blockIdx.x / P.n_seg;
+    }
   } else {
-    si = (int)(blockIdx.x % P.n_seg);
-    r = blockIdx.x / P.n_seg;
+    if (P.xcd_rows > 0) {
+      r = (int64_t)(blockIdx.x & 7) * P.xcd_rows + (blockIdx.x >> 3);
+      if (r >= P.n_rows) return;
+    } else {
+      r = blockIdx.x;
+    }
   }
-  const int64_t blk = r * P.n_seg + si;
+  const int64_t blk = SEGS ? r * P.n_seg + si : r;
   const SegDev sg = uniform_load(P.segs + si);
+  const int off = SEGS ? sg.off : 0;  // the segment's first column
   const int len = sg.len;
   const int nthr = blockDim.x;
   const int tid = threadIdx.x;
@@ -454,8 +465,8 @@ __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wave: loops over chunks stay scalar
   const int nwaves = nthr >> 6;
   const int64_t stride = P.gather ? P.n_rows : 1;
-  const zc128* src = P.gather ? (const zc128*)P.src + r + (int64_t)sg.off * P.n_rows
-                              : (const zc128*)P.src + r * P.row_len + sg.off;
+  const zc128* src = P.gather ? (const zc128*)P.src + r + (int64_t)off * P.n_rows
+                              : (const zc128*)P.src + r * P.row_len + off;
 
   // the row: every load in flight before the first is used; real parts to the
   // LDS plane, imaginary parts to registers; then the member-offset tables
@@ -478,7 +489,7 @@ __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
   bool lds_re = true;  // the LDS plane holds the real parts (the same in every thread)
 
   const uint32_t rmask = P.row_masks[r];
-  const uint32_t* cmask = P.col_masks + sg.off;
+  const uint32_t* cmask = P.col_masks + off;
   const int nbytes = (P.norb + 7) >> 3;
   double acc = 0.0;
   int s = 0;
@@ -509,7 +520,7 @@ __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
     const bool cross = dr.cross;
     if (st.type == ST_PHASE) {
       const zc128 rowf = cross ? zc128{1.0, 0.0} : dr.rowf;
-      const zc128* colf = st.colf ? (const zc128*)st.colf + sg.off : nullptr;
+      const zc128* colf = st.colf ? (const zc128*)st.colf + off : nullptr;
       const uint32_t sgn = st.sign_col;
       const bool use_cm = cross || sgn != 0;
 #pragma unroll
@@ -532,7 +543,7 @@ __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
         rp[k] = lds_re ? nim : nre;
       }
     } else {
-      const double* Bs = st.B ? st.B + sg.off : nullptr;
+      const double* Bs = st.B ? st.B + off : nullptr;
 #pragma unroll
       for (int k = 0; k < kPlaneRegs; ++k) {
         int e = tid + k * nthr;
@@ -559,7 +570,7 @@ __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
   if (P.mode != SEG_NONE) {
     // row r of this layout, or (scatter) column r of the other one
     const int64_t ostride = P.scatter ? P.n_rows : 1;
-    zc128* dst = P.scatter ? (zc128*)P.dst + r + (int64_t)sg.off * P.n_rows : (zc128*)P.dst + r * P.row_len + sg.off;
+    zc128* dst = P.scatter ? (zc128*)P.dst + r + (int64_t)off * P.n_rows : (zc128*)P.dst + r * P.row_len + off;
 #pragma unroll
     for (int k = 0; k < kPlaneRegs; ++k) {
       const int e = tid + k * nthr;
@@ -588,9 +599,9 @@ __global__ __launch_bounds__(NT) void k_seg_pass_planes(SegPassDev P) {
   }
 }
 
-template <int W, int NT>
+template <int W, int NT, bool SEGS>
 static void launch_planes(const SegPassDev& p, size_t lds, hipStream_t s) {
-  auto k = k_seg_pass_planes<W, NT>;
+  auto k = k_seg_pass_planes<W, NT, SEGS>;
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -600,12 +611,18 @@ static void launch_planes(const SegPassDev& p, size_t lds, hipStream_t s) {
   hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(NT), lds, s, p);
 }
 
+// rows split into segments only at window width 6 (the plan builds no
+// narrower segmented plane set)
 template <int NT>
 static void planes_w(int W, const SegPassDev& p, size_t lds, hipStream_t s) {
+  if (p.n_seg > 1) {
+    if (W == 6) launch_planes<6, NT, true>(p, lds, s);
+    return;
+  }
   switch (W) {
-    case 4: launch_planes<4, NT>(p, lds, s); break;
-    case 5: launch_planes<5, NT>(p, lds, s); break;
-    case 6: launch_planes<6, NT>(p, lds, s); break;
+    case 4: launch_planes<4, NT, false>(p, lds, s); break;
+    case 5: launch_planes<5, NT, false>(p, lds, s); break;
+    case 6: launch_planes<6, NT, false>(p, lds, s); break;
     default: break;
   }
 }

@@ -478,3 +478,46 @@ def _check_plane_plans(ffx, plans, seed):
         eo, go = ol.grad_adjoint(params, ham, norb, nelec, 2)
         assert abs(e - float(np.real(eo))) <= 1e-12 * max(1.0, abs(float(np.real(eo))))
         assert np.max(np.abs(g - go)) <= 1e-12 * max(1.0, np.max(np.abs(go)))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("switch", ["scatter", "gather", "transpose"])
+def test_layout_switch_variants(ffx, monkeypatch, switch, dtype):
+    """Every way a program switches layout between the visits of the two spins: the pass before the switch
+    stores its rows as columns of the new layout (scatter), the pass after it gathers them (gather), or a
+    transpose runs in between; square and rectangular states, whole rows and forced small segments (whose
+    crossing rotations take window passes), in both precisions, for a DF step (S_1, two steps), the DF
+    energy (reductions only), the Hamiltonian action (accumulation) and the LUCJ energy and gradient."""
+    monkeypatch.setenv("FFX_SCATTER", "1" if switch == "scatter" else "0")
+    monkeypatch.setenv("FFX_GATHER", "1" if switch == "gather" else "0")
+    import os
+    cases = [(8, (4, 4), None), (9, (3, 5), None), (10, (3, 6), "24")]
+    for norb, nelec, seg_max in cases:
+        print(f"layout switch {switch} {dtype} norb={norb} nelec={nelec} seg_max={seg_max}", flush=True)
+        if seg_max:
+            os.environ["FFX_SEG_MAX"] = seg_max
+            try:
+                plan = ffx.Plan(norb, nelec, dtype)
+            finally:
+                del os.environ["FFX_SEG_MAX"]
+        else:
+            plan = ffx.Plan(norb, nelec, dtype)
+        r = synth.rng([26, norb, len(switch)])
+        da, db = _dims(norb, nelec)
+        vec = _to_dev(synth.random_state(r, da, db), dtype)
+        x = _ref_input(vec)
+        ham = synth.df_hamiltonian(r, norb, 3)
+        out = ffx.simulate_trotter_double_factorized(vec, ham, 0.2, norb, nelec, n_steps=2, order=1, plan=plan)
+        ref = oh.simulate_trotter(x, ham, 0.2, norb, nelec, n_steps=2, order=1)
+        assert _maxdiff(out, ref) <= TOL[dtype]
+        e = ffx.df_energy(vec, ham, norb, nelec, plan=plan)
+        ref = oh.df_energy(x, ham, norb, nelec).real
+        assert abs(e - ref) <= RTOL[dtype] * max(1.0, abs(ref))
+        hv = ffx.apply_df_hamiltonian(vec, ham, norb, nelec, plan=plan)
+        ref = oh.apply_df_hamiltonian(x, ham, norb, nelec)
+        assert _maxdiff(hv, ref) <= RTOL[dtype] * max(1.0, float(np.abs(ref).max()))
+        params = synth.lucj_params(r, norb, 2, scale=0.3)
+        e, g = ffx.lucj_energy_grad(params, ham, norb, nelec, 2, dtype=dtype, plan=plan)
+        eo, go = ol.grad_adjoint(params, ham, norb, nelec, 2)
+        assert abs(e - float(np.real(eo))) <= RTOL[dtype] * max(1.0, abs(float(np.real(eo))))
+        assert np.max(np.abs(g - go)) <= RTOL[dtype] * max(1.0, np.max(np.abs(go)))

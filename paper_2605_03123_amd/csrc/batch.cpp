@@ -38,6 +38,7 @@ struct ffx_batch_s {
   int stage_rots = dev::kMaxStageRots;
   int lds_row_bytes = 0;
   int max_mt = 0;
+  int wq_rows = 1;  // the most rows of a segment task (cross weights and row factors in LDS)
   size_t lds = 0;
   int blocks = 0;
   // One persistent launch for the whole batch (task queue with per-instance
@@ -132,6 +133,7 @@ void build_tables(ffx_batch_s& b) {
   b.free_tables();
   b.lds_row_bytes = 16;
   b.max_mt = 0;
+  b.wq_rows = 1;
   for (size_t ti = 0; ti < b.plans.size(); ++ti) {
     const ffx_plan_s& P = *b.plans[ti];
     dev::BTypeDev& t = b.htypes[ti];
@@ -148,6 +150,7 @@ void build_tables(ffx_batch_s& b) {
       int R = (int)std::max<int64_t>(1, b.target_elems / std::max<int64_t>(len, 1));
       R = (int)std::min<int64_t>({(int64_t)R, (int64_t)64, std::max<int64_t>(nrows, 1)});
       t.rows_per_task[cs] = R;
+      b.wq_rows = std::max(b.wq_rows, R);
       std::vector<dev::SegWinDev> wins;
       std::vector<int> mt_all;
       for (int a = 0; ss.Wseg >= 2 && a + ss.Wseg <= ss.wt; ++a) {
@@ -198,7 +201,7 @@ void build_tables(ffx_batch_s& b) {
       b.lds_row_bytes = std::max<int>(b.lds_row_bytes, (int)rb);
     }
   }
-  b.lds = dev::batch_lds(b.c64, b.lds_row_bytes, b.max_mt, 16);
+  b.lds = dev::batch_lds(b.c64, b.lds_row_bytes, b.max_mt, b.wq_rows);
   if (b.lds > 160 * 1024 - 256) throw Error(FFX_EUNSUPPORTED, "batched task rows exceed LDS; lower the target");
   if (!b.d_types) b.d_types = (dev::BTypeDev*)b.dalloc(b.htypes.size() * sizeof(dev::BTypeDev));
   HIPCHK(hipMemcpy(b.d_types, b.htypes.data(), b.htypes.size() * sizeof(dev::BTypeDev), hipMemcpyHostToDevice));
@@ -615,6 +618,7 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
   bd.done = b.counters + 4;
   bd.lds_row_bytes = b.lds_row_bytes;
   bd.max_mt = b.max_mt;
+  bd.wq_rows = b.wq_rows;
   if (!b.ev[0]) HIPCHK(hipEventCreate(&b.ev[0]));
   if (!b.ev[1]) HIPCHK(hipEventCreate(&b.ev[1]));
   HIPCHK(hipEventRecord(b.ev[0], s));
@@ -645,7 +649,7 @@ void run_batch(ffx_batch_s& b, const ffx_lucj* ops, const ffx_df_ham* hams, doub
         const int64_t tasks = (p1 < (int)all.size() ? all[p1].first : first) - all[p0].first;
         if (tasks > 0) {
           dev::batch_launch_kind(b.c64, all[p0].kind, bd, p0, p1, tasks,
-                                 dev::batch_lds_for(all[p0].kind, b.lds_row_bytes, b.max_mt), s);
+                                 dev::batch_lds_for(all[p0].kind, b.lds_row_bytes, b.max_mt, b.wq_rows), s);
           check_launch();
           ++launches;
         }
@@ -762,7 +766,7 @@ int ffx_batch_tune(ffx_batch batch, const ffx_lucj* ops, const ffx_df_ham* hams,
     std::vector<double> g(ng);
     int best_t = b.target_elems, best_r = b.stage_rots;
     float best = 1e30f;
-    for (int tgt : {1024, 2048, 4096, 8192, 16384}) {
+    for (int tgt : {1024, 2048, 3072, 4096, 6144, 8192, 16384}) {
       b.target_elems = tgt;
       try {
         build_tables(b);

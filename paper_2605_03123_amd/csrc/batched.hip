@@ -48,8 +48,8 @@ constexpr int kBatchMaxDynLds = 160 * 1024 - 256;
 struct BatchLds {
   char* rows;
   int* mt;
-  double* wq;      // kBatchMaxRows x kBatchMaxOrb cross weights
-  double* rowf;    // kBatchMaxRows complex row factors (or real row values)
+  double* wq;      // wq_rows x kBatchMaxOrb cross weights
+  double* rowf;    // wq_rows complex row factors (or real row values)
   double* acc;     // 4 waves x 2 N^2 doubles (RDM) or 4 x 2N (diagonal gradients)
   double* red;     // 16 doubles
 };
@@ -60,10 +60,13 @@ struct BatchLds {
 // lay both out, the tables first (kind = -1).
 constexpr int kRedDoubles = 16;
 constexpr int kAccDoubles = 4 * 2 * kBatchMaxOrb * kBatchMaxOrb;
-constexpr int kSegTabDoubles = kBatchMaxRows * kBatchMaxOrb + 2 * kBatchMaxRows;
+// doubles of the cross weights and row factors of a task of at most wq_rows rows
+__host__ __device__ inline size_t seg_tab_doubles(int wq_rows) {
+  return (size_t)wq_rows * kBatchMaxOrb + 2 * (size_t)wq_rows;
+}
 
-__host__ __device__ inline size_t batch_lds_kind(int kind, int lds_row_bytes, int max_mt) {
-  const size_t tabs = (size_t)((max_mt + 3) & ~3) * 4 + (size_t)kSegTabDoubles * 8;
+__host__ __device__ inline size_t batch_lds_kind(int kind, int lds_row_bytes, int max_mt, int wq_rows) {
+  const size_t tabs = (size_t)((max_mt + 3) & ~3) * 4 + seg_tab_doubles(wq_rows) * 8;
   const size_t head = (size_t)lds_row_bytes + (size_t)kRedDoubles * 8;
   if (kind == BK_SEG) return head + tabs;
   if (kind >= 0) return head + (size_t)kAccDoubles * 8;
@@ -78,20 +81,21 @@ __device__ __forceinline__ BatchLds batch_lds_map(char* smem, const BatchDev& B,
   if (kind == BK_SEG || kind < 0) {
     L.mt = (int*)p;
     L.wq = (double*)(L.mt + ((B.max_mt + 3) & ~3));
-    L.rowf = L.wq + kBatchMaxRows * kBatchMaxOrb;
-    p = (char*)(L.rowf + 2 * kBatchMaxRows);
+    L.rowf = L.wq + B.wq_rows * kBatchMaxOrb;
+    p = (char*)(L.rowf + 2 * B.wq_rows);
   }
   if (kind != BK_SEG) L.acc = (double*)p;
   return L;
 }
 
-size_t batch_lds(bool c64, int lds_row_bytes, int max_mt, int norb_max) {
+size_t batch_lds(bool c64, int lds_row_bytes, int max_mt, int wq_rows) {
   (void)c64;
-  (void)norb_max;
-  return batch_lds_kind(-1, lds_row_bytes, max_mt);
+  return batch_lds_kind(-1, lds_row_bytes, max_mt, wq_rows);
 }
 
-size_t batch_lds_for(int kind, int lds_row_bytes, int max_mt) { return batch_lds_kind(kind, lds_row_bytes, max_mt); }
+size_t batch_lds_for(int kind, int lds_row_bytes, int max_mt, int wq_rows) {
+  return batch_lds_kind(kind, lds_row_bytes, max_mt, wq_rows);
+}
 
 // fixed-order block sum (4 waves); every thread gets the result
 __device__ __forceinline__ double batch_block_sum(double v, double* red) {

@@ -418,12 +418,14 @@ struct BatchDev {
   unsigned int* abort;    // set when a wait exceeds its bound
   int lds_row_bytes;      // LDS bytes reserved for the rows of one task
   int max_mt;             // ints reserved for member-offset tables
+  int wq_rows;            // rows reserved for the cross weights and row factors (the most rows of a task)
+  int pad2;
 };
 
 // LDS bytes of the batched kernel and its launch.  blocks: resident blocks to start.
-size_t batch_lds(bool c64, int lds_row_bytes, int max_mt, int norb_max);
+size_t batch_lds(bool c64, int lds_row_bytes, int max_mt, int wq_rows);
 // LDS bytes of a launch that runs tasks of one kind only
-size_t batch_lds_for(int kind, int lds_row_bytes, int max_mt);
+size_t batch_lds_for(int kind, int lds_row_bytes, int max_mt, int wq_rows);
 int batch_blocks_per_cu(bool c64, int threads, size_t lds);
 void batch_launch(bool c64, const BatchDev& b, int blocks, int threads, size_t lds, hipStream_t s);
 // level-synchronous form: the tasks of passes [p0, p1) (one level), one block each

@@ -215,6 +215,88 @@ std::vector<Pass> schedule_windows_beam(const std::vector<Givens>& rots, int nor
   return schedule_windows(rots, norb, w);
 }
 
+std::vector<SchedPass> schedule_windows_cross(const std::vector<Givens>& rots, int norb, int wt, int w, int W,
+                                              int beam, int win_cost) {
+  const int n = (int)rots.size();
+  if (n == 0) return {};
+  std::vector<std::vector<int>> deps(n);
+  std::vector<int> last(norb, -1);
+  for (int i = 0; i < n; ++i) {
+    const int p = rots[i].p;
+    if (p < 0 || p + 1 >= norb) throw Error(FFX_EINVAL, "rotation outside the orbitals");
+    for (int q : {p, p + 1})
+      if (last[q] >= 0) deps[i].push_back(last[q]);
+    last[p] = last[p + 1] = i;
+  }
+  using Set = std::vector<uint64_t>;
+  const int words = (n + 63) / 64;
+  auto has = [](const Set& d, int i) { return (d[i >> 6] >> (i & 63)) & 1ull; };
+  // the rotations inside [a, a + width) whose predecessors are applied or taken
+  auto take = [&](const Set& d, int a, int width) {
+    std::vector<int> out;
+    std::vector<char> taken(n, 0);
+    for (int i = 0; i < n; ++i) {
+      if (has(d, i)) continue;
+      const int p = rots[i].p;
+      if (p < a || p + 1 >= a + width) continue;
+      bool ok = true;
+      for (int dd : deps[i])
+        if (!has(d, dd) && !taken[dd]) {
+          ok = false;
+          break;
+        }
+      if (ok) {
+        taken[i] = 1;
+        out.push_back(i);
+      }
+    }
+    return out;
+  };
+  struct Node {
+    int count;
+    std::vector<SchedPass> hist;
+  };
+  // states by total cost; a state reached before at a lower or equal cost is not kept again
+  std::map<int, std::map<Set, Node>> bucket;
+  std::map<Set, int> seen;
+  bucket[0].emplace(Set(words, 0), Node{0, {}});
+  seen[Set(words, 0)] = 0;
+  const int max_cost = 4 * n + 16;
+  for (auto it = bucket.begin(); it != bucket.end() && it->first <= max_cost; it = bucket.erase(it)) {
+    const int cost = it->first;
+    std::vector<std::pair<Set, Node>> v;
+    for (auto& sn : it->second)
+      if (seen[sn.first] == cost) v.push_back(sn);  // (reached at a lower cost since: stale)
+    std::stable_sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.second.count > y.second.count; });
+    if ((int)v.size() > beam) v.resize(beam);
+    for (const auto& sn : v)
+      if (sn.second.count == n) return sn.second.hist;
+    auto push = [&](const Set& d0, const Node& nd0, bool win, int a, std::vector<int> t, int c) {
+      Set d = d0;
+      for (int i : t) d[i >> 6] |= 1ull << (i & 63);
+      auto sit = seen.find(d);
+      if (sit != seen.end() && sit->second <= c) return;
+      seen[d] = c;
+      Node nd{nd0.count + (int)t.size(), nd0.hist};
+      nd.hist.push_back(SchedPass{win, a, std::move(t)});
+      bucket[c][d] = std::move(nd);
+    };
+    for (const auto& sn : v) {
+      for (int a = 0; a + w <= wt; ++a) {
+        std::vector<int> t = take(sn.first, a, w);
+        if (!t.empty()) push(sn.first, sn.second, false, a, std::move(t), cost + 1);
+      }
+      for (int a = 0; a + W <= norb; ++a) {
+        std::vector<int> t = take(sn.first, a, W);
+        bool crosses = false;
+        for (int i : t) crosses = crosses || rots[i].p + 1 >= wt;
+        if (crosses) push(sn.first, sn.second, true, a, std::move(t), cost + win_cost);
+      }
+    }
+  }
+  return {};
+}
+
 WindowTable build_window_table(const std::vector<uint64_t>& strs, int norb, int n, int a, int w) {
   (void)norb;
   (void)n;

@@ -109,6 +109,22 @@ const std::vector<SchedStep>& rotation_schedule(const std::vector<Givens>& rots,
     if (fits) return cache.emplace(std::move(key), std::move(out)).first->second;
     out.clear();
   }
+  // rotations cross the segment window and none is applied at load: stages
+  // and whole-spin window passes from the cost search (a window pass counted
+  // as three stages, about its time against a stage's at 18 orbitals).  At 18
+  // orbitals with plane segments it needs 14 stages per decomposition where
+  // the greedy order below needs 16.  Up to 20 orbitals (190 rotations): its
+  // host time grows quickly with the rotation count (0.1 s at 18 orbitals,
+  // once per rotation structure).
+  if (wseg >= 2 && !cross && N <= 20) {
+    const std::vector<SchedPass> sp = schedule_windows_cross(rots, N, wt, wseg, W, kScheduleBeam, 3);
+    bool ok = !sp.empty();
+    for (const SchedPass& p : sp) ok = ok && (int)p.idx.size() <= cap;
+    if (ok) {
+      for (const SchedPass& p : sp) out.push_back(SchedStep{p.win ? 2 : 0, p.a, p.idx});
+      return cache.emplace(std::move(key), std::move(out)).first->second;
+    }
+  }
   const auto deps = rotation_deps(rots, N);
   std::vector<char> done(rots.size(), 0);
   size_t n_done = 0;

@@ -113,6 +113,103 @@ static void check_givens() {
   CHECK(threw, "non-unitary input accepted");
 }
 
+// Schedules of a decomposition whose rotations cross a segment window [0, wt):
+// every rotation exactly once, after the rotations it depends on (those
+// sharing an orbital and earlier in the list), stages inside [a, a + w) within
+// the segment window, window passes inside [a, a + W) taking a crossing
+// rotation; and the beam search needs no more stages than the greedy order
+// (stages first, then one whole-spin window pass when none can progress).
+static void check_cross_schedules() {
+  std::mt19937_64 rng(11);
+  for (int N : {8, 11, 17, 18}) {
+    const auto U = random_unitary(N, rng, true);
+    const ffx::Decomposition d = ffx::givens_decompose(N, U.data());
+    const int n = (int)d.rots.size();
+    for (int wt : {N - 1, N - 2, N - 3, 6}) {
+      const int w = std::min(6, wt);
+      const auto sp = ffx::schedule_windows_cross(d.rots, N, wt, w, 6, 300, 3);
+      CHECK(!sp.empty(), "cross schedule found N=%d wt=%d", N, wt);
+      std::vector<int> when(n, -1);
+      int step = 0, stages = 0;
+      for (const auto& p : sp) {
+        const int lo = p.a, hi = p.a + (p.win ? 6 : w);
+        CHECK(lo >= 0 && hi <= (p.win ? N : wt), "window bounds N=%d wt=%d", N, wt);
+        bool crosses = false;
+        for (int i : p.idx) {
+          CHECK(i >= 0 && i < n && when[i] < 0, "rotation once N=%d wt=%d", N, wt);
+          CHECK(d.rots[i].p >= lo && d.rots[i].p + 1 < hi, "rotation inside its window N=%d wt=%d", N, wt);
+          crosses = crosses || d.rots[i].p + 1 >= wt;
+          when[i] = step++;
+        }
+        if (p.win) CHECK(crosses, "window pass without a crossing rotation N=%d wt=%d", N, wt);
+        else ++stages;
+      }
+      for (int i = 0; i < n; ++i) {
+        CHECK(when[i] >= 0, "rotation scheduled N=%d wt=%d", N, wt);
+        for (int j = 0; j < i; ++j) {
+          const int pi = d.rots[i].p, pj = d.rots[j].p;
+          if (pj == pi || pj == pi + 1 || pj + 1 == pi) CHECK(when[j] < when[i], "dependency order N=%d wt=%d", N, wt);
+        }
+      }
+      // the greedy order, for comparison
+      std::vector<char> done(n, 0);
+      int greedy = 0, left = n;
+      while (left > 0) {
+        bool progressed = true;
+        while (progressed) {
+          progressed = false;
+          std::vector<int> best;
+          for (int a = 0; a + w <= wt; ++a) {
+            std::vector<int> t;
+            std::vector<char> taken(n, 0);
+            for (int i = 0; i < n; ++i) {
+              if (done[i] || d.rots[i].p < a || d.rots[i].p + 1 >= a + w) continue;
+              bool ok = true;
+              for (int j = 0; j < i; ++j) {
+                const int pi = d.rots[i].p, pj = d.rots[j].p;
+                if ((pj == pi || pj == pi + 1 || pj + 1 == pi) && !done[j] && !taken[j]) ok = false;
+              }
+              if (ok) {
+                taken[i] = 1;
+                t.push_back(i);
+              }
+            }
+            if (t.size() > best.size()) best = t;
+          }
+          if (!best.empty()) {
+            for (int i : best) done[i] = 1;
+            left -= (int)best.size();
+            ++greedy;
+            progressed = true;
+          }
+        }
+        if (left == 0) break;
+        std::vector<int> best;
+        for (int a = 0; a + 6 <= N; ++a) {
+          std::vector<int> t;
+          std::vector<char> taken(n, 0);
+          for (int i = 0; i < n; ++i) {
+            if (done[i] || d.rots[i].p < a || d.rots[i].p + 1 >= a + 6) continue;
+            bool ok = true;
+            for (int j = 0; j < i; ++j) {
+              const int pi = d.rots[i].p, pj = d.rots[j].p;
+              if ((pj == pi || pj == pi + 1 || pj + 1 == pi) && !done[j] && !taken[j]) ok = false;
+            }
+            if (ok) {
+              taken[i] = 1;
+              t.push_back(i);
+            }
+          }
+          if (t.size() > best.size()) best = t;
+        }
+        for (int i : best) done[i] = 1;
+        left -= (int)best.size();
+      }
+      CHECK(stages <= greedy, "beam stages %d > greedy %d at N=%d wt=%d", stages, greedy, N, wt);
+    }
+  }
+}
+
 static void check_window_tables() {
   for (auto [N, n] : std::vector<std::pair<int, int>>{{6, 3}, {8, 4}, {9, 2}, {10, 5}, {12, 6}, {13, 4}, {16, 8},
                                                        {16, 1}, {7, 0}, {7, 7}}) {
@@ -430,6 +527,7 @@ static void check_dense_helpers() {
 int main() {
   check_strings();
   check_givens();
+  check_cross_schedules();
   check_window_tables();
   check_segments();
   check_one_body_tables();

@@ -218,7 +218,7 @@ std::vector<Pass> schedule_windows_beam(const std::vector<Givens>& rots, int nor
 std::vector<SchedPass> schedule_windows_cross(const std::vector<Givens>& rots, int norb, int wt, int w, int W,
                                               int beam, int win_cost) {
   const int n = (int)rots.size();
-  if (n == 0) return {};
+  if (n == 0 || win_cost < 1) return {};
   std::vector<std::vector<int>> deps(n);
   std::vector<int> last(norb, -1);
   for (int i = 0; i < n; ++i) {

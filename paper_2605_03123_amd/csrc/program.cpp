@@ -125,6 +125,22 @@ const std::vector<SchedStep>& rotation_schedule(const std::vector<Givens>& rots,
       return cache.emplace(std::move(key), std::move(out)).first->second;
     }
   }
+  // the rotation on the pair straddling the segment window applied at load:
+  // the same search with that pair as the only "window pass" (a two-orbital
+  // window at wt - 1, which holds one ready rotation at a time); at 16
+  // orbitals with half rows, 12 stages per decomposition where the greedy
+  // order below needs 13.  (Rotations above the pair, which need window
+  // passes, leave the search without a schedule.)
+  if (wseg >= 2 && cross && N <= 20) {
+    const std::vector<SchedPass> sp = schedule_windows_cross(rots, N, wt, wseg, 2, kScheduleBeam, 3);
+    bool ok = !sp.empty();
+    for (const SchedPass& p : sp)
+      ok = ok && (int)p.idx.size() <= cap && (!p.win || (p.idx.size() == 1 && rots[p.idx[0]].p == wt - 1));
+    if (ok) {
+      for (const SchedPass& p : sp) out.push_back(p.win ? SchedStep{1, 0, p.idx} : SchedStep{0, p.a, p.idx});
+      return cache.emplace(std::move(key), std::move(out)).first->second;
+    }
+  }
   const auto deps = rotation_deps(rots, N);
   std::vector<char> done(rots.size(), 0);
   size_t n_done = 0;

@@ -207,6 +207,26 @@ static void check_cross_schedules() {
       }
       CHECK(stages <= greedy, "beam stages %d > greedy %d at N=%d wt=%d", stages, greedy, N, wt);
     }
+    // the pair straddling the window as a two-orbital window (applied at load): one rotation each time
+    const int wt = N - 1;
+    const auto sp = ffx::schedule_windows_cross(d.rots, N, wt, 6, 2, 300, 3);
+    CHECK(!sp.empty(), "at-load schedule found N=%d", N);
+    std::vector<int> when(n, -1);
+    int step = 0;
+    for (const auto& p : sp) {
+      if (p.win) CHECK(p.idx.size() == 1 && d.rots[p.idx[0]].p == wt - 1, "at-load step N=%d", N);
+      for (int i : p.idx) {
+        CHECK(when[i] < 0, "at-load rotation once N=%d", N);
+        when[i] = step++;
+      }
+    }
+    for (int i = 0; i < n; ++i) {
+      CHECK(when[i] >= 0, "at-load rotation scheduled N=%d", N);
+      for (int j = 0; j < i; ++j) {
+        const int pi = d.rots[i].p, pj = d.rots[j].p;
+        if (pj == pi || pj == pi + 1 || pj + 1 == pi) CHECK(when[j] < when[i], "at-load order N=%d", N);
+      }
+    }
   }
 }
 

@@ -216,7 +216,8 @@ std::vector<Pass> schedule_windows_beam(const std::vector<Givens>& rots, int nor
 }
 
 std::vector<SchedPass> schedule_windows_cross(const std::vector<Givens>& rots, int norb, int wt, int w, int W,
-                                              int beam, int win_cost) {
+                                              int beam, int win_cost,
+                                              const std::function<bool(const std::vector<int>&)>* shaped) {
   const int n = (int)rots.size();
   if (n == 0 || win_cost < 1) return {};
   std::vector<std::vector<int>> deps(n);
@@ -284,7 +285,14 @@ std::vector<SchedPass> schedule_windows_cross(const std::vector<Givens>& rots, i
     for (const auto& sn : v) {
       for (int a = 0; a + w <= wt; ++a) {
         std::vector<int> t = take(sn.first, a, w);
-        if (!t.empty()) push(sn.first, sn.second, false, a, std::move(t), cost + 1);
+        if (t.empty()) continue;
+        int c = 1;
+        if (shaped) {
+          std::vector<int> pos;
+          for (int i : t) pos.push_back(rots[i].p - a);
+          if (!(*shaped)(pos)) c = 2;
+        }
+        push(sn.first, sn.second, false, a, std::move(t), cost + c);
       }
       for (int a = 0; a + W <= norb; ++a) {
         std::vector<int> t = take(sn.first, a, W);

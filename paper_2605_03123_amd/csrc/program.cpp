@@ -116,8 +116,19 @@ const std::vector<SchedStep>& rotation_schedule(const std::vector<Givens>& rots,
   // the greedy order below needs 16.  Up to 20 orbitals (190 rotations): its
   // host time grows quickly with the rotation count (0.1 s at 18 orbitals,
   // once per rotation structure).
+  // a stage with straight-line code (one of the stage shapes) counts 1, any other 2
+  const std::function<bool(const std::vector<int>&)> shaped = [](const std::vector<int>& pos) {
+    for (int k = 0; k < dev::kNumShapes; ++k) {
+      if ((int)pos.size() != dev::kShapeLen[k]) continue;
+      bool same = true;
+      for (size_t i = 0; i < pos.size() && same; ++i) same = pos[i] == dev::kShapeP[k][i];
+      if (same) return true;
+    }
+    return false;
+  };
+  const auto* shaped_p = wseg == dev::kShapeW ? &shaped : nullptr;
   if (wseg >= 2 && !cross && N <= 20) {
-    const std::vector<SchedPass> sp = schedule_windows_cross(rots, N, wt, wseg, W, kScheduleBeam, 3);
+    const std::vector<SchedPass> sp = schedule_windows_cross(rots, N, wt, wseg, W, kScheduleBeam, 3, shaped_p);
     bool ok = !sp.empty();
     for (const SchedPass& p : sp) ok = ok && (int)p.idx.size() <= cap;
     if (ok) {
@@ -128,11 +139,12 @@ const std::vector<SchedStep>& rotation_schedule(const std::vector<Givens>& rots,
   // the rotation on the pair straddling the segment window applied at load:
   // the same search with that pair as the only "window pass" (a two-orbital
   // window at wt - 1, which holds one ready rotation at a time); at 16
-  // orbitals with half rows, 12 stages per decomposition where the greedy
-  // order below needs 13.  (Rotations above the pair, which need window
-  // passes, leave the search without a schedule.)
+  // orbitals with half rows, 12 stages per decomposition, all with
+  // straight-line code, where the greedy order below needs 13.  (Rotations
+  // above the pair, which need window passes, leave the search without a
+  // schedule.)
   if (wseg >= 2 && cross && N <= 20) {
-    const std::vector<SchedPass> sp = schedule_windows_cross(rots, N, wt, wseg, 2, kScheduleBeam, 3);
+    const std::vector<SchedPass> sp = schedule_windows_cross(rots, N, wt, wseg, 2, kScheduleBeam, 3, shaped_p);
     bool ok = !sp.empty();
     for (const SchedPass& p : sp)
       ok = ok && (int)p.idx.size() <= cap && (!p.win || (p.idx.size() == 1 && rots[p.idx[0]].p == wt - 1));

@@ -113,9 +113,11 @@ const std::vector<SchedStep>& rotation_schedule(const std::vector<Givens>& rots,
   // and whole-spin window passes from the cost search (a window pass counted
   // as three stages, about its time against a stage's at 18 orbitals).  At 18
   // orbitals with plane segments it needs 14 stages per decomposition where
-  // the greedy order below needs 16.  Up to 20 orbitals (190 rotations): its
-  // host time grows quickly with the rotation count (0.1 s at 18 orbitals,
-  // once per rotation structure).
+  // the greedy order below needs 16; at 32 orbitals with ten above the
+  // segment window, 46 stages and 8 window passes where the greedy order
+  // needs 55 and 8.  Its host time grows quickly with the rotation count
+  // (once per rotation structure): the full beam up to 20 orbitals (0.1 s at
+  // 18), a narrower one up to 32 (0.4 s).
   // a stage with straight-line code (one of the stage shapes) counts 1, any other 2
   const std::function<bool(const std::vector<int>&)> shaped = [](const std::vector<int>& pos) {
     for (int k = 0; k < dev::kNumShapes; ++k) {
@@ -127,8 +129,9 @@ const std::vector<SchedStep>& rotation_schedule(const std::vector<Givens>& rots,
     return false;
   };
   const auto* shaped_p = wseg == dev::kShapeW ? &shaped : nullptr;
-  if (wseg >= 2 && !cross && N <= 20) {
-    const std::vector<SchedPass> sp = schedule_windows_cross(rots, N, wt, wseg, W, kScheduleBeam, 3, shaped_p);
+  const int beam = N <= 20 ? kScheduleBeam : 60;
+  if (wseg >= 2 && !cross && N <= 32) {
+    const std::vector<SchedPass> sp = schedule_windows_cross(rots, N, wt, wseg, W, beam, 3, shaped_p);
     bool ok = !sp.empty();
     for (const SchedPass& p : sp) ok = ok && (int)p.idx.size() <= cap;
     if (ok) {
@@ -143,8 +146,8 @@ const std::vector<SchedStep>& rotation_schedule(const std::vector<Givens>& rots,
   // straight-line code, where the greedy order below needs 13.  (Rotations
   // above the pair, which need window passes, leave the search without a
   // schedule.)
-  if (wseg >= 2 && cross && N <= 20) {
-    const std::vector<SchedPass> sp = schedule_windows_cross(rots, N, wt, wseg, 2, kScheduleBeam, 3, shaped_p);
+  if (wseg >= 2 && cross && N <= 32) {
+    const std::vector<SchedPass> sp = schedule_windows_cross(rots, N, wt, wseg, 2, beam, 3, shaped_p);
     bool ok = !sp.empty();
     for (const SchedPass& p : sp)
       ok = ok && (int)p.idx.size() <= cap && (!p.win || (p.idx.size() == 1 && rots[p.idx[0]].p == wt - 1));
